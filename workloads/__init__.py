@@ -1,0 +1,152 @@
+"""Seeded synthetic inputs shared by the CPU oracle and the GPU path.
+
+This module only draws numbers and describes problem shapes.  It holds none of
+the solver's arithmetic (no operators, no transfers, no smoothing, no Krylov
+steps), so the oracle and the HIP path can both take their inputs from here
+without sharing any of the method.
+
+Workloads (all synthetic; the paper's own experiments use FEM meshes and a
+fracture geometry that are not reproduced here):
+
+* ``poisson2d_31``   2D, 31x31 interior nodes, 4 levels (31/15/7/3), b ~ U[-1,1], seed 1.
+* ``poisson3d_127``  3D, 127^3 interior nodes, 6 levels (127/63/31/15/7/3), b ~ U[-1,1], seed 2.
+* ``diffusion3d_127`` as above with kappa = exp(2 g), g a unit-variance Gaussian
+  field with squared-exponential covariance, correlation length 1/16, seed 3.
+* ``batched2d_512``  512 independent 2D Poisson instances, side n_i ~ U{31..255}
+  (seed 4), rhs seed 4000+i, levels max(2, floor(log2(n_i+1)) - 2).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class GridProblem:
+    """A structured problem: ``dim``-D unit cube, ``n`` interior nodes per axis."""
+    name: str
+    dim: int
+    n: int
+    nlevels: int
+    rhs_seed: int
+    kappa_seed: Optional[int] = None   # None => kappa == 1 (Poisson)
+    corr_len: float = 1.0 / 16.0
+
+    @property
+    def ndof(self) -> int:
+        return self.n ** self.dim
+
+
+POISSON2D_31 = GridProblem("poisson2d_31", 2, 31, 4, rhs_seed=1)
+POISSON3D_127 = GridProblem("poisson3d_127", 3, 127, 6, rhs_seed=2)
+DIFFUSION3D_127 = GridProblem("diffusion3d_127", 3, 127, 6, rhs_seed=2, kappa_seed=3)
+
+PROBLEMS = {p.name: p for p in (POISSON2D_31, POISSON3D_127, DIFFUSION3D_127)}
+
+
+def level_sizes(n: int, nlevels: int) -> List[int]:
+    """Per-axis node counts, finest first: n, floor(n/2), floor(n/4), ..."""
+    sizes = [n]
+    for _ in range(nlevels - 1):
+        sizes.append(sizes[-1] // 2)
+    if sizes[-1] < 1:
+        raise ValueError(f"n={n} too small for {nlevels} levels")
+    return sizes
+
+
+def rhs(ndof: int, seed: int) -> np.ndarray:
+    """b ~ U[-1, 1]^ndof in float64 from ``numpy.random.default_rng(seed)``."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-1.0, 1.0, size=ndof)
+
+
+def gaussian_field(n: int, dim: int, seed: int, corr_len: float = 1.0 / 16.0,
+                   periodic: int = 256) -> np.ndarray:
+    """Unit-variance stationary Gaussian field on the (n+2)^dim node grid.
+
+    Covariance exp(-r^2 / (2 corr_len^2)) with node spacing h = 1/(n+1),
+    synthesised by circulant embedding on a periodic ``periodic``^dim grid of
+    the same spacing and cropped to the (n+2)^dim corner (boundary nodes
+    included).  Returned with x fastest: shape (n+2,)*dim indexed [z, y, x].
+    """
+    m = periodic
+    if m < n + 2:
+        raise ValueError("periodic grid smaller than the node grid")
+    h = 1.0 / (n + 1)
+    d1 = np.minimum(np.arange(m), m - np.arange(m)) * h  # periodic distance
+    r2 = np.zeros((m,) * dim)
+    for ax in range(dim):
+        shape = [1] * dim
+        shape[ax] = m
+        r2 = r2 + (d1 ** 2).reshape(shape)
+    cov = np.exp(-r2 / (2.0 * corr_len ** 2))
+    spec = np.real(np.fft.fftn(cov))
+    spec = np.maximum(spec, 0.0)
+    rng = np.random.default_rng(seed)
+    white = rng.standard_normal((m,) * dim)
+    g = np.real(np.fft.ifftn(np.sqrt(spec) * np.fft.fftn(white)))
+    crop = tuple(slice(0, n + 2) for _ in range(dim))
+    return np.ascontiguousarray(g[crop])
+
+
+def kappa_field(problem: GridProblem) -> Optional[np.ndarray]:
+    """kappa = exp(2 g) on the (n+2)^dim node grid, or None for Poisson."""
+    if problem.kappa_seed is None:
+        return None
+    g = gaussian_field(problem.n, problem.dim, problem.kappa_seed, problem.corr_len)
+    return np.exp(2.0 * g)
+
+
+def problem_rhs(problem: GridProblem) -> np.ndarray:
+    return rhs(problem.ndof, problem.rhs_seed)
+
+
+@dataclass(frozen=True)
+class BatchedInstance:
+    index: int
+    n: int
+    nlevels: int
+    rhs_seed: int
+
+    @property
+    def ndof(self) -> int:
+        return self.n * self.n
+
+
+def batched_levels(n: int) -> int:
+    """Hierarchy depth for an instance of side n: max(2, floor(log2(n+1)) - 2)."""
+    return max(2, int(math.floor(math.log2(n + 1))) - 2)
+
+
+def batched_instances(count: int = 512, seed: int = 4, nmin: int = 31,
+                      nmax: int = 255) -> List[BatchedInstance]:
+    """``count`` 2D Poisson instances with side n_i ~ U{nmin..nmax} (seed)."""
+    rng = np.random.default_rng(seed)
+    sides = rng.integers(nmin, nmax + 1, size=count)
+    return [BatchedInstance(i, int(s), batched_levels(int(s)), 4000 + i)
+            for i, s in enumerate(sides)]
+
+
+def batched_rhs(inst: BatchedInstance) -> np.ndarray:
+    return rhs(inst.ndof, inst.rhs_seed)
+
+
+def manufactured_rhs(dim: int, n: int) -> np.ndarray:
+    """f = dim * pi^2 * prod_i sin(pi x_i) at interior nodes (x fastest).
+
+    The continuous solution of -Laplace(u) = f with u = 0 on the boundary is
+    u = prod_i sin(pi x_i); see ``manufactured_solution``.
+    """
+    return dim * math.pi ** 2 * manufactured_solution(dim, n)
+
+
+def manufactured_solution(dim: int, n: int) -> np.ndarray:
+    h = 1.0 / (n + 1)
+    s = np.sin(math.pi * h * np.arange(1, n + 1))
+    u = s
+    for _ in range(dim - 1):
+        u = np.multiply.outer(s, u)
+    return u.reshape(-1).copy()
