@@ -1,0 +1,143 @@
+/*
+ * amgmpcg — additive-multigrid multipreconditioned CG on AMD MI355X (gfx950).
+ *
+ * C ABI of the solver library libamgmpcg.so.  Plain C types only: sizes are
+ * int32/int64, arrays are raw pointers whose address space (host or device)
+ * is stated per argument.  Every call returns an int status (AMGMPCG_OK or an
+ * error code below); no C++ exception crosses this boundary.  A thread-local
+ * text for the last error is available from amgmpcg_last_error().
+ *
+ * The method (Sec. 2 of the paper, Algorithm 1):
+ *   r_0 = b - A x_0;  Z_k = [z^0 | ... | z^L] with z^l = P_l^L S_l^nu R_L^l r_k
+ *   (the additive-multigrid correction of each level kept as its own search
+ *   direction, coarsest first);  alpha = (P_k^T A P_k)^+ P_k^T r_k;
+ *   x_{k+1} = x_k + P_k alpha;  r_{k+1} = r_k - A P_k alpha  (eq. (4));
+ *   P_{k+1} = Z_{k+1} - P_k (P_k^T A P_k)^+ P_k^T A Z_{k+1}  (truncation m = 1).
+ * S_l^nu is nu damped-Jacobi sweeps from zero (eq. (2)), R = 2^-d P^T (full
+ * weighting), P tensor-product linear interpolation, A_l Galerkin products.
+ *
+ * Grid convention: unit square/cube, n interior nodes per axis, homogeneous
+ * Dirichlet boundary, h = 1/(n+1); flat index i + n*(j + n*k) (x fastest).
+ * Level l has floor(n / 2^(L-l)) nodes per axis; level L is the given grid.
+ */
+#ifndef AMGMPCG_H
+#define AMGMPCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define AMGMPCG_OK            0   /* converged (relative residual <= tol)          */
+#define AMGMPCG_MAXIT         1   /* iteration limit reached, x holds the iterate  */
+#define AMGMPCG_BREAKDOWN     2   /* every direction dropped by the pseudo-inverse */
+#define AMGMPCG_INVALID_ARG  -1   /* bad pointer, size or option                   */
+#define AMGMPCG_NOT_SPD      -2   /* a level operator has a diagonal entry <= 0    */
+#define AMGMPCG_DIM_MISMATCH -3   /* grid too small for the requested levels       */
+#define AMGMPCG_NONFINITE    -4   /* NaN/Inf in the data or the residual           */
+#define AMGMPCG_OOM          -5   /* device allocation failed                      */
+#define AMGMPCG_HIP_ERROR    -6   /* any other HIP runtime error                   */
+
+/* ---- problem description -------------------------------------------- */
+/* Structured diffusion problem -div(kappa grad u) = f on (0,1)^dim (eq. (1)
+ * with K = kappa I, Dirichlet boundary), discretised by 5-/7-point finite
+ * differences with harmonic-mean face coefficients 2 k_a k_b / (k_a + k_b).
+ * kappa: HOST pointer to (n+2)^dim node values including the boundary layer
+ * (x fastest), or NULL for kappa == 1 (Poisson).  Copied during setup. */
+typedef struct {
+    int32_t dim;        /* 2 or 3                                          */
+    int32_t n;          /* interior nodes per axis, >= 1                   */
+    int32_t nlevels;    /* levels including the finest, 1 <= nlevels <= 8  */
+    const double* kappa;
+} amgmpcg_grid;
+
+/* Solver options.  Fill with amgmpcg_default_options() first. */
+typedef struct {
+    int32_t m;            /* truncation window; only 1 is accepted             */
+    int32_t nu;           /* damped-Jacobi sweeps on every level, 1..8 (2)     */
+    double  omega;        /* Jacobi damping in (0, 1] (2/3)                   */
+    int32_t maxit;        /* iteration limit (1000)                            */
+    int32_t precision;    /* 0: FP64 throughout; 1: FP32 bulk (operators,
+                             transfers, smoothers, direction blocks) with FP64
+                             x, r, Gram, pseudo-inverse and residual refresh */
+    double  pinv_tau;     /* eigenvalue cut of the unit-diagonal Gram; <= 0:
+                             64 * b * u with u = 2^-53 (FP64) or 2^-24 (FP32) */
+    int32_t k_poll;       /* iterations per captured graph launch between
+                             host checks of the device stop flag (8)          */
+    int32_t record_history; /* keep alpha and ||r|| per iteration (1)          */
+    double  refresh_drop; /* FP32 bulk: replace r by b - A x (FP64) whenever
+                             ||r|| fell by this factor since the last refresh,
+                             and before accepting convergence (1e-2)          */
+} amgmpcg_options;
+
+typedef struct {
+    int32_t status;          /* AMGMPCG_OK / _MAXIT / _BREAKDOWN / _NONFINITE   */
+    int32_t iterations;      /* number of x updates                             */
+    double  bnorm;           /* ||b||_2                                         */
+    double  relres;          /* last ||r||_2 / ||b||_2 on the solver's r        */
+    int32_t refreshes;       /* FP32 bulk: true-residual refreshes performed   */
+    int32_t nb;              /* search directions per iteration (L + 1)         */
+    double  solve_ms;        /* device time of the solve (HIP events)           */
+} amgmpcg_info;
+
+typedef struct amgmpcg_handle amgmpcg_handle;
+
+/* Default options (m=1, nu=2, omega=2/3, maxit=1000, FP64, k_poll=8). */
+void amgmpcg_default_options(amgmpcg_options* opts);
+
+/* setup(A, hierarchy): build the level hierarchy of a structured problem.
+ * Level operators are Galerkin products A_l = R A_{l+1} P computed on the
+ * host (Sec. 2.1), stored symmetrised, checked for a positive diagonal
+ * (AMGMPCG_NOT_SPD otherwise) and uploaded.  stream: hipStream_t on which
+ * every device operation of this handle runs (NULL = default stream).  The
+ * handle owns all device memory it allocates; free with amgmpcg_destroy. */
+int amgmpcg_setup_grid(const amgmpcg_grid* grid, const amgmpcg_options* opts,
+                       void* stream, amgmpcg_handle** out);
+
+/* solve(b, x0, tol): Algorithm 1 until ||r_k||_2 <= tol ||b||_2 or maxit.
+ * b_dev: DEVICE pointer, n^dim doubles, read only.  x_dev: DEVICE pointer,
+ * n^dim doubles, x_0 on entry and the final iterate on return.  Both are
+ * used on the handle's stream and not retained after the call returns.
+ * maxit <= 0 uses the option value.  tol = 0 runs exactly maxit iterations
+ * (unless the residual vanishes).  info may be NULL.  Returns the solve
+ * status (also in info->status). */
+int amgmpcg_solve(amgmpcg_handle* h, const double* b_dev, double* x_dev,
+                  double tol, int32_t maxit, amgmpcg_info* info);
+
+/* As amgmpcg_solve with HOST b and x (copies over PCIe included). */
+int amgmpcg_solve_host(amgmpcg_handle* h, const double* b, double* x,
+                       double tol, int32_t maxit, amgmpcg_info* info);
+
+/* The block Z = [z^0 | ... | z^L] of level corrections of r (Algorithm 1,
+ * "corrections from all levels").  r_dev: DEVICE, n^dim doubles.  Z_dev:
+ * DEVICE, column-major n^dim x (L+1) doubles (column l = level l, coarsest
+ * first), written in the handle's precision and widened to double. */
+int amgmpcg_mg_block(amgmpcg_handle* h, const double* r_dev, double* Z_dev);
+
+/* Number of levels, search directions and per-axis nodes of level l. */
+int amgmpcg_level_count(const amgmpcg_handle* h, int32_t* nlevels, int32_t* nb);
+int amgmpcg_level_size(const amgmpcg_handle* h, int32_t level, int32_t* n_axis);
+
+/* The operator of a coarse level l < L as 3^dim stencil coefficients per node,
+ * HOST out array of 3^dim * n_l^dim doubles, out[s * N_l + i] = A_l(i, i+o_s)
+ * with o_s = (dx,dy,dz) and s = (dz+1)*9 + (dy+1)*3 + (dx+1) (2D: no dz
+ * term); entries whose neighbour lies outside the grid are 0. */
+int amgmpcg_level_stencil(const amgmpcg_handle* h, int32_t level, double* out);
+
+/* Per-iteration history of the last solve (record_history = 1): alpha_out
+ * (HOST, cap * nb doubles, row k = alpha_k) and resnorm_out (HOST, cap + 1
+ * doubles, ||r_k||_2).  Either may be NULL.  *count = iterations stored. */
+int amgmpcg_history(const amgmpcg_handle* h, int32_t cap, double* alpha_out,
+                    double* resnorm_out, int32_t* count);
+
+void amgmpcg_destroy(amgmpcg_handle* h);
+const char* amgmpcg_status_string(int status);
+const char* amgmpcg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AMGMPCG_H */

@@ -1,0 +1,720 @@
+// libamgmpcg: additive-multigrid MPCG (Algorithm 1 of the paper) on gfx950.
+//
+// Host driver: hierarchy setup, device workspace, the per-iteration launch
+// sequence captured once into a HIP graph (k_poll iterations per graph), the
+// device-side stop flag polled by the host between graph launches, and the
+// extern "C" entry points declared in include/amgmpcg.h.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "amgmpcg.h"
+#include "common.hpp"
+#include "grid_kernels.hpp"
+#include "setup.hpp"
+#include "small_kernels.hpp"
+
+namespace amg {
+
+static_assert(kOK == AMGMPCG_OK && kMAXIT == AMGMPCG_MAXIT && kBREAKDOWN == AMGMPCG_BREAKDOWN &&
+                  kNONFINITE == AMGMPCG_NONFINITE,
+              "status codes");
+
+thread_local std::string g_last_error;
+
+struct ApiError : std::runtime_error {
+    int code;
+    ApiError(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(expr)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (expr);                                                                        \
+        if (e_ != hipSuccess) {                                                                        \
+            if (e_ == hipErrorOutOfMemory)                                                             \
+                throw ApiError(AMGMPCG_OOM, std::string("out of device memory: ") + #expr);            \
+            throw ApiError(AMGMPCG_HIP_ERROR,                                                          \
+                           std::string(hipGetErrorString(e_)) + " at " + #expr + " line " +            \
+                               std::to_string(__LINE__));                                              \
+        }                                                                                              \
+    } while (0)
+
+constexpr int kMaxFineBlocks = 2048;
+constexpr int kPartRow = 2 + 1 + kMaxNB * kMaxNB + (kMaxNB * (kMaxNB + 1) / 2 + kMaxNB) + 1;
+
+template <typename T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    void alloc(size_t count) {
+        free();
+        if (count == 0) return;
+        HIPCHK(hipMalloc((void**)&p, count * sizeof(T)));
+        n = count;
+    }
+    void free() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    ~DevBuf() { free(); }
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) {
+        o.p = nullptr;
+        o.n = 0;
+    }
+    DevBuf& operator=(DevBuf&& o) noexcept {
+        if (this != &o) {
+            free();
+            p = o.p;
+            n = o.n;
+            o.p = nullptr;
+            o.n = 0;
+        }
+        return *this;
+    }
+};
+
+class SolverBase {
+   public:
+    virtual ~SolverBase() = default;
+    virtual int solve(const double* b_dev, double* x_dev, double tol, int maxit, amgmpcg_info* info) = 0;
+    virtual void mg_block(const double* r_dev, double* Z_dev) = 0;
+    virtual void level_stencil(int level, double* out) = 0;
+    virtual void history(int cap, double* alpha, double* res, int* count) = 0;
+    int dim = 0, nlev = 0, nb = 0;
+    std::vector<int> n_axis;   // per level, 0 = coarsest
+};
+
+static int fine_blocks(int N) {
+    int b = (N + kBlock - 1) / kBlock;
+    if (b > kMaxFineBlocks) b = kMaxFineBlocks;
+    if (b >= kNumXcd) b = (b / kNumXcd) * kNumXcd;
+    return b < 1 ? 1 : b;
+}
+
+template <typename T, int DIM>
+class Solver : public SolverBase {
+   public:
+    Solver(const amgmpcg_grid& g, const amgmpcg_options& o, hipStream_t stream) : opt_(o), stream_(stream) {
+        dim = DIM;
+        nlev = g.nlevels;
+        nb = nlev;
+        L_ = nlev - 1;
+        mixed_ = std::is_same<T, float>::value;
+        n_axis.resize(nlev);
+        n_axis[L_] = g.n;
+        for (int l = L_ - 1; l >= 0; --l) n_axis[l] = n_axis[l + 1] / 2;
+        N_.resize(nlev);
+        for (int l = 0; l < nlev; ++l) N_[l] = (int)host::ipow(n_axis[l], DIM);
+        const int N = N_[L_];
+        FB_ = fine_blocks(N);
+
+        // ---- host hierarchy (FP64) -------------------------------------
+        const bool var = g.kappa != nullptr;
+        host::FineFaces faces = host::fine_faces(DIM, g.n, g.kappa);
+        for (int64_t i = 0; i < (int64_t)N; ++i) {
+            if (!std::isfinite(faces.D[i])) throw ApiError(AMGMPCG_NONFINITE, "non-finite kappa");
+            if (!(faces.D[i] > 0.0)) throw ApiError(AMGMPCG_NOT_SPD, "non-positive diagonal on the finest level");
+        }
+        std::vector<host::StencilLevel> lev(nlev);
+        if (L_ > 0) {
+            lev[L_] = host::faces_to_stencil(DIM, g.n, faces);
+            for (int l = L_ - 1; l >= 0; --l) {
+                lev[l] = host::galerkin(lev[l + 1]);
+                const int ctr = lev[l].center();
+                for (int64_t i = 0; i < lev[l].N; ++i) {
+                    const double d = lev[l].coef[(size_t)ctr * lev[l].N + i];
+                    if (!std::isfinite(d)) throw ApiError(AMGMPCG_NONFINITE, "non-finite coarse operator");
+                    if (!(d > 0.0)) throw ApiError(AMGMPCG_NOT_SPD, "non-positive diagonal on a coarse level");
+                }
+            }
+        }
+
+        // ---- device memory ---------------------------------------------
+        const double h2inv = double(g.n + 1) * double(g.n + 1);
+        fop_.n = g.n;
+        fop_.N = N;
+        fop_.s0 = T(h2inv);
+        fop_.D = fop_.ex = fop_.ey = fop_.ez = nullptr;
+        f64_.n = g.n;
+        f64_.N = N;
+        f64_.s0 = h2inv;
+        f64_.D = f64_.ex = f64_.ey = f64_.ez = nullptr;
+        if (var) {
+            upload_faces(faces);
+        }
+        coef_.resize(nlev);
+        g_.resize(nlev);
+        c_.resize(nlev);
+        c2_.resize(nlev);
+        Y_.resize(nlev);
+        for (int l = 0; l < L_; ++l) {
+            const int S = lev[l].S();
+            coef_[l].alloc((size_t)S * N_[l]);
+            upload_conv(coef_[l].p, lev[l].coef);
+            g_[l].alloc(N_[l]);
+            c_[l].alloc(N_[l]);
+            if (opt_.nu > 2) c2_[l].alloc(N_[l]);
+            if (l >= 1) Y_[l].alloc((size_t)l * N_[l]);
+        }
+        x_.alloc(N);
+        r_.alloc(N);
+        b_.alloc(N);
+        P_.alloc((size_t)nb * N);
+        Q_.alloc((size_t)nb * N);
+        cL_.alloc(N);
+        if (opt_.nu > 2) cL2_.alloc(N);
+        part_.alloc((size_t)FB_ * kPartRow);
+        small_.alloc(kMaxNB + 2 * kMaxNB * kMaxNB);
+        hist_cap_ = opt_.record_history ? std::max(opt_.maxit, 1) : 0;
+        if (hist_cap_ > 0) {
+            ahist_.alloc((size_t)hist_cap_ * nb);
+            rhist_.alloc((size_t)hist_cap_ + 1);
+        }
+        HIPCHK(hipMalloc((void**)&ctl_, sizeof(Ctl)));
+        HIPCHK(hipMalloc((void**)&ctl_free_, sizeof(Ctl)));
+        HIPCHK(hipHostMalloc((void**)&hctl_, sizeof(Ctl), hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void**)&hctl_in_, sizeof(Ctl), hipHostMallocDefault));
+        std::memset(hctl_in_, 0, sizeof(Ctl));
+        HIPCHK(hipMemcpyAsync(ctl_free_, hctl_in_, sizeof(Ctl), hipMemcpyHostToDevice, stream_));
+        HIPCHK(hipMemsetAsync(small_.p, 0, small_.n * sizeof(double), stream_));
+        HIPCHK(hipEventCreate(&ev0_));
+        HIPCHK(hipEventCreate(&ev1_));
+        HIPCHK(hipStreamSynchronize(stream_));
+        tau_ = opt_.pinv_tau > 0 ? opt_.pinv_tau : 64.0 * nb * (mixed_ ? std::ldexp(1.0, -24) : std::ldexp(1.0, -53));
+    }
+
+    ~Solver() override {
+        if (exec_) (void)hipGraphExecDestroy(exec_);
+        if (graph_) (void)hipGraphDestroy(graph_);
+        if (cap_stream_) (void)hipStreamDestroy(cap_stream_);
+        if (ctl_) (void)hipFree(ctl_);
+        if (ctl_free_) (void)hipFree(ctl_free_);
+        if (hctl_) (void)hipHostFree(hctl_);
+        if (hctl_in_) (void)hipHostFree(hctl_in_);
+        if (ev0_) (void)hipEventDestroy(ev0_);
+        if (ev1_) (void)hipEventDestroy(ev1_);
+    }
+
+    int solve(const double* b_dev, double* x_dev, double tol, int maxit, amgmpcg_info* info) override {
+        const int N = N_[L_];
+        if (maxit <= 0) maxit = opt_.maxit;
+        if (!graph_ready_) capture_graph();
+        Ctl& c = *hctl_in_;
+        std::memset(&c, 0, sizeof(Ctl));
+        c.maxit = maxit;
+        c.hist_cap = std::min(hist_cap_, maxit);
+        c.drop2 = opt_.refresh_drop * opt_.refresh_drop;
+        c.tau = tau_;
+        HIPCHK(hipEventRecord(ev0_, stream_));
+        HIPCHK(hipMemcpyAsync(ctl_, hctl_in_, sizeof(Ctl), hipMemcpyHostToDevice, stream_));
+        HIPCHK(hipMemcpyAsync(b_.p, b_dev, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, stream_));
+        HIPCHK(hipMemcpyAsync(x_.p, x_dev, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, stream_));
+        enqueue_init(tol);
+        HIPCHK(hipGetLastError());
+        const int launches_max = maxit / opt_.k_poll + 3;
+        for (int launch = 0; launch < launches_max; ++launch) {
+            HIPCHK(hipMemcpyAsync(hctl_, ctl_, sizeof(Ctl), hipMemcpyDeviceToHost, stream_));
+            HIPCHK(hipStreamSynchronize(stream_));
+            if (hctl_->state == 2) break;
+            HIPCHK(hipGraphLaunch(exec_, stream_));
+        }
+        HIPCHK(hipMemcpyAsync(x_dev, x_.p, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, stream_));
+        HIPCHK(hipEventRecord(ev1_, stream_));
+        HIPCHK(hipMemcpyAsync(hctl_, ctl_, sizeof(Ctl), hipMemcpyDeviceToHost, stream_));
+        HIPCHK(hipStreamSynchronize(stream_));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, ev0_, ev1_));
+        const Ctl& h = *hctl_;
+        last_iters_ = h.it;
+        int status = h.state == 2 ? h.status : AMGMPCG_MAXIT;
+        if (info) {
+            info->status = status;
+            info->iterations = h.it;
+            info->bnorm = std::sqrt(h.bnorm2);
+            info->relres = h.bnorm2 > 0 ? std::sqrt(h.rho / h.bnorm2) : 0.0;
+            info->refreshes = h.refreshes;
+            info->nb = nb;
+            info->solve_ms = ms;
+        }
+        return status;
+    }
+
+    void mg_block(const double* r_dev, double* Z_dev) override {
+        enqueue_mg(ctl_free_, r_dev);
+        const int N = N_[L_];
+        dispatch_nb([&](auto nbc) {
+            constexpr int NB = decltype(nbc)::value;
+            k_write_Z<DIM, T, NB><<<(N + kBlock - 1) / kBlock, kBlock, 0, stream_>>>(
+                n_axis[L_], N, fine_cols(), L_ > 0 ? n_axis[L_ - 1] : 1, cL_final_, Z_dev);
+        });
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(stream_));
+    }
+
+    void level_stencil(int level, double* out) override {
+        if (level < 0 || level >= L_) throw ApiError(AMGMPCG_INVALID_ARG, "level must be a coarse level");
+        const size_t cnt = (size_t)(DIM == 2 ? 9 : 27) * N_[level];
+        std::vector<T> tmp(cnt);
+        HIPCHK(hipMemcpyAsync(tmp.data(), coef_[level].p, cnt * sizeof(T), hipMemcpyDeviceToHost, stream_));
+        HIPCHK(hipStreamSynchronize(stream_));
+        for (size_t i = 0; i < cnt; ++i) out[i] = double(tmp[i]);
+    }
+
+    void history(int cap, double* alpha, double* res, int* count) override {
+        const int k = std::min(std::min(last_iters_, hist_cap_), cap);
+        if (count) *count = k;
+        if (hist_cap_ == 0) {
+            if (count) *count = 0;
+            return;
+        }
+        if (alpha && k > 0)
+            HIPCHK(hipMemcpyAsync(alpha, ahist_.p, (size_t)k * nb * sizeof(double), hipMemcpyDeviceToHost, stream_));
+        if (res) HIPCHK(hipMemcpyAsync(res, rhist_.p, (size_t)(k + 1) * sizeof(double), hipMemcpyDeviceToHost, stream_));
+        HIPCHK(hipStreamSynchronize(stream_));
+    }
+
+   private:
+    template <int V>
+    struct IC {
+        static constexpr int value = V;
+    };
+
+    template <typename F>
+    void dispatch_nb(F&& f) {
+        switch (nb) {
+            case 1: f(IC<1>{}); break;
+            case 2: f(IC<2>{}); break;
+            case 3: f(IC<3>{}); break;
+            case 4: f(IC<4>{}); break;
+            case 5: f(IC<5>{}); break;
+            case 6: f(IC<6>{}); break;
+            case 7: f(IC<7>{}); break;
+            case 8: f(IC<8>{}); break;
+            default: throw ApiError(AMGMPCG_INVALID_ARG, "unsupported number of directions");
+        }
+    }
+
+    void upload_faces(const host::FineFaces& f) {
+        const int N = N_[L_];
+        auto up = [&](DevBuf<T>& d, const std::vector<double>& v) {
+            d.alloc(v.size());
+            upload_conv(d.p, v);
+        };
+        up(fD_, f.D);
+        up(fex_, f.ex);
+        up(fey_, f.ey);
+        if (DIM == 3) up(fez_, f.ez);
+        fop_.D = fD_.p;
+        fop_.ex = fex_.p;
+        fop_.ey = fey_.p;
+        fop_.ez = DIM == 3 ? fez_.p : nullptr;
+        if (std::is_same<T, double>::value) {
+            f64_.D = (const double*)fD_.p;
+            f64_.ex = (const double*)fex_.p;
+            f64_.ey = (const double*)fey_.p;
+            f64_.ez = DIM == 3 ? (const double*)fez_.p : nullptr;
+        } else {
+            auto up64 = [&](DevBuf<double>& d, const std::vector<double>& v) {
+                d.alloc(v.size());
+                HIPCHK(hipMemcpy(d.p, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
+            };
+            up64(gD_, f.D);
+            up64(gex_, f.ex);
+            up64(gey_, f.ey);
+            if (DIM == 3) up64(gez_, f.ez);
+            f64_.D = gD_.p;
+            f64_.ex = gex_.p;
+            f64_.ey = gey_.p;
+            f64_.ez = DIM == 3 ? gez_.p : nullptr;
+        }
+        (void)N;
+    }
+
+    void upload_conv(T* dst, const std::vector<double>& src) {
+        std::vector<T> tmp(src.begin(), src.end());
+        HIPCHK(hipMemcpy(dst, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice));
+    }
+
+    // Columns of the level-(L-1) block used to form the fine corrections.
+    ColPtrs<T> fine_cols() const {
+        ColPtrs<T> cp{};
+        if (L_ == 0) return cp;
+        const int l = L_ - 1;
+        for (int c = 0; c < l; ++c) cp.p[c] = Y_[l].p + (size_t)c * N_[l];
+        cp.p[l] = c_final_[l];
+        return cp;
+    }
+
+    // Z = MG(r) up to the coarse block and the fine smoother output.
+    void enqueue_mg(const Ctl* ctl, const double* r) {
+        const int L = L_;
+        const T omega = T(opt_.omega);
+        const int nu = opt_.nu;
+        const int two = nu >= 2 ? 1 : 0;
+        const int extra = nu > 2 ? nu - 2 : 0;
+        // fine smoother
+        {
+            T* first = (extra % 2 == 0) ? cL_.p : cL2_.p;
+            T* other = (extra % 2 == 0) ? cL2_.p : cL_.p;
+            k_fine_smooth<DIM, T, double><<<FB_, kBlock, 0, stream_>>>(ctl, fop_, r, first, omega, two);
+            T* cur = first;
+            for (int s = 0; s < extra; ++s) {
+                T* nxt = (cur == first) ? other : first;
+                k_fine_sweep<DIM, T, double><<<FB_, kBlock, 0, stream_>>>(ctl, fop_, r, cur, nxt, omega);
+                cur = nxt;
+            }
+            cL_final_ = cur;
+        }
+        if (L == 0) return;
+        // restriction chain
+        {
+            const int l = L - 1;
+            k_restrict<DIM, double, T><<<(N_[l] + kBlock - 1) / kBlock, kBlock, 0, stream_>>>(
+                ctl, r, n_axis[L], g_[l].p, n_axis[l], N_[l]);
+            for (int m = L - 2; m >= 0; --m)
+                k_restrict<DIM, T, T><<<(N_[m] + kBlock - 1) / kBlock, kBlock, 0, stream_>>>(
+                    ctl, g_[m + 1].p, n_axis[m + 1], g_[m].p, n_axis[m], N_[m]);
+        }
+        // all coarse levels smoothed in one launch (per sweep)
+        {
+            CoarseLevels<T> cl{};
+            cl.nlev = L;
+            int off = 0;
+            c_final_.assign(nlev, nullptr);
+            std::vector<T*> first(L), other(L);
+            for (int l = 0; l < L; ++l) {
+                cl.blk_off[l] = off;
+                off += (N_[l] + kBlock - 1) / kBlock;
+                cl.n[l] = n_axis[l];
+                cl.N[l] = N_[l];
+                cl.coef[l] = coef_[l].p;
+                cl.g[l] = g_[l].p;
+                first[l] = (extra % 2 == 0) ? c_[l].p : c2_[l].p;
+                other[l] = (extra % 2 == 0) ? c2_[l].p : c_[l].p;
+                cl.cout[l] = first[l];
+                cl.cin[l] = nullptr;
+            }
+            cl.blk_off[L] = off;
+            k_coarse_smooth<DIM, T><<<off, kBlock, 0, stream_>>>(ctl, cl, omega, 0, two);
+            std::vector<T*> cur = first;
+            for (int s = 0; s < extra; ++s) {
+                for (int l = 0; l < L; ++l) {
+                    cl.cin[l] = cur[l];
+                    cl.cout[l] = (cur[l] == first[l]) ? other[l] : first[l];
+                }
+                k_coarse_smooth<DIM, T><<<off, kBlock, 0, stream_>>>(ctl, cl, omega, 1, two);
+                for (int l = 0; l < L; ++l) cur[l] = cl.cout[l];
+            }
+            for (int l = 0; l < L; ++l) c_final_[l] = cur[l];
+        }
+        // prolongation chain: Y_{l+1} = [P Y_l | P c_l]
+        for (int l = 0; l + 1 < L; ++l) {
+            ColPtrs<T> in{};
+            for (int c = 0; c < l; ++c) in.p[c] = Y_[l].p + (size_t)c * N_[l];
+            in.p[l] = c_final_[l];
+            k_prolong<DIM, T><<<(N_[l + 1] + kBlock - 1) / kBlock, kBlock, 0, stream_>>>(
+                ctl, in, l + 1, n_axis[l], Y_[l + 1].p, n_axis[l + 1], N_[l + 1]);
+        }
+    }
+
+    double* part_init() { return part_.p; }
+    double* part_rho() { return part_.p + (size_t)FB_ * 2; }
+    double* part_W() { return part_.p + (size_t)FB_ * 3; }
+    double* part_G() { return part_.p + (size_t)FB_ * (3 + kMaxNB * kMaxNB); }
+    double* part_ref() { return part_.p + (size_t)FB_ * (kPartRow - 1); }
+    double* d_alpha() { return small_.p; }
+    double* d_beta() { return small_.p + kMaxNB; }
+    double* d_Gplus() { return small_.p + kMaxNB + kMaxNB * kMaxNB; }
+
+    void enqueue_init(double tol) {
+        const int N = N_[L_];
+        k_init_residual<DIM><<<FB_, kBlock, 0, stream_>>>(f64_, b_.p, x_.p, r_.p, part_init());
+        k_reduce_init<<<1, kBlock, 0, stream_>>>(ctl_, part_init(), FB_, tol, hist_cap_ ? rhist_.p : nullptr);
+        k_zero_if<<<FB_, kBlock, 0, stream_>>>(ctl_, x_.p, N);
+        enqueue_mg(ctl_, r_.p);
+        dispatch_nb([&](auto nbc) {
+            constexpr int NB = decltype(nbc)::value;
+            const int nc = L_ > 0 ? n_axis[L_ - 1] : 1;
+            k_update_xP<DIM, T, NB><<<FB_, kBlock, 0, stream_>>>(ctl_, n_axis[L_], N, fine_cols(), nc, cL_final_,
+                                                                   P_.p, x_.p, d_alpha(), d_beta(), 1);
+            k_spmm_gram<DIM, T, NB><<<FB_, kBlock, 0, stream_>>>(ctl_, fop_, P_.p, Q_.p, r_.p, part_G());
+            k_reduce_alpha<NB><<<1, kBlock, 0, stream_>>>(ctl_, part_G(), FB_, d_Gplus(), d_alpha(),
+                                                          hist_cap_ ? ahist_.p : nullptr);
+        });
+    }
+
+    void enqueue_iteration(hipStream_t s) {
+        const int N = N_[L_];
+        hipStream_t saved = stream_;
+        stream_ = s;
+        dispatch_nb([&](auto nbc) {
+            constexpr int NB = decltype(nbc)::value;
+            const int nc = L_ > 0 ? n_axis[L_ - 1] : 1;
+            k_update_r<T, NB><<<FB_, kBlock, 0, s>>>(ctl_, N, Q_.p, d_alpha(), r_.p, part_rho());
+            enqueue_mg(ctl_, r_.p);
+            k_fine_W<DIM, T, NB><<<FB_, kBlock, 0, s>>>(ctl_, n_axis[L_], N, fine_cols(), nc, cL_final_, Q_.p,
+                                                         part_W());
+            k_reduce_beta<NB><<<1, kBlock, 0, s>>>(ctl_, part_rho(), part_W(), FB_, d_Gplus(), d_beta(),
+                                                   hist_cap_ ? rhist_.p : nullptr, mixed_ ? 1 : 0);
+            k_update_xP<DIM, T, NB><<<FB_, kBlock, 0, s>>>(ctl_, n_axis[L_], N, fine_cols(), nc, cL_final_, P_.p,
+                                                            x_.p, d_alpha(), d_beta(), 0);
+            if (mixed_) {
+                k_refresh<DIM><<<FB_, kBlock, 0, s>>>(ctl_, f64_, b_.p, x_.p, r_.p, part_ref());
+                k_refresh_reduce<<<1, kBlock, 0, s>>>(ctl_, part_ref(), FB_, hist_cap_ ? rhist_.p : nullptr);
+            }
+            k_spmm_gram<DIM, T, NB><<<FB_, kBlock, 0, s>>>(ctl_, fop_, P_.p, Q_.p, r_.p, part_G());
+            k_reduce_alpha<NB><<<1, kBlock, 0, s>>>(ctl_, part_G(), FB_, d_Gplus(), d_alpha(),
+                                                    hist_cap_ ? ahist_.p : nullptr);
+        });
+        stream_ = saved;
+    }
+
+    void capture_graph() {
+        HIPCHK(hipStreamCreateWithFlags(&cap_stream_, hipStreamNonBlocking));
+        HIPCHK(hipStreamBeginCapture(cap_stream_, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < opt_.k_poll; ++k) enqueue_iteration(cap_stream_);
+        hipError_t launch_err = hipGetLastError();
+        HIPCHK(hipStreamEndCapture(cap_stream_, &graph_));
+        HIPCHK(launch_err);
+        HIPCHK(hipGraphInstantiate(&exec_, graph_, nullptr, nullptr, 0));
+        graph_ready_ = true;
+    }
+
+    amgmpcg_options opt_;
+    hipStream_t stream_;
+    hipStream_t cap_stream_ = nullptr;
+    hipGraph_t graph_ = nullptr;
+    hipGraphExec_t exec_ = nullptr;
+    bool graph_ready_ = false;
+    bool mixed_ = false;
+    int L_ = 0, FB_ = 1, hist_cap_ = 0, last_iters_ = 0;
+    double tau_ = 0.0;
+    std::vector<int> N_;
+    FineOp<T> fop_{};
+    FineOp<double> f64_{};
+    DevBuf<T> fD_, fex_, fey_, fez_;
+    DevBuf<double> gD_, gex_, gey_, gez_;
+    std::vector<DevBuf<T>> coef_, g_, c_, c2_, Y_;
+    std::vector<T*> c_final_;
+    T* cL_final_ = nullptr;
+    DevBuf<double> x_, r_, b_, part_, small_, ahist_, rhist_;
+    DevBuf<T> P_, Q_, cL_, cL2_;
+    Ctl* ctl_ = nullptr;
+    Ctl* ctl_free_ = nullptr;
+    Ctl* hctl_ = nullptr;
+    Ctl* hctl_in_ = nullptr;
+    hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
+};
+
+}  // namespace amg
+
+struct amgmpcg_handle {
+    std::unique_ptr<amg::SolverBase> s;
+};
+
+using amg::ApiError;
+
+template <typename F>
+static int guarded(F&& f) {
+    try {
+        amg::g_last_error.clear();
+        return f();
+    } catch (const ApiError& e) {
+        amg::g_last_error = e.what();
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        amg::g_last_error = "host out of memory";
+        return AMGMPCG_OOM;
+    } catch (const std::exception& e) {
+        amg::g_last_error = e.what();
+        return AMGMPCG_HIP_ERROR;
+    }
+}
+
+static void validate_options(const amgmpcg_options* o) {
+    if (!o) throw ApiError(AMGMPCG_INVALID_ARG, "options pointer is NULL");
+    if (o->m != 1) throw ApiError(AMGMPCG_INVALID_ARG, "only the truncation window m = 1 is implemented");
+    if (o->nu < 1 || o->nu > 8) throw ApiError(AMGMPCG_INVALID_ARG, "nu must be in 1..8");
+    if (!(o->omega > 0.0 && o->omega <= 1.0)) throw ApiError(AMGMPCG_INVALID_ARG, "omega must be in (0, 1]");
+    if (o->maxit < 1) throw ApiError(AMGMPCG_INVALID_ARG, "maxit must be >= 1");
+    if (o->precision != 0 && o->precision != 1) throw ApiError(AMGMPCG_INVALID_ARG, "precision must be 0 or 1");
+    if (o->k_poll < 1 || o->k_poll > 64) throw ApiError(AMGMPCG_INVALID_ARG, "k_poll must be in 1..64");
+    if (!(o->refresh_drop > 0.0 && o->refresh_drop < 1.0))
+        throw ApiError(AMGMPCG_INVALID_ARG, "refresh_drop must be in (0, 1)");
+}
+
+static void validate_grid(const amgmpcg_grid* g) {
+    if (!g) throw ApiError(AMGMPCG_INVALID_ARG, "grid pointer is NULL");
+    if (g->dim != 2 && g->dim != 3) throw ApiError(AMGMPCG_INVALID_ARG, "dim must be 2 or 3");
+    if (g->n < 1) throw ApiError(AMGMPCG_INVALID_ARG, "n must be >= 1");
+    if (g->nlevels < 1 || g->nlevels > amg::kMaxNB) throw ApiError(AMGMPCG_INVALID_ARG, "nlevels must be in 1..8");
+    const double total = std::pow((double)g->n, g->dim);
+    if (total > 1.0e9) throw ApiError(AMGMPCG_INVALID_ARG, "grid too large");
+    int n = g->n;
+    for (int l = 1; l < g->nlevels; ++l) {
+        n /= 2;
+        if (n < 1) throw ApiError(AMGMPCG_DIM_MISMATCH, "grid too small for the requested number of levels");
+    }
+    if (g->kappa) {
+        const int64_t m = (int64_t)std::llround(std::pow((double)(g->n + 2), g->dim));
+        for (int64_t i = 0; i < m; ++i) {
+            const double k = g->kappa[i];
+            if (!std::isfinite(k)) throw ApiError(AMGMPCG_NONFINITE, "kappa has a non-finite value");
+            if (!(k > 0.0)) throw ApiError(AMGMPCG_NOT_SPD, "kappa must be positive");
+        }
+    }
+}
+
+extern "C" {
+
+void amgmpcg_default_options(amgmpcg_options* o) {
+    if (!o) return;
+    o->m = 1;
+    o->nu = 2;
+    o->omega = 2.0 / 3.0;
+    o->maxit = 1000;
+    o->precision = 0;
+    o->pinv_tau = 0.0;
+    o->k_poll = 8;
+    o->record_history = 1;
+    o->refresh_drop = 1e-2;
+}
+
+int amgmpcg_setup_grid(const amgmpcg_grid* grid, const amgmpcg_options* opts, void* stream, amgmpcg_handle** out) {
+    return guarded([&]() -> int {
+        if (!out) throw ApiError(AMGMPCG_INVALID_ARG, "out pointer is NULL");
+        *out = nullptr;
+        validate_grid(grid);
+        validate_options(opts);
+        auto h = std::make_unique<amgmpcg_handle>();
+        hipStream_t s = (hipStream_t)stream;
+        if (opts->precision == 0) {
+            if (grid->dim == 2) h->s.reset(new amg::Solver<double, 2>(*grid, *opts, s));
+            else h->s.reset(new amg::Solver<double, 3>(*grid, *opts, s));
+        } else {
+            if (grid->dim == 2) h->s.reset(new amg::Solver<float, 2>(*grid, *opts, s));
+            else h->s.reset(new amg::Solver<float, 3>(*grid, *opts, s));
+        }
+        *out = h.release();
+        return AMGMPCG_OK;
+    });
+}
+
+int amgmpcg_solve(amgmpcg_handle* h, const double* b_dev, double* x_dev, double tol, int32_t maxit,
+                  amgmpcg_info* info) {
+    return guarded([&]() -> int {
+        if (!h || !h->s) throw ApiError(AMGMPCG_INVALID_ARG, "handle is NULL");
+        if (!b_dev || !x_dev) throw ApiError(AMGMPCG_INVALID_ARG, "b or x is NULL");
+        if (!(tol >= 0.0) || !std::isfinite(tol)) throw ApiError(AMGMPCG_INVALID_ARG, "tol must be finite and >= 0");
+        return h->s->solve(b_dev, x_dev, tol, maxit, info);
+    });
+}
+
+int amgmpcg_solve_host(amgmpcg_handle* h, const double* b, double* x, double tol, int32_t maxit,
+                       amgmpcg_info* info) {
+    return guarded([&]() -> int {
+        if (!h || !h->s) throw ApiError(AMGMPCG_INVALID_ARG, "handle is NULL");
+        if (!b || !x) throw ApiError(AMGMPCG_INVALID_ARG, "b or x is NULL");
+        int n = h->s->n_axis.back();
+        size_t N = (size_t)std::llround(std::pow((double)n, h->s->dim));
+        double *db = nullptr, *dx = nullptr;
+        HIPCHK(hipMalloc((void**)&db, N * sizeof(double)));
+        hipError_t e = hipMalloc((void**)&dx, N * sizeof(double));
+        if (e != hipSuccess) {
+            (void)hipFree(db);
+            HIPCHK(e);
+        }
+        int st;
+        try {
+            HIPCHK(hipMemcpy(db, b, N * sizeof(double), hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(dx, x, N * sizeof(double), hipMemcpyHostToDevice));
+            st = h->s->solve(db, dx, tol, maxit, info);
+            HIPCHK(hipMemcpy(x, dx, N * sizeof(double), hipMemcpyDeviceToHost));
+        } catch (...) {
+            (void)hipFree(db);
+            (void)hipFree(dx);
+            throw;
+        }
+        (void)hipFree(db);
+        (void)hipFree(dx);
+        return st;
+    });
+}
+
+int amgmpcg_mg_block(amgmpcg_handle* h, const double* r_dev, double* Z_dev) {
+    return guarded([&]() -> int {
+        if (!h || !h->s) throw ApiError(AMGMPCG_INVALID_ARG, "handle is NULL");
+        if (!r_dev || !Z_dev) throw ApiError(AMGMPCG_INVALID_ARG, "r or Z is NULL");
+        h->s->mg_block(r_dev, Z_dev);
+        return AMGMPCG_OK;
+    });
+}
+
+int amgmpcg_level_count(const amgmpcg_handle* h, int32_t* nlevels, int32_t* nb) {
+    return guarded([&]() -> int {
+        if (!h || !h->s) throw ApiError(AMGMPCG_INVALID_ARG, "handle is NULL");
+        if (nlevels) *nlevels = h->s->nlev;
+        if (nb) *nb = h->s->nb;
+        return AMGMPCG_OK;
+    });
+}
+
+int amgmpcg_level_size(const amgmpcg_handle* h, int32_t level, int32_t* n_axis) {
+    return guarded([&]() -> int {
+        if (!h || !h->s || !n_axis) throw ApiError(AMGMPCG_INVALID_ARG, "NULL argument");
+        if (level < 0 || level >= h->s->nlev) throw ApiError(AMGMPCG_INVALID_ARG, "level out of range");
+        *n_axis = h->s->n_axis[level];
+        return AMGMPCG_OK;
+    });
+}
+
+int amgmpcg_level_stencil(const amgmpcg_handle* h, int32_t level, double* out) {
+    return guarded([&]() -> int {
+        if (!h || !h->s || !out) throw ApiError(AMGMPCG_INVALID_ARG, "NULL argument");
+        h->s->level_stencil(level, out);
+        return AMGMPCG_OK;
+    });
+}
+
+int amgmpcg_history(const amgmpcg_handle* h, int32_t cap, double* alpha_out, double* resnorm_out, int32_t* count) {
+    return guarded([&]() -> int {
+        if (!h || !h->s) throw ApiError(AMGMPCG_INVALID_ARG, "handle is NULL");
+        if (cap < 0) throw ApiError(AMGMPCG_INVALID_ARG, "cap must be >= 0");
+        int c = 0;
+        h->s->history(cap, alpha_out, resnorm_out, &c);
+        if (count) *count = c;
+        return AMGMPCG_OK;
+    });
+}
+
+void amgmpcg_destroy(amgmpcg_handle* h) { delete h; }
+
+const char* amgmpcg_status_string(int s) {
+    switch (s) {
+        case AMGMPCG_OK: return "converged";
+        case AMGMPCG_MAXIT: return "iteration limit reached";
+        case AMGMPCG_BREAKDOWN: return "breakdown: every search direction dropped";
+        case AMGMPCG_INVALID_ARG: return "invalid argument";
+        case AMGMPCG_NOT_SPD: return "operator not SPD (non-positive diagonal)";
+        case AMGMPCG_DIM_MISMATCH: return "dimension mismatch";
+        case AMGMPCG_NONFINITE: return "non-finite value";
+        case AMGMPCG_OOM: return "out of memory";
+        case AMGMPCG_HIP_ERROR: return "HIP runtime error";
+        default: return "unknown status";
+    }
+}
+
+const char* amgmpcg_last_error(void) { return amg::g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,100 @@
+// Shared device helpers: control word, launch geometry, deterministic
+// block reductions.  gfx950: 64-wide wavefronts, 256-thread blocks.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace amg {
+
+constexpr int kBlock = 256;        // threads per block (4 wavefronts)
+constexpr int kWaves = kBlock / 64;
+constexpr int kMaxLevels = 8;
+constexpr int kMaxNB = 8;          // search directions per iteration (L + 1 [+ 1])
+constexpr int kNumXcd = 8;         // MI355X: 8 XCDs, blocks dispatched round-robin
+
+// Solver control word in device memory.  Only single-block kernels write it;
+// every other kernel reads `state` once at entry and exits early unless the
+// iteration is still running, so iterations launched after convergence are
+// no-ops and the count stays exact.
+struct Ctl {
+    int state;        // 0 running, 1 stop after the pending x update, 2 finished
+    int it;           // number of x updates
+    int status;       // AMGMPCG_* status once finished
+    int refreshes;    // true-residual refreshes (FP32 bulk)
+    int refresh_req;  // 1: refresh r = b - A x after this iteration's x update
+    int rank;         // rank of the last Gram pseudo-inverse
+    int maxit;
+    int zero_x;       // 1: b == 0, the solution is x = 0
+    int hist_cap;     // capacity of the history buffers (iterations)
+    int pad0, pad1, pad2;
+    double bnorm2;    // ||b||^2
+    double tol2;      // tol^2 ||b||^2
+    double rho;       // ||r||^2 of the current residual
+    double rho_ref;   // ||r||^2 at the last refresh
+    double drop2;     // refresh_drop^2
+    double tau;       // eigenvalue cut of the unit-diagonal Gram
+};
+
+// Logical block index so that each XCD (blockIdx % 8) owns a contiguous range
+// of logical blocks, hence a contiguous slab of the grid: stencil neighbours in
+// y and z are then mostly produced and consumed inside the same XCD's L2.
+__device__ __forceinline__ int xcd_block(int nblocks) {
+    const int b = blockIdx.x;
+    if (nblocks % kNumXcd) return b;
+    return (b % kNumXcd) * (nblocks / kNumXcd) + b / kNumXcd;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Sum K per-thread values over the block in a fixed order and let thread k
+// (k < K) write value k to out[k].  Deterministic: butterfly within each wave,
+// then the wave sums in wave order.
+template <int K>
+__device__ __forceinline__ void block_sum_store(double (&v)[K], double* out) {
+    __shared__ double sh[kWaves][K > 0 ? K : 1];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double s = wave_sum(v[k]);
+        if (lane == 0) sh[w][k] = s;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < K; k += kBlock) {
+        double s = sh[0][k];
+#pragma unroll
+        for (int q = 1; q < kWaves; ++q) s += sh[q][k];
+        out[k] = s;
+    }
+    __syncthreads();
+}
+
+// Reduce nblk partial rows of K doubles (row-major part[b*K + k]) into
+// res[k] (shared memory), inside one block, in a fixed order.
+template <int K>
+__device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int nblk,
+                                                double* res /* shared, K */) {
+    constexpr int R = (kBlock / K) > 0 ? (kBlock / K) : 1;   // rows of threads
+    __shared__ double sh[R][K];
+    const int t = threadIdx.x;
+    if (t < R * K) {
+        const int k = t % K, r0 = t / K;
+        double s = 0.0;
+        for (int b = r0; b < nblk; b += R) s += part[(size_t)b * K + k];
+        sh[r0][k] = s;
+    }
+    __syncthreads();
+    if (t < K) {
+        double s = sh[0][t];
+        for (int r = 1; r < R; ++r) s += sh[r][t];
+        res[t] = s;
+    }
+    __syncthreads();
+}
+
+}  // namespace amg

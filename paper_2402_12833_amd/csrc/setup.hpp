@@ -1,0 +1,239 @@
+// Host-side hierarchy construction (Sec. 2.1): the finest FD operator as a
+// 3^d-point stencil, Galerkin coarse operators A_c = R A_f P with
+// R = 2^-d P^T (tensor linear interpolation, coarse node J on fine node 2J+1),
+// symmetrised by mirroring the upper triangle.  Multithreaded over coarse
+// planes; deterministic (each coarse entry is summed by one thread in a
+// fixed order).
+#pragma once
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <stdexcept>
+#include <thread>
+#include <vector>
+
+namespace amg {
+namespace host {
+
+struct StencilLevel {
+    int dim = 0, n = 0;
+    int64_t N = 0;
+    std::vector<double> coef;   // S * N, coef[s*N + idx] = A(idx, idx + o_s)
+    int S() const { return dim == 2 ? 9 : 27; }
+    int center() const { return dim == 2 ? 4 : 13; }
+};
+
+// Face data of the finest operator: diagonal and +x/+y/+z couplings
+// (positive numbers, e[idx] = -A(idx, idx + e)), all h^-2 scaled.
+struct FineFaces {
+    std::vector<double> D, ex, ey, ez;
+};
+
+inline int64_t ipow(int64_t a, int e) {
+    int64_t r = 1;
+    while (e-- > 0) r *= a;
+    return r;
+}
+
+template <typename F>
+inline void parallel_for(int count, F&& body) {
+    int nt = (int)std::thread::hardware_concurrency();
+    nt = std::max(1, std::min(nt, std::min(count, 32)));
+    if (nt == 1) {
+        for (int i = 0; i < count; ++i) body(i);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t)
+        th.emplace_back([&, t]() {
+            for (int i = t; i < count; i += nt) body(i);
+        });
+    for (auto& x : th) x.join();
+}
+
+// Harmonic-mean FD operator.  kappa: (n+2)^dim node values (x fastest) or
+// nullptr for kappa == 1.
+inline FineFaces fine_faces(int dim, int n, const double* kappa) {
+    const int64_t N = ipow(n, dim);
+    const double h2inv = double(n + 1) * double(n + 1);
+    FineFaces f;
+    f.D.assign(N, 0.0);
+    f.ex.assign(N, 0.0);
+    f.ey.assign(N, 0.0);
+    f.ez.assign(dim == 3 ? N : 0, 0.0);
+    const int m = n + 2;
+    auto K = [&](int i, int j, int k) -> double {   // node-grid coords incl. boundary
+        if (!kappa) return 1.0;
+        return kappa[i + (int64_t)m * (j + (int64_t)m * (dim == 3 ? k : 0))];
+    };
+    auto hm = [](double a, double b) { return 2.0 * a * b / (a + b); };
+    const int nz = dim == 3 ? n : 1;
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                const int64_t idx = i + (int64_t)n * (j + (int64_t)n * k);
+                const int I = i + 1, J = j + 1, Kk = dim == 3 ? k + 1 : 0;
+                const double kc = K(I, J, Kk);
+                double d = 0.0;
+                const double fxm = hm(kc, K(I - 1, J, Kk)), fxp = hm(kc, K(I + 1, J, Kk));
+                const double fym = hm(kc, K(I, J - 1, Kk)), fyp = hm(kc, K(I, J + 1, Kk));
+                d += fxm + fxp + fym + fyp;
+                f.ex[idx] = h2inv * fxp;
+                f.ey[idx] = h2inv * fyp;
+                if (dim == 3) {
+                    const double fzm = hm(kc, K(I, J, Kk - 1)), fzp = hm(kc, K(I, J, Kk + 1));
+                    d += fzm + fzp;
+                    f.ez[idx] = h2inv * fzp;
+                }
+                f.D[idx] = h2inv * d;
+            }
+    return f;
+}
+
+inline StencilLevel faces_to_stencil(int dim, int n, const FineFaces& f) {
+    StencilLevel L;
+    L.dim = dim;
+    L.n = n;
+    L.N = ipow(n, dim);
+    const int S = L.S();
+    L.coef.assign((size_t)S * L.N, 0.0);
+    const int nz = dim == 3 ? n : 1;
+    auto sidx = [&](int dx, int dy, int dz) { return dim == 2 ? (dy + 1) * 3 + (dx + 1) : (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1); };
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                const int64_t idx = i + (int64_t)n * (j + (int64_t)n * k);
+                const int64_t sy = n, sz = (int64_t)n * n;
+                L.coef[(size_t)sidx(0, 0, 0) * L.N + idx] = f.D[idx];
+                if (i > 0) L.coef[(size_t)sidx(-1, 0, 0) * L.N + idx] = -f.ex[idx - 1];
+                if (i < n - 1) L.coef[(size_t)sidx(1, 0, 0) * L.N + idx] = -f.ex[idx];
+                if (j > 0) L.coef[(size_t)sidx(0, -1, 0) * L.N + idx] = -f.ey[idx - sy];
+                if (j < n - 1) L.coef[(size_t)sidx(0, 1, 0) * L.N + idx] = -f.ey[idx];
+                if (dim == 3) {
+                    if (k > 0) L.coef[(size_t)sidx(0, 0, -1) * L.N + idx] = -f.ez[idx - sz];
+                    if (k < n - 1) L.coef[(size_t)sidx(0, 0, 1) * L.N + idx] = -f.ez[idx];
+                }
+            }
+    return L;
+}
+
+// Galerkin product R A P for one level; nc = floor(nf / 2).
+inline StencilLevel galerkin(const StencilLevel& F) {
+    const int dim = F.dim, nf = F.n, nc = nf / 2;
+    if (nc < 1) throw std::invalid_argument("grid too small for another level");
+    StencilLevel C;
+    C.dim = dim;
+    C.n = nc;
+    C.N = ipow(nc, dim);
+    const int S = F.S();
+    C.coef.assign((size_t)S * C.N, 0.0);
+    const int nzc = dim == 3 ? nc : 1;
+    const double rscale = dim == 3 ? 0.125 : 0.25;
+    // per-axis parents of a fine coordinate
+    auto par = [&](int f, int* J, double* w) -> int {
+        if (f & 1) {
+            J[0] = (f - 1) / 2;
+            w[0] = 1.0;
+            return 1;
+        }
+        int c = 0;
+        const int Jm = f / 2;
+        if (Jm - 1 >= 0) { J[c] = Jm - 1; w[c++] = 0.5; }
+        if (Jm < nc) { J[c] = Jm; w[c++] = 0.5; }
+        return c;
+    };
+    parallel_for(nzc, [&](int cz) {
+        for (int cy = 0; cy < nc; ++cy)
+            for (int cx = 0; cx < nc; ++cx) {
+                const int64_t I = cx + (int64_t)nc * (cy + (int64_t)nc * cz);
+                double acc[27] = {0};
+                const int zlo = dim == 3 ? -1 : 0, zhi = dim == 3 ? 1 : 0;
+                for (int az = zlo; az <= zhi; ++az) {
+                    const int fz = dim == 3 ? 2 * cz + 1 + az : 0;
+                    if (dim == 3 && fz >= nf) continue;
+                    const double wz = az ? 0.5 : 1.0;
+                    for (int ay = -1; ay <= 1; ++ay) {
+                        const int fy = 2 * cy + 1 + ay;
+                        if (fy >= nf) continue;
+                        const double wy = ay ? 0.5 : 1.0;
+                        for (int ax = -1; ax <= 1; ++ax) {
+                            const int fx = 2 * cx + 1 + ax;
+                            if (fx >= nf) continue;
+                            const double wi = (ax ? 0.5 : 1.0) * wy * wz;
+                            const int64_t fidx = fx + (int64_t)nf * (fy + (int64_t)nf * fz);
+                            int s = 0;
+                            for (int oz = zlo; oz <= zhi; ++oz)
+                                for (int oy = -1; oy <= 1; ++oy)
+                                    for (int ox = -1; ox <= 1; ++ox, ++s) {
+                                        const double a = F.coef[(size_t)s * F.N + fidx];
+                                        if (a == 0.0) continue;
+                                        const int jx = fx + ox, jy = fy + oy, jz = fz + oz;
+                                        if (jx < 0 || jx >= nf || jy < 0 || jy >= nf) continue;
+                                        if (dim == 3 && (jz < 0 || jz >= nf)) continue;
+                                        int Jx[2], Jy[2], Jz[2] = {0, 0};
+                                        double wx_[2], wy_[2], wz_[2] = {1.0, 1.0};
+                                        const int nx_ = par(jx, Jx, wx_), ny_ = par(jy, Jy, wy_);
+                                        const int nz_ = dim == 3 ? par(jz, Jz, wz_) : 1;
+                                        for (int c3 = 0; c3 < nz_; ++c3)
+                                            for (int c2 = 0; c2 < ny_; ++c2)
+                                                for (int c1 = 0; c1 < nx_; ++c1) {
+                                                    const int dx = Jx[c1] - cx, dy = Jy[c2] - cy;
+                                                    const int dz = dim == 3 ? Jz[c3] - cz : 0;
+                                                    const int so = dim == 2 ? (dy + 1) * 3 + (dx + 1)
+                                                                            : (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+                                                    acc[so] += wi * a * (wx_[c1] * wy_[c2] * wz_[c3]);
+                                                }
+                                    }
+                        }
+                    }
+                }
+                for (int s = 0; s < S; ++s) C.coef[(size_t)s * C.N + I] = rscale * acc[s];
+            }
+    });
+    // symmetrise: entries below the diagonal (s < centre) mirror the upper ones
+    const int ctr = C.center();
+    std::vector<double> sym(C.coef);
+    for (int cz = 0; cz < nzc; ++cz)
+        for (int cy = 0; cy < nc; ++cy)
+            for (int cx = 0; cx < nc; ++cx) {
+                const int64_t I = cx + (int64_t)nc * (cy + (int64_t)nc * cz);
+                int s = 0;
+                const int zlo = dim == 3 ? -1 : 0, zhi = dim == 3 ? 1 : 0;
+                for (int oz = zlo; oz <= zhi; ++oz)
+                    for (int oy = -1; oy <= 1; ++oy)
+                        for (int ox = -1; ox <= 1; ++ox, ++s) {
+                            if (s >= ctr) continue;
+                            const int jx = cx + ox, jy = cy + oy, jz = cz + oz;
+                            const bool in = jx >= 0 && jx < nc && jy >= 0 && jy < nc &&
+                                            (dim == 2 || (jz >= 0 && jz < nc));
+                            double v = 0.0;
+                            if (in) {
+                                const int64_t Jn = jx + (int64_t)nc * (jy + (int64_t)nc * (dim == 3 ? jz : 0));
+                                v = C.coef[(size_t)(S - 1 - s) * C.N + Jn];
+                            }
+                            sym[(size_t)s * C.N + I] = v;
+                        }
+            }
+    // neighbours outside the grid carry no coefficient
+    for (int cz = 0; cz < nzc; ++cz)
+        for (int cy = 0; cy < nc; ++cy)
+            for (int cx = 0; cx < nc; ++cx) {
+                const int64_t I = cx + (int64_t)nc * (cy + (int64_t)nc * cz);
+                int s = 0;
+                const int zlo = dim == 3 ? -1 : 0, zhi = dim == 3 ? 1 : 0;
+                for (int oz = zlo; oz <= zhi; ++oz)
+                    for (int oy = -1; oy <= 1; ++oy)
+                        for (int ox = -1; ox <= 1; ++ox, ++s) {
+                            const int jx = cx + ox, jy = cy + oy, jz = cz + oz;
+                            const bool in = jx >= 0 && jx < nc && jy >= 0 && jy < nc &&
+                                            (dim == 2 || (jz >= 0 && jz < nc));
+                            if (!in) sym[(size_t)s * C.N + I] = 0.0;
+                        }
+            }
+    C.coef.swap(sym);
+    return C;
+}
+
+}  // namespace host
+}  // namespace amg

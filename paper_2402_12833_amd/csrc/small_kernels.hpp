@@ -1,0 +1,222 @@
+// Single-block kernels: the global reductions of one iteration, the b x b
+// pseudo-inverse of the Gram matrix, the step coefficients alpha and beta,
+// convergence and stop logic.  They run as one 256-thread block; the
+// eigen-decomposition runs in wavefront 0 with one Gram entry per lane.
+#pragma once
+
+#include "common.hpp"
+
+namespace amg {
+
+// Status codes mirrored from the public header (kept numerically equal).
+constexpr int kOK = 0, kMAXIT = 1, kBREAKDOWN = 2, kNONFINITE = -4;
+
+// Pseudo-inverse of a symmetric PSD NB x NB matrix G (row-major, shared
+// memory) by cyclic Jacobi on the unit-diagonal scaling Ghat = S G S,
+// S = diag(G_ii^{-1/2}) over the active columns (finite, positive diagonal).
+// Eigenvalues <= tau are dropped; G^+ = S V Lambda^+ V^T S.  Must be called
+// by all 64 lanes of one wavefront; lane l < NB*NB owns entry (l / NB, l % NB).
+// Writes Gplus (row-major) and returns the rank to every lane.
+template <int NB>
+__device__ int wave_pinv(const double* G, double tau, double* Gplus) {
+    const int lane = threadIdx.x & 63;
+    const bool live = lane < NB * NB;
+    const int i = live ? lane / NB : 0, j = live ? lane % NB : 0;
+    const double gii = G[i * NB + i], gjj = G[j * NB + j], gij = G[i * NB + j];
+    const bool ai = isfinite(gii) && gii > 0.0, aj = isfinite(gjj) && gjj > 0.0;
+    const double si = ai ? 1.0 / sqrt(gii) : 0.0, sj = aj ? 1.0 / sqrt(gjj) : 0.0;
+    const bool bad = live && ai && aj && !isfinite(gij);
+    if (__any(bad)) {
+        if (live) Gplus[lane] = 0.0;
+        return 0;
+    }
+    double a = (live && ai && aj) ? (gij * si) * sj : 0.0;
+    double v = (live && i == j) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 30; ++sweep) {
+        const double off = wave_sum((live && i != j) ? a * a : 0.0);
+        const double fro = wave_sum(live ? a * a : 0.0);
+        if (!(off > 1e-30 * fro)) break;
+        for (int p = 0; p < NB - 1; ++p) {
+            for (int q = p + 1; q < NB; ++q) {
+                const double apq = __shfl(a, p * NB + q);
+                if (apq == 0.0) continue;
+                const double app = __shfl(a, p * NB + p), aqq = __shfl(a, q * NB + q);
+                // rotation zeroing (p,q): cot(2 theta) = (aqq - app) / (2 apq)
+                const double zeta = (aqq - app) / (2.0 * apq);
+                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(zeta * zeta + 1.0));
+                const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+                // columns p, q of A J
+                const double aip = __shfl(a, i * NB + p), aiq = __shfl(a, i * NB + q);
+                double bb = a;
+                if (j == p) bb = c * aip - s * aiq;
+                else if (j == q) bb = s * aip + c * aiq;
+                // rows p, q of J^T (A J)
+                const double bpj = __shfl(bb, p * NB + j), bqj = __shfl(bb, q * NB + j);
+                double a2 = bb;
+                if (i == p) a2 = c * bpj - s * bqj;
+                else if (i == q) a2 = s * bpj + c * bqj;
+                if ((i == p && j == q) || (i == q && j == p)) a2 = 0.0;
+                a = live ? a2 : 0.0;
+                // V J
+                const double vip = __shfl(v, i * NB + p), viq = __shfl(v, i * NB + q);
+                if (j == p) v = c * vip - s * viq;
+                else if (j == q) v = s * vip + c * viq;
+            }
+        }
+    }
+    double gp = 0.0;
+    int rank = 0;
+    for (int k = 0; k < NB; ++k) {
+        const double lam = __shfl(a, k * NB + k);
+        const double vik = __shfl(v, i * NB + k), vjk = __shfl(v, j * NB + k);
+        if (lam > tau) {
+            gp += vik * vjk / lam;
+            ++rank;
+        }
+    }
+    if (live) Gplus[lane] = si * gp * sj;
+    return rank;
+}
+
+// After the init residual: ||b||, ||r_0||, stop if r_0 already small.
+__global__ void __launch_bounds__(kBlock) k_reduce_init(Ctl* ctl, const double* part, int nblk, double tol,
+                                                        double* rhist) {
+    __shared__ double res[2];
+    reduce_partials<2>(part, nblk, res);
+    if (threadIdx.x != 0) return;
+    const double bn2 = res[0], rho = res[1];
+    ctl->bnorm2 = bn2;
+    ctl->tol2 = tol * tol * bn2;
+    ctl->rho = rho;
+    ctl->rho_ref = rho;
+    ctl->it = 0;
+    ctl->refreshes = 0;
+    ctl->refresh_req = 0;
+    ctl->zero_x = 0;
+    ctl->status = kOK;
+    ctl->state = 0;
+    if (rhist && ctl->hist_cap > 0) rhist[0] = sqrt(rho);
+    if (bn2 == 0.0) {
+        ctl->zero_x = 1;
+        ctl->state = 2;
+    } else if (!isfinite(rho) || !isfinite(bn2)) {
+        ctl->status = kNONFINITE;
+        ctl->state = 2;
+    } else if (rho <= ctl->tol2) {
+        ctl->state = 2;
+    }
+}
+
+// Residual check of r_{k+1} and beta = G_k^+ W (W = Q_k^T Z_{k+1}).
+// mixed != 0: convergence on the recursive residual only requests a
+// true-residual refresh; the refresh decides.
+template <int NB>
+__global__ void __launch_bounds__(kBlock) k_reduce_beta(Ctl* ctl, const double* part_rho, const double* part_W,
+                                                        int nblk, const double* Gplus, double* beta, double* rhist,
+                                                        int mixed) {
+    if (ctl->state != 0) return;
+    __shared__ double rho_s[1];
+    __shared__ double W[NB * NB];
+    reduce_partials<1>(part_rho, nblk, rho_s);
+    reduce_partials<NB * NB>(part_W, nblk, W);
+    __shared__ int stop;
+    if (threadIdx.x == 0) {
+        const double rho = rho_s[0];
+        const int it = ctl->it + 1;
+        ctl->it = it;
+        ctl->rho = rho;
+        if (rhist && it < ctl->hist_cap + 1) rhist[it] = sqrt(rho);
+        int st = 0;
+        if (!isfinite(rho)) {
+            ctl->status = kNONFINITE;
+            st = 1;
+        } else if (rho <= ctl->tol2 && !mixed) {
+            ctl->status = kOK;
+            st = 1;
+        } else if (it >= ctl->maxit) {
+            ctl->status = kMAXIT;
+            st = 1;
+        } else if (mixed && (rho <= ctl->tol2 || rho <= ctl->drop2 * ctl->rho_ref)) {
+            ctl->refresh_req = 1;
+        }
+        ctl->state = st;
+        stop = st;
+    }
+    __syncthreads();
+    if (stop) return;
+    for (int q = threadIdx.x; q < NB * NB; q += kBlock) {
+        const int a = q / NB, c = q % NB;
+        double s = 0.0;
+        for (int m = 0; m < NB; ++m) s += Gplus[a * NB + m] * W[m * NB + c];
+        beta[q] = s;
+    }
+}
+
+// Gram G = P^T A P (upper triangle mirrored), g = P^T r, pseudo-inverse,
+// alpha = G^+ g.  State 1 (stop after the x update) becomes 2 here.
+template <int NB>
+__global__ void __launch_bounds__(kBlock) k_reduce_alpha(Ctl* ctl, const double* part, int nblk, double* Gplus,
+                                                         double* alpha, double* ahist) {
+    const int state = ctl->state;
+    if (state == 2) return;
+    if (state == 1) {
+        if (threadIdx.x == 0) ctl->state = 2;
+        return;
+    }
+    constexpr int NG = NB * (NB + 1) / 2;
+    __shared__ double red[NG + NB];
+    __shared__ double G[NB * NB];
+    __shared__ double Gp[NB * NB];
+    __shared__ int rank_s;
+    reduce_partials<NG + NB>(part, nblk, red);
+    if (threadIdx.x == 0) {
+        int q = 0;
+        for (int a = 0; a < NB; ++a)
+            for (int c = a; c < NB; ++c, ++q) G[a * NB + c] = G[c * NB + a] = red[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int rk = wave_pinv<NB>(G, ctl->tau, Gp);
+        if (threadIdx.x == 0) rank_s = rk;
+    }
+    __syncthreads();
+    if (threadIdx.x < NB * NB) Gplus[threadIdx.x] = Gp[threadIdx.x];
+    if (threadIdx.x < NB) {
+        double s = 0.0;
+        for (int m = 0; m < NB; ++m) s += Gp[threadIdx.x * NB + m] * red[NG + m];
+        alpha[threadIdx.x] = s;
+        const int it = ctl->it;
+        if (ahist && it < ctl->hist_cap) ahist[(size_t)it * NB + threadIdx.x] = s;
+    }
+    if (threadIdx.x == 0) {
+        ctl->rank = rank_s;
+        if (rank_s == 0) {
+            ctl->status = kBREAKDOWN;
+            ctl->state = 2;
+        }
+    }
+}
+
+// After a true-residual refresh r = b - A x: accept convergence or go on.
+__global__ void __launch_bounds__(kBlock) k_refresh_reduce(Ctl* ctl, const double* part, int nblk, double* rhist) {
+    if (ctl->state == 2 || !ctl->refresh_req) return;
+    __shared__ double res[1];
+    reduce_partials<1>(part, nblk, res);
+    if (threadIdx.x != 0) return;
+    const double rho = res[0];
+    ctl->refresh_req = 0;
+    ctl->refreshes += 1;
+    ctl->rho = rho;
+    ctl->rho_ref = rho;
+    const int it = ctl->it;
+    if (rhist && it < ctl->hist_cap + 1) rhist[it] = sqrt(rho);
+    if (!isfinite(rho)) {
+        ctl->status = kNONFINITE;
+        ctl->state = 2;
+    } else if (rho <= ctl->tol2) {
+        ctl->status = kOK;
+        ctl->state = 2;
+    }
+}
+
+}  // namespace amg

@@ -1,0 +1,89 @@
+"""C-ABI library: loads, exports every declared symbol, validates arguments
+on the host before any device work (no GPU needed for these checks)."""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_2402_12833_amd as amg
+from paper_2402_12833_amd import binding as B
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        from paper_2402_12833_amd import build
+        build.build()
+    return B.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = B.header_functions()
+    assert len(names) >= 10
+    out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], capture_output=True, text=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    for n in names:
+        assert n in exported, n
+        assert hasattr(lib, n)
+
+
+def test_default_options(lib):
+    o = amg.default_options()
+    assert (o.m, o.nu, o.maxit, o.precision, o.k_poll) == (1, 2, 1000, 0, 8)
+    assert o.omega == pytest.approx(2.0 / 3.0)
+    assert o.refresh_drop == pytest.approx(1e-2)
+
+
+def _setup(lib, grid, opts):
+    h = ctypes.c_void_p()
+    code = lib.amgmpcg_setup_grid(ctypes.byref(grid) if grid is not None else None,
+                                  ctypes.byref(opts) if opts is not None else None, None, ctypes.byref(h))
+    return code, h
+
+
+@pytest.mark.parametrize("grid,expect", [
+    (B.Grid(4, 31, 3, None), B.INVALID_ARG),     # dim
+    (B.Grid(2, 0, 1, None), B.INVALID_ARG),      # n
+    (B.Grid(2, 31, 0, None), B.INVALID_ARG),     # levels
+    (B.Grid(2, 31, 9, None), B.INVALID_ARG),     # too many directions
+    (B.Grid(2, 7, 4, None), B.DIM_MISMATCH),     # 7 -> 3 -> 1 -> 0
+])
+def test_grid_validation(lib, grid, expect):
+    code, h = _setup(lib, grid, amg.default_options())
+    assert code == expect
+    assert not h.value
+    assert B.last_error()
+
+
+@pytest.mark.parametrize("kw", [dict(m=5), dict(nu=0), dict(omega=1.5), dict(maxit=0), dict(precision=3),
+                                dict(k_poll=0), dict(refresh_drop=2.0)])
+def test_option_validation(lib, kw):
+    code, _ = _setup(lib, B.Grid(2, 31, 3, None), amg.default_options(**kw))
+    assert code == B.INVALID_ARG
+
+
+def test_kappa_validation(lib):
+    n = 7
+    kap = np.ones((n + 2) ** 2)
+    kap[10] = np.nan
+    g = B.Grid(2, n, 2, kap.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    assert _setup(lib, g, amg.default_options())[0] == B.NONFINITE
+    kap[10] = -1.0
+    assert _setup(lib, g, amg.default_options())[0] == B.NOT_SPD
+
+
+def test_null_arguments(lib):
+    assert _setup(lib, None, amg.default_options())[0] == B.INVALID_ARG
+    assert _setup(lib, B.Grid(2, 31, 3, None), None)[0] == B.INVALID_ARG
+    info = B.Info()
+    assert lib.amgmpcg_solve(None, None, None, 1e-8, 0, ctypes.byref(info)) == B.INVALID_ARG
+    assert lib.amgmpcg_mg_block(None, None, None) == B.INVALID_ARG
+    lib.amgmpcg_destroy(None)
+
+
+def test_status_strings(lib):
+    for c in (0, 1, 2, -1, -2, -3, -4, -5, -6):
+        assert B.status_string(c) and B.status_string(c) != "unknown status"
+    assert B.status_string(99) == "unknown status"

@@ -1,0 +1,246 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars (FP64 form): level operators to 1e-14 relative, the level-correction
+block Z = MG(r) to 1e-13 per column, iterates x_k at equal k to 1e-10
+relative, converged iteration counts equal or within one, alpha to 1e-8
+when no eigenvalue is dropped.  The mixed form (FP32 bulk) must reach a true
+FP64 relative residual <= 1e-8; its distance to the oracle is reported.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import hierarchy, mpcg, operators as ops
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2402_12833_amd as amg  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    amg.load()
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+# (dim, n, levels, kappa_seed, rhs_seed): the 2D 31^2 workload plus ragged and
+# degenerate shapes (even n, odd non-power-of-two n, one and two levels).
+SMALL = [
+    (2, 31, 4, None, 1),
+    (2, 30, 3, None, 11),
+    (2, 45, 4, 5, 12),
+    (2, 31, 1, None, 13),
+    (2, 20, 2, None, 14),
+    (3, 17, 3, None, 15),
+    (3, 15, 3, 3, 16),
+    (3, 31, 4, None, 17),
+]
+
+
+def case_id(c):
+    return f"d{c[0]}n{c[1]}L{c[2]}k{c[3]}"
+
+
+def build_pair(dim, n, nl, kseed, seed, **opts):
+    prob = W.GridProblem("t", dim, n, nl, seed, kappa_seed=kseed)
+    kap = W.kappa_field(prob)
+    h = hierarchy.build(dim, n, nl, kappa=kap)
+    s = amg.Solver(dim, n, nl, kappa=kap, **opts)
+    b = W.rhs(n ** dim, seed)
+    return h, s, b
+
+
+@pytest.mark.parametrize("case", SMALL, ids=case_id)
+def test_level_operators(case):
+    dim, n, nl, ks, seed = case
+    h, s, _ = build_pair(*case)
+    S = 9 if dim == 2 else 27
+    for l in range(nl - 1):
+        st = s.level_stencil(l)                 # (S, N_l)
+        A = h.levels[l].A.tocsr()
+        nlx = h.levels[l].n
+        N = nlx ** dim
+        idx = np.arange(N)
+        coords = [(idx // nlx ** a) % nlx for a in range(dim)]
+        dense = np.zeros((S, N))
+        sidx = 0
+        offs = [(dx, dy, dz) for dz in ((-1, 0, 1) if dim == 3 else (0,)) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+        for sidx, o in enumerate(offs):
+            ok = np.ones(N, bool)
+            nb = idx.copy()
+            for a in range(dim):
+                ok &= (coords[a] + o[a] >= 0) & (coords[a] + o[a] < nlx)
+                nb = nb + o[a] * nlx ** a
+            rows = idx[ok]
+            dense[sidx, ok] = np.asarray(A[rows, nb[ok]]).ravel()
+        scale = np.abs(dense).max()
+        assert np.abs(st - dense).max() <= 1e-14 * scale
+    s.close()
+
+
+@pytest.mark.parametrize("case", SMALL, ids=case_id)
+def test_mg_block(case):
+    dim, n, nl, ks, seed = case
+    h, s, b = build_pair(*case)
+    Zg = host(s.mg_block(dev(b)))
+    Zo = mpcg.mg_block(h, b)
+    for l in range(nl):
+        assert rel(Zg[l], Zo[:, l]) <= 1e-13, l
+    s.close()
+
+
+@pytest.mark.parametrize("case", SMALL, ids=case_id)
+def test_iterates_match_oracle(case):
+    dim, n, nl, ks, seed = case
+    h, s, b = build_pair(*case)
+    ref = mpcg.mpcg(h, b, tol=1e-8)
+    bg = dev(b)
+    x, info = s.solve(bg, tol=1e-8)
+    assert info["status"] == amg.OK
+    assert abs(info["iterations"] - ref.iterations) <= 1
+    k = ref.iterations
+    for kk in sorted({1, min(5, k), k}):
+        o = mpcg.mpcg(h, b, tol=0.0, maxit=kk)
+        xg, inf = s.solve(bg, tol=0.0, maxit=kk)
+        assert inf["iterations"] == kk
+        assert rel(host(xg), o.x) <= 1e-10, kk
+    # alpha history and residual norms of the converged run
+    s.solve(bg, tol=1e-8)
+    alph, res = s.history()
+    m = min(len(alph), len(ref.alphas))
+    if all(r == nl for r in ref.ranks[:m]):
+        A_o = np.array(ref.alphas[:m])
+        assert np.abs(alph[:m] - A_o).max() <= 1e-8 * np.abs(A_o).max()
+    np.testing.assert_allclose(res[: m + 1], ref.resnorms[: m + 1], rtol=1e-8)
+    s.close()
+
+
+def test_edge_cases():
+    dim, n, nl = 2, 31, 4
+    h, s, b = build_pair(dim, n, nl, None, 1)
+    # b = 0 -> x = 0, no iterations
+    x0 = dev(np.ones(n * n))
+    x, info = s.solve(dev(np.zeros(n * n)), x0, tol=1e-8)
+    assert info["iterations"] == 0 and info["status"] == amg.OK
+    assert torch.count_nonzero(x).item() == 0
+    # start at the solution -> no iterations
+    xs = np.linalg.solve(h.fine.A.toarray(), b)
+    x, info = s.solve(dev(b), dev(xs), tol=1e-8)
+    assert info["iterations"] == 0
+    # iteration limit
+    x, info = s.solve(dev(b), tol=1e-14, maxit=1)
+    assert info["status"] == amg.MAXIT and info["iterations"] == 1
+    # non-finite data
+    bb = b.copy()
+    bb[7] = np.nan
+    x, info = s.solve(dev(bb), tol=1e-8)
+    assert info["status"] == amg.NONFINITE
+    # host-buffer entry point agrees with the device one
+    xh, infoh = s.solve_host(b, tol=1e-8)
+    xd, infod = s.solve(dev(b), tol=1e-8)
+    assert infoh["iterations"] == infod["iterations"]
+    assert np.array_equal(xh, host(xd))
+    s.close()
+
+
+def test_deterministic_bitwise():
+    h, s, b = build_pair(3, 31, 4, 3, 21)
+    x1, i1 = s.solve(dev(b), tol=1e-8)
+    a1, r1 = s.history()
+    x2, i2 = s.solve(dev(b), tol=1e-8)
+    a2, r2 = s.history()
+    assert i1["iterations"] == i2["iterations"]
+    assert torch.equal(x1, x2)
+    assert np.array_equal(a1, a2) and np.array_equal(r1, r2)
+    s.close()
+
+
+@pytest.mark.parametrize("case", [(2, 31, 4, None, 1), (3, 31, 4, None, 17), (3, 31, 4, 3, 18)], ids=case_id)
+def test_mixed_precision_reaches_tolerance(case):
+    dim, n, nl, ks, seed = case
+    h, s, b = build_pair(*case, precision=1)
+    x, info = s.solve(dev(b), tol=1e-8)
+    assert info["status"] == amg.OK
+    xh = host(x)
+    true_rel = np.linalg.norm(b - h.fine.A @ xh) / np.linalg.norm(b)
+    assert true_rel <= 1e-8
+    ref = mpcg.mpcg(h, b, tol=1e-8)
+    xs = np.linalg.solve(h.fine.A.toarray(), b) if n ** dim <= 4096 else ref.x
+    err = rel(xh, xs)
+    print(f"mixed {case_id(case)}: iters {info['iterations']} (fp64 oracle {ref.iterations}), "
+          f"true relres {true_rel:.2e}, refreshes {info['refreshes']}, rel err vs oracle {err:.2e}")
+    assert info["iterations"] <= ref.iterations + 5
+    s.close()
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, f"oracle_{name}.json")) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("name", ["poisson3d_127", "diffusion3d_127"])
+def test_full_size_fp64(name):
+    """Full 127^3 workloads in the bench's launch configuration."""
+    g = _golden(name)
+    prob = W.PROBLEMS[name]
+    kap = W.kappa_field(prob)
+    b = W.problem_rhs(prob)
+    s = amg.Solver(prob.dim, prob.n, prob.nlevels, kappa=kap)
+    bg = dev(b)
+    x, info = s.solve(bg, tol=1e-8)
+    assert info["status"] == amg.OK
+    assert abs(info["iterations"] - g["iterations"]) <= 1
+    idx = np.array(g["sample_idx"])
+    k = g["iterations"]
+    for kk in (1, 5, k):
+        xg, inf = s.solve(bg, tol=0.0, maxit=kk)
+        xs = host(xg)
+        ref = np.array(g["x"][str(kk)])
+        assert rel(xs[idx], ref) <= 1e-10, kk
+        assert abs(np.linalg.norm(xs) - g["xnorm"][str(kk)]) <= 1e-10 * g["xnorm"][str(kk)]
+    # true residual of the converged iterate (oracle operator, FP64 on the host)
+    xg, _ = s.solve(bg, tol=1e-8)
+    A = ops.fd_matrix(prob.dim, prob.n, kap)
+    xh = host(xg)
+    assert np.linalg.norm(b - A @ xh) / np.linalg.norm(b) <= 1.05e-8
+    s.close()
+
+
+@pytest.mark.parametrize("name", ["poisson3d_127", "diffusion3d_127"])
+def test_full_size_mixed(name):
+    g = _golden(name)
+    prob = W.PROBLEMS[name]
+    kap = W.kappa_field(prob)
+    b = W.problem_rhs(prob)
+    s = amg.Solver(prob.dim, prob.n, prob.nlevels, kappa=kap, precision=1)
+    x, info = s.solve(dev(b), tol=1e-8)
+    assert info["status"] == amg.OK
+    A = ops.fd_matrix(prob.dim, prob.n, kap)
+    xh = host(x)
+    true_rel = np.linalg.norm(b - A @ xh) / np.linalg.norm(b)
+    idx = np.array(g["sample_idx"])
+    err = rel(xh[idx], np.array(g["x"][str(g["iterations"])]))
+    print(f"mixed {name}: iters {info['iterations']} (fp64 {g['iterations']}), true relres {true_rel:.2e}, "
+          f"refreshes {info['refreshes']}, sampled rel err vs FP64 oracle {err:.2e}")
+    assert true_rel <= 1e-8
+    s.close()
