@@ -1,0 +1,210 @@
+#!/usr/bin/env python3
+"""Benchmark: time-to-1e-8 relative residual and HBM GB/s of additive-MG MPCG.
+
+One step = one complete solve (setup excluded) of the 3D Poisson problem on
+127^3 interior nodes (2,048,383 DoF, 6 levels, 7-point FD, Galerkin coarse
+levels, damped Jacobi nu=2 omega=2/3, b ~ U[-1,1] seed 2, x0 = 0) to
+||r|| <= 1e-8 ||b|| in FP64, with b and x resident in device memory.
+``value`` is the mean time per solve (ms, lower is better).  The same
+protocol is applied to the FP32-bulk form and to the heterogeneous-kappa
+workload; they are reported under ``variants``.
+
+The roofline entry is for the kernel with the largest measured time per
+iteration; its average launch duration is measured with HIP events on the
+solver's stream (amgmpcg_time_kernels), and its algorithmic bytes come from
+the per-DoF traffic model below.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu] [--no-variants]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "time-to-1e-8 rel. residual & HBM GB/s, 3D Poisson 2.1M DoF, plain vs learned/FP32"
+
+
+def traffic_model(dim, n, nlevels, bulk, var):
+    """Algorithmic HBM bytes per launch of each kernel of one iteration.
+
+    bulk: bytes of the bulk type (8 FP64, 4 FP32).  var: face arrays stored
+    for the finest operator (heterogeneous kappa).  x, r, b are FP64.
+    Every array a kernel touches is counted once (compulsory traffic).
+    """
+    L = nlevels - 1
+    b = nlevels
+    sizes = [n // (2 ** (L - l)) for l in range(nlevels)]
+    N = [s ** dim for s in sizes]
+    S = 3 ** dim
+    Nf = N[L]
+    faces = (dim + 1) * bulk * Nf if var else 0
+    faces64 = (dim + 1) * 8 * Nf if var else 0
+    m = {}
+    m["update_r"] = (b * bulk + 16) * Nf
+    m["fine_smooth"] = (8 + bulk) * Nf + faces
+    if L > 0:
+        m["restrict_fine"] = 8 * Nf + bulk * N[L - 1]
+        m["restrict_coarse"] = sum(bulk * (N[l + 1] + N[l]) for l in range(L - 1))
+        m["coarse_smooth"] = sum((S + 2) * bulk * N[l] for l in range(L))
+        m["prolong_top"] = (L - 1) * bulk * (N[L - 2] + N[L - 1]) if L >= 2 else 0
+        m["prolong_all"] = sum((l + 1) * bulk * (N[l] + N[l + 1]) for l in range(L - 1))
+        coarse_cols = L * bulk * N[L - 1]
+    else:
+        coarse_cols = 0
+    m["fine_W"] = (b * bulk + bulk) * Nf + coarse_cols
+    m["update_xP"] = (2 * b * bulk + 16 + bulk) * Nf + coarse_cols
+    m["spmm_gram"] = (2 * b * bulk + 8) * Nf + faces
+    m["residual"] = 24 * Nf + faces64
+    per_iter = sum(v for k, v in m.items() if k not in ("prolong_top", "residual"))
+    return m, per_iter
+
+
+def per_dof(dim, nlevels, bulk, var):
+    """Per fine DoF bytes of the fine kernels (the units of the model)."""
+    b = nlevels
+    faces = (dim + 1) * bulk if var else 0
+    return {"update_r": b * bulk + 16, "fine_smooth": 8 + bulk + faces, "spmm_gram": 2 * b * bulk + 8 + faces,
+            "update_xP": 2 * b * bulk + 16 + bulk, "fine_W": b * bulk + bulk}
+
+
+def run_solver(amg, torch, prob, precision, steps, warmup, kappa=None):
+    import workloads as W
+    b = torch.as_tensor(W.problem_rhs(prob), device="cuda")
+    t0 = time.time()
+    s = amg.Solver(prob.dim, prob.n, prob.nlevels, kappa=kappa, precision=precision)
+    setup_s = time.time() - t0
+    x = torch.zeros_like(b)
+    for _ in range(warmup):
+        x.zero_()
+        s.solve(b, x, tol=1e-8)
+    torch.cuda.synchronize()
+    infos = []
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    tot = 0.0
+    for _ in range(steps):
+        x.zero_()
+        torch.cuda.synchronize()
+        ev0.record()
+        _, info = s.solve(b, x, tol=1e-8)
+        ev1.record()
+        torch.cuda.synchronize()
+        tot += ev0.elapsed_time(ev1)
+        infos.append(info)
+    ms = tot / steps
+    it = infos[-1]["iterations"]
+    assert all(i["status"] == amg.OK for i in infos), infos[-1]
+    return s, b, x, ms, it, setup_s, infos[-1]
+
+
+def cpu_baseline(prob, max_iters=None):
+    """The FP64 oracle (numpy/scipy, one thread) on the same workload."""
+    from threadpoolctl import threadpool_limits
+    import workloads as W
+    from oracle import hierarchy, mpcg
+    with threadpool_limits(limits=1):
+        h = hierarchy.build(prob.dim, prob.n, prob.nlevels, kappa=W.kappa_field(prob))
+        b = W.problem_rhs(prob)
+        t0 = time.perf_counter()
+        res = mpcg.mpcg(h, b, tol=1e-8, maxit=max_iters or 1000)
+        dt = time.perf_counter() - t0
+    return dt * 1e3, res.iterations
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); multi-GPU runs are not "
+              f"part of this build", file=sys.stderr)
+        return 2
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 1
+    import paper_2402_12833_amd as amg
+    import workloads as W
+    amg.load()
+
+    prob = W.POISSON3D_127
+    s, b, x, ms, iters, setup_s, info = run_solver(amg, torch, prob, 0, args.steps, args.warmup)
+    m, per_iter = traffic_model(prob.dim, prob.n, prob.nlevels, 8, False)
+    gbs = per_iter * iters / (ms * 1e-3) / 1e9
+    kt = s.time_kernels(args.kernel_reps)
+    fine = {k: v for k, v in kt.items() if k in ("update_r", "fine_smooth", "fine_W", "update_xP", "spmm_gram")}
+    dom = max(fine, key=lambda k: fine[k])
+    dom_bytes = m[dom]
+    achieved = dom_bytes / (kt[dom] * 1e-3) / 1e9
+    kernels = {k: {"ms": round(v, 5), "bytes": m.get(k), "GB/s": round(m[k] / (v * 1e-3) / 1e9, 1) if m.get(k) and v > 0 else None}
+               for k, v in kt.items()}
+    out = {
+        "metric": METRIC,
+        "value": round(ms, 4),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "poisson3d_127", "dofs": prob.ndof, "levels": prob.nlevels, "stencil": "7-point FD",
+                   "coarse": "Galerkin 27-point", "smoother": "damped Jacobi nu=2 omega=2/3", "m": 1,
+                   "tol": 1e-8, "rhs": "U[-1,1] seed 2", "x0": 0},
+        "iterations": iters,
+        "ms_per_iteration": round(ms / max(iters, 1), 5),
+        "hbm_GBps_algorithmic": round(gbs, 1),
+        "bytes_per_iteration_model": per_iter,
+        "setup_s": round(setup_s, 3),
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_launch": dom_bytes, "bytes_per_dof": per_dof(3, prob.nlevels, 8, False)[dom],
+                     "avg_launch_ms": round(kt[dom], 5)},
+        "kernels": kernels,
+    }
+    s.close()
+    if not args.no_variants:
+        var = {}
+        s2, _, _, ms2, it2, _, info2 = run_solver(amg, torch, prob, 1, args.steps, args.warmup)
+        _, pi2 = traffic_model(3, prob.n, prob.nlevels, 4, False)
+        var["poisson3d_127_fp32bulk"] = {"ms": round(ms2, 4), "iterations": it2, "refreshes": info2["refreshes"],
+                                        "hbm_GBps_algorithmic": round(pi2 * it2 / (ms2 * 1e-3) / 1e9, 1),
+                                        "speedup_vs_fp64": round(ms / ms2, 3)}
+        s2.close()
+        dprob = W.DIFFUSION3D_127
+        kap = W.kappa_field(dprob)
+        for prec, tag, bulk in ((0, "fp64", 8), (1, "fp32bulk", 4)):
+            s3, _, _, ms3, it3, _, info3 = run_solver(amg, torch, dprob, prec, args.steps, args.warmup, kappa=kap)
+            _, pi3 = traffic_model(3, dprob.n, dprob.nlevels, bulk, True)
+            var[f"diffusion3d_127_{tag}"] = {"ms": round(ms3, 4), "iterations": it3, "refreshes": info3["refreshes"],
+                                             "hbm_GBps_algorithmic": round(pi3 * it3 / (ms3 * 1e-3) / 1e9, 1)}
+            s3.close()
+        out["variants"] = var
+    if not args.no_cpu:
+        cpu_ms, cpu_it = cpu_baseline(prob)
+        out["cpu_baseline"] = {"value": round(cpu_ms, 1), "unit": "ms", "cores": 1, "kind": "oracle",
+                               "sample": f"FP64 oracle (numpy/scipy, 1 thread) full solve of poisson3d_127 to 1e-8, "
+                                         f"{cpu_it} iterations, setup excluded",
+                               "cpu": platform.processor() or platform.machine()}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

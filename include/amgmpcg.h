@@ -133,6 +133,15 @@ int amgmpcg_level_stencil(const amgmpcg_handle* h, int32_t level, double* out);
 int amgmpcg_history(const amgmpcg_handle* h, int32_t cap, double* alpha_out,
                     double* resnorm_out, int32_t* count);
 
+/* Measurement aid: average duration in ms of each hot kernel of one
+ * iteration, each launched reps times back to back between two HIP events
+ * on the handle's stream, on the state left by the last solve (call it after
+ * a solve; it overwrites the solver's work vectors, not the caller's x).
+ * ms_out: HOST, cap doubles, in the order update_r, fine_smooth,
+ * restrict_fine, coarse_smooth, prolong_top, fine_W, update_xP, spmm_gram,
+ * residual (9 entries; 0 where a level does not exist). *count = entries. */
+int amgmpcg_time_kernels(amgmpcg_handle* h, int32_t reps, double* ms_out, int32_t cap, int32_t* count);
+
 void amgmpcg_destroy(amgmpcg_handle* h);
 const char* amgmpcg_status_string(int status);
 const char* amgmpcg_last_error(void);

@@ -76,6 +76,8 @@ def load(path: str = LIB_PATH):
     lib.amgmpcg_level_size.argtypes = [c_void_p, c_int32, POINTER(c_int32)]
     lib.amgmpcg_level_stencil.argtypes = [c_void_p, c_int32, POINTER(c_double)]
     lib.amgmpcg_history.argtypes = [c_void_p, c_int32, POINTER(c_double), POINTER(c_double), POINTER(c_int32)]
+    lib.amgmpcg_time_kernels.argtypes = [c_void_p, c_int32, POINTER(c_double), c_int32, POINTER(c_int32)]
+    lib.amgmpcg_time_kernels.restype = c_int32
     lib.amgmpcg_destroy.argtypes = [c_void_p]
     lib.amgmpcg_destroy.restype = None
     lib.amgmpcg_status_string.argtypes = [c_int32]
@@ -202,6 +204,17 @@ class Solver:
         out = np.empty(S * nl ** self.dim)
         _check(self._lib.amgmpcg_level_stencil(self._h, level, out.ctypes.data_as(POINTER(c_double))))
         return out.reshape(S, nl ** self.dim)
+
+    KERNELS = ("update_r", "fine_smooth", "restrict_fine", "coarse_smooth", "prolong_top", "fine_W",
+               "update_xP", "spmm_gram", "residual")
+
+    def time_kernels(self, reps: int = 50) -> dict:
+        """Average ms per launch of each hot kernel (HIP events, handle stream)."""
+        out = np.zeros(16)
+        cnt = c_int32()
+        _check(self._lib.amgmpcg_time_kernels(self._h, reps, out.ctypes.data_as(POINTER(c_double)), 16,
+                                              byref(cnt)))
+        return {k: float(out[i]) for i, k in enumerate(self.KERNELS[: cnt.value])}
 
     def history(self, cap: int = 100000) -> Tuple[np.ndarray, np.ndarray]:
         a = np.empty(cap * self.nb)

@@ -91,6 +91,7 @@ class SolverBase {
     virtual void mg_block(const double* r_dev, double* Z_dev) = 0;
     virtual void level_stencil(int level, double* out) = 0;
     virtual void history(int cap, double* alpha, double* res, int* count) = 0;
+    virtual int time_kernels(int reps, double* ms, int cap) = 0;
     int dim = 0, nlev = 0, nb = 0;
     std::vector<int> n_axis;   // per level, 0 = coarsest
 };
@@ -282,6 +283,87 @@ class Solver : public SolverBase {
             HIPCHK(hipMemcpyAsync(alpha, ahist_.p, (size_t)k * nb * sizeof(double), hipMemcpyDeviceToHost, stream_));
         if (res) HIPCHK(hipMemcpyAsync(res, rhist_.p, (size_t)(k + 1) * sizeof(double), hipMemcpyDeviceToHost, stream_));
         HIPCHK(hipStreamSynchronize(stream_));
+    }
+
+    // Average duration (ms) of each hot kernel, launched reps times back to
+    // back between two HIP events on the handle's stream, on the state left
+    // by the last solve.  Order: update_r, fine_smooth, restrict_fine,
+    // coarse_smooth, prolong_top, fine_W, update_xP, spmm_gram, residual.
+    int time_kernels(int reps, double* ms, int cap) override {
+        const int N = N_[L_];
+        const Ctl* cf = ctl_free_;
+        const T omega = T(opt_.omega);
+        int count = 0;
+        auto timed = [&](auto&& launch) {
+            HIPCHK(hipEventRecord(ev0_, stream_));
+            for (int i = 0; i < reps; ++i) launch();
+            HIPCHK(hipEventRecord(ev1_, stream_));
+            HIPCHK(hipEventSynchronize(ev1_));
+            HIPCHK(hipGetLastError());
+            float t = 0.f;
+            HIPCHK(hipEventElapsedTime(&t, ev0_, ev1_));
+            if (count < cap) ms[count] = double(t) / reps;
+            ++count;
+        };
+        enqueue_mg(cf, r_.p);   // sets the final smoother buffers
+        dispatch_nb([&](auto nbc) {
+            constexpr int NB = decltype(nbc)::value;
+            const int nc = L_ > 0 ? n_axis[L_ - 1] : 1;
+            timed([&] { k_update_r<T, NB><<<FB_, kBlock, 0, stream_>>>(cf, N, Q_.p, d_alpha(), r_.p, part_rho()); });
+            timed([&] {
+                k_fine_smooth<DIM, T, double><<<FB_, kBlock, 0, stream_>>>(cf, fop_, r_.p, cL_.p, omega,
+                                                                            opt_.nu >= 2 ? 1 : 0);
+            });
+            if (L_ > 0) {
+                const int l = L_ - 1;
+                timed([&] {
+                    k_restrict<DIM, double, T><<<(N_[l] + kBlock - 1) / kBlock, kBlock, 0, stream_>>>(
+                        cf, r_.p, n_axis[L_], g_[l].p, n_axis[l], N_[l]);
+                });
+                CoarseLevels<T> cl{};
+                cl.nlev = L_;
+                int off = 0;
+                for (int m = 0; m < L_; ++m) {
+                    cl.blk_off[m] = off;
+                    off += (N_[m] + kBlock - 1) / kBlock;
+                    cl.n[m] = n_axis[m];
+                    cl.N[m] = N_[m];
+                    cl.coef[m] = coef_[m].p;
+                    cl.g[m] = g_[m].p;
+                    cl.cout[m] = c_[m].p;
+                }
+                cl.blk_off[L_] = off;
+                timed([&] { k_coarse_smooth<DIM, T><<<off, kBlock, 0, stream_>>>(cf, cl, omega, 0, opt_.nu >= 2 ? 1 : 0); });
+                if (L_ >= 2) {
+                    const int m = L_ - 2;
+                    ColPtrs<T> in{};
+                    for (int c = 0; c < m; ++c) in.p[c] = Y_[m].p + (size_t)c * N_[m];
+                    in.p[m] = c_[m].p;
+                    timed([&] {
+                        k_prolong<DIM, T><<<(N_[m + 1] + kBlock - 1) / kBlock, kBlock, 0, stream_>>>(
+                            cf, in, m + 1, n_axis[m], Y_[m + 1].p, n_axis[m + 1], N_[m + 1]);
+                    });
+                } else {
+                    timed([&] {});
+                }
+            } else {
+                timed([&] {});
+                timed([&] {});
+                timed([&] {});
+            }
+            enqueue_mg(cf, r_.p);
+            timed([&] {
+                k_fine_W<DIM, T, NB><<<FB_, kBlock, 0, stream_>>>(cf, n_axis[L_], N, fine_cols(), nc, cL_final_, Q_.p,
+                                                                   part_W());
+            });
+            timed([&] {
+                k_update_xP<DIM, T, NB><<<FB_, kBlock, 0, stream_>>>(cf, n_axis[L_], N, fine_cols(), nc, cL_final_,
+                                                                      P_.p, x_.p, d_alpha(), d_beta(), 0);
+            });
+            timed([&] { k_spmm_gram<DIM, T, NB><<<FB_, kBlock, 0, stream_>>>(cf, fop_, P_.p, Q_.p, r_.p, part_G()); });
+            timed([&] { k_init_residual<DIM><<<FB_, kBlock, 0, stream_>>>(f64_, b_.p, x_.p, r_.p, part_init()); });
+        });
+        return count;
     }
 
    private:
@@ -693,6 +775,16 @@ int amgmpcg_history(const amgmpcg_handle* h, int32_t cap, double* alpha_out, dou
         if (cap < 0) throw ApiError(AMGMPCG_INVALID_ARG, "cap must be >= 0");
         int c = 0;
         h->s->history(cap, alpha_out, resnorm_out, &c);
+        if (count) *count = c;
+        return AMGMPCG_OK;
+    });
+}
+
+int amgmpcg_time_kernels(amgmpcg_handle* h, int32_t reps, double* ms_out, int32_t cap, int32_t* count) {
+    return guarded([&]() -> int {
+        if (!h || !h->s || !ms_out) throw ApiError(AMGMPCG_INVALID_ARG, "NULL argument");
+        if (reps < 1 || cap < 0) throw ApiError(AMGMPCG_INVALID_ARG, "reps must be >= 1");
+        const int c = h->s->time_kernels(reps, ms_out, cap);
         if (count) *count = c;
         return AMGMPCG_OK;
     });
