@@ -142,6 +142,15 @@ int amgmpcg_history(const amgmpcg_handle* h, int32_t cap, double* alpha_out,
  * residual (9 entries; 0 where a level does not exist). *count = entries. */
 int amgmpcg_time_kernels(amgmpcg_handle* h, int32_t reps, double* ms_out, int32_t cap, int32_t* count);
 
+/* The device pseudo-inverse used for the step coefficients (Sec. 2.2: the
+ * Gram P^T A P may be singular), applied to one symmetric positive
+ * semi-definite nb x nb matrix.  G, Gplus: HOST, nb*nb doubles row-major.
+ * Columns with a non-positive or non-finite diagonal are inactive; on the
+ * unit-diagonal scaling Ghat = S G S eigenvalues <= tau are dropped and
+ * Gplus = S Ghat^+ S.  *rank = eigenvalues kept.  Runs on the default
+ * stream and synchronises. */
+int amgmpcg_gram_pinv(const double* G, int32_t nb, double tau, double* Gplus, int32_t* rank);
+
 void amgmpcg_destroy(amgmpcg_handle* h);
 const char* amgmpcg_status_string(int status);
 const char* amgmpcg_last_error(void);

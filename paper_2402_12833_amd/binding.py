@@ -78,6 +78,8 @@ def load(path: str = LIB_PATH):
     lib.amgmpcg_history.argtypes = [c_void_p, c_int32, POINTER(c_double), POINTER(c_double), POINTER(c_int32)]
     lib.amgmpcg_time_kernels.argtypes = [c_void_p, c_int32, POINTER(c_double), c_int32, POINTER(c_int32)]
     lib.amgmpcg_time_kernels.restype = c_int32
+    lib.amgmpcg_gram_pinv.argtypes = [POINTER(c_double), c_int32, c_double, POINTER(c_double), POINTER(c_int32)]
+    lib.amgmpcg_gram_pinv.restype = c_int32
     lib.amgmpcg_destroy.argtypes = [c_void_p]
     lib.amgmpcg_destroy.restype = None
     lib.amgmpcg_status_string.argtypes = [c_int32]
@@ -113,6 +115,17 @@ def default_options(**kw) -> Options:
             raise TypeError(f"unknown option {k}")
         setattr(o, k, v)
     return o
+
+
+def gram_pinv(G: np.ndarray, tau: float):
+    """Device pseudo-inverse of one Gram matrix; returns (Gplus, rank)."""
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    nb = G.shape[0]
+    out = np.empty((nb, nb))
+    rank = c_int32()
+    _check(load().amgmpcg_gram_pinv(G.ctypes.data_as(POINTER(c_double)), nb, float(tau),
+                                    out.ctypes.data_as(POINTER(c_double)), byref(rank)))
+    return out, rank.value
 
 
 def _current_stream():

@@ -46,7 +46,7 @@ struct ApiError : std::runtime_error {
         }                                                                                              \
     } while (0)
 
-constexpr int kMaxFineBlocks = 2048;
+constexpr int kMaxFineBlocks = 1024;
 constexpr int kPartRow = 2 + 1 + kMaxNB * kMaxNB + (kMaxNB * (kMaxNB + 1) / 2 + kMaxNB) + 1;
 
 template <typename T>
@@ -118,7 +118,10 @@ class Solver : public SolverBase {
         N_.resize(nlev);
         for (int l = 0; l < nlev; ++l) N_[l] = (int)host::ipow(n_axis[l], DIM);
         const int N = N_[L_];
-        FB_ = fine_blocks(N);
+        rows_.n = g.n;
+        rows_.nxp = (g.n + 63) / 64 * 64;
+        rows_.total = (int)host::ipow(g.n, DIM - 1) * rows_.nxp;
+        FB_ = fine_blocks(rows_.total);
 
         // ---- host hierarchy (FP64) -------------------------------------
         const bool var = g.kappa != nullptr;
@@ -256,8 +259,8 @@ class Solver : public SolverBase {
         const int N = N_[L_];
         dispatch_nb([&](auto nbc) {
             constexpr int NB = decltype(nbc)::value;
-            k_write_Z<DIM, T, NB><<<(N + kBlock - 1) / kBlock, kBlock, 0, stream_>>>(
-                n_axis[L_], N, fine_cols(), L_ > 0 ? n_axis[L_ - 1] : 1, cL_final_, Z_dev);
+            k_write_Z<DIM, T, NB><<<(rows_.total + kBlock - 1) / kBlock, kBlock, 0, stream_>>>(
+                rows_, N, fine_cols(), L_ > 0 ? n_axis[L_ - 1] : 1, cL_final_, Z_dev);
         });
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(stream_));
@@ -311,7 +314,7 @@ class Solver : public SolverBase {
             const int nc = L_ > 0 ? n_axis[L_ - 1] : 1;
             timed([&] { k_update_r<T, NB><<<FB_, kBlock, 0, stream_>>>(cf, N, Q_.p, d_alpha(), r_.p, part_rho()); });
             timed([&] {
-                k_fine_smooth<DIM, T, double><<<FB_, kBlock, 0, stream_>>>(cf, fop_, r_.p, cL_.p, omega,
+                k_fine_smooth<DIM, T, double><<<FB_, kBlock, 0, stream_>>>(cf, rows_, fop_, r_.p, cL_.p, omega,
                                                                             opt_.nu >= 2 ? 1 : 0);
             });
             if (L_ > 0) {
@@ -353,15 +356,15 @@ class Solver : public SolverBase {
             }
             enqueue_mg(cf, r_.p);
             timed([&] {
-                k_fine_W<DIM, T, NB><<<FB_, kBlock, 0, stream_>>>(cf, n_axis[L_], N, fine_cols(), nc, cL_final_, Q_.p,
+                k_fine_W<DIM, T, NB><<<FB_, kBlock, 0, stream_>>>(cf, rows_, N, fine_cols(), nc, cL_final_, Q_.p,
                                                                    part_W());
             });
             timed([&] {
-                k_update_xP<DIM, T, NB><<<FB_, kBlock, 0, stream_>>>(cf, n_axis[L_], N, fine_cols(), nc, cL_final_,
+                k_update_xP<DIM, T, NB><<<FB_, kBlock, 0, stream_>>>(cf, rows_, N, fine_cols(), nc, cL_final_,
                                                                       P_.p, x_.p, d_alpha(), d_beta(), 0);
             });
-            timed([&] { k_spmm_gram<DIM, T, NB><<<FB_, kBlock, 0, stream_>>>(cf, fop_, P_.p, Q_.p, r_.p, part_G()); });
-            timed([&] { k_init_residual<DIM><<<FB_, kBlock, 0, stream_>>>(f64_, b_.p, x_.p, r_.p, part_init()); });
+            timed([&] { k_spmm_gram<DIM, T, NB><<<FB_, kBlock, 0, stream_>>>(cf, rows_, fop_, P_.p, Q_.p, r_.p, part_G()); });
+            timed([&] { k_init_residual<DIM><<<FB_, kBlock, 0, stream_>>>(rows_, f64_, b_.p, x_.p, r_.p, part_init()); });
         });
         return count;
     }
@@ -449,11 +452,11 @@ class Solver : public SolverBase {
         {
             T* first = (extra % 2 == 0) ? cL_.p : cL2_.p;
             T* other = (extra % 2 == 0) ? cL2_.p : cL_.p;
-            k_fine_smooth<DIM, T, double><<<FB_, kBlock, 0, stream_>>>(ctl, fop_, r, first, omega, two);
+            k_fine_smooth<DIM, T, double><<<FB_, kBlock, 0, stream_>>>(ctl, rows_, fop_, r, first, omega, two);
             T* cur = first;
             for (int s = 0; s < extra; ++s) {
                 T* nxt = (cur == first) ? other : first;
-                k_fine_sweep<DIM, T, double><<<FB_, kBlock, 0, stream_>>>(ctl, fop_, r, cur, nxt, omega);
+                k_fine_sweep<DIM, T, double><<<FB_, kBlock, 0, stream_>>>(ctl, rows_, fop_, r, cur, nxt, omega);
                 cur = nxt;
             }
             cL_final_ = cur;
@@ -521,17 +524,17 @@ class Solver : public SolverBase {
 
     void enqueue_init(double tol) {
         const int N = N_[L_];
-        k_init_residual<DIM><<<FB_, kBlock, 0, stream_>>>(f64_, b_.p, x_.p, r_.p, part_init());
-        k_reduce_init<<<1, kBlock, 0, stream_>>>(ctl_, part_init(), FB_, tol, hist_cap_ ? rhist_.p : nullptr);
+        k_init_residual<DIM><<<FB_, kBlock, 0, stream_>>>(rows_, f64_, b_.p, x_.p, r_.p, part_init());
+        k_reduce_init<<<1, kRedBlock, 0, stream_>>>(ctl_, part_init(), FB_, tol, hist_cap_ ? rhist_.p : nullptr);
         k_zero_if<<<FB_, kBlock, 0, stream_>>>(ctl_, x_.p, N);
         enqueue_mg(ctl_, r_.p);
         dispatch_nb([&](auto nbc) {
             constexpr int NB = decltype(nbc)::value;
             const int nc = L_ > 0 ? n_axis[L_ - 1] : 1;
-            k_update_xP<DIM, T, NB><<<FB_, kBlock, 0, stream_>>>(ctl_, n_axis[L_], N, fine_cols(), nc, cL_final_,
+            k_update_xP<DIM, T, NB><<<FB_, kBlock, 0, stream_>>>(ctl_, rows_, N, fine_cols(), nc, cL_final_,
                                                                    P_.p, x_.p, d_alpha(), d_beta(), 1);
-            k_spmm_gram<DIM, T, NB><<<FB_, kBlock, 0, stream_>>>(ctl_, fop_, P_.p, Q_.p, r_.p, part_G());
-            k_reduce_alpha<NB><<<1, kBlock, 0, stream_>>>(ctl_, part_G(), FB_, d_Gplus(), d_alpha(),
+            k_spmm_gram<DIM, T, NB><<<FB_, kBlock, 0, stream_>>>(ctl_, rows_, fop_, P_.p, Q_.p, r_.p, part_G());
+            k_reduce_alpha<NB><<<1, kRedBlock, 0, stream_>>>(ctl_, part_G(), FB_, d_Gplus(), d_alpha(),
                                                           hist_cap_ ? ahist_.p : nullptr);
         });
     }
@@ -545,18 +548,18 @@ class Solver : public SolverBase {
             const int nc = L_ > 0 ? n_axis[L_ - 1] : 1;
             k_update_r<T, NB><<<FB_, kBlock, 0, s>>>(ctl_, N, Q_.p, d_alpha(), r_.p, part_rho());
             enqueue_mg(ctl_, r_.p);
-            k_fine_W<DIM, T, NB><<<FB_, kBlock, 0, s>>>(ctl_, n_axis[L_], N, fine_cols(), nc, cL_final_, Q_.p,
+            k_fine_W<DIM, T, NB><<<FB_, kBlock, 0, s>>>(ctl_, rows_, N, fine_cols(), nc, cL_final_, Q_.p,
                                                          part_W());
-            k_reduce_beta<NB><<<1, kBlock, 0, s>>>(ctl_, part_rho(), part_W(), FB_, d_Gplus(), d_beta(),
+            k_reduce_beta<NB><<<1, kRedBlock, 0, s>>>(ctl_, part_rho(), part_W(), FB_, d_Gplus(), d_beta(),
                                                    hist_cap_ ? rhist_.p : nullptr, mixed_ ? 1 : 0);
-            k_update_xP<DIM, T, NB><<<FB_, kBlock, 0, s>>>(ctl_, n_axis[L_], N, fine_cols(), nc, cL_final_, P_.p,
+            k_update_xP<DIM, T, NB><<<FB_, kBlock, 0, s>>>(ctl_, rows_, N, fine_cols(), nc, cL_final_, P_.p,
                                                             x_.p, d_alpha(), d_beta(), 0);
             if (mixed_) {
-                k_refresh<DIM><<<FB_, kBlock, 0, s>>>(ctl_, f64_, b_.p, x_.p, r_.p, part_ref());
-                k_refresh_reduce<<<1, kBlock, 0, s>>>(ctl_, part_ref(), FB_, hist_cap_ ? rhist_.p : nullptr);
+                k_refresh<DIM><<<FB_, kBlock, 0, s>>>(ctl_, rows_, f64_, b_.p, x_.p, r_.p, part_ref());
+                k_refresh_reduce<<<1, kRedBlock, 0, s>>>(ctl_, part_ref(), FB_, hist_cap_ ? rhist_.p : nullptr);
             }
-            k_spmm_gram<DIM, T, NB><<<FB_, kBlock, 0, s>>>(ctl_, fop_, P_.p, Q_.p, r_.p, part_G());
-            k_reduce_alpha<NB><<<1, kBlock, 0, s>>>(ctl_, part_G(), FB_, d_Gplus(), d_alpha(),
+            k_spmm_gram<DIM, T, NB><<<FB_, kBlock, 0, s>>>(ctl_, rows_, fop_, P_.p, Q_.p, r_.p, part_G());
+            k_reduce_alpha<NB><<<1, kRedBlock, 0, s>>>(ctl_, part_G(), FB_, d_Gplus(), d_alpha(),
                                                     hist_cap_ ? ahist_.p : nullptr);
         });
         stream_ = saved;
@@ -584,6 +587,7 @@ class Solver : public SolverBase {
     double tau_ = 0.0;
     std::vector<int> N_;
     FineOp<T> fop_{};
+    Rows rows_{};
     FineOp<double> f64_{};
     DevBuf<T> fD_, fex_, fey_, fez_;
     DevBuf<double> gD_, gex_, gey_, gez_;
@@ -786,6 +790,35 @@ int amgmpcg_time_kernels(amgmpcg_handle* h, int32_t reps, double* ms_out, int32_
         if (reps < 1 || cap < 0) throw ApiError(AMGMPCG_INVALID_ARG, "reps must be >= 1");
         const int c = h->s->time_kernels(reps, ms_out, cap);
         if (count) *count = c;
+        return AMGMPCG_OK;
+    });
+}
+
+int amgmpcg_gram_pinv(const double* G, int32_t nb, double tau, double* Gplus, int32_t* rank) {
+    return guarded([&]() -> int {
+        if (!G || !Gplus || !rank) throw ApiError(AMGMPCG_INVALID_ARG, "NULL argument");
+        if (nb < 1 || nb > amg::kMaxNB) throw ApiError(AMGMPCG_INVALID_ARG, "nb must be in 1..8");
+        if (!(tau > 0.0)) throw ApiError(AMGMPCG_INVALID_ARG, "tau must be > 0");
+        amg::DevBuf<double> d;
+        d.alloc(2 * (size_t)nb * nb + 1);
+        HIPCHK(hipMemcpy(d.p, G, sizeof(double) * nb * nb, hipMemcpyHostToDevice));
+        int* drank = (int*)(d.p + 2 * nb * nb);
+        double* dGp = d.p + nb * nb;
+        switch (nb) {
+            case 1: amg::k_pinv_only<1><<<1, 64>>>(d.p, tau, dGp, drank); break;
+            case 2: amg::k_pinv_only<2><<<1, 64>>>(d.p, tau, dGp, drank); break;
+            case 3: amg::k_pinv_only<3><<<1, 64>>>(d.p, tau, dGp, drank); break;
+            case 4: amg::k_pinv_only<4><<<1, 64>>>(d.p, tau, dGp, drank); break;
+            case 5: amg::k_pinv_only<5><<<1, 64>>>(d.p, tau, dGp, drank); break;
+            case 6: amg::k_pinv_only<6><<<1, 64>>>(d.p, tau, dGp, drank); break;
+            case 7: amg::k_pinv_only<7><<<1, 64>>>(d.p, tau, dGp, drank); break;
+            default: amg::k_pinv_only<8><<<1, 64>>>(d.p, tau, dGp, drank); break;
+        }
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpy(Gplus, dGp, sizeof(double) * nb * nb, hipMemcpyDeviceToHost));
+        int r = 0;
+        HIPCHK(hipMemcpy(&r, drank, sizeof(int), hipMemcpyDeviceToHost));
+        *rank = r;
         return AMGMPCG_OK;
     });
 }

@@ -52,11 +52,12 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Sum K per-thread values over the block in a fixed order and let thread k
-// (k < K) write value k to out[k].  Deterministic: butterfly within each wave,
-// then the wave sums in wave order.
+// Sum K per-thread values over the block in a fixed order and store value k
+// of logical block lb at part[k * nblk + lb] (value-major, so that the final
+// reduction reads each value's partials contiguously).  Deterministic:
+// butterfly within each wave, then the wave sums in wave order.
 template <int K>
-__device__ __forceinline__ void block_sum_store(double (&v)[K], double* out) {
+__device__ __forceinline__ void block_sum_store(double (&v)[K], double* part, int nblk, int lb) {
     __shared__ double sh[kWaves][K > 0 ? K : 1];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
@@ -69,30 +70,34 @@ __device__ __forceinline__ void block_sum_store(double (&v)[K], double* out) {
         double s = sh[0][k];
 #pragma unroll
         for (int q = 1; q < kWaves; ++q) s += sh[q][k];
-        out[k] = s;
+        part[(size_t)k * nblk + lb] = s;
     }
     __syncthreads();
 }
 
-// Reduce nblk partial rows of K doubles (row-major part[b*K + k]) into
-// res[k] (shared memory), inside one block, in a fixed order.
+constexpr int kRedBlock = 1024;    // threads of the single-block reduction kernels
+constexpr int kRedWaves = kRedBlock / 64;
+
+// Reduce the value-major partials part[k * nblk + b] (b < nblk) of K values
+// into res[k] (shared memory).  Wave w sums values k = w, w + 16, ...: each
+// lane adds rows lane, lane + 64, ... in order, then a butterfly; fixed order.
 template <int K>
 __device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int nblk,
                                                 double* res /* shared, K */) {
-    constexpr int R = (kBlock / K) > 0 ? (kBlock / K) : 1;   // rows of threads
-    __shared__ double sh[R][K];
-    const int t = threadIdx.x;
-    if (t < R * K) {
-        const int k = t % K, r0 = t / K;
-        double s = 0.0;
-        for (int b = r0; b < nblk; b += R) s += part[(size_t)b * K + k];
-        sh[r0][k] = s;
-    }
-    __syncthreads();
-    if (t < K) {
-        double s = sh[0][t];
-        for (int r = 1; r < R; ++r) s += sh[r][t];
-        res[t] = s;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int k = w; k < K; k += kRedWaves) {
+        const double* p = part + (size_t)k * nblk;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int b = lane;
+        for (; b + 192 < nblk; b += 256) {
+            s0 += p[b];
+            s1 += p[b + 64];
+            s2 += p[b + 128];
+            s3 += p[b + 192];
+        }
+        for (; b < nblk; b += 64) s0 += p[b];
+        const double s = wave_sum((s0 + s1) + (s2 + s3));
+        if (lane == 0) res[k] = s;
     }
     __syncthreads();
 }

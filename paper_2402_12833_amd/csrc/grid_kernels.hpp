@@ -202,41 +202,161 @@ __device__ __forceinline__ C interp_at(const T* __restrict__ v, int nc, const Id
     return acc;
 }
 
+// ------------------------------------------------------- row-mapped fine loop
+//
+// Fine-level kernels map work items to (x-row, i): each x-row of n nodes is
+// padded to nxp = roundup(n, 64) items, so every wavefront lies inside one
+// row and the row's (j, k) -- hence every y/z neighbour test and every y/z
+// interpolation weight -- is uniform across the wavefront.  Lanes with
+// i >= n idle.  The flat node index is i + n * row.
+struct Rows {
+    int n;       // nodes per axis
+    int nxp;     // padded row length (multiple of 64)
+    int total;   // rows * nxp
+};
+
+template <int DIM>
+__device__ __forceinline__ bool row_item(const Rows& R, int w, Idx<DIM>& p, int& idx) {
+    const int w0 = __builtin_amdgcn_readfirstlane(w);
+    const int row = w0 / R.nxp;
+    p.i = w - row * R.nxp;
+    if (DIM == 2) {
+        p.j = row;
+        p.k = 0;
+    } else {
+        p.k = row / R.n;
+        p.j = row - p.k * R.n;
+    }
+    const bool act = p.i < R.n;
+    if (!act) p.i = R.n - 1;   // keep addresses in range on idle lanes
+    idx = p.i + R.n * row;
+    return act;
+}
+
+// Each block walks one contiguous range of rows (kBlock items at a time);
+// with the XCD-aware logical block index, each XCD owns a contiguous slab.
+__device__ __forceinline__ int row_chunk(int total) {
+    const int per = (total + gridDim.x - 1) / gridDim.x;
+    return (per + kBlock - 1) / kBlock * kBlock;
+}
+
+#define ROW_LOOP(R, lb)                                                                           \
+    for (int c_ = row_chunk((R).total), w_ = (lb) * c_ + (int)threadIdx.x,                        \
+             e_ = min((R).total, ((lb) + 1) * c_);                                                \
+         w_ < e_; w_ += kBlock)
+
+// Branch-free x-axis interpolation parents: two (possibly equal) coarse
+// indices with weights (1, 0) on a coarse node, (1/2, 1/2) between two, and a
+// zero weight for a boundary neighbour.
+struct XPar {
+    int lo, hi;
+    float wlo, whi;
+};
+
+__device__ __forceinline__ XPar xparents(int f, int nc) {
+    XPar q;
+    if (f & 1) {
+        q.lo = q.hi = (f - 1) >> 1;
+        q.wlo = 1.f;
+        q.whi = 0.f;
+    } else {
+        const int J = f >> 1;
+        q.lo = J - 1;
+        q.hi = J;
+        q.wlo = q.whi = 0.5f;
+        if (q.lo < 0) {
+            q.lo = 0;
+            q.wlo = 0.f;
+        }
+        if (q.hi >= nc) {
+            q.hi = nc - 1;
+            q.whi = 0.f;
+        }
+    }
+    return q;
+}
+
+// Interpolate a coarse column at a fine node whose y/z parents are uniform.
+template <int DIM, typename C, typename T>
+__device__ __forceinline__ C interp_row(const T* __restrict__ v, int nc, const XPar& px, const Par& py,
+                                        const Par& pz) {
+    C acc = C(0);
+    const int nzc = DIM == 3 ? pz.cnt : 1;
+    for (int c = 0; c < nzc; ++c) {
+        const int K = DIM == 3 ? (c ? pz.hi : pz.lo) : 0;
+        const C wz = DIM == 3 ? C(c ? pz.whi : pz.wlo) : C(1);
+        C plane = C(0);
+        for (int b = 0; b < py.cnt; ++b) {
+            const int J = b ? py.hi : py.lo;
+            const C wy = C(b ? py.whi : py.wlo);
+            const T* rowp = v + (size_t)nc * (J + (size_t)nc * K);
+            const C rowv = C(px.wlo) * C(rowp[px.lo]) + C(px.whi) * C(rowp[px.hi]);
+            plane += wy * rowv;
+        }
+        acc += wz * plane;
+    }
+    return acc;
+}
+
+// Level corrections at one fine node: z[c] for c < NB-1 interpolated from the
+// NB-1 level-(L-1) columns, z[NB-1] = cL (the finest smoother output).
+template <typename T>
+struct ColPtrs {
+    const T* p[kMaxNB];
+};
+
+template <int DIM, typename T, int NB>
+__device__ __forceinline__ void fine_z(const ColPtrs<T>& Y, int nc, const T* __restrict__ cL, int idx,
+                                       const Idx<DIM>& p, T (&z)[NB]) {
+    if (NB > 1) {
+        const XPar px = xparents(p.i, nc);
+        const Par py = parents(p.j, nc);
+        const Par pz = DIM == 3 ? parents(p.k, nc) : Par{0, 0, 1.f, 0.f, 1};
+#pragma unroll
+        for (int c = 0; c < NB - 1; ++c) z[c] = interp_row<DIM, T>(Y.p[c], nc, px, py, pz);
+    }
+    z[NB - 1] = cL[idx];
+}
+
 // ---------------------------------------------------------------- kernels
 
 // r = b - A x (FP64), partial sums of ||b||^2 and ||r||^2.
 template <int DIM>
-__global__ void __launch_bounds__(kBlock) k_init_residual(FineOp<double> op, const double* __restrict__ b,
+__global__ void __launch_bounds__(kBlock) k_init_residual(Rows R, FineOp<double> op, const double* __restrict__ b,
                                                           const double* __restrict__ x, double* __restrict__ r,
                                                           double* __restrict__ part) {
     const int lb = xcd_block(gridDim.x);
     double v[2] = {0.0, 0.0};
-    for (int idx = lb * kBlock + threadIdx.x; idx < op.N; idx += gridDim.x * kBlock) {
-        const Idx<DIM> p = decomp<DIM>(idx, op.n);
+    ROW_LOOP(R, lb) {
+        Idx<DIM> p;
+        int idx;
+        if (!row_item<DIM>(R, w_, p, idx)) continue;
         const double bi = b[idx];
         const double ri = bi - fine_apply<DIM, double>(op, x, idx, p);
         r[idx] = ri;
         v[0] += bi * bi;
         v[1] += ri * ri;
     }
-    block_sum_store<2>(v, part + (size_t)lb * 2);
+    block_sum_store<2>(v, part, gridDim.x, lb);
 }
 
 // True-residual refresh r = b - A x in FP64 (mixed form, only when requested).
 template <int DIM>
-__global__ void __launch_bounds__(kBlock) k_refresh(const Ctl* __restrict__ ctl, FineOp<double> op,
+__global__ void __launch_bounds__(kBlock) k_refresh(const Ctl* __restrict__ ctl, Rows R, FineOp<double> op,
                                                     const double* __restrict__ b, const double* __restrict__ x,
                                                     double* __restrict__ r, double* __restrict__ part) {
     if (ctl->state == 2 || !ctl->refresh_req) return;
     const int lb = xcd_block(gridDim.x);
     double v[1] = {0.0};
-    for (int idx = lb * kBlock + threadIdx.x; idx < op.N; idx += gridDim.x * kBlock) {
-        const Idx<DIM> p = decomp<DIM>(idx, op.n);
+    ROW_LOOP(R, lb) {
+        Idx<DIM> p;
+        int idx;
+        if (!row_item<DIM>(R, w_, p, idx)) continue;
         const double ri = b[idx] - fine_apply<DIM, double>(op, x, idx, p);
         r[idx] = ri;
         v[0] += ri * ri;
     }
-    block_sum_store<1>(v, part + lb);
+    block_sum_store<1>(v, part, gridDim.x, lb);
 }
 
 // r -= Q alpha (pointwise, FP64 r), partial ||r||^2.
@@ -257,18 +377,22 @@ __global__ void __launch_bounds__(kBlock) k_update_r(const Ctl* __restrict__ ctl
         r[idx] = ri;
         v[0] += ri * ri;
     }
-    block_sum_store<1>(v, part + lb);
+    block_sum_store<1>(v, part, gridDim.x, lb);
 }
 
 // Fine-level damped Jacobi, first min(nu, 2) sweeps from c0 = 0:
 //   c1 = omega (g / D);  c2 = c1 + omega ((g - A c1) / D)   (eq. (2)).
 template <int DIM, typename T, typename G>
-__global__ void __launch_bounds__(kBlock) k_fine_smooth(const Ctl* __restrict__ ctl, FineOp<T> op,
+__global__ void __launch_bounds__(kBlock) k_fine_smooth(const Ctl* __restrict__ ctl, Rows R, FineOp<T> op,
                                                         const G* __restrict__ g, T* __restrict__ c, T omega,
                                                         int two_sweeps) {
     if (ctl->state != 0) return;
     const int lb = xcd_block(gridDim.x);
-    for (int idx = lb * kBlock + threadIdx.x; idx < op.N; idx += gridDim.x * kBlock) {
+    const int n = op.n, sy = n, sz = n * n;
+    ROW_LOOP(R, lb) {
+        Idx<DIM> p;
+        int idx;
+        if (!row_item<DIM>(R, w_, p, idx)) continue;
         const T gi = T(g[idx]);
         const T Di = fine_diag<DIM>(op, idx);
         const T c1 = omega * (gi / Di);
@@ -276,9 +400,7 @@ __global__ void __launch_bounds__(kBlock) k_fine_smooth(const Ctl* __restrict__ 
             c[idx] = c1;
             continue;
         }
-        const Idx<DIM> p = decomp<DIM>(idx, op.n);
         // A c1 with c1_j = omega (g_j / D_j) formed on the fly
-        const int n = op.n, sy = n, sz = n * n;
         auto c1at = [&](int j) -> T { return omega * (T(g[j]) / fine_diag<DIM>(op, j)); };
         T Ac;
         if (!op.D) {
@@ -310,13 +432,15 @@ __global__ void __launch_bounds__(kBlock) k_fine_smooth(const Ctl* __restrict__ 
 
 // One further fine sweep: cout = cin + omega ((g - A cin) / D).
 template <int DIM, typename T, typename G>
-__global__ void __launch_bounds__(kBlock) k_fine_sweep(const Ctl* __restrict__ ctl, FineOp<T> op,
+__global__ void __launch_bounds__(kBlock) k_fine_sweep(const Ctl* __restrict__ ctl, Rows R, FineOp<T> op,
                                                        const G* __restrict__ g, const T* __restrict__ cin,
                                                        T* __restrict__ cout, T omega) {
     if (ctl->state != 0) return;
     const int lb = xcd_block(gridDim.x);
-    for (int idx = lb * kBlock + threadIdx.x; idx < op.N; idx += gridDim.x * kBlock) {
-        const Idx<DIM> p = decomp<DIM>(idx, op.n);
+    ROW_LOOP(R, lb) {
+        Idx<DIM> p;
+        int idx;
+        if (!row_item<DIM>(R, w_, p, idx)) continue;
         const T res = T(g[idx]) - fine_apply<DIM, T>(op, cin, idx, p);
         cout[idx] = cin[idx] + omega * (res / fine_diag<DIM>(op, idx));
     }
@@ -398,10 +522,6 @@ __global__ void __launch_bounds__(kBlock) k_coarse_smooth(const Ctl* __restrict_
 }
 
 // Prolongate ncols coarse columns to the next finer level (thread per fine node).
-template <typename T>
-struct ColPtrs {
-    const T* p[kMaxNB];
-};
 
 template <int DIM, typename T>
 __global__ void __launch_bounds__(kBlock) k_prolong(const Ctl* __restrict__ ctl, ColPtrs<T> in, int ncols, int nc,
@@ -413,28 +533,20 @@ __global__ void __launch_bounds__(kBlock) k_prolong(const Ctl* __restrict__ ctl,
     for (int c = 0; c < ncols; ++c) out[(size_t)c * Nf + idx] = interp_at<DIM, T>(in.p[c], nc, p);
 }
 
-// Level corrections at one fine node: z[c] for c < NB-1 interpolated from the
-// NB-1 level-(L-1) columns, z[NB-1] = cL (the finest smoother output).
+// W = Q_k^T Z_{k+1} partial sums (NB x NB, entry a*NB+c = Q column a . z^c).
 template <int DIM, typename T, int NB>
-__device__ __forceinline__ void fine_z(const ColPtrs<T>& Y, int nc, const T* __restrict__ cL, int idx,
-                                       const Idx<DIM>& p, T (&z)[NB]) {
-#pragma unroll
-    for (int c = 0; c < NB - 1; ++c) z[c] = interp_at<DIM, T>(Y.p[c], nc, p);
-    z[NB - 1] = cL[idx];
-}
-
-// W = Q_k^T Z_{k+1} partial sums (NB x NB, row a = Q column a).
-template <int DIM, typename T, int NB>
-__global__ void __launch_bounds__(kBlock) k_fine_W(const Ctl* __restrict__ ctl, int nf, int N, ColPtrs<T> Y, int nc,
-                                                   const T* __restrict__ cL, const T* __restrict__ Q,
+__global__ void __launch_bounds__(kBlock) k_fine_W(const Ctl* __restrict__ ctl, Rows R, int N, ColPtrs<T> Y,
+                                                   int nc, const T* __restrict__ cL, const T* __restrict__ Q,
                                                    double* __restrict__ part) {
     if (ctl->state != 0) return;
     const int lb = xcd_block(gridDim.x);
     double w[NB * NB];
 #pragma unroll
     for (int q = 0; q < NB * NB; ++q) w[q] = 0.0;
-    for (int idx = lb * kBlock + threadIdx.x; idx < N; idx += gridDim.x * kBlock) {
-        const Idx<DIM> p = decomp<DIM>(idx, nf);
+    ROW_LOOP(R, lb) {
+        Idx<DIM> p;
+        int idx;
+        if (!row_item<DIM>(R, w_, p, idx)) continue;
         T z[NB];
         fine_z<DIM, T, NB>(Y, nc, cL, idx, p, z);
 #pragma unroll
@@ -444,40 +556,40 @@ __global__ void __launch_bounds__(kBlock) k_fine_W(const Ctl* __restrict__ ctl, 
             for (int c = 0; c < NB; ++c) w[a * NB + c] += qa * double(z[c]);
         }
     }
-    block_sum_store<NB * NB>(w, part + (size_t)lb * NB * NB);
+    block_sum_store<NB * NB>(w, part, gridDim.x, lb);
 }
 
 // x += P_k alpha_k (deferred update of Algorithm 1); then, unless stopping,
 // P_{k+1} = Z_{k+1} - P_k beta in place (Z recomputed from the coarse block).
 // init = 1: P_0 = Z_0 only.
 template <int DIM, typename T, int NB>
-__global__ void __launch_bounds__(kBlock) k_update_xP(const Ctl* __restrict__ ctl, int nf, int N, ColPtrs<T> Y,
+__global__ void __launch_bounds__(kBlock) k_update_xP(const Ctl* __restrict__ ctl, Rows R, int N, ColPtrs<T> Y,
                                                       int nc, const T* __restrict__ cL, T* __restrict__ P,
                                                       double* __restrict__ x, const double* __restrict__ alpha,
                                                       const double* __restrict__ beta, int init) {
     const int state = ctl->state;
     if (state == 2 || (init && state != 0)) return;
     const int lb = xcd_block(gridDim.x);
-    double a[NB], bt[NB * NB];
+    __shared__ double sab[NB + NB * NB];
     if (!init) {
-#pragma unroll
-        for (int c = 0; c < NB; ++c) a[c] = alpha[c];
-#pragma unroll
-        for (int q = 0; q < NB * NB; ++q) bt[q] = beta[q];
+        for (int q = threadIdx.x; q < NB + NB * NB; q += kBlock) sab[q] = q < NB ? alpha[q] : beta[q - NB];
     }
-    for (int idx = lb * kBlock + threadIdx.x; idx < N; idx += gridDim.x * kBlock) {
+    __syncthreads();
+    ROW_LOOP(R, lb) {
+        Idx<DIM> p;
+        int idx;
+        if (!row_item<DIM>(R, w_, p, idx)) continue;
         T pk[NB];
         if (!init) {
             double xi = x[idx];
 #pragma unroll
             for (int c = 0; c < NB; ++c) {
                 pk[c] = P[(size_t)c * N + idx];
-                xi += double(pk[c]) * a[c];
+                xi += double(pk[c]) * sab[c];
             }
             x[idx] = xi;
             if (state != 0) continue;
         }
-        const Idx<DIM> p = decomp<DIM>(idx, nf);
         T z[NB];
         fine_z<DIM, T, NB>(Y, nc, cL, idx, p, z);
 #pragma unroll
@@ -485,7 +597,7 @@ __global__ void __launch_bounds__(kBlock) k_update_xP(const Ctl* __restrict__ ct
             double v = double(z[c]);
             if (!init) {
 #pragma unroll
-                for (int a2 = 0; a2 < NB; ++a2) v -= double(pk[a2]) * bt[a2 * NB + c];
+                for (int a2 = 0; a2 < NB; ++a2) v -= double(pk[a2]) * sab[NB + a2 * NB + c];
             }
             P[(size_t)c * N + idx] = T(v);
         }
@@ -493,9 +605,9 @@ __global__ void __launch_bounds__(kBlock) k_update_xP(const Ctl* __restrict__ ct
 }
 
 // Q = A P (block SpMM), partial sums of the Gram upper triangle P^T Q and of
-// P^T r:  part row = [G_00, G_01, .., G_0,NB-1, G_11, .., G_NB-1,NB-1, g_0..g_NB-1].
+// P^T r, value order [G_00, G_01, .., G_0,NB-1, G_11, .., G_NB-1,NB-1, g_0..g_NB-1].
 template <int DIM, typename T, int NB>
-__global__ void __launch_bounds__(kBlock) k_spmm_gram(const Ctl* __restrict__ ctl, FineOp<T> op,
+__global__ void __launch_bounds__(kBlock) k_spmm_gram(const Ctl* __restrict__ ctl, Rows R, FineOp<T> op,
                                                       const T* __restrict__ P, T* __restrict__ Q,
                                                       const double* __restrict__ r, double* __restrict__ part) {
     if (ctl->state != 0) return;
@@ -505,8 +617,10 @@ __global__ void __launch_bounds__(kBlock) k_spmm_gram(const Ctl* __restrict__ ct
     double acc[NG + NB];
 #pragma unroll
     for (int q = 0; q < NG + NB; ++q) acc[q] = 0.0;
-    for (int idx = lb * kBlock + threadIdx.x; idx < N; idx += gridDim.x * kBlock) {
-        const Idx<DIM> p = decomp<DIM>(idx, op.n);
+    ROW_LOOP(R, lb) {
+        Idx<DIM> p;
+        int idx;
+        if (!row_item<DIM>(R, w_, p, idx)) continue;
         double pv[NB], qv[NB];
 #pragma unroll
         for (int c = 0; c < NB; ++c) {
@@ -525,20 +639,22 @@ __global__ void __launch_bounds__(kBlock) k_spmm_gram(const Ctl* __restrict__ ct
 #pragma unroll
         for (int a = 0; a < NB; ++a) acc[NG + a] += pv[a] * ri;
     }
-    block_sum_store<NG + NB>(acc, part + (size_t)lb * (NG + NB));
+    block_sum_store<NG + NB>(acc, part, gridDim.x, lb);
 }
 
 // Explicit Z (widened to double), for the mg_block entry point.
 template <int DIM, typename T, int NB>
-__global__ void __launch_bounds__(kBlock) k_write_Z(int nf, int N, ColPtrs<T> Y, int nc, const T* __restrict__ cL,
+__global__ void __launch_bounds__(kBlock) k_write_Z(Rows R, int N, ColPtrs<T> Y, int nc, const T* __restrict__ cL,
                                                     double* __restrict__ Z) {
-    const int idx = blockIdx.x * kBlock + threadIdx.x;
-    if (idx >= N) return;
-    const Idx<DIM> p = decomp<DIM>(idx, nf);
-    T z[NB];
-    fine_z<DIM, T, NB>(Y, nc, cL, idx, p, z);
+    ROW_LOOP(R, blockIdx.x) {
+        Idx<DIM> p;
+        int idx;
+        if (!row_item<DIM>(R, w_, p, idx)) continue;
+        T z[NB];
+        fine_z<DIM, T, NB>(Y, nc, cL, idx, p, z);
 #pragma unroll
-    for (int c = 0; c < NB; ++c) Z[(size_t)c * N + idx] = double(z[c]);
+        for (int c = 0; c < NB; ++c) Z[(size_t)c * N + idx] = double(z[c]);
+    }
 }
 
 // b == 0: x = 0.

@@ -1,6 +1,6 @@
 // Single-block kernels: the global reductions of one iteration, the b x b
 // pseudo-inverse of the Gram matrix, the step coefficients alpha and beta,
-// convergence and stop logic.  They run as one 256-thread block; the
+// convergence and stop logic.  They run as one 1024-thread block; the
 // eigen-decomposition runs in wavefront 0 with one Gram entry per lane.
 #pragma once
 
@@ -10,6 +10,25 @@ namespace amg {
 
 // Status codes mirrored from the public header (kept numerically equal).
 constexpr int kOK = 0, kMAXIT = 1, kBREAKDOWN = 2, kNONFINITE = -4;
+
+// In-place Gauss-Jordan inversion of a symmetric positive definite NB x NB
+// matrix held one entry per lane (lane l < NB*NB owns (i, j)); no pivoting.
+// ok becomes false if a pivot is not positive (then the content is garbage).
+template <int NB>
+__device__ __forceinline__ void wave_gauss_jordan(double& a, int i, int j, bool live, bool& ok) {
+    for (int p = 0; p < NB; ++p) {
+        const double piv = __shfl(a, p * NB + p);
+        const double apj = __shfl(a, p * NB + j);
+        const double aip = __shfl(a, i * NB + p);
+        if (!(piv > 0.0)) {
+            ok = false;
+            return;
+        }
+        const double rpj = ((j == p) ? 1.0 : apj) / piv;
+        const double a2 = (i == p) ? rpj : ((j == p) ? 0.0 : a) - aip * rpj;
+        a = live ? a2 : 0.0;
+    }
+}
 
 // Pseudo-inverse of a symmetric PSD NB x NB matrix G (row-major, shared
 // memory) by cyclic Jacobi on the unit-diagonal scaling Ghat = S G S,
@@ -31,6 +50,23 @@ __device__ int wave_pinv(const double* G, double tau, double* Gplus) {
         return 0;
     }
     double a = (live && ai && aj) ? (gij * si) * sj : 0.0;
+    // Fast path: if Ghat - 2 tau I is positive definite (all Gauss-Jordan
+    // pivots positive), no eigenvalue of Ghat is <= tau, so the pseudo-inverse
+    // is the inverse; it is formed by in-place Gauss-Jordan.  Otherwise the
+    // eigen-decomposition below applies the cut.
+    {
+        bool ok = true;
+        double shifted = a - ((live && i == j) ? 2.0 * tau : 0.0);
+        wave_gauss_jordan<NB>(shifted, i, j, live, ok);
+        if (ok) {
+            double inv = a;
+            wave_gauss_jordan<NB>(inv, i, j, live, ok);
+            if (ok) {
+                if (live) Gplus[lane] = si * inv * sj;
+                return NB;
+            }
+        }
+    }
     double v = (live && i == j) ? 1.0 : 0.0;
     for (int sweep = 0; sweep < 30; ++sweep) {
         const double off = wave_sum((live && i != j) ? a * a : 0.0);
@@ -79,7 +115,7 @@ __device__ int wave_pinv(const double* G, double tau, double* Gplus) {
 }
 
 // After the init residual: ||b||, ||r_0||, stop if r_0 already small.
-__global__ void __launch_bounds__(kBlock) k_reduce_init(Ctl* ctl, const double* part, int nblk, double tol,
+__global__ void __launch_bounds__(kRedBlock) k_reduce_init(Ctl* ctl, const double* part, int nblk, double tol,
                                                         double* rhist) {
     __shared__ double res[2];
     reduce_partials<2>(part, nblk, res);
@@ -111,7 +147,7 @@ __global__ void __launch_bounds__(kBlock) k_reduce_init(Ctl* ctl, const double* 
 // mixed != 0: convergence on the recursive residual only requests a
 // true-residual refresh; the refresh decides.
 template <int NB>
-__global__ void __launch_bounds__(kBlock) k_reduce_beta(Ctl* ctl, const double* part_rho, const double* part_W,
+__global__ void __launch_bounds__(kRedBlock) k_reduce_beta(Ctl* ctl, const double* part_rho, const double* part_W,
                                                         int nblk, const double* Gplus, double* beta, double* rhist,
                                                         int mixed) {
     if (ctl->state != 0) return;
@@ -144,7 +180,7 @@ __global__ void __launch_bounds__(kBlock) k_reduce_beta(Ctl* ctl, const double* 
     }
     __syncthreads();
     if (stop) return;
-    for (int q = threadIdx.x; q < NB * NB; q += kBlock) {
+    for (int q = threadIdx.x; q < NB * NB; q += kRedBlock) {
         const int a = q / NB, c = q % NB;
         double s = 0.0;
         for (int m = 0; m < NB; ++m) s += Gplus[a * NB + m] * W[m * NB + c];
@@ -155,7 +191,7 @@ __global__ void __launch_bounds__(kBlock) k_reduce_beta(Ctl* ctl, const double* 
 // Gram G = P^T A P (upper triangle mirrored), g = P^T r, pseudo-inverse,
 // alpha = G^+ g.  State 1 (stop after the x update) becomes 2 here.
 template <int NB>
-__global__ void __launch_bounds__(kBlock) k_reduce_alpha(Ctl* ctl, const double* part, int nblk, double* Gplus,
+__global__ void __launch_bounds__(kRedBlock) k_reduce_alpha(Ctl* ctl, const double* part, int nblk, double* Gplus,
                                                          double* alpha, double* ahist) {
     const int state = ctl->state;
     if (state == 2) return;
@@ -198,7 +234,7 @@ __global__ void __launch_bounds__(kBlock) k_reduce_alpha(Ctl* ctl, const double*
 }
 
 // After a true-residual refresh r = b - A x: accept convergence or go on.
-__global__ void __launch_bounds__(kBlock) k_refresh_reduce(Ctl* ctl, const double* part, int nblk, double* rhist) {
+__global__ void __launch_bounds__(kRedBlock) k_refresh_reduce(Ctl* ctl, const double* part, int nblk, double* rhist) {
     if (ctl->state == 2 || !ctl->refresh_req) return;
     __shared__ double res[1];
     reduce_partials<1>(part, nblk, res);
@@ -217,6 +253,16 @@ __global__ void __launch_bounds__(kBlock) k_refresh_reduce(Ctl* ctl, const doubl
         ctl->status = kOK;
         ctl->state = 2;
     }
+}
+
+// Standalone pseudo-inverse of one Gram matrix (for the gram_pinv entry point).
+template <int NB>
+__global__ void __launch_bounds__(64) k_pinv_only(const double* G, double tau, double* Gplus, int* rank) {
+    __shared__ double Gs[NB * NB];
+    for (int q = threadIdx.x; q < NB * NB; q += 64) Gs[q] = G[q];
+    __syncthreads();
+    const int rk = wave_pinv<NB>(Gs, tau, Gplus);
+    if (threadIdx.x == 0) *rank = rk;
 }
 
 }  // namespace amg

@@ -244,3 +244,55 @@ def test_full_size_mixed(name):
           f"refreshes {info['refreshes']}, sampled rel err vs FP64 oracle {err:.2e}")
     assert true_rel <= 1e-8
     s.close()
+
+
+@pytest.mark.parametrize("nb", [1, 4, 6, 7, 8])
+def test_pinv_full_rank(nb):
+    rng = np.random.default_rng(nb)
+    B = rng.standard_normal((60, nb)) * np.exp(rng.uniform(-5, 5, nb))
+    G = B.T @ B
+    tau = mpcg.default_tau(nb)
+    Gp, rank = amg.gram_pinv(G, tau)
+    ref = mpcg.pinv_gram(G, tau)
+    assert rank == ref.rank == nb
+    np.testing.assert_allclose(Gp, ref.Gplus, rtol=1e-9, atol=1e-12 * np.abs(ref.Gplus).max())
+
+
+@pytest.mark.parametrize("kind", ["duplicate", "zero", "nan", "near_tau"])
+def test_pinv_rank_deficient(kind):
+    rng = np.random.default_rng(3)
+    nb = 6
+    B = rng.standard_normal((40, nb))
+    tau = mpcg.default_tau(nb)
+    if kind == "duplicate":
+        B[:, 5] = 2.0 * B[:, 1]
+    elif kind == "zero":
+        B[:, 2] = 0.0
+    elif kind == "near_tau":
+        # smallest eigenvalue of the unit-diagonal Gram between tau and 2 tau:
+        # kept by both (exercises the eigen path on the device)
+        B[:, 5] = B[:, 1] + 4e-7 * rng.standard_normal(40)   # lambda_min ~ 1.5 tau
+    G = B.T @ B
+    if kind == "nan":
+        G[3, 3] = np.nan
+    Gp, rank = amg.gram_pinv(G, tau)
+    ref = mpcg.pinv_gram(G, tau)
+    assert rank == ref.rank
+    y = rng.standard_normal(40)
+    g = B.T @ y
+    if kind == "near_tau":
+        # condition ~ 1/tau: alpha itself is ill-determined; what the step uses
+        # is the minimised residual ||y - B alpha||, which both must reach
+        ra = np.linalg.norm(y - B @ (Gp @ g))
+        rb = np.linalg.norm(y - B @ (ref.Gplus @ g))
+        assert abs(ra - rb) <= 1e-6 * rb
+        return
+    if kind == "nan":
+        keep = [0, 1, 2, 4, 5]
+        Bk = B[:, keep]
+        np.testing.assert_allclose(Bk @ (Gp[np.ix_(keep, keep)] @ g[keep]),
+                                   Bk @ (ref.Gplus[np.ix_(keep, keep)] @ g[keep]), rtol=1e-8, atol=1e-10)
+        assert np.all(Gp[3] == 0) and np.all(Gp[:, 3] == 0)
+    else:
+        ya, yb = B @ (Gp @ g), B @ (ref.Gplus @ g)
+        assert np.linalg.norm(ya - yb) <= 1e-8 * np.linalg.norm(yb)
