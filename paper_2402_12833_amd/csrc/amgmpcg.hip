@@ -46,7 +46,9 @@ struct ApiError : std::runtime_error {
         }                                                                                              \
     } while (0)
 
-constexpr int kMaxFineBlocks = 1024;
+constexpr int kMaxFineBlocks = 2048;
+constexpr int kTailMax = 4096;          // prolongation outputs up to this size: single-block chain
+constexpr int kRestrictTailMax = 512;   // restriction outputs up to this size: single-block chain
 constexpr int kPartRow = 2 + 1 + kMaxNB * kMaxNB + (kMaxNB * (kMaxNB + 1) / 2 + kMaxNB) + 1;
 
 template <typename T>
@@ -159,6 +161,7 @@ class Solver : public SolverBase {
         }
         coef_.resize(nlev);
         g_.resize(nlev);
+        c1_.resize(nlev);
         c_.resize(nlev);
         c2_.resize(nlev);
         Y_.resize(nlev);
@@ -167,15 +170,22 @@ class Solver : public SolverBase {
             coef_[l].alloc((size_t)S * N_[l]);
             upload_conv(coef_[l].p, lev[l].coef);
             g_[l].alloc(N_[l]);
-            c_[l].alloc(N_[l]);
-            if (opt_.nu > 2) c2_[l].alloc(N_[l]);
-            if (l >= 1) Y_[l].alloc((size_t)l * N_[l]);
+            c1_[l].alloc(N_[l]);
+            if (opt_.nu > 2) {
+                c_[l].alloc(N_[l]);
+                c2_[l].alloc(N_[l]);
+            }
+            // node-major block carry [P Y_{l-1} | c_l], l+1 columns, even stride
+            Y_[l].alloc((size_t)even_up(l + 1) * N_[l]);
+            HIPCHK(hipMemset(Y_[l].p, 0, Y_[l].n * sizeof(T)));
         }
         x_.alloc(N);
         r_.alloc(N);
         b_.alloc(N);
-        P_.alloc((size_t)nb * N);
-        Q_.alloc((size_t)nb * N);
+        P_.alloc((size_t)even_up(nb) * N);
+        Q_.alloc((size_t)even_up(nb) * N);
+        HIPCHK(hipMemset(P_.p, 0, P_.n * sizeof(T)));
+        HIPCHK(hipMemset(Q_.p, 0, Q_.n * sizeof(T)));
         cL_.alloc(N);
         if (opt_.nu > 2) cL2_.alloc(N);
         part_.alloc((size_t)FB_ * kPartRow);
@@ -260,7 +270,7 @@ class Solver : public SolverBase {
         dispatch_nb([&](auto nbc) {
             constexpr int NB = decltype(nbc)::value;
             k_write_Z<DIM, T, NB><<<(rows_.total + kBlock - 1) / kBlock, kBlock, 0, stream_>>>(
-                rows_, N, fine_cols(), L_ > 0 ? n_axis[L_ - 1] : 1, cL_final_, Z_dev);
+                rows_, N, fine_Y(), L_ > 0 ? n_axis[L_ - 1] : 1, cL_final_, Z_dev);
         });
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(stream_));
@@ -321,31 +331,13 @@ class Solver : public SolverBase {
                 const int l = L_ - 1;
                 timed([&] {
                     k_restrict<DIM, double, T><<<(N_[l] + kBlock - 1) / kBlock, kBlock, 0, stream_>>>(
-                        cf, r_.p, n_axis[L_], g_[l].p, n_axis[l], N_[l]);
+                        cf, r_.p, n_axis[L_], g_[l].p, n_axis[l], N_[l], diag(l), c1_[l].p, omega);
                 });
-                CoarseLevels<T> cl{};
-                cl.nlev = L_;
-                int off = 0;
-                for (int m = 0; m < L_; ++m) {
-                    cl.blk_off[m] = off;
-                    off += (N_[m] + kBlock - 1) / kBlock;
-                    cl.n[m] = n_axis[m];
-                    cl.N[m] = N_[m];
-                    cl.coef[m] = coef_[m].p;
-                    cl.g[m] = g_[m].p;
-                    cl.cout[m] = c_[m].p;
-                }
-                cl.blk_off[L_] = off;
+                CoarseLevels<T> cl = coarse_arg(0);
+                const int off = cl.blk_off[L_];
                 timed([&] { k_coarse_smooth<DIM, T><<<off, kBlock, 0, stream_>>>(cf, cl, omega, 0, opt_.nu >= 2 ? 1 : 0); });
                 if (L_ >= 2) {
-                    const int m = L_ - 2;
-                    ColPtrs<T> in{};
-                    for (int c = 0; c < m; ++c) in.p[c] = Y_[m].p + (size_t)c * N_[m];
-                    in.p[m] = c_[m].p;
-                    timed([&] {
-                        k_prolong<DIM, T><<<(N_[m + 1] + kBlock - 1) / kBlock, kBlock, 0, stream_>>>(
-                            cf, in, m + 1, n_axis[m], Y_[m + 1].p, n_axis[m + 1], N_[m + 1]);
-                    });
+                    timed([&] { launch_prolong(cf, L_ - 2); });
                 } else {
                     timed([&] {});
                 }
@@ -356,12 +348,11 @@ class Solver : public SolverBase {
             }
             enqueue_mg(cf, r_.p);
             timed([&] {
-                k_fine_W<DIM, T, NB><<<FB_, kBlock, 0, stream_>>>(cf, rows_, N, fine_cols(), nc, cL_final_, Q_.p,
-                                                                   part_W());
+                k_fine_W<DIM, T, NB><<<FB_, kBlock, 0, stream_>>>(cf, rows_, fine_Y(), nc, cL_final_, Q_.p, part_W());
             });
             timed([&] {
-                k_update_xP<DIM, T, NB><<<FB_, kBlock, 0, stream_>>>(cf, rows_, N, fine_cols(), nc, cL_final_,
-                                                                      P_.p, x_.p, d_alpha(), d_beta(), 0);
+                k_update_xP<DIM, T, NB><<<FB_, kBlock, 0, stream_>>>(cf, rows_, fine_Y(), nc, cL_final_, P_.p, x_.p,
+                                                                      d_alpha(), d_beta(), 0);
             });
             timed([&] { k_spmm_gram<DIM, T, NB><<<FB_, kBlock, 0, stream_>>>(cf, rows_, fop_, P_.p, Q_.p, r_.p, part_G()); });
             timed([&] { k_init_residual<DIM><<<FB_, kBlock, 0, stream_>>>(rows_, f64_, b_.p, x_.p, r_.p, part_init()); });
@@ -431,14 +422,54 @@ class Solver : public SolverBase {
         HIPCHK(hipMemcpy(dst, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice));
     }
 
-    // Columns of the level-(L-1) block used to form the fine corrections.
-    ColPtrs<T> fine_cols() const {
-        ColPtrs<T> cp{};
-        if (L_ == 0) return cp;
-        const int l = L_ - 1;
-        for (int c = 0; c < l; ++c) cp.p[c] = Y_[l].p + (size_t)c * N_[l];
-        cp.p[l] = c_final_[l];
-        return cp;
+    // Diagonal (stencil centre) of coarse level l.
+    const T* diag(int l) const { return coef_[l].p + (size_t)(DIM == 2 ? 4 : 13) * N_[l]; }
+
+    // The node-major level-(L-1) block from which the fine corrections are formed.
+    const T* fine_Y() const { return L_ > 0 ? Y_[L_ - 1].p : nullptr; }
+
+    // Arguments of the level-fused coarse smoother.  final_out: write into the
+    // last column of each level's block carry (else into the c_ buffer).
+    CoarseLevels<T> coarse_arg(int final_out) const {
+        CoarseLevels<T> cl{};
+        cl.nlev = L_;
+        int off = 0;
+        for (int l = 0; l < L_; ++l) {
+            cl.blk_off[l] = off;
+            off += (N_[l] + kBlock - 1) / kBlock;
+            cl.n[l] = n_axis[l];
+            cl.N[l] = N_[l];
+            cl.coef[l] = coef_[l].p;
+            cl.g[l] = g_[l].p;
+            cl.c1[l] = c1_[l].p;
+            if (final_out || !c_[l].p) {
+                cl.cout[l] = Y_[l].p + l;
+                cl.cstride[l] = even_up(l + 1);
+            } else {
+                cl.cout[l] = c_[l].p;
+                cl.cstride[l] = 1;
+            }
+            cl.cin[l] = nullptr;
+        }
+        cl.blk_off[L_] = off;
+        return cl;
+    }
+
+    // Y_{l+1}[:, 0..l] = P Y_l (l+1 columns).
+    void launch_prolong(const Ctl* ctl, int l) {
+        const int grid = (N_[l + 1] + kBlock - 1) / kBlock;
+        const T* Yc = Y_[l].p;
+        T* Yf = Y_[l + 1].p;
+        const int nc = n_axis[l], nf = n_axis[l + 1], Nf = N_[l + 1];
+        switch (l + 1) {
+            case 1: k_prolong<DIM, T, 1><<<grid, kBlock, 0, stream_>>>(ctl, Yc, nc, Yf, nf, Nf); break;
+            case 2: k_prolong<DIM, T, 2><<<grid, kBlock, 0, stream_>>>(ctl, Yc, nc, Yf, nf, Nf); break;
+            case 3: k_prolong<DIM, T, 3><<<grid, kBlock, 0, stream_>>>(ctl, Yc, nc, Yf, nf, Nf); break;
+            case 4: k_prolong<DIM, T, 4><<<grid, kBlock, 0, stream_>>>(ctl, Yc, nc, Yf, nf, Nf); break;
+            case 5: k_prolong<DIM, T, 5><<<grid, kBlock, 0, stream_>>>(ctl, Yc, nc, Yf, nf, Nf); break;
+            case 6: k_prolong<DIM, T, 6><<<grid, kBlock, 0, stream_>>>(ctl, Yc, nc, Yf, nf, Nf); break;
+            default: k_prolong<DIM, T, 7><<<grid, kBlock, 0, stream_>>>(ctl, Yc, nc, Yf, nf, Nf); break;
+        }
     }
 
     // Z = MG(r) up to the coarse block and the fine smoother output.
@@ -462,54 +493,72 @@ class Solver : public SolverBase {
             cL_final_ = cur;
         }
         if (L == 0) return;
-        // restriction chain
+        // restriction chain: big levels one launch each, the small ones in one block
         {
             const int l = L - 1;
             k_restrict<DIM, double, T><<<(N_[l] + kBlock - 1) / kBlock, kBlock, 0, stream_>>>(
-                ctl, r, n_axis[L], g_[l].p, n_axis[l], N_[l]);
-            for (int m = L - 2; m >= 0; --m)
+                ctl, r, n_axis[L], g_[l].p, n_axis[l], N_[l], diag(l), c1_[l].p, omega);
+            int m = L - 2;
+            for (; m >= 0 && N_[m] > kRestrictTailMax; --m)
                 k_restrict<DIM, T, T><<<(N_[m] + kBlock - 1) / kBlock, kBlock, 0, stream_>>>(
-                    ctl, g_[m + 1].p, n_axis[m + 1], g_[m].p, n_axis[m], N_[m]);
-        }
-        // all coarse levels smoothed in one launch (per sweep)
-        {
-            CoarseLevels<T> cl{};
-            cl.nlev = L;
-            int off = 0;
-            c_final_.assign(nlev, nullptr);
-            std::vector<T*> first(L), other(L);
-            for (int l = 0; l < L; ++l) {
-                cl.blk_off[l] = off;
-                off += (N_[l] + kBlock - 1) / kBlock;
-                cl.n[l] = n_axis[l];
-                cl.N[l] = N_[l];
-                cl.coef[l] = coef_[l].p;
-                cl.g[l] = g_[l].p;
-                first[l] = (extra % 2 == 0) ? c_[l].p : c2_[l].p;
-                other[l] = (extra % 2 == 0) ? c2_[l].p : c_[l].p;
-                cl.cout[l] = first[l];
-                cl.cin[l] = nullptr;
-            }
-            cl.blk_off[L] = off;
-            k_coarse_smooth<DIM, T><<<off, kBlock, 0, stream_>>>(ctl, cl, omega, 0, two);
-            std::vector<T*> cur = first;
-            for (int s = 0; s < extra; ++s) {
-                for (int l = 0; l < L; ++l) {
-                    cl.cin[l] = cur[l];
-                    cl.cout[l] = (cur[l] == first[l]) ? other[l] : first[l];
+                    ctl, g_[m + 1].p, n_axis[m + 1], g_[m].p, n_axis[m], N_[m], diag(m), c1_[m].p, omega);
+            if (m >= 0) {
+                RestrictChain<T> ch{};
+                for (; m >= 0; --m) {
+                    const int q = ch.count++;
+                    ch.nf[q] = n_axis[m + 1];
+                    ch.nc[q] = n_axis[m];
+                    ch.Nc[q] = N_[m];
+                    ch.gf[q] = g_[m + 1].p;
+                    ch.gc[q] = g_[m].p;
+                    ch.D[q] = diag(m);
+                    ch.c1[q] = c1_[m].p;
                 }
-                k_coarse_smooth<DIM, T><<<off, kBlock, 0, stream_>>>(ctl, cl, omega, 1, two);
-                for (int l = 0; l < L; ++l) cur[l] = cl.cout[l];
+                k_restrict_tail<DIM, T><<<1, kTailBlock, 0, stream_>>>(ctl, ch, omega);
             }
-            for (int l = 0; l < L; ++l) c_final_[l] = cur[l];
         }
-        // prolongation chain: Y_{l+1} = [P Y_l | P c_l]
-        for (int l = 0; l + 1 < L; ++l) {
-            ColPtrs<T> in{};
-            for (int c = 0; c < l; ++c) in.p[c] = Y_[l].p + (size_t)c * N_[l];
-            in.p[l] = c_final_[l];
-            k_prolong<DIM, T><<<(N_[l + 1] + kBlock - 1) / kBlock, kBlock, 0, stream_>>>(
-                ctl, in, l + 1, n_axis[l], Y_[l + 1].p, n_axis[l + 1], N_[l + 1]);
+        // all coarse levels smoothed in one launch (per sweep); the final sweep
+        // writes c_l into the last column of the level's block carry
+        {
+            const int two_f = two;
+            if (extra == 0) {
+                CoarseLevels<T> cl = coarse_arg(1);
+                k_coarse_smooth<DIM, T><<<cl.blk_off[L], kBlock, 0, stream_>>>(ctl, cl, omega, 0, two_f);
+            } else {
+                CoarseLevels<T> cl = coarse_arg(0);     // first sweeps into c_
+                k_coarse_smooth<DIM, T><<<cl.blk_off[L], kBlock, 0, stream_>>>(ctl, cl, omega, 0, two_f);
+                for (int s2 = 0; s2 < extra; ++s2) {
+                    const bool last = s2 == extra - 1;
+                    const bool from_c = (s2 % 2) == 0;
+                    for (int l = 0; l < L; ++l) {
+                        cl.cin[l] = from_c ? c_[l].p : c2_[l].p;
+                        if (last) {
+                            cl.cout[l] = Y_[l].p + l;
+                            cl.cstride[l] = even_up(l + 1);
+                        } else {
+                            cl.cout[l] = from_c ? c2_[l].p : c_[l].p;
+                            cl.cstride[l] = 1;
+                        }
+                    }
+                    k_coarse_smooth<DIM, T><<<cl.blk_off[L], kBlock, 0, stream_>>>(ctl, cl, omega, 1, two_f);
+                }
+            }
+        }
+        // prolongation chain Y_{l+1}[:, 0..l] = P Y_l: small levels in one block
+        {
+            int l = 0;
+            ProlongChain<T> ch{};
+            ch.l0 = 0;
+            for (; l + 1 < L && N_[l + 1] <= kTailMax; ++l) {
+                const int q = ch.count++;
+                ch.nc[q] = n_axis[l];
+                ch.nf[q] = n_axis[l + 1];
+                ch.Nf[q] = N_[l + 1];
+                ch.Yc[q] = Y_[l].p;
+                ch.Yf[q] = Y_[l + 1].p;
+            }
+            if (ch.count > 0) k_prolong_head<DIM, T><<<1, kTailBlock, 0, stream_>>>(ctl, ch);
+            for (; l + 1 < L; ++l) launch_prolong(ctl, l);
         }
     }
 
@@ -531,7 +580,7 @@ class Solver : public SolverBase {
         dispatch_nb([&](auto nbc) {
             constexpr int NB = decltype(nbc)::value;
             const int nc = L_ > 0 ? n_axis[L_ - 1] : 1;
-            k_update_xP<DIM, T, NB><<<FB_, kBlock, 0, stream_>>>(ctl_, rows_, N, fine_cols(), nc, cL_final_,
+            k_update_xP<DIM, T, NB><<<FB_, kBlock, 0, stream_>>>(ctl_, rows_, fine_Y(), nc, cL_final_,
                                                                    P_.p, x_.p, d_alpha(), d_beta(), 1);
             k_spmm_gram<DIM, T, NB><<<FB_, kBlock, 0, stream_>>>(ctl_, rows_, fop_, P_.p, Q_.p, r_.p, part_G());
             k_reduce_alpha<NB><<<1, kRedBlock, 0, stream_>>>(ctl_, part_G(), FB_, d_Gplus(), d_alpha(),
@@ -548,11 +597,11 @@ class Solver : public SolverBase {
             const int nc = L_ > 0 ? n_axis[L_ - 1] : 1;
             k_update_r<T, NB><<<FB_, kBlock, 0, s>>>(ctl_, N, Q_.p, d_alpha(), r_.p, part_rho());
             enqueue_mg(ctl_, r_.p);
-            k_fine_W<DIM, T, NB><<<FB_, kBlock, 0, s>>>(ctl_, rows_, N, fine_cols(), nc, cL_final_, Q_.p,
+            k_fine_W<DIM, T, NB><<<FB_, kBlock, 0, s>>>(ctl_, rows_, fine_Y(), nc, cL_final_, Q_.p,
                                                          part_W());
             k_reduce_beta<NB><<<1, kRedBlock, 0, s>>>(ctl_, part_rho(), part_W(), FB_, d_Gplus(), d_beta(),
                                                    hist_cap_ ? rhist_.p : nullptr, mixed_ ? 1 : 0);
-            k_update_xP<DIM, T, NB><<<FB_, kBlock, 0, s>>>(ctl_, rows_, N, fine_cols(), nc, cL_final_, P_.p,
+            k_update_xP<DIM, T, NB><<<FB_, kBlock, 0, s>>>(ctl_, rows_, fine_Y(), nc, cL_final_, P_.p,
                                                             x_.p, d_alpha(), d_beta(), 0);
             if (mixed_) {
                 k_refresh<DIM><<<FB_, kBlock, 0, s>>>(ctl_, rows_, f64_, b_.p, x_.p, r_.p, part_ref());
@@ -591,8 +640,7 @@ class Solver : public SolverBase {
     FineOp<double> f64_{};
     DevBuf<T> fD_, fex_, fey_, fez_;
     DevBuf<double> gD_, gex_, gey_, gez_;
-    std::vector<DevBuf<T>> coef_, g_, c_, c2_, Y_;
-    std::vector<T*> c_final_;
+    std::vector<DevBuf<T>> coef_, g_, c1_, c_, c2_, Y_;
     T* cL_final_ = nullptr;
     DevBuf<double> x_, r_, b_, part_, small_, ahist_, rhist_;
     DevBuf<T> P_, Q_, cL_, cL2_;

@@ -52,19 +52,58 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Smallest power of two >= k (k <= 64).
+__host__ __device__ constexpr int pow2_up(int k) { return k <= 1 ? 1 : 2 * pow2_up((k + 1) / 2); }
+
+// Reduce K values per lane over the 64 lanes of a wavefront by recursive
+// halving: at distance d = 32, 16, ... each lane keeps one half of its value
+// list and adds the partner's copy of that half, so K values cost about K
+// shuffles instead of 6 K.  Afterwards lane l holds the wave sum of value
+// index vidx(l) in v[0] (lanes sharing an index hold the same sum).  The
+// order of additions is fixed, so the result is deterministic.
+template <int K>
+__device__ __forceinline__ int wave_reduce_multi(double (&v)[K]) {
+    constexpr int KP = pow2_up(K);
+    constexpr int LOG = KP == 1 ? 0 : KP == 2 ? 1 : KP == 4 ? 2 : KP == 8 ? 3 : KP == 16 ? 4 : KP == 32 ? 5 : 6;
+    const int lane = threadIdx.x & 63;
+    int vidx = 0;
+#pragma unroll
+    for (int s = 0; s < LOG; ++s) {
+        const int half = KP >> (s + 1), d = 32 >> s;
+        const bool up = (lane & d) != 0;
+#pragma unroll
+        for (int i = 0; i < KP / 2; ++i) {
+            if (i < half && i < K) {
+                // values past K (padding of the first step) are zero
+                const double lo = v[i];
+                const double hi = (i + half < K) ? v[(i + half < K) ? i + half : 0] : 0.0;
+                const double send = up ? lo : hi;
+                const double keep = up ? hi : lo;
+                v[i] = keep + __shfl_xor(send, d);
+            }
+        }
+        vidx = 2 * vidx + (up ? 1 : 0);
+    }
+    // remaining distances: plain butterfly on the single value
+#pragma unroll
+    for (int s = LOG; s < 6; ++s) v[0] += __shfl_xor(v[0], 32 >> s);
+    return vidx;
+}
+
 // Sum K per-thread values over the block in a fixed order and store value k
 // of logical block lb at part[k * nblk + lb] (value-major, so that the final
-// reduction reads each value's partials contiguously).  Deterministic:
-// butterfly within each wave, then the wave sums in wave order.
+// reduction reads each value's partials contiguously).
 template <int K>
-__device__ __forceinline__ void block_sum_store(double (&v)[K], double* part, int nblk, int lb) {
-    __shared__ double sh[kWaves][K > 0 ? K : 1];
+__device__ __forceinline__ void block_sum_store(const double (&v)[K], double* part, int nblk, int lb) {
+    constexpr int KP = pow2_up(K);
+    __shared__ double sh[kWaves][KP];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double t[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        double s = wave_sum(v[k]);
-        if (lane == 0) sh[w][k] = s;
-    }
+    for (int k = 0; k < K; ++k) t[k] = v[k];
+    const int vi = wave_reduce_multi<K>(t);
+    // lanes holding the same index carry the same sum; the lowest one writes
+    if ((lane & (64 / KP - 1)) == 0) sh[w][vi] = t[0];
     __syncthreads();
     for (int k = threadIdx.x; k < K; k += kBlock) {
         double s = sh[0][k];

@@ -1,8 +1,10 @@
 // Structured-grid kernels of one MPCG iteration (Sec. 2, Algorithm 1).
 //
-// Layout in HBM (all levels): one value per node, flat index i + n*(j + n*k)
-// (x fastest); a block of b directions is b such vectors back to back
-// (column-major, leading dimension N).  Coarse operators are 3^d-point
+// Layout in HBM (all levels): flat node index i + n*(j + n*k) (x fastest).
+// Single vectors hold one value per node.  Blocks of several directions (the
+// search block P, Q = A P, and the coarse block carry Y) are node-major: the
+// S values of one node are contiguous, S = number of columns rounded up to
+// even, so that one node's values move with paired (16-byte / 8-byte) loads.  Coarse operators are 3^d-point
 // stencils stored coefficient-major: coef[s*N + idx] = A(idx, idx + o_s) with
 // s = (dz+1)*9 + (dy+1)*3 + (dx+1).  The finest operator is either the
 // constant 2d+1-point Laplacian (only h^-2 stored) or four face arrays
@@ -202,6 +204,46 @@ __device__ __forceinline__ C interp_at(const T* __restrict__ v, int nc, const Id
     return acc;
 }
 
+// ------------------------------------------------------------ vector access
+
+template <typename T>
+struct Pair;
+template <>
+struct Pair<double> {
+    using type = double2;
+};
+template <>
+struct Pair<float> {
+    using type = float2;
+};
+
+// Columns rounded up to even: the node stride of a block.
+__host__ __device__ constexpr int even_up(int k) { return k + (k & 1); }
+
+template <typename T, int S>
+__device__ __forceinline__ void load_node(const T* __restrict__ p, T (&o)[S]) {
+    static_assert(S % 2 == 0, "node stride must be even");
+    const typename Pair<T>::type* q = reinterpret_cast<const typename Pair<T>::type*>(p);
+#pragma unroll
+    for (int c = 0; c < S / 2; ++c) {
+        const typename Pair<T>::type v = q[c];
+        o[2 * c] = v.x;
+        o[2 * c + 1] = v.y;
+    }
+}
+
+template <typename T, int S>
+__device__ __forceinline__ void store_node(T* __restrict__ p, const T (&o)[S]) {
+    typename Pair<T>::type* q = reinterpret_cast<typename Pair<T>::type*>(p);
+#pragma unroll
+    for (int c = 0; c < S / 2; ++c) {
+        typename Pair<T>::type v;
+        v.x = o[2 * c];
+        v.y = o[2 * c + 1];
+        q[c] = v;
+    }
+}
+
 // ------------------------------------------------------- row-mapped fine loop
 //
 // Fine-level kernels map work items to (x-row, i): each x-row of n nodes is
@@ -276,46 +318,97 @@ __device__ __forceinline__ XPar xparents(int f, int nc) {
     return q;
 }
 
-// Interpolate a coarse column at a fine node whose y/z parents are uniform.
-template <int DIM, typename C, typename T>
-__device__ __forceinline__ C interp_row(const T* __restrict__ v, int nc, const XPar& px, const Par& py,
-                                        const Par& pz) {
-    C acc = C(0);
+// Interpolate all S columns of a node-major coarse block (stride S) at a fine
+// node; the y/z parents are uniform across the wavefront.
+template <int DIM, typename T, int S>
+__device__ __forceinline__ void interp_block(const T* __restrict__ Y, int nc, const XPar& px, const Par& py,
+                                             const Par& pz, T (&z)[S]) {
+#pragma unroll
+    for (int c = 0; c < S; ++c) z[c] = T(0);
     const int nzc = DIM == 3 ? pz.cnt : 1;
-    for (int c = 0; c < nzc; ++c) {
-        const int K = DIM == 3 ? (c ? pz.hi : pz.lo) : 0;
-        const C wz = DIM == 3 ? C(c ? pz.whi : pz.wlo) : C(1);
-        C plane = C(0);
+    for (int cz = 0; cz < nzc; ++cz) {
+        const int K = DIM == 3 ? (cz ? pz.hi : pz.lo) : 0;
+        const T wz = DIM == 3 ? T(cz ? pz.whi : pz.wlo) : T(1);
+        T plane[S];
+#pragma unroll
+        for (int c = 0; c < S; ++c) plane[c] = T(0);
         for (int b = 0; b < py.cnt; ++b) {
             const int J = b ? py.hi : py.lo;
-            const C wy = C(b ? py.whi : py.wlo);
-            const T* rowp = v + (size_t)nc * (J + (size_t)nc * K);
-            const C rowv = C(px.wlo) * C(rowp[px.lo]) + C(px.whi) * C(rowp[px.hi]);
-            plane += wy * rowv;
+            const T wy = T(b ? py.whi : py.wlo);
+            const size_t rowbase = (size_t)nc * (J + (size_t)nc * K);
+            T lo[S], hi[S];
+            load_node<T, S>(Y + (rowbase + px.lo) * S, lo);
+            load_node<T, S>(Y + (rowbase + px.hi) * S, hi);
+#pragma unroll
+            for (int c = 0; c < S; ++c) plane[c] += wy * (T(px.wlo) * lo[c] + T(px.whi) * hi[c]);
         }
-        acc += wz * plane;
+#pragma unroll
+        for (int c = 0; c < S; ++c) z[c] += wz * plane[c];
     }
-    return acc;
 }
 
 // Level corrections at one fine node: z[c] for c < NB-1 interpolated from the
-// NB-1 level-(L-1) columns, z[NB-1] = cL (the finest smoother output).
-template <typename T>
-struct ColPtrs {
-    const T* p[kMaxNB];
-};
-
+// node-major level-(L-1) block Y (NB-1 columns, stride even_up(NB-1)),
+// z[NB-1] = cL (the finest smoother output).
 template <int DIM, typename T, int NB>
-__device__ __forceinline__ void fine_z(const ColPtrs<T>& Y, int nc, const T* __restrict__ cL, int idx,
+__device__ __forceinline__ void fine_z(const T* __restrict__ Y, int nc, const T* __restrict__ cL, int idx,
                                        const Idx<DIM>& p, T (&z)[NB]) {
     if (NB > 1) {
+        constexpr int SY = even_up(NB > 1 ? NB - 1 : 1);
         const XPar px = xparents(p.i, nc);
         const Par py = parents(p.j, nc);
         const Par pz = DIM == 3 ? parents(p.k, nc) : Par{0, 0, 1.f, 0.f, 1};
+        T zy[SY];
+        interp_block<DIM, T, SY>(Y, nc, px, py, pz, zy);
 #pragma unroll
-        for (int c = 0; c < NB - 1; ++c) z[c] = interp_row<DIM, T>(Y.p[c], nc, px, py, pz);
+        for (int c = 0; c < NB - 1; ++c) z[c] = zy[c];
     }
     z[NB - 1] = cL[idx];
+}
+
+// (A P)_idx for all columns of a node-major block on the finest level.
+template <int DIM, typename T, int S>
+__device__ __forceinline__ void fine_apply_block(const FineOp<T>& op, const T* __restrict__ P, int idx,
+                                                 const Idx<DIM>& p, T (&own)[S], T (&q)[S]) {
+    const int n = op.n, sy = n, sz = n * n;
+    load_node<T, S>(P + (size_t)idx * S, own);
+    T nb[S];
+    if (!op.D) {
+#pragma unroll
+        for (int c = 0; c < S; ++c) q[c] = T(2 * DIM) * own[c];
+        auto sub = [&](int j) {
+            load_node<T, S>(P + (size_t)j * S, nb);
+#pragma unroll
+            for (int c = 0; c < S; ++c) q[c] -= nb[c];
+        };
+        if (p.i > 0) sub(idx - 1);
+        if (p.i < n - 1) sub(idx + 1);
+        if (p.j > 0) sub(idx - sy);
+        if (p.j < n - 1) sub(idx + sy);
+        if (DIM == 3) {
+            if (p.k > 0) sub(idx - sz);
+            if (p.k < n - 1) sub(idx + sz);
+        }
+#pragma unroll
+        for (int c = 0; c < S; ++c) q[c] *= op.s0;
+        return;
+    }
+    const T d = op.D[idx];
+#pragma unroll
+    for (int c = 0; c < S; ++c) q[c] = d * own[c];
+    auto sub = [&](int j, T e) {
+        load_node<T, S>(P + (size_t)j * S, nb);
+#pragma unroll
+        for (int c = 0; c < S; ++c) q[c] -= e * nb[c];
+    };
+    if (p.i > 0) sub(idx - 1, op.ex[idx - 1]);
+    if (p.i < n - 1) sub(idx + 1, op.ex[idx]);
+    if (p.j > 0) sub(idx - sy, op.ey[idx - sy]);
+    if (p.j < n - 1) sub(idx + sy, op.ey[idx]);
+    if (DIM == 3) {
+        if (p.k > 0) sub(idx - sz, op.ez[idx - sz]);
+        if (p.k < n - 1) sub(idx + sz, op.ez[idx]);
+    }
 }
 
 // ---------------------------------------------------------------- kernels
@@ -359,21 +452,26 @@ __global__ void __launch_bounds__(kBlock) k_refresh(const Ctl* __restrict__ ctl,
     block_sum_store<1>(v, part, gridDim.x, lb);
 }
 
-// r -= Q alpha (pointwise, FP64 r), partial ||r||^2.
+// r -= Q alpha (pointwise, FP64 r; Q node-major), partial ||r||^2.
 template <typename T, int NB>
 __global__ void __launch_bounds__(kBlock) k_update_r(const Ctl* __restrict__ ctl, int N, const T* __restrict__ Q,
                                                      const double* __restrict__ alpha, double* __restrict__ r,
                                                      double* __restrict__ part) {
     if (ctl->state != 0) return;
+    constexpr int S = even_up(NB);
     const int lb = xcd_block(gridDim.x);
     double a[NB];
 #pragma unroll
     for (int c = 0; c < NB; ++c) a[c] = alpha[c];
     double v[1] = {0.0};
-    for (int idx = lb * kBlock + threadIdx.x; idx < N; idx += gridDim.x * kBlock) {
+    const int per = ((N + gridDim.x - 1) / gridDim.x + kBlock - 1) / kBlock * kBlock;
+    const int end = min(N, (lb + 1) * per);
+    for (int idx = lb * per + threadIdx.x; idx < end; idx += kBlock) {
+        T q[S];
+        load_node<T, S>(Q + (size_t)idx * S, q);
         double ri = r[idx];
 #pragma unroll
-        for (int c = 0; c < NB; ++c) ri -= double(Q[(size_t)c * N + idx]) * a[c];
+        for (int c = 0; c < NB; ++c) ri -= double(q[c]) * a[c];
         r[idx] = ri;
         v[0] += ri * ri;
     }
@@ -446,48 +544,96 @@ __global__ void __launch_bounds__(kBlock) k_fine_sweep(const Ctl* __restrict__ c
     }
 }
 
-// Full weighting g_c = 2^-d P^T g_f at every coarse node (thread per node).
+// Full weighting g_c = 2^-d P^T g_f at coarse node idx (coarse node J on
+// fine node 2J+1; weights 1, 1/2 per axis, boundary neighbours dropped).
+template <int DIM, typename TI, typename C>
+__device__ __forceinline__ C restrict_at(const TI* __restrict__ gf, int nf, int nc, int idx) {
+    const Idx<DIM> p = decomp<DIM>(idx, nc);
+    // per axis: fine 2J, 2J+1, 2J+2 with weights 1/2, 1, 1/2; a node past the
+    // grid gets weight 0 and a clamped (valid) address, so all loads issue at once
+    const int fx = 2 * p.i, fy = 2 * p.j, fz = 2 * p.k;
+    const C w2x = fx + 2 < nf ? C(0.5) : C(0), w2y = fy + 2 < nf ? C(0.5) : C(0);
+    const int x2 = min(fx + 2, nf - 1), y2 = min(fy + 2, nf - 1);
+    const int ys[3] = {fy, fy + 1, y2};
+    const C wy[3] = {C(0.5), C(1), w2y};
+    C acc = C(0);
+    const int nzs = DIM == 3 ? 3 : 1;
+    const C w2z = DIM == 3 && fz + 2 < nf ? C(0.5) : C(0);
+    const int zs[3] = {fz, fz + 1, min(fz + 2, nf - 1)};
+    const C wz[3] = {C(0.5), C(1), w2z};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (a >= nzs) break;
+        const size_t zb = DIM == 3 ? (size_t)nf * nf * zs[a] : 0;
+        C plane = C(0);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const TI* rowp = gf + zb + (size_t)nf * ys[b];
+            const C row = C(0.5) * C(rowp[fx]) + C(rowp[fx + 1]) + w2x * C(rowp[x2]);
+            plane += wy[b] * row;
+        }
+        acc += (DIM == 3 ? wz[a] : C(1)) * plane;
+    }
+    return (DIM == 3 ? C(0.125) : C(0.25)) * acc;
+}
+
+// Restriction to one coarse level (thread per coarse node).  Also writes the
+// first Jacobi sweep c1 = omega (g / D) of that level (read by the smoother).
 template <int DIM, typename TI, typename TO>
 __global__ void __launch_bounds__(kBlock) k_restrict(const Ctl* __restrict__ ctl, const TI* __restrict__ gf, int nf,
-                                                     TO* __restrict__ gc, int nc, int Nc) {
+                                                     TO* __restrict__ gc, int nc, int Nc, const TO* __restrict__ D,
+                                                     TO* __restrict__ c1, TO omega) {
     if (ctl->state != 0) return;
     const int idx = blockIdx.x * kBlock + threadIdx.x;
     if (idx >= Nc) return;
-    const Idx<DIM> p = decomp<DIM>(idx, nc);
-    using C = TO;
-    C acc = C(0);
-    const int fx = 2 * p.i + 1, fy = 2 * p.j + 1, fz = 2 * p.k + 1;
-    for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz) {
-        const int z = fz + dz;
-        if (DIM == 3 && z >= nf) continue;
-        const C wz = (DIM == 3 && dz != 0) ? C(0.5) : C(1);
-        C plane = C(0);
-        for (int dy = -1; dy <= 1; ++dy) {
-            const int y = fy + dy;
-            if (y >= nf) continue;
-            const C wy = dy ? C(0.5) : C(1);
-            const size_t rowbase = (size_t)nf * (y + (DIM == 3 ? (size_t)nf * z : 0));
-            C row = C(gf[rowbase + fx]);
-            row += C(0.5) * C(gf[rowbase + fx - 1]);
-            if (fx + 1 < nf) row += C(0.5) * C(gf[rowbase + fx + 1]);
-            plane += wy * row;
+    const TO g = restrict_at<DIM, TI, TO>(gf, nf, nc, idx);
+    gc[idx] = g;
+    c1[idx] = omega * (g / D[idx]);
+}
+
+// The small coarse levels of the restriction chain in one block, one level
+// after the other.
+template <typename T>
+struct RestrictChain {
+    int count;
+    int nf[kMaxLevels], nc[kMaxLevels], Nc[kMaxLevels];
+    const T* gf[kMaxLevels];
+    T* gc[kMaxLevels];
+    const T* D[kMaxLevels];
+    T* c1[kMaxLevels];
+};
+
+constexpr int kTailBlock = 1024;
+
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kTailBlock) k_restrict_tail(const Ctl* __restrict__ ctl, RestrictChain<T> ch,
+                                                              T omega) {
+    if (ctl->state != 0) return;
+    for (int m = 0; m < ch.count; ++m) {
+        for (int idx = threadIdx.x; idx < ch.Nc[m]; idx += kTailBlock) {
+            const T g = restrict_at<DIM, T, T>(ch.gf[m], ch.nf[m], ch.nc[m], idx);
+            ch.gc[m][idx] = g;
+            ch.c1[m][idx] = omega * (g / ch.D[m][idx]);
         }
-        acc += wz * plane;
+        __syncthreads();
     }
-    gc[idx] = (DIM == 3 ? C(0.125) : C(0.25)) * acc;
 }
 
 // Level-fused damped Jacobi on all coarse levels in one launch: blocks
 // [blk_off[l], blk_off[l+1]) smooth level l.  mode 0: first min(nu,2) sweeps
 // from g (c1 formed on the fly); mode 1: one further sweep cin -> cout.
+// The output of level l goes to cout[l][idx * cstride[l]] (the last column
+// of the node-major block carry after the final sweep).
 template <typename T>
 struct CoarseLevels {
     int nlev;
     int blk_off[kMaxLevels + 1];
     int n[kMaxLevels];
     int N[kMaxLevels];
+    int cstride[kMaxLevels];
     const T* coef[kMaxLevels];
     const T* g[kMaxLevels];
+    const T* c1[kMaxLevels];   // first sweep omega (g / D), written by the restriction
     const T* cin[kMaxLevels];
     T* cout[kMaxLevels];
 };
@@ -506,39 +652,85 @@ __global__ void __launch_bounds__(kBlock) k_coarse_smooth(const Ctl* __restrict_
     const T* __restrict__ D = op.coef + (size_t)stencil_center<DIM>() * N;
     const Idx<DIM> p = decomp<DIM>(idx, op.n);
     const T gi = g[idx], Di = D[idx];
+    T out;
     if (mode == 0) {
-        const T c1 = omega * (gi / Di);
+        const T* __restrict__ c1 = L.c1[l];
         if (!two_sweeps) {
-            L.cout[l][idx] = c1;
-            return;
+            out = c1[idx];
+        } else {
+            const T Ac = coarse_apply_fn<DIM, T>(op, idx, p, [&](int j) -> T { return c1[j]; });
+            out = c1[idx] + omega * ((gi - Ac) / Di);
         }
-        const T Ac = coarse_apply_fn<DIM, T>(op, idx, p, [&](int j) -> T { return omega * (g[j] / D[j]); });
-        L.cout[l][idx] = c1 + omega * ((gi - Ac) / Di);
     } else {
         const T* __restrict__ cin = L.cin[l];
         const T Ac = coarse_apply_fn<DIM, T>(op, idx, p, [&](int j) -> T { return cin[j]; });
-        L.cout[l][idx] = cin[idx] + omega * ((gi - Ac) / Di);
+        out = cin[idx] + omega * ((gi - Ac) / Di);
     }
+    L.cout[l][(size_t)idx * L.cstride[l]] = out;
 }
 
-// Prolongate ncols coarse columns to the next finer level (thread per fine node).
+// Block carry up one level: Y_{l+1}[:, 0..NC-1] = P Y_l[:, 0..NC-1], both
+// node-major (strides even_up(NC) and even_up(NC+1)).
+template <int DIM, typename T, int NC>
+__device__ __forceinline__ void prolong_at(const T* __restrict__ Yc, int nc, T* __restrict__ Yf, int nf, int idx) {
+    constexpr int SC = even_up(NC), SF = even_up(NC + 1);
+    const Idx<DIM> p = decomp<DIM>(idx, nf);
+    const XPar px = xparents(p.i, nc);
+    const Par py = parents(p.j, nc);
+    const Par pz = DIM == 3 ? parents(p.k, nc) : Par{0, 0, 1.f, 0.f, 1};
+    T z[SC];
+    interp_block<DIM, T, SC>(Yc, nc, px, py, pz, z);
+    T* o = Yf + (size_t)idx * SF;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) o[c] = z[c];
+}
 
-template <int DIM, typename T>
-__global__ void __launch_bounds__(kBlock) k_prolong(const Ctl* __restrict__ ctl, ColPtrs<T> in, int ncols, int nc,
-                                                    T* __restrict__ out, int nf, int Nf) {
+template <int DIM, typename T, int NC>
+__global__ void __launch_bounds__(kBlock) k_prolong(const Ctl* __restrict__ ctl, const T* __restrict__ Yc, int nc,
+                                                    T* __restrict__ Yf, int nf, int Nf) {
     if (ctl->state != 0) return;
     const int idx = blockIdx.x * kBlock + threadIdx.x;
     if (idx >= Nf) return;
-    const Idx<DIM> p = decomp<DIM>(idx, nf);
-    for (int c = 0; c < ncols; ++c) out[(size_t)c * Nf + idx] = interp_at<DIM, T>(in.p[c], nc, p);
+    prolong_at<DIM, T, NC>(Yc, nc, Yf, nf, idx);
+}
+
+// The small levels of the prolongation chain (levels l0 .. l0+count-1 to the
+// next finer one) in one block, one level after the other.
+template <typename T>
+struct ProlongChain {
+    int count, l0;
+    int nc[kMaxLevels], nf[kMaxLevels], Nf[kMaxLevels];
+    const T* Yc[kMaxLevels];
+    T* Yf[kMaxLevels];
+};
+
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kTailBlock) k_prolong_head(const Ctl* __restrict__ ctl, ProlongChain<T> ch) {
+    if (ctl->state != 0) return;
+    for (int m = 0; m < ch.count; ++m) {
+        const int NC = ch.l0 + m + 1;
+        for (int idx = threadIdx.x; idx < ch.Nf[m]; idx += kTailBlock) {
+            switch (NC) {
+                case 1: prolong_at<DIM, T, 1>(ch.Yc[m], ch.nc[m], ch.Yf[m], ch.nf[m], idx); break;
+                case 2: prolong_at<DIM, T, 2>(ch.Yc[m], ch.nc[m], ch.Yf[m], ch.nf[m], idx); break;
+                case 3: prolong_at<DIM, T, 3>(ch.Yc[m], ch.nc[m], ch.Yf[m], ch.nf[m], idx); break;
+                case 4: prolong_at<DIM, T, 4>(ch.Yc[m], ch.nc[m], ch.Yf[m], ch.nf[m], idx); break;
+                case 5: prolong_at<DIM, T, 5>(ch.Yc[m], ch.nc[m], ch.Yf[m], ch.nf[m], idx); break;
+                case 6: prolong_at<DIM, T, 6>(ch.Yc[m], ch.nc[m], ch.Yf[m], ch.nf[m], idx); break;
+                default: prolong_at<DIM, T, 7>(ch.Yc[m], ch.nc[m], ch.Yf[m], ch.nf[m], idx); break;
+            }
+        }
+        __syncthreads();
+    }
 }
 
 // W = Q_k^T Z_{k+1} partial sums (NB x NB, entry a*NB+c = Q column a . z^c).
 template <int DIM, typename T, int NB>
-__global__ void __launch_bounds__(kBlock) k_fine_W(const Ctl* __restrict__ ctl, Rows R, int N, ColPtrs<T> Y,
+__global__ void __launch_bounds__(kBlock) k_fine_W(const Ctl* __restrict__ ctl, Rows R, const T* __restrict__ Y,
                                                    int nc, const T* __restrict__ cL, const T* __restrict__ Q,
                                                    double* __restrict__ part) {
     if (ctl->state != 0) return;
+    constexpr int S = even_up(NB);
     const int lb = xcd_block(gridDim.x);
     double w[NB * NB];
 #pragma unroll
@@ -549,9 +741,11 @@ __global__ void __launch_bounds__(kBlock) k_fine_W(const Ctl* __restrict__ ctl, 
         if (!row_item<DIM>(R, w_, p, idx)) continue;
         T z[NB];
         fine_z<DIM, T, NB>(Y, nc, cL, idx, p, z);
+        T q[S];
+        load_node<T, S>(Q + (size_t)idx * S, q);
 #pragma unroll
         for (int a = 0; a < NB; ++a) {
-            const double qa = double(Q[(size_t)a * N + idx]);
+            const double qa = double(q[a]);
 #pragma unroll
             for (int c = 0; c < NB; ++c) w[a * NB + c] += qa * double(z[c]);
         }
@@ -563,12 +757,13 @@ __global__ void __launch_bounds__(kBlock) k_fine_W(const Ctl* __restrict__ ctl, 
 // P_{k+1} = Z_{k+1} - P_k beta in place (Z recomputed from the coarse block).
 // init = 1: P_0 = Z_0 only.
 template <int DIM, typename T, int NB>
-__global__ void __launch_bounds__(kBlock) k_update_xP(const Ctl* __restrict__ ctl, Rows R, int N, ColPtrs<T> Y,
+__global__ void __launch_bounds__(kBlock) k_update_xP(const Ctl* __restrict__ ctl, Rows R, const T* __restrict__ Y,
                                                       int nc, const T* __restrict__ cL, T* __restrict__ P,
                                                       double* __restrict__ x, const double* __restrict__ alpha,
                                                       const double* __restrict__ beta, int init) {
     const int state = ctl->state;
     if (state == 2 || (init && state != 0)) return;
+    constexpr int S = even_up(NB);
     const int lb = xcd_block(gridDim.x);
     __shared__ double sab[NB + NB * NB];
     if (!init) {
@@ -579,19 +774,18 @@ __global__ void __launch_bounds__(kBlock) k_update_xP(const Ctl* __restrict__ ct
         Idx<DIM> p;
         int idx;
         if (!row_item<DIM>(R, w_, p, idx)) continue;
-        T pk[NB];
+        T pk[S];
         if (!init) {
+            load_node<T, S>(P + (size_t)idx * S, pk);
             double xi = x[idx];
 #pragma unroll
-            for (int c = 0; c < NB; ++c) {
-                pk[c] = P[(size_t)c * N + idx];
-                xi += double(pk[c]) * sab[c];
-            }
+            for (int c = 0; c < NB; ++c) xi += double(pk[c]) * sab[c];
             x[idx] = xi;
             if (state != 0) continue;
         }
         T z[NB];
         fine_z<DIM, T, NB>(Y, nc, cL, idx, p, z);
+        T pn[S];
 #pragma unroll
         for (int c = 0; c < NB; ++c) {
             double v = double(z[c]);
@@ -599,8 +793,11 @@ __global__ void __launch_bounds__(kBlock) k_update_xP(const Ctl* __restrict__ ct
 #pragma unroll
                 for (int a2 = 0; a2 < NB; ++a2) v -= double(pk[a2]) * sab[NB + a2 * NB + c];
             }
-            P[(size_t)c * N + idx] = T(v);
+            pn[c] = T(v);
         }
+#pragma unroll
+        for (int c = NB; c < S; ++c) pn[c] = T(0);
+        store_node<T, S>(P + (size_t)idx * S, pn);
     }
 }
 
@@ -612,8 +809,8 @@ __global__ void __launch_bounds__(kBlock) k_spmm_gram(const Ctl* __restrict__ ct
                                                       const double* __restrict__ r, double* __restrict__ part) {
     if (ctl->state != 0) return;
     constexpr int NG = NB * (NB + 1) / 2;
+    constexpr int S = even_up(NB);
     const int lb = xcd_block(gridDim.x);
-    const int N = op.N;
     double acc[NG + NB];
 #pragma unroll
     for (int q = 0; q < NG + NB; ++q) acc[q] = 0.0;
@@ -621,31 +818,25 @@ __global__ void __launch_bounds__(kBlock) k_spmm_gram(const Ctl* __restrict__ ct
         Idx<DIM> p;
         int idx;
         if (!row_item<DIM>(R, w_, p, idx)) continue;
-        double pv[NB], qv[NB];
-#pragma unroll
-        for (int c = 0; c < NB; ++c) {
-            const T* Pc = P + (size_t)c * N;
-            const T qc = fine_apply<DIM, T>(op, Pc, idx, p);
-            Q[(size_t)c * N + idx] = qc;
-            pv[c] = double(Pc[idx]);
-            qv[c] = double(qc);
-        }
+        T pv[S], qv[S];
+        fine_apply_block<DIM, T, S>(op, P, idx, p, pv, qv);
+        store_node<T, S>(Q + (size_t)idx * S, qv);
         const double ri = r[idx];
         int q = 0;
 #pragma unroll
         for (int a = 0; a < NB; ++a)
 #pragma unroll
-            for (int c = a; c < NB; ++c) acc[q++] += pv[a] * qv[c];
+            for (int c = a; c < NB; ++c) acc[q++] += double(pv[a]) * double(qv[c]);
 #pragma unroll
-        for (int a = 0; a < NB; ++a) acc[NG + a] += pv[a] * ri;
+        for (int a = 0; a < NB; ++a) acc[NG + a] += double(pv[a]) * ri;
     }
     block_sum_store<NG + NB>(acc, part, gridDim.x, lb);
 }
 
-// Explicit Z (widened to double), for the mg_block entry point.
+// Explicit Z (widened to double, column-major), for the mg_block entry point.
 template <int DIM, typename T, int NB>
-__global__ void __launch_bounds__(kBlock) k_write_Z(Rows R, int N, ColPtrs<T> Y, int nc, const T* __restrict__ cL,
-                                                    double* __restrict__ Z) {
+__global__ void __launch_bounds__(kBlock) k_write_Z(Rows R, int N, const T* __restrict__ Y, int nc,
+                                                    const T* __restrict__ cL, double* __restrict__ Z) {
     ROW_LOOP(R, blockIdx.x) {
         Idx<DIM> p;
         int idx;

@@ -296,3 +296,23 @@ def test_pinv_rank_deficient(kind):
     else:
         ya, yb = B @ (Gp @ g), B @ (ref.Gplus @ g)
         assert np.linalg.norm(ya - yb) <= 1e-8 * np.linalg.norm(yb)
+
+
+@pytest.mark.parametrize("nu", [1, 3, 4])
+@pytest.mark.parametrize("case", [(2, 31, 4, None, 1), (3, 15, 3, 3, 16)], ids=case_id)
+def test_smoothing_sweeps(case, nu):
+    """nu damped-Jacobi sweeps on every level (eq. (2)) other than the default 2."""
+    dim, n, nl, ks, seed = case
+    h, s, b = build_pair(*case, nu=nu)
+    Zg = host(s.mg_block(dev(b)))
+    Zo = mpcg.mg_block(h, b, nu=nu)
+    for l in range(nl):
+        assert rel(Zg[l], Zo[:, l]) <= 1e-13, l
+    ref = mpcg.mpcg(h, b, tol=1e-8, nu=nu)
+    x, info = s.solve(dev(b), tol=1e-8)
+    assert abs(info["iterations"] - ref.iterations) <= 1
+    k = min(ref.iterations, info["iterations"])
+    xg, _ = s.solve(dev(b), tol=0.0, maxit=k)
+    o = mpcg.mpcg(h, b, tol=0.0, maxit=k, nu=nu)
+    assert rel(host(xg), o.x) <= 1e-10
+    s.close()
