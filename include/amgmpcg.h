@@ -40,6 +40,7 @@ extern "C" {
 #define AMGMPCG_NONFINITE    -4   /* NaN/Inf in the data or the residual           */
 #define AMGMPCG_OOM          -5   /* device allocation failed                      */
 #define AMGMPCG_HIP_ERROR    -6   /* any other HIP runtime error                   */
+#define AMGMPCG_UNAVAILABLE  -7   /* entry point switched off in this build        */
 
 /* ---- problem description -------------------------------------------- */
 /* Structured diffusion problem -div(kappa grad u) = f on (0,1)^dim (eq. (1)
@@ -132,6 +133,29 @@ int amgmpcg_level_stencil(const amgmpcg_handle* h, int32_t level, double* out);
  * doubles, ||r_k||_2).  Either may be NULL.  *count = iterations stored. */
 int amgmpcg_history(const amgmpcg_handle* h, int32_t cap, double* alpha_out,
                     double* resnorm_out, int32_t* count);
+
+/* Batched solves: count independent Poisson problems (kappa must be NULL,
+ * all of one dim, each with its own n and nlevels <= 6) whose hierarchies
+ * are built here (Sec. 2.1 per problem); grids: HOST array of count entries.
+ * opts as for amgmpcg_setup_grid (nu must be 1 or 2).  The problems are
+ * solved together by one persistent kernel launch captured in a HIP graph:
+ * workgroups take problems largest first from an atomic queue and each runs
+ * Algorithm 1 for its problem to the end.
+ * CURRENTLY SWITCHED OFF: returns AMGMPCG_UNAVAILABLE after validating its
+ * arguments (its first GPU run faulted; the cause is not yet established). */
+int amgmpcg_setup_batched(int32_t count, const amgmpcg_grid* grids, const amgmpcg_options* opts,
+                          void* stream, amgmpcg_handle** out);
+
+/* b_dev, x_dev: DEVICE, the problems' vectors concatenated in the order of
+ * grids (problem i starts at offset sum_{j<i} n_j^dim); x holds every x_0 on
+ * entry and every result on return.  infos: HOST, count entries or NULL.
+ * batch_ms: device time of the launch (HIP events) or NULL.  Returns
+ * AMGMPCG_OK if every problem converged, else the first other status. */
+int amgmpcg_solve_batched(amgmpcg_handle* h, const double* b_dev, double* x_dev, double tol,
+                          int32_t maxit, amgmpcg_info* infos, double* batch_ms);
+
+/* Number of problems and total unknowns of a batched handle. */
+int amgmpcg_batched_size(const amgmpcg_handle* h, int32_t* count, int64_t* total_dofs);
 
 /* Measurement aid: average duration in ms of each hot kernel of one
  * iteration, each launched reps times back to back between two HIP events

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libamgmpcg.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "amgmpcg.h")
 
 OK, MAXIT, BREAKDOWN = 0, 1, 2
-INVALID_ARG, NOT_SPD, DIM_MISMATCH, NONFINITE, OOM, HIP_ERROR = -1, -2, -3, -4, -5, -6
+INVALID_ARG, NOT_SPD, DIM_MISMATCH, NONFINITE, OOM, HIP_ERROR, UNAVAILABLE = -1, -2, -3, -4, -5, -6, -7
 
 
 class Grid(ctypes.Structure):
@@ -78,6 +78,13 @@ def load(path: str = LIB_PATH):
     lib.amgmpcg_history.argtypes = [c_void_p, c_int32, POINTER(c_double), POINTER(c_double), POINTER(c_int32)]
     lib.amgmpcg_time_kernels.argtypes = [c_void_p, c_int32, POINTER(c_double), c_int32, POINTER(c_int32)]
     lib.amgmpcg_time_kernels.restype = c_int32
+    lib.amgmpcg_setup_batched.argtypes = [c_int32, POINTER(Grid), POINTER(Options), c_void_p, POINTER(c_void_p)]
+    lib.amgmpcg_setup_batched.restype = c_int32
+    lib.amgmpcg_solve_batched.argtypes = [c_void_p, c_void_p, c_void_p, c_double, c_int32, POINTER(Info),
+                                          POINTER(c_double)]
+    lib.amgmpcg_solve_batched.restype = c_int32
+    lib.amgmpcg_batched_size.argtypes = [c_void_p, POINTER(c_int32), POINTER(ctypes.c_int64)]
+    lib.amgmpcg_batched_size.restype = c_int32
     lib.amgmpcg_gram_pinv.argtypes = [POINTER(c_double), c_int32, c_double, POINTER(c_double), POINTER(c_int32)]
     lib.amgmpcg_gram_pinv.restype = c_int32
     lib.amgmpcg_destroy.argtypes = [c_void_p]
@@ -237,3 +244,57 @@ class Solver:
                                          r.ctypes.data_as(POINTER(c_double)), byref(cnt)))
         k = cnt.value
         return a[: k * self.nb].reshape(k, self.nb), r[: k + 1]
+
+
+class BatchedSolver:
+    """Many independent Poisson problems solved by one persistent launch.
+
+    problems: sequence of (dim, n, nlevels).  Vectors are concatenated in
+    problem order (problem i starts at sum_{j<i} n_j^dim).
+    """
+
+    def __init__(self, problems, stream=None, **options):
+        lib = load()
+        self._lib = lib
+        self.problems = [tuple(int(v) for v in p) for p in problems]
+        arr = (Grid * len(self.problems))()
+        for i, (d, n, nl) in enumerate(self.problems):
+            arr[i] = Grid(d, n, nl, None)
+        self.sizes = [n ** d for d, n, _ in self.problems]
+        self.offsets = np.concatenate([[0], np.cumsum(self.sizes)]).astype(np.int64)
+        self.N = int(self.offsets[-1])
+        self.options = default_options(**options)
+        self.stream = _current_stream() if stream is None else stream
+        h = c_void_p()
+        _check(lib.amgmpcg_setup_batched(len(self.problems), arr, byref(self.options), self.stream, byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.amgmpcg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, b, x=None, tol: float = 1e-8, maxit: int = 0):
+        """b, x: contiguous float64 device tensors of all problems concatenated.
+
+        Returns (x, list of per-problem info dicts, device ms of the launch).
+        """
+        import torch
+        if b.dtype != torch.float64 or not b.is_cuda or not b.is_contiguous() or b.numel() != self.N:
+            raise ValueError("b must be a contiguous float64 device tensor of all problems")
+        if x is None:
+            x = torch.zeros_like(b)
+        if x.dtype != torch.float64 or not x.is_cuda or not x.is_contiguous() or x.numel() != self.N:
+            raise ValueError("x must match b")
+        infos = (Info * len(self.problems))()
+        ms = c_double()
+        code = self._lib.amgmpcg_solve_batched(self._h, c_void_p(b.data_ptr()), c_void_p(x.data_ptr()),
+                                               float(tol), int(maxit), infos, byref(ms))
+        _check(code, (OK, MAXIT, BREAKDOWN, NONFINITE))
+        return x, [i.as_dict() for i in infos], ms.value

@@ -20,6 +20,7 @@
 #include "grid_kernels.hpp"
 #include "setup.hpp"
 #include "small_kernels.hpp"
+#include "batched.hpp"
 
 namespace amg {
 
@@ -651,10 +652,219 @@ class Solver : public SolverBase {
     hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
 };
 
+
+// ------------------------------------------------------------------ batched
+
+class BatchedBase {
+   public:
+    virtual ~BatchedBase() = default;
+    virtual int solve(const double* b_dev, double* x_dev, double tol, int maxit, amgmpcg_info* infos,
+                      double* batch_ms) = 0;
+    int count = 0;
+    int64_t total = 0;
+};
+
+template <typename T, int DIM>
+class BatchedSolver : public BatchedBase {
+   public:
+    BatchedSolver(int cnt, const amgmpcg_grid* grids, const amgmpcg_options& o, hipStream_t stream)
+        : opt_(o), stream_(stream) {
+        count = cnt;
+        mixed_ = std::is_same<T, float>::value;
+        hinst_.resize(cnt);
+        offs_.resize(cnt + 1);
+        offs_[0] = 0;
+        // sizes of every arena
+        size_t nx = 0, nP = 0, ncoef = 0, nvec = 0, nY = 0;
+        std::vector<std::vector<int>> sizes(cnt);
+        for (int i = 0; i < cnt; ++i) {
+            const int nl = grids[i].nlevels;
+            sizes[i].resize(nl);
+            sizes[i][nl - 1] = grids[i].n;
+            for (int l = nl - 2; l >= 0; --l) sizes[i][l] = sizes[i][l + 1] / 2;
+            const size_t N = (size_t)host::ipow(grids[i].n, DIM);
+            offs_[i + 1] = offs_[i] + N;
+            nx += N;
+            nP += (size_t)even_up(nl) * N;
+            for (int l = 0; l + 1 < nl; ++l) {
+                const size_t Nl = (size_t)host::ipow(sizes[i][l], DIM);
+                ncoef += (size_t)(DIM == 2 ? 9 : 27) * Nl;
+                nvec += Nl;
+                nY += (size_t)even_up(l + 1) * Nl;
+            }
+        }
+        total = (int64_t)nx;
+        r_.alloc(nx);
+        P_.alloc(nP);
+        Q_.alloc(nP);
+        cL_.alloc(nx);
+        coef_.alloc(std::max<size_t>(ncoef, 1));
+        g_.alloc(std::max<size_t>(nvec, 1));
+        c1_.alloc(std::max<size_t>(nvec, 1));
+        Y_.alloc(std::max<size_t>(nY, 1));
+        HIPCHK(hipMemset(P_.p, 0, P_.n * sizeof(T)));
+        HIPCHK(hipMemset(Y_.p, 0, Y_.n * sizeof(T)));
+        // per-instance hierarchy (host Galerkin) and device pointers
+        size_t oP = 0, oc = 0, ov = 0, oY = 0;
+        std::vector<T> coef_host(ncoef);
+        for (int i = 0; i < cnt; ++i) {
+            const int nl = grids[i].nlevels, n = grids[i].n;
+            BInst<T>& I = hinst_[i];
+            std::memset(&I, 0, sizeof(I));
+            I.nlev = nl;
+            for (int l = 0; l < nl; ++l) {
+                I.n[l] = sizes[i][l];
+                I.N[l] = (int)host::ipow(sizes[i][l], DIM);
+            }
+            const size_t N = offs_[i + 1] - offs_[i];
+            I.r = r_.p + offs_[i];
+            I.cL = cL_.p + offs_[i];
+            I.P = P_.p + oP;
+            I.Q = Q_.p + oP;
+            oP += (size_t)even_up(nl) * N;
+            if (nl > 1) {
+                host::FineFaces faces = host::fine_faces(DIM, n, nullptr);
+                std::vector<host::StencilLevel> lev(nl);
+                lev[nl - 1] = host::faces_to_stencil(DIM, n, faces);
+                for (int l = nl - 2; l >= 0; --l) {
+                    lev[l] = host::galerkin(lev[l + 1]);
+                    const int ctr = lev[l].center();
+                    for (int64_t q = 0; q < lev[l].N; ++q)
+                        if (!(lev[l].coef[(size_t)ctr * lev[l].N + q] > 0.0))
+                            throw ApiError(AMGMPCG_NOT_SPD, "non-positive diagonal on a coarse level");
+                }
+                for (int l = 0; l + 1 < nl; ++l) {
+                    const size_t Nl = (size_t)I.N[l];
+                    const size_t cnt_c = (size_t)(DIM == 2 ? 9 : 27) * Nl;
+                    for (size_t q = 0; q < cnt_c; ++q) coef_host[oc + q] = T(lev[l].coef[q]);
+                    I.coef[l] = coef_.p + oc;
+                    oc += cnt_c;
+                    I.g[l] = g_.p + ov;
+                    I.c1[l] = c1_.p + ov;
+                    ov += Nl;
+                    I.Y[l] = Y_.p + oY;
+                    oY += (size_t)even_up(l + 1) * Nl;
+                }
+            }
+        }
+        if (ncoef) HIPCHK(hipMemcpy(coef_.p, coef_host.data(), ncoef * sizeof(T), hipMemcpyHostToDevice));
+        // largest first
+        std::vector<int> order(cnt);
+        for (int i = 0; i < cnt; ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            return offs_[a + 1] - offs_[a] > offs_[b + 1] - offs_[b];
+        });
+        order_.alloc(cnt);
+        HIPCHK(hipMemcpy(order_.p, order.data(), cnt * sizeof(int), hipMemcpyHostToDevice));
+        queue_.alloc(1);
+        out_.alloc(cnt);
+        inst_.alloc(cnt);
+        params_.alloc(1);
+        HIPCHK(hipHostMalloc((void**)&hparams_, sizeof(BatchParams), hipHostMallocDefault));
+        HIPCHK(hipEventCreate(&ev0_));
+        HIPCHK(hipEventCreate(&ev1_));
+        int dev = 0, ncu = 0;
+        HIPCHK(hipGetDevice(&dev));
+        HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+        grid_ = std::min(cnt, std::max(1, 2 * ncu));
+        tau_ = opt_.pinv_tau > 0 ? opt_.pinv_tau : 0.0;
+    }
+
+    ~BatchedSolver() override {
+        if (exec_) (void)hipGraphExecDestroy(exec_);
+        if (graph_) (void)hipGraphDestroy(graph_);
+        if (cap_stream_) (void)hipStreamDestroy(cap_stream_);
+        if (hparams_) (void)hipHostFree(hparams_);
+        if (ev0_) (void)hipEventDestroy(ev0_);
+        if (ev1_) (void)hipEventDestroy(ev1_);
+    }
+
+    int solve(const double* b_dev, double* x_dev, double tol, int maxit, amgmpcg_info* infos,
+              double* batch_ms) override {
+        if (maxit <= 0) maxit = opt_.maxit;
+        // the caller's concatenated b and x
+        for (int i = 0; i < count; ++i) {
+            hinst_[i].b = b_dev + offs_[i];
+            hinst_[i].x = x_dev + offs_[i];
+        }
+        BatchParams& bp = *hparams_;
+        bp.count = count;
+        bp.order = order_.p;
+        bp.queue = queue_.p;
+        bp.tol = tol;
+        bp.maxit = maxit;
+        bp.two_sweeps = opt_.nu >= 2 ? 1 : 0;
+        bp.omega = opt_.omega;
+        bp.drop2 = opt_.refresh_drop * opt_.refresh_drop;
+        bp.mixed = mixed_ ? 1 : 0;
+        bp.out = out_.p;
+        bp.tau = tau_;
+        bp.unit = mixed_ ? std::ldexp(1.0, -24) : std::ldexp(1.0, -53);
+        HIPCHK(hipMemcpyAsync(inst_.p, hinst_.data(), count * sizeof(BInst<T>), hipMemcpyHostToDevice, stream_));
+        HIPCHK(hipMemcpyAsync(params_.p, hparams_, sizeof(BatchParams), hipMemcpyHostToDevice, stream_));
+        if (!exec_) capture();
+        HIPCHK(hipEventRecord(ev0_, stream_));
+        HIPCHK(hipGraphLaunch(exec_, stream_));
+        HIPCHK(hipEventRecord(ev1_, stream_));
+        std::vector<BOut> hout(count);
+        HIPCHK(hipMemcpyAsync(hout.data(), out_.p, count * sizeof(BOut), hipMemcpyDeviceToHost, stream_));
+        HIPCHK(hipStreamSynchronize(stream_));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, ev0_, ev1_));
+        if (batch_ms) *batch_ms = ms;
+        int worst = AMGMPCG_OK;
+        for (int i = 0; i < count; ++i) {
+            if (infos) {
+                infos[i].status = hout[i].status;
+                infos[i].iterations = hout[i].iterations;
+                infos[i].bnorm = hout[i].bnorm;
+                infos[i].relres = hout[i].relres;
+                infos[i].refreshes = hout[i].refreshes;
+                infos[i].nb = hinst_[i].nlev;
+                infos[i].solve_ms = ms;
+            }
+            if (hout[i].status != AMGMPCG_OK && worst == AMGMPCG_OK) worst = hout[i].status;
+        }
+        return worst;
+    }
+
+   private:
+    void capture() {
+        HIPCHK(hipStreamCreateWithFlags(&cap_stream_, hipStreamNonBlocking));
+        HIPCHK(hipStreamBeginCapture(cap_stream_, hipStreamCaptureModeThreadLocal));
+        k_queue_reset<<<1, 64, 0, cap_stream_>>>(queue_.p);
+        k_batched<DIM, T><<<grid_, kBatchBlock, 0, cap_stream_>>>(inst_.p, params_.p);
+        hipError_t launch_err = hipGetLastError();
+        HIPCHK(hipStreamEndCapture(cap_stream_, &graph_));
+        HIPCHK(launch_err);
+        HIPCHK(hipGraphInstantiate(&exec_, graph_, nullptr, nullptr, 0));
+    }
+
+    amgmpcg_options opt_;
+    hipStream_t stream_;
+    hipStream_t cap_stream_ = nullptr;
+    hipGraph_t graph_ = nullptr;
+    hipGraphExec_t exec_ = nullptr;
+    bool mixed_ = false;
+    int grid_ = 1;
+    double tau_ = 0.0;
+    std::vector<size_t> offs_;
+    std::vector<BInst<T>> hinst_;
+    DevBuf<double> r_;
+    DevBuf<T> P_, Q_, cL_, coef_, g_, c1_, Y_;
+    DevBuf<int> order_, queue_;
+    DevBuf<BOut> out_;
+    DevBuf<BInst<T>> inst_;
+    DevBuf<BatchParams> params_;
+    BatchParams* hparams_ = nullptr;
+    hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
+};
+
 }  // namespace amg
 
 struct amgmpcg_handle {
     std::unique_ptr<amg::SolverBase> s;
+    std::unique_ptr<amg::BatchedBase> bs;
 };
 
 using amg::ApiError;
@@ -842,6 +1052,59 @@ int amgmpcg_time_kernels(amgmpcg_handle* h, int32_t reps, double* ms_out, int32_
     });
 }
 
+int amgmpcg_setup_batched(int32_t count, const amgmpcg_grid* grids, const amgmpcg_options* opts, void* stream,
+                          amgmpcg_handle** out) {
+    return guarded([&]() -> int {
+        if (!out) throw ApiError(AMGMPCG_INVALID_ARG, "out pointer is NULL");
+        *out = nullptr;
+        if (count < 1 || !grids) throw ApiError(AMGMPCG_INVALID_ARG, "need count >= 1 problems");
+        validate_options(opts);
+        if (opts->nu > 2) throw ApiError(AMGMPCG_INVALID_ARG, "batched solves support nu = 1 or 2");
+        const int dim = grids[0].dim;
+        for (int i = 0; i < count; ++i) {
+            validate_grid(&grids[i]);
+            if (grids[i].dim != dim) throw ApiError(AMGMPCG_INVALID_ARG, "all batched problems need the same dim");
+            if (grids[i].kappa) throw ApiError(AMGMPCG_INVALID_ARG, "batched problems are Poisson (kappa must be NULL)");
+            if (grids[i].nlevels > 6) throw ApiError(AMGMPCG_INVALID_ARG, "batched problems support up to 6 levels");
+        }
+        // The persistent batched kernel took a GPU memory fault in its first
+        // run whose cause is not established (a host emulation of the kernel
+        // under AddressSanitizer finds no out-of-range access); the entry
+        // point stays switched off until the cause is shown.
+        throw ApiError(AMGMPCG_UNAVAILABLE, "the batched persistent solve is switched off in this build");
+        auto h = std::make_unique<amgmpcg_handle>();
+        hipStream_t s = (hipStream_t)stream;
+        if (opts->precision == 0) {
+            if (dim == 2) h->bs.reset(new amg::BatchedSolver<double, 2>(count, grids, *opts, s));
+            else h->bs.reset(new amg::BatchedSolver<double, 3>(count, grids, *opts, s));
+        } else {
+            if (dim == 2) h->bs.reset(new amg::BatchedSolver<float, 2>(count, grids, *opts, s));
+            else h->bs.reset(new amg::BatchedSolver<float, 3>(count, grids, *opts, s));
+        }
+        *out = h.release();
+        return AMGMPCG_OK;
+    });
+}
+
+int amgmpcg_solve_batched(amgmpcg_handle* h, const double* b_dev, double* x_dev, double tol, int32_t maxit,
+                          amgmpcg_info* infos, double* batch_ms) {
+    return guarded([&]() -> int {
+        if (!h || !h->bs) throw ApiError(AMGMPCG_INVALID_ARG, "handle is not a batched handle");
+        if (!b_dev || !x_dev) throw ApiError(AMGMPCG_INVALID_ARG, "b or x is NULL");
+        if (!(tol >= 0.0) || !std::isfinite(tol)) throw ApiError(AMGMPCG_INVALID_ARG, "tol must be finite and >= 0");
+        return h->bs->solve(b_dev, x_dev, tol, maxit, infos, batch_ms);
+    });
+}
+
+int amgmpcg_batched_size(const amgmpcg_handle* h, int32_t* count, int64_t* total_dofs) {
+    return guarded([&]() -> int {
+        if (!h || !h->bs) throw ApiError(AMGMPCG_INVALID_ARG, "handle is not a batched handle");
+        if (count) *count = h->bs->count;
+        if (total_dofs) *total_dofs = h->bs->total;
+        return AMGMPCG_OK;
+    });
+}
+
 int amgmpcg_gram_pinv(const double* G, int32_t nb, double tau, double* Gplus, int32_t* rank) {
     return guarded([&]() -> int {
         if (!G || !Gplus || !rank) throw ApiError(AMGMPCG_INVALID_ARG, "NULL argument");
@@ -884,6 +1147,7 @@ const char* amgmpcg_status_string(int s) {
         case AMGMPCG_NONFINITE: return "non-finite value";
         case AMGMPCG_OOM: return "out of memory";
         case AMGMPCG_HIP_ERROR: return "HIP runtime error";
+        case AMGMPCG_UNAVAILABLE: return "entry point switched off in this build";
         default: return "unknown status";
     }
 }

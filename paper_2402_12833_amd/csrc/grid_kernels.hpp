@@ -478,53 +478,56 @@ __global__ void __launch_bounds__(kBlock) k_update_r(const Ctl* __restrict__ ctl
     block_sum_store<1>(v, part, gridDim.x, lb);
 }
 
-// Fine-level damped Jacobi, first min(nu, 2) sweeps from c0 = 0:
+// Fine-level damped Jacobi at one node, first min(nu, 2) sweeps from c0 = 0:
 //   c1 = omega (g / D);  c2 = c1 + omega ((g - A c1) / D)   (eq. (2)).
+template <int DIM, typename T, typename G>
+__device__ __forceinline__ T fine_smooth_at(const FineOp<T>& op, const G* __restrict__ g, int idx, const Idx<DIM>& p,
+                                            T omega, int two_sweeps) {
+    const int n = op.n, sy = n, sz = n * n;
+    const T gi = T(g[idx]);
+    const T Di = fine_diag<DIM>(op, idx);
+    const T c1 = omega * (gi / Di);
+    if (!two_sweeps) return c1;
+    // A c1 with c1_j = omega (g_j / D_j) formed on the fly
+    auto c1at = [&](int j) -> T { return omega * (T(g[j]) / fine_diag<DIM>(op, j)); };
+    T Ac;
+    if (!op.D) {
+        T acc = T(2 * DIM) * c1;
+        if (p.i > 0) acc -= c1at(idx - 1);
+        if (p.i < n - 1) acc -= c1at(idx + 1);
+        if (p.j > 0) acc -= c1at(idx - sy);
+        if (p.j < n - 1) acc -= c1at(idx + sy);
+        if (DIM == 3) {
+            if (p.k > 0) acc -= c1at(idx - sz);
+            if (p.k < n - 1) acc -= c1at(idx + sz);
+        }
+        Ac = op.s0 * acc;
+    } else {
+        T acc = Di * c1;
+        if (p.i > 0) acc -= op.ex[idx - 1] * c1at(idx - 1);
+        if (p.i < n - 1) acc -= op.ex[idx] * c1at(idx + 1);
+        if (p.j > 0) acc -= op.ey[idx - sy] * c1at(idx - sy);
+        if (p.j < n - 1) acc -= op.ey[idx] * c1at(idx + sy);
+        if (DIM == 3) {
+            if (p.k > 0) acc -= op.ez[idx - sz] * c1at(idx - sz);
+            if (p.k < n - 1) acc -= op.ez[idx] * c1at(idx + sz);
+        }
+        Ac = acc;
+    }
+    return c1 + omega * ((gi - Ac) / Di);
+}
+
 template <int DIM, typename T, typename G>
 __global__ void __launch_bounds__(kBlock) k_fine_smooth(const Ctl* __restrict__ ctl, Rows R, FineOp<T> op,
                                                         const G* __restrict__ g, T* __restrict__ c, T omega,
                                                         int two_sweeps) {
     if (ctl->state != 0) return;
     const int lb = xcd_block(gridDim.x);
-    const int n = op.n, sy = n, sz = n * n;
     ROW_LOOP(R, lb) {
         Idx<DIM> p;
         int idx;
         if (!row_item<DIM>(R, w_, p, idx)) continue;
-        const T gi = T(g[idx]);
-        const T Di = fine_diag<DIM>(op, idx);
-        const T c1 = omega * (gi / Di);
-        if (!two_sweeps) {
-            c[idx] = c1;
-            continue;
-        }
-        // A c1 with c1_j = omega (g_j / D_j) formed on the fly
-        auto c1at = [&](int j) -> T { return omega * (T(g[j]) / fine_diag<DIM>(op, j)); };
-        T Ac;
-        if (!op.D) {
-            T acc = T(2 * DIM) * c1;
-            if (p.i > 0) acc -= c1at(idx - 1);
-            if (p.i < n - 1) acc -= c1at(idx + 1);
-            if (p.j > 0) acc -= c1at(idx - sy);
-            if (p.j < n - 1) acc -= c1at(idx + sy);
-            if (DIM == 3) {
-                if (p.k > 0) acc -= c1at(idx - sz);
-                if (p.k < n - 1) acc -= c1at(idx + sz);
-            }
-            Ac = op.s0 * acc;
-        } else {
-            T acc = Di * c1;
-            if (p.i > 0) acc -= op.ex[idx - 1] * c1at(idx - 1);
-            if (p.i < n - 1) acc -= op.ex[idx] * c1at(idx + 1);
-            if (p.j > 0) acc -= op.ey[idx - sy] * c1at(idx - sy);
-            if (p.j < n - 1) acc -= op.ey[idx] * c1at(idx + sy);
-            if (DIM == 3) {
-                if (p.k > 0) acc -= op.ez[idx - sz] * c1at(idx - sz);
-                if (p.k < n - 1) acc -= op.ez[idx] * c1at(idx + sz);
-            }
-            Ac = acc;
-        }
-        c[idx] = c1 + omega * ((gi - Ac) / Di);
+        c[idx] = fine_smooth_at<DIM, T, G>(op, g, idx, p, omega, two_sweeps);
     }
 }
 
@@ -638,6 +641,24 @@ struct CoarseLevels {
     T* cout[kMaxLevels];
 };
 
+// Damped Jacobi at one coarse node: first min(nu,2) sweeps (mode 0, c1 =
+// omega g / D precomputed by the restriction) or one further sweep (mode 1).
+template <int DIM, typename T>
+__device__ __forceinline__ T coarse_smooth_at(const CoarseOp<T>& op, const T* __restrict__ g,
+                                              const T* __restrict__ c1, const T* __restrict__ cin, int idx,
+                                              T omega, int mode, int two_sweeps) {
+    const T* __restrict__ D = op.coef + (size_t)stencil_center<DIM>() * op.N;
+    const Idx<DIM> p = decomp<DIM>(idx, op.n);
+    const T gi = g[idx], Di = D[idx];
+    if (mode == 0) {
+        if (!two_sweeps) return c1[idx];
+        const T Ac = coarse_apply_fn<DIM, T>(op, idx, p, [&](int j) -> T { return c1[j]; });
+        return c1[idx] + omega * ((gi - Ac) / Di);
+    }
+    const T Ac = coarse_apply_fn<DIM, T>(op, idx, p, [&](int j) -> T { return cin[j]; });
+    return cin[idx] + omega * ((gi - Ac) / Di);
+}
+
 template <int DIM, typename T>
 __global__ void __launch_bounds__(kBlock) k_coarse_smooth(const Ctl* __restrict__ ctl, CoarseLevels<T> L,
                                                           T omega, int mode, int two_sweeps) {
@@ -648,25 +669,8 @@ __global__ void __launch_bounds__(kBlock) k_coarse_smooth(const Ctl* __restrict_
     const int N = L.N[l];
     if (idx >= N) return;
     CoarseOp<T> op{L.n[l], N, L.coef[l]};
-    const T* __restrict__ g = L.g[l];
-    const T* __restrict__ D = op.coef + (size_t)stencil_center<DIM>() * N;
-    const Idx<DIM> p = decomp<DIM>(idx, op.n);
-    const T gi = g[idx], Di = D[idx];
-    T out;
-    if (mode == 0) {
-        const T* __restrict__ c1 = L.c1[l];
-        if (!two_sweeps) {
-            out = c1[idx];
-        } else {
-            const T Ac = coarse_apply_fn<DIM, T>(op, idx, p, [&](int j) -> T { return c1[j]; });
-            out = c1[idx] + omega * ((gi - Ac) / Di);
-        }
-    } else {
-        const T* __restrict__ cin = L.cin[l];
-        const T Ac = coarse_apply_fn<DIM, T>(op, idx, p, [&](int j) -> T { return cin[j]; });
-        out = cin[idx] + omega * ((gi - Ac) / Di);
-    }
-    L.cout[l][(size_t)idx * L.cstride[l]] = out;
+    L.cout[l][(size_t)idx * L.cstride[l]] =
+        coarse_smooth_at<DIM, T>(op, L.g[l], L.c1[l], L.cin[l], idx, omega, mode, two_sweeps);
 }
 
 // Block carry up one level: Y_{l+1}[:, 0..NC-1] = P Y_l[:, 0..NC-1], both

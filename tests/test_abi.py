@@ -84,6 +84,17 @@ def test_null_arguments(lib):
 
 
 def test_status_strings(lib):
-    for c in (0, 1, 2, -1, -2, -3, -4, -5, -6):
+    for c in (0, 1, 2, -1, -2, -3, -4, -5, -6, -7):
         assert B.status_string(c) and B.status_string(c) != "unknown status"
     assert B.status_string(99) == "unknown status"
+
+
+def test_batched_switched_off(lib):
+    grids = (B.Grid * 2)(B.Grid(2, 31, 3, None), B.Grid(2, 15, 2, None))
+    h = ctypes.c_void_p()
+    code = lib.amgmpcg_setup_batched(2, grids, ctypes.byref(amg.default_options()), None, ctypes.byref(h))
+    assert code == B.UNAVAILABLE and not h.value
+    # argument validation still runs first
+    kap = np.ones(33 * 33)
+    bad = (B.Grid * 1)(B.Grid(2, 31, 3, kap.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    assert lib.amgmpcg_setup_batched(1, bad, ctypes.byref(amg.default_options()), None, ctypes.byref(h)) == B.INVALID_ARG

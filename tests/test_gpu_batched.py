@@ -1,0 +1,120 @@
+"""GPU parity of the batched persistent launch against the FP64 oracle.
+
+Each problem of the batch must match the oracle run on that problem alone:
+iterates at equal k to 1e-10 relative (FP64), converged iteration counts
+within one; in the mixed form every problem reaches a true FP64 relative
+residual <= 1e-8.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import hierarchy, mpcg, operators as ops
+
+torch = pytest.importorskip("torch")
+pytestmark = [
+    pytest.mark.gpu,
+    pytest.mark.skip(reason="batched persistent kernel switched off: its first GPU run took a memory fault "
+                            "whose cause is not established (a host emulation under AddressSanitizer finds "
+                            "no out-of-range access); amgmpcg_setup_batched returns AMGMPCG_UNAVAILABLE"),
+]
+
+import paper_2402_12833_amd as amg  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    amg.load()
+
+
+def small_batch():
+    # ragged sides (odd and even), every depth the batched rule gives
+    sides = [31, 7, 45, 64, 100, 33, 15, 63, 2, 20, 127, 50]
+    probs = []
+    for i, n in enumerate(sides):
+        nl = W.batched_levels(n) if n >= 31 else max(1, min(3, int(np.log2(n + 1)) - 1))
+        probs.append((2, n, nl, 500 + i))
+    probs.append((2, 31, 1, 600))    # single level (plain PCG with Jacobi)
+    return probs
+
+
+def test_batched_iterates_match_oracle():
+    probs = small_batch()
+    bs = [W.rhs(n * n, seed) for (_, n, _, seed) in probs]
+    s = amg.BatchedSolver([(d, n, nl) for (d, n, nl, _) in probs])
+    bcat = torch.as_tensor(np.concatenate(bs), device="cuda")
+    for k in (1, 4):
+        x, infos, _ = s.solve(bcat, tol=0.0, maxit=k)
+        xh = x.cpu().numpy()
+        for i, (d, n, nl, seed) in enumerate(probs):
+            h = hierarchy.build(d, n, nl)
+            o = mpcg.mpcg(h, bs[i], tol=0.0, maxit=k)
+            xi = xh[s.offsets[i]:s.offsets[i + 1]]
+            assert infos[i]["iterations"] == o.iterations, (i, n)
+            assert np.linalg.norm(xi - o.x) <= 1e-10 * np.linalg.norm(o.x), (i, n, k)
+    x, infos, ms = s.solve(bcat, tol=1e-8)
+    for i, (d, n, nl, seed) in enumerate(probs):
+        h = hierarchy.build(d, n, nl)
+        o = mpcg.mpcg(h, bs[i], tol=1e-8)
+        assert infos[i]["status"] == amg.OK
+        assert abs(infos[i]["iterations"] - o.iterations) <= 1, (i, n)
+    s.close()
+
+
+def test_batched_mixed_precision():
+    probs = small_batch()
+    bs = [W.rhs(n * n, seed) for (_, n, _, seed) in probs]
+    s = amg.BatchedSolver([(d, n, nl) for (d, n, nl, _) in probs], precision=1)
+    x, infos, ms = s.solve(torch.as_tensor(np.concatenate(bs), device="cuda"), tol=1e-8)
+    xh = x.cpu().numpy()
+    for i, (d, n, nl, seed) in enumerate(probs):
+        A = ops.fd_matrix(d, n)
+        xi = xh[s.offsets[i]:s.offsets[i + 1]]
+        assert infos[i]["status"] == amg.OK, (i, infos[i])
+        assert np.linalg.norm(bs[i] - A @ xi) / np.linalg.norm(bs[i]) <= 1e-8
+    s.close()
+
+
+def test_batched_edge_cases():
+    probs = [(2, 31, 3), (2, 15, 2)]
+    s = amg.BatchedSolver(probs)
+    b = np.concatenate([np.zeros(31 * 31), W.rhs(225, 3)])
+    x0 = torch.ones(31 * 31 + 225, dtype=torch.float64, device="cuda")
+    x, infos, _ = s.solve(torch.as_tensor(b, device="cuda"), x0, tol=1e-8)
+    assert infos[0]["iterations"] == 0 and torch.count_nonzero(x[: 31 * 31]).item() == 0
+    assert infos[1]["status"] == amg.OK
+    b[5] = np.nan
+    x, infos, _ = s.solve(torch.as_tensor(b, device="cuda"), tol=1e-8)
+    assert infos[0]["status"] == amg.NONFINITE and infos[1]["status"] == amg.OK
+    x, infos, _ = s.solve(torch.as_tensor(np.concatenate([W.rhs(961, 1), W.rhs(225, 3)]), device="cuda"),
+                          tol=1e-14, maxit=2)
+    assert all(i["status"] == amg.MAXIT and i["iterations"] == 2 for i in infos)
+    s.close()
+
+
+def test_batched_512_full():
+    """The 512-problem workload (sides 31..255) in one launch, FP32 bulk."""
+    table = W.batched_instances()
+    s = amg.BatchedSolver([(2, t.n, t.nlevels) for t in table], precision=1)
+    bs = [W.batched_rhs(t) for t in table]
+    x, infos, ms = s.solve(torch.as_tensor(np.concatenate(bs), device="cuda"), tol=1e-8)
+    xh = x.cpu().numpy()
+    worst = 0.0
+    for i, t in enumerate(table):
+        assert infos[i]["status"] == amg.OK, (i, t, infos[i])
+        A = ops.fd_matrix(2, t.n)
+        xi = xh[s.offsets[i]:s.offsets[i + 1]]
+        worst = max(worst, np.linalg.norm(bs[i] - A @ xi) / np.linalg.norm(bs[i]))
+    assert worst <= 1e-8
+    # iteration counts against the FP64 oracle on the extreme and a few other problems
+    sizes = np.array([t.n for t in table])
+    pick = sorted({int(np.argmax(sizes)), int(np.argmin(sizes)), 0, 100, 255, 511})
+    for i in pick:
+        t = table[i]
+        o = mpcg.mpcg(hierarchy.build(2, t.n, t.nlevels), bs[i], tol=1e-8)
+        assert abs(infos[i]["iterations"] - o.iterations) <= 2, (i, t, infos[i]["iterations"], o.iterations)
+    print(f"batched 512: {ms:.2f} ms, worst true relres {worst:.2e}, "
+          f"iterations {min(i['iterations'] for i in infos)}..{max(i['iterations'] for i in infos)}")
+    s.close()
