@@ -80,7 +80,8 @@ typedef struct {
     double  bnorm;           /* ||b||_2                                         */
     double  relres;          /* last ||r||_2 / ||b||_2 on the solver's r        */
     int32_t refreshes;       /* FP32 bulk: true-residual refreshes performed   */
-    int32_t nb;              /* search directions per iteration (L + 1)         */
+    int32_t nb;              /* search directions per iteration (L + 1, or L + 2
+                                with the learned direction)                     */
     double  solve_ms;        /* device time of the solve (HIP events)           */
 } amgmpcg_info;
 
@@ -174,6 +175,104 @@ int amgmpcg_time_kernels(amgmpcg_handle* h, int32_t reps, double* ms_out, int32_
  * Gplus = S Ghat^+ S.  *rank = eigenvalues kept.  Runs on the default
  * stream and synchronises. */
 int amgmpcg_gram_pinv(const double* G, int32_t nb, double tau, double* Gplus, int32_t* rank);
+
+/* r = b - A x with the finest operator in FP64.  b_dev, x_dev, r_dev:
+ * DEVICE, n^dim doubles each (r may not alias b or x). */
+int amgmpcg_residual(amgmpcg_handle* h, const double* b_dev, const double* x_dev, double* r_dev);
+
+/* ---- learned search direction --------------------------------------- */
+/* A convolutional network N (a 3-level U-Net: 3x3x3 convolutions without
+ * bias, ReLU, 2x2x2 average pooling, nearest upsampling with skip
+ * concatenation, 16/32/64 channels, a 1x1x1 output convolution) maps a
+ * residual r to an approximation of the error; its output is appended to the
+ * block Z of Algorithm 1 as one more column, so that the energy minimisation
+ * over span(P_k) chooses its coefficient (and can set it to zero).  Inputs:
+ * channel 0 = r / rms(r), channel 1 = log kappa at the nodes normalised to
+ * zero mean and unit standard deviation (0 for Poisson).  The network runs
+ * on an S^3 grid, S = n rounded up to a multiple of 4, holding the n^3 nodes
+ * in its low corner and zeros elsewhere.  Weights, activations and their
+ * gradients are bfloat16 with FP32 accumulation on the matrix cores; the
+ * FP32 master weights are trained with Adam on the device.  3D only. */
+typedef struct amgmpcg_cnn amgmpcg_cnn;
+
+/* Number of FP32 weights.  Layout: layers w1..w11 in order, each
+ * [tap][Cout][Cin] row-major with tap t = (dz+1)*9 + (dy+1)*3 + (dx+1)
+ * (one tap for w11), layer shapes (Cin -> Cout): w1 16->16 (input channels
+ * 2..15 are zero), w2 16->16, w3 16->32, w4 32->32, w5 32->64, w6 64->64,
+ * w7 96->32, w8 32->32, w9 48->16, w10 16->16, w11 16->16 (only output
+ * channel 0 is used). */
+int64_t amgmpcg_cnn_weight_count(void);
+
+/* A network for n^3 problem grids (1 <= n <= 1000) with He-normal initial
+ * weights from seed; stream: hipStream_t of every operation (NULL = the
+ * default stream).  The network owns its device memory; one network serves
+ * one call at a time. */
+int amgmpcg_cnn_create(int32_t n, uint64_t seed, void* stream, amgmpcg_cnn** out);
+
+/* Weights, HOST, count = amgmpcg_cnn_weight_count() floats.  set_weights
+ * also resets the Adam moments and step count. */
+int amgmpcg_cnn_set_weights(amgmpcg_cnn* net, const float* w, int64_t count);
+int amgmpcg_cnn_get_weights(amgmpcg_cnn* net, float* w, int64_t count);
+/* Weight gradients of the last amgmpcg_cnn_gradients/train_step call. */
+int amgmpcg_cnn_get_gradients(amgmpcg_cnn* net, float* g, int64_t count);
+
+/* d = N(r).  r_dev, d_dev: DEVICE, n^3 doubles.  lk_dev: DEVICE, n^3
+ * bfloat16 bit patterns of the normalised log kappa (amgmpcg_log_kappa), or
+ * NULL for zeros.  Returns AMGMPCG_NONFINITE if d has a NaN/Inf (d is
+ * still written). */
+int amgmpcg_cnn_forward(amgmpcg_cnn* net, const double* r_dev, const uint16_t* lk_dev, double* d_dev);
+
+/* Loss and gradients for one training pair (r, e) with e the error x* - x
+ * that left residual r: loss = mean over the n^3 nodes of
+ * (N(r) - e / rms(e))^2.  r_dev, e_dev: DEVICE, n^3 doubles; lk_dev as for
+ * forward.  *loss (HOST) receives the loss of the forward pass.
+ * train_step additionally applies one Adam step (beta1 0.9, beta2 0.999,
+ * eps 1e-8) with learning rate lr > 0 to the FP32 masters. */
+int amgmpcg_cnn_gradients(amgmpcg_cnn* net, const double* r_dev, const uint16_t* lk_dev,
+                          const double* e_dev, double* loss);
+int amgmpcg_cnn_train_step(amgmpcg_cnn* net, const double* r_dev, const uint16_t* lk_dev,
+                           const double* e_dev, float lr, double* loss);
+
+/* Average time in ms of one inference (reps back-to-back forward passes
+ * between two HIP events on the network's stream).  ms: HOST. */
+int amgmpcg_cnn_time_forward(amgmpcg_cnn* net, const double* r_dev, const uint16_t* lk_dev,
+                             int32_t reps, double* ms);
+
+/* One layer l (0..10 for w1..w11) of the network, with its current
+ * weights, on caller tensors: channels-last bfloat16 bit patterns on an S^3
+ * grid (1 <= S <= 512), zero outside the grid.
+ *   op 0: out = relu(conv_l(A)), bfloat16 with Cout channels (l = 10: no
+ *         ReLU, FP32 output with 16 channels);
+ *   op 1: out = conv_l^T(A): the data gradient for an output gradient A
+ *         (Cout channels), bfloat16 with Cin channels;
+ *   op 2: out = the weight gradient for output gradient A (Cout channels)
+ *         and layer input B (Cin channels): FP32 [tap][Cout][Cin].
+ * A_dev, B_dev, out_dev: DEVICE.  Synchronises. */
+int amgmpcg_cnn_layer(amgmpcg_cnn* net, int32_t layer, int32_t op, int32_t S, const uint16_t* A_dev,
+                      const uint16_t* B_dev, void* out_dev);
+
+/* Free a network.  Detach it from every handle first. */
+void amgmpcg_cnn_destroy(amgmpcg_cnn* net);
+
+/* Append the learned direction N(r_k) to every block Z_k of the solves of
+ * this 3D handle (net = NULL removes it).  nb becomes nlevels + 1 (needs
+ * nlevels <= 7); a direction with a NaN/Inf value is replaced by zero, which
+ * the pseudo-inverse then drops.  The handle keeps the pointer: the network
+ * must outlive the attachment.  AMGMPCG_DIM_MISMATCH if the network's n
+ * differs from the grid's. */
+int amgmpcg_attach_cnn(amgmpcg_handle* h, amgmpcg_cnn* net);
+
+/* The network's second input channel for this handle's kappa: DEVICE out,
+ * n^3 bfloat16 bit patterns (zeros for Poisson). */
+int amgmpcg_log_kappa(amgmpcg_handle* h, uint16_t* lk_dev);
+
+/* Training pairs from this handle's iteration: for each k = ks[i] (HOST,
+ * nk entries, k >= 0), x_k = k iterations of amgmpcg_solve from x_0 = 0
+ * with tol = 0, R_dev[i*N ..] = b - A x_k and E_dev[i*N ..] = xs - x_k
+ * (N = n^dim; DEVICE, nk*N doubles each; xs_dev the converged solution).
+ * Uses the attached network if any. */
+int amgmpcg_make_pairs(amgmpcg_handle* h, const double* b_dev, const double* xs_dev, const int32_t* ks,
+                       int32_t nk, double* R_dev, double* E_dev);
 
 void amgmpcg_destroy(amgmpcg_handle* h);
 const char* amgmpcg_status_string(int status);

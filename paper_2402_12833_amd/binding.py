@@ -93,8 +93,31 @@ def load(path: str = LIB_PATH):
     lib.amgmpcg_status_string.restype = ctypes.c_char_p
     lib.amgmpcg_last_error.argtypes = []
     lib.amgmpcg_last_error.restype = ctypes.c_char_p
+    lib.amgmpcg_residual.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
+    lib.amgmpcg_cnn_weight_count.argtypes = []
+    lib.amgmpcg_cnn_weight_count.restype = ctypes.c_int64
+    lib.amgmpcg_cnn_create.argtypes = [c_int32, ctypes.c_uint64, c_void_p, POINTER(c_void_p)]
+    lib.amgmpcg_cnn_set_weights.argtypes = [c_void_p, POINTER(ctypes.c_float), ctypes.c_int64]
+    lib.amgmpcg_cnn_get_weights.argtypes = [c_void_p, POINTER(ctypes.c_float), ctypes.c_int64]
+    lib.amgmpcg_cnn_get_gradients.argtypes = [c_void_p, POINTER(ctypes.c_float), ctypes.c_int64]
+    lib.amgmpcg_cnn_forward.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
+    lib.amgmpcg_cnn_gradients.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_double)]
+    lib.amgmpcg_cnn_train_step.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.c_float,
+                                           POINTER(c_double)]
+    lib.amgmpcg_cnn_time_forward.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, POINTER(c_double)]
+    lib.amgmpcg_cnn_layer.argtypes = [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p]
+    lib.amgmpcg_cnn_destroy.argtypes = [c_void_p]
+    lib.amgmpcg_cnn_destroy.restype = None
+    lib.amgmpcg_attach_cnn.argtypes = [c_void_p, c_void_p]
+    lib.amgmpcg_log_kappa.argtypes = [c_void_p, c_void_p]
+    lib.amgmpcg_make_pairs.argtypes = [c_void_p, c_void_p, c_void_p, POINTER(c_int32), c_int32, c_void_p,
+                                       c_void_p]
     for name in ("amgmpcg_setup_grid", "amgmpcg_solve", "amgmpcg_solve_host", "amgmpcg_mg_block",
-                 "amgmpcg_level_count", "amgmpcg_level_size", "amgmpcg_level_stencil", "amgmpcg_history"):
+                 "amgmpcg_level_count", "amgmpcg_level_size", "amgmpcg_level_stencil", "amgmpcg_history",
+                 "amgmpcg_residual", "amgmpcg_cnn_create", "amgmpcg_cnn_set_weights", "amgmpcg_cnn_get_weights",
+                 "amgmpcg_cnn_get_gradients", "amgmpcg_cnn_forward", "amgmpcg_cnn_gradients",
+                 "amgmpcg_cnn_train_step", "amgmpcg_cnn_time_forward", "amgmpcg_cnn_layer", "amgmpcg_attach_cnn", "amgmpcg_log_kappa",
+                 "amgmpcg_make_pairs"):
         getattr(lib, name).restype = c_int32
     _lib = lib
     return lib
@@ -213,6 +236,45 @@ class Solver:
         _check(self._lib.amgmpcg_mg_block(self._h, c_void_p(r.data_ptr()), c_void_p(Z.data_ptr())))
         return Z
 
+    def _vec(self, t, name):
+        import torch
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() != self.N:
+            raise ValueError(f"{name} must be a contiguous float64 device tensor of n^dim entries")
+        return c_void_p(t.data_ptr())
+
+    def residual(self, b, x):
+        """r = b - A x (FP64 finest operator) as a new device tensor."""
+        import torch
+        r = torch.empty_like(b)
+        _check(self._lib.amgmpcg_residual(self._h, self._vec(b, "b"), self._vec(x, "x"), c_void_p(r.data_ptr())))
+        return r
+
+    def attach(self, net: Optional["Network"]):
+        """Append the network's output as one more search direction (None removes it)."""
+        _check(self._lib.amgmpcg_attach_cnn(self._h, None if net is None else net._h))
+        self._net = net
+        nl, nb = c_int32(), c_int32()
+        _check(self._lib.amgmpcg_level_count(self._h, byref(nl), byref(nb)))
+        self.nb = nb.value
+
+    def log_kappa(self):
+        """The network's normalised log-kappa input channel (bfloat16 device tensor)."""
+        import torch
+        lk = torch.empty(self.N, dtype=torch.bfloat16, device="cuda")
+        _check(self._lib.amgmpcg_log_kappa(self._h, c_void_p(lk.data_ptr())))
+        return lk
+
+    def make_pairs(self, b, xs, ks):
+        """(R, E): rows r_k = b - A x_k and e_k = xs - x_k for k in ks (x_0 = 0)."""
+        import torch
+        ks = np.ascontiguousarray(ks, dtype=np.int32)
+        R = torch.empty((len(ks), self.N), dtype=torch.float64, device=b.device)
+        E = torch.empty_like(R)
+        _check(self._lib.amgmpcg_make_pairs(self._h, self._vec(b, "b"), self._vec(xs, "xs"),
+                                            ks.ctypes.data_as(POINTER(c_int32)), len(ks), c_void_p(R.data_ptr()),
+                                            c_void_p(E.data_ptr())))
+        return R, E
+
     def level_size(self, level: int) -> int:
         v = c_int32()
         _check(self._lib.amgmpcg_level_size(self._h, level, byref(v)))
@@ -298,3 +360,134 @@ class BatchedSolver:
                                                float(tol), int(maxit), infos, byref(ms))
         _check(code, (OK, MAXIT, BREAKDOWN, NONFINITE))
         return x, [i.as_dict() for i in infos], ms.value
+
+
+def cnn_weight_count() -> int:
+    return int(load().amgmpcg_cnn_weight_count())
+
+
+# Layer shapes (taps, Cin, Cout) in weight-array order.
+CNN_LAYERS = (("w1", 27, 16, 16), ("w2", 27, 16, 16), ("w3", 27, 16, 32), ("w4", 27, 32, 32),
+              ("w5", 27, 32, 64), ("w6", 27, 64, 64), ("w7", 27, 96, 32), ("w8", 27, 32, 32),
+              ("w9", 27, 48, 16), ("w10", 27, 16, 16), ("w11", 1, 16, 16))
+
+
+class Network:
+    """The U-Net learned direction for n^3 grids (device weights, Adam state)."""
+
+    def __init__(self, n: int, seed: int = 0, stream=None):
+        lib = load()
+        self._lib = lib
+        self.n = n
+        self.N = n ** 3
+        self.stream = _current_stream() if stream is None else stream
+        h = c_void_p()
+        _check(lib.amgmpcg_cnn_create(int(n), int(seed), self.stream, byref(h)))
+        self._h = h
+        self.count = cnn_weight_count()
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.amgmpcg_cnn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _vec(self, t, name):
+        import torch
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() != self.N:
+            raise ValueError(f"{name} must be a contiguous float64 device tensor of n^3 entries")
+        return c_void_p(t.data_ptr())
+
+    def _lk(self, lk):
+        import torch
+        if lk is None:
+            return None
+        if lk.dtype != torch.bfloat16 or not lk.is_cuda or not lk.is_contiguous() or lk.numel() != self.N:
+            raise ValueError("lk must be a contiguous bfloat16 device tensor of n^3 entries")
+        return c_void_p(lk.data_ptr())
+
+    def get_weights(self) -> np.ndarray:
+        w = np.empty(self.count, dtype=np.float32)
+        _check(self._lib.amgmpcg_cnn_get_weights(self._h, w.ctypes.data_as(POINTER(ctypes.c_float)), self.count))
+        return w
+
+    def set_weights(self, w: np.ndarray):
+        w = np.ascontiguousarray(w, dtype=np.float32).reshape(-1)
+        _check(self._lib.amgmpcg_cnn_set_weights(self._h, w.ctypes.data_as(POINTER(ctypes.c_float)), w.size))
+
+    def get_gradients(self) -> np.ndarray:
+        g = np.empty(self.count, dtype=np.float32)
+        _check(self._lib.amgmpcg_cnn_get_gradients(self._h, g.ctypes.data_as(POINTER(ctypes.c_float)), self.count))
+        return g
+
+    @staticmethod
+    def split(flat: np.ndarray) -> dict:
+        """Flat weight array -> {name: (taps, Cout, Cin) array} (w11: (Cout, Cin))."""
+        out, off = {}, 0
+        for name, taps, cin, cout in CNN_LAYERS:
+            cnt = taps * cin * cout
+            a = np.asarray(flat[off:off + cnt]).reshape(taps, cout, cin)
+            out[name] = a[0] if taps == 1 else a
+            off += cnt
+        return out
+
+    @staticmethod
+    def join(layers: dict) -> np.ndarray:
+        return np.concatenate([np.asarray(layers[name], dtype=np.float32).reshape(-1)
+                               for name, *_ in CNN_LAYERS])
+
+    def forward(self, r, lk=None, allow=(OK, NONFINITE)):
+        """d = N(r) as a new float64 device tensor; returns (d, status)."""
+        import torch
+        d = torch.empty_like(r)
+        code = self._lib.amgmpcg_cnn_forward(self._h, self._vec(r, "r"), self._lk(lk), c_void_p(d.data_ptr()))
+        _check(code, allow)
+        return d, code
+
+    def gradients(self, r, e, lk=None) -> float:
+        loss = c_double()
+        _check(self._lib.amgmpcg_cnn_gradients(self._h, self._vec(r, "r"), self._lk(lk), self._vec(e, "e"),
+                                               byref(loss)))
+        return loss.value
+
+    def train_step(self, r, e, lr: float, lk=None) -> float:
+        loss = c_double()
+        _check(self._lib.amgmpcg_cnn_train_step(self._h, self._vec(r, "r"), self._lk(lk), self._vec(e, "e"),
+                                                float(lr), byref(loss)))
+        return loss.value
+
+    def layer(self, layer: int, op: int, A, B=None):
+        """One layer on bfloat16 device tensors of shape (S, S, S, C): op 0
+        forward (+ReLU), op 1 data gradient, op 2 weight gradient (A = output
+        gradient, B = layer input).  Returns a new device tensor."""
+        import torch
+        _, taps, cin, cout = CNN_LAYERS[layer]
+        S = A.shape[0]
+        for t in (A, B):
+            if t is not None and (t.dtype != torch.bfloat16 or not t.is_cuda or not t.is_contiguous()
+                                  or t.dim() != 4 or t.shape[:3] != (S, S, S)):
+                raise ValueError("tensors must be contiguous bfloat16 (S, S, S, C) device tensors")
+        need_a = cin if op == 0 else cout
+        if A.shape[3] != need_a or (op == 2 and (B is None or B.shape[3] != cin)):
+            raise ValueError("channel count does not match the layer")
+        if op == 0:
+            out = torch.empty((S, S, S, cout), dtype=torch.float32 if layer == 10 else torch.bfloat16,
+                              device=A.device)
+        elif op == 1:
+            out = torch.empty((S, S, S, cin), dtype=torch.bfloat16, device=A.device)
+        else:
+            out = torch.empty((taps, cout, cin), dtype=torch.float32, device=A.device)
+        _check(self._lib.amgmpcg_cnn_layer(self._h, layer, op, S, c_void_p(A.data_ptr()),
+                                           None if B is None else c_void_p(B.data_ptr()),
+                                           c_void_p(out.data_ptr())))
+        return out
+
+    def time_forward(self, r, lk=None, reps: int = 10) -> float:
+        ms = c_double()
+        _check(self._lib.amgmpcg_cnn_time_forward(self._h, self._vec(r, "r"), self._lk(lk), int(reps), byref(ms)))
+        return ms.value

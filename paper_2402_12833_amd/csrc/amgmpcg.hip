@@ -21,6 +21,7 @@
 #include "setup.hpp"
 #include "small_kernels.hpp"
 #include "batched.hpp"
+#include "cnn_host.hpp"
 
 namespace amg {
 
@@ -95,6 +96,12 @@ class SolverBase {
     virtual void level_stencil(int level, double* out) = 0;
     virtual void history(int cap, double* alpha, double* res, int* count) = 0;
     virtual int time_kernels(int reps, double* ms, int cap) = 0;
+    virtual void attach(cnn::Net* net) = 0;
+    virtual void residual(const double* b_dev, const double* x_dev, double* r_dev) = 0;
+    virtual void make_pairs(const double* b_dev, const double* xs_dev, const int* ks, int nk, double* R_dev,
+                            double* E_dev) = 0;
+    virtual void log_kappa(unsigned short* lk_dev) = 0;
+    cnn::Net* net_ = nullptr;
     int dim = 0, nlev = 0, nb = 0;
     std::vector<int> n_axis;   // per level, 0 = coarsest
 };
@@ -206,7 +213,110 @@ class Solver : public SolverBase {
         HIPCHK(hipEventCreate(&ev0_));
         HIPCHK(hipEventCreate(&ev1_));
         HIPCHK(hipStreamSynchronize(stream_));
+        set_tau();
+        if (DIM == 3 && var) {
+            // network input channel: log kappa at the n^3 nodes, normalised
+            // to zero mean and unit standard deviation, rounded to bfloat16
+            const int n = g.n, m = n + 2;
+            std::vector<double> lk((size_t)N);
+            double mean = 0.0;
+            for (int z = 0; z < n; ++z)
+                for (int y = 0; y < n; ++y)
+                    for (int x = 0; x < n; ++x) {
+                        const double v = std::log(g.kappa[((size_t)(z + 1) * m + (y + 1)) * m + (x + 1)]);
+                        lk[((size_t)z * n + y) * n + x] = v;
+                        mean += v;
+                    }
+            mean /= N;
+            double var2 = 0.0;
+            for (double v : lk) var2 += (v - mean) * (v - mean);
+            const double sd = std::sqrt(var2 / N);
+            std::vector<unsigned short> h((size_t)N);
+            for (size_t i = 0; i < h.size(); ++i) {
+                const float f = (float)((lk[i] - mean) / (sd > 0.0 ? sd : 1.0));
+                uint32_t u;
+                std::memcpy(&u, &f, 4);
+                u += 0x7fffu + ((u >> 16) & 1u);
+                h[i] = (unsigned short)(u >> 16);
+            }
+            lk_.alloc(N);
+            HIPCHK(hipMemcpy(lk_.p, h.data(), h.size() * sizeof(unsigned short), hipMemcpyHostToDevice));
+        }
+    }
+
+    void set_tau() {
         tau_ = opt_.pinv_tau > 0 ? opt_.pinv_tau : 64.0 * nb * (mixed_ ? std::ldexp(1.0, -24) : std::ldexp(1.0, -53));
+    }
+
+    // Append (net != null) or remove the learned direction.  The column count
+    // becomes L + 2; P, Q and the history grow, the captured graph is redone.
+    void attach(cnn::Net* net) override {
+        const int N = N_[L_];
+        if (net) {
+            if (DIM != 3) throw ApiError(AMGMPCG_INVALID_ARG, "the learned direction needs a 3D problem");
+            if (net->n != n_axis[L_]) throw ApiError(AMGMPCG_DIM_MISMATCH, "network grid differs from the problem grid");
+            if (nlev + 1 > kMaxNB) throw ApiError(AMGMPCG_INVALID_ARG, "too many levels for an extra direction");
+        }
+        net_ = net;
+        nb = nlev + (net ? 1 : 0);
+        const size_t need = (size_t)even_up(nb) * N;
+        if (P_.n < need) {
+            P_.alloc(need);
+            Q_.alloc(need);
+            HIPCHK(hipMemset(P_.p, 0, P_.n * sizeof(T)));
+            HIPCHK(hipMemset(Q_.p, 0, Q_.n * sizeof(T)));
+        }
+        if (net && !dl_.p) dl_.alloc(N);
+        if (hist_cap_ > 0) ahist_.alloc((size_t)hist_cap_ * nb);
+        set_tau();
+        if (exec_) (void)hipGraphExecDestroy(exec_);
+        if (graph_) (void)hipGraphDestroy(graph_);
+        exec_ = nullptr;
+        graph_ = nullptr;
+        graph_ready_ = false;
+    }
+
+    void residual(const double* b_dev, const double* x_dev, double* r_dev) override {
+        k_init_residual<DIM><<<FB_, kBlock, 0, stream_>>>(rows_, f64_, b_dev, x_dev, r_dev, part_init());
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(stream_));
+    }
+
+    // Training pairs from this handle's own iterates: for each k in ks, x_k =
+    // k iterations from x0 = 0 (x_0 = 0), r_k = b - A x_k, e_k = xs - x_k.
+    void make_pairs(const double* b_dev, const double* xs_dev, const int* ks, int nk, double* R_dev,
+                    double* E_dev) override {
+        const int N = N_[L_];
+        if (!xt_.p) xt_.alloc(N);
+        for (int i = 0; i < nk; ++i) {
+            HIPCHK(hipMemsetAsync(xt_.p, 0, (size_t)N * sizeof(double), stream_));
+            if (ks[i] > 0) solve(b_dev, xt_.p, 0.0, ks[i], nullptr);
+            k_pair<DIM><<<(rows_.total + kBlock - 1) / kBlock, kBlock, 0, stream_>>>(
+                rows_, f64_, b_dev, xs_dev, xt_.p, R_dev + (size_t)i * N, E_dev + (size_t)i * N);
+            HIPCHK(hipGetLastError());
+        }
+        HIPCHK(hipStreamSynchronize(stream_));
+    }
+
+    void log_kappa(unsigned short* lk_dev) override {
+        const int N = N_[L_];
+        if (lk_.p)
+            HIPCHK(hipMemcpyAsync(lk_dev, lk_.p, (size_t)N * sizeof(unsigned short), hipMemcpyDeviceToDevice, stream_));
+        else
+            HIPCHK(hipMemsetAsync(lk_dev, 0, (size_t)N * sizeof(unsigned short), stream_));
+        HIPCHK(hipStreamSynchronize(stream_));
+    }
+
+    const T* dl() const { return net_ ? dl_.p : nullptr; }
+    const int* dflag() const { return net_ ? net_->flag.p : nullptr; }
+
+    // The learned direction d = N(r) into dl_ (bulk type); flag on non-finite.
+    void enqueue_learned(const Ctl* ctl, const double* r) {
+        const int n = n_axis[L_];
+        net_->forward(ctl, r, lk_.p, stream_);
+        cnn::k_clear_flag<<<1, 64, 0, stream_>>>(ctl, net_->flag.p);
+        cnn::k_unpack_output<T><<<(N_[L_] + cnn::kCB - 1) / cnn::kCB, cnn::kCB, 0, stream_>>>(
+            ctl, net_->out.p, dl_.p, n, net_->S, net_->flag.p);
     }
 
     ~Solver() override {
@@ -269,9 +379,9 @@ class Solver : public SolverBase {
         enqueue_mg(ctl_free_, r_dev);
         const int N = N_[L_];
         dispatch_nb([&](auto nbc) {
-            constexpr int NB = decltype(nbc)::value;
-            k_write_Z<DIM, T, NB><<<(rows_.total + kBlock - 1) / kBlock, kBlock, 0, stream_>>>(
-                rows_, N, fine_Y(), L_ > 0 ? n_axis[L_ - 1] : 1, cL_final_, Z_dev);
+            constexpr int NB = decltype(nbc)::value, NE = decltype(nbc)::ne;
+            k_write_Z<DIM, T, NB, NE><<<(rows_.total + kBlock - 1) / kBlock, kBlock, 0, stream_>>>(
+                rows_, N, fine_Y(), L_ > 0 ? n_axis[L_ - 1] : 1, cL_final_, dl(), dflag(), Z_dev);
         });
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(stream_));
@@ -322,6 +432,7 @@ class Solver : public SolverBase {
         enqueue_mg(cf, r_.p);   // sets the final smoother buffers
         dispatch_nb([&](auto nbc) {
             constexpr int NB = decltype(nbc)::value;
+            [[maybe_unused]] constexpr int NE = decltype(nbc)::ne;
             const int nc = L_ > 0 ? n_axis[L_ - 1] : 1;
             timed([&] { k_update_r<T, NB><<<FB_, kBlock, 0, stream_>>>(cf, N, Q_.p, d_alpha(), r_.p, part_rho()); });
             timed([&] {
@@ -349,10 +460,12 @@ class Solver : public SolverBase {
             }
             enqueue_mg(cf, r_.p);
             timed([&] {
-                k_fine_W<DIM, T, NB><<<FB_, kBlock, 0, stream_>>>(cf, rows_, fine_Y(), nc, cL_final_, Q_.p, part_W());
+                k_fine_W<DIM, T, NB, NE><<<FB_, kBlock, 0, stream_>>>(cf, rows_, fine_Y(), nc, cL_final_, dl(), dflag(),
+                                                                      Q_.p, part_W());
             });
             timed([&] {
-                k_update_xP<DIM, T, NB><<<FB_, kBlock, 0, stream_>>>(cf, rows_, fine_Y(), nc, cL_final_, P_.p, x_.p,
+                k_update_xP<DIM, T, NB, NE><<<FB_, kBlock, 0, stream_>>>(cf, rows_, fine_Y(), nc, cL_final_, dl(),
+                                                                         dflag(), P_.p, x_.p,
                                                                       d_alpha(), d_beta(), 0);
             });
             timed([&] { k_spmm_gram<DIM, T, NB><<<FB_, kBlock, 0, stream_>>>(cf, rows_, fop_, P_.p, Q_.p, r_.p, part_G()); });
@@ -362,13 +475,29 @@ class Solver : public SolverBase {
     }
 
    private:
-    template <int V>
+    template <int V, int E = 0>
     struct IC {
         static constexpr int value = V;
+        static constexpr int ne = E;   // 1: the last column is the learned direction
     };
 
     template <typename F>
     void dispatch_nb(F&& f) {
+        if constexpr (DIM == 3) {
+            if (net_) {
+                switch (nb) {
+                    case 2: f(IC<2, 1>{}); break;
+                    case 3: f(IC<3, 1>{}); break;
+                    case 4: f(IC<4, 1>{}); break;
+                    case 5: f(IC<5, 1>{}); break;
+                    case 6: f(IC<6, 1>{}); break;
+                    case 7: f(IC<7, 1>{}); break;
+                    case 8: f(IC<8, 1>{}); break;
+                    default: throw ApiError(AMGMPCG_INVALID_ARG, "unsupported number of directions");
+                }
+                return;
+            }
+        }
         switch (nb) {
             case 1: f(IC<1>{}); break;
             case 2: f(IC<2>{}); break;
@@ -474,7 +603,13 @@ class Solver : public SolverBase {
     }
 
     // Z = MG(r) up to the coarse block and the fine smoother output.
+    // Z = MG(r): every level correction and, when attached, the learned one.
     void enqueue_mg(const Ctl* ctl, const double* r) {
+        enqueue_levels(ctl, r);
+        if (net_) enqueue_learned(ctl, r);
+    }
+
+    void enqueue_levels(const Ctl* ctl, const double* r) {
         const int L = L_;
         const T omega = T(opt_.omega);
         const int nu = opt_.nu;
@@ -580,9 +715,10 @@ class Solver : public SolverBase {
         enqueue_mg(ctl_, r_.p);
         dispatch_nb([&](auto nbc) {
             constexpr int NB = decltype(nbc)::value;
+            [[maybe_unused]] constexpr int NE = decltype(nbc)::ne;
             const int nc = L_ > 0 ? n_axis[L_ - 1] : 1;
-            k_update_xP<DIM, T, NB><<<FB_, kBlock, 0, stream_>>>(ctl_, rows_, fine_Y(), nc, cL_final_,
-                                                                   P_.p, x_.p, d_alpha(), d_beta(), 1);
+            k_update_xP<DIM, T, NB, NE><<<FB_, kBlock, 0, stream_>>>(ctl_, rows_, fine_Y(), nc, cL_final_, dl(),
+                                                                       dflag(), P_.p, x_.p, d_alpha(), d_beta(), 1);
             k_spmm_gram<DIM, T, NB><<<FB_, kBlock, 0, stream_>>>(ctl_, rows_, fop_, P_.p, Q_.p, r_.p, part_G());
             k_reduce_alpha<NB><<<1, kRedBlock, 0, stream_>>>(ctl_, part_G(), FB_, d_Gplus(), d_alpha(),
                                                           hist_cap_ ? ahist_.p : nullptr);
@@ -595,14 +731,15 @@ class Solver : public SolverBase {
         stream_ = s;
         dispatch_nb([&](auto nbc) {
             constexpr int NB = decltype(nbc)::value;
+            [[maybe_unused]] constexpr int NE = decltype(nbc)::ne;
             const int nc = L_ > 0 ? n_axis[L_ - 1] : 1;
             k_update_r<T, NB><<<FB_, kBlock, 0, s>>>(ctl_, N, Q_.p, d_alpha(), r_.p, part_rho());
             enqueue_mg(ctl_, r_.p);
-            k_fine_W<DIM, T, NB><<<FB_, kBlock, 0, s>>>(ctl_, rows_, fine_Y(), nc, cL_final_, Q_.p,
+            k_fine_W<DIM, T, NB, NE><<<FB_, kBlock, 0, s>>>(ctl_, rows_, fine_Y(), nc, cL_final_, dl(), dflag(), Q_.p,
                                                          part_W());
             k_reduce_beta<NB><<<1, kRedBlock, 0, s>>>(ctl_, part_rho(), part_W(), FB_, d_Gplus(), d_beta(),
                                                    hist_cap_ ? rhist_.p : nullptr, mixed_ ? 1 : 0);
-            k_update_xP<DIM, T, NB><<<FB_, kBlock, 0, s>>>(ctl_, rows_, fine_Y(), nc, cL_final_, P_.p,
+            k_update_xP<DIM, T, NB, NE><<<FB_, kBlock, 0, s>>>(ctl_, rows_, fine_Y(), nc, cL_final_, dl(), dflag(), P_.p,
                                                             x_.p, d_alpha(), d_beta(), 0);
             if (mixed_) {
                 k_refresh<DIM><<<FB_, kBlock, 0, s>>>(ctl_, rows_, f64_, b_.p, x_.p, r_.p, part_ref());
@@ -616,7 +753,7 @@ class Solver : public SolverBase {
     }
 
     void capture_graph() {
-        HIPCHK(hipStreamCreateWithFlags(&cap_stream_, hipStreamNonBlocking));
+        if (!cap_stream_) HIPCHK(hipStreamCreateWithFlags(&cap_stream_, hipStreamNonBlocking));
         HIPCHK(hipStreamBeginCapture(cap_stream_, hipStreamCaptureModeThreadLocal));
         for (int k = 0; k < opt_.k_poll; ++k) enqueue_iteration(cap_stream_);
         hipError_t launch_err = hipGetLastError();
@@ -644,7 +781,9 @@ class Solver : public SolverBase {
     std::vector<DevBuf<T>> coef_, g_, c1_, c_, c2_, Y_;
     T* cL_final_ = nullptr;
     DevBuf<double> x_, r_, b_, part_, small_, ahist_, rhist_;
-    DevBuf<T> P_, Q_, cL_, cL2_;
+    DevBuf<T> P_, Q_, cL_, cL2_, dl_;
+    DevBuf<double> xt_;
+    DevBuf<unsigned short> lk_;
     Ctl* ctl_ = nullptr;
     Ctl* ctl_free_ = nullptr;
     Ctl* hctl_ = nullptr;
@@ -865,6 +1004,10 @@ class BatchedSolver : public BatchedBase {
 struct amgmpcg_handle {
     std::unique_ptr<amg::SolverBase> s;
     std::unique_ptr<amg::BatchedBase> bs;
+};
+
+struct amgmpcg_cnn {
+    amg::cnn::Net net;
 };
 
 using amg::ApiError;
@@ -1130,6 +1273,170 @@ int amgmpcg_gram_pinv(const double* G, int32_t nb, double tau, double* Gplus, in
         int r = 0;
         HIPCHK(hipMemcpy(&r, drank, sizeof(int), hipMemcpyDeviceToHost));
         *rank = r;
+        return AMGMPCG_OK;
+    });
+}
+
+int amgmpcg_residual(amgmpcg_handle* h, const double* b_dev, const double* x_dev, double* r_dev) {
+    return guarded([&]() -> int {
+        if (!h || !h->s) throw ApiError(AMGMPCG_INVALID_ARG, "handle is NULL");
+        if (!b_dev || !x_dev || !r_dev) throw ApiError(AMGMPCG_INVALID_ARG, "NULL vector");
+        if (r_dev == b_dev || r_dev == x_dev) throw ApiError(AMGMPCG_INVALID_ARG, "r may not alias b or x");
+        h->s->residual(b_dev, x_dev, r_dev);
+        return AMGMPCG_OK;
+    });
+}
+
+int64_t amgmpcg_cnn_weight_count(void) { return amg::cnn::total_weights(); }
+
+static void check_net(const amgmpcg_cnn* net) {
+    if (!net) throw ApiError(AMGMPCG_INVALID_ARG, "network is NULL");
+}
+
+static void check_count(int64_t count) {
+    if (count != amg::cnn::total_weights()) throw ApiError(AMGMPCG_INVALID_ARG, "weight count mismatch");
+}
+
+int amgmpcg_cnn_create(int32_t n, uint64_t seed, void* stream, amgmpcg_cnn** out) {
+    return guarded([&]() -> int {
+        if (!out) throw ApiError(AMGMPCG_INVALID_ARG, "out pointer is NULL");
+        *out = nullptr;
+        if (n < 1 || n > 1000) throw ApiError(AMGMPCG_INVALID_ARG, "n must be in 1..1000");
+        auto c = std::make_unique<amgmpcg_cnn>();
+        HIPCHK(c->net.init(n, seed, (hipStream_t)stream));
+        *out = c.release();
+        return AMGMPCG_OK;
+    });
+}
+
+int amgmpcg_cnn_set_weights(amgmpcg_cnn* net, const float* w, int64_t count) {
+    return guarded([&]() -> int {
+        check_net(net);
+        check_count(count);
+        if (!w) throw ApiError(AMGMPCG_INVALID_ARG, "weights are NULL");
+        HIPCHK(net->net.set_weights(w));
+        return AMGMPCG_OK;
+    });
+}
+
+int amgmpcg_cnn_get_weights(amgmpcg_cnn* net, float* w, int64_t count) {
+    return guarded([&]() -> int {
+        check_net(net);
+        check_count(count);
+        if (!w) throw ApiError(AMGMPCG_INVALID_ARG, "output is NULL");
+        HIPCHK(net->net.get(net->net.w.p, w));
+        return AMGMPCG_OK;
+    });
+}
+
+int amgmpcg_cnn_get_gradients(amgmpcg_cnn* net, float* g, int64_t count) {
+    return guarded([&]() -> int {
+        check_net(net);
+        check_count(count);
+        if (!g) throw ApiError(AMGMPCG_INVALID_ARG, "output is NULL");
+        HIPCHK(net->net.get(net->net.g.p, g));
+        return AMGMPCG_OK;
+    });
+}
+
+int amgmpcg_cnn_forward(amgmpcg_cnn* net, const double* r_dev, const uint16_t* lk_dev, double* d_dev) {
+    return guarded([&]() -> int {
+        check_net(net);
+        if (!r_dev || !d_dev) throw ApiError(AMGMPCG_INVALID_ARG, "r or d is NULL");
+        bool finite = true;
+        HIPCHK(net->net.infer(r_dev, lk_dev, d_dev, &finite));
+        return finite ? AMGMPCG_OK : AMGMPCG_NONFINITE;
+    });
+}
+
+int amgmpcg_cnn_gradients(amgmpcg_cnn* net, const double* r_dev, const uint16_t* lk_dev, const double* e_dev,
+                          double* loss) {
+    return guarded([&]() -> int {
+        check_net(net);
+        if (!r_dev || !e_dev) throw ApiError(AMGMPCG_INVALID_ARG, "r or e is NULL");
+        HIPCHK(net->net.step_pair(r_dev, lk_dev, e_dev, 0.f, loss));
+        return AMGMPCG_OK;
+    });
+}
+
+int amgmpcg_cnn_train_step(amgmpcg_cnn* net, const double* r_dev, const uint16_t* lk_dev, const double* e_dev,
+                           float lr, double* loss) {
+    return guarded([&]() -> int {
+        check_net(net);
+        if (!r_dev || !e_dev) throw ApiError(AMGMPCG_INVALID_ARG, "r or e is NULL");
+        if (!(lr > 0.f) || !std::isfinite(lr)) throw ApiError(AMGMPCG_INVALID_ARG, "lr must be finite and > 0");
+        HIPCHK(net->net.step_pair(r_dev, lk_dev, e_dev, lr, loss));
+        return AMGMPCG_OK;
+    });
+}
+
+int amgmpcg_cnn_time_forward(amgmpcg_cnn* net, const double* r_dev, const uint16_t* lk_dev, int32_t reps,
+                             double* ms) {
+    return guarded([&]() -> int {
+        check_net(net);
+        if (!r_dev || !ms) throw ApiError(AMGMPCG_INVALID_ARG, "NULL argument");
+        if (reps < 1) throw ApiError(AMGMPCG_INVALID_ARG, "reps must be >= 1");
+        hipStream_t s = net->net.stream;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        HIPCHK(hipEventCreate(&e0));
+        hipError_t err = hipEventCreate(&e1);
+        if (err == hipSuccess) err = hipEventRecord(e0, s);
+        for (int i = 0; i < reps && err == hipSuccess; ++i) net->net.forward(nullptr, r_dev, lk_dev, s);
+        if (err == hipSuccess) err = hipGetLastError();
+        if (err == hipSuccess) err = hipEventRecord(e1, s);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float t = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+        (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        HIPCHK(err);
+        *ms = double(t) / reps;
+        return AMGMPCG_OK;
+    });
+}
+
+int amgmpcg_cnn_layer(amgmpcg_cnn* net, int32_t layer, int32_t op, int32_t S, const uint16_t* A_dev,
+                      const uint16_t* B_dev, void* out_dev) {
+    return guarded([&]() -> int {
+        check_net(net);
+        if (layer < 0 || layer > 10) throw ApiError(AMGMPCG_INVALID_ARG, "layer must be in 0..10");
+        if (op < 0 || op > 2) throw ApiError(AMGMPCG_INVALID_ARG, "op must be 0, 1 or 2");
+        if (S < 1 || S > 512) throw ApiError(AMGMPCG_INVALID_ARG, "S must be in 1..512");
+        if (!A_dev || !out_dev || (op == 2 && !B_dev)) throw ApiError(AMGMPCG_INVALID_ARG, "NULL tensor");
+        HIPCHK(net->net.layer_op(layer, op, S, A_dev, B_dev, out_dev));
+        return AMGMPCG_OK;
+    });
+}
+
+void amgmpcg_cnn_destroy(amgmpcg_cnn* net) { delete net; }
+
+int amgmpcg_attach_cnn(amgmpcg_handle* h, amgmpcg_cnn* net) {
+    return guarded([&]() -> int {
+        if (!h || !h->s) throw ApiError(AMGMPCG_INVALID_ARG, "handle is NULL");
+        h->s->attach(net ? &net->net : nullptr);
+        return AMGMPCG_OK;
+    });
+}
+
+int amgmpcg_log_kappa(amgmpcg_handle* h, uint16_t* lk_dev) {
+    return guarded([&]() -> int {
+        if (!h || !h->s) throw ApiError(AMGMPCG_INVALID_ARG, "handle is NULL");
+        if (!lk_dev) throw ApiError(AMGMPCG_INVALID_ARG, "output is NULL");
+        if (h->s->dim != 3) throw ApiError(AMGMPCG_INVALID_ARG, "the learned direction needs a 3D problem");
+        h->s->log_kappa(lk_dev);
+        return AMGMPCG_OK;
+    });
+}
+
+int amgmpcg_make_pairs(amgmpcg_handle* h, const double* b_dev, const double* xs_dev, const int32_t* ks,
+                       int32_t nk, double* R_dev, double* E_dev) {
+    return guarded([&]() -> int {
+        if (!h || !h->s) throw ApiError(AMGMPCG_INVALID_ARG, "handle is NULL");
+        if (!b_dev || !xs_dev || !ks || !R_dev || !E_dev) throw ApiError(AMGMPCG_INVALID_ARG, "NULL argument");
+        if (nk < 1) throw ApiError(AMGMPCG_INVALID_ARG, "nk must be >= 1");
+        for (int i = 0; i < nk; ++i)
+            if (ks[i] < 0) throw ApiError(AMGMPCG_INVALID_ARG, "iteration counts must be >= 0");
+        h->s->make_pairs(b_dev, xs_dev, ks, nk, R_dev, E_dev);
         return AMGMPCG_OK;
     });
 }

@@ -225,7 +225,7 @@ __device__ void solve_instance(const BInst<T>& I, const BatchParams& bp, BOut& o
         for (int idx = threadIdx.x; idx < N; idx += kBatchBlock) {
             const Idx<DIM> p = decomp<DIM>(idx, nf);
             T z[NB], pn[S];
-            fine_z<DIM, T, NB>(Ytop, nc, I.cL, idx, p, z);
+            fine_z<DIM, T, NB, 0>(Ytop, nc, I.cL, nullptr, false, idx, p, z);
 #pragma unroll
             for (int c = 0; c < S; ++c) pn[c] = c < NB ? z[c] : T(0);
             store_node<T, S>(I.P + (size_t)idx * S, pn);
@@ -284,7 +284,7 @@ __device__ void solve_instance(const BInst<T>& I, const BatchParams& bp, BOut& o
                 for (int idx = threadIdx.x; idx < N; idx += kBatchBlock) {
                     const Idx<DIM> p = decomp<DIM>(idx, nf);
                     T z[NB], q[S];
-                    fine_z<DIM, T, NB>(Ytop, nc, I.cL, idx, p, z);
+                    fine_z<DIM, T, NB, 0>(Ytop, nc, I.cL, nullptr, false, idx, p, z);
                     load_node<T, S>(I.Q + (size_t)idx * S, q);
 #pragma unroll
                     for (int a = 0; a < NB; ++a)
@@ -309,7 +309,7 @@ __device__ void solve_instance(const BInst<T>& I, const BatchParams& bp, BOut& o
 #pragma unroll
                 for (int c = 0; c < NB; ++c) xi += double(pk[c]) * sh.alpha[c];
                 I.x[idx] = xi;
-                fine_z<DIM, T, NB>(Ytop, nc, I.cL, idx, p, z);
+                fine_z<DIM, T, NB, 0>(Ytop, nc, I.cL, nullptr, false, idx, p, z);
 #pragma unroll
                 for (int c = 0; c < S; ++c) {
                     if (c < NB) {

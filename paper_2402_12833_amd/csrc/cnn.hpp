@@ -1,0 +1,364 @@
+// Learned search direction: a 3-level U-Net (16/32/64 channels, 3x3x3
+// convolutions, no bias, ReLU, 2x average pooling, nearest upsampling with
+// skip concatenation, 1x1 output) whose output is appended to the MPCG block
+// as one more direction, so the energy minimisation decides its coefficient.
+//
+// Tensors are channels-last bfloat16 on an S^3 grid (S a multiple of 4 that
+// holds the n^3 problem grid in its low corner): t[((z*S + y)*S + x)*C + c].
+// Convolutions are implicit GEMMs on the matrix cores: M = voxels (16 along
+// x per wavefront), N = output channels, K = taps x input channels, with
+// v_mfma_f32_16x16x16_bf16 and FP32 accumulation.  Weights: bfloat16 copies
+// [tap][Cout][Cin] of FP32 masters (Adam).  The backward data gradient is the
+// same forward kernel on the tap-flipped, channel-transposed weights; weight
+// gradients are GEMMs over voxels accumulated with FP32 atomics.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace amg {
+namespace cnn {
+
+using bf16 = unsigned short;
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// float -> bfloat16, round to nearest even
+__device__ __forceinline__ bf16 f2bf(float f) {
+    unsigned u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (bf16)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(bf16 h) { return __uint_as_float((unsigned)h << 16); }
+
+__host__ __device__ constexpr int tap_dz(int t) { return t / 9 - 1; }
+__host__ __device__ constexpr int tap_dy(int t) { return (t / 3) % 3 - 1; }
+__host__ __device__ constexpr int tap_dx(int t) { return t % 3 - 1; }
+
+constexpr int kCB = 256;   // threads per block of the CNN kernels (4 wavefronts)
+
+// ------------------------------------------------------------- convolution
+// Y[v, co] = sum_t sum_ci X[v + o_t, ci] W[t, co, ci]  (zero outside the grid)
+// KS = 3 (27 taps) or 1 (one tap).  OUT_F32: write FP32 (final layer) else
+// bfloat16, with ReLU when RELU.  One wavefront = 16 voxels along x and all
+// output channels; lane l supplies A[m = l%16][k = 4(l/16)+j] and
+// B[k][n = l%16] and receives D[m = 4(l/16)+j][n = l%16].
+template <int CIN, int COUT, int KS, int RELU, int OUT_F32>
+__global__ void __launch_bounds__(kCB) k_conv_fwd(const Ctl* __restrict__ ctl, const bf16* __restrict__ X,
+                                                  const bf16* __restrict__ W, void* __restrict__ Yv, int S) {
+    if (ctl && ctl->state != 0) return;
+    static_assert(CIN % 16 == 0 && COUT % 16 == 0, "channels must be multiples of 16");
+    constexpr int NT = COUT / 16, KC = CIN / 16, TAPS = KS == 3 ? 27 : 1;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int xtiles = (S + 15) >> 4;
+    const int tile = blockIdx.x * (kCB / 64) + wv;
+    if (tile >= S * S * xtiles) return;
+    const int row = tile / xtiles, xt = tile - row * xtiles;
+    const int y = row % S, z = row / S, x0 = xt * 16;
+    const int m = lane & 15, kq = lane >> 4;
+    f32x4 acc[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < TAPS; ++t) {
+        const int dz = KS == 3 ? tap_dz(t) : 0, dy = KS == 3 ? tap_dy(t) : 0, dx = KS == 3 ? tap_dx(t) : 0;
+        const int zz = z + dz, yy = y + dy, xx = x0 + m + dx;
+        const bool ok = zz >= 0 && zz < S && yy >= 0 && yy < S && xx >= 0 && xx < S;
+        const size_t base = ok ? ((size_t)(zz * S + yy) * S + xx) * CIN : 0;
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) {
+            bf16x4 a = bf16x4{0, 0, 0, 0};
+            if (ok) a = *reinterpret_cast<const bf16x4*>(X + base + kc * 16 + kq * 4);
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const bf16x4 b = *reinterpret_cast<const bf16x4*>(
+                    W + ((size_t)(t * COUT + nt * 16 + m) * CIN + kc * 16 + kq * 4));
+                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nt], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int x = x0 + kq * 4 + j;
+            if (x >= S) continue;
+            float v = acc[nt][j];
+            if (RELU) v = v > 0.f ? v : 0.f;
+            const size_t o = ((size_t)(z * S + y) * S + x) * COUT + nt * 16 + m;
+            if (OUT_F32) static_cast<float*>(Yv)[o] = v;
+            else static_cast<bf16*>(Yv)[o] = f2bf(v);
+        }
+    }
+}
+
+// dW[t, co, ci] += sum over voxels of dY[v, co] X[v + o_t, ci]; block = one
+// tap and a range of 16-voxel x-tiles; lane l supplies A[m = co][k = voxel
+// 4(l/16)+j] and B[k][n = ci]; each wavefront adds its sums with FP32 atomics.
+template <int CIN, int COUT, int KS>
+__global__ void __launch_bounds__(kCB) k_conv_wgrad(const Ctl* __restrict__ ctl, const bf16* __restrict__ dY,
+                                                    const bf16* __restrict__ X, float* __restrict__ dW, int S,
+                                                    int tiles_per_block) {
+    if (ctl && ctl->state != 0) return;
+    constexpr int MT = COUT / 16, NTI = CIN / 16, TAPS = KS == 3 ? 27 : 1;
+    const int t = blockIdx.y;
+    if (t >= TAPS) return;
+    const int dz = KS == 3 ? tap_dz(t) : 0, dy = KS == 3 ? tap_dy(t) : 0, dx = KS == 3 ? tap_dx(t) : 0;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int m = lane & 15, kq = lane >> 4;
+    const int xtiles = (S + 15) >> 4;
+    const int ntiles = S * S * xtiles;
+    f32x4 acc[MT][NTI];
+#pragma unroll
+    for (int a = 0; a < MT; ++a)
+#pragma unroll
+        for (int b = 0; b < NTI; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int t0 = blockIdx.x * tiles_per_block;
+    const int t1 = min(ntiles, t0 + tiles_per_block);
+    for (int tile = t0 + wv; tile < t1; tile += kCB / 64) {
+        const int row = tile / xtiles, xt = tile - row * xtiles;
+        const int y = row % S, z = row / S, x0 = xt * 16;
+        const int zz = z + dz, yy = y + dy;
+        const bool rowok = zz >= 0 && zz < S && yy >= 0 && yy < S;
+        bf16x4 af[MT], bfr[NTI];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int x = x0 + kq * 4 + j;          // the voxel of k = 4 kq + j
+            const bool vin = x < S;
+            const size_t vo = ((size_t)(z * S + y) * S + (vin ? x : 0)) * COUT;
+#pragma unroll
+            for (int a = 0; a < MT; ++a) af[a][j] = vin ? (short)dY[vo + a * 16 + m] : (short)0;
+            const int xs = x + dx;
+            const bool xin = vin && rowok && xs >= 0 && xs < S;
+            const size_t xo = xin ? ((size_t)(zz * S + yy) * S + xs) * CIN : 0;
+#pragma unroll
+            for (int b = 0; b < NTI; ++b) bfr[b][j] = xin ? (short)X[xo + b * 16 + m] : (short)0;
+        }
+#pragma unroll
+        for (int a = 0; a < MT; ++a)
+#pragma unroll
+            for (int b = 0; b < NTI; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[a], bfr[b], acc[a][b], 0, 0, 0);
+    }
+    // D[m = co (4 kq + j)][n = ci (lane % 16)]
+#pragma unroll
+    for (int a = 0; a < MT; ++a)
+#pragma unroll
+        for (int b = 0; b < NTI; ++b)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int co = a * 16 + kq * 4 + j, ci = b * 16 + m;
+                atomicAdd(&dW[((size_t)t * COUT + co) * CIN + ci], acc[a][b][j]);
+            }
+}
+
+// --------------------------------------------------------------- elementwise
+
+// Network input: channel 0 = r * scale (scale = 1 / rms(r)), channel 1 =
+// normalised log kappa (or 0), channels 2..15 = 0; voxels outside n^3 = 0.
+__global__ void __launch_bounds__(kCB) k_pack_input(const Ctl* __restrict__ ctl, const double* __restrict__ r,
+                                                    const double* __restrict__ scale, const bf16* __restrict__ lk,
+                                                    bf16* __restrict__ X, int n, int S) {
+    if (ctl && ctl->state != 0) return;
+    const int v = blockIdx.x * kCB + threadIdx.x;
+    if (v >= S * S * S) return;
+    const int x = v % S, y = (v / S) % S, z = v / (S * S);
+    const bool in = x < n && y < n && z < n;
+    const int idx = x + n * (y + n * z);
+    const float s = (float)(*scale);
+    bf16* o = X + (size_t)v * 16;
+    o[0] = in ? f2bf((float)r[idx] * s) : (bf16)0;
+    o[1] = (in && lk) ? lk[idx] : (bf16)0;
+#pragma unroll
+    for (int c = 2; c < 16; ++c) o[c] = 0;
+}
+
+// Sum of squares of v (N values): per-block partials part[b], fixed order.
+__global__ void __launch_bounds__(kCB) k_sumsq(const Ctl* __restrict__ ctl, const double* __restrict__ v, int N,
+                                               double* __restrict__ part) {
+    if (ctl && ctl->state != 0) return;
+    double s[1] = {0.0};
+    for (int i = blockIdx.x * kCB + threadIdx.x; i < N; i += gridDim.x * kCB) s[0] += v[i] * v[i];
+    block_sum_store<1>(s, part, gridDim.x, blockIdx.x);
+}
+
+// mode 0: out = 1 / rms (1 if the values are all zero), rms^2 = sum / N;
+// mode 1: out = sum of the partials (the loss).
+__global__ void __launch_bounds__(kRedBlock) k_finish_sum(const Ctl* __restrict__ ctl,
+                                                         const double* __restrict__ part, int nblk, int N, int mode,
+                                                         double* __restrict__ out) {
+    if (ctl && ctl->state != 0) return;
+    __shared__ double res[1];
+    reduce_partials<1>(part, nblk, res);
+    if (threadIdx.x == 0) {
+        if (mode == 0) {
+            const double rms = sqrt(res[0] / N);
+            *out = rms > 0.0 ? 1.0 / rms : 1.0;
+        } else {
+            *out = res[0];
+        }
+    }
+}
+
+// 2x2x2 average pooling, S -> S/2 (C channels).
+__global__ void __launch_bounds__(kCB) k_avgpool(const Ctl* __restrict__ ctl, const bf16* __restrict__ X,
+                                                 bf16* __restrict__ Y, int Sc, int C) {
+    if (ctl && ctl->state != 0) return;
+    const size_t e = (size_t)blockIdx.x * kCB + threadIdx.x;
+    if (e >= (size_t)Sc * Sc * Sc * C) return;
+    const int c = e % C;
+    const size_t v = e / C;
+    const int x = v % Sc, y = (v / Sc) % Sc, z = v / ((size_t)Sc * Sc);
+    const int Sf = 2 * Sc;
+    float s = 0.f;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int d = 0; d < 2; ++d)
+                s += bf2f(X[(((size_t)(2 * z + a) * Sf + 2 * y + b) * Sf + 2 * x + d) * C + c]);
+    Y[e] = f2bf(s * 0.125f);
+}
+
+// Y (S^3, C1 + C2 channels) = [upsample2(A) (C1 channels, grid S/2) | B (C2)].
+__global__ void __launch_bounds__(kCB) k_upcat(const Ctl* __restrict__ ctl, const bf16* __restrict__ A,
+                                               const bf16* __restrict__ B, bf16* __restrict__ Y, int S, int C1,
+                                               int C2) {
+    if (ctl && ctl->state != 0) return;
+    const int C = C1 + C2;
+    const size_t e = (size_t)blockIdx.x * kCB + threadIdx.x;
+    if (e >= (size_t)S * S * S * C) return;
+    const int c = e % C;
+    const size_t v = e / C;
+    if (c < C1) {
+        const int x = v % S, y = (v / S) % S, z = v / ((size_t)S * S);
+        const int Sc = S / 2;
+        Y[e] = A[(((size_t)(z / 2) * Sc + y / 2) * Sc + x / 2) * C1 + c];
+    } else {
+        Y[e] = B[v * C2 + (c - C1)];
+    }
+}
+
+// dPre = dPost * (post > 0)
+__global__ void __launch_bounds__(kCB) k_relu_mask(const Ctl* __restrict__ ctl, const bf16* __restrict__ dpost,
+                                                   const bf16* __restrict__ post, bf16* __restrict__ dpre,
+                                                   size_t count) {
+    if (ctl && ctl->state != 0) return;
+    const size_t e = (size_t)blockIdx.x * kCB + threadIdx.x;
+    if (e >= count) return;
+    dpre[e] = (bf2f(post[e]) > 0.f) ? dpost[e] : (bf16)0;
+}
+
+// dA (S/2 grid, C1 channels) = sum over the 8 children of dY[:, c0 + c]
+// (adjoint of nearest upsampling on the first C1 of C channels).
+__global__ void __launch_bounds__(kCB) k_upsample_bwd(const Ctl* __restrict__ ctl, const bf16* __restrict__ dY,
+                                                      bf16* __restrict__ dA, int Sc, int C1, int C) {
+    if (ctl && ctl->state != 0) return;
+    const size_t e = (size_t)blockIdx.x * kCB + threadIdx.x;
+    if (e >= (size_t)Sc * Sc * Sc * C1) return;
+    const int c = e % C1;
+    const size_t v = e / C1;
+    const int x = v % Sc, y = (v / Sc) % Sc, z = v / ((size_t)Sc * Sc);
+    const int Sf = 2 * Sc;
+    float s = 0.f;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int d = 0; d < 2; ++d)
+                s += bf2f(dY[(((size_t)(2 * z + a) * Sf + 2 * y + b) * Sf + 2 * x + d) * C + c]);
+    dA[e] = f2bf(s);
+}
+
+// dE (S^3, C2 channels) = dY[:, C1 + c] (skip part of a concat gradient)
+// + upsample2(dP) / 8 (adjoint of average pooling).
+__global__ void __launch_bounds__(kCB) k_skip_pool_bwd(const Ctl* __restrict__ ctl, const bf16* __restrict__ dY,
+                                                       const bf16* __restrict__ dP, bf16* __restrict__ dE, int S,
+                                                       int C1, int C2) {
+    if (ctl && ctl->state != 0) return;
+    const size_t e = (size_t)blockIdx.x * kCB + threadIdx.x;
+    if (e >= (size_t)S * S * S * C2) return;
+    const int c = e % C2;
+    const size_t v = e / C2;
+    const int x = v % S, y = (v / S) % S, z = v / ((size_t)S * S);
+    const int Sc = S / 2;
+    const float a = bf2f(dY[v * (C1 + C2) + C1 + c]);
+    const float p = bf2f(dP[(((size_t)(z / 2) * Sc + y / 2) * Sc + x / 2) * C2 + c]) * 0.125f;
+    dE[e] = f2bf(a + p);
+}
+
+// MSE loss over the n^3 voxels against target e * escale; writes the FP32
+// loss partials and the bfloat16 gradient (16 channels, channel 0).
+__global__ void __launch_bounds__(kCB) k_mse_grad(const float* __restrict__ out, const double* __restrict__ e,
+                                                  const double* __restrict__ escale, bf16* __restrict__ G, int n,
+                                                  int S, double* __restrict__ part) {
+    const int v = blockIdx.x * kCB + threadIdx.x;
+    double l = 0.0;
+    if (v < S * S * S) {
+        const int x = v % S, y = (v / S) % S, z = v / (S * S);
+        const bool in = x < n && y < n && z < n;
+        float g = 0.f;
+        if (in) {
+            const double diff = (double)out[(size_t)v * 16] - e[x + n * (y + n * z)] * (*escale);
+            const double cnt = (double)n * n * n;
+            l = diff * diff / cnt;
+            g = (float)(2.0 * diff / cnt);
+        }
+        bf16* o = G + (size_t)v * 16;
+        o[0] = f2bf(g);
+#pragma unroll
+        for (int c = 1; c < 16; ++c) o[c] = 0;
+    }
+    double acc[1] = {l};
+    block_sum_store<1>(acc, part, gridDim.x, blockIdx.x);
+}
+
+// The network output (channel 0 of the FP32 final layer) as an MPCG column
+// (bulk type T, n^3 values); flag = 1 if any value is not finite.
+template <typename T>
+__global__ void __launch_bounds__(kCB) k_unpack_output(const Ctl* __restrict__ ctl, const float* __restrict__ out,
+                                                       T* __restrict__ d, int n, int S, int* __restrict__ flag) {
+    if (ctl && ctl->state != 0) return;
+    const int idx = blockIdx.x * kCB + threadIdx.x;
+    if (idx >= n * n * n) return;
+    const int x = idx % n, y = (idx / n) % n, z = idx / (n * n);
+    const float v = out[(((size_t)z * S + y) * S + x) * 16];
+    if (!isfinite(v)) atomicOr(flag, 1);
+    d[idx] = T(v);
+}
+
+__global__ void k_clear_flag(const Ctl* __restrict__ ctl, int* flag) {
+    if (ctl && ctl->state != 0) return;
+    if (threadIdx.x == 0) *flag = 0;
+}
+
+// Adam on FP32 masters; refreshes the bfloat16 forward copy [t][co][ci] and
+// the tap-flipped, transposed copy [26 - t][ci][co] used by the data gradient.
+__global__ void __launch_bounds__(kCB) k_adam(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
+                                              const float* __restrict__ g, bf16* __restrict__ wb,
+                                              bf16* __restrict__ wt, int taps, int cout, int cin, float lr,
+                                              float b1, float b2, float eps, float c1, float c2) {
+    const int e = blockIdx.x * kCB + threadIdx.x;
+    if (e >= taps * cout * cin) return;
+    const float gi = g[e];
+    const float mi = b1 * m[e] + (1.f - b1) * gi;
+    const float vi = b2 * v[e] + (1.f - b2) * gi * gi;
+    m[e] = mi;
+    v[e] = vi;
+    const float wi = w[e] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    w[e] = wi;
+    const bf16 h = f2bf(wi);
+    wb[e] = h;
+    const int ci = e % cin, co = (e / cin) % cout, t = e / (cin * cout);
+    wt[((size_t)(taps - 1 - t) * cin + ci) * cout + co] = h;
+}
+
+// bfloat16 copies of FP32 weights (forward and flipped-transposed layouts).
+__global__ void __launch_bounds__(kCB) k_weights_bf16(const float* __restrict__ w, bf16* __restrict__ wb,
+                                                      bf16* __restrict__ wt, int taps, int cout, int cin) {
+    const int e = blockIdx.x * kCB + threadIdx.x;
+    if (e >= taps * cout * cin) return;
+    const bf16 h = f2bf(w[e]);
+    wb[e] = h;
+    const int ci = e % cin, co = (e / cin) % cout, t = e / (cin * cout);
+    wt[((size_t)(taps - 1 - t) * cin + ci) * cout + co] = h;
+}
+
+}  // namespace cnn
+}  // namespace amg

@@ -347,23 +347,28 @@ __device__ __forceinline__ void interp_block(const T* __restrict__ Y, int nc, co
     }
 }
 
-// Level corrections at one fine node: z[c] for c < NB-1 interpolated from the
-// node-major level-(L-1) block Y (NB-1 columns, stride even_up(NB-1)),
-// z[NB-1] = cL (the finest smoother output).
-template <int DIM, typename T, int NB>
-__device__ __forceinline__ void fine_z(const T* __restrict__ Y, int nc, const T* __restrict__ cL, int idx,
-                                       const Idx<DIM>& p, T (&z)[NB]) {
-    if (NB > 1) {
-        constexpr int SY = even_up(NB > 1 ? NB - 1 : 1);
+// Directions at one fine node: the NB - NE level corrections, z[c] for
+// c < NB-NE-1 interpolated from the node-major level-(L-1) block Y (stride
+// even_up(NB-NE-1)) and z[NB-NE-1] = cL (the finest smoother output); with
+// NE = 1 the learned direction z[NB-1] = dl[idx] (0 when dzero: a non-finite
+// network output gives a zero column).
+template <int DIM, typename T, int NB, int NE>
+__device__ __forceinline__ void fine_z(const T* __restrict__ Y, int nc, const T* __restrict__ cL,
+                                       const T* __restrict__ dl, bool dzero, int idx, const Idx<DIM>& p,
+                                       T (&z)[NB]) {
+    constexpr int NL = NB - NE;
+    if (NL > 1) {
+        constexpr int SY = even_up(NL > 1 ? NL - 1 : 1);
         const XPar px = xparents(p.i, nc);
         const Par py = parents(p.j, nc);
         const Par pz = DIM == 3 ? parents(p.k, nc) : Par{0, 0, 1.f, 0.f, 1};
         T zy[SY];
         interp_block<DIM, T, SY>(Y, nc, px, py, pz, zy);
 #pragma unroll
-        for (int c = 0; c < NB - 1; ++c) z[c] = zy[c];
+        for (int c = 0; c < NL - 1; ++c) z[c] = zy[c];
     }
-    z[NB - 1] = cL[idx];
+    z[NL - 1] = cL[idx];
+    if (NE) z[NB - 1] = dzero ? T(0) : dl[idx];
 }
 
 // (A P)_idx for all columns of a node-major block on the finest level.
@@ -450,6 +455,20 @@ __global__ void __launch_bounds__(kBlock) k_refresh(const Ctl* __restrict__ ctl,
         v[0] += ri * ri;
     }
     block_sum_store<1>(v, part, gridDim.x, lb);
+}
+
+// Training pair of the learned direction: r = b - A x (FP64) and e = xs - x.
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_pair(Rows R, FineOp<double> op, const double* __restrict__ b,
+                                                 const double* __restrict__ xs, const double* __restrict__ x,
+                                                 double* __restrict__ r, double* __restrict__ e) {
+    ROW_LOOP(R, blockIdx.x) {
+        Idx<DIM> p;
+        int idx;
+        if (!row_item<DIM>(R, w_, p, idx)) continue;
+        r[idx] = b[idx] - fine_apply<DIM, double>(op, x, idx, p);
+        e[idx] = xs[idx] - x[idx];
+    }
 }
 
 // r -= Q alpha (pointwise, FP64 r; Q node-major), partial ||r||^2.
@@ -729,11 +748,13 @@ __global__ void __launch_bounds__(kTailBlock) k_prolong_head(const Ctl* __restri
 }
 
 // W = Q_k^T Z_{k+1} partial sums (NB x NB, entry a*NB+c = Q column a . z^c).
-template <int DIM, typename T, int NB>
+template <int DIM, typename T, int NB, int NE>
 __global__ void __launch_bounds__(kBlock) k_fine_W(const Ctl* __restrict__ ctl, Rows R, const T* __restrict__ Y,
-                                                   int nc, const T* __restrict__ cL, const T* __restrict__ Q,
+                                                   int nc, const T* __restrict__ cL, const T* __restrict__ dl,
+                                                   const int* __restrict__ dflag, const T* __restrict__ Q,
                                                    double* __restrict__ part) {
     if (ctl->state != 0) return;
+    const bool dzero = NE && *dflag != 0;
     constexpr int S = even_up(NB);
     const int lb = xcd_block(gridDim.x);
     double w[NB * NB];
@@ -744,7 +765,7 @@ __global__ void __launch_bounds__(kBlock) k_fine_W(const Ctl* __restrict__ ctl, 
         int idx;
         if (!row_item<DIM>(R, w_, p, idx)) continue;
         T z[NB];
-        fine_z<DIM, T, NB>(Y, nc, cL, idx, p, z);
+        fine_z<DIM, T, NB, NE>(Y, nc, cL, dl, dzero, idx, p, z);
         T q[S];
         load_node<T, S>(Q + (size_t)idx * S, q);
 #pragma unroll
@@ -760,13 +781,15 @@ __global__ void __launch_bounds__(kBlock) k_fine_W(const Ctl* __restrict__ ctl, 
 // x += P_k alpha_k (deferred update of Algorithm 1); then, unless stopping,
 // P_{k+1} = Z_{k+1} - P_k beta in place (Z recomputed from the coarse block).
 // init = 1: P_0 = Z_0 only.
-template <int DIM, typename T, int NB>
+template <int DIM, typename T, int NB, int NE>
 __global__ void __launch_bounds__(kBlock) k_update_xP(const Ctl* __restrict__ ctl, Rows R, const T* __restrict__ Y,
-                                                      int nc, const T* __restrict__ cL, T* __restrict__ P,
+                                                      int nc, const T* __restrict__ cL, const T* __restrict__ dl,
+                                                      const int* __restrict__ dflag, T* __restrict__ P,
                                                       double* __restrict__ x, const double* __restrict__ alpha,
                                                       const double* __restrict__ beta, int init) {
     const int state = ctl->state;
     if (state == 2 || (init && state != 0)) return;
+    const bool dzero = NE && *dflag != 0;
     constexpr int S = even_up(NB);
     const int lb = xcd_block(gridDim.x);
     __shared__ double sab[NB + NB * NB];
@@ -788,7 +811,7 @@ __global__ void __launch_bounds__(kBlock) k_update_xP(const Ctl* __restrict__ ct
             if (state != 0) continue;
         }
         T z[NB];
-        fine_z<DIM, T, NB>(Y, nc, cL, idx, p, z);
+        fine_z<DIM, T, NB, NE>(Y, nc, cL, dl, dzero, idx, p, z);
         T pn[S];
 #pragma unroll
         for (int c = 0; c < NB; ++c) {
@@ -838,15 +861,17 @@ __global__ void __launch_bounds__(kBlock) k_spmm_gram(const Ctl* __restrict__ ct
 }
 
 // Explicit Z (widened to double, column-major), for the mg_block entry point.
-template <int DIM, typename T, int NB>
+template <int DIM, typename T, int NB, int NE>
 __global__ void __launch_bounds__(kBlock) k_write_Z(Rows R, int N, const T* __restrict__ Y, int nc,
-                                                    const T* __restrict__ cL, double* __restrict__ Z) {
+                                                    const T* __restrict__ cL, const T* __restrict__ dl,
+                                                    const int* __restrict__ dflag, double* __restrict__ Z) {
+    const bool dzero = NE && *dflag != 0;
     ROW_LOOP(R, blockIdx.x) {
         Idx<DIM> p;
         int idx;
         if (!row_item<DIM>(R, w_, p, idx)) continue;
         T z[NB];
-        fine_z<DIM, T, NB>(Y, nc, cL, idx, p, z);
+        fine_z<DIM, T, NB, NE>(Y, nc, cL, dl, dzero, idx, p, z);
 #pragma unroll
         for (int c = 0; c < NB; ++c) Z[(size_t)c * N + idx] = double(z[c]);
     }

@@ -98,3 +98,30 @@ def test_batched_switched_off(lib):
     kap = np.ones(33 * 33)
     bad = (B.Grid * 1)(B.Grid(2, 31, 3, kap.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
     assert lib.amgmpcg_setup_batched(1, bad, ctypes.byref(amg.default_options()), None, ctypes.byref(h)) == B.INVALID_ARG
+
+
+def test_cnn_weight_count_matches_the_oracle_layers(lib):
+    from oracle import cnn
+    total = sum((27 if k == 3 else 1) * cin * cout for _, k, cin, cout in cnn.LAYERS)
+    assert amg.cnn_weight_count() == total
+    assert [(n, cin, cout) for n, _, cin, cout in B.CNN_LAYERS] == [(n, cin, cout) for n, _, cin, cout in cnn.LAYERS]
+
+
+def test_cnn_argument_validation(lib):
+    h = ctypes.c_void_p()
+    assert lib.amgmpcg_cnn_create(0, 0, None, ctypes.byref(h)) == B.INVALID_ARG and not h.value
+    assert lib.amgmpcg_cnn_create(1001, 0, None, ctypes.byref(h)) == B.INVALID_ARG and not h.value
+    assert lib.amgmpcg_cnn_create(15, 0, None, None) == B.INVALID_ARG
+    w = np.zeros(amg.cnn_weight_count(), dtype=np.float32)
+    fp = w.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    assert lib.amgmpcg_cnn_set_weights(None, fp, w.size) == B.INVALID_ARG
+    assert lib.amgmpcg_cnn_get_weights(None, fp, w.size) == B.INVALID_ARG
+    assert lib.amgmpcg_cnn_forward(None, None, None, None) == B.INVALID_ARG
+    loss = ctypes.c_double()
+    assert lib.amgmpcg_cnn_train_step(None, None, None, None, 1e-3, ctypes.byref(loss)) == B.INVALID_ARG
+    assert lib.amgmpcg_attach_cnn(None, None) == B.INVALID_ARG
+    assert lib.amgmpcg_log_kappa(None, None) == B.INVALID_ARG
+    assert lib.amgmpcg_residual(None, None, None, None) == B.INVALID_ARG
+    ks = (ctypes.c_int32 * 1)(0)
+    assert lib.amgmpcg_make_pairs(None, None, None, ks, 1, None, None) == B.INVALID_ARG
+    lib.amgmpcg_cnn_destroy(None)

@@ -1,0 +1,349 @@
+"""GPU parity of the learned direction (U-Net) against the FP64 oracle.
+
+The network runs in bfloat16 storage with FP32 accumulation on the matrix
+cores; the oracle (oracle/cnn.py) computes in FP64 and rounds to bfloat16
+where the GPU stores a tensor, on identical bfloat16 weights and inputs.
+
+Per layer (identical bfloat16 operands, the kernels' own parity): forward
+and data-gradient outputs agree element by element to one bfloat16 ulp,
+with at most 0.1 % of the elements differing (a different summation order
+moves an exact value across a rounding boundary with probability about
+2^-24 / 2^-9); weight gradients (FP32 sums) within 1e-4 relative.
+
+End to end (whole network): the forward output within 1e-2 and each weight
+gradient within 0.1 normwise relative with cosine >= 0.99.  The looser
+gradient bar is derived, not chosen: a single rounding flip in an early
+activation changes its element by 2^-8 relative, which moves later exact
+sums across further boundaries, and the flips cascade through the eleven
+layers and back.  Re-running the FP64 oracle with FP32 accumulation in the
+convolutions (CPU only) differs from the FP64 oracle by up to 5e-2 in the
+weight gradients on the n = 19 case below, by the same cascade.  The grids
+cover one 16-voxel x tile (S = 16), a ragged second tile (S = 20) and two
+full tiles (S = 32).
+
+The solver plumbing of the extra column is checked exactly where the column
+is exactly known (zero weights, non-finite output: the solve must equal the
+plain solve), and against the oracle's MPCG with the oracle network as its
+extra direction otherwise (iteration counts within one).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import cnn, hierarchy, mpcg
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2402_12833_amd as amg  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    amg.load()
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / (nb if nb > 0 else 1.0))
+
+
+def lk_dev(lk):
+    return torch.as_tensor(np.asarray(lk, dtype=np.float32), device="cuda").to(torch.bfloat16)
+
+
+def inputs(n, seed):
+    rng = np.random.default_rng(seed)
+    r = rng.uniform(-1.0, 1.0, n ** 3)
+    lk = cnn.round_bf16(rng.standard_normal(n ** 3))
+    e = rng.uniform(-1.0, 1.0, n ** 3)
+    return r, lk, e
+
+
+def make_net(n, seed):
+    Wd = cnn.init_weights(seed)
+    net = amg.Network(n, seed=seed)
+    net.set_weights(amg.Network.join(Wd))
+    return Wd, net
+
+
+def oracle_forward(Wd, r, lk, n):
+    S = (n + 3) // 4 * 4
+    x0 = cnn.pack_input(r, None, n, S)
+    if lk is not None:
+        x0[:n, :n, :n, 1] = np.asarray(lk).reshape(n, n, n)
+    out, cache = cnn.forward(Wd, x0)
+    return out, cache, S
+
+
+SIZES = [13, 19, 30]
+
+
+def test_weight_layout_roundtrip():
+    Wd, net = make_net(9, 5)
+    back = amg.Network.split(net.get_weights())
+    for name, *_ in amg.CNN_LAYERS:
+        assert np.array_equal(back[name], Wd[name].astype(np.float32)), name
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_forward_matches_oracle(n):
+    Wd, net = make_net(n, 21 + n)
+    r, lk, _ = inputs(n, 100 + n)
+    out, _, _ = oracle_forward(Wd, r, lk, n)
+    ref = out[:n, :n, :n].reshape(-1)
+    d, code = net.forward(dev(r), lk_dev(lk))
+    assert code == amg.OK
+    err = rel(host(d), ref)
+    print(f"n={n} forward rel err {err:.2e}")
+    assert err <= 1e-2
+
+
+def test_forward_without_kappa_channel():
+    n = 13
+    Wd, net = make_net(n, 3)
+    r, _, _ = inputs(n, 7)
+    out, _, _ = oracle_forward(Wd, r, None, n)
+    d, _ = net.forward(dev(r), None)
+    assert rel(host(d), out[:n, :n, :n].reshape(-1)) <= 1e-2
+
+
+def test_forward_is_scale_free_in_r():
+    # the input channel is r / rms(r): N(c r) = N(r) for c > 0 (up to the
+    # rounding of the scaled product)
+    n = 13
+    _, net = make_net(n, 4)
+    r, lk, _ = inputs(n, 8)
+    d1, _ = net.forward(dev(r), lk_dev(lk))
+    d2, _ = net.forward(dev(4.0 * r), lk_dev(lk))
+    assert torch.equal(d1, d2)
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_gradients_match_oracle(n):
+    Wd, net = make_net(n, 31 + n)
+    r, lk, e = inputs(n, 200 + n)
+    out, cache, S = oracle_forward(Wd, r, lk, n)
+    ee = e.reshape(n, n, n)
+    tgt = np.zeros((S, S, S))
+    tgt[:n, :n, :n] = ee / np.sqrt(np.mean(ee ** 2))
+    mask = np.zeros((S, S, S))
+    mask[:n, :n, :n] = 1.0
+    loss, dout = cnn.mse_loss(out, tgt, mask)
+    g = cnn.backward(Wd, cache, dout)
+    loss_gpu = net.gradients(dev(r), dev(e), lk_dev(lk))
+    assert abs(loss_gpu - loss) <= 1e-2 * loss
+    G = amg.Network.split(net.get_gradients())
+    errs = {name: rel(G[name], g[name]) for name, *_ in amg.CNN_LAYERS}
+    cos = {name: float(np.sum(G[name] * g[name]) / (np.linalg.norm(G[name]) * np.linalg.norm(g[name])))
+           for name, *_ in amg.CNN_LAYERS}
+    print(f"n={n} loss {loss:.4e} gpu {loss_gpu:.4e}; gradient errors " +
+          " ".join(f"{k}:{v:.1e}" for k, v in errs.items()))
+    for name, err in errs.items():
+        assert err <= 0.1 and cos[name] >= 0.99, (name, err, cos[name])
+
+
+def bf16_dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device="cuda").to(torch.bfloat16)
+
+
+def random_weights(seed, scale=0.1):
+    rng = np.random.default_rng(seed)
+    return {name: cnn.round_bf16(rng.standard_normal((cout, cin) if taps == 1 else (taps, cout, cin)) * scale)
+            for name, taps, cin, cout in amg.CNN_LAYERS}
+
+
+def assert_bf16_match(got, ref, what):
+    got = np.asarray(got, dtype=np.float64)
+    scale = float(np.max(np.abs(ref))) if ref.size else 0.0
+    diff = np.abs(got - ref)
+    tol = np.abs(ref) * 2.0 ** -7 + 1e-6 * scale
+    frac = float(np.mean(diff > 0))
+    print(f"{what}: {frac * 100:.4f}% of elements differ, max diff/tol {np.max(diff / np.maximum(tol, 1e-300)):.2f}")
+    assert np.all(diff <= tol), what
+    assert frac <= 1e-3, what
+
+
+@pytest.mark.parametrize("S", [12, 20])
+@pytest.mark.parametrize("layer", range(11))
+def test_layer_ops_match_oracle(layer, S):
+    name, taps, cin, cout = amg.CNN_LAYERS[layer]
+    Wd = random_weights(40 + layer)
+    net = amg.Network(7)
+    net.set_weights(amg.Network.join(Wd))
+    w = Wd[name]
+    rng = np.random.default_rng(1000 * layer + S)
+    X = cnn.round_bf16(rng.standard_normal((S, S, S, cin)))
+    dY = cnn.round_bf16(rng.standard_normal((S, S, S, cout)))
+    Xd, dYd = bf16_dev(X), bf16_dev(dY)
+    # op 0: forward
+    y = host(net.layer(layer, 0, Xd).float()).astype(np.float64)
+    if taps == 27:
+        assert_bf16_match(y, cnn.round_bf16(np.maximum(cnn.conv3(X, w), 0.0)), f"{name} forward S={S}")
+    else:
+        ref = cnn.conv1(X, w)
+        assert rel(y, ref) <= 1e-6
+    # op 1: data gradient
+    dx = host(net.layer(layer, 1, dYd).float()).astype(np.float64)
+    ref = cnn.conv3_dgrad(dY, w) if taps == 27 else dY @ w
+    assert_bf16_match(dx, cnn.round_bf16(ref), f"{name} dgrad S={S}")
+    # op 2: weight gradient
+    dw = host(net.layer(layer, 2, dYd, Xd)).astype(np.float64)
+    ref = cnn.conv3_wgrad(dY, X) if taps == 27 else (dY.reshape(-1, cout).T @ X.reshape(-1, cin))[None]
+    err = rel(dw, ref)
+    print(f"{name} wgrad S={S}: rel err {err:.2e}")
+    assert err <= 1e-4
+
+
+def test_adam_first_step():
+    # first Adam step from zero moments: w1 = w0 - lr g / (|g| + eps) (bias-corrected)
+    n = 13
+    Wd, net = make_net(n, 6)
+    r, lk, e = inputs(n, 9)
+    w0 = net.get_weights().astype(np.float64)
+    lr = 1e-3
+    net.train_step(dev(r), dev(e), lr, lk_dev(lk))
+    g = net.get_gradients().astype(np.float64)
+    w1 = net.get_weights().astype(np.float64)
+    expect = w0 - lr * g / (np.abs(g) + 1e-8)
+    assert np.max(np.abs(w1 - expect)) <= 1e-6
+
+
+def test_training_reduces_loss_on_a_pair():
+    n = 15
+    _, net = make_net(n, 7)
+    r, lk, e = inputs(n, 10)
+    rd, ed, ld = dev(r), dev(e), lk_dev(lk)
+    first = net.gradients(rd, ed, ld)
+    for _ in range(30):
+        net.train_step(rd, ed, 3e-3, ld)
+    last = net.gradients(rd, ed, ld)
+    print(f"loss {first:.4f} -> {last:.4f}")
+    assert last < 0.9 * first
+
+
+# ---------------------------------------------------------------- solver plumbing
+
+def small_problem(n=15, nl=3, kseed=3, bseed=5):
+    g = W.gaussian_field(n, 3, kseed, periodic=64)
+    kap = np.exp(2.0 * g)
+    b = W.rhs(n ** 3, bseed)
+    return kap, b
+
+
+def test_log_kappa_channel():
+    n = 15
+    kap, _ = small_problem(n)
+    s = amg.Solver(3, n, 3, kappa=kap)
+    lk = host(s.log_kappa().float()).astype(np.float64)
+    v = np.log(kap[1:-1, 1:-1, 1:-1]).reshape(-1)
+    expect = cnn.round_bf16((v - v.mean()) / v.std())
+    diff = np.abs(lk - expect)
+    ulp = np.abs(expect) * 2.0 ** -7 + 1e-30
+    assert np.all(diff <= ulp)
+    assert np.mean(diff == 0) >= 0.999
+    s0 = amg.Solver(3, n, 3)
+    assert not torch.any(s0.log_kappa().float() != 0)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_zero_network_equals_plain_solve(precision):
+    n = 15
+    kap, b = small_problem(n)
+    plain = amg.Solver(3, n, 3, kappa=kap, precision=precision)
+    xp, ip = plain.solve(dev(b), tol=1e-8)
+    net = amg.Network(n)
+    net.set_weights(np.zeros(amg.cnn_weight_count(), dtype=np.float32))
+    s = amg.Solver(3, n, 3, kappa=kap, precision=precision)
+    s.attach(net)
+    assert s.nb == 4
+    x, info = s.solve(dev(b), tol=1e-8)
+    assert info["status"] == amg.OK and info["nb"] == 4
+    assert info["iterations"] == ip["iterations"]
+    assert rel(host(x), host(xp)) <= (1e-10 if precision == 0 else 1e-6)
+
+
+def test_nonfinite_network_output_is_dropped():
+    n = 15
+    kap, b = small_problem(n)
+    plain = amg.Solver(3, n, 3, kappa=kap)
+    xp, ip = plain.solve(dev(b), tol=1e-8)
+    Wd = cnn.init_weights(11)
+    Wd["w11"] = Wd["w11"].copy()
+    Wd["w11"][0, :] = np.nan
+    net = amg.Network(n)
+    net.set_weights(amg.Network.join(Wd))
+    _, code = net.forward(dev(b), None)
+    assert code == amg.NONFINITE
+    s = amg.Solver(3, n, 3, kappa=kap)
+    s.attach(net)
+    x, info = s.solve(dev(b), tol=1e-8)
+    assert info["status"] == amg.OK
+    assert info["iterations"] == ip["iterations"]
+    assert rel(host(x), host(xp)) <= 1e-10
+
+
+def test_mg_block_learned_column_is_the_network_output():
+    n = 15
+    kap, b = small_problem(n)
+    Wd, net = make_net(n, 12)
+    s = amg.Solver(3, n, 3, kappa=kap)
+    s.attach(net)
+    r = dev(b)
+    Z = s.mg_block(r)
+    assert Z.shape[0] == 4
+    d, _ = net.forward(r, s.log_kappa())
+    assert torch.equal(Z[3], d)
+    s.attach(None)
+    assert s.nb == 3 and s.mg_block(r).shape[0] == 3
+
+
+def test_learned_solve_against_oracle_extra_direction():
+    n, nl = 15, 3
+    kap, b = small_problem(n)
+    Wd, net = make_net(n, 13)
+    s = amg.Solver(3, n, nl, kappa=kap)
+    s.attach(net)
+    lk = host(s.log_kappa().float()).astype(np.float64)
+    x, info = s.solve(dev(b), tol=1e-8)
+    assert info["status"] == amg.OK
+
+    def extra(r):
+        out, _, _ = oracle_forward(Wd, r, lk, n)
+        return out[:n, :n, :n].reshape(-1)
+
+    h = hierarchy.build(3, n, nl, kappa=kap)
+    res = mpcg.mpcg(h, b, tol=1e-8, extra=extra)
+    print(f"learned: gpu {info['iterations']} its, oracle {res.iterations} its")
+    assert res.status == mpcg.OK
+    assert abs(info["iterations"] - res.iterations) <= 1
+    rtrue = b - h.fine.A @ host(x)
+    assert np.linalg.norm(rtrue) <= 1e-8 * np.linalg.norm(b) * 1.01
+
+
+def test_make_pairs():
+    n, nl = 15, 3
+    kap, bh = small_problem(n)
+    s = amg.Solver(3, n, nl, kappa=kap)
+    b = dev(bh)
+    xs, info = s.solve(b, tol=1e-12)
+    assert info["status"] == amg.OK
+    R, E = s.make_pairs(b, xs, [0, 1, 3])
+    assert torch.equal(R[0], b) and torch.equal(E[0], xs)
+    h = hierarchy.build(3, n, nl, kappa=kap)
+    for row, k in ((1, 1), (2, 3)):
+        xk = mpcg.mpcg(h, bh, tol=0.0, maxit=k).x
+        assert rel(host(xs) - host(E[row]), xk) <= 1e-10
+        assert rel(host(R[row]), bh - h.fine.A @ xk) <= 1e-9
+    r1 = s.residual(b, xs - E[1])
+    assert rel(host(r1), host(R[1])) <= 1e-12

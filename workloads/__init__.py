@@ -64,13 +64,15 @@ def rhs(ndof: int, seed: int) -> np.ndarray:
 
 
 def gaussian_field(n: int, dim: int, seed: int, corr_len: float = 1.0 / 16.0,
-                   periodic: int = 256) -> np.ndarray:
+                   periodic: int = 256, workers: Optional[int] = None) -> np.ndarray:
     """Unit-variance stationary Gaussian field on the (n+2)^dim node grid.
 
     Covariance exp(-r^2 / (2 corr_len^2)) with node spacing h = 1/(n+1),
     synthesised by circulant embedding on a periodic ``periodic``^dim grid of
     the same spacing and cropped to the (n+2)^dim corner (boundary nodes
     included).  Returned with x fastest: shape (n+2,)*dim indexed [z, y, x].
+    ``workers``: use scipy's multi-threaded FFT (same field up to rounding;
+    for bulk generation of training fields).  Default: numpy's FFT.
     """
     m = periodic
     if m < n + 2:
@@ -83,21 +85,39 @@ def gaussian_field(n: int, dim: int, seed: int, corr_len: float = 1.0 / 16.0,
         shape[ax] = m
         r2 = r2 + (d1 ** 2).reshape(shape)
     cov = np.exp(-r2 / (2.0 * corr_len ** 2))
-    spec = np.real(np.fft.fftn(cov))
+    if workers is None:
+        fftn, ifftn = np.fft.fftn, np.fft.ifftn
+    else:
+        import scipy.fft as sfft
+        fftn = lambda a: sfft.fftn(a, workers=workers)
+        ifftn = lambda a: sfft.ifftn(a, workers=workers)
+    spec = np.real(fftn(cov))
     spec = np.maximum(spec, 0.0)
     rng = np.random.default_rng(seed)
     white = rng.standard_normal((m,) * dim)
-    g = np.real(np.fft.ifftn(np.sqrt(spec) * np.fft.fftn(white)))
+    g = np.real(ifftn(np.sqrt(spec) * fftn(white)))
     crop = tuple(slice(0, n + 2) for _ in range(dim))
     return np.ascontiguousarray(g[crop])
 
 
-def kappa_field(problem: GridProblem) -> Optional[np.ndarray]:
+def kappa_field(problem: GridProblem, workers: Optional[int] = None) -> Optional[np.ndarray]:
     """kappa = exp(2 g) on the (n+2)^dim node grid, or None for Poisson."""
     if problem.kappa_seed is None:
         return None
-    g = gaussian_field(problem.n, problem.dim, problem.kappa_seed, problem.corr_len)
+    g = gaussian_field(problem.n, problem.dim, problem.kappa_seed, problem.corr_len, workers=workers)
     return np.exp(2.0 * g)
+
+
+# Learned direction on the heterogeneous 127^3 problem: training kappa seeds
+# 10000 + j, held-out test seeds 900000 + i (rhs seed = kappa seed + 1).
+TRAIN_KAPPA_SEED0 = 10000
+TEST_KAPPA_SEED0 = 900000
+
+
+def diffusion_instance(kappa_seed: int, n: int = 127, nlevels: int = 6) -> GridProblem:
+    """A fresh heterogeneous instance from the distribution of diffusion3d_127."""
+    return GridProblem(f"diffusion3d_{n}_k{kappa_seed}", 3, n, nlevels, rhs_seed=kappa_seed + 1,
+                       kappa_seed=kappa_seed)
 
 
 def problem_rhs(problem: GridProblem) -> np.ndarray:
