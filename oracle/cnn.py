@@ -202,6 +202,25 @@ def mse_loss(out: np.ndarray, target: np.ndarray, mask: np.ndarray):
     return float((diff ** 2).sum() / n), 2.0 * diff / n
 
 
+def energy_loss(d: np.ndarray, r: np.ndarray, e: np.ndarray, Ad: np.ndarray):
+    """Energy loss of a search direction and its gradient in d.
+
+    For the error e with A e = r, min over c of ||e - c d||_A^2 equals
+    ||e||_A^2 L with L = 1 - (d.r)^2 / ((d.A d) (e.r)) (e.r = ||e||_A^2):
+    the fraction of the squared A-norm error left after the best step along
+    d alone (the energy minimisation of Sec. 2.2 restricted to one
+    direction).  Scale-free in d.
+    dL/dd = 2 (d.r) / ((d.A d)(e.r)) ((d.r)/(d.A d) A d - r).
+    All arrays are flat vectors over the n^3 nodes; Ad = A d.
+    """
+    a = float(d @ r)
+    c = float(d @ Ad)
+    E = float(e @ r)
+    loss = 1.0 - a * a / (c * E)
+    grad = (2.0 * a / (c * E)) * ((a / c) * Ad - r)
+    return loss, grad
+
+
 def pack_input(r: np.ndarray, logk: np.ndarray | None, n: int, S: int) -> np.ndarray:
     """Channels-last network input on the S^3 grid: channel 0 = r / rms(r),
     channel 1 = (log kappa - mean) / std (0 for Poisson); the n^3 grid sits in

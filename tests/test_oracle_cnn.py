@@ -99,3 +99,54 @@ def test_pack_input_normalises():
     x = cnn.pack_input(r, None, n, S)
     assert np.sqrt(np.mean(x[:n, :n, :n, 0] ** 2)) == pytest.approx(1.0)
     assert np.all(x[n:, :, :, 0] == 0) and np.all(x[..., 1:] == 0)
+
+
+def _spd(n, seed):
+    """A small SPD matrix (1D Laplacian plus a random diagonal)."""
+    rng = np.random.default_rng(seed)
+    A = 2.0 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)
+    return A + np.diag(rng.uniform(0.1, 1.0, n))
+
+
+def test_energy_loss_closed_forms():
+    n = 30
+    A = _spd(n, 1)
+    rng = np.random.default_rng(2)
+    e = rng.standard_normal(n)
+    r = A @ e
+    # the exact error as direction leaves nothing; any multiple too
+    L, g = cnn.energy_loss(e, r, e, A @ e)
+    assert L == pytest.approx(0.0, abs=1e-14)
+    assert np.linalg.norm(g) <= 1e-12 * np.linalg.norm(r)
+    L2, _ = cnn.energy_loss(-3.5 * e, r, e, A @ (-3.5 * e))
+    assert L2 == pytest.approx(0.0, abs=1e-14)
+    # an A-orthogonal direction removes nothing
+    d = rng.standard_normal(n)
+    d -= (d @ A @ e) / (e @ A @ e) * e
+    L3, _ = cnn.energy_loss(d, r, e, A @ d)
+    assert L3 == pytest.approx(1.0, abs=1e-12)
+    # the definition: min over c of ||e - c d||_A^2 / ||e||_A^2
+    d = rng.standard_normal(n)
+    cs = np.linspace(-5, 5, 200001)
+    best = min(((e - c * d) @ A @ (e - c * d)) for c in cs) / (e @ A @ e)
+    L4, g4 = cnn.energy_loss(d, r, e, A @ d)
+    assert L4 == pytest.approx(best, rel=1e-6)
+    # scale invariance: the gradient is orthogonal to d
+    assert abs(g4 @ d) <= 1e-12 * np.linalg.norm(g4) * np.linalg.norm(d)
+
+
+def test_energy_loss_gradient_finite_differences():
+    n = 25
+    A = _spd(n, 3)
+    rng = np.random.default_rng(4)
+    e = rng.standard_normal(n)
+    r = A @ e
+    d = rng.standard_normal(n)
+    _, g = cnn.energy_loss(d, r, e, A @ d)
+    for i in (0, 7, 24):
+        h = 1e-6
+        dp, dm = d.copy(), d.copy()
+        dp[i] += h
+        dm[i] -= h
+        fd = (cnn.energy_loss(dp, r, e, A @ dp)[0] - cnn.energy_loss(dm, r, e, A @ dm)[0]) / (2 * h)
+        assert g[i] == pytest.approx(fd, rel=1e-6, abs=1e-10)
