@@ -221,6 +221,28 @@ def energy_loss(d: np.ndarray, r: np.ndarray, e: np.ndarray, Ad: np.ndarray):
     return loss, grad
 
 
+def marginal_energy_loss(d: np.ndarray, r: np.ndarray, e: np.ndarray, A, Z: np.ndarray, tau: float):
+    """Energy loss of d on top of the block Z (columns: the level corrections
+    of r), and its gradient in d.
+
+    With Pi the A-orthogonal projection onto span(Z) (through the
+    pseudo-inverse of the Gram Z^T A Z, as in the step of Sec. 2.2), the best
+    combination of the columns of Z and d leaves the squared A-norm error
+    ||e - Pi e||_A^2 L, L = 1 - (d.r^)^2 / ((d.A d^)(e.r^)), where r^ = A (e -
+    Pi e) = r - A Z alpha (alpha = G^+ Z^T r) is the residual after the step
+    over Z and A d^ = A d - A Z G^+ Z^T A d.  This is ``energy_loss`` of d
+    with r and A d replaced by r^ and A d^.
+    """
+    from .mpcg import pinv_gram
+    Q = A @ Z
+    G = Z.T @ Q
+    Gp = pinv_gram(0.5 * (G + G.T), tau).Gplus
+    rhat = r - Q @ (Gp @ (Z.T @ r))
+    Ad = A @ d
+    Adhat = Ad - Q @ (Gp @ (Q.T @ d))
+    return energy_loss(d, rhat, e, Adhat)
+
+
 def pack_input(r: np.ndarray, logk: np.ndarray | None, n: int, S: int) -> np.ndarray:
     """Channels-last network input on the S^3 grid: channel 0 = r / rms(r),
     channel 1 = (log kappa - mean) / std (0 for Poisson); the n^3 grid sits in

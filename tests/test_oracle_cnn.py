@@ -150,3 +150,38 @@ def test_energy_loss_gradient_finite_differences():
         dm[i] -= h
         fd = (cnn.energy_loss(dp, r, e, A @ dp)[0] - cnn.energy_loss(dm, r, e, A @ dm)[0]) / (2 * h)
         assert g[i] == pytest.approx(fd, rel=1e-6, abs=1e-10)
+
+
+def test_marginal_energy_loss_brute_force():
+    # L = min over (c_Z, c_d) ||e - Z c_Z - c_d d||_A^2 / min over c_Z ||e - Z c_Z||_A^2,
+    # both minimisations by dense A-norm least squares (Cholesky of A)
+    n, m = 40, 4
+    A = _spd(n, 5)
+    rng = np.random.default_rng(6)
+    e = rng.standard_normal(n)
+    r = A @ e
+    Z = rng.standard_normal((n, m))
+    d = rng.standard_normal(n)
+    L, g = cnn.marginal_energy_loss(d, r, e, A, Z, tau=1e-12)
+    C = np.linalg.cholesky(A).T          # A = C^T C, ||v||_A = ||C v||
+    def left(B):
+        c, *_ = np.linalg.lstsq(C @ B, C @ e, rcond=None)
+        v = e - B @ c
+        return v @ A @ v
+    expect = left(np.column_stack([Z, d])) / left(Z)
+    assert L == pytest.approx(expect, rel=1e-9)
+    # a direction inside span(Z) adds nothing: the loss is one, the gradient zero
+    Lz, gz = cnn.marginal_energy_loss(Z @ rng.standard_normal(m) + 1e-300, r, e, A, Z, tau=1e-12)
+    assert Lz == pytest.approx(1.0, abs=1e-6)
+    # the gradient by central differences
+    for i in (0, 13, 39):
+        h = 1e-6
+        dp, dm = d.copy(), d.copy()
+        dp[i] += h
+        dm[i] -= h
+        fd = (cnn.marginal_energy_loss(dp, r, e, A, Z, 1e-12)[0] -
+              cnn.marginal_energy_loss(dm, r, e, A, Z, 1e-12)[0]) / (2 * h)
+        assert g[i] == pytest.approx(fd, rel=1e-5, abs=1e-10)
+    # a singular block (a repeated column) gives the same loss as the unique columns
+    Ls, _ = cnn.marginal_energy_loss(d, r, e, A, np.column_stack([Z, Z[:, :1]]), tau=1e-10)
+    assert Ls == pytest.approx(L, rel=1e-8)
