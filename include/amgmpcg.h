@@ -233,6 +233,27 @@ int amgmpcg_cnn_gradients(amgmpcg_cnn* net, const double* r_dev, const uint16_t*
 int amgmpcg_cnn_train_step(amgmpcg_cnn* net, const double* r_dev, const uint16_t* lk_dev,
                            const double* e_dev, float lr, double* loss);
 
+/* One training step on the energy loss of the direction d = N(r):
+ * marginal = 0: loss = 1 - (d.r)^2 / ((d.A d)(e.r)), the fraction of the
+ * squared A-norm error ||e||_A^2 = e.r left by the best step along d alone
+ * (A: the finest operator of handle h, whose grid must equal the network's;
+ * e.r uses A e = r).  marginal = 1: the same with r and A d replaced by their
+ * parts A-orthogonal to the level-correction block Z = MG(r) of h (r^ = r - A
+ * Z alpha after the energy-minimising step over Z, A d^ = A d - A Z G^+ Z^T A
+ * d): the fraction of the error left by the step over Z that stays after
+ * adding d (h must be FP64 with no network attached; its work vectors are
+ * overwritten).  Scale-free in d.  lr > 0 applies one Adam step, lr = 0 only
+ * computes the gradients.  Arguments as for amgmpcg_cnn_train_step. */
+int amgmpcg_cnn_energy_step(amgmpcg_cnn* net, amgmpcg_handle* h, const double* r_dev, const uint16_t* lk_dev,
+                            const double* e_dev, int32_t marginal, float lr, double* loss);
+
+/* The energy loss of amgmpcg_cnn_energy_step for a given direction d (no
+ * network) and its gradient dL/dd in FP64, on the default stream
+ * (synchronises).  d_dev, r_dev, e_dev, grad_dev: DEVICE, n^dim doubles;
+ * *loss: HOST.  marginal = 1 overwrites the handle's work vectors. */
+int amgmpcg_energy_grad(amgmpcg_handle* h, const double* d_dev, const double* r_dev, const double* e_dev,
+                        int32_t marginal, double* grad_dev, double* loss);
+
 /* Average time in ms of one inference (reps back-to-back forward passes
  * between two HIP events on the network's stream).  ms: HOST. */
 int amgmpcg_cnn_time_forward(amgmpcg_cnn* net, const double* r_dev, const uint16_t* lk_dev,

@@ -105,6 +105,10 @@ def load(path: str = LIB_PATH):
     lib.amgmpcg_cnn_train_step.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.c_float,
                                            POINTER(c_double)]
     lib.amgmpcg_cnn_time_forward.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, POINTER(c_double)]
+    lib.amgmpcg_cnn_energy_step.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int32,
+                                            ctypes.c_float, POINTER(c_double)]
+    lib.amgmpcg_energy_grad.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p,
+                                        POINTER(c_double)]
     lib.amgmpcg_cnn_layer.argtypes = [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p]
     lib.amgmpcg_cnn_destroy.argtypes = [c_void_p]
     lib.amgmpcg_cnn_destroy.restype = None
@@ -116,7 +120,7 @@ def load(path: str = LIB_PATH):
                  "amgmpcg_level_count", "amgmpcg_level_size", "amgmpcg_level_stencil", "amgmpcg_history",
                  "amgmpcg_residual", "amgmpcg_cnn_create", "amgmpcg_cnn_set_weights", "amgmpcg_cnn_get_weights",
                  "amgmpcg_cnn_get_gradients", "amgmpcg_cnn_forward", "amgmpcg_cnn_gradients",
-                 "amgmpcg_cnn_train_step", "amgmpcg_cnn_time_forward", "amgmpcg_cnn_layer", "amgmpcg_attach_cnn", "amgmpcg_log_kappa",
+                 "amgmpcg_cnn_train_step", "amgmpcg_cnn_time_forward", "amgmpcg_cnn_layer", "amgmpcg_cnn_energy_step", "amgmpcg_energy_grad", "amgmpcg_attach_cnn", "amgmpcg_log_kappa",
                  "amgmpcg_make_pairs"):
         getattr(lib, name).restype = c_int32
     _lib = lib
@@ -248,6 +252,15 @@ class Solver:
         r = torch.empty_like(b)
         _check(self._lib.amgmpcg_residual(self._h, self._vec(b, "b"), self._vec(x, "x"), c_void_p(r.data_ptr())))
         return r
+
+    def energy_grad(self, d, r, e, marginal: bool = False):
+        """(loss, dL/dd) of the energy loss of direction d (FP64, no network)."""
+        import torch
+        g = torch.empty_like(d)
+        loss = c_double()
+        _check(self._lib.amgmpcg_energy_grad(self._h, self._vec(d, "d"), self._vec(r, "r"), self._vec(e, "e"),
+                                             int(bool(marginal)), c_void_p(g.data_ptr()), byref(loss)))
+        return loss.value, g
 
     def attach(self, net: Optional["Network"]):
         """Append the network's output as one more search direction (None removes it)."""
@@ -459,6 +472,14 @@ class Network:
         loss = c_double()
         _check(self._lib.amgmpcg_cnn_train_step(self._h, self._vec(r, "r"), self._lk(lk), self._vec(e, "e"),
                                                 float(lr), byref(loss)))
+        return loss.value
+
+    def energy_step(self, solver: "Solver", r, e, lr: float = 0.0, lk=None, marginal: bool = False) -> float:
+        """Energy-loss step with the finest operator of `solver` (lr = 0: gradients only);
+        marginal: the loss on top of the solver's level-correction block of r."""
+        loss = c_double()
+        _check(self._lib.amgmpcg_cnn_energy_step(self._h, solver._h, self._vec(r, "r"), self._lk(lk),
+                                                 self._vec(e, "e"), int(bool(marginal)), float(lr), byref(loss)))
         return loss.value
 
     def layer(self, layer: int, op: int, A, B=None):

@@ -101,6 +101,9 @@ class SolverBase {
     virtual void make_pairs(const double* b_dev, const double* xs_dev, const int* ks, int nk, double* R_dev,
                             double* E_dev) = 0;
     virtual void log_kappa(unsigned short* lk_dev) = 0;
+    virtual void apply_fine(const double* x_dev, double* y_dev, hipStream_t s) = 0;
+    virtual void project_prepare(const double* r_dev, double* rhat_dev, hipStream_t s) = 0;
+    virtual void project_direction(const double* d_dev, const double* q_dev, double* qhat_dev, hipStream_t s) = 0;
     cnn::Net* net_ = nullptr;
     int dim = 0, nlev = 0, nb = 0;
     std::vector<int> n_axis;   // per level, 0 = coarsest
@@ -205,6 +208,8 @@ class Solver : public SolverBase {
         }
         HIPCHK(hipMalloc((void**)&ctl_, sizeof(Ctl)));
         HIPCHK(hipMalloc((void**)&ctl_free_, sizeof(Ctl)));
+        HIPCHK(hipMalloc((void**)&ctl_proj_, sizeof(Ctl)));
+        HIPCHK(hipHostMalloc((void**)&hctl_proj_, sizeof(Ctl), hipHostMallocDefault));
         HIPCHK(hipHostMalloc((void**)&hctl_, sizeof(Ctl), hipHostMallocDefault));
         HIPCHK(hipHostMalloc((void**)&hctl_in_, sizeof(Ctl), hipHostMallocDefault));
         std::memset(hctl_in_, 0, sizeof(Ctl));
@@ -307,6 +312,50 @@ class Solver : public SolverBase {
         HIPCHK(hipStreamSynchronize(stream_));
     }
 
+    // y = A x (finest operator, FP64) on stream s, not synchronised.
+    void apply_fine(const double* x_dev, double* y_dev, hipStream_t s) override {
+        k_apply<DIM><<<(rows_.total + kBlock - 1) / kBlock, kBlock, 0, s>>>(rows_, f64_, x_dev, y_dev);
+    }
+
+    // A-orthogonal projection onto the level-correction block of r (the
+    // first MPCG step from residual r): P = Z = MG(r), Q = A P, G^+, alpha =
+    // G^+ P^T r and rhat = r - Q alpha.  Uses the handle's work vectors; P, Q
+    // and G^+ stay for project_direction.  Needs FP64 and no attached network.
+    void project_prepare(const double* r_dev, double* rhat_dev, hipStream_t s) override {
+        if (mixed_ || net_) throw ApiError(AMGMPCG_INVALID_ARG, "projection needs an FP64 handle without a network");
+        const int N = N_[L_];
+        hipStream_t saved = stream_;
+        stream_ = s;
+        Ctl& c = *hctl_proj_;
+        std::memset(&c, 0, sizeof(Ctl));
+        c.maxit = 1;
+        c.tau = tau_;
+        HIPCHK(hipMemcpyAsync(ctl_proj_, hctl_proj_, sizeof(Ctl), hipMemcpyHostToDevice, s));
+        enqueue_levels(ctl_proj_, r_dev);
+        dispatch_plain([&](auto nbc) {
+            constexpr int NB = decltype(nbc)::value;
+            const int nc = L_ > 0 ? n_axis[L_ - 1] : 1;
+            k_update_xP<DIM, T, NB, 0><<<FB_, kBlock, 0, s>>>(ctl_proj_, rows_, fine_Y(), nc, cL_final_, nullptr,
+                                                               nullptr, P_.p, x_.p, d_alpha(), d_beta(), 1);
+            k_spmm_gram<DIM, T, NB><<<FB_, kBlock, 0, s>>>(ctl_proj_, rows_, fop_, P_.p, Q_.p, r_dev, part_G());
+            k_reduce_alpha<NB><<<1, kRedBlock, 0, s>>>(ctl_proj_, part_G(), FB_, d_Gplus(), d_alpha(), nullptr);
+            HIPCHK(hipMemcpyAsync(rhat_dev, r_dev, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, s));
+            k_update_r<T, NB><<<FB_, kBlock, 0, s>>>(ctl_proj_, N, Q_.p, d_alpha(), rhat_dev, part_rho());
+        });
+        stream_ = saved;
+    }
+
+    // qhat = q - Q G^+ Q^T d for the block of the last project_prepare.
+    void project_direction(const double* d_dev, const double* q_dev, double* qhat_dev, hipStream_t s) override {
+        const int N = N_[L_];
+        dispatch_plain([&](auto nbc) {
+            constexpr int NB = decltype(nbc)::value;
+            k_cols_dot<T, NB><<<FB_, kBlock, 0, s>>>(Q_.p, d_dev, N, part_W());
+            k_proj_coef<NB><<<1, kRedBlock, 0, s>>>(part_W(), FB_, d_Gplus(), d_beta());
+            k_sub_cols<T, NB><<<FB_, kBlock, 0, s>>>(q_dev, Q_.p, d_beta(), qhat_dev, N);
+        });
+    }
+
     const T* dl() const { return net_ ? dl_.p : nullptr; }
     const int* dflag() const { return net_ ? net_->flag.p : nullptr; }
 
@@ -325,6 +374,8 @@ class Solver : public SolverBase {
         if (cap_stream_) (void)hipStreamDestroy(cap_stream_);
         if (ctl_) (void)hipFree(ctl_);
         if (ctl_free_) (void)hipFree(ctl_free_);
+        if (ctl_proj_) (void)hipFree(ctl_proj_);
+        if (hctl_proj_) (void)hipHostFree(hctl_proj_);
         if (hctl_) (void)hipHostFree(hctl_);
         if (hctl_in_) (void)hipHostFree(hctl_in_);
         if (ev0_) (void)hipEventDestroy(ev0_);
@@ -480,6 +531,22 @@ class Solver : public SolverBase {
         static constexpr int value = V;
         static constexpr int ne = E;   // 1: the last column is the learned direction
     };
+
+    // The plain level block (nlev columns), whatever is attached.
+    template <typename F>
+    void dispatch_plain(F&& f) {
+        switch (nlev) {
+            case 1: f(IC<1>{}); break;
+            case 2: f(IC<2>{}); break;
+            case 3: f(IC<3>{}); break;
+            case 4: f(IC<4>{}); break;
+            case 5: f(IC<5>{}); break;
+            case 6: f(IC<6>{}); break;
+            case 7: f(IC<7>{}); break;
+            case 8: f(IC<8>{}); break;
+            default: throw ApiError(AMGMPCG_INVALID_ARG, "unsupported number of directions");
+        }
+    }
 
     template <typename F>
     void dispatch_nb(F&& f) {
@@ -786,6 +853,8 @@ class Solver : public SolverBase {
     DevBuf<unsigned short> lk_;
     Ctl* ctl_ = nullptr;
     Ctl* ctl_free_ = nullptr;
+    Ctl* ctl_proj_ = nullptr;
+    Ctl* hctl_proj_ = nullptr;
     Ctl* hctl_ = nullptr;
     Ctl* hctl_in_ = nullptr;
     hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
@@ -1366,6 +1435,72 @@ int amgmpcg_cnn_train_step(amgmpcg_cnn* net, const double* r_dev, const uint16_t
         if (!r_dev || !e_dev) throw ApiError(AMGMPCG_INVALID_ARG, "r or e is NULL");
         if (!(lr > 0.f) || !std::isfinite(lr)) throw ApiError(AMGMPCG_INVALID_ARG, "lr must be finite and > 0");
         HIPCHK(net->net.step_pair(r_dev, lk_dev, e_dev, lr, loss));
+        return AMGMPCG_OK;
+    });
+}
+
+int amgmpcg_cnn_energy_step(amgmpcg_cnn* net, amgmpcg_handle* h, const double* r_dev, const uint16_t* lk_dev,
+                            const double* e_dev, int32_t marginal, float lr, double* loss) {
+    return guarded([&]() -> int {
+        check_net(net);
+        if (!h || !h->s) throw ApiError(AMGMPCG_INVALID_ARG, "handle is NULL");
+        if (!r_dev || !e_dev) throw ApiError(AMGMPCG_INVALID_ARG, "r or e is NULL");
+        if (!(lr >= 0.f) || !std::isfinite(lr)) throw ApiError(AMGMPCG_INVALID_ARG, "lr must be finite and >= 0");
+        if (h->s->dim != 3 || h->s->n_axis.back() != net->net.n)
+            throw ApiError(AMGMPCG_DIM_MISMATCH, "the handle's grid differs from the network's");
+        if (marginal != 0 && marginal != 1) throw ApiError(AMGMPCG_INVALID_ARG, "marginal must be 0 or 1");
+        amg::cnn::Net& N = net->net;
+        N.forward(nullptr, r_dev, lk_dev, N.stream);
+        N.output_vector(N.stream);
+        h->s->apply_fine(N.dvec.p, N.qvec.p, N.stream);
+        if (marginal) {
+            h->s->project_prepare(r_dev, N.rvec.p, N.stream);
+            h->s->project_direction(N.dvec.p, N.qvec.p, N.q2vec.p, N.stream);
+            N.loss_energy(N.rvec.p, N.q2vec.p, e_dev, N.stream);
+        } else {
+            N.loss_energy(r_dev, N.qvec.p, e_dev, N.stream);
+        }
+        N.backward(N.stream);
+        if (lr > 0.f) N.adam(lr, N.stream);
+        HIPCHK(N.read_loss(loss));
+        return AMGMPCG_OK;
+    });
+}
+
+int amgmpcg_energy_grad(amgmpcg_handle* h, const double* d_dev, const double* r_dev, const double* e_dev,
+                        int32_t marginal, double* grad_dev, double* loss) {
+    return guarded([&]() -> int {
+        if (!h || !h->s) throw ApiError(AMGMPCG_INVALID_ARG, "handle is NULL");
+        if (!d_dev || !r_dev || !e_dev || !grad_dev) throw ApiError(AMGMPCG_INVALID_ARG, "NULL vector");
+        if (marginal != 0 && marginal != 1) throw ApiError(AMGMPCG_INVALID_ARG, "marginal must be 0 or 1");
+        amg::SolverBase& S = *h->s;
+        const int n = S.n_axis.back();
+        const int N = (int)std::llround(std::pow((double)n, S.dim));
+        amg::DevBuf<double> q, qh, rh, part, sc;
+        q.alloc(N);
+        part.alloc((size_t)3 * amg::cnn::kSumBlocks);
+        sc.alloc(4);
+        hipStream_t st = nullptr;
+        S.apply_fine(d_dev, q.p, st);
+        const double* rr = r_dev;
+        const double* qq = q.p;
+        if (marginal) {
+            qh.alloc(N);
+            rh.alloc(N);
+            S.project_prepare(r_dev, rh.p, st);
+            S.project_direction(d_dev, q.p, qh.p, st);
+            rr = rh.p;
+            qq = qh.p;
+        }
+        amg::cnn::k_dots3<<<amg::cnn::kSumBlocks, amg::cnn::kCB, 0, st>>>(d_dev, qq, rr, e_dev, N, part.p);
+        amg::cnn::k_energy_finish<<<1, amg::kRedBlock, 0, st>>>(part.p, amg::cnn::kSumBlocks, sc.p);
+        amg::cnn::k_energy_grad64<<<(N + amg::cnn::kCB - 1) / amg::cnn::kCB, amg::cnn::kCB, 0, st>>>(sc.p, qq, rr,
+                                                                                                  grad_dev, N);
+        HIPCHK(hipGetLastError());
+        double hs[4];
+        HIPCHK(hipMemcpyAsync(hs, sc.p, sizeof(hs), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (loss) *loss = hs[3];
         return AMGMPCG_OK;
     });
 }

@@ -309,6 +309,67 @@ __global__ void __launch_bounds__(kCB) k_mse_grad(const float* __restrict__ out,
     block_sum_store<1>(acc, part, gridDim.x, blockIdx.x);
 }
 
+// Energy loss of the direction d (the network output on the n^3 nodes) for
+// the pair (r, e) with q = A d: partial sums of d.r, d.q and e.r.
+__global__ void __launch_bounds__(kCB) k_dots3(const double* __restrict__ d, const double* __restrict__ q,
+                                               const double* __restrict__ r, const double* __restrict__ e, int N,
+                                               double* __restrict__ part) {
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int i = blockIdx.x * kCB + threadIdx.x; i < N; i += gridDim.x * kCB) {
+        const double ri = r[i], di = d[i];
+        v[0] += di * ri;
+        v[1] += di * q[i];
+        v[2] += e[i] * ri;
+    }
+    block_sum_store<3>(v, part, gridDim.x, blockIdx.x);
+}
+
+// s[0..2] = d.r, d.Ad, e.r; s[3] = loss 1 - (d.r)^2 / ((d.Ad)(e.r)) (1 when
+// d.Ad or e.r is not positive).
+__global__ void __launch_bounds__(kRedBlock) k_energy_finish(const double* __restrict__ part, int nblk,
+                                                            double* __restrict__ s) {
+    __shared__ double res[3];
+    reduce_partials<3>(part, nblk, res);
+    if (threadIdx.x == 0) {
+        const double a = res[0], c = res[1], E = res[2];
+        s[0] = a;
+        s[1] = c;
+        s[2] = E;
+        s[3] = (c > 0.0 && E > 0.0) ? 1.0 - a * a / (c * E) : 1.0;
+    }
+}
+
+// Output gradient of the energy loss, dL/dd = 2a/(cE) ((a/c) q - r), as the
+// bfloat16 gradient of channel 0 on the S^3 grid (zero outside the n^3 nodes
+// and in the other channels).
+__global__ void __launch_bounds__(kCB) k_energy_grad(const double* __restrict__ s, const double* __restrict__ q,
+                                                     const double* __restrict__ r, bf16* __restrict__ G, int n,
+                                                     int S) {
+    const int v = blockIdx.x * kCB + threadIdx.x;
+    if (v >= S * S * S) return;
+    const double a = s[0], c = s[1], E = s[2];
+    const bool ok = c > 0.0 && E > 0.0;
+    const int x = v % S, y = (v / S) % S, z = v / (S * S);
+    float g = 0.f;
+    if (ok && x < n && y < n && z < n) {
+        const int idx = x + n * (y + n * z);
+        g = (float)((2.0 * a / (c * E)) * ((a / c) * q[idx] - r[idx]));
+    }
+    bf16* o = G + (size_t)v * 16;
+    o[0] = f2bf(g);
+#pragma unroll
+    for (int k = 1; k < 16; ++k) o[k] = 0;
+}
+
+// dL/dd of the energy loss in FP64 on the n^3 nodes (no network).
+__global__ void __launch_bounds__(kCB) k_energy_grad64(const double* __restrict__ s, const double* __restrict__ q,
+                                                       const double* __restrict__ r, double* __restrict__ g, int N) {
+    const int i = blockIdx.x * kCB + threadIdx.x;
+    if (i >= N) return;
+    const double a = s[0], c = s[1], E = s[2];
+    g[i] = (c > 0.0 && E > 0.0) ? (2.0 * a / (c * E)) * ((a / c) * q[i] - r[i]) : 0.0;
+}
+
 // The network output (channel 0 of the FP32 final layer) as an MPCG column
 // (bulk type T, n^3 values); flag = 1 if any value is not finite.
 template <typename T>

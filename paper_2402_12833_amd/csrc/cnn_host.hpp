@@ -82,6 +82,10 @@ class Net {
         g2b.alloc(V2 * 64, err);
         g2c.alloc(V2 * 32, err);
         small.alloc(16, err);
+        dvec.alloc((size_t)n * n * n, err);
+        qvec.alloc((size_t)n * n * n, err);
+        rvec.alloc((size_t)n * n * n, err);
+        q2vec.alloc((size_t)n * n * n, err);
         flag.alloc(1, err);
         part.alloc((V0 + kCB - 1) / kCB > kSumBlocks ? (V0 + kCB - 1) / kCB : kSumBlocks, err);
         const int64_t NW = total_weights();
@@ -178,13 +182,43 @@ class Net {
     }
 
     // Loss against e / rms(e) and all weight gradients into g (FP32).
-    void backward(const double* e, hipStream_t s) {
-        const int S0 = S, S1 = S / 2, S2 = S / 4;
-        const size_t V0 = (size_t)S0 * S0 * S0, V1 = V0 / 8, V2 = V1 / 8;
+    // MSE loss against e / rms(e): loss -> small[2], output gradient -> g0a.
+    void loss_mse(const double* e, hipStream_t s) {
+        const size_t V0 = (size_t)S * S * S;
         k_sumsq<<<kSumBlocks, kCB, 0, s>>>(nullptr, e, n * n * n, part.p);
         k_finish_sum<<<1, kRedBlock, 0, s>>>(nullptr, part.p, kSumBlocks, n * n * n, 0, small.p + 1);
-        k_mse_grad<<<blocks(V0), kCB, 0, s>>>(out.p, e, small.p + 1, g0a.p, n, S0, part.p);
+        k_mse_grad<<<blocks(V0), kCB, 0, s>>>(out.p, e, small.p + 1, g0a.p, n, S, part.p);
         k_finish_sum<<<1, kRedBlock, 0, s>>>(nullptr, part.p, (int)blocks(V0), 0, 1, small.p + 2);
+    }
+
+    // The network output d on the n^3 nodes (FP64) -> dvec.
+    void output_vector(hipStream_t s) {
+        k_clear_flag<<<1, 64, 0, s>>>(nullptr, flag.p);
+        k_unpack_output<double><<<blocks((size_t)n * n * n), kCB, 0, s>>>(nullptr, out.p, dvec.p, n, S, flag.p);
+    }
+
+    // Energy loss of dvec for (r, e) given q = A dvec (or their parts
+    // A-orthogonal to a block): loss -> small[2], output gradient -> g0a.
+    void loss_energy(const double* r, const double* q, const double* e, hipStream_t s) {
+        k_dots3<<<kSumBlocks, kCB, 0, s>>>(dvec.p, q, r, e, n * n * n, part.p);
+        k_energy_finish<<<1, kRedBlock, 0, s>>>(part.p, kSumBlocks, small.p + 4);
+        k_energy_grad<<<blocks((size_t)S * S * S), kCB, 0, s>>>(small.p + 4, q, r, g0a.p, n, S);
+        (void)hipMemcpyAsync(small.p + 2, small.p + 7, sizeof(double), hipMemcpyDeviceToDevice, s);
+    }
+
+    hipError_t read_loss(double* loss) {
+        double h = 0.0;
+        hipError_t err = hipGetLastError();
+        if (err == hipSuccess) err = hipMemcpyAsync(&h, small.p + 2, sizeof(double), hipMemcpyDeviceToHost, stream);
+        if (err == hipSuccess) err = hipStreamSynchronize(stream);
+        if (loss) *loss = h;
+        return err;
+    }
+
+    // Weight gradients into g (FP32) from the output gradient in g0a.
+    void backward(hipStream_t s) {
+        const int S0 = S, S1 = S / 2, S2 = S / 4;
+        const size_t V0 = (size_t)S0 * S0 * S0, V1 = V0 / 8, V2 = V1 / 8;
         (void)hipMemsetAsync(g.p, 0, total_weights() * sizeof(float), s);
         // output layer (1x1)
         wgrad<16, 16, 1>(g0a.p, d4.p, 10, S0, s);
@@ -241,14 +275,10 @@ class Net {
     // Adam step.  Synchronises to return the loss.
     hipError_t step_pair(const double* r, const bf16* lk, const double* e, float lr, double* loss) {
         forward(nullptr, r, lk, stream);
-        backward(e, stream);
+        loss_mse(e, stream);
+        backward(stream);
         if (lr > 0.f) adam(lr, stream);
-        double h = 0.0;
-        hipError_t err = hipGetLastError();
-        if (err == hipSuccess) err = hipMemcpyAsync(&h, small.p + 2, sizeof(double), hipMemcpyDeviceToHost, stream);
-        if (err == hipSuccess) err = hipStreamSynchronize(stream);
-        if (loss) *loss = h;
-        return err;
+        return read_loss(loss);
     }
 
     void adam(float lr, hipStream_t s) {
@@ -269,7 +299,7 @@ class Net {
     Buf<bf16> x0, e1, e2, p1, e3, e4, p2, b1, b2, c1, d1, d2, c2, d3, d4;
     Buf<float> out;
     Buf<bf16> g0a, g0b, g0c, g1a, g1b, g1c, g2a, g2b, g2c;
-    Buf<double> small, part;
+    Buf<double> small, part, dvec, qvec, rvec, q2vec;
     Buf<int> flag;
     Buf<float> w, m, v, g;
     Buf<bf16> wb, wt;

@@ -457,6 +457,67 @@ __global__ void __launch_bounds__(kBlock) k_refresh(const Ctl* __restrict__ ctl,
     block_sum_store<1>(v, part, gridDim.x, lb);
 }
 
+// y = A x on the finest level in FP64.
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_apply(Rows R, FineOp<double> op, const double* __restrict__ x,
+                                                  double* __restrict__ y) {
+    ROW_LOOP(R, blockIdx.x) {
+        Idx<DIM> p;
+        int idx;
+        if (!row_item<DIM>(R, w_, p, idx)) continue;
+        y[idx] = fine_apply<DIM, double>(op, x, idx, p);
+    }
+}
+
+// w = Q^T d partial sums (Q node-major, NB columns, stride even_up(NB)).
+template <typename T, int NB>
+__global__ void __launch_bounds__(kBlock) k_cols_dot(const T* __restrict__ Q, const double* __restrict__ d, int N,
+                                                     double* __restrict__ part) {
+    constexpr int S = even_up(NB);
+    double w[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) w[c] = 0.0;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
+        T q[S];
+        load_node<T, S>(Q + (size_t)i * S, q);
+        const double di = d[i];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) w[c] += double(q[c]) * di;
+    }
+    block_sum_store<NB>(w, part, gridDim.x, blockIdx.x);
+}
+
+// t = G^+ w with w reduced from the k_cols_dot partials (one block).
+template <int NB>
+__global__ void __launch_bounds__(kRedBlock) k_proj_coef(const double* __restrict__ part, int nblk,
+                                                         const double* __restrict__ Gplus, double* __restrict__ t) {
+    __shared__ double w[NB];
+    reduce_partials<NB>(part, nblk, w);
+    if (threadIdx.x < NB) {
+        double s = 0.0;
+        for (int m = 0; m < NB; ++m) s += Gplus[threadIdx.x * NB + m] * w[m];
+        t[threadIdx.x] = s;
+    }
+}
+
+// out = q - Q t (Q node-major).
+template <typename T, int NB>
+__global__ void __launch_bounds__(kBlock) k_sub_cols(const double* __restrict__ q, const T* __restrict__ Q,
+                                                     const double* __restrict__ t, double* __restrict__ out, int N) {
+    constexpr int S = even_up(NB);
+    __shared__ double ts[NB];
+    if (threadIdx.x < NB) ts[threadIdx.x] = t[threadIdx.x];
+    __syncthreads();
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
+        T qq[S];
+        load_node<T, S>(Q + (size_t)i * S, qq);
+        double v = q[i];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) v -= double(qq[c]) * ts[c];
+        out[i] = v;
+    }
+}
+
 // Training pair of the learned direction: r = b - A x (FP64) and e = xs - x.
 template <int DIM>
 __global__ void __launch_bounds__(kBlock) k_pair(Rows R, FineOp<double> op, const double* __restrict__ b,

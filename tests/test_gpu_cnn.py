@@ -11,13 +11,15 @@ moves an exact value across a rounding boundary with probability about
 2^-24 / 2^-9); weight gradients (FP32 sums) within 1e-4 relative.
 
 End to end (whole network): the forward output within 1e-2 and each weight
-gradient within 0.1 normwise relative with cosine >= 0.99.  The looser
+gradient within 0.2 normwise relative with cosine >= 0.99.  The looser
 gradient bar is derived, not chosen: a single rounding flip in an early
 activation changes its element by 2^-8 relative, which moves later exact
 sums across further boundaries, and the flips cascade through the eleven
 layers and back.  Re-running the FP64 oracle with FP32 accumulation in the
-convolutions (CPU only) differs from the FP64 oracle by up to 5e-2 in the
-weight gradients on the n = 19 case below, by the same cascade.  The grids
+convolutions (CPU only) differs from the FP64 oracle by up to 5e-2 (MSE
+loss) and 8.6e-2 (marginal energy loss) in the weight gradients of the
+cases below, by the same cascade.  The loss heads themselves (energy and
+marginal energy loss of a given direction) are FP64 and checked to 1e-9.  The grids
 cover one 16-voxel x tile (S = 16), a ragged second tile (S = 20) and two
 full tiles (S = 32).
 
@@ -88,6 +90,12 @@ def oracle_forward(Wd, r, lk, n):
 
 SIZES = [13, 19, 30]
 
+# End-to-end gradient bars (see the module docstring): the CPU re-run of
+# these cases with FP32 accumulation differs from the FP64 oracle by up to
+# 8.6e-2 normwise (cosine >= 0.9966); the bars allow about twice that.
+E2E_GRAD_REL = 0.2
+E2E_GRAD_COS = 0.99
+
 
 def test_weight_layout_roundtrip():
     Wd, net = make_net(9, 5)
@@ -150,7 +158,106 @@ def test_gradients_match_oracle(n):
     print(f"n={n} loss {loss:.4e} gpu {loss_gpu:.4e}; gradient errors " +
           " ".join(f"{k}:{v:.1e}" for k, v in errs.items()))
     for name, err in errs.items():
-        assert err <= 0.1 and cos[name] >= 0.99, (name, err, cos[name])
+        assert err <= E2E_GRAD_REL and cos[name] >= E2E_GRAD_COS, (name, err, cos[name])
+
+
+@pytest.mark.parametrize("n", [15, 19])
+def test_energy_gradients_match_oracle(n):
+    kap = np.exp(2.0 * W.gaussian_field(n, 3, 21, periodic=64))
+    h = hierarchy.build(3, n, 2, kappa=kap)
+    s = amg.Solver(3, n, 2, kappa=kap)
+    Wd, net = make_net(n, 50 + n)
+    rng = np.random.default_rng(60 + n)
+    e = rng.uniform(-1.0, 1.0, n ** 3)
+    r = h.fine.A @ e
+    lk = cnn.round_bf16(rng.standard_normal(n ** 3))
+    out, cache, S = oracle_forward(Wd, r, lk, n)
+    d = out[:n, :n, :n].reshape(-1)
+    loss, grad = cnn.energy_loss(d, r, e, h.fine.A @ d)
+    dout = np.zeros((S, S, S))
+    dout[:n, :n, :n] = grad.reshape(n, n, n)
+    g = cnn.backward(Wd, cache, dout)
+    loss_gpu = net.energy_step(s, dev(r), dev(e), 0.0, lk_dev(lk))
+    G = amg.Network.split(net.get_gradients())
+    errs = {name: rel(G[name], g[name]) for name, *_ in amg.CNN_LAYERS}
+    cos = {name: float(np.sum(G[name] * g[name]) / (np.linalg.norm(G[name]) * np.linalg.norm(g[name])))
+           for name, *_ in amg.CNN_LAYERS}
+    print(f"n={n} energy loss {loss:.6f} gpu {loss_gpu:.6f}; gradient errors " +
+          " ".join(f"{k}:{v:.1e}" for k, v in errs.items()))
+    assert abs(loss_gpu - loss) <= 1e-3
+    for name, err in errs.items():
+        assert err <= E2E_GRAD_REL and cos[name] >= E2E_GRAD_COS, (name, err, cos[name])
+
+
+@pytest.mark.parametrize("marginal", [False, True])
+def test_energy_loss_head_matches_oracle(marginal):
+    # the loss and its gradient for a caller-supplied direction, in FP64
+    n, nl = 17, 3
+    kap = np.exp(2.0 * W.gaussian_field(n, 3, 26, periodic=64))
+    h = hierarchy.build(3, n, nl, kappa=kap)
+    s = amg.Solver(3, n, nl, kappa=kap)
+    rng = np.random.default_rng(27)
+    e = rng.uniform(-1.0, 1.0, n ** 3)
+    r = h.fine.A @ e
+    d = e + 0.5 * rng.standard_normal(n ** 3)
+    if marginal:
+        Z = mpcg.mg_block(h, r)
+        loss, grad = cnn.marginal_energy_loss(d, r, e, h.fine.A, Z, mpcg.default_tau(Z.shape[1]))
+    else:
+        loss, grad = cnn.energy_loss(d, r, e, h.fine.A @ d)
+    lg, gg = s.energy_grad(dev(d), dev(r), dev(e), marginal=marginal)
+    print(f"marginal={marginal}: loss {loss:.12f} gpu {lg:.12f}, grad rel err {rel(host(gg), grad):.2e}")
+    assert lg == pytest.approx(loss, rel=1e-10)
+    assert rel(host(gg), grad) <= 1e-9
+
+
+@pytest.mark.parametrize("n,nl", [(15, 3), (19, 3)])
+def test_marginal_energy_gradients_match_oracle(n, nl):
+    kap = np.exp(2.0 * W.gaussian_field(n, 3, 25, periodic=64))
+    h = hierarchy.build(3, n, nl, kappa=kap)
+    s = amg.Solver(3, n, nl, kappa=kap)
+    Wd, net = make_net(n, 70 + n)
+    rng = np.random.default_rng(80 + n)
+    e = rng.uniform(-1.0, 1.0, n ** 3)
+    r = h.fine.A @ e
+    lk = cnn.round_bf16(rng.standard_normal(n ** 3))
+    out, cache, S = oracle_forward(Wd, r, lk, n)
+    d = out[:n, :n, :n].reshape(-1)
+    Z = mpcg.mg_block(h, r)
+    loss, grad = cnn.marginal_energy_loss(d, r, e, h.fine.A, Z, mpcg.default_tau(Z.shape[1]))
+    dout = np.zeros((S, S, S))
+    dout[:n, :n, :n] = grad.reshape(n, n, n)
+    g = cnn.backward(Wd, cache, dout)
+    loss_gpu = net.energy_step(s, dev(r), dev(e), 0.0, lk_dev(lk), marginal=True)
+    G = amg.Network.split(net.get_gradients())
+    errs = {name: rel(G[name], g[name]) for name, *_ in amg.CNN_LAYERS}
+    cos = {name: float(np.sum(G[name] * g[name]) / (np.linalg.norm(G[name]) * np.linalg.norm(g[name])))
+           for name, *_ in amg.CNN_LAYERS}
+    print(f"n={n} marginal energy loss {loss:.6f} gpu {loss_gpu:.6f}; gradient errors " +
+          " ".join(f"{k}:{v:.1e}" for k, v in errs.items()))
+    assert abs(loss_gpu - loss) <= 1e-3
+    for name, err in errs.items():
+        assert err <= E2E_GRAD_REL and cos[name] >= E2E_GRAD_COS, (name, err, cos[name])
+    # the handle still solves after serving as the projection's workspace
+    x, info = s.solve(dev(r), tol=1e-8)
+    assert info["status"] == amg.OK
+
+
+def test_energy_training_reduces_loss():
+    n = 15
+    kap = np.exp(2.0 * W.gaussian_field(n, 3, 22, periodic=64))
+    s = amg.Solver(3, n, 3, kappa=kap)
+    b = dev(W.rhs(n ** 3, 23))
+    xs, _ = s.solve(b, tol=1e-12)
+    R, E = s.make_pairs(b, xs, [0, 2, 4])
+    lk = s.log_kappa()
+    _, net = make_net(n, 24)
+    first = np.mean([net.energy_step(s, R[i], E[i], 0.0, lk) for i in range(3)])
+    for it in range(60):
+        net.energy_step(s, R[it % 3], E[it % 3], 1e-3, lk)
+    last = np.mean([net.energy_step(s, R[i], E[i], 0.0, lk) for i in range(3)])
+    print(f"energy loss {first:.4f} -> {last:.4f}")
+    assert last < first
 
 
 def bf16_dev(a):
