@@ -1450,7 +1450,7 @@ int amgmpcg_cnn_energy_step(amgmpcg_cnn* net, amgmpcg_handle* h, const double* r
             throw ApiError(AMGMPCG_DIM_MISMATCH, "the handle's grid differs from the network's");
         if (marginal != 0 && marginal != 1) throw ApiError(AMGMPCG_INVALID_ARG, "marginal must be 0 or 1");
         amg::cnn::Net& N = net->net;
-        N.forward(nullptr, r_dev, lk_dev, N.stream);
+        N.forward(nullptr, r_dev, lk_dev, N.stream, true);
         N.output_vector(N.stream);
         h->s->apply_fine(N.dvec.p, N.qvec.p, N.stream);
         if (marginal) {

@@ -6,11 +6,13 @@
 // Tensors are channels-last bfloat16 on an S^3 grid (S a multiple of 4 that
 // holds the n^3 problem grid in its low corner): t[((z*S + y)*S + x)*C + c].
 // Convolutions are implicit GEMMs on the matrix cores: M = voxels (16 along
-// x per wavefront), N = output channels, K = taps x input channels, with
-// v_mfma_f32_16x16x16_bf16 and FP32 accumulation.  Weights: bfloat16 copies
-// [tap][Cout][Cin] of FP32 masters (Adam).  The backward data gradient is the
-// same forward kernel on the tap-flipped, channel-transposed weights; weight
-// gradients are GEMMs over voxels accumulated with FP32 atomics.
+// x per M tile), N = output channels, K = taps x input channels, with
+// v_mfma_f32_16x16x32_bf16 (forward and data gradient, input tiles staged in
+// LDS) and v_mfma_f32_16x16x16_bf16 (weight gradient), FP32 accumulation.
+// Weights: bfloat16 copies [tap][Cout][Cin] of FP32 masters (Adam).  The
+// backward data gradient is the same forward kernel on the tap-flipped,
+// channel-transposed weights; weight gradients are GEMMs over voxels
+// accumulated with FP32 atomics.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -39,56 +41,111 @@ __host__ __device__ constexpr int tap_dx(int t) { return t % 3 - 1; }
 constexpr int kCB = 256;   // threads per block of the CNN kernels (4 wavefronts)
 
 // ------------------------------------------------------------- convolution
-// Y[v, co] = sum_t sum_ci X[v + o_t, ci] W[t, co, ci]  (zero outside the grid)
-// KS = 3 (27 taps) or 1 (one tap).  OUT_F32: write FP32 (final layer) else
-// bfloat16, with ReLU when RELU.  One wavefront = 16 voxels along x and all
-// output channels; lane l supplies A[m = l%16][k = 4(l/16)+j] and
-// B[k][n = l%16] and receives D[m = 4(l/16)+j][n = l%16].
-template <int CIN, int COUT, int KS, int RELU, int OUT_F32>
-__global__ void __launch_bounds__(kCB) k_conv_fwd(const Ctl* __restrict__ ctl, const bf16* __restrict__ X,
-                                                  const bf16* __restrict__ W, void* __restrict__ Yv, int S) {
+// Y[v, co] = sum_t sum_ci X[v + o_t, ci] W[t, co, ci] (zero outside the grid).
+
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+
+// LDS-tiled convolution.  A block computes a
+// 16 (x) x 4 (y) x 4 (z) tile of output voxels, one z plane per wavefront and
+// four 16-voxel rows (M tiles) per wavefront, all output channels.  The input
+// tile with its one-voxel halo is staged in LDS once per chunk of CC input
+// channels, so each input value leaves L2 once per block instead of once per
+// tap.  The K dimension (taps x channels of the chunk) is walked in steps of
+// 32 with v_mfma_f32_16x16x32_bf16: lane group kq takes the 8 consecutive
+// K indices 32 s + 8 kq .. + 7, i.e. 8 channels of one tap (a 16-channel
+// chunk pairs two taps per step); A (input) and B (weights) use the same K
+// assignment, so the sum is independent of the hardware's K order.
+// Input channels c < C1 come from Xc, a grid of S/2 read at (z/2, y/2, x/2)
+// (nearest upsampling), the rest from X (CIN - C1 channels): the skip
+// concatenation is read in place.
+template <int CIN, int C1, int COUT, int KS, int RELU, int OUT_F32>
+__global__ void __launch_bounds__(kCB) k_conv_lds(const Ctl* __restrict__ ctl, const bf16* __restrict__ Xc,
+                                                  const bf16* __restrict__ X, const bf16* __restrict__ W,
+                                                  void* __restrict__ Yv, int S) {
     if (ctl && ctl->state != 0) return;
-    static_assert(CIN % 16 == 0 && COUT % 16 == 0, "channels must be multiples of 16");
-    constexpr int NT = COUT / 16, KC = CIN / 16, TAPS = KS == 3 ? 27 : 1;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int xtiles = (S + 15) >> 4;
-    const int tile = blockIdx.x * (kCB / 64) + wv;
-    if (tile >= S * S * xtiles) return;
-    const int row = tile / xtiles, xt = tile - row * xtiles;
-    const int y = row % S, z = row / S, x0 = xt * 16;
+    static_assert(CIN % 16 == 0 && COUT % 16 == 0 && C1 % 16 == 0 && C1 < CIN, "channel layout");
+    constexpr int C2 = CIN - C1;
+    constexpr int CC = (CIN % 32 == 0) ? 32 : 16;      // channels per LDS stage
+    constexpr int NCH = CIN / CC;
+    constexpr int TAPS = KS == 3 ? 27 : 1;
+    constexpr int H = KS == 3 ? 1 : 0;
+    constexpr int LX = 16 + 2 * H, LY = 4 + 2 * H, LZ = 4 + 2 * H;
+    constexpr int NV = LX * LY * LZ;
+    constexpr int VS = CC + 8;                         // padded voxel stride (elements)
+    constexpr int NT = COUT / 16;
+    constexpr int STEPS = (TAPS * CC + 31) / 32;
+    constexpr int PIECES = CC / 8;                     // 16-byte pieces per voxel and stage
+    __shared__ __attribute__((aligned(16))) bf16 tile[NV * VS];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int m = lane & 15, kq = lane >> 4;
-    f32x4 acc[NT];
+    const int x0 = blockIdx.x * 16, y0 = blockIdx.y * 4, z0 = blockIdx.z * 4;
+    const int Sc = S >> 1;
+    f32x4 acc[4][NT];
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int t = 0; t < TAPS; ++t) {
-        const int dz = KS == 3 ? tap_dz(t) : 0, dy = KS == 3 ? tap_dy(t) : 0, dx = KS == 3 ? tap_dx(t) : 0;
-        const int zz = z + dz, yy = y + dy, xx = x0 + m + dx;
-        const bool ok = zz >= 0 && zz < S && yy >= 0 && yy < S && xx >= 0 && xx < S;
-        const size_t base = ok ? ((size_t)(zz * S + yy) * S + xx) * CIN : 0;
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int kc = 0; kc < KC; ++kc) {
-            bf16x4 a = bf16x4{0, 0, 0, 0};
-            if (ok) a = *reinterpret_cast<const bf16x4*>(X + base + kc * 16 + kq * 4);
+        for (int nt = 0; nt < NT; ++nt) acc[i][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int ch = 0; ch < NCH; ++ch) {
+        for (int p = threadIdx.x; p < NV * PIECES; p += kCB) {
+            const int v = p / PIECES, q = p - v * PIECES;
+            const int lx = v % LX, ly = (v / LX) % LY, lz = v / (LX * LY);
+            const int gx = x0 - H + lx, gy = y0 - H + ly, gz = z0 - H + lz;
+            int4 val = int4{0, 0, 0, 0};
+            if (gx >= 0 && gx < S && gy >= 0 && gy < S && gz >= 0 && gz < S) {
+                const int c = ch * CC + q * 8;
+                if (c < C1)
+                    val = *reinterpret_cast<const int4*>(
+                        Xc + ((size_t)((gz >> 1) * Sc + (gy >> 1)) * Sc + (gx >> 1)) * C1 + c);
+                else
+                    val = *reinterpret_cast<const int4*>(X + ((size_t)(gz * S + gy) * S + gx) * C2 + (c - C1));
+            }
+            *reinterpret_cast<int4*>(tile + v * VS + q * 8) = val;
+        }
+        __syncthreads();
+#pragma unroll 3
+        for (int st = 0; st < STEPS; ++st) {
+            const int kg = st * 32 + 8 * kq;
+            const int t = kg / CC, c = kg - t * CC;
+            const bool valid = t < TAPS;
+            const int tt = valid ? t : 0;
+            bf16x8 b[NT];
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
-                const bf16x4 b = *reinterpret_cast<const bf16x4*>(
-                    W + ((size_t)(t * COUT + nt * 16 + m) * CIN + kc * 16 + kq * 4));
-                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nt], 0, 0, 0);
+                b[nt] = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+                if (valid)
+                    b[nt] = *reinterpret_cast<const bf16x8*>(W + ((size_t)(tt * COUT + nt * 16 + m) * CIN + ch * CC + c));
+            }
+            const int dz = KS == 3 ? tap_dz(tt) : 0, dy = KS == 3 ? tap_dy(tt) : 0, dx = KS == 3 ? tap_dx(tt) : 0;
+            const int vbase = ((w + dz + H) * LY + (dy + H)) * LX + (m + dx + H);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                bf16x8 a = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+                if (valid) a = *reinterpret_cast<const bf16x8*>(tile + (vbase + i * LX) * VS + c);
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    acc[i][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[nt], acc[i][nt], 0, 0, 0);
             }
         }
+        __syncthreads();
     }
+    const int z = z0 + w;
+    if (z >= S) return;
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
+    for (int i = 0; i < 4; ++i) {
+        const int y = y0 + i;
+        if (y >= S) continue;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int x = x0 + kq * 4 + j;
-            if (x >= S) continue;
-            float v = acc[nt][j];
-            if (RELU) v = v > 0.f ? v : 0.f;
-            const size_t o = ((size_t)(z * S + y) * S + x) * COUT + nt * 16 + m;
-            if (OUT_F32) static_cast<float*>(Yv)[o] = v;
-            else static_cast<bf16*>(Yv)[o] = f2bf(v);
-        }
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int x = x0 + kq * 4 + j;
+                if (x >= S) continue;
+                float v = acc[i][nt][j];
+                if (RELU) v = v > 0.f ? v : 0.f;
+                const size_t o = ((size_t)(z * S + y) * S + x) * COUT + nt * 16 + m;
+                if (OUT_F32) static_cast<float*>(Yv)[o] = v;
+                else static_cast<bf16*>(Yv)[o] = f2bf(v);
+            }
     }
 }
 

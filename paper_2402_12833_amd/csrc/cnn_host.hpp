@@ -159,7 +159,9 @@ class Net {
     // Forward pass on r (n^3 doubles, device); lk: normalised log kappa or
     // null.  Result: FP32 channel 0 of `out`.  ctl (nullable) predicates all
     // kernels on the solver's stop flag.
-    void forward(const Ctl* ctl, const double* r, const bf16* lk, hipStream_t s) {
+    // train: also materialise the skip concatenations (the weight gradients
+    // of w7 and w9 read them); inference reads them in place.
+    void forward(const Ctl* ctl, const double* r, const bf16* lk, hipStream_t s, bool train = false) {
         const int S0 = S, S1 = S / 2, S2 = S / 4;
         k_sumsq<<<kSumBlocks, kCB, 0, s>>>(ctl, r, n * n * n, part.p);
         k_finish_sum<<<1, kRedBlock, 0, s>>>(ctl, part.p, kSumBlocks, n * n * n, 0, small.p);
@@ -172,11 +174,11 @@ class Net {
         k_avgpool<<<blocks((size_t)S2 * S2 * S2 * 32), kCB, 0, s>>>(ctl, e4.p, p2.p, S2, 32);
         conv<32, 64, 3, 1, 0>(ctl, p2.p, 4, b1.p, S2, s);
         conv<64, 64, 3, 1, 0>(ctl, b1.p, 5, b2.p, S2, s);
-        k_upcat<<<blocks((size_t)S1 * S1 * S1 * 96), kCB, 0, s>>>(ctl, b2.p, e4.p, c1.p, S1, 64, 32);
-        conv<96, 32, 3, 1, 0>(ctl, c1.p, 6, d1.p, S1, s);
+        if (train) k_upcat<<<blocks((size_t)S1 * S1 * S1 * 96), kCB, 0, s>>>(ctl, b2.p, e4.p, c1.p, S1, 64, 32);
+        conv_cat<96, 64, 32>(ctl, b2.p, e4.p, 6, d1.p, S1, s);
         conv<32, 32, 3, 1, 0>(ctl, d1.p, 7, d2.p, S1, s);
-        k_upcat<<<blocks((size_t)S0 * S0 * S0 * 48), kCB, 0, s>>>(ctl, d2.p, e2.p, c2.p, S0, 32, 16);
-        conv<48, 16, 3, 1, 0>(ctl, c2.p, 8, d3.p, S0, s);
+        if (train) k_upcat<<<blocks((size_t)S0 * S0 * S0 * 48), kCB, 0, s>>>(ctl, d2.p, e2.p, c2.p, S0, 32, 16);
+        conv_cat<48, 32, 16>(ctl, d2.p, e2.p, 8, d3.p, S0, s);
         conv<16, 16, 3, 1, 0>(ctl, d3.p, 9, d4.p, S0, s);
         conv<16, 16, 1, 0, 1>(ctl, d4.p, 10, out.p, S0, s);
     }
@@ -274,7 +276,7 @@ class Net {
     // Loss and weight gradients for one pair (r, e); with lr > 0 also one
     // Adam step.  Synchronises to return the loss.
     hipError_t step_pair(const double* r, const bf16* lk, const double* e, float lr, double* loss) {
-        forward(nullptr, r, lk, stream);
+        forward(nullptr, r, lk, stream, true);
         loss_mse(e, stream);
         backward(stream);
         if (lr > 0.f) adam(lr, stream);
@@ -344,17 +346,22 @@ class Net {
         }
     }
 
+    static dim3 conv_grid(int Sg) { return dim3((Sg + 15) / 16, (Sg + 3) / 4, (Sg + 3) / 4); }
+
     template <int CIN, int COUT, int KS, int RELU, int F32>
     static void conv_p(const Ctl* ctl, const bf16* X, const bf16* Wl, void* Y, int Sg, hipStream_t s) {
-        const int tiles = Sg * Sg * ((Sg + 15) / 16);
-        k_conv_fwd<CIN, COUT, KS, RELU, F32><<<(tiles + 3) / 4, kCB, 0, s>>>(ctl, X, Wl, Y, Sg);
+        k_conv_lds<CIN, 0, COUT, KS, RELU, F32><<<conv_grid(Sg), kCB, 0, s>>>(ctl, nullptr, X, Wl, Y, Sg);
     }
     // data gradient of a layer (CIN, COUT): the forward kernel on the
     // flipped, transposed weights, input dY (COUT channels) -> dX (CIN)
     template <int CIN, int COUT, int KS>
     static void dgrad_p(const bf16* dY, const bf16* Wt, bf16* dX, int Sg, hipStream_t s) {
-        const int tiles = Sg * Sg * ((Sg + 15) / 16);
-        k_conv_fwd<COUT, CIN, KS, 0, 0><<<(tiles + 3) / 4, kCB, 0, s>>>(nullptr, dY, Wt, dX, Sg);
+        k_conv_lds<COUT, 0, CIN, KS, 0, 0><<<conv_grid(Sg), kCB, 0, s>>>(nullptr, nullptr, dY, Wt, dX, Sg);
+    }
+    // conv + ReLU of [upsample2(Xc) (C1 channels) | X] without forming the concatenation
+    template <int CIN, int C1, int COUT>
+    void conv_cat(const Ctl* ctl, const bf16* Xc, const bf16* X, int layer, bf16* Y, int Sg, hipStream_t s) {
+        k_conv_lds<CIN, C1, COUT, 3, 1, 0><<<conv_grid(Sg), kCB, 0, s>>>(ctl, Xc, X, wb.p + woff(layer), Y, Sg);
     }
     template <int CIN, int COUT, int KS>
     static void wgrad_p(const bf16* dY, const bf16* X, float* dW, int Sg, hipStream_t s) {
