@@ -9,10 +9,12 @@ levels, damped Jacobi nu=2 omega=2/3, b ~ U[-1,1] seed 2, x0 = 0) to
 protocol is applied to the FP32-bulk form and to the heterogeneous-kappa
 workload; they are reported under ``variants``.
 
-The roofline entry is for the kernel with the largest measured time per
+The roofline entry is for the fine-level kernel with the largest time per
 iteration; its average launch duration is measured with HIP events on the
-solver's stream (amgmpcg_time_kernels), and its algorithmic bytes come from
-the per-DoF traffic model below.
+solver's stream around the kernel inside the iterations of one more solve
+of the same workload (amgmpcg_profile_solve: the iterations launched one by
+one, every kernel on the data its predecessor just wrote), and its
+algorithmic bytes come from the per-DoF traffic model below.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu] [--no-variants]
 """
@@ -67,6 +69,13 @@ def traffic_model(dim, n, nlevels, bulk, var):
     return m, per_iter
 
 
+def unet_gflop(S):
+    """MFMA work of one U-Net forward on an S^3 grid (padded channel counts)."""
+    from paper_2402_12833_amd import CNN_LAYERS
+    level = {"w1": 0, "w2": 0, "w3": 1, "w4": 1, "w5": 2, "w6": 2, "w7": 1, "w8": 1, "w9": 0, "w10": 0, "w11": 0}
+    return sum(2.0 * (S >> level[name]) ** 3 * taps * cin * cout for name, taps, cin, cout in CNN_LAYERS) / 1e9
+
+
 def kernel_source_hash():
     """Hash of the device sources the counters were taken on."""
     import hashlib
@@ -102,12 +111,14 @@ def per_dof(dim, nlevels, bulk, var):
             "update_xP": 2 * b * bulk + 16 + bulk, "fine_W": b * bulk + bulk}
 
 
-def run_solver(amg, torch, prob, precision, steps, warmup, kappa=None):
+def run_solver(amg, torch, prob, precision, steps, warmup, kappa=None, net=None):
     import workloads as W
     b = torch.as_tensor(W.problem_rhs(prob), device="cuda")
     t0 = time.time()
     s = amg.Solver(prob.dim, prob.n, prob.nlevels, kappa=kappa, precision=precision)
     setup_s = time.time() - t0
+    if net is not None:
+        s.attach(net)
     x = torch.zeros_like(b)
     for _ in range(warmup):
         x.zero_()
@@ -153,7 +164,6 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--calibrate", action="store_true",
                     help="end with one plain 512 MiB read + 512 MiB write elementwise kernel (counter calibration)")
     args = ap.parse_args(argv)
@@ -173,13 +183,20 @@ def main(argv=None):
     s, b, x, ms, iters, setup_s, info = run_solver(amg, torch, prob, 0, args.steps, args.warmup)
     m, per_iter = traffic_model(prob.dim, prob.n, prob.nlevels, 8, False)
     gbs = per_iter * iters / (ms * 1e-3) / 1e9
-    kt = s.time_kernels(args.kernel_reps)
-    fine = {k: v for k, v in kt.items() if k in ("update_r", "fine_smooth", "fine_W", "update_xP", "spmm_gram")}
+    # kernel durations inside real iterations (each kernel on the data the
+    # previous one just wrote), HIP events on the solver's stream
+    x.zero_()
+    _, pinfo, sec, samples = s.profile_solve(b, x, tol=1e-8)
+    assert pinfo["status"] == amg.OK and pinfo["iterations"] == iters, pinfo
+    m["restrict"] = m.get("restrict_fine", 0) + m.get("restrict_coarse", 0)
+    m["prolong"] = m.get("prolong_all", 0)
+    fine = {k: sec[k] for k in ("update_r", "fine_smooth", "fine_W", "update_xP", "spmm_gram")}
     dom = max(fine, key=lambda k: fine[k])
     dom_bytes = m[dom]
-    achieved = dom_bytes / (kt[dom] * 1e-3) / 1e9
-    kernels = {k: {"ms": round(v, 5), "bytes": m.get(k), "GB/s": round(m[k] / (v * 1e-3) / 1e9, 1) if m.get(k) and v > 0 else None}
-               for k, v in kt.items()}
+    achieved = dom_bytes / (sec[dom] * 1e-3) / 1e9
+    kernels = {k: {"ms": round(v, 5), "bytes": m.get(k),
+                   "GB/s": round(m[k] / (v * 1e-3) / 1e9, 1) if m.get(k) and v > 0 else None}
+               for k, v in sec.items() if v > 0}
     out = {
         "metric": METRIC,
         "value": round(ms, 4),
@@ -204,8 +221,9 @@ def main(argv=None):
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
                      "bytes_per_launch": dom_bytes, "bytes_per_dof": per_dof(3, prob.nlevels, 8, False)[dom],
-                     "avg_launch_ms": round(kt[dom], 5)},
-        "kernels": kernels,
+                     "avg_launch_ms": round(sec[dom], 5), "launches_averaged": samples,
+                     "timing": "HIP events around the kernel inside the iterations of a solve of this workload"},
+        "kernels_in_solve": kernels,
     }
     s.close()
     if not args.no_variants:
@@ -224,6 +242,25 @@ def main(argv=None):
             var[f"diffusion3d_127_{tag}"] = {"ms": round(ms3, 4), "iterations": it3, "refreshes": info3["refreshes"],
                                              "hbm_GBps_algorithmic": round(pi3 * it3 / (ms3 * 1e-3) / 1e9, 1)}
             s3.close()
+        # the learned direction (committed trained weights) on the same problem
+        from paper_2402_12833_amd import train as T
+        net = amg.Network(dprob.n)
+        T.load_weights(net)
+        for prec, tag in ((0, "fp64"), (1, "fp32bulk")):
+            s4, b4, _, ms4, it4, _, info4 = run_solver(amg, torch, dprob, prec, args.steps, args.warmup, kappa=kap,
+                                                       net=net)
+            plain = var[f"diffusion3d_127_{tag}"]
+            var[f"diffusion3d_127_learned_{tag}"] = {
+                "ms": round(ms4, 4), "iterations": it4, "refreshes": info4["refreshes"], "nb": info4["nb"],
+                "iterations_plain": plain["iterations"], "time_vs_plain": round(ms4 / plain["ms"], 3)}
+            if prec == 0:
+                lk = s4.log_kappa()
+                fms = net.time_forward(b4, lk, reps=20)
+                gf = unet_gflop((dprob.n + 3) // 4 * 4)
+                var["unet_forward_128"] = {"ms": round(fms, 4), "gflop_padded": round(gf, 1),
+                                           "TFLOPs": round(gf / fms, 1), "bf16_peak_frac": round(gf / fms / 2500.0, 4)}
+            s4.close()
+        net.close()
         out["variants"] = var
     if not args.no_cpu:
         cpu_ms, cpu_it = cpu_baseline(prob)

@@ -167,6 +167,19 @@ int amgmpcg_batched_size(const amgmpcg_handle* h, int32_t* count, int64_t* total
  * residual (9 entries; 0 where a level does not exist). *count = entries. */
 int amgmpcg_time_kernels(amgmpcg_handle* h, int32_t reps, double* ms_out, int32_t cap, int32_t* count);
 
+/* Measurement aid: amgmpcg_solve with the iterations launched one by one
+ * (no graph) and HIP events between the kernel groups of each iteration, so
+ * every kernel runs on the data the previous one just wrote.  ms_out (HOST,
+ * cap doubles) receives the average duration in ms, over the iterations
+ * that ran in full (*samples of them; the last iteration, whose SpMM and
+ * alpha step the stop flag skips, is left out), of: update_r, fine_smooth,
+ * restrict, coarse_smooth, prolong, learned, fine_W, reduce_beta,
+ * update_xP, refresh, spmm_gram, reduce_alpha, whole iteration (13
+ * entries, *count = 13; 0 for a group that does not run).  b, x, tol, maxit
+ * and the result as for amgmpcg_solve (info->solve_ms = 0). */
+int amgmpcg_profile_solve(amgmpcg_handle* h, const double* b_dev, double* x_dev, double tol, int32_t maxit,
+                          amgmpcg_info* info, double* ms_out, int32_t cap, int32_t* count, int32_t* samples);
+
 /* The device pseudo-inverse used for the step coefficients (Sec. 2.2: the
  * Gram P^T A P may be singular), applied to one symmetric positive
  * semi-definite nb x nb matrix.  G, Gplus: HOST, nb*nb doubles row-major.

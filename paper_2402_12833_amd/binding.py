@@ -78,6 +78,9 @@ def load(path: str = LIB_PATH):
     lib.amgmpcg_history.argtypes = [c_void_p, c_int32, POINTER(c_double), POINTER(c_double), POINTER(c_int32)]
     lib.amgmpcg_time_kernels.argtypes = [c_void_p, c_int32, POINTER(c_double), c_int32, POINTER(c_int32)]
     lib.amgmpcg_time_kernels.restype = c_int32
+    lib.amgmpcg_profile_solve.argtypes = [c_void_p, c_void_p, c_void_p, c_double, c_int32, POINTER(Info),
+                                          POINTER(c_double), c_int32, POINTER(c_int32), POINTER(c_int32)]
+    lib.amgmpcg_profile_solve.restype = c_int32
     lib.amgmpcg_setup_batched.argtypes = [c_int32, POINTER(Grid), POINTER(Options), c_void_p, POINTER(c_void_p)]
     lib.amgmpcg_setup_batched.restype = c_int32
     lib.amgmpcg_solve_batched.argtypes = [c_void_p, c_void_p, c_void_p, c_double, c_int32, POINTER(Info),
@@ -310,6 +313,25 @@ class Solver:
         _check(self._lib.amgmpcg_time_kernels(self._h, reps, out.ctypes.data_as(POINTER(c_double)), 16,
                                               byref(cnt)))
         return {k: float(out[i]) for i, k in enumerate(self.KERNELS[: cnt.value])}
+
+    SECTIONS = ("update_r", "fine_smooth", "restrict", "coarse_smooth", "prolong", "learned", "fine_W",
+                "reduce_beta", "update_xP", "refresh", "spmm_gram", "reduce_alpha", "iteration")
+
+    def profile_solve(self, b, x=None, tol: float = 1e-8, maxit: int = 0):
+        """Solve with per-section HIP-event timing inside the iterations.
+
+        Returns (x, info, {section: average ms per full iteration}, samples)."""
+        import torch
+        if x is None:
+            x = torch.zeros_like(b)
+        out = np.zeros(16)
+        cnt, smp = c_int32(), c_int32()
+        info = Info()
+        code = self._lib.amgmpcg_profile_solve(self._h, self._vec(b, "b"), self._vec(x, "x"), float(tol), int(maxit),
+                                               byref(info), out.ctypes.data_as(POINTER(c_double)), 16, byref(cnt),
+                                               byref(smp))
+        _check(code, (OK, MAXIT, BREAKDOWN, NONFINITE))
+        return x, info.as_dict(), {k: float(out[i]) for i, k in enumerate(self.SECTIONS[: cnt.value])}, smp.value
 
     def history(self, cap: int = 100000) -> Tuple[np.ndarray, np.ndarray]:
         a = np.empty(cap * self.nb)

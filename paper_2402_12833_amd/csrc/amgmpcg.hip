@@ -48,7 +48,10 @@ struct ApiError : std::runtime_error {
         }                                                                                              \
     } while (0)
 
-constexpr int kMaxFineBlocks = 2048;
+#ifndef AMG_FINE_BLOCKS
+#define AMG_FINE_BLOCKS 2048
+#endif
+constexpr int kMaxFineBlocks = AMG_FINE_BLOCKS;   // blocks of the fine-level kernels (multiple of 8)
 constexpr int kTailMax = 4096;          // prolongation outputs up to this size: single-block chain
 constexpr int kRestrictTailMax = 512;   // restriction outputs up to this size: single-block chain
 constexpr int kPartRow = 2 + 1 + kMaxNB * kMaxNB + (kMaxNB * (kMaxNB + 1) / 2 + kMaxNB) + 1;
@@ -96,6 +99,8 @@ class SolverBase {
     virtual void level_stencil(int level, double* out) = 0;
     virtual void history(int cap, double* alpha, double* res, int* count) = 0;
     virtual int time_kernels(int reps, double* ms, int cap) = 0;
+    virtual int profile_solve(const double* b_dev, double* x_dev, double tol, int maxit, amgmpcg_info* info,
+                              double* ms, int cap, int* samples) = 0;
     virtual void attach(cnn::Net* net) = 0;
     virtual void residual(const double* b_dev, const double* x_dev, double* r_dev) = 0;
     virtual void make_pairs(const double* b_dev, const double* xs_dev, const int* ks, int nk, double* R_dev,
@@ -109,12 +114,16 @@ class SolverBase {
     std::vector<int> n_axis;   // per level, 0 = coarsest
 };
 
-static int fine_blocks(int N) {
+static int fine_blocks(int N, int cap = kMaxFineBlocks) {
     int b = (N + kBlock - 1) / kBlock;
-    if (b > kMaxFineBlocks) b = kMaxFineBlocks;
+    if (b > cap) b = cap;
     if (b >= kNumXcd) b = (b / kNumXcd) * kNumXcd;
     return b < 1 ? 1 : b;
 }
+
+// The block SpMM + Gram and W = Q^T Z kernels carry 27-44 accumulators per
+// thread: fewer, longer-running blocks amortise their block reductions.
+constexpr int kGramBlocks = 1024;
 
 template <typename T, int DIM>
 class Solver : public SolverBase {
@@ -135,6 +144,7 @@ class Solver : public SolverBase {
         rows_.nxp = (g.n + 63) / 64 * 64;
         rows_.total = (int)host::ipow(g.n, DIM - 1) * rows_.nxp;
         FB_ = fine_blocks(rows_.total);
+        FBG_ = fine_blocks(rows_.total, kGramBlocks);
 
         // ---- host hierarchy (FP64) -------------------------------------
         const bool var = g.kappa != nullptr;
@@ -163,10 +173,14 @@ class Solver : public SolverBase {
         fop_.N = N;
         fop_.s0 = T(h2inv);
         fop_.D = fop_.ex = fop_.ey = fop_.ez = nullptr;
+        fop_.inv0 = T(1.0 / (2.0 * DIM * h2inv));
+        fop_.iD = nullptr;
         f64_.n = g.n;
         f64_.N = N;
         f64_.s0 = h2inv;
         f64_.D = f64_.ex = f64_.ey = f64_.ez = nullptr;
+        f64_.inv0 = 1.0 / (2.0 * DIM * h2inv);
+        f64_.iD = nullptr;
         if (var) {
             upload_faces(faces);
         }
@@ -337,8 +351,8 @@ class Solver : public SolverBase {
             const int nc = L_ > 0 ? n_axis[L_ - 1] : 1;
             k_update_xP<DIM, T, NB, 0><<<FB_, kBlock, 0, s>>>(ctl_proj_, rows_, fine_Y(), nc, cL_final_, nullptr,
                                                                nullptr, P_.p, x_.p, d_alpha(), d_beta(), 1);
-            k_spmm_gram<DIM, T, NB><<<FB_, kBlock, 0, s>>>(ctl_proj_, rows_, fop_, P_.p, Q_.p, r_dev, part_G());
-            k_reduce_alpha<NB><<<1, kRedBlock, 0, s>>>(ctl_proj_, part_G(), FB_, d_Gplus(), d_alpha(), nullptr);
+            k_spmm_gram<DIM, T, NB><<<FBG_, kBlock, 0, s>>>(ctl_proj_, rows_, fop_, P_.p, Q_.p, r_dev, part_G());
+            k_reduce_alpha<NB><<<1, kRedBlock, 0, s>>>(ctl_proj_, part_G(), FBG_, d_Gplus(), d_alpha(), nullptr);
             HIPCHK(hipMemcpyAsync(rhat_dev, r_dev, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, s));
             k_update_r<T, NB><<<FB_, kBlock, 0, s>>>(ctl_proj_, N, Q_.p, d_alpha(), rhat_dev, part_rho());
         });
@@ -380,6 +394,7 @@ class Solver : public SolverBase {
         if (hctl_in_) (void)hipHostFree(hctl_in_);
         if (ev0_) (void)hipEventDestroy(ev0_);
         if (ev1_) (void)hipEventDestroy(ev1_);
+        for (hipEvent_t e : prof_ev_) (void)hipEventDestroy(e);
     }
 
     int solve(const double* b_dev, double* x_dev, double tol, int maxit, amgmpcg_info* info) override {
@@ -511,7 +526,7 @@ class Solver : public SolverBase {
             }
             enqueue_mg(cf, r_.p);
             timed([&] {
-                k_fine_W<DIM, T, NB, NE><<<FB_, kBlock, 0, stream_>>>(cf, rows_, fine_Y(), nc, cL_final_, dl(), dflag(),
+                k_fine_W<DIM, T, NB, NE><<<FBG_, kBlock, 0, stream_>>>(cf, rows_, fine_Y(), nc, cL_final_, dl(), dflag(),
                                                                       Q_.p, part_W());
             });
             timed([&] {
@@ -519,7 +534,7 @@ class Solver : public SolverBase {
                                                                          dflag(), P_.p, x_.p,
                                                                       d_alpha(), d_beta(), 0);
             });
-            timed([&] { k_spmm_gram<DIM, T, NB><<<FB_, kBlock, 0, stream_>>>(cf, rows_, fop_, P_.p, Q_.p, r_.p, part_G()); });
+            timed([&] { k_spmm_gram<DIM, T, NB><<<FBG_, kBlock, 0, stream_>>>(cf, rows_, fop_, P_.p, Q_.p, r_.p, part_G()); });
             timed([&] { k_init_residual<DIM><<<FB_, kBlock, 0, stream_>>>(rows_, f64_, b_.p, x_.p, r_.p, part_init()); });
         });
         return count;
@@ -585,6 +600,19 @@ class Solver : public SolverBase {
             upload_conv(d.p, v);
         };
         up(fD_, f.D);
+        {
+            std::vector<double> inv(f.D.size());
+            for (size_t i = 0; i < inv.size(); ++i) inv[i] = 1.0 / f.D[i];
+            up(fiD_, inv);
+            fop_.iD = fiD_.p;
+            if (std::is_same<T, double>::value) {
+                f64_.iD = (const double*)fiD_.p;
+            } else {
+                giD_.alloc(inv.size());
+                HIPCHK(hipMemcpy(giD_.p, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice));
+                f64_.iD = giD_.p;
+            }
+        }
         up(fex_, f.ex);
         up(fey_, f.ey);
         if (DIM == 3) up(fez_, f.ez);
@@ -673,7 +701,10 @@ class Solver : public SolverBase {
     // Z = MG(r): every level correction and, when attached, the learned one.
     void enqueue_mg(const Ctl* ctl, const double* r) {
         enqueue_levels(ctl, r);
-        if (net_) enqueue_learned(ctl, r);
+        if (net_) {
+            mark(kSecLearned);
+            enqueue_learned(ctl, r);
+        }
     }
 
     void enqueue_levels(const Ctl* ctl, const double* r) {
@@ -683,6 +714,7 @@ class Solver : public SolverBase {
         const int two = nu >= 2 ? 1 : 0;
         const int extra = nu > 2 ? nu - 2 : 0;
         // fine smoother
+        mark(kSecFineSmooth);
         {
             T* first = (extra % 2 == 0) ? cL_.p : cL2_.p;
             T* other = (extra % 2 == 0) ? cL2_.p : cL_.p;
@@ -697,6 +729,7 @@ class Solver : public SolverBase {
         }
         if (L == 0) return;
         // restriction chain: big levels one launch each, the small ones in one block
+        mark(kSecRestrict);
         {
             const int l = L - 1;
             k_restrict<DIM, double, T><<<(N_[l] + kBlock - 1) / kBlock, kBlock, 0, stream_>>>(
@@ -722,6 +755,7 @@ class Solver : public SolverBase {
         }
         // all coarse levels smoothed in one launch (per sweep); the final sweep
         // writes c_l into the last column of the level's block carry
+        mark(kSecCoarseSmooth);
         {
             const int two_f = two;
             if (extra == 0) {
@@ -748,6 +782,7 @@ class Solver : public SolverBase {
             }
         }
         // prolongation chain Y_{l+1}[:, 0..l] = P Y_l: small levels in one block
+        mark(kSecProlong);
         {
             int l = 0;
             ProlongChain<T> ch{};
@@ -786,8 +821,8 @@ class Solver : public SolverBase {
             const int nc = L_ > 0 ? n_axis[L_ - 1] : 1;
             k_update_xP<DIM, T, NB, NE><<<FB_, kBlock, 0, stream_>>>(ctl_, rows_, fine_Y(), nc, cL_final_, dl(),
                                                                        dflag(), P_.p, x_.p, d_alpha(), d_beta(), 1);
-            k_spmm_gram<DIM, T, NB><<<FB_, kBlock, 0, stream_>>>(ctl_, rows_, fop_, P_.p, Q_.p, r_.p, part_G());
-            k_reduce_alpha<NB><<<1, kRedBlock, 0, stream_>>>(ctl_, part_G(), FB_, d_Gplus(), d_alpha(),
+            k_spmm_gram<DIM, T, NB><<<FBG_, kBlock, 0, stream_>>>(ctl_, rows_, fop_, P_.p, Q_.p, r_.p, part_G());
+            k_reduce_alpha<NB><<<1, kRedBlock, 0, stream_>>>(ctl_, part_G(), FBG_, d_Gplus(), d_alpha(),
                                                           hist_cap_ ? ahist_.p : nullptr);
         });
     }
@@ -800,24 +835,111 @@ class Solver : public SolverBase {
             constexpr int NB = decltype(nbc)::value;
             [[maybe_unused]] constexpr int NE = decltype(nbc)::ne;
             const int nc = L_ > 0 ? n_axis[L_ - 1] : 1;
+            mark(kSecUpdateR);
             k_update_r<T, NB><<<FB_, kBlock, 0, s>>>(ctl_, N, Q_.p, d_alpha(), r_.p, part_rho());
             enqueue_mg(ctl_, r_.p);
-            k_fine_W<DIM, T, NB, NE><<<FB_, kBlock, 0, s>>>(ctl_, rows_, fine_Y(), nc, cL_final_, dl(), dflag(), Q_.p,
+            mark(kSecFineW);
+            k_fine_W<DIM, T, NB, NE><<<FBG_, kBlock, 0, s>>>(ctl_, rows_, fine_Y(), nc, cL_final_, dl(), dflag(), Q_.p,
                                                          part_W());
-            k_reduce_beta<NB><<<1, kRedBlock, 0, s>>>(ctl_, part_rho(), part_W(), FB_, d_Gplus(), d_beta(),
+            mark(kSecReduceBeta);
+            k_reduce_beta<NB><<<1, kRedBlock, 0, s>>>(ctl_, part_rho(), FB_, part_W(), FBG_, d_Gplus(), d_beta(),
                                                    hist_cap_ ? rhist_.p : nullptr, mixed_ ? 1 : 0);
+            mark(kSecUpdateXP);
             k_update_xP<DIM, T, NB, NE><<<FB_, kBlock, 0, s>>>(ctl_, rows_, fine_Y(), nc, cL_final_, dl(), dflag(), P_.p,
                                                             x_.p, d_alpha(), d_beta(), 0);
             if (mixed_) {
+                mark(kSecRefresh);
                 k_refresh<DIM><<<FB_, kBlock, 0, s>>>(ctl_, rows_, f64_, b_.p, x_.p, r_.p, part_ref());
                 k_refresh_reduce<<<1, kRedBlock, 0, s>>>(ctl_, part_ref(), FB_, hist_cap_ ? rhist_.p : nullptr);
             }
-            k_spmm_gram<DIM, T, NB><<<FB_, kBlock, 0, s>>>(ctl_, rows_, fop_, P_.p, Q_.p, r_.p, part_G());
-            k_reduce_alpha<NB><<<1, kRedBlock, 0, s>>>(ctl_, part_G(), FB_, d_Gplus(), d_alpha(),
+            mark(kSecSpmmGram);
+            k_spmm_gram<DIM, T, NB><<<FBG_, kBlock, 0, s>>>(ctl_, rows_, fop_, P_.p, Q_.p, r_.p, part_G());
+            mark(kSecReduceAlpha);
+            k_reduce_alpha<NB><<<1, kRedBlock, 0, s>>>(ctl_, part_G(), FBG_, d_Gplus(), d_alpha(),
                                                     hist_cap_ ? ahist_.p : nullptr);
+            mark(kSecEnd);
         });
         stream_ = saved;
     }
+
+    // ---- per-section timing inside real iterations --------------------
+    // mark(sec) records an event before the launches of section sec; a
+    // section lasts until the next mark.  A no-op outside profile_solve, in
+    // particular during graph capture.
+    void mark(int sec) {
+        if (!prof_on_) return;
+        if (prof_n_ == (int)prof_ev_.size()) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            prof_ev_.push_back(e);
+        }
+        HIPCHK(hipEventRecord(prof_ev_[prof_n_], stream_));
+        prof_sec_.resize(prof_n_ + 1);
+        prof_sec_[prof_n_++] = sec;
+    }
+
+    // As solve(), with each iteration launched eagerly between events: the
+    // average duration (ms) of each section over the iterations that ran in
+    // full (not the last, whose SpMM and alpha step the stop flag skips).
+    int profile_solve(const double* b_dev, double* x_dev, double tol, int maxit, amgmpcg_info* info, double* ms,
+                      int cap, int* samples) override {
+        const int N = N_[L_];
+        if (maxit <= 0) maxit = opt_.maxit;
+        Ctl& c = *hctl_in_;
+        std::memset(&c, 0, sizeof(Ctl));
+        c.maxit = maxit;
+        c.hist_cap = std::min(hist_cap_, maxit);
+        c.drop2 = opt_.refresh_drop * opt_.refresh_drop;
+        c.tau = tau_;
+        HIPCHK(hipMemcpyAsync(ctl_, hctl_in_, sizeof(Ctl), hipMemcpyHostToDevice, stream_));
+        HIPCHK(hipMemcpyAsync(b_.p, b_dev, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, stream_));
+        HIPCHK(hipMemcpyAsync(x_.p, x_dev, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, stream_));
+        enqueue_init(tol);
+        HIPCHK(hipGetLastError());
+        double sum[kSecCount] = {0.0};
+        int full = 0;
+        for (int it = 0; it <= maxit; ++it) {
+            HIPCHK(hipMemcpyAsync(hctl_, ctl_, sizeof(Ctl), hipMemcpyDeviceToHost, stream_));
+            HIPCHK(hipStreamSynchronize(stream_));
+            if (hctl_->state != 0) break;
+            prof_on_ = true;
+            prof_n_ = 0;
+            enqueue_iteration(stream_);
+            prof_on_ = false;
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipMemcpyAsync(hctl_, ctl_, sizeof(Ctl), hipMemcpyDeviceToHost, stream_));
+            HIPCHK(hipStreamSynchronize(stream_));
+            if (hctl_->state != 0) continue;   // the stopping iteration: partly skipped
+            ++full;
+            for (int k = 0; k + 1 < prof_n_; ++k) {
+                float t = 0.f;
+                HIPCHK(hipEventElapsedTime(&t, prof_ev_[k], prof_ev_[k + 1]));
+                sum[prof_sec_[k]] += t;
+            }
+            float t = 0.f;
+            HIPCHK(hipEventElapsedTime(&t, prof_ev_[0], prof_ev_[prof_n_ - 1]));
+            sum[kSecEnd] += t;
+        }
+        HIPCHK(hipMemcpyAsync(x_dev, x_.p, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, stream_));
+        HIPCHK(hipMemcpyAsync(hctl_, ctl_, sizeof(Ctl), hipMemcpyDeviceToHost, stream_));
+        HIPCHK(hipStreamSynchronize(stream_));
+        const Ctl& h = *hctl_;
+        last_iters_ = h.it;
+        const int status = h.state == 2 ? h.status : AMGMPCG_MAXIT;
+        if (info) {
+            info->status = status;
+            info->iterations = h.it;
+            info->bnorm = std::sqrt(h.bnorm2);
+            info->relres = h.bnorm2 > 0 ? std::sqrt(h.rho / h.bnorm2) : 0.0;
+            info->refreshes = h.refreshes;
+            info->nb = nb;
+            info->solve_ms = 0.0;
+        }
+        for (int k = 0; k < kSecCount && k < cap; ++k) ms[k] = full ? sum[k] / full : 0.0;
+        if (samples) *samples = full;
+        return kSecCount;
+    }
+
 
     void capture_graph() {
         if (!cap_stream_) HIPCHK(hipStreamCreateWithFlags(&cap_stream_, hipStreamNonBlocking));
@@ -830,6 +952,27 @@ class Solver : public SolverBase {
         graph_ready_ = true;
     }
 
+    enum : int {
+        kSecUpdateR,
+        kSecFineSmooth,
+        kSecRestrict,
+        kSecCoarseSmooth,
+        kSecProlong,
+        kSecLearned,
+        kSecFineW,
+        kSecReduceBeta,
+        kSecUpdateXP,
+        kSecRefresh,
+        kSecSpmmGram,
+        kSecReduceAlpha,
+        kSecEnd,          // slot of the whole iteration
+        kSecCount
+    };
+    bool prof_on_ = false;
+    int prof_n_ = 0;
+    std::vector<hipEvent_t> prof_ev_;
+    std::vector<int> prof_sec_;
+
     amgmpcg_options opt_;
     hipStream_t stream_;
     hipStream_t cap_stream_ = nullptr;
@@ -837,14 +980,14 @@ class Solver : public SolverBase {
     hipGraphExec_t exec_ = nullptr;
     bool graph_ready_ = false;
     bool mixed_ = false;
-    int L_ = 0, FB_ = 1, hist_cap_ = 0, last_iters_ = 0;
+    int L_ = 0, FB_ = 1, FBG_ = 1, hist_cap_ = 0, last_iters_ = 0;
     double tau_ = 0.0;
     std::vector<int> N_;
     FineOp<T> fop_{};
     Rows rows_{};
     FineOp<double> f64_{};
-    DevBuf<T> fD_, fex_, fey_, fez_;
-    DevBuf<double> gD_, gex_, gey_, gez_;
+    DevBuf<T> fD_, fex_, fey_, fez_, fiD_;
+    DevBuf<double> gD_, gex_, gey_, gez_, giD_;
     std::vector<DevBuf<T>> coef_, g_, c1_, c_, c2_, Y_;
     T* cL_final_ = nullptr;
     DevBuf<double> x_, r_, b_, part_, small_, ahist_, rhist_;
@@ -1261,6 +1404,23 @@ int amgmpcg_time_kernels(amgmpcg_handle* h, int32_t reps, double* ms_out, int32_
         const int c = h->s->time_kernels(reps, ms_out, cap);
         if (count) *count = c;
         return AMGMPCG_OK;
+    });
+}
+
+int amgmpcg_profile_solve(amgmpcg_handle* h, const double* b_dev, double* x_dev, double tol, int32_t maxit,
+                          amgmpcg_info* info, double* ms_out, int32_t cap, int32_t* count, int32_t* samples) {
+    return guarded([&]() -> int {
+        if (!h || !h->s) throw ApiError(AMGMPCG_INVALID_ARG, "handle is NULL");
+        if (!b_dev || !x_dev || !ms_out) throw ApiError(AMGMPCG_INVALID_ARG, "NULL argument");
+        if (!(tol >= 0.0) || !std::isfinite(tol)) throw ApiError(AMGMPCG_INVALID_ARG, "tol must be finite and >= 0");
+        if (cap < 0) throw ApiError(AMGMPCG_INVALID_ARG, "cap must be >= 0");
+        amgmpcg_info local{};
+        int smp = 0;
+        const int c = h->s->profile_solve(b_dev, x_dev, tol, maxit, &local, ms_out, cap, &smp);
+        if (info) *info = local;
+        if (count) *count = c;
+        if (samples) *samples = smp;
+        return local.status;
     });
 }
 

@@ -203,8 +203,8 @@ __device__ void solve_instance(const BInst<T>& I, const BatchParams& bp, BOut& o
     __shared__ BShared<NB> sh;
     const int nf = I.n[L], N = I.N[L];
     const double h2inv = double(nf + 1) * double(nf + 1);
-    FineOp<T> op{nf, N, T(h2inv), nullptr, nullptr, nullptr, nullptr};
-    FineOp<double> op64{nf, N, h2inv, nullptr, nullptr, nullptr, nullptr};
+    FineOp<T> op{nf, N, T(h2inv), nullptr, nullptr, nullptr, nullptr, T(1.0 / (2 * DIM * h2inv)), nullptr};
+    FineOp<double> op64{nf, N, h2inv, nullptr, nullptr, nullptr, nullptr, 1.0 / (2 * DIM * h2inv), nullptr};
     const T omega = T(bp.omega);
     const int nc = L > 0 ? I.n[L - 1] : 1;
     const T* Ytop = L > 0 ? I.Y[L - 1] : nullptr;

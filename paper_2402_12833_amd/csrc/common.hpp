@@ -117,28 +117,63 @@ __device__ __forceinline__ void block_sum_store(const double (&v)[K], double* pa
 constexpr int kRedBlock = 1024;    // threads of the single-block reduction kernels
 constexpr int kRedWaves = kRedBlock / 64;
 
-// Reduce the value-major partials part[k * nblk + b] (b < nblk) of K values
-// into res[k] (shared memory).  Wave w sums values k = w, w + 16, ...: each
-// lane adds rows lane, lane + 64, ... in order, then a butterfly; fixed order.
+// Thread t's sum of rows t, t + kRedBlock, ... of each of K value-major
+// partial arrays part[k * nblk + b] (b < nblk), fixed order.  For
+// nblk <= kRedBlock that is one load per value, all issued together.
+template <int K>
+__device__ __forceinline__ void partial_rows(const double* __restrict__ part, int nblk, double (&v)[K]) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = 0.0;
+    if (t < nblk) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = part[(size_t)k * nblk + t];
+    }
+    for (int b = t + kRedBlock; b < nblk; b += kRedBlock) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] += part[(size_t)k * nblk + b];
+    }
+}
+
+// Sum K per-thread values over a kRedBlock block into res[0 .. count)
+// (shared): the waves reduce by recursive halving, then the wave sums are
+// added in wave order.  Fixed order: deterministic.
+template <int K>
+__device__ __forceinline__ void block_reduce(double (&v)[K], double* res, int count = K) {
+    constexpr int KP = pow2_up(K);
+    __shared__ double sh[kRedWaves][KP];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int vi = wave_reduce_multi<K>(v);
+    if ((lane & (64 / KP - 1)) == 0) sh[w][vi] = v[0];
+    __syncthreads();
+    for (int k = t; k < count; k += kRedBlock) {
+        double s = sh[0][k];
+#pragma unroll
+        for (int q = 1; q < kRedWaves; ++q) s += sh[q][k];
+        res[k] = s;
+    }
+    __syncthreads();
+}
+
+// Reduce the value-major partials part[k * nblk + b] of K values into res[k]
+// (shared memory); groups of up to 40 values, each with its loads in flight
+// together.
 template <int K>
 __device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int nblk,
                                                 double* res /* shared, K */) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int k = w; k < K; k += kRedWaves) {
-        const double* p = part + (size_t)k * nblk;
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        int b = lane;
-        for (; b + 192 < nblk; b += 256) {
-            s0 += p[b];
-            s1 += p[b + 64];
-            s2 += p[b + 128];
-            s3 += p[b + 192];
+    constexpr int GK = K <= 40 ? K : 32;
+    for (int k0 = 0; k0 < K; k0 += GK) {
+        double v[GK];
+        if (k0 + GK <= K) {
+            partial_rows<GK>(part + (size_t)k0 * nblk, nblk, v);
+        } else {
+#pragma unroll
+            for (int g = 0; g < GK; ++g) v[g] = 0.0;
+            for (int g = 0; g < K - k0; ++g)
+                for (int b = threadIdx.x; b < nblk; b += kRedBlock) v[g] += part[(size_t)(k0 + g) * nblk + b];
         }
-        for (; b < nblk; b += 64) s0 += p[b];
-        const double s = wave_sum((s0 + s1) + (s2 + s3));
-        if (lane == 0) res[k] = s;
+        block_reduce<GK>(v, res + k0, K - k0 < GK ? K - k0 : GK);
     }
-    __syncthreads();
 }
 
 }  // namespace amg

@@ -53,11 +53,19 @@ struct FineOp {
     const T* ex;           // coupling to +x neighbour (positive)
     const T* ey;
     const T* ez;
+    T inv0;                // 1 / (2 dim h^-2) (constant coefficient)
+    const T* iD;           // variable coefficient: 1 / diagonal (rounded once)
 };
 
 template <int DIM, typename T>
 __device__ __forceinline__ T fine_diag(const FineOp<T>& op, int idx) {
     return op.D ? op.D[idx] : T(2 * DIM) * op.s0;
+}
+
+// 1 / D, precomputed: the smoother multiplies by it instead of dividing.
+template <int DIM, typename T>
+__device__ __forceinline__ T fine_invdiag(const FineOp<T>& op, int idx) {
+    return op.iD ? op.iD[idx] : op.inv0;
 }
 
 // (A u)_idx on the finest level, computed in type C.
@@ -275,17 +283,36 @@ __device__ __forceinline__ bool row_item(const Rows& R, int w, Idx<DIM>& p, int&
     return act;
 }
 
-// Each block walks one contiguous range of rows (kBlock items at a time);
-// with the XCD-aware logical block index, each XCD owns a contiguous slab.
-__device__ __forceinline__ int row_chunk(int total) {
-    const int per = (total + gridDim.x - 1) / gridDim.x;
-    return (per + kBlock - 1) / kBlock * kBlock;
+// Each XCD (blocks b with the same b % 8) owns one contiguous slab of the
+// rows, and its blocks walk the slab together, kBlock items per block and
+// step, block j of the XCD taking the j-th kBlock items of each step's band.
+// The XCD's resident blocks thus cover a thin band of consecutive rows at a
+// time, so the +-y and +-z neighbours (and coarse interpolation parents) a
+// kernel reads were fetched shortly before by a block of the same XCD and
+// are still in that XCD's L2.  Grids whose size is not a multiple of 8 walk
+// the whole range as one slab.
+struct Band {
+    int start, end, stride;
+};
+
+__device__ __forceinline__ Band row_band(int total) {
+    const int g = gridDim.x;
+    const int x = (g % kNumXcd) ? 0 : (int)blockIdx.x % kNumXcd;
+    const int nb = (g % kNumXcd) ? g : g / kNumXcd;
+    const int j = (g % kNumXcd) ? (int)blockIdx.x : (int)blockIdx.x / kNumXcd;
+    const int slabs = (g % kNumXcd) ? 1 : kNumXcd;
+    const int per = ((total + slabs - 1) / slabs + kBlock - 1) / kBlock * kBlock;
+    Band b;
+    b.start = x * per + j * kBlock + (int)threadIdx.x;
+    b.end = min(total, (x + 1) * per);
+    b.stride = nb * kBlock;
+    return b;
 }
 
+// lb: the block's index for its reduction partials (unused by the walk).
 #define ROW_LOOP(R, lb)                                                                           \
-    for (int c_ = row_chunk((R).total), w_ = (lb) * c_ + (int)threadIdx.x,                        \
-             e_ = min((R).total, ((lb) + 1) * c_);                                                \
-         w_ < e_; w_ += kBlock)
+    for (Band b_ = row_band((R).total), *bp_ = &b_; bp_; bp_ = nullptr)                            \
+        for (int w_ = b_.start; w_ < b_.end; w_ += b_.stride)
 
 // Branch-free x-axis interpolation parents: two (possibly equal) coarse
 // indices with weights (1, 0) on a coarse node, (1/2, 1/2) between two, and a
@@ -565,11 +592,11 @@ __device__ __forceinline__ T fine_smooth_at(const FineOp<T>& op, const G* __rest
                                             T omega, int two_sweeps) {
     const int n = op.n, sy = n, sz = n * n;
     const T gi = T(g[idx]);
-    const T Di = fine_diag<DIM>(op, idx);
-    const T c1 = omega * (gi / Di);
+    const T iDi = fine_invdiag<DIM>(op, idx);
+    const T c1 = omega * (gi * iDi);
     if (!two_sweeps) return c1;
-    // A c1 with c1_j = omega (g_j / D_j) formed on the fly
-    auto c1at = [&](int j) -> T { return omega * (T(g[j]) / fine_diag<DIM>(op, j)); };
+    // A c1 with c1_j = omega g_j / D_j formed on the fly
+    auto c1at = [&](int j) -> T { return omega * (T(g[j]) * fine_invdiag<DIM>(op, j)); };
     T Ac;
     if (!op.D) {
         T acc = T(2 * DIM) * c1;
@@ -583,7 +610,7 @@ __device__ __forceinline__ T fine_smooth_at(const FineOp<T>& op, const G* __rest
         }
         Ac = op.s0 * acc;
     } else {
-        T acc = Di * c1;
+        T acc = op.D[idx] * c1;
         if (p.i > 0) acc -= op.ex[idx - 1] * c1at(idx - 1);
         if (p.i < n - 1) acc -= op.ex[idx] * c1at(idx + 1);
         if (p.j > 0) acc -= op.ey[idx - sy] * c1at(idx - sy);
@@ -594,7 +621,7 @@ __device__ __forceinline__ T fine_smooth_at(const FineOp<T>& op, const G* __rest
         }
         Ac = acc;
     }
-    return c1 + omega * ((gi - Ac) / Di);
+    return c1 + omega * ((gi - Ac) * iDi);
 }
 
 template <int DIM, typename T, typename G>
@@ -623,7 +650,7 @@ __global__ void __launch_bounds__(kBlock) k_fine_sweep(const Ctl* __restrict__ c
         int idx;
         if (!row_item<DIM>(R, w_, p, idx)) continue;
         const T res = T(g[idx]) - fine_apply<DIM, T>(op, cin, idx, p);
-        cout[idx] = cin[idx] + omega * (res / fine_diag<DIM>(op, idx));
+        cout[idx] = cin[idx] + omega * (res * fine_invdiag<DIM>(op, idx));
     }
 }
 

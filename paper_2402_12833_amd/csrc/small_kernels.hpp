@@ -147,14 +147,27 @@ __global__ void __launch_bounds__(kRedBlock) k_reduce_init(Ctl* ctl, const doubl
 // mixed != 0: convergence on the recursive residual only requests a
 // true-residual refresh; the refresh decides.
 template <int NB>
-__global__ void __launch_bounds__(kRedBlock) k_reduce_beta(Ctl* ctl, const double* part_rho, const double* part_W,
-                                                        int nblk, const double* Gplus, double* beta, double* rhist,
-                                                        int mixed) {
+__global__ void __launch_bounds__(kRedBlock) k_reduce_beta(Ctl* ctl, const double* part_rho, int nblk_rho,
+                                                        const double* part_W, int nblk_W, const double* Gplus,
+                                                        double* beta, double* rhist, int mixed) {
     if (ctl->state != 0) return;
-    __shared__ double rho_s[1];
-    __shared__ double W[NB * NB];
-    reduce_partials<1>(part_rho, nblk, rho_s);
-    reduce_partials<NB * NB>(part_W, nblk, W);
+    __shared__ double red[1 + NB * NB];
+    double* rho_s = red;
+    double* W = red + 1;
+    if constexpr (1 + NB * NB <= 40) {
+        // ||r||^2 and W in one round of loads
+        double v[1 + NB * NB];
+        double v0[1], vW[NB * NB];
+        partial_rows<1>(part_rho, nblk_rho, v0);
+        partial_rows<NB * NB>(part_W, nblk_W, vW);
+        v[0] = v0[0];
+#pragma unroll
+        for (int k = 0; k < NB * NB; ++k) v[1 + k] = vW[k];
+        block_reduce<1 + NB * NB>(v, red);
+    } else {
+        reduce_partials<1>(part_rho, nblk_rho, rho_s);
+        reduce_partials<NB * NB>(part_W, nblk_W, W);
+    }
     __shared__ int stop;
     if (threadIdx.x == 0) {
         const double rho = rho_s[0];

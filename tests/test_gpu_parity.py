@@ -316,3 +316,22 @@ def test_smoothing_sweeps(case, nu):
     o = mpcg.mpcg(h, b, tol=0.0, maxit=k, nu=nu)
     assert rel(host(xg), o.x) <= 1e-10
     s.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_profile_solve_matches_solve(precision):
+    # the event-instrumented eager iteration computes the same iterates as the graph
+    dim, n, nl, seed = 3, 31, 4, 41
+    kap = np.exp(2.0 * W.gaussian_field(n, 3, 42, periodic=64))
+    s = amg.Solver(dim, n, nl, kappa=kap, precision=precision)
+    b = dev(W.rhs(n ** dim, seed))
+    x1, i1 = s.solve(b, tol=1e-8)
+    x2, i2, sec, samples = s.profile_solve(b, tol=1e-8)
+    assert i1["status"] == i2["status"] == amg.OK
+    assert i1["iterations"] == i2["iterations"]
+    assert torch.equal(x1, x2)
+    assert samples == i1["iterations"] - 1
+    parts = sum(v for k, v in sec.items() if k != "iteration")
+    assert sec["spmm_gram"] > 0 and sec["update_xP"] > 0 and sec["iteration"] > 0
+    assert abs(parts - sec["iteration"]) <= 0.05 * sec["iteration"]
+    assert (sec["refresh"] > 0) == (precision == 1)
