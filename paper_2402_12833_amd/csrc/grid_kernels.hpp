@@ -283,6 +283,13 @@ __device__ __forceinline__ bool row_item(const Rows& R, int w, Idx<DIM>& p, int&
     return act;
 }
 
+// The unclamped x index of item w in its row (lanes past the row end
+// included).
+__device__ __forceinline__ int row_x(const Rows& R, int w) {
+    const int w0 = __builtin_amdgcn_readfirstlane(w);
+    return w - (w0 / R.nxp) * R.nxp;
+}
+
 // Each XCD (blocks b with the same b % 8) owns one contiguous slab of the
 // rows, and its blocks walk the slab together, kBlock items per block and
 // step, block j of the XCD taking the j-th kBlock items of each step's band.
@@ -393,6 +400,64 @@ __device__ __forceinline__ void fine_z(const T* __restrict__ Y, int nc, const T*
         interp_block<DIM, T, SY>(Y, nc, px, py, pz, zy);
 #pragma unroll
         for (int c = 0; c < NL - 1; ++c) z[c] = zy[c];
+    }
+    z[NL - 1] = cL[idx];
+    if (NE) z[NB - 1] = dzero ? T(0) : dl[idx];
+}
+
+// fine_z for a whole wavefront (all 64 lanes must call it; lanes past the
+// row end use a clamped node and their result is discarded).  The wave's 64
+// fine nodes lie in one x-row, so their y/z parents are common and their x
+// parents are 33 consecutive coarse nodes: lane l (< 33) first combines the
+// y/z parents at coarse x = i0/2 - 1 + l into one value per column, and each
+// fine lane then takes its two x parents from those lanes by shuffles.  Per
+// fine node that is a quarter of the coarse loads of fine_z.
+template <int DIM, typename T, int NB, int NE>
+__device__ __forceinline__ void fine_z_wave(const T* __restrict__ Y, int nc, const T* __restrict__ cL,
+                                            const T* __restrict__ dl, bool dzero, int idx, const Idx<DIM>& p,
+                                            int i_row, T (&z)[NB]) {
+    constexpr int NL = NB - NE;
+    if constexpr (NL > 1) {
+        constexpr int SY = even_up(NL > 1 ? NL - 1 : 1);
+        const int lane = threadIdx.x & 63;
+        const int i0 = __builtin_amdgcn_readfirstlane(i_row);
+        const int jb = (i0 >> 1) - 1;
+        const Par py = parents(p.j, nc);
+        const Par pz = DIM == 3 ? parents(p.k, nc) : Par{0, 0, 1.f, 0.f, 1};
+        const int J = jb + lane;
+        const bool jin = lane <= 32 && J >= 0 && J < nc;
+        const int Jc = jin ? J : 0;
+        T row[SY];
+#pragma unroll
+        for (int c = 0; c < SY; ++c) row[c] = T(0);
+        if (jin) {
+            const int nzc = DIM == 3 ? pz.cnt : 1;
+            for (int cz = 0; cz < nzc; ++cz) {
+                const int K = DIM == 3 ? (cz ? pz.hi : pz.lo) : 0;
+                const T wz = DIM == 3 ? T(cz ? pz.whi : pz.wlo) : T(1);
+                T plane[SY];
+#pragma unroll
+                for (int c = 0; c < SY; ++c) plane[c] = T(0);
+                for (int b = 0; b < py.cnt; ++b) {
+                    const int Jy = b ? py.hi : py.lo;
+                    const T wy = T(b ? py.whi : py.wlo);
+                    T v[SY];
+                    load_node<T, SY>(Y + ((size_t)nc * (Jy + (size_t)nc * K) + Jc) * SY, v);
+#pragma unroll
+                    for (int c = 0; c < SY; ++c) plane[c] += wy * v[c];
+                }
+#pragma unroll
+                for (int c = 0; c < SY; ++c) row[c] += wz * plane[c];
+            }
+        }
+        const XPar px = xparents(p.i, nc);
+        const int llo = min(max(px.lo - jb, 0), 32), lhi = min(max(px.hi - jb, 0), 32);
+#pragma unroll
+        for (int c = 0; c < NL - 1; ++c) {
+            const T a = __shfl(row[c], llo);
+            const T b2 = __shfl(row[c], lhi);
+            z[c] = T(px.wlo) * a + T(px.whi) * b2;
+        }
     }
     z[NL - 1] = cL[idx];
     if (NE) z[NB - 1] = dzero ? T(0) : dl[idx];
@@ -851,9 +916,10 @@ __global__ void __launch_bounds__(kBlock) k_fine_W(const Ctl* __restrict__ ctl, 
     ROW_LOOP(R, lb) {
         Idx<DIM> p;
         int idx;
-        if (!row_item<DIM>(R, w_, p, idx)) continue;
+        const bool act = row_item<DIM>(R, w_, p, idx);
         T z[NB];
-        fine_z<DIM, T, NB, NE>(Y, nc, cL, dl, dzero, idx, p, z);
+        fine_z_wave<DIM, T, NB, NE>(Y, nc, cL, dl, dzero, idx, p, row_x(R, w_), z);
+        if (!act) continue;
         T q[S];
         load_node<T, S>(Q + (size_t)idx * S, q);
 #pragma unroll
@@ -888,18 +954,21 @@ __global__ void __launch_bounds__(kBlock) k_update_xP(const Ctl* __restrict__ ct
     ROW_LOOP(R, lb) {
         Idx<DIM> p;
         int idx;
-        if (!row_item<DIM>(R, w_, p, idx)) continue;
+        const bool act = row_item<DIM>(R, w_, p, idx);
         T pk[S];
         if (!init) {
             load_node<T, S>(P + (size_t)idx * S, pk);
-            double xi = x[idx];
+            if (act) {
+                double xi = x[idx];
 #pragma unroll
-            for (int c = 0; c < NB; ++c) xi += double(pk[c]) * sab[c];
-            x[idx] = xi;
+                for (int c = 0; c < NB; ++c) xi += double(pk[c]) * sab[c];
+                x[idx] = xi;
+            }
             if (state != 0) continue;
         }
         T z[NB];
-        fine_z<DIM, T, NB, NE>(Y, nc, cL, dl, dzero, idx, p, z);
+        fine_z_wave<DIM, T, NB, NE>(Y, nc, cL, dl, dzero, idx, p, row_x(R, w_), z);
+        if (!act) continue;
         T pn[S];
 #pragma unroll
         for (int c = 0; c < NB; ++c) {
@@ -957,9 +1026,10 @@ __global__ void __launch_bounds__(kBlock) k_write_Z(Rows R, int N, const T* __re
     ROW_LOOP(R, blockIdx.x) {
         Idx<DIM> p;
         int idx;
-        if (!row_item<DIM>(R, w_, p, idx)) continue;
+        const bool act = row_item<DIM>(R, w_, p, idx);
         T z[NB];
-        fine_z<DIM, T, NB, NE>(Y, nc, cL, dl, dzero, idx, p, z);
+        fine_z_wave<DIM, T, NB, NE>(Y, nc, cL, dl, dzero, idx, p, row_x(R, w_), z);
+        if (!act) continue;
 #pragma unroll
         for (int c = 0; c < NB; ++c) Z[(size_t)c * N + idx] = double(z[c]);
     }
