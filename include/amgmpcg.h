@@ -276,7 +276,7 @@ int amgmpcg_cnn_time_forward(amgmpcg_cnn* net, const double* r_dev, const uint16
  * weights, on caller tensors: channels-last bfloat16 bit patterns on an S^3
  * grid (1 <= S <= 512), zero outside the grid.
  *   op 0: out = relu(conv_l(A)), bfloat16 with Cout channels (l = 10: no
- *         ReLU, FP32 output with 16 channels);
+ *         ReLU, FP32 output channel 0 only, one value per voxel);
  *   op 1: out = conv_l^T(A): the data gradient for an output gradient A
  *         (Cout channels), bfloat16 with Cin channels;
  *   op 2: out = the weight gradient for output gradient A (Cout channels)

@@ -64,6 +64,12 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with paper_2402_12833_amd.build.build()")
+    try:
+        # torch owns the device memory and streams: let it bring up the HIP
+        # runtime first, so that the library binds to the same runtime
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     lib.amgmpcg_default_options.argtypes = [POINTER(Options)]
     lib.amgmpcg_default_options.restype = None
@@ -506,8 +512,9 @@ class Network:
 
     def layer(self, layer: int, op: int, A, B=None):
         """One layer on bfloat16 device tensors of shape (S, S, S, C): op 0
-        forward (+ReLU), op 1 data gradient, op 2 weight gradient (A = output
-        gradient, B = layer input).  Returns a new device tensor."""
+        forward (+ReLU; the output layer gives FP32 channel 0 only), op 1 data
+        gradient, op 2 weight gradient (A = output gradient, B = layer
+        input).  Returns a new device tensor."""
         import torch
         _, taps, cin, cout = CNN_LAYERS[layer]
         S = A.shape[0]
@@ -518,9 +525,10 @@ class Network:
         need_a = cin if op == 0 else cout
         if A.shape[3] != need_a or (op == 2 and (B is None or B.shape[3] != cin)):
             raise ValueError("channel count does not match the layer")
-        if op == 0:
-            out = torch.empty((S, S, S, cout), dtype=torch.float32 if layer == 10 else torch.bfloat16,
-                              device=A.device)
+        if op == 0 and layer == 10:
+            out = torch.empty((S, S, S, 1), dtype=torch.float32, device=A.device)
+        elif op == 0:
+            out = torch.empty((S, S, S, cout), dtype=torch.bfloat16, device=A.device)
         elif op == 1:
             out = torch.empty((S, S, S, cin), dtype=torch.bfloat16, device=A.device)
         else:

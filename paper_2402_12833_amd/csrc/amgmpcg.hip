@@ -123,7 +123,10 @@ static int fine_blocks(int N, int cap = kMaxFineBlocks) {
 
 // The block SpMM + Gram and W = Q^T Z kernels carry 27-44 accumulators per
 // thread: fewer, longer-running blocks amortise their block reductions.
-constexpr int kGramBlocks = 1024;
+#ifndef AMG_GRAM_BLOCKS
+#define AMG_GRAM_BLOCKS 1024
+#endif
+constexpr int kGramBlocks = AMG_GRAM_BLOCKS;
 
 template <typename T, int DIM>
 class Solver : public SolverBase {
@@ -231,6 +234,9 @@ class Solver : public SolverBase {
         HIPCHK(hipMemsetAsync(small_.p, 0, small_.n * sizeof(double), stream_));
         HIPCHK(hipEventCreate(&ev0_));
         HIPCHK(hipEventCreate(&ev1_));
+        HIPCHK(hipStreamCreateWithFlags(&side_, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&ev_fork_, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&ev_join_, hipEventDisableTiming));
         HIPCHK(hipStreamSynchronize(stream_));
         set_tau();
         if (DIM == 3 && var) {
@@ -345,7 +351,8 @@ class Solver : public SolverBase {
         c.maxit = 1;
         c.tau = tau_;
         HIPCHK(hipMemcpyAsync(ctl_proj_, hctl_proj_, sizeof(Ctl), hipMemcpyHostToDevice, s));
-        enqueue_levels(ctl_proj_, r_dev);
+        enqueue_fine(ctl_proj_, r_dev);
+        enqueue_coarse(ctl_proj_, r_dev);
         dispatch_plain([&](auto nbc) {
             constexpr int NB = decltype(nbc)::value;
             const int nc = L_ > 0 ? n_axis[L_ - 1] : 1;
@@ -395,6 +402,9 @@ class Solver : public SolverBase {
         if (ev0_) (void)hipEventDestroy(ev0_);
         if (ev1_) (void)hipEventDestroy(ev1_);
         for (hipEvent_t e : prof_ev_) (void)hipEventDestroy(e);
+        if (ev_fork_) (void)hipEventDestroy(ev_fork_);
+        if (ev_join_) (void)hipEventDestroy(ev_join_);
+        if (side_) (void)hipStreamDestroy(side_);
     }
 
     int solve(const double* b_dev, double* x_dev, double tol, int maxit, amgmpcg_info* info) override {
@@ -697,23 +707,42 @@ class Solver : public SolverBase {
         }
     }
 
-    // Z = MG(r) up to the coarse block and the fine smoother output.
     // Z = MG(r): every level correction and, when attached, the learned one.
+    // With a network attached, the network and the fine smoother (they
+    // depend only on r, like the coarse chain of restriction, coarse
+    // smoothing and prolongation) run on a second stream, forked from and
+    // joined back into the current one (inside graph capture this gives
+    // parallel branches), so the coarse chain hides under the inference.
+    // Without a network the fork costs more than it overlaps (measured), and
+    // while profiling every kernel is timed alone: serial.
     void enqueue_mg(const Ctl* ctl, const double* r) {
-        enqueue_levels(ctl, r);
-        if (net_) {
-            mark(kSecLearned);
-            enqueue_learned(ctl, r);
+        if (prof_on_ || !side_ || !net_) {
+            enqueue_fine(ctl, r);
+            enqueue_coarse(ctl, r);
+            if (net_) {
+                mark(kSecLearned);
+                enqueue_learned(ctl, r);
+            }
+            return;
         }
+        HIPCHK(hipEventRecord(ev_fork_, stream_));
+        HIPCHK(hipStreamWaitEvent(side_, ev_fork_, 0));
+        hipStream_t main = stream_;
+        stream_ = side_;
+        enqueue_fine(ctl, r);
+        if (net_) enqueue_learned(ctl, r);
+        stream_ = main;
+        HIPCHK(hipEventRecord(ev_join_, side_));
+        enqueue_coarse(ctl, r);
+        HIPCHK(hipStreamWaitEvent(stream_, ev_join_, 0));
     }
 
-    void enqueue_levels(const Ctl* ctl, const double* r) {
-        const int L = L_;
+    // the finest level's smoother output cL_final_ (nu sweeps from zero)
+    void enqueue_fine(const Ctl* ctl, const double* r) {
         const T omega = T(opt_.omega);
         const int nu = opt_.nu;
         const int two = nu >= 2 ? 1 : 0;
         const int extra = nu > 2 ? nu - 2 : 0;
-        // fine smoother
         mark(kSecFineSmooth);
         {
             T* first = (extra % 2 == 0) ? cL_.p : cL2_.p;
@@ -727,6 +756,15 @@ class Solver : public SolverBase {
             }
             cL_final_ = cur;
         }
+    }
+
+    // the coarse levels: restriction chain, smoothing, prolongation chain
+    void enqueue_coarse(const Ctl* ctl, const double* r) {
+        const int L = L_;
+        const T omega = T(opt_.omega);
+        const int nu = opt_.nu;
+        const int two = nu >= 2 ? 1 : 0;
+        const int extra = nu > 2 ? nu - 2 : 0;
         if (L == 0) return;
         // restriction chain: big levels one launch each, the small ones in one block
         mark(kSecRestrict);
@@ -969,6 +1007,8 @@ class Solver : public SolverBase {
         kSecCount
     };
     bool prof_on_ = false;
+    hipStream_t side_ = nullptr;
+    hipEvent_t ev_fork_ = nullptr, ev_join_ = nullptr;
     int prof_n_ = 0;
     std::vector<hipEvent_t> prof_ev_;
     std::vector<int> prof_sec_;

@@ -45,40 +45,46 @@ constexpr int kCB = 256;   // threads per block of the CNN kernels (4 wavefronts
 
 typedef short bf16x8 __attribute__((ext_vector_type(8)));
 
-// LDS-tiled convolution.  A block computes a
-// 16 (x) x 4 (y) x 4 (z) tile of output voxels, one z plane per wavefront and
-// four 16-voxel rows (M tiles) per wavefront, all output channels.  The input
-// tile with its one-voxel halo is staged in LDS once per chunk of CC input
-// channels, so each input value leaves L2 once per block instead of once per
-// tap.  The K dimension (taps x channels of the chunk) is walked in steps of
-// 32 with v_mfma_f32_16x16x32_bf16: lane group kq takes the 8 consecutive
-// K indices 32 s + 8 kq .. + 7, i.e. 8 channels of one tap (a 16-channel
-// chunk pairs two taps per step); A (input) and B (weights) use the same K
-// assignment, so the sum is independent of the hardware's K order.
+// LDS-tiled convolution.  A block computes a 16 (x) x 4 (y) x 4 (z) tile of
+// output voxels, one z plane per wavefront and four 16-voxel rows (M tiles)
+// per wavefront, for COUT / CSPLIT output channels (blockIdx.z also selects
+// the channel slice).  The input tile with its one-voxel halo is staged in
+// LDS once per chunk of CC input channels.  K (taps x channels) is walked
+// with v_mfma_f32_16x16x32_bf16: a step fixes, per lane group kq, one
+// (dz, dx) offset and 8 channels (CC = 32: one offset, channels 8 kq..;
+// CC = 16: two offsets, lane groups 0-1 and 2-3), reads the A fragments of
+// the six input rows once and uses row y0 + i + dy for output row i and tap
+// dy, so each fragment serves three taps.  A (input) and B (weights) use the
+// same K assignment, so the sum does not depend on the hardware's K order.
 // Input channels c < C1 come from Xc, a grid of S/2 read at (z/2, y/2, x/2)
 // (nearest upsampling), the rest from X (CIN - C1 channels): the skip
-// concatenation is read in place.
-template <int CIN, int C1, int COUT, int KS, int RELU, int OUT_F32>
+// concatenation is read in place.  OUT_F32: FP32 output of channel 0 only,
+// one value per voxel (the network output layer).
+template <int CIN, int C1, int COUT, int KS, int RELU, int OUT_F32, int CSPLIT>
 __global__ void __launch_bounds__(kCB) k_conv_lds(const Ctl* __restrict__ ctl, const bf16* __restrict__ Xc,
                                                   const bf16* __restrict__ X, const bf16* __restrict__ W,
                                                   void* __restrict__ Yv, int S) {
     if (ctl && ctl->state != 0) return;
-    static_assert(CIN % 16 == 0 && COUT % 16 == 0 && C1 % 16 == 0 && C1 < CIN, "channel layout");
+    static_assert(CIN % 16 == 0 && COUT % (16 * CSPLIT) == 0 && C1 % 16 == 0 && C1 < CIN, "channel layout");
     constexpr int C2 = CIN - C1;
     constexpr int CC = (CIN % 32 == 0) ? 32 : 16;      // channels per LDS stage
     constexpr int NCH = CIN / CC;
-    constexpr int TAPS = KS == 3 ? 27 : 1;
     constexpr int H = KS == 3 ? 1 : 0;
     constexpr int LX = 16 + 2 * H, LY = 4 + 2 * H, LZ = 4 + 2 * H;
     constexpr int NV = LX * LY * LZ;
     constexpr int VS = CC + 8;                         // padded voxel stride (elements)
-    constexpr int NT = COUT / 16;
-    constexpr int STEPS = (TAPS * CC + 31) / 32;
+    constexpr int NT = COUT / 16 / CSPLIT;
+    constexpr int NCOMBO = KS == 3 ? 9 : 1;            // (dz, dx) offsets
+    constexpr int NSTEP = CC == 32 ? NCOMBO : (NCOMBO + 1) / 2;
+    constexpr int NDY = KS == 3 ? 3 : 1;
     constexpr int PIECES = CC / 8;                     // 16-byte pieces per voxel and stage
     __shared__ __attribute__((aligned(16))) bf16 tile[NV * VS];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int m = lane & 15, kq = lane >> 4;
-    const int x0 = blockIdx.x * 16, y0 = blockIdx.y * 4, z0 = blockIdx.z * 4;
+    const int ztiles = (S + 3) >> 2;
+    const int zt = blockIdx.z % ztiles, cs = blockIdx.z / ztiles;
+    const int x0 = blockIdx.x * 16, y0 = blockIdx.y * 4, z0 = zt * 4;
+    const int co0 = cs * NT * 16;
     const int Sc = S >> 1;
     f32x4 acc[4][NT];
 #pragma unroll
@@ -102,28 +108,39 @@ __global__ void __launch_bounds__(kCB) k_conv_lds(const Ctl* __restrict__ ctl, c
             *reinterpret_cast<int4*>(tile + v * VS + q * 8) = val;
         }
         __syncthreads();
-#pragma unroll 3
-        for (int st = 0; st < STEPS; ++st) {
-            const int kg = st * 32 + 8 * kq;
-            const int t = kg / CC, c = kg - t * CC;
-            const bool valid = t < TAPS;
-            const int tt = valid ? t : 0;
-            bf16x8 b[NT];
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                b[nt] = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+        for (int st = 0; st < NSTEP; ++st) {
+            const int combo = CC == 32 ? st : 2 * st + (kq >> 1);
+            const int c = CC == 32 ? 8 * kq : 8 * (kq & 1);
+            const bool valid = combo < NCOMBO;
+            const int cb = valid ? combo : 0;
+            const int dz = KS == 3 ? cb / 3 - 1 : 0, dx = KS == 3 ? cb % 3 - 1 : 0;
+            bf16x8 a[4 + 2 * H];
+#pragma unroll
+            for (int r = 0; r < 4 + 2 * H; ++r) {
+                a[r] = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
                 if (valid)
-                    b[nt] = *reinterpret_cast<const bf16x8*>(W + ((size_t)(tt * COUT + nt * 16 + m) * CIN + ch * CC + c));
+                    a[r] = *reinterpret_cast<const bf16x8*>(
+                        tile + (((w + dz + H) * LY + r) * LX + (m + dx + H)) * VS + c);
             }
-            const int dz = KS == 3 ? tap_dz(tt) : 0, dy = KS == 3 ? tap_dy(tt) : 0, dx = KS == 3 ? tap_dx(tt) : 0;
-            const int vbase = ((w + dz + H) * LY + (dy + H)) * LX + (m + dx + H);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                bf16x8 a = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
-                if (valid) a = *reinterpret_cast<const bf16x8*>(tile + (vbase + i * LX) * VS + c);
+            for (int dyi = 0; dyi < NDY; ++dyi) {
+                const int dy = KS == 3 ? dyi - 1 : 0;
+                const int tap = KS == 3 ? (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1) : 0;
+                bf16x8 b[NT];
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt)
-                    acc[i][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[nt], acc[i][nt], 0, 0, 0);
+                for (int nt = 0; nt < NT; ++nt) {
+                    b[nt] = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+                    if (valid)
+                        b[nt] = *reinterpret_cast<const bf16x8*>(
+                            W + ((size_t)(tap * COUT + co0 + nt * 16 + m) * CIN + ch * CC + c));
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt)
+                        acc[i][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i + dy + H], b[nt], acc[i][nt], 0,
+                                                                             0, 0);
             }
         }
         __syncthreads();
@@ -142,9 +159,12 @@ __global__ void __launch_bounds__(kCB) k_conv_lds(const Ctl* __restrict__ ctl, c
                 if (x >= S) continue;
                 float v = acc[i][nt][j];
                 if (RELU) v = v > 0.f ? v : 0.f;
-                const size_t o = ((size_t)(z * S + y) * S + x) * COUT + nt * 16 + m;
-                if (OUT_F32) static_cast<float*>(Yv)[o] = v;
-                else static_cast<bf16*>(Yv)[o] = f2bf(v);
+                const size_t vox = (size_t)(z * S + y) * S + x;
+                if (OUT_F32) {
+                    if (co0 + nt * 16 + m == 0) static_cast<float*>(Yv)[vox] = v;
+                } else {
+                    static_cast<bf16*>(Yv)[vox * COUT + co0 + nt * 16 + m] = f2bf(v);
+                }
             }
     }
 }
@@ -352,7 +372,7 @@ __global__ void __launch_bounds__(kCB) k_mse_grad(const float* __restrict__ out,
         const bool in = x < n && y < n && z < n;
         float g = 0.f;
         if (in) {
-            const double diff = (double)out[(size_t)v * 16] - e[x + n * (y + n * z)] * (*escale);
+            const double diff = (double)out[v] - e[x + n * (y + n * z)] * (*escale);
             const double cnt = (double)n * n * n;
             l = diff * diff / cnt;
             g = (float)(2.0 * diff / cnt);
@@ -427,7 +447,7 @@ __global__ void __launch_bounds__(kCB) k_energy_grad64(const double* __restrict_
     g[i] = (c > 0.0 && E > 0.0) ? (2.0 * a / (c * E)) * ((a / c) * q[i] - r[i]) : 0.0;
 }
 
-// The network output (channel 0 of the FP32 final layer) as an MPCG column
+// The network output (the FP32 final layer, one value per voxel) as an MPCG column
 // (bulk type T, n^3 values); flag = 1 if any value is not finite.
 template <typename T>
 __global__ void __launch_bounds__(kCB) k_unpack_output(const Ctl* __restrict__ ctl, const float* __restrict__ out,
@@ -436,7 +456,7 @@ __global__ void __launch_bounds__(kCB) k_unpack_output(const Ctl* __restrict__ c
     const int idx = blockIdx.x * kCB + threadIdx.x;
     if (idx >= n * n * n) return;
     const int x = idx % n, y = (idx / n) % n, z = idx / (n * n);
-    const float v = out[(((size_t)z * S + y) * S + x) * 16];
+    const float v = out[((size_t)z * S + y) * S + x];
     if (!isfinite(v)) atomicOr(flag, 1);
     d[idx] = T(v);
 }

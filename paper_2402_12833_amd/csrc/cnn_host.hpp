@@ -71,7 +71,7 @@ class Net {
         c2.alloc(V0 * 48, err);
         d3.alloc(V0 * 16, err);
         d4.alloc(V0 * 16, err);
-        out.alloc(V0 * 16, err);
+        out.alloc(V0, err);
         g0a.alloc(V0 * 16, err);
         g0b.alloc(V0 * 16, err);
         g0c.alloc(V0 * 48, err);
@@ -87,7 +87,9 @@ class Net {
         rvec.alloc((size_t)n * n * n, err);
         q2vec.alloc((size_t)n * n * n, err);
         flag.alloc(1, err);
-        part.alloc((V0 + kCB - 1) / kCB > kSumBlocks ? (V0 + kCB - 1) / kCB : kSumBlocks, err);
+        // block partials: one per block of the loss kernel, or up to three
+        // values (k_dots3) per block of the kSumBlocks-block reductions
+        part.alloc((V0 + kCB - 1) / kCB > 3 * kSumBlocks ? (V0 + kCB - 1) / kCB : 3 * kSumBlocks, err);
         const int64_t NW = total_weights();
         w.alloc(NW, err);
         m.alloc(NW, err);
@@ -308,8 +310,8 @@ class Net {
     int step = 0;
 
     // One layer on caller tensors (S^3 grid, channels-last bfloat16) with
-    // the current weights.  op 0: out = relu(conv(A)) (layer 11: FP32, no
-    // ReLU); op 1: out = data gradient of output gradient A; op 2: out (FP32,
+    // the current weights.  op 0: out = relu(conv(A)) (layer 11: FP32 output
+    // channel 0, no ReLU); op 1: out = data gradient of output gradient A; op 2: out (FP32,
     // the layer's weight count) = weight gradient of output gradient A and
     // layer input B.
     hipError_t layer_op(int l, int op, int Sg, const bf16* A, const bf16* B, void* out) {
@@ -346,22 +348,46 @@ class Net {
         }
     }
 
-    static dim3 conv_grid(int Sg) { return dim3((Sg + 15) / 16, (Sg + 3) / 4, (Sg + 3) / 4); }
+    static dim3 conv_grid(int Sg, int split) {
+        return dim3((Sg + 15) / 16, (Sg + 3) / 4, ((Sg + 3) / 4) * split);
+    }
+
+    // Small grids (fewer than kConvFill tiles) split the output channels
+    // over blocks so that the whole chip works.
+    static constexpr int kConvFill = 2048;
+    template <int CIN, int C1, int COUT, int KS, int RELU, int F32>
+    static void conv_launch(const Ctl* ctl, const bf16* Xc, const bf16* X, const bf16* Wl, void* Y, int Sg,
+                            hipStream_t s) {
+        const int tiles = ((Sg + 15) / 16) * ((Sg + 3) / 4) * ((Sg + 3) / 4);
+        if constexpr (!F32 && COUT % 64 == 0) {
+            if (tiles < kConvFill) {
+                k_conv_lds<CIN, C1, COUT, KS, RELU, F32, 4><<<conv_grid(Sg, 4), kCB, 0, s>>>(ctl, Xc, X, Wl, Y, Sg);
+                return;
+            }
+        }
+        if constexpr (!F32 && COUT % 32 == 0) {
+            if (tiles < kConvFill) {
+                k_conv_lds<CIN, C1, COUT, KS, RELU, F32, 2><<<conv_grid(Sg, 2), kCB, 0, s>>>(ctl, Xc, X, Wl, Y, Sg);
+                return;
+            }
+        }
+        k_conv_lds<CIN, C1, COUT, KS, RELU, F32, 1><<<conv_grid(Sg, 1), kCB, 0, s>>>(ctl, Xc, X, Wl, Y, Sg);
+    }
 
     template <int CIN, int COUT, int KS, int RELU, int F32>
     static void conv_p(const Ctl* ctl, const bf16* X, const bf16* Wl, void* Y, int Sg, hipStream_t s) {
-        k_conv_lds<CIN, 0, COUT, KS, RELU, F32><<<conv_grid(Sg), kCB, 0, s>>>(ctl, nullptr, X, Wl, Y, Sg);
+        conv_launch<CIN, 0, COUT, KS, RELU, F32>(ctl, nullptr, X, Wl, Y, Sg, s);
     }
     // data gradient of a layer (CIN, COUT): the forward kernel on the
     // flipped, transposed weights, input dY (COUT channels) -> dX (CIN)
     template <int CIN, int COUT, int KS>
     static void dgrad_p(const bf16* dY, const bf16* Wt, bf16* dX, int Sg, hipStream_t s) {
-        k_conv_lds<COUT, 0, CIN, KS, 0, 0><<<conv_grid(Sg), kCB, 0, s>>>(nullptr, nullptr, dY, Wt, dX, Sg);
+        conv_launch<COUT, 0, CIN, KS, 0, 0>(nullptr, nullptr, dY, Wt, dX, Sg, s);
     }
     // conv + ReLU of [upsample2(Xc) (C1 channels) | X] without forming the concatenation
     template <int CIN, int C1, int COUT>
     void conv_cat(const Ctl* ctl, const bf16* Xc, const bf16* X, int layer, bf16* Y, int Sg, hipStream_t s) {
-        k_conv_lds<CIN, C1, COUT, 3, 1, 0><<<conv_grid(Sg), kCB, 0, s>>>(ctl, Xc, X, wb.p + woff(layer), Y, Sg);
+        conv_launch<CIN, C1, COUT, 3, 1, 0>(ctl, Xc, X, wb.p + woff(layer), Y, Sg, s);
     }
     template <int CIN, int COUT, int KS>
     static void wgrad_p(const bf16* dY, const bf16* X, float* dW, int Sg, hipStream_t s) {
