@@ -6,8 +6,9 @@ One step = one complete solve (setup excluded) of the 3D Poisson problem on
 levels, damped Jacobi nu=2 omega=2/3, b ~ U[-1,1] seed 2, x0 = 0) to
 ||r|| <= 1e-8 ||b|| in FP64, with b and x resident in device memory.
 ``value`` is the mean time per solve (ms, lower is better).  The same
-protocol is applied to the FP32-bulk form and to the heterogeneous-kappa
-workload; they are reported under ``variants``.
+protocol is applied to the FP32-bulk form, to the heterogeneous-kappa
+workload (truncation window m = 1 and m = 5) and to the learned direction;
+they are reported under ``variants``.
 
 The roofline entry is for the fine-level kernel with the largest time per
 iteration; its average launch duration is measured with HIP events on the
@@ -111,11 +112,11 @@ def per_dof(dim, nlevels, bulk, var):
             "update_xP": 2 * b * bulk + 16 + bulk, "fine_W": b * bulk + bulk}
 
 
-def run_solver(amg, torch, prob, precision, steps, warmup, kappa=None, net=None):
+def run_solver(amg, torch, prob, precision, steps, warmup, kappa=None, net=None, m=1):
     import workloads as W
     b = torch.as_tensor(W.problem_rhs(prob), device="cuda")
     t0 = time.time()
-    s = amg.Solver(prob.dim, prob.n, prob.nlevels, kappa=kappa, precision=precision)
+    s = amg.Solver(prob.dim, prob.n, prob.nlevels, kappa=kappa, precision=precision, m=m)
     setup_s = time.time() - t0
     if net is not None:
         s.attach(net)
@@ -242,6 +243,15 @@ def main(argv=None):
             var[f"diffusion3d_127_{tag}"] = {"ms": round(ms3, 4), "iterations": it3, "refreshes": info3["refreshes"],
                                              "hbm_GBps_algorithmic": round(pi3 * it3 / (ms3 * 1e-3) / 1e9, 1)}
             s3.close()
+            # truncation window m = 5: each new direction block A-orthogonalised
+            # against the last four blocks as well
+            s5, _, _, ms5, it5, _, info5 = run_solver(amg, torch, dprob, prec, args.steps, args.warmup, kappa=kap,
+                                                      m=5)
+            plain = var[f"diffusion3d_127_{tag}"]
+            var[f"diffusion3d_127_m5_{tag}"] = {"ms": round(ms5, 4), "iterations": it5, "refreshes": info5["refreshes"],
+                                                "iterations_m1": plain["iterations"],
+                                                "time_vs_m1": round(ms5 / plain["ms"], 3)}
+            s5.close()
         # the learned direction (committed trained weights) on the same problem
         from paper_2402_12833_amd import train as T
         net = amg.Network(dprob.n)

@@ -12,7 +12,8 @@
  *   (the additive-multigrid correction of each level kept as its own search
  *   direction, coarsest first);  alpha = (P_k^T A P_k)^+ P_k^T r_k;
  *   x_{k+1} = x_k + P_k alpha;  r_{k+1} = r_k - A P_k alpha  (eq. (4));
- *   P_{k+1} = Z_{k+1} - P_k (P_k^T A P_k)^+ P_k^T A Z_{k+1}  (truncation m = 1).
+ *   P_{k+1} = Z_{k+1} - sum_j P_j (P_j^T A P_j)^+ P_j^T A Z_{k+1} over the last
+ *   m blocks j (truncation window m, option; m = 1: against P_k only).
  * S_l^nu is nu damped-Jacobi sweeps from zero (eq. (2)), R = 2^-d P^T (full
  * weighting), P tensor-product linear interpolation, A_l Galerkin products.
  *
@@ -57,7 +58,10 @@ typedef struct {
 
 /* Solver options.  Fill with amgmpcg_default_options() first. */
 typedef struct {
-    int32_t m;            /* truncation window; only 1 is accepted             */
+    int32_t m;            /* truncation window 1..8 (1): P_{k+1} is made
+                             A-orthogonal to the last m direction blocks
+                             (classical Gram-Schmidt, every beta_j from Z);
+                             the blocks and their Q = A P are kept in a ring */
     int32_t nu;           /* damped-Jacobi sweeps on every level, 1..8 (2)     */
     double  omega;        /* Jacobi damping in (0, 1] (2/3)                   */
     int32_t maxit;        /* iteration limit (1000)                            */

@@ -210,14 +210,18 @@ class Solver : public SolverBase {
         x_.alloc(N);
         r_.alloc(N);
         b_.alloc(N);
-        P_.alloc((size_t)even_up(nb) * N);
-        Q_.alloc((size_t)even_up(nb) * N);
+        m_ = opt_.m;
+        kpoll_ = (opt_.k_poll + m_ - 1) / m_ * m_;
+        pstride_ = (size_t)even_up(nb) * N;
+        P_.alloc((size_t)m_ * pstride_);
+        Q_.alloc((size_t)m_ * pstride_);
         HIPCHK(hipMemset(P_.p, 0, P_.n * sizeof(T)));
         HIPCHK(hipMemset(Q_.p, 0, Q_.n * sizeof(T)));
         cL_.alloc(N);
         if (opt_.nu > 2) cL2_.alloc(N);
         part_.alloc((size_t)FB_ * kPartRow);
-        small_.alloc(kMaxNB + 2 * kMaxNB * kMaxNB);
+        small_.alloc(kMaxNB + 2 * kMaxWin * kMaxNB * kMaxNB);
+        partWin_.alloc((size_t)kMaxWin * kMaxNB * kMaxNB * FBG_);
         hist_cap_ = opt_.record_history ? std::max(opt_.maxit, 1) : 0;
         if (hist_cap_ > 0) {
             ahist_.alloc((size_t)hist_cap_ * nb);
@@ -269,6 +273,16 @@ class Solver : public SolverBase {
         }
     }
 
+    // m > 1: the slots a solve has not written yet must hold zero blocks and a
+    // zero G^+ (so that their beta and P_j beta vanish, also after a solve
+    // that left non-finite values); slot 0 is written by the start.
+    void clear_window() {
+        if (m_ == 1) return;
+        HIPCHK(hipMemsetAsync(Pslot(1), 0, (size_t)(m_ - 1) * pstride_ * sizeof(T), stream_));
+        HIPCHK(hipMemsetAsync(Qslot(1), 0, (size_t)(m_ - 1) * pstride_ * sizeof(T), stream_));
+        HIPCHK(hipMemsetAsync(d_beta(0), 0, (size_t)2 * kMaxWin * kMaxNB * kMaxNB * sizeof(double), stream_));
+    }
+
     void set_tau() {
         tau_ = opt_.pinv_tau > 0 ? opt_.pinv_tau : 64.0 * nb * (mixed_ ? std::ldexp(1.0, -24) : std::ldexp(1.0, -53));
     }
@@ -284,7 +298,8 @@ class Solver : public SolverBase {
         }
         net_ = net;
         nb = nlev + (net ? 1 : 0);
-        const size_t need = (size_t)even_up(nb) * N;
+        pstride_ = (size_t)even_up(nb) * N;
+        const size_t need = (size_t)m_ * pstride_;
         if (P_.n < need) {
             P_.alloc(need);
             Q_.alloc(need);
@@ -357,7 +372,8 @@ class Solver : public SolverBase {
             constexpr int NB = decltype(nbc)::value;
             const int nc = L_ > 0 ? n_axis[L_ - 1] : 1;
             k_update_xP<DIM, T, NB, 0><<<FB_, kBlock, 0, s>>>(ctl_proj_, rows_, fine_Y(), nc, cL_final_, nullptr,
-                                                               nullptr, P_.p, x_.p, d_alpha(), d_beta(), 1);
+                                                               nullptr, single(), 1, 0, 0, x_.p, d_alpha(), d_beta(),
+                                                               1);
             k_spmm_gram<DIM, T, NB><<<FBG_, kBlock, 0, s>>>(ctl_proj_, rows_, fop_, P_.p, Q_.p, r_dev, part_G());
             k_reduce_alpha<NB><<<1, kRedBlock, 0, s>>>(ctl_proj_, part_G(), FBG_, d_Gplus(), d_alpha(), nullptr);
             HIPCHK(hipMemcpyAsync(rhat_dev, r_dev, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -421,9 +437,10 @@ class Solver : public SolverBase {
         HIPCHK(hipMemcpyAsync(ctl_, hctl_in_, sizeof(Ctl), hipMemcpyHostToDevice, stream_));
         HIPCHK(hipMemcpyAsync(b_.p, b_dev, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, stream_));
         HIPCHK(hipMemcpyAsync(x_.p, x_dev, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, stream_));
+        clear_window();
         enqueue_init(tol);
         HIPCHK(hipGetLastError());
-        const int launches_max = maxit / opt_.k_poll + 3;
+        const int launches_max = maxit / kpoll_ + 3;
         for (int launch = 0; launch < launches_max; ++launch) {
             HIPCHK(hipMemcpyAsync(hctl_, ctl_, sizeof(Ctl), hipMemcpyDeviceToHost, stream_));
             HIPCHK(hipStreamSynchronize(stream_));
@@ -541,8 +558,8 @@ class Solver : public SolverBase {
             });
             timed([&] {
                 k_update_xP<DIM, T, NB, NE><<<FB_, kBlock, 0, stream_>>>(cf, rows_, fine_Y(), nc, cL_final_, dl(),
-                                                                         dflag(), P_.p, x_.p,
-                                                                      d_alpha(), d_beta(), 0);
+                                                                         dflag(), single(), 1, 0, 0, x_.p,
+                                                                         d_alpha(), d_beta(), 0);
             });
             timed([&] { k_spmm_gram<DIM, T, NB><<<FBG_, kBlock, 0, stream_>>>(cf, rows_, fop_, P_.p, Q_.p, r_.p, part_G()); });
             timed([&] { k_init_residual<DIM><<<FB_, kBlock, 0, stream_>>>(rows_, f64_, b_.p, x_.p, r_.p, part_init()); });
@@ -844,8 +861,22 @@ class Solver : public SolverBase {
     double* part_G() { return part_.p + (size_t)FB_ * (3 + kMaxNB * kMaxNB); }
     double* part_ref() { return part_.p + (size_t)FB_ * (kPartRow - 1); }
     double* d_alpha() { return small_.p; }
-    double* d_beta() { return small_.p + kMaxNB; }
-    double* d_Gplus() { return small_.p + kMaxNB + kMaxNB * kMaxNB; }
+    // beta_j and G_j^+ of the window's slot j (kMaxNB^2 doubles each)
+    double* d_beta(int j = 0) { return small_.p + kMaxNB + (size_t)j * kMaxNB * kMaxNB; }
+    double* d_Gplus(int j = 0) { return small_.p + kMaxNB + (size_t)(kMaxWin + j) * kMaxNB * kMaxNB; }
+    T* Pslot(int j) { return P_.p + (size_t)j * pstride_; }
+    T* Qslot(int j) { return Q_.p + (size_t)j * pstride_; }
+    double* part_Wslot(int j) { return partWin_.p + (size_t)j * kMaxNB * kMaxNB * FBG_; }
+    PWin<T> window() {
+        PWin<T> w{};
+        for (int j = 0; j < m_; ++j) w.p[j] = Pslot(j);
+        return w;
+    }
+    PWin<T> single() {
+        PWin<T> w{};
+        w.p[0] = Pslot(0);
+        return w;
+    }
 
     void enqueue_init(double tol) {
         const int N = N_[L_];
@@ -858,15 +889,20 @@ class Solver : public SolverBase {
             [[maybe_unused]] constexpr int NE = decltype(nbc)::ne;
             const int nc = L_ > 0 ? n_axis[L_ - 1] : 1;
             k_update_xP<DIM, T, NB, NE><<<FB_, kBlock, 0, stream_>>>(ctl_, rows_, fine_Y(), nc, cL_final_, dl(),
-                                                                       dflag(), P_.p, x_.p, d_alpha(), d_beta(), 1);
-            k_spmm_gram<DIM, T, NB><<<FBG_, kBlock, 0, stream_>>>(ctl_, rows_, fop_, P_.p, Q_.p, r_.p, part_G());
-            k_reduce_alpha<NB><<<1, kRedBlock, 0, stream_>>>(ctl_, part_G(), FBG_, d_Gplus(), d_alpha(),
+                                                                       dflag(), window(), m_, 0, 0, x_.p, d_alpha(),
+                                                                       d_beta(), 1);
+            k_spmm_gram<DIM, T, NB><<<FBG_, kBlock, 0, stream_>>>(ctl_, rows_, fop_, Pslot(0), Qslot(0), r_.p,
+                                                                   part_G());
+            k_reduce_alpha<NB><<<1, kRedBlock, 0, stream_>>>(ctl_, part_G(), FBG_, d_Gplus(0), d_alpha(),
                                                           hist_cap_ ? ahist_.p : nullptr);
         });
     }
 
-    void enqueue_iteration(hipStream_t s) {
+    // Iteration j (0-based count of x updates): P_j sits in slot j mod m and
+    // P_{j+1} goes into slot (j+1) mod m.
+    void enqueue_iteration(hipStream_t s, int j) {
         const int N = N_[L_];
+        const int cur = j % m_, nxt = (j + 1) % m_;
         hipStream_t saved = stream_;
         stream_ = s;
         dispatch_nb([&](auto nbc) {
@@ -874,26 +910,29 @@ class Solver : public SolverBase {
             [[maybe_unused]] constexpr int NE = decltype(nbc)::ne;
             const int nc = L_ > 0 ? n_axis[L_ - 1] : 1;
             mark(kSecUpdateR);
-            k_update_r<T, NB><<<FB_, kBlock, 0, s>>>(ctl_, N, Q_.p, d_alpha(), r_.p, part_rho());
+            k_update_r<T, NB><<<FB_, kBlock, 0, s>>>(ctl_, N, Qslot(cur), d_alpha(), r_.p, part_rho());
             enqueue_mg(ctl_, r_.p);
             mark(kSecFineW);
-            k_fine_W<DIM, T, NB, NE><<<FBG_, kBlock, 0, s>>>(ctl_, rows_, fine_Y(), nc, cL_final_, dl(), dflag(), Q_.p,
-                                                         part_W());
+            for (int q = 0; q < m_; ++q)
+                k_fine_W<DIM, T, NB, NE><<<FBG_, kBlock, 0, s>>>(ctl_, rows_, fine_Y(), nc, cL_final_, dl(), dflag(),
+                                                             Qslot(q), part_Wslot(q));
             mark(kSecReduceBeta);
-            k_reduce_beta<NB><<<1, kRedBlock, 0, s>>>(ctl_, part_rho(), FB_, part_W(), FBG_, d_Gplus(), d_beta(),
-                                                   hist_cap_ ? rhist_.p : nullptr, mixed_ ? 1 : 0);
+            k_reduce_beta<NB><<<1, kRedBlock, 0, s>>>(ctl_, part_rho(), FB_, part_Wslot(0), FBG_, m_, cur,
+                                                   d_Gplus(0), d_beta(0), hist_cap_ ? rhist_.p : nullptr,
+                                                   mixed_ ? 1 : 0);
             mark(kSecUpdateXP);
-            k_update_xP<DIM, T, NB, NE><<<FB_, kBlock, 0, s>>>(ctl_, rows_, fine_Y(), nc, cL_final_, dl(), dflag(), P_.p,
-                                                            x_.p, d_alpha(), d_beta(), 0);
+            k_update_xP<DIM, T, NB, NE><<<FB_, kBlock, 0, s>>>(ctl_, rows_, fine_Y(), nc, cL_final_, dl(), dflag(),
+                                                            window(), m_, cur, nxt, x_.p, d_alpha(), d_beta(0), 0);
             if (mixed_) {
                 mark(kSecRefresh);
                 k_refresh<DIM><<<FB_, kBlock, 0, s>>>(ctl_, rows_, f64_, b_.p, x_.p, r_.p, part_ref());
                 k_refresh_reduce<<<1, kRedBlock, 0, s>>>(ctl_, part_ref(), FB_, hist_cap_ ? rhist_.p : nullptr);
             }
             mark(kSecSpmmGram);
-            k_spmm_gram<DIM, T, NB><<<FBG_, kBlock, 0, s>>>(ctl_, rows_, fop_, P_.p, Q_.p, r_.p, part_G());
+            k_spmm_gram<DIM, T, NB><<<FBG_, kBlock, 0, s>>>(ctl_, rows_, fop_, Pslot(nxt), Qslot(nxt), r_.p,
+                                                         part_G());
             mark(kSecReduceAlpha);
-            k_reduce_alpha<NB><<<1, kRedBlock, 0, s>>>(ctl_, part_G(), FBG_, d_Gplus(), d_alpha(),
+            k_reduce_alpha<NB><<<1, kRedBlock, 0, s>>>(ctl_, part_G(), FBG_, d_Gplus(nxt), d_alpha(),
                                                     hist_cap_ ? ahist_.p : nullptr);
             mark(kSecEnd);
         });
@@ -932,6 +971,7 @@ class Solver : public SolverBase {
         HIPCHK(hipMemcpyAsync(ctl_, hctl_in_, sizeof(Ctl), hipMemcpyHostToDevice, stream_));
         HIPCHK(hipMemcpyAsync(b_.p, b_dev, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, stream_));
         HIPCHK(hipMemcpyAsync(x_.p, x_dev, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, stream_));
+        clear_window();
         enqueue_init(tol);
         HIPCHK(hipGetLastError());
         double sum[kSecCount] = {0.0};
@@ -942,7 +982,7 @@ class Solver : public SolverBase {
             if (hctl_->state != 0) break;
             prof_on_ = true;
             prof_n_ = 0;
-            enqueue_iteration(stream_);
+            enqueue_iteration(stream_, it);
             prof_on_ = false;
             HIPCHK(hipGetLastError());
             HIPCHK(hipMemcpyAsync(hctl_, ctl_, sizeof(Ctl), hipMemcpyDeviceToHost, stream_));
@@ -982,7 +1022,7 @@ class Solver : public SolverBase {
     void capture_graph() {
         if (!cap_stream_) HIPCHK(hipStreamCreateWithFlags(&cap_stream_, hipStreamNonBlocking));
         HIPCHK(hipStreamBeginCapture(cap_stream_, hipStreamCaptureModeThreadLocal));
-        for (int k = 0; k < opt_.k_poll; ++k) enqueue_iteration(cap_stream_);
+        for (int k = 0; k < kpoll_; ++k) enqueue_iteration(cap_stream_, k);
         hipError_t launch_err = hipGetLastError();
         HIPCHK(hipStreamEndCapture(cap_stream_, &graph_));
         HIPCHK(launch_err);
@@ -1021,6 +1061,8 @@ class Solver : public SolverBase {
     bool graph_ready_ = false;
     bool mixed_ = false;
     int L_ = 0, FB_ = 1, FBG_ = 1, hist_cap_ = 0, last_iters_ = 0;
+    int m_ = 1, kpoll_ = 1;      // truncation window; iterations per captured graph (a multiple of m)
+    size_t pstride_ = 0;         // elements per direction block slot
     double tau_ = 0.0;
     std::vector<int> N_;
     FineOp<T> fop_{};
@@ -1030,7 +1072,7 @@ class Solver : public SolverBase {
     DevBuf<double> gD_, gex_, gey_, gez_, giD_;
     std::vector<DevBuf<T>> coef_, g_, c1_, c_, c2_, Y_;
     T* cL_final_ = nullptr;
-    DevBuf<double> x_, r_, b_, part_, small_, ahist_, rhist_;
+    DevBuf<double> x_, r_, b_, part_, small_, ahist_, rhist_, partWin_;
     DevBuf<T> P_, Q_, cL_, cL2_, dl_;
     DevBuf<double> xt_;
     DevBuf<unsigned short> lk_;
@@ -1283,7 +1325,7 @@ static int guarded(F&& f) {
 
 static void validate_options(const amgmpcg_options* o) {
     if (!o) throw ApiError(AMGMPCG_INVALID_ARG, "options pointer is NULL");
-    if (o->m != 1) throw ApiError(AMGMPCG_INVALID_ARG, "only the truncation window m = 1 is implemented");
+    if (o->m < 1 || o->m > amg::kMaxWin) throw ApiError(AMGMPCG_INVALID_ARG, "m must be in 1..8");
     if (o->nu < 1 || o->nu > 8) throw ApiError(AMGMPCG_INVALID_ARG, "nu must be in 1..8");
     if (!(o->omega > 0.0 && o->omega <= 1.0)) throw ApiError(AMGMPCG_INVALID_ARG, "omega must be in (0, 1]");
     if (o->maxit < 1) throw ApiError(AMGMPCG_INVALID_ARG, "maxit must be >= 1");

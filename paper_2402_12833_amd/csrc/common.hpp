@@ -12,6 +12,7 @@ constexpr int kBlock = 256;        // threads per block (4 wavefronts)
 constexpr int kWaves = kBlock / 64;
 constexpr int kMaxLevels = 8;
 constexpr int kMaxNB = 8;          // search directions per iteration (L + 1 [+ 1])
+constexpr int kMaxWin = 8;         // truncation window m: direction blocks kept
 constexpr int kNumXcd = 8;         // MI355X: 8 XCDs, blocks dispatched round-robin
 
 // Solver control word in device memory.  Only single-block kernels write it;

@@ -932,32 +932,50 @@ __global__ void __launch_bounds__(kBlock) k_fine_W(const Ctl* __restrict__ ctl, 
     block_sum_store<NB * NB>(w, part, gridDim.x, lb);
 }
 
+// The stored direction blocks of the truncation window (a ring of m slots).
+template <typename T>
+struct PWin {
+    T* p[kMaxWin];
+};
+
 // x += P_k alpha_k (deferred update of Algorithm 1); then, unless stopping,
-// P_{k+1} = Z_{k+1} - P_k beta in place (Z recomputed from the coarse block).
-// init = 1: P_0 = Z_0 only.
+// P_{k+1} = Z_{k+1} - sum_j P_j beta_j over the m stored blocks (slot cur
+// holds P_k), written into slot nxt (the oldest, read first at each node);
+// Z recomputed from the coarse block.  beta_j at beta + j kMaxNB^2.
+// init = 1: P_0 = Z_0 only, into slot nxt.
 template <int DIM, typename T, int NB, int NE>
 __global__ void __launch_bounds__(kBlock) k_update_xP(const Ctl* __restrict__ ctl, Rows R, const T* __restrict__ Y,
                                                       int nc, const T* __restrict__ cL, const T* __restrict__ dl,
-                                                      const int* __restrict__ dflag, T* __restrict__ P,
-                                                      double* __restrict__ x, const double* __restrict__ alpha,
+                                                      const int* __restrict__ dflag, PWin<T> win, int m, int cur,
+                                                      int nxt, double* __restrict__ x,
+                                                      const double* __restrict__ alpha,
                                                       const double* __restrict__ beta, int init) {
     const int state = ctl->state;
     if (state == 2 || (init && state != 0)) return;
     const bool dzero = NE && *dflag != 0;
     constexpr int S = even_up(NB);
     const int lb = xcd_block(gridDim.x);
-    __shared__ double sab[NB + NB * NB];
+    __shared__ double sab[NB + kMaxWin * NB * NB];
     if (!init) {
-        for (int q = threadIdx.x; q < NB + NB * NB; q += kBlock) sab[q] = q < NB ? alpha[q] : beta[q - NB];
+        for (int q = threadIdx.x; q < NB + m * NB * NB; q += kBlock) {
+            if (q < NB) {
+                sab[q] = alpha[q];
+            } else {
+                const int j = (q - NB) / (NB * NB), e = (q - NB) - j * NB * NB;
+                sab[q] = beta[(size_t)j * kMaxNB * kMaxNB + e];
+            }
+        }
     }
     __syncthreads();
+    T* __restrict__ Pc = win.p[cur];
+    T* __restrict__ Pn = win.p[nxt];
     ROW_LOOP(R, lb) {
         Idx<DIM> p;
         int idx;
         const bool act = row_item<DIM>(R, w_, p, idx);
         T pk[S];
         if (!init) {
-            load_node<T, S>(P + (size_t)idx * S, pk);
+            load_node<T, S>(Pc + (size_t)idx * S, pk);
             if (act) {
                 double xi = x[idx];
 #pragma unroll
@@ -969,19 +987,32 @@ __global__ void __launch_bounds__(kBlock) k_update_xP(const Ctl* __restrict__ ct
         T z[NB];
         fine_z_wave<DIM, T, NB, NE>(Y, nc, cL, dl, dzero, idx, p, row_x(R, w_), z);
         if (!act) continue;
+        double v[NB];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) v[c] = double(z[c]);
+        if (!init) {
+            const double* bc = sab + NB + cur * NB * NB;
+#pragma unroll
+            for (int c = 0; c < NB; ++c)
+#pragma unroll
+                for (int a2 = 0; a2 < NB; ++a2) v[c] -= double(pk[a2]) * bc[a2 * NB + c];
+            for (int j = 0; j < m; ++j) {
+                if (j == cur) continue;
+                T pj[S];
+                load_node<T, S>(win.p[j] + (size_t)idx * S, pj);
+                const double* bj = sab + NB + j * NB * NB;
+#pragma unroll
+                for (int c = 0; c < NB; ++c)
+#pragma unroll
+                    for (int a2 = 0; a2 < NB; ++a2) v[c] -= double(pj[a2]) * bj[a2 * NB + c];
+            }
+        }
         T pn[S];
 #pragma unroll
-        for (int c = 0; c < NB; ++c) {
-            double v = double(z[c]);
-            if (!init) {
-#pragma unroll
-                for (int a2 = 0; a2 < NB; ++a2) v -= double(pk[a2]) * sab[NB + a2 * NB + c];
-            }
-            pn[c] = T(v);
-        }
+        for (int c = 0; c < NB; ++c) pn[c] = T(v[c]);
 #pragma unroll
         for (int c = NB; c < S; ++c) pn[c] = T(0);
-        store_node<T, S>(P + (size_t)idx * S, pn);
+        store_node<T, S>(Pn + (size_t)idx * S, pn);
     }
 }
 

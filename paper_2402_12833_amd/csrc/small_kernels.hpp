@@ -148,9 +148,14 @@ __global__ void __launch_bounds__(kRedBlock) k_reduce_init(Ctl* ctl, const doubl
 // true-residual refresh; the refresh decides.
 template <int NB>
 __global__ void __launch_bounds__(kRedBlock) k_reduce_beta(Ctl* ctl, const double* part_rho, int nblk_rho,
-                                                        const double* part_W, int nblk_W, const double* Gplus,
-                                                        double* beta, double* rhist, int mixed) {
+                                                        const double* part_Wall, int nblk_W, int nwin, int cur,
+                                                        const double* Gplus_all, double* beta_all, double* rhist,
+                                                        int mixed) {
     if (ctl->state != 0) return;
+    // slot j of W partials / G^+ / beta: part_Wall + j kMaxNB^2 nblk_W, + j kMaxNB^2
+    const double* part_W = part_Wall + (size_t)cur * kMaxNB * kMaxNB * nblk_W;
+    const double* Gplus = Gplus_all + (size_t)cur * kMaxNB * kMaxNB;
+    double* beta = beta_all + (size_t)cur * kMaxNB * kMaxNB;
     __shared__ double red[1 + NB * NB];
     double* rho_s = red;
     double* W = red + 1;
@@ -198,6 +203,20 @@ __global__ void __launch_bounds__(kRedBlock) k_reduce_beta(Ctl* ctl, const doubl
         double s = 0.0;
         for (int m = 0; m < NB; ++m) s += Gplus[a * NB + m] * W[m * NB + c];
         beta[q] = s;
+    }
+    // the other blocks of the window: beta_j = G_j^+ (Q_j^T Z)
+    for (int j = 0; j < nwin; ++j) {
+        if (j == cur) continue;
+        __syncthreads();
+        reduce_partials<NB * NB>(part_Wall + (size_t)j * kMaxNB * kMaxNB * nblk_W, nblk_W, W);
+        const double* Gj = Gplus_all + (size_t)j * kMaxNB * kMaxNB;
+        double* bj = beta_all + (size_t)j * kMaxNB * kMaxNB;
+        for (int q = threadIdx.x; q < NB * NB; q += kRedBlock) {
+            const int a = q / NB, c = q % NB;
+            double s = 0.0;
+            for (int m = 0; m < NB; ++m) s += Gj[a * NB + m] * W[m * NB + c];
+            bj[q] = s;
+        }
     }
 }
 

@@ -57,7 +57,7 @@ def test_grid_validation(lib, grid, expect):
     assert B.last_error()
 
 
-@pytest.mark.parametrize("kw", [dict(m=5), dict(nu=0), dict(omega=1.5), dict(maxit=0), dict(precision=3),
+@pytest.mark.parametrize("kw", [dict(m=0), dict(m=9), dict(nu=0), dict(omega=1.5), dict(maxit=0), dict(precision=3),
                                 dict(k_poll=0), dict(refresh_drop=2.0)])
 def test_option_validation(lib, kw):
     code, _ = _setup(lib, B.Grid(2, 31, 3, None), amg.default_options(**kw))

@@ -335,3 +335,71 @@ def test_profile_solve_matches_solve(precision):
     assert sec["spmm_gram"] > 0 and sec["update_xP"] > 0 and sec["iteration"] > 0
     assert abs(parts - sec["iteration"]) <= 0.05 * sec["iteration"]
     assert (sec["refresh"] > 0) == (precision == 1)
+
+
+# Truncation window m > 1 (the paper's experiments keep m = 5 blocks):
+# (dim, n, levels, kappa seed, rhs seed, m)
+WINDOW = [
+    (2, 31, 4, None, 1, 5),
+    (2, 45, 4, 5, 12, 2),
+    (3, 15, 3, 3, 16, 5),
+    (3, 17, 3, 7, 18, 3),
+    (3, 31, 4, 8, 19, 8),
+]
+
+
+def window_id(c):
+    return f"d{c[0]}n{c[1]}L{c[2]}k{c[3]}m{c[5]}"
+
+
+@pytest.mark.parametrize("case", WINDOW, ids=window_id)
+def test_window_iterates_match_oracle(case):
+    dim, n, nl, ks, seed, m = case
+    h, s, b = build_pair(dim, n, nl, ks, seed, m=m)
+    bg = dev(b)
+    # k spans the filling of the window and several turns of the ring
+    for k in (1, 2, m, m + 1, 2 * m + 3):
+        x, _ = s.solve(bg, tol=0.0, maxit=k)
+        ref = mpcg.mpcg(h, b, tol=0.0, maxit=k, m=m)
+        err = rel(host(x), ref.x)
+        assert err <= 1e-10, (k, err)
+    x, info = s.solve(bg, tol=1e-8)
+    ref = mpcg.mpcg(h, b, tol=1e-8, m=m)
+    print(f"{window_id(case)}: gpu {info['iterations']} its, oracle {ref.iterations} its")
+    assert info["status"] == amg.OK
+    assert abs(info["iterations"] - ref.iterations) <= 1
+    # a second solve on the same handle starts from an empty window
+    x2, info2 = s.solve(bg, tol=1e-8)
+    assert info2["iterations"] == info["iterations"] and torch.equal(x, x2)
+    s.close()
+
+
+@pytest.mark.parametrize("case", [WINDOW[2], WINDOW[4]], ids=window_id)
+def test_window_mixed_precision(case):
+    dim, n, nl, ks, seed, m = case
+    h, s, b = build_pair(dim, n, nl, ks, seed, m=m, precision=1)
+    x, info = s.solve(dev(b), tol=1e-8)
+    true_rel = np.linalg.norm(b - h.fine.A @ host(x)) / np.linalg.norm(b)
+    ref = mpcg.mpcg(h, b, tol=1e-8, m=m)
+    print(f"mixed {window_id(case)}: {info['iterations']} its (fp64 oracle {ref.iterations}), true relres {true_rel:.2e}")
+    assert info["status"] == amg.OK and true_rel <= 1e-8
+    assert info["iterations"] <= ref.iterations + 5
+    s.close()
+
+
+def test_window_full_size_diffusion_m5():
+    g = _golden("diffusion3d_127_m5")
+    prob = W.DIFFUSION3D_127
+    kap = W.kappa_field(prob)
+    b = W.problem_rhs(prob)
+    s = amg.Solver(prob.dim, prob.n, prob.nlevels, kappa=kap, m=5)
+    bg = dev(b)
+    x, info = s.solve(bg, tol=1e-8)
+    assert info["status"] == amg.OK
+    assert abs(info["iterations"] - g["iterations"]) <= 1
+    idx = np.array(g["sample_idx"])
+    k = g["iterations"]
+    for kk in (1, 5, k):
+        xg, _ = s.solve(bg, tol=0.0, maxit=kk)
+        assert rel(host(xg)[idx], np.array(g["x"][str(kk)])) <= 1e-10, kk
+    s.close()
