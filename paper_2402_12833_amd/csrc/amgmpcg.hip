@@ -128,6 +128,24 @@ static int fine_blocks(int N, int cap = kMaxFineBlocks) {
 #endif
 constexpr int kGramBlocks = AMG_GRAM_BLOCKS;
 
+// z-marching SpMM + Gram on 3D grids: TY rows per tile (a multiple of 2) and
+// kz planes per unit.
+#ifndef AMG_ZTILE_TY
+#define AMG_ZTILE_TY 2
+#endif
+#ifndef AMG_ZTILE_KZ
+#define AMG_ZTILE_KZ 0
+#endif
+constexpr int kZTY = AMG_ZTILE_TY;
+constexpr int kZKZ = AMG_ZTILE_KZ;    // 0: split z so that the units fill the resident blocks once
+constexpr int kNumCU = 256;
+constexpr int kGramRow = kMaxNB * (kMaxNB + 1) / 2 + kMaxNB;   // Gram + P^T r partial values
+constexpr size_t kBlockSlack = 16;   // elements past the last slot (16-byte chunk reads)
+
+// Elements per direction-block slot: b columns (even stride) per node, rounded
+// up to 64 elements so that every slot starts 256-byte aligned.
+inline size_t slot_elems(int nb, int N) { return ((size_t)even_up(nb) * N + 63) / 64 * 64; }
+
 template <typename T, int DIM>
 class Solver : public SolverBase {
    public:
@@ -148,6 +166,18 @@ class Solver : public SolverBase {
         rows_.total = (int)host::ipow(g.n, DIM - 1) * rows_.nxp;
         FB_ = fine_blocks(rows_.total);
         FBG_ = fine_blocks(rows_.total, kGramBlocks);
+        if (DIM == 3) {
+            // z chunks so that the units fill the resident blocks (2 or 3 per
+            // CU) about once
+            zntx_ = (g.n + kZTileX - 1) / kZTileX;
+            const int tiles = zntx_ * ((g.n + kZTY - 1) / kZTY);
+            for (int v = 0; v < 2; ++v) {
+                const int chunks = std::max(1, (v + 2) * kNumCU / tiles);
+                zkz_[v] = kZKZ > 0 ? std::min(kZKZ, g.n) : (g.n + chunks - 1) / chunks;
+                znkz_[v] = (g.n + zkz_[v] - 1) / zkz_[v];
+                SB_[v] = tiles * znkz_[v];
+            }
+        }
 
         // ---- host hierarchy (FP64) -------------------------------------
         const bool var = g.kappa != nullptr;
@@ -212,14 +242,15 @@ class Solver : public SolverBase {
         b_.alloc(N);
         m_ = opt_.m;
         kpoll_ = (opt_.k_poll + m_ - 1) / m_ * m_;
-        pstride_ = (size_t)even_up(nb) * N;
-        P_.alloc((size_t)m_ * pstride_);
-        Q_.alloc((size_t)m_ * pstride_);
+        pstride_ = slot_elems(nb, N);
+        P_.alloc((size_t)m_ * pstride_ + kBlockSlack);
+        Q_.alloc((size_t)m_ * pstride_ + kBlockSlack);
         HIPCHK(hipMemset(P_.p, 0, P_.n * sizeof(T)));
         HIPCHK(hipMemset(Q_.p, 0, Q_.n * sizeof(T)));
         cL_.alloc(N);
         if (opt_.nu > 2) cL2_.alloc(N);
         part_.alloc((size_t)FB_ * kPartRow);
+        partG_.alloc((size_t)kGramRow * std::max(std::max(SB_[0], SB_[1]), FBG_));
         small_.alloc(kMaxNB + 2 * kMaxWin * kMaxNB * kMaxNB);
         partWin_.alloc((size_t)kMaxWin * kMaxNB * kMaxNB * FBG_);
         hist_cap_ = opt_.record_history ? std::max(opt_.maxit, 1) : 0;
@@ -298,8 +329,8 @@ class Solver : public SolverBase {
         }
         net_ = net;
         nb = nlev + (net ? 1 : 0);
-        pstride_ = (size_t)even_up(nb) * N;
-        const size_t need = (size_t)m_ * pstride_;
+        pstride_ = slot_elems(nb, N);
+        const size_t need = (size_t)m_ * pstride_ + kBlockSlack;
         if (P_.n < need) {
             P_.alloc(need);
             Q_.alloc(need);
@@ -374,8 +405,8 @@ class Solver : public SolverBase {
             k_update_xP<DIM, T, NB, 0><<<FB_, kBlock, 0, s>>>(ctl_proj_, rows_, fine_Y(), nc, cL_final_, nullptr,
                                                                nullptr, single(), 1, 0, 0, x_.p, d_alpha(), d_beta(),
                                                                1);
-            k_spmm_gram<DIM, T, NB><<<FBG_, kBlock, 0, s>>>(ctl_proj_, rows_, fop_, P_.p, Q_.p, r_dev, part_G());
-            k_reduce_alpha<NB><<<1, kRedBlock, 0, s>>>(ctl_proj_, part_G(), FBG_, d_Gplus(), d_alpha(), nullptr);
+            launch_spmm<NB>(ctl_proj_, P_.p, Q_.p, r_dev, s);
+            k_reduce_alpha<NB><<<1, kRedBlock, 0, s>>>(ctl_proj_, part_G(), spmm_blocks<NB>(), d_Gplus(), d_alpha(), nullptr);
             HIPCHK(hipMemcpyAsync(rhat_dev, r_dev, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, s));
             k_update_r<T, NB><<<FB_, kBlock, 0, s>>>(ctl_proj_, N, Q_.p, d_alpha(), rhat_dev, part_rho());
         });
@@ -561,7 +592,7 @@ class Solver : public SolverBase {
                                                                          dflag(), single(), 1, 0, 0, x_.p,
                                                                          d_alpha(), d_beta(), 0);
             });
-            timed([&] { k_spmm_gram<DIM, T, NB><<<FBG_, kBlock, 0, stream_>>>(cf, rows_, fop_, P_.p, Q_.p, r_.p, part_G()); });
+            timed([&] { launch_spmm<NB>(cf, P_.p, Q_.p, r_.p, stream_); });
             timed([&] { k_init_residual<DIM><<<FB_, kBlock, 0, stream_>>>(rows_, f64_, b_.p, x_.p, r_.p, part_init()); });
         });
         return count;
@@ -858,7 +889,36 @@ class Solver : public SolverBase {
     double* part_init() { return part_.p; }
     double* part_rho() { return part_.p + (size_t)FB_ * 2; }
     double* part_W() { return part_.p + (size_t)FB_ * 3; }
-    double* part_G() { return part_.p + (size_t)FB_ * (3 + kMaxNB * kMaxNB); }
+    double* part_G() { return partG_.p; }
+
+    // Q = A P and the Gram partials (spmm_blocks<NB>() partial rows at
+    // part_G()): z-marching on 3D grids for blocks of <= 48 bytes per node,
+    // row-mapped otherwise.
+    template <int NB>
+    int spmm_blocks() const {
+        if constexpr (DIM == 3 && zt_fits<T, NB>()) return SB_[zvar<NB>()];
+        return FBG_;
+    }
+    // unit split of the z-marching kernel: 0 for 2 resident blocks per CU, 1 for 3
+    template <int NB>
+    int zvar() const {
+        return (fop_.D ? zt_min_blocks<T, NB, true>() : zt_min_blocks<T, NB, false>()) - 2;
+    }
+    template <int NB>
+    void launch_spmm(const Ctl* c, const T* P, T* Q, const double* r, hipStream_t s) {
+        if constexpr (DIM == 3 && zt_fits<T, NB>()) {
+            const long long pbytes = (long long)((P_.p + P_.n) - P) * (long long)sizeof(T);
+            const int n = n_axis[L_], v = zvar<NB>();
+            if (fop_.D)
+                k_spmm_gram_z<T, NB, kZTY, true><<<SB_[v], kBlock, 0, s>>>(c, n, zntx_, zkz_[v], znkz_[v], fop_, P,
+                                                                          pbytes, Q, r, part_G());
+            else
+                k_spmm_gram_z<T, NB, kZTY, false><<<SB_[v], kBlock, 0, s>>>(c, n, zntx_, zkz_[v], znkz_[v], fop_, P,
+                                                                           pbytes, Q, r, part_G());
+        } else {
+            k_spmm_gram<DIM, T, NB><<<FBG_, kBlock, 0, s>>>(c, rows_, fop_, P, Q, r, part_G());
+        }
+    }
     double* part_ref() { return part_.p + (size_t)FB_ * (kPartRow - 1); }
     double* d_alpha() { return small_.p; }
     // beta_j and G_j^+ of the window's slot j (kMaxNB^2 doubles each)
@@ -891,9 +951,8 @@ class Solver : public SolverBase {
             k_update_xP<DIM, T, NB, NE><<<FB_, kBlock, 0, stream_>>>(ctl_, rows_, fine_Y(), nc, cL_final_, dl(),
                                                                        dflag(), window(), m_, 0, 0, x_.p, d_alpha(),
                                                                        d_beta(), 1);
-            k_spmm_gram<DIM, T, NB><<<FBG_, kBlock, 0, stream_>>>(ctl_, rows_, fop_, Pslot(0), Qslot(0), r_.p,
-                                                                   part_G());
-            k_reduce_alpha<NB><<<1, kRedBlock, 0, stream_>>>(ctl_, part_G(), FBG_, d_Gplus(0), d_alpha(),
+            launch_spmm<NB>(ctl_, Pslot(0), Qslot(0), r_.p, stream_);
+            k_reduce_alpha<NB><<<1, kRedBlock, 0, stream_>>>(ctl_, part_G(), spmm_blocks<NB>(), d_Gplus(0), d_alpha(),
                                                           hist_cap_ ? ahist_.p : nullptr);
         });
     }
@@ -929,10 +988,9 @@ class Solver : public SolverBase {
                 k_refresh_reduce<<<1, kRedBlock, 0, s>>>(ctl_, part_ref(), FB_, hist_cap_ ? rhist_.p : nullptr);
             }
             mark(kSecSpmmGram);
-            k_spmm_gram<DIM, T, NB><<<FBG_, kBlock, 0, s>>>(ctl_, rows_, fop_, Pslot(nxt), Qslot(nxt), r_.p,
-                                                         part_G());
+            launch_spmm<NB>(ctl_, Pslot(nxt), Qslot(nxt), r_.p, s);
             mark(kSecReduceAlpha);
-            k_reduce_alpha<NB><<<1, kRedBlock, 0, s>>>(ctl_, part_G(), FBG_, d_Gplus(nxt), d_alpha(),
+            k_reduce_alpha<NB><<<1, kRedBlock, 0, s>>>(ctl_, part_G(), spmm_blocks<NB>(), d_Gplus(nxt), d_alpha(),
                                                     hist_cap_ ? ahist_.p : nullptr);
             mark(kSecEnd);
         });
@@ -1061,6 +1119,9 @@ class Solver : public SolverBase {
     bool graph_ready_ = false;
     bool mixed_ = false;
     int L_ = 0, FB_ = 1, FBG_ = 1, hist_cap_ = 0, last_iters_ = 0;
+    // z-marching SpMM: x tiles; per resident-block count (2, 3): planes per
+    // unit, z chunks, units (= blocks)
+    int zntx_ = 1, zkz_[2] = {1, 1}, znkz_[2] = {1, 1}, SB_[2] = {1, 1};
     int m_ = 1, kpoll_ = 1;      // truncation window; iterations per captured graph (a multiple of m)
     size_t pstride_ = 0;         // elements per direction block slot
     double tau_ = 0.0;
@@ -1072,7 +1133,7 @@ class Solver : public SolverBase {
     DevBuf<double> gD_, gex_, gey_, gez_, giD_;
     std::vector<DevBuf<T>> coef_, g_, c1_, c_, c2_, Y_;
     T* cL_final_ = nullptr;
-    DevBuf<double> x_, r_, b_, part_, small_, ahist_, rhist_, partWin_;
+    DevBuf<double> x_, r_, b_, part_, small_, ahist_, rhist_, partWin_, partG_;
     DevBuf<T> P_, Q_, cL_, cL2_, dl_;
     DevBuf<double> xt_;
     DevBuf<unsigned short> lk_;

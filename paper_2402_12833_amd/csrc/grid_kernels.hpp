@@ -1048,6 +1048,259 @@ __global__ void __launch_bounds__(kBlock) k_spmm_gram(const Ctl* __restrict__ ct
     block_sum_store<NG + NB>(acc, part, gridDim.x, lb);
 }
 
+// ------------------------------------------- z-marching block SpMM (3D)
+//
+// The same Q = A P and Gram partials as k_spmm_gram, for 3D grids, with the
+// work split into units of (an x tile of kZTileX nodes) x (TY rows) x (kz
+// planes).  A block marches its unit along z.  The plane it works on and the
+// next one sit in LDS with a one-node halo in x and a one-row halo in y; the
+// block fills them with 16-byte chunk loads that read every row segment
+// contiguously (the node-major block is one run of bytes per row), and keeps
+// each node's value one plane down in registers.  P is thus read from global
+// memory about once per unit, plus the halos, with full-width loads, instead
+// of as seven strided node loads per node.
+constexpr int kZTileX = 128;
+
+template <typename T, int NB>
+struct ZTile {
+    static constexpr int S = even_up(NB);
+    static constexpr int NODE = S * (int)sizeof(T);            // bytes per node
+    static constexpr int U = NODE % 16 == 0 ? 1 : 2;           // nodes per 16-byte step
+    // nodes i0-1 .. i0+kZTileX, from a U-aligned start, rounded to U nodes
+    static constexpr int L = (kZTileX + 2 + (U - 1) + U - 1) / U * U;
+    static constexpr int CR = L * NODE / 16;                   // chunks per row segment
+};
+
+// Flat index of the first node of the segment of row (j, k) of the tile
+// starting at x = i0, and that node's offset (0 .. U-1) below the wanted
+// first node i0 - 1.
+template <int U>
+__device__ __forceinline__ long long zt_start(int n, int i0, int j, int k, int& off) {
+    const long long f = ((long long)k * n + j) * n + i0 - 1;
+    const int m = U == 1 ? 0 : (int)(((f % U) + U) % U);
+    off = m;
+    return f - m;
+}
+
+// Chunks of plane k (rows j0-1 .. j0+TY) into registers; chunks outside
+// [0, pbytes) and rows or planes outside the grid are left as zeros.
+template <typename T, int NB, int TY, int CPT>
+__device__ __forceinline__ void zt_fetch(const char* __restrict__ P, long long pbytes, int n, int i0, int j0, int k,
+                                         uint4 (&buf)[CPT]) {
+    using Z = ZTile<T, NB>;
+    constexpr int C = (TY + 2) * Z::CR;
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+        buf[q] = make_uint4(0u, 0u, 0u, 0u);
+        const int c = (int)threadIdx.x + q * kBlock;
+        if (c >= C || k < 0 || k >= n) continue;
+        const int row = c / Z::CR, cc = c - row * Z::CR;
+        const int j = j0 - 1 + row;
+        if (j < 0 || j >= n) continue;
+        int off;
+        const long long b = zt_start<Z::U>(n, i0, j, k, off) * Z::NODE + (long long)cc * 16;
+        if (b >= 0 && b + 16 <= pbytes) buf[q] = *reinterpret_cast<const uint4*>(P + b);
+    }
+}
+
+template <typename T, int NB, int TY, int CPT>
+__device__ __forceinline__ void zt_put(char* slot, const uint4 (&buf)[CPT]) {
+    using Z = ZTile<T, NB>;
+    constexpr int C = (TY + 2) * Z::CR;
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+        const int c = (int)threadIdx.x + q * kBlock;
+        if (c < C) reinterpret_cast<uint4*>(slot)[c] = buf[q];
+    }
+}
+
+// Node (x, y) of the tile (x in -1 .. kZTileX, y in -1 .. TY) in a slot
+// holding plane k.
+template <typename T, int NB>
+__device__ __forceinline__ const T* zt_node(const char* slot, int n, int i0, int j0, int k, int x, int y) {
+    using Z = ZTile<T, NB>;
+    int off = 0;
+    if (Z::U > 1) (void)zt_start<Z::U>(n, i0, j0 + y, k, off);
+    return reinterpret_cast<const T*>(slot + ((y + 1) * Z::L + x + 1 + off) * Z::NODE);
+}
+
+// Per-node operands of one plane step: r and the variable coefficients.
+template <typename T>
+struct ZOps {
+    double r;
+    T d, exm, exp, eym, eyp, ezp;
+};
+
+// The z-marching SpMM serves blocks of at most 48 bytes per node (FP64 up to
+// six columns, FP32 up to eight); wider ones use the row-mapped kernel.
+template <typename T, int NB>
+__host__ __device__ constexpr bool zt_fits() { return even_up(NB) * (int)sizeof(T) <= 48; }
+
+template <typename T, int NPT, int RPP, bool VAR>
+__device__ __forceinline__ void zt_ops(const FineOp<T>& op, const double* __restrict__ r, int n, int i, int j0, int yl,
+                                       int k, ZOps<T> (&o)[NPT]) {
+    const long long sy = n;
+#pragma unroll
+    for (int s = 0; s < NPT; ++s) {
+        const int j = j0 + yl + RPP * s;
+        o[s].r = 0.0;
+        o[s].d = o[s].exm = o[s].exp = o[s].eym = o[s].eyp = o[s].ezp = T(0);
+        if (i < n && j < n) {
+            const long long idx = ((long long)k * n + j) * n + i;
+            o[s].r = r[idx];
+            if (VAR) {
+                o[s].d = op.D[idx];
+                if (i > 0) o[s].exm = op.ex[idx - 1];
+                if (i < n - 1) o[s].exp = op.ex[idx];
+                if (j > 0) o[s].eym = op.ey[idx - sy];
+                if (j < n - 1) o[s].eyp = op.ey[idx];
+                if (k < n - 1) o[s].ezp = op.ez[idx];
+            }
+        }
+    }
+}
+
+// One unit per block: lb = (ty * nkz + kc) * ntx + tx (XCD-contiguous ranges
+// of lb are slabs of y tiles with all their z chunks).  pbytes: readable
+// bytes from P.  Each thread owns x = t mod kZTileX and rows
+// y = t / kZTileX + 2 s.  Each step first issues the loads of the next
+// step's per-node operands and the chunks of the plane after next, then
+// works on LDS and registers only, so the loads stay in flight across it.
+// VAR: variable coefficients (op.D, ex, ey, ez), else the constant h^-2
+// stencil.  Three blocks of 4 waves fit a CU (LDS of the FP64 six-column tile
+// ~51 KB); the variable-coefficient kernels on wide blocks carry the next
+// step's coefficients as well and get two, which keeps them free of spills.
+template <typename T, int NB, bool VAR>
+__host__ __device__ constexpr int zt_min_blocks() {
+    return (VAR && (sizeof(T) == 8 ? NB >= 5 : NB >= 7)) ? 2 : 3;
+}
+template <typename T, int NB, int TY, bool VAR>
+__global__ void __launch_bounds__(kBlock, (zt_min_blocks<T, NB, VAR>())) k_spmm_gram_z(const Ctl* __restrict__ ctl, int n, int ntx, int kz,
+                                                           int nkz, FineOp<T> op, const T* __restrict__ P,
+                                                           long long pbytes, T* __restrict__ Q,
+                                                           const double* __restrict__ r, double* __restrict__ part) {
+    if (ctl->state != 0) return;
+    using Z = ZTile<T, NB>;
+    constexpr int S = Z::S;
+    constexpr int NG = NB * (NB + 1) / 2;
+    constexpr int RPP = kBlock / kZTileX;                        // rows per pass
+    static_assert(TY % RPP == 0, "TY must be a multiple of the rows per pass");
+    constexpr int NPT = TY / RPP;                                // nodes per thread and plane
+    constexpr int SLOT = (TY + 2) * Z::L * Z::NODE;
+    constexpr int CPT = ((TY + 2) * Z::CR + kBlock - 1) / kBlock;
+    __shared__ __align__(16) char lds[2 * SLOT];
+
+    const int lb = xcd_block(gridDim.x);
+    const int tx = lb % ntx, rest = lb / ntx;
+    const int kc = rest % nkz, ty = rest / nkz;
+    const int i0 = tx * kZTileX, j0 = ty * TY, k0 = kc * kz, k1 = min(n, k0 + kz);
+    const int xl = (int)threadIdx.x % kZTileX, yl = (int)threadIdx.x / kZTileX;
+    const int i = i0 + xl;
+    const char* Pb = reinterpret_cast<const char*>(P);
+    constexpr bool var = VAR;
+
+    double acc[NG + NB];
+#pragma unroll
+    for (int q = 0; q < NG + NB; ++q) acc[q] = 0.0;
+    T pm[NPT][S];     // own node, plane k - 1
+    T ezm[NPT];       // ez between planes k - 1 and k (variable coefficient)
+#pragma unroll
+    for (int s = 0; s < NPT; ++s) {
+        const int j = j0 + yl + RPP * s;
+#pragma unroll
+        for (int c = 0; c < S; ++c) pm[s][c] = T(0);
+        ezm[s] = T(0);
+        if (i < n && j < n && k0 > 0 && k0 < n) {
+            const long long idx = ((long long)(k0 - 1) * n + j) * n + i;
+            load_node<T, S>(P + idx * S, pm[s]);
+            if (var) ezm[s] = op.ez[idx];
+        }
+    }
+    const int klast = min(k1, n - 1);       // last plane a step reads
+    ZOps<T> ops[NPT];
+    zt_ops<T, NPT, RPP, VAR>(op, r, n, i, j0, yl, k0, ops);
+    uint4 buf[CPT];
+    zt_fetch<T, NB, TY, CPT>(Pb, pbytes, n, i0, j0, k0, buf);
+    zt_put<T, NB, TY, CPT>(lds, buf);
+    if (k0 + 1 <= klast) {
+        zt_fetch<T, NB, TY, CPT>(Pb, pbytes, n, i0, j0, k0 + 1, buf);
+        zt_put<T, NB, TY, CPT>(lds + SLOT, buf);
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int k = k0; k < k1; ++k) {
+        ZOps<T> nops[NPT];
+        if (k + 1 < k1) zt_ops<T, NPT, RPP, VAR>(op, r, n, i, j0, yl, k + 1, nops);
+        const bool more = k + 2 <= klast;
+        if (more) zt_fetch<T, NB, TY, CPT>(Pb, pbytes, n, i0, j0, k + 2, buf);
+        const char* sc = lds + cur * SLOT;
+        const char* sn = lds + (cur ^ 1) * SLOT;
+#pragma unroll
+        for (int s = 0; s < NPT; ++s) {
+            const int y = yl + RPP * s, j = j0 + y;
+            if (i >= n || j >= n) continue;
+            const long long idx = ((long long)k * n + j) * n + i;
+            T own[S], q[S], nb[S];
+            load_node<T, S>(zt_node<T, NB>(sc, n, i0, j0, k, xl, y), own);
+            if constexpr (!var) {
+#pragma unroll
+                for (int c = 0; c < S; ++c) q[c] = T(6) * own[c];
+                auto sub = [&](const T* src) {
+                    load_node<T, S>(src, nb);
+#pragma unroll
+                    for (int c = 0; c < S; ++c) q[c] -= nb[c];
+                };
+                if (i > 0) sub(zt_node<T, NB>(sc, n, i0, j0, k, xl - 1, y));
+                if (i < n - 1) sub(zt_node<T, NB>(sc, n, i0, j0, k, xl + 1, y));
+                if (j > 0) sub(zt_node<T, NB>(sc, n, i0, j0, k, xl, y - 1));
+                if (j < n - 1) sub(zt_node<T, NB>(sc, n, i0, j0, k, xl, y + 1));
+                if (k > 0) {
+#pragma unroll
+                    for (int c = 0; c < S; ++c) q[c] -= pm[s][c];
+                }
+                if (k < n - 1) sub(zt_node<T, NB>(sn, n, i0, j0, k + 1, xl, y));
+#pragma unroll
+                for (int c = 0; c < S; ++c) q[c] *= op.s0;
+            } else {
+#pragma unroll
+                for (int c = 0; c < S; ++c) q[c] = ops[s].d * own[c];
+                auto sub = [&](const T* src, T e) {
+                    load_node<T, S>(src, nb);
+#pragma unroll
+                    for (int c = 0; c < S; ++c) q[c] -= e * nb[c];
+                };
+                if (i > 0) sub(zt_node<T, NB>(sc, n, i0, j0, k, xl - 1, y), ops[s].exm);
+                if (i < n - 1) sub(zt_node<T, NB>(sc, n, i0, j0, k, xl + 1, y), ops[s].exp);
+                if (j > 0) sub(zt_node<T, NB>(sc, n, i0, j0, k, xl, y - 1), ops[s].eym);
+                if (j < n - 1) sub(zt_node<T, NB>(sc, n, i0, j0, k, xl, y + 1), ops[s].eyp);
+                if (k > 0) {
+#pragma unroll
+                    for (int c = 0; c < S; ++c) q[c] -= ezm[s] * pm[s][c];
+                }
+                if (k < n - 1) sub(zt_node<T, NB>(sn, n, i0, j0, k + 1, xl, y), ops[s].ezp);
+                ezm[s] = ops[s].ezp;
+            }
+            store_node<T, S>(Q + idx * S, q);
+            int g = 0;
+#pragma unroll
+            for (int a = 0; a < NB; ++a)
+#pragma unroll
+                for (int c = a; c < NB; ++c) acc[g++] += double(own[a]) * double(q[c]);
+#pragma unroll
+            for (int a = 0; a < NB; ++a) acc[NG + a] += double(own[a]) * ops[s].r;
+#pragma unroll
+            for (int c = 0; c < S; ++c) pm[s][c] = own[c];
+        }
+#pragma unroll
+        for (int s = 0; s < NPT; ++s) ops[s] = nops[s];
+        __syncthreads();
+        if (more) zt_put<T, NB, TY, CPT>(lds + cur * SLOT, buf);
+        __syncthreads();
+        cur ^= 1;
+    }
+    block_sum_store<NG + NB>(acc, part, gridDim.x, lb);
+}
+
 // Explicit Z (widened to double, column-major), for the mg_block entry point.
 template <int DIM, typename T, int NB, int NE>
 __global__ void __launch_bounds__(kBlock) k_write_Z(Rows R, int N, const T* __restrict__ Y, int nc,

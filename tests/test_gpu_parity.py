@@ -135,6 +135,39 @@ def test_iterates_match_oracle(case):
     s.close()
 
 
+# 3D grids for the z-marching SpMM: two x tiles (n > 128, the second one
+# three nodes wide), partial y tiles and z chunks, and tiny grids (one tile,
+# fewer planes than a chunk).
+ZGRIDS = [
+    (3, 131, 3, None, 21),
+    (3, 131, 3, 7, 22),
+    (3, 3, 1, None, 23),
+    (3, 2, 2, 9, 24),
+    (3, 5, 2, None, 25),
+]
+
+
+@pytest.mark.parametrize("case", ZGRIDS, ids=case_id)
+@pytest.mark.parametrize("precision", [0, 1])
+def test_ztile_grids_iterates_match_oracle(case, precision):
+    dim, n, nl, ks, seed = case
+    h, s, b = build_pair(*case, precision=precision)
+    bg = dev(b)
+    ks_ = (1, 2, 3)
+    for kk in ks_:
+        o = mpcg.mpcg(h, b, tol=0.0, maxit=kk)
+        xg, inf = s.solve(bg, tol=0.0, maxit=kk)
+        if inf["status"] != amg.OK or o.iterations < kk:
+            break           # converged or exhausted before kk on a tiny grid
+        bar = 1e-10 if precision == 0 else 1e-3   # FP32 bulk: indexing, not rounding
+        assert rel(host(xg), o.x) <= bar, (kk, rel(host(xg), o.x))
+    x, info = s.solve(bg, tol=1e-8)
+    assert info["status"] == amg.OK
+    rt = s.residual(bg, x)
+    assert float(torch.linalg.norm(rt) / torch.linalg.norm(bg)) <= 1e-8
+    s.close()
+
+
 def test_edge_cases():
     dim, n, nl = 2, 31, 4
     h, s, b = build_pair(dim, n, nl, None, 1)
