@@ -13,10 +13,13 @@ Modules
   smoother   damped-Jacobi smoothing iteration, eq. (2)
   mpcg       additive-MG corrections as a direction block, the pseudo-inverse
              step, eq. (4) and Algorithm 1 (Sec. 2.2)
-  pcg        textbook preconditioned CG, used only as a pin
+  pcg        textbook preconditioned CG (a pin, and the outer loop of the
+             comparators)
+  comparators  the comparison methods of Sec. 3: additive MG-PCG and
+             MG(V)-PCG (one V-cycle as preconditioner)
   cnn        FP64 U-Net forward/backward for the learned direction
 
 Every function is pinned by the tests against closed forms, invariants, dense
 brute force or textbook routines; anything unpinned says so in its docstring.
 """
-from . import operators, hierarchy, smoother, mpcg, pcg  # noqa: F401
+from . import operators, hierarchy, smoother, mpcg, pcg, comparators  # noqa: F401
