@@ -7,8 +7,9 @@ levels, damped Jacobi nu=2 omega=2/3, b ~ U[-1,1] seed 2, x0 = 0) to
 ||r|| <= 1e-8 ||b|| in FP64, with b and x resident in device memory.
 ``value`` is the mean time per solve (ms, lower is better).  The same
 protocol is applied to the FP32-bulk form, to the heterogeneous-kappa
-workload (truncation window m = 1 and m = 5) and to the learned direction;
-they are reported under ``variants``.
+workload (truncation window m = 1 and m = 5), to the comparison methods of
+Sec. 3 (additive MG-PCG, MG(V)-PCG) and to the learned direction; they are
+reported under ``variants``.
 
 The roofline entry is for the fine-level kernel with the largest time per
 iteration; its average launch duration is measured with HIP events on the
@@ -112,11 +113,11 @@ def per_dof(dim, nlevels, bulk, var):
             "update_xP": 2 * b * bulk + 16 + bulk, "fine_W": b * bulk + bulk}
 
 
-def run_solver(amg, torch, prob, precision, steps, warmup, kappa=None, net=None, m=1):
+def run_solver(amg, torch, prob, precision, steps, warmup, kappa=None, net=None, m=1, method=0):
     import workloads as W
     b = torch.as_tensor(W.problem_rhs(prob), device="cuda")
     t0 = time.time()
-    s = amg.Solver(prob.dim, prob.n, prob.nlevels, kappa=kappa, precision=precision, m=m)
+    s = amg.Solver(prob.dim, prob.n, prob.nlevels, kappa=kappa, precision=precision, m=m, method=method)
     setup_s = time.time() - t0
     if net is not None:
         s.attach(net)
@@ -252,6 +253,17 @@ def main(argv=None):
                                                 "iterations_m1": plain["iterations"],
                                                 "time_vs_m1": round(ms5 / plain["ms"], 3)}
             s5.close()
+        # the comparison methods of Sec. 3 on the same hierarchy and kernels:
+        # CG preconditioned by the summed additive correction and by one
+        # V-cycle (1 + 1 damped-Jacobi sweeps, the additive nu = 2 per level)
+        for pname, pr, kp in (("poisson3d_127", prob, None), ("diffusion3d_127", dprob, kap)):
+            ref = var.get(f"{pname}_fp64") if pname == "diffusion3d_127" else {"ms": round(ms, 4), "iterations": iters}
+            for meth, tag in ((amg.ADDITIVE_PCG, "additive_pcg"), (amg.VCYCLE_PCG, "vcycle_pcg")):
+                s6, _, _, ms6, it6, _, _ = run_solver(amg, torch, pr, 0, args.steps, args.warmup, kappa=kp,
+                                                      method=meth)
+                var[f"{pname}_{tag}_fp64"] = {"ms": round(ms6, 4), "iterations": it6,
+                                              "mpcg_iterations": ref["iterations"], "mpcg_ms": ref["ms"]}
+                s6.close()
         # the learned direction (committed trained weights) on the same problem
         from paper_2402_12833_amd import train as T
         net = amg.Network(dprob.n)

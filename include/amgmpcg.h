@@ -76,7 +76,26 @@ typedef struct {
     double  refresh_drop; /* FP32 bulk: replace r by b - A x (FP64) whenever
                              ||r|| fell by this factor since the last refresh,
                              and before accepting convergence (1e-2)          */
+    int32_t method;       /* AMGMPCG_METHOD_*: the solver of Algorithm 1 (0)
+                             or one of the comparison methods of Sec. 3, CG
+                             with one search direction per iteration         */
+    int32_t nu_pre;       /* V-cycle (method 2): damped-Jacobi sweeps before
+                             and after the coarse correction on every level
+                             but the coarsest, which gets nu_pre + nu_post
+                             from zero; 0: max(1, nu / 2).  Must be equal
+                             (a symmetric preconditioner for CG)            */
+    int32_t nu_post;
 } amgmpcg_options;
+
+/* Solution methods (amgmpcg_options.method).  The comparison methods share
+ * the hierarchy, smoother, transfers and the SpMM/Gram and reduction kernels
+ * of the MPCG solver; they need m = 1 and no learned direction. */
+#define AMGMPCG_METHOD_MPCG          0  /* Algorithm 1: the L+1 level
+                                           corrections as separate directions */
+#define AMGMPCG_METHOD_ADDITIVE_PCG  1  /* CG preconditioned by the sum of the
+                                           level corrections (eq. (3))        */
+#define AMGMPCG_METHOD_VCYCLE_PCG    2  /* CG preconditioned by one V-cycle
+                                           (multiplicative MG, Sec. 2.1)      */
 
 typedef struct {
     int32_t status;          /* AMGMPCG_OK / _MAXIT / _BREAKDOWN / _NONFINITE   */
@@ -91,7 +110,8 @@ typedef struct {
 
 typedef struct amgmpcg_handle amgmpcg_handle;
 
-/* Default options (m=1, nu=2, omega=2/3, maxit=1000, FP64, k_poll=8). */
+/* Default options (m=1, nu=2, omega=2/3, maxit=1000, FP64, k_poll=8,
+ * method MPCG, nu_pre = nu_post = 0). */
 void amgmpcg_default_options(amgmpcg_options* opts);
 
 /* setup(A, hierarchy): build the level hierarchy of a structured problem.
@@ -120,7 +140,8 @@ int amgmpcg_solve_host(amgmpcg_handle* h, const double* b, double* x,
 /* The block Z = [z^0 | ... | z^L] of level corrections of r (Algorithm 1,
  * "corrections from all levels").  r_dev: DEVICE, n^dim doubles.  Z_dev:
  * DEVICE, column-major n^dim x (L+1) doubles (column l = level l, coarsest
- * first), written in the handle's precision and widened to double. */
+ * first), written in the handle's precision and widened to double.
+ * AMGMPCG_INVALID_ARG for a handle set up with a comparison method. */
 int amgmpcg_mg_block(amgmpcg_handle* h, const double* r_dev, double* Z_dev);
 
 /* Number of levels, search directions and per-axis nodes of level l. */

@@ -6,4 +6,5 @@ The solver lives in ``libamgmpcg.so`` (HIP kernels + C ABI, header
 from .binding import (  # noqa: F401
     AmgMpcgError, BatchedSolver, Network, Solver, cnn_weight_count, CNN_LAYERS, default_options, gram_pinv, header_functions, last_error, load, status_string,
     OK, MAXIT, BREAKDOWN, INVALID_ARG, NOT_SPD, DIM_MISMATCH, NONFINITE, OOM, HIP_ERROR, UNAVAILABLE,
+    MPCG, ADDITIVE_PCG, VCYCLE_PCG,
 )

@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(HERE, "libamgmpcg.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "amgmpcg.h")
 
 OK, MAXIT, BREAKDOWN = 0, 1, 2
+# solution methods (Solver(..., method=...))
+MPCG, ADDITIVE_PCG, VCYCLE_PCG = 0, 1, 2
 INVALID_ARG, NOT_SPD, DIM_MISMATCH, NONFINITE, OOM, HIP_ERROR, UNAVAILABLE = -1, -2, -3, -4, -5, -6, -7
 
 
@@ -29,7 +31,8 @@ class Grid(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("m", c_int32), ("nu", c_int32), ("omega", c_double), ("maxit", c_int32),
                 ("precision", c_int32), ("pinv_tau", c_double), ("k_poll", c_int32),
-                ("record_history", c_int32), ("refresh_drop", c_double)]
+                ("record_history", c_int32), ("refresh_drop", c_double), ("method", c_int32),
+                ("nu_pre", c_int32), ("nu_post", c_int32)]
 
 
 class Info(ctypes.Structure):

@@ -20,6 +20,7 @@
 #include "grid_kernels.hpp"
 #include "setup.hpp"
 #include "small_kernels.hpp"
+#include "pcg_kernels.hpp"
 #include "batched.hpp"
 #include "cnn_host.hpp"
 
@@ -152,7 +153,9 @@ class Solver : public SolverBase {
     Solver(const amgmpcg_grid& g, const amgmpcg_options& o, hipStream_t stream) : opt_(o), stream_(stream) {
         dim = DIM;
         nlev = g.nlevels;
-        nb = nlev;
+        method_ = o.method;
+        nb = method_ == AMGMPCG_METHOD_MPCG ? nlev : 1;
+        vnu_ = o.nu_pre > 0 ? o.nu_pre : std::max(1, o.nu / 2);
         L_ = nlev - 1;
         mixed_ = std::is_same<T, float>::value;
         n_axis.resize(nlev);
@@ -249,6 +252,22 @@ class Solver : public SolverBase {
         HIPCHK(hipMemset(Q_.p, 0, Q_.n * sizeof(T)));
         cL_.alloc(N);
         if (opt_.nu > 2) cL2_.alloc(N);
+        if (method_ != AMGMPCG_METHOD_MPCG) zv_.alloc(N);
+        if (method_ == AMGMPCG_METHOD_VCYCLE_PCG) {
+            vcL_.alloc(N);
+            vtL_.alloc(N);
+            vrL_.alloc(N);
+            vg_.resize(nlev);
+            vc_.resize(nlev);
+            vt_.resize(nlev);
+            vr_.resize(nlev);
+            for (int l = 0; l < L_; ++l) {
+                vg_[l].alloc(N_[l]);
+                vc_[l].alloc(N_[l]);
+                vt_[l].alloc(N_[l]);
+                vr_[l].alloc(N_[l]);
+            }
+        }
         part_.alloc((size_t)FB_ * kPartRow);
         partG_.alloc((size_t)kGramRow * std::max(std::max(SB_[0], SB_[1]), FBG_));
         small_.alloc(kMaxNB + 2 * kMaxWin * kMaxNB * kMaxNB);
@@ -323,6 +342,8 @@ class Solver : public SolverBase {
     void attach(cnn::Net* net) override {
         const int N = N_[L_];
         if (net) {
+            if (method_ != AMGMPCG_METHOD_MPCG)
+                throw ApiError(AMGMPCG_INVALID_ARG, "the learned direction needs the MPCG method");
             if (DIM != 3) throw ApiError(AMGMPCG_INVALID_ARG, "the learned direction needs a 3D problem");
             if (net->n != n_axis[L_]) throw ApiError(AMGMPCG_DIM_MISMATCH, "network grid differs from the problem grid");
             if (nlev + 1 > kMaxNB) throw ApiError(AMGMPCG_INVALID_ARG, "too many levels for an extra direction");
@@ -500,6 +521,8 @@ class Solver : public SolverBase {
     }
 
     void mg_block(const double* r_dev, double* Z_dev) override {
+        if (method_ != AMGMPCG_METHOD_MPCG)
+            throw ApiError(AMGMPCG_INVALID_ARG, "mg_block is defined for the MPCG method");
         enqueue_mg(ctl_free_, r_dev);
         const int N = N_[L_];
         dispatch_nb([&](auto nbc) {
@@ -943,6 +966,15 @@ class Solver : public SolverBase {
         k_init_residual<DIM><<<FB_, kBlock, 0, stream_>>>(rows_, f64_, b_.p, x_.p, r_.p, part_init());
         k_reduce_init<<<1, kRedBlock, 0, stream_>>>(ctl_, part_init(), FB_, tol, hist_cap_ ? rhist_.p : nullptr);
         k_zero_if<<<FB_, kBlock, 0, stream_>>>(ctl_, x_.p, N);
+        if (method_ != AMGMPCG_METHOD_MPCG) {
+            // comparison methods: p_0 = z_0 = B r_0, one direction
+            T* z = precondition(ctl_, r_.p);
+            k_xP1<T><<<FB_, kBlock, 0, stream_>>>(ctl_, N, Pslot(0), z, x_.p, d_alpha(), d_beta(), 1);
+            launch_spmm<1>(ctl_, Pslot(0), Qslot(0), r_.p, stream_);
+            k_reduce_alpha<1><<<1, kRedBlock, 0, stream_>>>(ctl_, part_G(), spmm_blocks<1>(), d_Gplus(0), d_alpha(),
+                                                         hist_cap_ ? ahist_.p : nullptr);
+            return;
+        }
         enqueue_mg(ctl_, r_.p);
         dispatch_nb([&](auto nbc) {
             constexpr int NB = decltype(nbc)::value;
@@ -964,6 +996,11 @@ class Solver : public SolverBase {
         const int cur = j % m_, nxt = (j + 1) % m_;
         hipStream_t saved = stream_;
         stream_ = s;
+        if (method_ != AMGMPCG_METHOD_MPCG) {
+            enqueue_iteration_pcg(s);
+            stream_ = saved;
+            return;
+        }
         dispatch_nb([&](auto nbc) {
             constexpr int NB = decltype(nbc)::value;
             [[maybe_unused]] constexpr int NE = decltype(nbc)::ne;
@@ -995,6 +1032,115 @@ class Solver : public SolverBase {
             mark(kSecEnd);
         });
         stream_ = saved;
+    }
+
+    // One iteration of a comparison method (CG, one direction, m = 1): the
+    // MPCG iteration with the block replaced by z = B r.
+    void enqueue_iteration_pcg(hipStream_t s) {
+        const int N = N_[L_];
+        mark(kSecUpdateR);
+        k_update_r<T, 1><<<FB_, kBlock, 0, s>>>(ctl_, N, Qslot(0), d_alpha(), r_.p, part_rho());
+        T* z = precondition(ctl_, r_.p);
+        mark(kSecFineW);
+        k_W1<T><<<FB_, kBlock, 0, s>>>(ctl_, N, Qslot(0), z, part_Wslot(0));
+        mark(kSecReduceBeta);
+        k_reduce_beta<1><<<1, kRedBlock, 0, s>>>(ctl_, part_rho(), FB_, part_Wslot(0), FB_, 1, 0, d_Gplus(0),
+                                              d_beta(0), hist_cap_ ? rhist_.p : nullptr, mixed_ ? 1 : 0);
+        mark(kSecUpdateXP);
+        k_xP1<T><<<FB_, kBlock, 0, s>>>(ctl_, N, Pslot(0), z, x_.p, d_alpha(), d_beta(0), 0);
+        if (mixed_) {
+            mark(kSecRefresh);
+            k_refresh<DIM><<<FB_, kBlock, 0, s>>>(ctl_, rows_, f64_, b_.p, x_.p, r_.p, part_ref());
+            k_refresh_reduce<<<1, kRedBlock, 0, s>>>(ctl_, part_ref(), FB_, hist_cap_ ? rhist_.p : nullptr);
+        }
+        mark(kSecSpmmGram);
+        launch_spmm<1>(ctl_, Pslot(0), Qslot(0), r_.p, s);
+        mark(kSecReduceAlpha);
+        k_reduce_alpha<1><<<1, kRedBlock, 0, s>>>(ctl_, part_G(), spmm_blocks<1>(), d_Gplus(0), d_alpha(),
+                                               hist_cap_ ? ahist_.p : nullptr);
+        mark(kSecEnd);
+    }
+
+    // z = B r of a comparison method; returns the device vector holding z.
+    T* precondition(const Ctl* ctl, const double* r) {
+        if (method_ == AMGMPCG_METHOD_ADDITIVE_PCG) {
+            enqueue_mg(ctl, r);
+            mark(kSecFineW);
+            dispatch_plain([&](auto nlc) {
+                constexpr int NL = decltype(nlc)::value;
+                const int nc = L_ > 0 ? n_axis[L_ - 1] : 1;
+                k_sum_z<DIM, T, NL><<<FB_, kBlock, 0, stream_>>>(ctl, rows_, fine_Y(), nc, cL_final_, zv_.p);
+            });
+            return zv_.p;
+        }
+        return enqueue_vcycle(ctl, r);
+    }
+
+    // ---- V-cycle (multiplicative MG, Sec. 2.1) -------------------------
+    // damped-Jacobi sweeps on the finest level: `count` sweeps from zero
+    // (count >= 1), or `count` sweeps from `start`; results ping-pong between
+    // vcL_ and vtL_, the buffer holding the result is returned.
+    T* vc_fine_from_zero(const Ctl* ctl, const double* r, int count) {
+        const T omega = T(opt_.omega);
+        k_fine_smooth<DIM, T, double><<<FB_, kBlock, 0, stream_>>>(ctl, rows_, fop_, r, vcL_.p, omega,
+                                                                   count >= 2 ? 1 : 0);
+        return vc_fine_sweeps(ctl, r, vcL_.p, count - std::min(count, 2));
+    }
+    T* vc_fine_sweeps(const Ctl* ctl, const double* r, T* cur, int count) {
+        const T omega = T(opt_.omega);
+        for (int s = 0; s < count; ++s) {
+            T* nxt = cur == vcL_.p ? vtL_.p : vcL_.p;
+            k_fine_sweep<DIM, T, double><<<FB_, kBlock, 0, stream_>>>(ctl, rows_, fop_, r, cur, nxt, omega);
+            cur = nxt;
+        }
+        return cur;
+    }
+    T* vc_coarse_sweeps(const Ctl* ctl, int l, T* cur, int count) {
+        const T omega = T(opt_.omega);
+        CoarseOp<T> op{n_axis[l], N_[l], coef_[l].p};
+        const int blocks = (N_[l] + kBlock - 1) / kBlock;
+        for (int s = 0; s < count; ++s) {
+            T* nxt = cur == vc_[l].p ? vt_[l].p : vc_[l].p;
+            k_vc_coarse<DIM, T><<<blocks, kBlock, 0, stream_>>>(ctl, op, vg_[l].p, cur, nxt, omega, 1);
+            cur = nxt;
+        }
+        return cur;
+    }
+
+    // One V-cycle for A c = r from c = 0: nu sweeps before and after the
+    // coarse correction on every level but the coarsest (2 nu sweeps from
+    // zero); the restriction kernels also write the first sweep from zero of
+    // the coarser level.  Returns the vector holding c on the finest level.
+    T* enqueue_vcycle(const Ctl* ctl, const double* r) {
+        const T omega = T(opt_.omega);
+        const int nu = vnu_, L = L_;
+        mark(kSecFineSmooth);
+        if (L == 0) return vc_fine_from_zero(ctl, r, 2 * nu);
+        T* cf = vc_fine_from_zero(ctl, r, nu);
+        mark(kSecRestrict);
+        k_fine_resid<DIM, T, double><<<FB_, kBlock, 0, stream_>>>(ctl, rows_, fop_, r, cf, vrL_.p);
+        k_restrict<DIM, T, T><<<(N_[L - 1] + kBlock - 1) / kBlock, kBlock, 0, stream_>>>(
+            ctl, vrL_.p, n_axis[L], vg_[L - 1].p, n_axis[L - 1], N_[L - 1], diag(L - 1), vc_[L - 1].p, omega);
+        std::vector<T*> c(L, nullptr);
+        for (int l = L - 1; l >= 1; --l) {
+            c[l] = vc_coarse_sweeps(ctl, l, vc_[l].p, nu - 1);
+            CoarseOp<T> op{n_axis[l], N_[l], coef_[l].p};
+            k_vc_coarse<DIM, T><<<(N_[l] + kBlock - 1) / kBlock, kBlock, 0, stream_>>>(ctl, op, vg_[l].p, c[l],
+                                                                                     vr_[l].p, omega, 2);
+            k_restrict<DIM, T, T><<<(N_[l - 1] + kBlock - 1) / kBlock, kBlock, 0, stream_>>>(
+                ctl, vr_[l].p, n_axis[l], vg_[l - 1].p, n_axis[l - 1], N_[l - 1], diag(l - 1), vc_[l - 1].p, omega);
+        }
+        mark(kSecCoarseSmooth);
+        c[0] = vc_coarse_sweeps(ctl, 0, vc_[0].p, 2 * nu - 1);
+        mark(kSecProlong);
+        for (int l = 1; l < L; ++l) {
+            k_prolong_add<DIM, T><<<(N_[l] + kBlock - 1) / kBlock, kBlock, 0, stream_>>>(ctl, c[l - 1], n_axis[l - 1],
+                                                                                       c[l], n_axis[l], N_[l]);
+            c[l] = vc_coarse_sweeps(ctl, l, c[l], nu);
+        }
+        k_prolong_add<DIM, T><<<(N_[L] + kBlock - 1) / kBlock, kBlock, 0, stream_>>>(ctl, c[L - 1], n_axis[L - 1], cf,
+                                                                                   n_axis[L], N_[L]);
+        return vc_fine_sweeps(ctl, r, cf, nu);
     }
 
     // ---- per-section timing inside real iterations --------------------
@@ -1119,6 +1265,7 @@ class Solver : public SolverBase {
     bool graph_ready_ = false;
     bool mixed_ = false;
     int L_ = 0, FB_ = 1, FBG_ = 1, hist_cap_ = 0, last_iters_ = 0;
+    int method_ = AMGMPCG_METHOD_MPCG, vnu_ = 1;   // solution method; V-cycle sweeps per side
     // z-marching SpMM: x tiles; per resident-block count (2, 3): planes per
     // unit, z chunks, units (= blocks)
     int zntx_ = 1, zkz_[2] = {1, 1}, znkz_[2] = {1, 1}, SB_[2] = {1, 1};
@@ -1135,6 +1282,8 @@ class Solver : public SolverBase {
     T* cL_final_ = nullptr;
     DevBuf<double> x_, r_, b_, part_, small_, ahist_, rhist_, partWin_, partG_;
     DevBuf<T> P_, Q_, cL_, cL2_, dl_;
+    DevBuf<T> zv_, vcL_, vtL_, vrL_;                   // comparison methods: z = B r; fine V-cycle vectors
+    std::vector<DevBuf<T>> vg_, vc_, vt_, vr_;         // coarse V-cycle vectors (rhs, iterate x2, residual)
     DevBuf<double> xt_;
     DevBuf<unsigned short> lk_;
     Ctl* ctl_ = nullptr;
@@ -1394,6 +1543,14 @@ static void validate_options(const amgmpcg_options* o) {
     if (o->k_poll < 1 || o->k_poll > 64) throw ApiError(AMGMPCG_INVALID_ARG, "k_poll must be in 1..64");
     if (!(o->refresh_drop > 0.0 && o->refresh_drop < 1.0))
         throw ApiError(AMGMPCG_INVALID_ARG, "refresh_drop must be in (0, 1)");
+    if (o->method < AMGMPCG_METHOD_MPCG || o->method > AMGMPCG_METHOD_VCYCLE_PCG)
+        throw ApiError(AMGMPCG_INVALID_ARG, "method must be 0, 1 or 2");
+    if (o->method != AMGMPCG_METHOD_MPCG && o->m != 1)
+        throw ApiError(AMGMPCG_INVALID_ARG, "the comparison methods need m = 1");
+    if (o->nu_pre < 0 || o->nu_pre > 8 || o->nu_post < 0 || o->nu_post > 8)
+        throw ApiError(AMGMPCG_INVALID_ARG, "nu_pre and nu_post must be in 0..8");
+    if (o->nu_pre != o->nu_post)
+        throw ApiError(AMGMPCG_INVALID_ARG, "nu_pre and nu_post must be equal (symmetric V-cycle)");
 }
 
 static void validate_grid(const amgmpcg_grid* g) {
@@ -1431,6 +1588,9 @@ void amgmpcg_default_options(amgmpcg_options* o) {
     o->k_poll = 8;
     o->record_history = 1;
     o->refresh_drop = 1e-2;
+    o->method = AMGMPCG_METHOD_MPCG;
+    o->nu_pre = 0;
+    o->nu_post = 0;
 }
 
 int amgmpcg_setup_grid(const amgmpcg_grid* grid, const amgmpcg_options* opts, void* stream, amgmpcg_handle** out) {

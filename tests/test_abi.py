@@ -58,7 +58,8 @@ def test_grid_validation(lib, grid, expect):
 
 
 @pytest.mark.parametrize("kw", [dict(m=0), dict(m=9), dict(nu=0), dict(omega=1.5), dict(maxit=0), dict(precision=3),
-                                dict(k_poll=0), dict(refresh_drop=2.0)])
+                                dict(k_poll=0), dict(refresh_drop=2.0), dict(method=3), dict(method=-1),
+                                dict(method=1, m=2), dict(method=2, nu_pre=1, nu_post=2), dict(nu_pre=9, nu_post=9)])
 def test_option_validation(lib, kw):
     code, _ = _setup(lib, B.Grid(2, 31, 3, None), amg.default_options(**kw))
     assert code == B.INVALID_ARG
