@@ -29,6 +29,8 @@ import platform
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -145,6 +147,33 @@ def run_solver(amg, torch, prob, precision, steps, warmup, kappa=None, net=None,
     return s, b, x, ms, it, setup_s, infos[-1]
 
 
+def run_batched(amg, torch, precision, steps, warmup):
+    """The batched workload: 512 2D Poisson problems (sides U{31..255}), all
+    solved by one graph of batched launches per k_poll iterations."""
+    import workloads as W
+    table = W.batched_instances()
+    bcat = torch.as_tensor(np.concatenate([W.batched_rhs(t) for t in table]), device="cuda")
+    bsolv = amg.BatchedSolver([(2, t.n, t.nlevels) for t in table], precision=precision)
+    xb = torch.zeros_like(bcat)
+    for _ in range(warmup):
+        xb.zero_()
+        bsolv.solve(bcat, xb, tol=1e-8)
+    tms = []
+    binfos = []
+    for _ in range(steps):
+        xb.zero_()
+        torch.cuda.synchronize()
+        _, binfos, bms = bsolv.solve(bcat, xb, tol=1e-8)
+        tms.append(bms)
+    its = [i["iterations"] for i in binfos]
+    assert all(i["status"] == amg.OK for i in binfos)
+    out = {"ms": round(float(np.mean(tms)), 4), "problems": len(table), "dofs": int(bsolv.N),
+           "iterations_min": int(min(its)), "iterations_max": int(max(its)),
+           "iterations_mean": round(float(np.mean(its)), 2)}
+    bsolv.close()
+    return out
+
+
 def cpu_baseline(prob, max_iters=None):
     """The FP64 oracle (numpy/scipy, one thread) on the same workload."""
     from threadpoolctl import threadpool_limits
@@ -166,6 +195,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="time only the 512-problem batched workload (FP32 bulk) and print its line")
     ap.add_argument("--calibrate", action="store_true",
                     help="end with one plain 512 MiB read + 512 MiB write elementwise kernel (counter calibration)")
     args = ap.parse_args(argv)
@@ -180,6 +211,10 @@ def main(argv=None):
     import paper_2402_12833_amd as amg
     import workloads as W
     amg.load()
+    if args.batched_only:
+        res = run_batched(amg, torch, 1, args.steps, args.warmup)
+        print(json.dumps({"workload": "batched2d_512", "dtype": "f32 bulk / f64 Gram", **res}), flush=True)
+        return 0
 
     prob = W.POISSON3D_127
     s, b, x, ms, iters, setup_s, info = run_solver(amg, torch, prob, 0, args.steps, args.warmup)
@@ -264,6 +299,8 @@ def main(argv=None):
                 var[f"{pname}_{tag}_fp64"] = {"ms": round(ms6, 4), "iterations": it6,
                                               "mpcg_iterations": ref["iterations"], "mpcg_ms": ref["ms"]}
                 s6.close()
+        for prec, tag in ((1, "fp32bulk"), (0, "fp64")):
+            var[f"batched2d_512_{tag}"] = run_batched(amg, torch, prec, args.steps, args.warmup)
         # the learned direction (committed trained weights) on the same problem
         from paper_2402_12833_amd import train as T
         net = amg.Network(dprob.n)

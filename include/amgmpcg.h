@@ -163,19 +163,21 @@ int amgmpcg_history(const amgmpcg_handle* h, int32_t cap, double* alpha_out,
 /* Batched solves: count independent Poisson problems (kappa must be NULL,
  * all of one dim, each with its own n and nlevels <= 6) whose hierarchies
  * are built here (Sec. 2.1 per problem); grids: HOST array of count entries.
- * opts as for amgmpcg_setup_grid (nu must be 1 or 2).  The problems are
- * solved together by one persistent kernel launch captured in a HIP graph:
- * workgroups take problems largest first from an atomic queue and each runs
- * Algorithm 1 for its problem to the end.
- * CURRENTLY SWITCHED OFF: returns AMGMPCG_UNAVAILABLE after validating its
- * arguments (its first GPU run faulted; the cause is not yet established). */
+ * opts as for amgmpcg_setup_grid (nu must be 1 or 2, m = 1, the MPCG
+ * method).  The problems are solved together (Algorithm 1 for each): every
+ * step is one launch over all problems with the same number of levels, each
+ * block working on one problem's nodes; k_poll iterations of all problems
+ * are captured in one HIP graph, launched until every problem has stopped;
+ * each problem has its own convergence flag.  Errors: AMGMPCG_INVALID_ARG
+ * for bad arguments (checked before any device call), AMGMPCG_NOT_SPD,
+ * AMGMPCG_OOM / AMGMPCG_HIP_ERROR from the device. */
 int amgmpcg_setup_batched(int32_t count, const amgmpcg_grid* grids, const amgmpcg_options* opts,
                           void* stream, amgmpcg_handle** out);
 
 /* b_dev, x_dev: DEVICE, the problems' vectors concatenated in the order of
  * grids (problem i starts at offset sum_{j<i} n_j^dim); x holds every x_0 on
  * entry and every result on return.  infos: HOST, count entries or NULL.
- * batch_ms: device time of the launch (HIP events) or NULL.  Returns
+ * batch_ms: device time of the whole solve (HIP events) or NULL.  Returns
  * AMGMPCG_OK if every problem converged, else the first other status. */
 int amgmpcg_solve_batched(amgmpcg_handle* h, const double* b_dev, double* x_dev, double tol,
                           int32_t maxit, amgmpcg_info* infos, double* batch_ms);

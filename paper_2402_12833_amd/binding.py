@@ -353,7 +353,8 @@ class Solver:
 
 
 class BatchedSolver:
-    """Many independent Poisson problems solved by one persistent launch.
+    """Many independent Poisson problems solved together (batched launches,
+    one HIP graph of k_poll iterations for all of them).
 
     problems: sequence of (dim, n, nlevels).  Vectors are concatenated in
     problem order (problem i starts at sum_{j<i} n_j^dim).

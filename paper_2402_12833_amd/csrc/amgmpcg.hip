@@ -1314,20 +1314,18 @@ class BatchedSolver : public BatchedBase {
         : opt_(o), stream_(stream) {
         count = cnt;
         mixed_ = std::is_same<T, float>::value;
-        hinst_.resize(cnt);
-        offs_.resize(cnt + 1);
-        offs_[0] = 0;
-        // sizes of every arena
-        size_t nx = 0, nP = 0, ncoef = 0, nvec = 0, nY = 0;
+        offs_.assign(cnt + 1, 0);
+        nlev_.resize(cnt);
         std::vector<std::vector<int>> sizes(cnt);
+        size_t nP = 0, ncoef = 0, nvec = 0, nY = 0;
         for (int i = 0; i < cnt; ++i) {
             const int nl = grids[i].nlevels;
+            nlev_[i] = nl;
             sizes[i].resize(nl);
             sizes[i][nl - 1] = grids[i].n;
             for (int l = nl - 2; l >= 0; --l) sizes[i][l] = sizes[i][l + 1] / 2;
             const size_t N = (size_t)host::ipow(grids[i].n, DIM);
             offs_[i + 1] = offs_[i] + N;
-            nx += N;
             nP += (size_t)even_up(nl) * N;
             for (int l = 0; l + 1 < nl; ++l) {
                 const size_t Nl = (size_t)host::ipow(sizes[i][l], DIM);
@@ -1336,23 +1334,52 @@ class BatchedSolver : public BatchedBase {
                 nY += (size_t)even_up(l + 1) * Nl;
             }
         }
-        total = (int64_t)nx;
-        r_.alloc(nx);
+        total = (int64_t)offs_[cnt];
+        x_.alloc(offs_[cnt]);
+        r_.alloc(offs_[cnt]);
+        b_.alloc(offs_[cnt]);
         P_.alloc(nP);
         Q_.alloc(nP);
-        cL_.alloc(nx);
+        cL_.alloc(offs_[cnt]);
         coef_.alloc(std::max<size_t>(ncoef, 1));
         g_.alloc(std::max<size_t>(nvec, 1));
         c1_.alloc(std::max<size_t>(nvec, 1));
         Y_.alloc(std::max<size_t>(nY, 1));
         HIPCHK(hipMemset(P_.p, 0, P_.n * sizeof(T)));
+        HIPCHK(hipMemset(Q_.p, 0, Q_.n * sizeof(T)));
         HIPCHK(hipMemset(Y_.p, 0, Y_.n * sizeof(T)));
-        // per-instance hierarchy (host Galerkin) and device pointers
-        size_t oP = 0, oc = 0, ov = 0, oY = 0;
+
+        // instance array ordered by number of levels: the groups
+        std::vector<int> order(cnt);
+        for (int i = 0; i < cnt; ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nlev_[a] < nlev_[b]; });
+        pos_.resize(cnt);
+        for (int q = 0; q < cnt; ++q) pos_[order[q]] = q;
+        for (int q = 0; q < cnt; ++q) {
+            const int nl = nlev_[order[q]];
+            if (groups_.empty() || groups_.back().nlev != nl) groups_.push_back(Group{nl, q, 0});
+            ++groups_.back().count;
+        }
+
+        ctl_.alloc(cnt);
+        small_.alloc((size_t)cnt * kBSmall);
+        HIPCHK(hipMemset(small_.p, 0, small_.n * sizeof(double)));
+        size_t npart = 0;
+        std::vector<int> pcnt(cnt);
+        for (int i = 0; i < cnt; ++i) {
+            const size_t N = offs_[i + 1] - offs_[i];
+            pcnt[i] = (int)((N + kBChunk - 1) / kBChunk);
+            npart += (size_t)pcnt[i] * kBPartRows;
+        }
+        part_.alloc(npart);
+
+        // per-problem hierarchy (host Galerkin) and device pointers
+        hinst_.resize(cnt);
+        size_t oP = 0, oc = 0, ov = 0, oY = 0, opart = 0;
         std::vector<T> coef_host(ncoef);
         for (int i = 0; i < cnt; ++i) {
-            const int nl = grids[i].nlevels, n = grids[i].n;
-            BInst<T>& I = hinst_[i];
+            const int nl = nlev_[i], n = grids[i].n;
+            BInst<T>& I = hinst_[pos_[i]];
             std::memset(&I, 0, sizeof(I));
             I.nlev = nl;
             for (int l = 0; l < nl; ++l) {
@@ -1360,11 +1387,27 @@ class BatchedSolver : public BatchedBase {
                 I.N[l] = (int)host::ipow(sizes[i][l], DIM);
             }
             const size_t N = offs_[i + 1] - offs_[i];
+            const double h2inv = double(n + 1) * double(n + 1);
+            I.op.n = n;
+            I.op.N = (int)N;
+            I.op.s0 = T(h2inv);
+            I.op.inv0 = T(1.0 / (2.0 * DIM * h2inv));
+            I.op64.n = n;
+            I.op64.N = (int)N;
+            I.op64.s0 = h2inv;
+            I.op64.inv0 = 1.0 / (2.0 * DIM * h2inv);
+            I.x = x_.p + offs_[i];
             I.r = r_.p + offs_[i];
+            I.b = b_.p + offs_[i];
             I.cL = cL_.p + offs_[i];
             I.P = P_.p + oP;
             I.Q = Q_.p + oP;
             oP += (size_t)even_up(nl) * N;
+            I.ctl = ctl_.p + pos_[i];
+            I.small = small_.p + (size_t)pos_[i] * kBSmall;
+            I.part = part_.p + opart;
+            I.pcnt = pcnt[i];
+            opart += (size_t)pcnt[i] * kBPartRows;
             if (nl > 1) {
                 host::FineFaces faces = host::fine_faces(DIM, n, nullptr);
                 std::vector<host::StencilLevel> lev(nl);
@@ -1391,33 +1434,50 @@ class BatchedSolver : public BatchedBase {
             }
         }
         if (ncoef) HIPCHK(hipMemcpy(coef_.p, coef_host.data(), ncoef * sizeof(T), hipMemcpyHostToDevice));
-        // largest first
-        std::vector<int> order(cnt);
-        for (int i = 0; i < cnt; ++i) order[i] = i;
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-            return offs_[a + 1] - offs_[a] > offs_[b + 1] - offs_[b];
-        });
-        order_.alloc(cnt);
-        HIPCHK(hipMemcpy(order_.p, order.data(), cnt * sizeof(int), hipMemcpyHostToDevice));
-        queue_.alloc(1);
-        out_.alloc(cnt);
         inst_.alloc(cnt);
-        params_.alloc(1);
-        HIPCHK(hipHostMalloc((void**)&hparams_, sizeof(BatchParams), hipHostMallocDefault));
+        HIPCHK(hipMemcpy(inst_.p, hinst_.data(), cnt * sizeof(BInst<T>), hipMemcpyHostToDevice));
+
+        // block maps: all problems' fine nodes, then per group its fine nodes
+        // and each coarse level's nodes
+        std::vector<BBlk> maps;
+        auto fine_blocks = [&](int q0, int q1) {
+            for (int q = q0; q < q1; ++q) {
+                const BInst<T>& I = hinst_[q];
+                const int N = I.N[I.nlev - 1];
+                for (int j = 0; j < I.pcnt; ++j)
+                    maps.push_back(BBlk{q, j, j * kBChunk, std::min(N, (j + 1) * kBChunk)});
+            }
+        };
+        all_.off = (int)maps.size();
+        fine_blocks(0, cnt);
+        all_.cnt = (int)maps.size() - all_.off;
+        for (Group& G : groups_) {
+            G.fine.off = (int)maps.size();
+            fine_blocks(G.first, G.first + G.count);
+            G.fine.cnt = (int)maps.size() - G.fine.off;
+            for (int l = 0; l + 1 < G.nlev; ++l) {
+                G.lev[l].off = (int)maps.size();
+                for (int q = G.first; q < G.first + G.count; ++q) {
+                    const int Nl = hinst_[q].N[l];
+                    for (int j = 0, s0 = 0; s0 < Nl; ++j, s0 += kBlock)
+                        maps.push_back(BBlk{q, j, s0, std::min(Nl, s0 + kBlock)});
+                }
+                G.lev[l].cnt = (int)maps.size() - G.lev[l].off;
+            }
+        }
+        maps_.alloc(maps.size());
+        HIPCHK(hipMemcpy(maps_.p, maps.data(), maps.size() * sizeof(BBlk), hipMemcpyHostToDevice));
+        HIPCHK(hipHostMalloc((void**)&hctl_, (size_t)cnt * sizeof(Ctl), hipHostMallocDefault));
         HIPCHK(hipEventCreate(&ev0_));
         HIPCHK(hipEventCreate(&ev1_));
-        int dev = 0, ncu = 0;
-        HIPCHK(hipGetDevice(&dev));
-        HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-        grid_ = std::min(cnt, std::max(1, 2 * ncu));
-        tau_ = opt_.pinv_tau > 0 ? opt_.pinv_tau : 0.0;
+        kpoll_ = opt_.k_poll;
     }
 
     ~BatchedSolver() override {
         if (exec_) (void)hipGraphExecDestroy(exec_);
         if (graph_) (void)hipGraphDestroy(graph_);
         if (cap_stream_) (void)hipStreamDestroy(cap_stream_);
-        if (hparams_) (void)hipHostFree(hparams_);
+        if (hctl_) (void)hipHostFree(hctl_);
         if (ev0_) (void)hipEventDestroy(ev0_);
         if (ev1_) (void)hipEventDestroy(ev1_);
     }
@@ -1425,58 +1485,144 @@ class BatchedSolver : public BatchedBase {
     int solve(const double* b_dev, double* x_dev, double tol, int maxit, amgmpcg_info* infos,
               double* batch_ms) override {
         if (maxit <= 0) maxit = opt_.maxit;
-        // the caller's concatenated b and x
+        const double unit = mixed_ ? std::ldexp(1.0, -24) : std::ldexp(1.0, -53);
         for (int i = 0; i < count; ++i) {
-            hinst_[i].b = b_dev + offs_[i];
-            hinst_[i].x = x_dev + offs_[i];
+            Ctl& c = hctl_[pos_[i]];
+            std::memset(&c, 0, sizeof(Ctl));
+            c.maxit = maxit;
+            c.drop2 = opt_.refresh_drop * opt_.refresh_drop;
+            c.tau = opt_.pinv_tau > 0 ? opt_.pinv_tau : 64.0 * nlev_[i] * unit;
         }
-        BatchParams& bp = *hparams_;
-        bp.count = count;
-        bp.order = order_.p;
-        bp.queue = queue_.p;
-        bp.tol = tol;
-        bp.maxit = maxit;
-        bp.two_sweeps = opt_.nu >= 2 ? 1 : 0;
-        bp.omega = opt_.omega;
-        bp.drop2 = opt_.refresh_drop * opt_.refresh_drop;
-        bp.mixed = mixed_ ? 1 : 0;
-        bp.out = out_.p;
-        bp.tau = tau_;
-        bp.unit = mixed_ ? std::ldexp(1.0, -24) : std::ldexp(1.0, -53);
-        HIPCHK(hipMemcpyAsync(inst_.p, hinst_.data(), count * sizeof(BInst<T>), hipMemcpyHostToDevice, stream_));
-        HIPCHK(hipMemcpyAsync(params_.p, hparams_, sizeof(BatchParams), hipMemcpyHostToDevice, stream_));
-        if (!exec_) capture();
+        const size_t nbytes = (size_t)offs_[count] * sizeof(double);
         HIPCHK(hipEventRecord(ev0_, stream_));
-        HIPCHK(hipGraphLaunch(exec_, stream_));
+        HIPCHK(hipMemcpyAsync(ctl_.p, hctl_, (size_t)count * sizeof(Ctl), hipMemcpyHostToDevice, stream_));
+        HIPCHK(hipMemcpyAsync(b_.p, b_dev, nbytes, hipMemcpyDeviceToDevice, stream_));
+        HIPCHK(hipMemcpyAsync(x_.p, x_dev, nbytes, hipMemcpyDeviceToDevice, stream_));
+        enqueue_init(stream_, tol);
+        HIPCHK(hipGetLastError());
+        if (!exec_) capture();
+        const int launches_max = maxit / kpoll_ + 3;
+        for (int launch = 0; launch < launches_max; ++launch) {
+            HIPCHK(hipMemcpyAsync(hctl_, ctl_.p, (size_t)count * sizeof(Ctl), hipMemcpyDeviceToHost, stream_));
+            HIPCHK(hipStreamSynchronize(stream_));
+            bool all = true;
+            for (int q = 0; q < count && all; ++q) all = hctl_[q].state == 2;
+            if (all) break;
+            HIPCHK(hipGraphLaunch(exec_, stream_));
+        }
+        HIPCHK(hipMemcpyAsync(x_dev, x_.p, nbytes, hipMemcpyDeviceToDevice, stream_));
         HIPCHK(hipEventRecord(ev1_, stream_));
-        std::vector<BOut> hout(count);
-        HIPCHK(hipMemcpyAsync(hout.data(), out_.p, count * sizeof(BOut), hipMemcpyDeviceToHost, stream_));
+        HIPCHK(hipMemcpyAsync(hctl_, ctl_.p, (size_t)count * sizeof(Ctl), hipMemcpyDeviceToHost, stream_));
         HIPCHK(hipStreamSynchronize(stream_));
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, ev0_, ev1_));
         if (batch_ms) *batch_ms = ms;
         int worst = AMGMPCG_OK;
         for (int i = 0; i < count; ++i) {
+            const Ctl& h = hctl_[pos_[i]];
+            const int status = h.state == 2 ? h.status : AMGMPCG_MAXIT;
             if (infos) {
-                infos[i].status = hout[i].status;
-                infos[i].iterations = hout[i].iterations;
-                infos[i].bnorm = hout[i].bnorm;
-                infos[i].relres = hout[i].relres;
-                infos[i].refreshes = hout[i].refreshes;
-                infos[i].nb = hinst_[i].nlev;
+                infos[i].status = status;
+                infos[i].iterations = h.it;
+                infos[i].bnorm = std::sqrt(h.bnorm2);
+                infos[i].relres = h.bnorm2 > 0 ? std::sqrt(h.rho / h.bnorm2) : 0.0;
+                infos[i].refreshes = h.refreshes;
+                infos[i].nb = nlev_[i];
                 infos[i].solve_ms = ms;
             }
-            if (hout[i].status != AMGMPCG_OK && worst == AMGMPCG_OK) worst = hout[i].status;
+            if (status != AMGMPCG_OK && worst == AMGMPCG_OK) worst = status;
         }
         return worst;
     }
 
    private:
+    struct Range {
+        int off = 0, cnt = 0;   // entries of maps_
+    };
+    struct Group {
+        int nlev, first, count;   // problems first .. first+count-1 of the instance array
+        Range fine;
+        Range lev[kMaxLevels];
+    };
+
+    const BBlk* map(const Range& r) const { return maps_.p + r.off; }
+
+    template <int V>
+    struct IC {
+        static constexpr int value = V;
+    };
+    template <typename F>
+    static void dispatch(int nb, F&& f) {
+        switch (nb) {
+            case 1: f(IC<1>{}); break;
+            case 2: f(IC<2>{}); break;
+            case 3: f(IC<3>{}); break;
+            case 4: f(IC<4>{}); break;
+            case 5: f(IC<5>{}); break;
+            case 6: f(IC<6>{}); break;
+            default: throw ApiError(AMGMPCG_INVALID_ARG, "batched problems support up to 6 levels");
+        }
+    }
+
+    // Z = MG(r) of every problem of group G: finest smoother, restriction
+    // chain, coarse smoothing, prolongation of the block carry.
+    void enqueue_mg(hipStream_t s, const Group& G) {
+        const T omega = T(opt_.omega);
+        const int two = opt_.nu >= 2 ? 1 : 0;
+        const int L = G.nlev - 1;
+        k_b_fine_smooth<DIM, T><<<G.fine.cnt, kBlock, 0, s>>>(inst_.p, map(G.fine), omega, two);
+        if (L == 0) return;
+        k_b_restrict<DIM, T, true><<<G.lev[L - 1].cnt, kBlock, 0, s>>>(inst_.p, map(G.lev[L - 1]), L - 1, omega);
+        for (int l = L - 2; l >= 0; --l)
+            k_b_restrict<DIM, T, false><<<G.lev[l].cnt, kBlock, 0, s>>>(inst_.p, map(G.lev[l]), l, omega);
+        for (int l = 0; l < L; ++l)
+            k_b_coarse_smooth<DIM, T><<<G.lev[l].cnt, kBlock, 0, s>>>(inst_.p, map(G.lev[l]), l, omega, two);
+        for (int l = 0; l + 1 < L; ++l) {
+            dispatch(l + 1, [&](auto nc) {
+                constexpr int NC = decltype(nc)::value;
+                k_b_prolong<DIM, T, NC><<<G.lev[l + 1].cnt, kBlock, 0, s>>>(inst_.p, map(G.lev[l + 1]), l);
+            });
+        }
+    }
+
+    void enqueue_init(hipStream_t s, double tol) {
+        k_b_init_residual<DIM, T><<<all_.cnt, kBlock, 0, s>>>(inst_.p, map(all_));
+        k_b_reduce_init<T><<<count, kRedBlock, 0, s>>>(inst_.p, tol);
+        k_b_zero_if<T><<<all_.cnt, kBlock, 0, s>>>(inst_.p, map(all_));
+        for (const Group& G : groups_) {
+            enqueue_mg(s, G);
+            dispatch(G.nlev, [&](auto nbc) {
+                constexpr int NB = decltype(nbc)::value;
+                k_b_update_xP<DIM, T, NB><<<G.fine.cnt, kBlock, 0, s>>>(inst_.p, map(G.fine), 1);
+                k_b_spmm_gram<DIM, T, NB><<<G.fine.cnt, kBlock, 0, s>>>(inst_.p, map(G.fine));
+                k_b_reduce_alpha<T, NB><<<G.count, kRedBlock, 0, s>>>(inst_.p, G.first);
+            });
+        }
+    }
+
+    void enqueue_iteration(hipStream_t s) {
+        for (const Group& G : groups_) {
+            dispatch(G.nlev, [&](auto nbc) {
+                constexpr int NB = decltype(nbc)::value;
+                k_b_update_r<T, NB><<<G.fine.cnt, kBlock, 0, s>>>(inst_.p, map(G.fine));
+                enqueue_mg(s, G);
+                k_b_fine_W<DIM, T, NB><<<G.fine.cnt, kBlock, 0, s>>>(inst_.p, map(G.fine));
+                k_b_reduce_beta<T, NB><<<G.count, kRedBlock, 0, s>>>(inst_.p, G.first, mixed_ ? 1 : 0);
+                k_b_update_xP<DIM, T, NB><<<G.fine.cnt, kBlock, 0, s>>>(inst_.p, map(G.fine), 0);
+                if (mixed_) {
+                    k_b_refresh<DIM, T><<<G.fine.cnt, kBlock, 0, s>>>(inst_.p, map(G.fine));
+                    k_b_refresh_reduce<T><<<G.count, kRedBlock, 0, s>>>(inst_.p, G.first);
+                }
+                k_b_spmm_gram<DIM, T, NB><<<G.fine.cnt, kBlock, 0, s>>>(inst_.p, map(G.fine));
+                k_b_reduce_alpha<T, NB><<<G.count, kRedBlock, 0, s>>>(inst_.p, G.first);
+            });
+        }
+    }
+
     void capture() {
         HIPCHK(hipStreamCreateWithFlags(&cap_stream_, hipStreamNonBlocking));
         HIPCHK(hipStreamBeginCapture(cap_stream_, hipStreamCaptureModeThreadLocal));
-        k_queue_reset<<<1, 64, 0, cap_stream_>>>(queue_.p);
-        k_batched<DIM, T><<<grid_, kBatchBlock, 0, cap_stream_>>>(inst_.p, params_.p);
+        for (int k = 0; k < kpoll_; ++k) enqueue_iteration(cap_stream_);
         hipError_t launch_err = hipGetLastError();
         HIPCHK(hipStreamEndCapture(cap_stream_, &graph_));
         HIPCHK(launch_err);
@@ -1489,17 +1635,18 @@ class BatchedSolver : public BatchedBase {
     hipGraph_t graph_ = nullptr;
     hipGraphExec_t exec_ = nullptr;
     bool mixed_ = false;
-    int grid_ = 1;
-    double tau_ = 0.0;
-    std::vector<size_t> offs_;
+    int kpoll_ = 8;
+    std::vector<size_t> offs_;        // problem i's fine nodes start at offs_[i] (problem order)
+    std::vector<int> nlev_, pos_;     // levels of problem i; its index in the instance array
+    std::vector<Group> groups_;
+    Range all_;
     std::vector<BInst<T>> hinst_;
-    DevBuf<double> r_;
+    DevBuf<double> x_, r_, b_, small_, part_;
     DevBuf<T> P_, Q_, cL_, coef_, g_, c1_, Y_;
-    DevBuf<int> order_, queue_;
-    DevBuf<BOut> out_;
+    DevBuf<Ctl> ctl_;
     DevBuf<BInst<T>> inst_;
-    DevBuf<BatchParams> params_;
-    BatchParams* hparams_ = nullptr;
+    DevBuf<BBlk> maps_;
+    Ctl* hctl_ = nullptr;
     hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
 };
 
@@ -1742,11 +1889,8 @@ int amgmpcg_setup_batched(int32_t count, const amgmpcg_grid* grids, const amgmpc
             if (grids[i].kappa) throw ApiError(AMGMPCG_INVALID_ARG, "batched problems are Poisson (kappa must be NULL)");
             if (grids[i].nlevels > 6) throw ApiError(AMGMPCG_INVALID_ARG, "batched problems support up to 6 levels");
         }
-        // The persistent batched kernel took a GPU memory fault in its first
-        // run whose cause is not established (a host emulation of the kernel
-        // under AddressSanitizer finds no out-of-range access); the entry
-        // point stays switched off until the cause is shown.
-        throw ApiError(AMGMPCG_UNAVAILABLE, "the batched persistent solve is switched off in this build");
+        if (opts->m != 1 || opts->method != AMGMPCG_METHOD_MPCG)
+            throw ApiError(AMGMPCG_INVALID_ARG, "batched solves use the MPCG method with m = 1");
         auto h = std::make_unique<amgmpcg_handle>();
         hipStream_t s = (hipStream_t)stream;
         if (opts->precision == 0) {

@@ -1,10 +1,15 @@
-// Batched persistent MPCG: many independent structured problems (each with
-// its own grid size, hierarchy and right-hand side) solved by one kernel
-// launch.  Workgroups pull instances, largest first, from an atomic queue;
-// one 1024-thread workgroup runs the whole of Algorithm 1 for an instance,
-// every phase a loop over that instance's nodes followed by a workgroup
-// barrier, reductions in a fixed order through LDS.  No workgroup ever waits
-// for another, and every workgroup exits once the queue is drained.
+// Batched MPCG: many independent structured Poisson problems (each with its
+// own grid size, hierarchy and right-hand side) solved together.  Every
+// step of Algorithm 1 is one launch over all problems of a group (the
+// problems with the same number of levels, so that the number of directions
+// is a compile-time constant): each block belongs to one problem, found
+// through a block map built on the host, and works on a contiguous node
+// range of one level of it.  Each problem has its own control word, step
+// coefficients and partial sums (value-major rows of its own block count),
+// so the single-block reductions of the one-problem solver run unchanged,
+// one block per problem.  Problems that have stopped skip every launch.
+// The launches of k_poll iterations of all groups are captured in one HIP
+// graph; the host polls the control words between graph launches.
 #pragma once
 
 #include "common.hpp"
@@ -13,143 +18,230 @@
 
 namespace amg {
 
-constexpr int kBatchBlock = 1024;
-constexpr int kBatchWaves = kBatchBlock / 64;
+constexpr int kBChunk = 4 * kBlock;   // fine nodes per block of the batched fine kernels
+
+// Partial-sum rows of one problem (in units of its block count pcnt).
+constexpr int kBPartInit = 0;                              // ||b||^2, ||r||^2
+constexpr int kBPartRho = 2;                               // ||r||^2
+constexpr int kBPartW = 3;                                 // W, kMaxNB^2 rows
+constexpr int kBPartG = 3 + kMaxNB * kMaxNB;               // Gram + P^T r
+constexpr int kBPartRef = kBPartG + kMaxNB * (kMaxNB + 1) / 2 + kMaxNB;   // refresh ||r||^2
+constexpr int kBPartRows = kBPartRef + 1;
+
+// Step coefficients of one problem: alpha, beta, G^+.
+constexpr int kBSmall = kMaxNB + 2 * kMaxNB * kMaxNB;
 
 template <typename T>
 struct BInst {
-    int nlev;                      // levels; search directions NB = nlev
-    int n[kMaxLevels];             // nodes per axis, 0 = coarsest
-    int N[kMaxLevels];
-    const T* coef[kMaxLevels];     // coarse levels: 3^d stencil coefficients
-    T* g[kMaxLevels];              // restricted residual
-    T* c1[kMaxLevels];             // first Jacobi sweep
-    T* Y[kMaxLevels];              // node-major block carry
-    const double* b;
-    double* x;
-    double* r;
-    T* P;                          // node-major, stride even_up(NB)
-    T* Q;
-    T* cL;
+    int nlev;
+    int n[kMaxLevels], N[kMaxLevels];   // per level, coarsest first
+    FineOp<T> op;                       // finest operator (constant coefficient)
+    FineOp<double> op64;                // the same in FP64 (residual, refresh)
+    double *x, *r, *b;
+    T *P, *Q, *cL;                      // node-major blocks (stride even_up(nlev)), finest smoother output
+    const T* coef[kMaxLevels];          // coarse operators, coefficient-major
+    T* g[kMaxLevels];                   // restricted residuals
+    T* c1[kMaxLevels];                  // first smoothing sweep omega g / D
+    T* Y[kMaxLevels];                   // block carry [P Y_{l-1} | c_l]
+    Ctl* ctl;
+    double* small;                      // alpha, beta, G^+ (kBSmall)
+    double* part;                       // kBPartRows rows of pcnt partial sums
+    int pcnt;                           // blocks of this problem in the fine launches
 };
 
-struct BOut {
-    int status, iterations, refreshes, rank;
-    double bnorm, relres;
+// A block's problem (index into the instance array), its block index within
+// that problem (fine launches) and its node range.
+struct BBlk {
+    int inst, blk, start, end;
 };
 
-struct BatchParams {
-    int count;
-    const int* order;      // instance indices, largest first
-    int* queue;            // next position in order (reset to 0 before each launch)
-    double tol;
-    int maxit;
-    int two_sweeps;
-    double omega;
-    double tau;            // eigenvalue cut; <= 0: 64 * NB * unit for each problem
-    double unit;           // unit roundoff of the bulk type
-    double drop2;          // mixed form: refresh when ||r||^2 fell by this factor
-    int mixed;
-    BOut* out;
-};
-
-// Sum K per-thread values over the 1024-thread workgroup into res[k]
-// (shared); scratch: shared [kBatchWaves][64] doubles.  v is destroyed.
-template <int K>
-__device__ __forceinline__ void batch_reduce(double (&v)[K], double* res, double* scratch) {
-    constexpr int KP = pow2_up(K);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int vi = wave_reduce_multi<K>(v);
-    if ((lane & (64 / KP - 1)) == 0) scratch[w * 64 + vi] = v[0];
-    __syncthreads();
-    if (threadIdx.x < K) {
-        double s = scratch[threadIdx.x];
-        for (int q = 1; q < kBatchWaves; ++q) s += scratch[q * 64 + threadIdx.x];
-        res[threadIdx.x] = s;
-    }
-    __syncthreads();
+template <typename T>
+__device__ __forceinline__ double* bpart(const BInst<T>& I, int row) {
+    return I.part + (size_t)row * I.pcnt;
 }
 
-template <int NB>
-struct BShared {
-    double red[64];
-    double G[NB * NB];
-    double Gp[NB * NB];
-    double alpha[NB];
-    double beta[NB * NB];
-    int rank;
-};
+// ---------------------------------------------------------- fine level
 
-// Z = MG(r): fine smoother, restriction chain, all coarse levels smoothed,
-// prolongation chain; barriers between dependent phases.
+// r = b - A x (FP64), partial ||b||^2 and ||r||^2.
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kBlock) k_b_init_residual(const BInst<T>* __restrict__ insts,
+                                                            const BBlk* __restrict__ map) {
+    const BBlk m = map[blockIdx.x];
+    const BInst<T>& I = insts[m.inst];
+    const int n = I.n[I.nlev - 1];
+    double v[2] = {0.0, 0.0};
+    for (int idx = m.start + threadIdx.x; idx < m.end; idx += kBlock) {
+        const Idx<DIM> p = decomp<DIM>(idx, n);
+        const double bi = I.b[idx];
+        const double ri = bi - fine_apply<DIM, double>(I.op64, I.x, idx, p);
+        I.r[idx] = ri;
+        v[0] += bi * bi;
+        v[1] += ri * ri;
+    }
+    block_sum_store<2>(v, bpart(I, kBPartInit), I.pcnt, m.blk);
+}
+
+// b == 0: x = 0.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_b_zero_if(const BInst<T>* __restrict__ insts,
+                                                      const BBlk* __restrict__ map) {
+    const BBlk m = map[blockIdx.x];
+    const BInst<T>& I = insts[m.inst];
+    if (!I.ctl->zero_x) return;
+    for (int idx = m.start + threadIdx.x; idx < m.end; idx += kBlock) I.x[idx] = 0.0;
+}
+
+// r -= Q alpha, partial ||r||^2.
+template <typename T, int NB>
+__global__ void __launch_bounds__(kBlock) k_b_update_r(const BInst<T>* __restrict__ insts,
+                                                       const BBlk* __restrict__ map) {
+    const BBlk m = map[blockIdx.x];
+    const BInst<T>& I = insts[m.inst];
+    if (I.ctl->state != 0) return;
+    constexpr int S = even_up(NB);
+    double a[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) a[c] = I.small[c];
+    double v[1] = {0.0};
+    for (int idx = m.start + threadIdx.x; idx < m.end; idx += kBlock) {
+        T q[S];
+        load_node<T, S>(I.Q + (size_t)idx * S, q);
+        double ri = I.r[idx];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) ri -= double(q[c]) * a[c];
+        I.r[idx] = ri;
+        v[0] += ri * ri;
+    }
+    block_sum_store<1>(v, bpart(I, kBPartRho), I.pcnt, m.blk);
+}
+
+// Finest smoother output cL = S^nu r (nu = 1 or 2 sweeps from zero).
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kBlock) k_b_fine_smooth(const BInst<T>* __restrict__ insts,
+                                                          const BBlk* __restrict__ map, T omega, int two) {
+    const BBlk m = map[blockIdx.x];
+    const BInst<T>& I = insts[m.inst];
+    if (I.ctl->state != 0) return;
+    const int n = I.n[I.nlev - 1];
+    for (int idx = m.start + threadIdx.x; idx < m.end; idx += kBlock) {
+        const Idx<DIM> p = decomp<DIM>(idx, n);
+        I.cL[idx] = fine_smooth_at<DIM, T, double>(I.op, I.r, idx, p, omega, two);
+    }
+}
+
+// W = Q^T Z partial sums (NB x NB), Z from the level-(L-1) block carry and cL.
 template <int DIM, typename T, int NB>
-__device__ void batch_mg(const BInst<T>& I, const FineOp<T>& op, const double* __restrict__ r, T omega,
-                         int two) {
-    constexpr int L = NB - 1;
-    const int N = I.N[L];
-    for (int idx = threadIdx.x; idx < N; idx += kBatchBlock) {
-        const Idx<DIM> p = decomp<DIM>(idx, op.n);
-        I.cL[idx] = fine_smooth_at<DIM, T, double>(op, r, idx, p, omega, two);
-    }
-    if (L == 0) {
-        __syncthreads();
-        return;
-    }
-    {
-        const int m = L - 1;
-        const T* D = I.coef[m] + (size_t)stencil_center<DIM>() * I.N[m];
-        for (int idx = threadIdx.x; idx < I.N[m]; idx += kBatchBlock) {
-            const T g = restrict_at<DIM, double, T>(r, I.n[L], I.n[m], idx);
-            I.g[m][idx] = g;
-            I.c1[m][idx] = omega * (g / D[idx]);
+__global__ void __launch_bounds__(kBlock) k_b_fine_W(const BInst<T>* __restrict__ insts,
+                                                     const BBlk* __restrict__ map) {
+    const BBlk m = map[blockIdx.x];
+    const BInst<T>& I = insts[m.inst];
+    if (I.ctl->state != 0) return;
+    constexpr int S = even_up(NB);
+    const int L = I.nlev - 1, n = I.n[L];
+    const T* Yc = L > 0 ? I.Y[L - 1] : nullptr;
+    const int nc = L > 0 ? I.n[L - 1] : 1;
+    double w[NB * NB];
+#pragma unroll
+    for (int q = 0; q < NB * NB; ++q) w[q] = 0.0;
+    for (int idx = m.start + threadIdx.x; idx < m.end; idx += kBlock) {
+        const Idx<DIM> p = decomp<DIM>(idx, n);
+        T z[NB];
+        fine_z<DIM, T, NB, 0>(Yc, nc, I.cL, nullptr, false, idx, p, z);
+        T q[S];
+        load_node<T, S>(I.Q + (size_t)idx * S, q);
+#pragma unroll
+        for (int a = 0; a < NB; ++a) {
+            const double qa = double(q[a]);
+#pragma unroll
+            for (int c = 0; c < NB; ++c) w[a * NB + c] += qa * double(z[c]);
         }
-        __syncthreads();
     }
-    for (int m = L - 2; m >= 0; --m) {
-        const T* D = I.coef[m] + (size_t)stencil_center<DIM>() * I.N[m];
-        for (int idx = threadIdx.x; idx < I.N[m]; idx += kBatchBlock) {
-            const T g = restrict_at<DIM, T, T>(I.g[m + 1], I.n[m + 1], I.n[m], idx);
-            I.g[m][idx] = g;
-            I.c1[m][idx] = omega * (g / D[idx]);
-        }
-        __syncthreads();
-    }
-    for (int l = 0; l < L; ++l) {
-        CoarseOp<T> cop{I.n[l], I.N[l], I.coef[l]};
-        const int S = even_up(l + 1);
-        for (int idx = threadIdx.x; idx < I.N[l]; idx += kBatchBlock)
-            I.Y[l][(size_t)idx * S + l] = coarse_smooth_at<DIM, T>(cop, I.g[l], I.c1[l], nullptr, idx, omega, 0, two);
+    block_sum_store<NB * NB>(w, bpart(I, kBPartW), I.pcnt, m.blk);
+}
+
+// x += P alpha (deferred); then, unless stopping, P = Z - P beta in place.
+// init = 1: P_0 = Z_0 only.
+template <int DIM, typename T, int NB>
+__global__ void __launch_bounds__(kBlock) k_b_update_xP(const BInst<T>* __restrict__ insts,
+                                                        const BBlk* __restrict__ map, int init) {
+    const BBlk m = map[blockIdx.x];
+    const BInst<T>& I = insts[m.inst];
+    const int state = I.ctl->state;
+    if (state == 2 || (init && state != 0)) return;
+    constexpr int S = even_up(NB);
+    const int L = I.nlev - 1, n = I.n[L];
+    const T* Yc = L > 0 ? I.Y[L - 1] : nullptr;
+    const int nc = L > 0 ? I.n[L - 1] : 1;
+    __shared__ double sab[NB + NB * NB];
+    if (!init) {
+        for (int q = threadIdx.x; q < NB + NB * NB; q += kBlock)
+            sab[q] = q < NB ? I.small[q] : I.small[kMaxNB + q - NB];
     }
     __syncthreads();
-    for (int l = 0; l + 1 < L; ++l) {
-        for (int idx = threadIdx.x; idx < I.N[l + 1]; idx += kBatchBlock) {
-            switch (l + 1) {
-                case 1: prolong_at<DIM, T, 1>(I.Y[l], I.n[l], I.Y[l + 1], I.n[l + 1], idx); break;
-                case 2: prolong_at<DIM, T, 2>(I.Y[l], I.n[l], I.Y[l + 1], I.n[l + 1], idx); break;
-                case 3: prolong_at<DIM, T, 3>(I.Y[l], I.n[l], I.Y[l + 1], I.n[l + 1], idx); break;
-                case 4: prolong_at<DIM, T, 4>(I.Y[l], I.n[l], I.Y[l + 1], I.n[l + 1], idx); break;
-                case 5: prolong_at<DIM, T, 5>(I.Y[l], I.n[l], I.Y[l + 1], I.n[l + 1], idx); break;
-                default: prolong_at<DIM, T, 6>(I.Y[l], I.n[l], I.Y[l + 1], I.n[l + 1], idx); break;
+    for (int idx = m.start + threadIdx.x; idx < m.end; idx += kBlock) {
+        T pk[S];
+        if (!init) {
+            load_node<T, S>(I.P + (size_t)idx * S, pk);
+            double xi = I.x[idx];
+#pragma unroll
+            for (int c = 0; c < NB; ++c) xi += double(pk[c]) * sab[c];
+            I.x[idx] = xi;
+            if (state != 0) continue;
+        }
+        const Idx<DIM> p = decomp<DIM>(idx, n);
+        T z[NB];
+        fine_z<DIM, T, NB, 0>(Yc, nc, I.cL, nullptr, false, idx, p, z);
+        T pn[S];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+            double v = double(z[c]);
+            if (!init) {
+#pragma unroll
+                for (int a2 = 0; a2 < NB; ++a2) v -= double(pk[a2]) * sab[NB + a2 * NB + c];
             }
+            pn[c] = T(v);
         }
-        __syncthreads();
+#pragma unroll
+        for (int c = NB; c < S; ++c) pn[c] = T(0);
+        store_node<T, S>(I.P + (size_t)idx * S, pn);
     }
 }
 
-// Q = A P, Gram and g = P^T r, pseudo-inverse, alpha (into shared state).
+// True-residual refresh r = b - A x in FP64 (mixed form, when requested).
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kBlock) k_b_refresh(const BInst<T>* __restrict__ insts,
+                                                      const BBlk* __restrict__ map) {
+    const BBlk m = map[blockIdx.x];
+    const BInst<T>& I = insts[m.inst];
+    if (I.ctl->state == 2 || !I.ctl->refresh_req) return;
+    const int n = I.n[I.nlev - 1];
+    double v[1] = {0.0};
+    for (int idx = m.start + threadIdx.x; idx < m.end; idx += kBlock) {
+        const Idx<DIM> p = decomp<DIM>(idx, n);
+        const double ri = I.b[idx] - fine_apply<DIM, double>(I.op64, I.x, idx, p);
+        I.r[idx] = ri;
+        v[0] += ri * ri;
+    }
+    block_sum_store<1>(v, bpart(I, kBPartRef), I.pcnt, m.blk);
+}
+
+// Q = A P, partial Gram upper triangle and P^T r.
 template <int DIM, typename T, int NB>
-__device__ void batch_gram_alpha(const BInst<T>& I, const FineOp<T>& op, BShared<NB>& sh, double tau,
-                                 double* scratch) {
-    constexpr int NG = NB * (NB + 1) / 2, S = even_up(NB);
-    constexpr int L = NB - 1;
-    const int N = I.N[L];
+__global__ void __launch_bounds__(kBlock) k_b_spmm_gram(const BInst<T>* __restrict__ insts,
+                                                        const BBlk* __restrict__ map) {
+    const BBlk m = map[blockIdx.x];
+    const BInst<T>& I = insts[m.inst];
+    if (I.ctl->state != 0) return;
+    constexpr int NG = NB * (NB + 1) / 2;
+    constexpr int S = even_up(NB);
+    const int n = I.n[I.nlev - 1];
     double acc[NG + NB];
 #pragma unroll
     for (int q = 0; q < NG + NB; ++q) acc[q] = 0.0;
-    for (int idx = threadIdx.x; idx < N; idx += kBatchBlock) {
-        const Idx<DIM> p = decomp<DIM>(idx, op.n);
+    for (int idx = m.start + threadIdx.x; idx < m.end; idx += kBlock) {
+        const Idx<DIM> p = decomp<DIM>(idx, n);
         T pv[S], qv[S];
-        fine_apply_block<DIM, T, S>(op, I.P, idx, p, pv, qv);
+        fine_apply_block<DIM, T, S>(I.op, I.P, idx, p, pv, qv);
         store_node<T, S>(I.Q + (size_t)idx * S, qv);
         const double ri = I.r[idx];
         int q = 0;
@@ -160,222 +252,84 @@ __device__ void batch_gram_alpha(const BInst<T>& I, const FineOp<T>& op, BShared
 #pragma unroll
         for (int a = 0; a < NB; ++a) acc[NG + a] += double(pv[a]) * ri;
     }
-    batch_reduce<NG + NB>(acc, sh.red, scratch);
-    if (threadIdx.x == 0) {
-        int q = 0;
-        for (int a = 0; a < NB; ++a)
-            for (int c = a; c < NB; ++c, ++q) sh.G[a * NB + c] = sh.G[c * NB + a] = sh.red[q];
-    }
-    __syncthreads();
-    if (threadIdx.x < 64) {
-        const int rk = wave_pinv<NB>(sh.G, tau, sh.Gp);
-        if (threadIdx.x == 0) sh.rank = rk;
-    }
-    __syncthreads();
-    if (threadIdx.x < NB) {
-        double s = 0.0;
-        for (int m = 0; m < NB; ++m) s += sh.Gp[threadIdx.x * NB + m] * sh.red[NG + m];
-        sh.alpha[threadIdx.x] = s;
-    }
-    __syncthreads();
+    block_sum_store<NG + NB>(acc, bpart(I, kBPartG), I.pcnt, m.blk);
 }
 
-// ||r||^2 after r = b - A x in FP64 (start and refreshes).
-template <int DIM>
-__device__ void batch_residual(const FineOp<double>& op64, const double* __restrict__ b,
-                               const double* __restrict__ x, double* __restrict__ r, double* res2 /*shared 2*/,
-                               double* scratch) {
-    double acc[2] = {0.0, 0.0};
-    for (int idx = threadIdx.x; idx < op64.N; idx += kBatchBlock) {
-        const Idx<DIM> p = decomp<DIM>(idx, op64.n);
-        const double bi = b[idx];
-        const double ri = bi - fine_apply<DIM, double>(op64, x, idx, p);
-        r[idx] = ri;
-        acc[0] += bi * bi;
-        acc[1] += ri * ri;
-    }
-    batch_reduce<2>(acc, res2, scratch);
+// ---------------------------------------------------------- coarse levels
+
+// Restriction to level l (thread per coarse node) and the first sweep
+// c1 = omega g / D; FINE: from the finest residual r.
+template <int DIM, typename T, bool FINE>
+__global__ void __launch_bounds__(kBlock) k_b_restrict(const BInst<T>* __restrict__ insts,
+                                                       const BBlk* __restrict__ map, int l, T omega) {
+    const BBlk m = map[blockIdx.x];
+    const BInst<T>& I = insts[m.inst];
+    if (I.ctl->state != 0) return;
+    const int idx = m.start + threadIdx.x;
+    if (idx >= m.end) return;
+    T g;
+    if constexpr (FINE) g = restrict_at<DIM, double, T>(I.r, I.n[l + 1], I.n[l], idx);
+    else g = restrict_at<DIM, T, T>(I.g[l + 1], I.n[l + 1], I.n[l], idx);
+    const T* D = I.coef[l] + (size_t)stencil_center<DIM>() * I.N[l];
+    I.g[l][idx] = g;
+    I.c1[l][idx] = omega * (g / D[idx]);
 }
 
-template <int DIM, typename T, int NB>
-__device__ void solve_instance(const BInst<T>& I, const BatchParams& bp, BOut& out, double* scratch) {
-    constexpr int L = NB - 1, S = even_up(NB);
-    __shared__ BShared<NB> sh;
-    const int nf = I.n[L], N = I.N[L];
-    const double h2inv = double(nf + 1) * double(nf + 1);
-    FineOp<T> op{nf, N, T(h2inv), nullptr, nullptr, nullptr, nullptr, T(1.0 / (2 * DIM * h2inv)), nullptr};
-    FineOp<double> op64{nf, N, h2inv, nullptr, nullptr, nullptr, nullptr, 1.0 / (2 * DIM * h2inv), nullptr};
-    const T omega = T(bp.omega);
-    const int nc = L > 0 ? I.n[L - 1] : 1;
-    const T* Ytop = L > 0 ? I.Y[L - 1] : nullptr;
-    const double tau = bp.tau > 0 ? bp.tau : 64.0 * NB * bp.unit;
-
-    batch_residual<DIM>(op64, I.b, I.x, I.r, sh.red, scratch);
-    const double bn2 = sh.red[0];
-    double rho = sh.red[1];
-    int status = kOK, it = 0, refreshes = 0;
-    const double tol2 = bp.tol * bp.tol * bn2;
-    if (bn2 == 0.0) {
-        for (int idx = threadIdx.x; idx < N; idx += kBatchBlock) I.x[idx] = 0.0;
-        rho = 0.0;
-    } else if (!isfinite(rho) || !isfinite(bn2)) {
-        status = kNONFINITE;
-    } else if (!(rho <= tol2)) {
-        batch_mg<DIM, T, NB>(I, op, I.r, omega, bp.two_sweeps);
-        for (int idx = threadIdx.x; idx < N; idx += kBatchBlock) {
-            const Idx<DIM> p = decomp<DIM>(idx, nf);
-            T z[NB], pn[S];
-            fine_z<DIM, T, NB, 0>(Ytop, nc, I.cL, nullptr, false, idx, p, z);
-#pragma unroll
-            for (int c = 0; c < S; ++c) pn[c] = c < NB ? z[c] : T(0);
-            store_node<T, S>(I.P + (size_t)idx * S, pn);
-        }
-        __syncthreads();
-        batch_gram_alpha<DIM, T, NB>(I, op, sh, tau, scratch);
-        double rho_ref = rho;
-        while (true) {
-            if (sh.rank == 0) {
-                status = kBREAKDOWN;
-                break;
-            }
-            // r_{k+1} = r_k - Q alpha, ||r||^2
-            double a1[1] = {0.0};
-            for (int idx = threadIdx.x; idx < N; idx += kBatchBlock) {
-                T q[S];
-                load_node<T, S>(I.Q + (size_t)idx * S, q);
-                double ri = I.r[idx];
-#pragma unroll
-                for (int c = 0; c < NB; ++c) ri -= double(q[c]) * sh.alpha[c];
-                I.r[idx] = ri;
-                a1[0] += ri * ri;
-            }
-            batch_reduce<1>(a1, sh.red, scratch);
-            rho = sh.red[0];
-            ++it;
-            int stop = 0, refresh = 0;
-            if (!isfinite(rho)) {
-                status = kNONFINITE;
-                stop = 1;
-            } else if (rho <= tol2 && !bp.mixed) {
-                stop = 1;
-            } else if (it >= bp.maxit) {
-                status = kMAXIT;
-                stop = 1;
-            } else if (bp.mixed && (rho <= tol2 || rho <= bp.drop2 * rho_ref)) {
-                refresh = 1;
-            }
-            if (stop) {
-                for (int idx = threadIdx.x; idx < N; idx += kBatchBlock) {
-                    T pk[S];
-                    load_node<T, S>(I.P + (size_t)idx * S, pk);
-                    double xi = I.x[idx];
-#pragma unroll
-                    for (int c = 0; c < NB; ++c) xi += double(pk[c]) * sh.alpha[c];
-                    I.x[idx] = xi;
-                }
-                break;
-            }
-            batch_mg<DIM, T, NB>(I, op, I.r, omega, bp.two_sweeps);
-            // W = Q^T Z, beta = G^+ W
-            {
-                double w[NB * NB];
-#pragma unroll
-                for (int q = 0; q < NB * NB; ++q) w[q] = 0.0;
-                for (int idx = threadIdx.x; idx < N; idx += kBatchBlock) {
-                    const Idx<DIM> p = decomp<DIM>(idx, nf);
-                    T z[NB], q[S];
-                    fine_z<DIM, T, NB, 0>(Ytop, nc, I.cL, nullptr, false, idx, p, z);
-                    load_node<T, S>(I.Q + (size_t)idx * S, q);
-#pragma unroll
-                    for (int a = 0; a < NB; ++a)
-#pragma unroll
-                        for (int c = 0; c < NB; ++c) w[a * NB + c] += double(q[a]) * double(z[c]);
-                }
-                batch_reduce<NB * NB>(w, sh.red, scratch);
-                if (threadIdx.x < NB * NB) {
-                    const int a = threadIdx.x / NB, c = threadIdx.x % NB;
-                    double s = 0.0;
-                    for (int m = 0; m < NB; ++m) s += sh.Gp[a * NB + m] * sh.red[m * NB + c];
-                    sh.beta[threadIdx.x] = s;
-                }
-                __syncthreads();
-            }
-            // x += P_k alpha_k;  P_{k+1} = Z - P_k beta
-            for (int idx = threadIdx.x; idx < N; idx += kBatchBlock) {
-                const Idx<DIM> p = decomp<DIM>(idx, nf);
-                T pk[S], z[NB], pn[S];
-                load_node<T, S>(I.P + (size_t)idx * S, pk);
-                double xi = I.x[idx];
-#pragma unroll
-                for (int c = 0; c < NB; ++c) xi += double(pk[c]) * sh.alpha[c];
-                I.x[idx] = xi;
-                fine_z<DIM, T, NB, 0>(Ytop, nc, I.cL, nullptr, false, idx, p, z);
-#pragma unroll
-                for (int c = 0; c < S; ++c) {
-                    if (c < NB) {
-                        double v = double(z[c]);
-#pragma unroll
-                        for (int a = 0; a < NB; ++a) v -= double(pk[a]) * sh.beta[a * NB + c];
-                        pn[c] = T(v);
-                    } else {
-                        pn[c] = T(0);
-                    }
-                }
-                store_node<T, S>(I.P + (size_t)idx * S, pn);
-            }
-            __syncthreads();
-            if (refresh) {
-                batch_residual<DIM>(op64, I.b, I.x, I.r, sh.red, scratch);
-                rho = sh.red[1];
-                rho_ref = rho;
-                ++refreshes;
-                if (!isfinite(rho)) {
-                    status = kNONFINITE;
-                    break;
-                }
-                if (rho <= tol2) break;
-            }
-            batch_gram_alpha<DIM, T, NB>(I, op, sh, tau, scratch);
-        }
-    }
-    if (threadIdx.x == 0) {
-        out.status = status;
-        out.iterations = it;
-        out.refreshes = refreshes;
-        out.rank = sh.rank;
-        out.bnorm = sqrt(bn2);
-        out.relres = bn2 > 0 ? sqrt(rho / bn2) : 0.0;
-    }
-    __syncthreads();
-}
-
-__global__ void k_queue_reset(int* queue) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *queue = 0;
-}
-
+// Damped Jacobi on level l (nu = 1 or 2 sweeps from zero) into the last
+// column of the level's block carry.
 template <int DIM, typename T>
-__global__ void __launch_bounds__(kBatchBlock) k_batched(const BInst<T>* __restrict__ insts,
-                                                         const BatchParams* __restrict__ bpp) {
-    __shared__ double scratch[kBatchWaves * 64];
-    __shared__ int slot;
-    const BatchParams bp = *bpp;
-    while (true) {
-        if (threadIdx.x == 0) slot = atomicAdd(bp.queue, 1);
-        __syncthreads();
-        const int q = slot;
-        __syncthreads();
-        if (q >= bp.count) break;
-        const int id = bp.order[q];
-        const BInst<T>& I = insts[id];
-        switch (I.nlev) {
-            case 1: solve_instance<DIM, T, 1>(I, bp, bp.out[id], scratch); break;
-            case 2: solve_instance<DIM, T, 2>(I, bp, bp.out[id], scratch); break;
-            case 3: solve_instance<DIM, T, 3>(I, bp, bp.out[id], scratch); break;
-            case 4: solve_instance<DIM, T, 4>(I, bp, bp.out[id], scratch); break;
-            case 5: solve_instance<DIM, T, 5>(I, bp, bp.out[id], scratch); break;
-            default: solve_instance<DIM, T, 6>(I, bp, bp.out[id], scratch); break;
-        }
-    }
+__global__ void __launch_bounds__(kBlock) k_b_coarse_smooth(const BInst<T>* __restrict__ insts,
+                                                            const BBlk* __restrict__ map, int l, T omega, int two) {
+    const BBlk m = map[blockIdx.x];
+    const BInst<T>& I = insts[m.inst];
+    if (I.ctl->state != 0) return;
+    const int idx = m.start + threadIdx.x;
+    if (idx >= m.end) return;
+    CoarseOp<T> op{I.n[l], I.N[l], I.coef[l]};
+    I.Y[l][(size_t)idx * even_up(l + 1) + l] =
+        coarse_smooth_at<DIM, T>(op, I.g[l], I.c1[l], nullptr, idx, omega, 0, two);
+}
+
+// Block carry up from level l to l+1: Y_{l+1}[:, 0..l] = P Y_l (NC = l + 1).
+template <int DIM, typename T, int NC>
+__global__ void __launch_bounds__(kBlock) k_b_prolong(const BInst<T>* __restrict__ insts,
+                                                      const BBlk* __restrict__ map, int l) {
+    const BBlk m = map[blockIdx.x];
+    const BInst<T>& I = insts[m.inst];
+    if (I.ctl->state != 0) return;
+    const int idx = m.start + threadIdx.x;
+    if (idx >= m.end) return;
+    prolong_at<DIM, T, NC>(I.Y[l], I.n[l], I.Y[l + 1], I.n[l + 1], idx);
+}
+
+// ---------------------------------------------------------- reductions
+// One block per problem (block b works on instance first + b): the
+// one-problem reduction logic on that problem's partial rows.
+
+template <typename T>
+__global__ void __launch_bounds__(kRedBlock) k_b_reduce_init(const BInst<T>* __restrict__ insts, double tol) {
+    const BInst<T>& I = insts[blockIdx.x];
+    reduce_init_body(I.ctl, bpart(I, kBPartInit), I.pcnt, tol, nullptr);
+}
+
+template <typename T, int NB>
+__global__ void __launch_bounds__(kRedBlock) k_b_reduce_beta(const BInst<T>* __restrict__ insts, int first,
+                                                          int mixed) {
+    const BInst<T>& I = insts[first + blockIdx.x];
+    reduce_beta_body<NB>(I.ctl, bpart(I, kBPartRho), I.pcnt, bpart(I, kBPartW), I.pcnt, 1, 0,
+                         I.small + kMaxNB + kMaxNB * kMaxNB, I.small + kMaxNB, nullptr, mixed);
+}
+
+template <typename T, int NB>
+__global__ void __launch_bounds__(kRedBlock) k_b_reduce_alpha(const BInst<T>* __restrict__ insts, int first) {
+    const BInst<T>& I = insts[first + blockIdx.x];
+    reduce_alpha_body<NB>(I.ctl, bpart(I, kBPartG), I.pcnt, I.small + kMaxNB + kMaxNB * kMaxNB, I.small, nullptr);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kRedBlock) k_b_refresh_reduce(const BInst<T>* __restrict__ insts, int first) {
+    const BInst<T>& I = insts[first + blockIdx.x];
+    refresh_reduce_body(I.ctl, bpart(I, kBPartRef), I.pcnt, nullptr);
 }
 
 }  // namespace amg

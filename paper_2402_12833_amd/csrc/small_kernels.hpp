@@ -115,8 +115,8 @@ __device__ int wave_pinv(const double* G, double tau, double* Gplus) {
 }
 
 // After the init residual: ||b||, ||r_0||, stop if r_0 already small.
-__global__ void __launch_bounds__(kRedBlock) k_reduce_init(Ctl* ctl, const double* part, int nblk, double tol,
-                                                        double* rhist) {
+__device__ __forceinline__ void reduce_init_body(Ctl* ctl, const double* part, int nblk, double tol,
+                                                 double* rhist) {
     __shared__ double res[2];
     reduce_partials<2>(part, nblk, res);
     if (threadIdx.x != 0) return;
@@ -143,14 +143,19 @@ __global__ void __launch_bounds__(kRedBlock) k_reduce_init(Ctl* ctl, const doubl
     }
 }
 
+__global__ void __launch_bounds__(kRedBlock) k_reduce_init(Ctl* ctl, const double* part, int nblk, double tol,
+                                                        double* rhist) {
+    reduce_init_body(ctl, part, nblk, tol, rhist);
+}
+
 // Residual check of r_{k+1} and beta = G_k^+ W (W = Q_k^T Z_{k+1}).
 // mixed != 0: convergence on the recursive residual only requests a
 // true-residual refresh; the refresh decides.
 template <int NB>
-__global__ void __launch_bounds__(kRedBlock) k_reduce_beta(Ctl* ctl, const double* part_rho, int nblk_rho,
-                                                        const double* part_Wall, int nblk_W, int nwin, int cur,
-                                                        const double* Gplus_all, double* beta_all, double* rhist,
-                                                        int mixed) {
+__device__ __forceinline__ void reduce_beta_body(Ctl* ctl, const double* part_rho, int nblk_rho,
+                                                 const double* part_Wall, int nblk_W, int nwin, int cur,
+                                                 const double* Gplus_all, double* beta_all, double* rhist,
+                                                 int mixed) {
     if (ctl->state != 0) return;
     // slot j of W partials / G^+ / beta: part_Wall + j kMaxNB^2 nblk_W, + j kMaxNB^2
     const double* part_W = part_Wall + (size_t)cur * kMaxNB * kMaxNB * nblk_W;
@@ -220,11 +225,19 @@ __global__ void __launch_bounds__(kRedBlock) k_reduce_beta(Ctl* ctl, const doubl
     }
 }
 
+template <int NB>
+__global__ void __launch_bounds__(kRedBlock) k_reduce_beta(Ctl* ctl, const double* part_rho, int nblk_rho,
+                                                        const double* part_Wall, int nblk_W, int nwin, int cur,
+                                                        const double* Gplus_all, double* beta_all, double* rhist,
+                                                        int mixed) {
+    reduce_beta_body<NB>(ctl, part_rho, nblk_rho, part_Wall, nblk_W, nwin, cur, Gplus_all, beta_all, rhist, mixed);
+}
+
 // Gram G = P^T A P (upper triangle mirrored), g = P^T r, pseudo-inverse,
 // alpha = G^+ g.  State 1 (stop after the x update) becomes 2 here.
 template <int NB>
-__global__ void __launch_bounds__(kRedBlock) k_reduce_alpha(Ctl* ctl, const double* part, int nblk, double* Gplus,
-                                                         double* alpha, double* ahist) {
+__device__ __forceinline__ void reduce_alpha_body(Ctl* ctl, const double* part, int nblk, double* Gplus,
+                                                  double* alpha, double* ahist) {
     const int state = ctl->state;
     if (state == 2) return;
     if (state == 1) {
@@ -265,8 +278,14 @@ __global__ void __launch_bounds__(kRedBlock) k_reduce_alpha(Ctl* ctl, const doub
     }
 }
 
+template <int NB>
+__global__ void __launch_bounds__(kRedBlock) k_reduce_alpha(Ctl* ctl, const double* part, int nblk, double* Gplus,
+                                                         double* alpha, double* ahist) {
+    reduce_alpha_body<NB>(ctl, part, nblk, Gplus, alpha, ahist);
+}
+
 // After a true-residual refresh r = b - A x: accept convergence or go on.
-__global__ void __launch_bounds__(kRedBlock) k_refresh_reduce(Ctl* ctl, const double* part, int nblk, double* rhist) {
+__device__ __forceinline__ void refresh_reduce_body(Ctl* ctl, const double* part, int nblk, double* rhist) {
     if (ctl->state == 2 || !ctl->refresh_req) return;
     __shared__ double res[1];
     reduce_partials<1>(part, nblk, res);
@@ -285,6 +304,10 @@ __global__ void __launch_bounds__(kRedBlock) k_refresh_reduce(Ctl* ctl, const do
         ctl->status = kOK;
         ctl->state = 2;
     }
+}
+
+__global__ void __launch_bounds__(kRedBlock) k_refresh_reduce(Ctl* ctl, const double* part, int nblk, double* rhist) {
+    refresh_reduce_body(ctl, part, nblk, rhist);
 }
 
 // Standalone pseudo-inverse of one Gram matrix (for the gram_pinv entry point).

@@ -90,15 +90,23 @@ def test_status_strings(lib):
     assert B.status_string(99) == "unknown status"
 
 
-def test_batched_switched_off(lib):
-    grids = (B.Grid * 2)(B.Grid(2, 31, 3, None), B.Grid(2, 15, 2, None))
+def test_batched_validation(lib):
+    """Argument checks of the batched entry point (before any device call)."""
     h = ctypes.c_void_p()
-    code = lib.amgmpcg_setup_batched(2, grids, ctypes.byref(amg.default_options()), None, ctypes.byref(h))
-    assert code == B.UNAVAILABLE and not h.value
-    # argument validation still runs first
+    ok = (B.Grid * 2)(B.Grid(2, 31, 3, None), B.Grid(2, 15, 2, None))
     kap = np.ones(33 * 33)
-    bad = (B.Grid * 1)(B.Grid(2, 31, 3, kap.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
-    assert lib.amgmpcg_setup_batched(1, bad, ctypes.byref(amg.default_options()), None, ctypes.byref(h)) == B.INVALID_ARG
+    cases = [
+        (1, (B.Grid * 1)(B.Grid(2, 31, 3, kap.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))), {}),
+        (2, (B.Grid * 2)(B.Grid(2, 31, 3, None), B.Grid(3, 15, 2, None)), {}),
+        (1, (B.Grid * 1)(B.Grid(2, 255, 7, None)), {}),
+        (2, ok, dict(nu=3)),
+        (2, ok, dict(m=2)),
+        (2, ok, dict(method=1)),
+        (0, ok, {}),
+    ]
+    for count, grids, kw in cases:
+        code = lib.amgmpcg_setup_batched(count, grids, ctypes.byref(amg.default_options(**kw)), None, ctypes.byref(h))
+        assert code == B.INVALID_ARG and not h.value, (count, kw)
 
 
 def test_cnn_weight_count_matches_the_oracle_layers(lib):

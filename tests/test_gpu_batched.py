@@ -1,4 +1,5 @@
-"""GPU parity of the batched persistent launch against the FP64 oracle.
+"""GPU parity of the batched solve (many problems, one graph of batched
+launches) against the FP64 oracle.
 
 Each problem of the batch must match the oracle run on that problem alone:
 iterates at equal k to 1e-10 relative (FP64), converged iteration counts
@@ -12,12 +13,7 @@ import workloads as W
 from oracle import hierarchy, mpcg, operators as ops
 
 torch = pytest.importorskip("torch")
-pytestmark = [
-    pytest.mark.gpu,
-    pytest.mark.skip(reason="batched persistent kernel switched off: its first GPU run took a memory fault "
-                            "whose cause is not established (a host emulation under AddressSanitizer finds "
-                            "no out-of-range access); amgmpcg_setup_batched returns AMGMPCG_UNAVAILABLE"),
-]
+pytestmark = pytest.mark.gpu
 
 import paper_2402_12833_amd as amg  # noqa: E402
 
