@@ -174,6 +174,32 @@ def run_batched(amg, torch, precision, steps, warmup):
     return out
 
 
+def run_example1(amg, torch):
+    """Sec. 3, Example 1 (bilinear FEM, anisotropic diffusion, 160 x 160
+    elements, 4 levels): iterations to 1e-8 for kxx = 1e-7 .. 1 of additive-MG
+    MPCG (m = 5, nu = 6), additive MG-PCG (nu = 6) and MG(V)-PCG (3 + 3
+    sweeps), damped Jacobi omega = 1/2, FP64; device ms of one solve each."""
+    import workloads as W
+    n = W.EXAMPLE1_ELEMENTS - 1
+    b = torch.as_tensor(W.example1_rhs(), device="cuda")
+    methods = (("mpcg_m5", dict(m=5, nu=6)), ("additive_pcg", dict(method=amg.ADDITIVE_PCG, nu=6)),
+               ("vcycle_pcg", dict(method=amg.VCYCLE_PCG, nu_pre=3, nu_post=3)))
+    out = {"elements": W.EXAMPLE1_ELEMENTS, "levels": W.EXAMPLE1_LEVELS, "omega": 0.5, "kxx": W.EXAMPLE1_KXX}
+    for tag, opts in methods:
+        its, ms = [], []
+        for kxx in W.EXAMPLE1_KXX:
+            s = amg.Solver(2, n, W.EXAMPLE1_LEVELS, stencil=W.example1_stencil(kxx), omega=0.5, maxit=5000, **opts)
+            x = torch.zeros_like(b)
+            _, info = s.solve(b, x, tol=1e-8)
+            assert info["status"] == amg.OK, (tag, kxx, info)
+            its.append(info["iterations"])
+            ms.append(round(info["solve_ms"], 3))
+            s.close()
+        out[f"{tag}_iterations"] = its
+        out[f"{tag}_ms"] = ms
+    return out
+
+
 def cpu_baseline(prob, max_iters=None):
     """The FP64 oracle (numpy/scipy, one thread) on the same workload."""
     from threadpoolctl import threadpool_limits
@@ -301,6 +327,7 @@ def main(argv=None):
                 s6.close()
         for prec, tag in ((1, "fp32bulk"), (0, "fp64")):
             var[f"batched2d_512_{tag}"] = run_batched(amg, torch, prec, args.steps, args.warmup)
+        var["example1_160"] = run_example1(amg, torch)
         # the learned direction (committed trained weights) on the same problem
         from paper_2402_12833_amd import train as T
         net = amg.Network(dprob.n)

@@ -123,6 +123,20 @@ void amgmpcg_default_options(amgmpcg_options* opts);
 int amgmpcg_setup_grid(const amgmpcg_grid* grid, const amgmpcg_options* opts,
                        void* stream, amgmpcg_handle** out);
 
+/* setup(A, hierarchy) for a 2D operator given by a constant 9-point stencil
+ * on the finest level (Sec. 3, Example 1: bilinear finite elements for
+ * anisotropic diffusion on a uniform mesh), the rest as amgmpcg_setup_grid
+ * (the same nested grids, transfers and Galerkin coarse operators).
+ * grid: dim must be 2 and kappa NULL; n interior nodes per axis (m = n + 1
+ * elements).  stencil: HOST, 9 doubles, stencil[(dy+1)*3 + (dx+1)] =
+ * A(idx, idx + dx + n dy) at interior nodes, couplings to the boundary
+ * dropped (homogeneous Dirichlet); it must be symmetric
+ * (stencil[q] == stencil[8-q]) with a positive centre.  Errors:
+ * AMGMPCG_INVALID_ARG, AMGMPCG_NONFINITE, AMGMPCG_NOT_SPD (before any device
+ * call), AMGMPCG_OOM / AMGMPCG_HIP_ERROR. */
+int amgmpcg_setup_stencil(const amgmpcg_grid* grid, const double* stencil, const amgmpcg_options* opts,
+                          void* stream, amgmpcg_handle** out);
+
 /* solve(b, x0, tol): Algorithm 1 until ||r_k||_2 <= tol ||b||_2 or maxit.
  * b_dev: DEVICE pointer, n^dim doubles, read only.  x_dev: DEVICE pointer,
  * n^dim doubles, x_0 on entry and the final iterate on return.  Both are

@@ -77,6 +77,9 @@ def load(path: str = LIB_PATH):
     lib.amgmpcg_default_options.argtypes = [POINTER(Options)]
     lib.amgmpcg_default_options.restype = None
     lib.amgmpcg_setup_grid.argtypes = [POINTER(Grid), POINTER(Options), c_void_p, POINTER(c_void_p)]
+    lib.amgmpcg_setup_stencil.argtypes = [POINTER(Grid), POINTER(c_double), POINTER(Options), c_void_p,
+                                          POINTER(c_void_p)]
+    lib.amgmpcg_setup_stencil.restype = c_int32
     lib.amgmpcg_solve.argtypes = [c_void_p, c_void_p, c_void_p, c_double, c_int32, POINTER(Info)]
     lib.amgmpcg_solve_host.argtypes = [c_void_p, POINTER(c_double), POINTER(c_double), c_double, c_int32,
                                        POINTER(Info)]
@@ -183,7 +186,7 @@ class Solver:
     """setup(A, hierarchy) on a structured grid; solve(b, x0, tol) on device tensors."""
 
     def __init__(self, dim: int, n: int, nlevels: int, kappa: Optional[np.ndarray] = None,
-                 stream=None, **options):
+                 stream=None, stencil: Optional[np.ndarray] = None, **options):
         lib = load()
         self._lib = lib
         self.dim, self.n, self.nlevels = dim, n, nlevels
@@ -199,7 +202,15 @@ class Solver:
         self.options = default_options(**options)
         self.stream = _current_stream() if stream is None else stream
         h = c_void_p()
-        _check(lib.amgmpcg_setup_grid(byref(self.grid), byref(self.options), self.stream, byref(h)))
+        if stencil is None:
+            _check(lib.amgmpcg_setup_grid(byref(self.grid), byref(self.options), self.stream, byref(h)))
+        else:
+            # constant 9-point finest stencil (2D), rows dy = -1, 0, 1
+            self._stencil = np.ascontiguousarray(stencil, dtype=np.float64).reshape(-1)
+            if self._stencil.size != 9:
+                raise ValueError("stencil must have 9 entries")
+            _check(lib.amgmpcg_setup_stencil(byref(self.grid), self._stencil.ctypes.data_as(POINTER(c_double)),
+                                             byref(self.options), self.stream, byref(h)))
         self._h = h
         nl, nb = c_int32(), c_int32()
         _check(lib.amgmpcg_level_count(h, byref(nl), byref(nb)))

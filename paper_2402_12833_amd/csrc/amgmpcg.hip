@@ -150,7 +150,9 @@ inline size_t slot_elems(int nb, int N) { return ((size_t)even_up(nb) * N + 63) 
 template <typename T, int DIM>
 class Solver : public SolverBase {
    public:
-    Solver(const amgmpcg_grid& g, const amgmpcg_options& o, hipStream_t stream) : opt_(o), stream_(stream) {
+    // st9: NULL, or (2D, kappa NULL) the constant 9-point finest stencil
+    Solver(const amgmpcg_grid& g, const amgmpcg_options& o, hipStream_t stream, const double* st9 = nullptr)
+        : opt_(o), stream_(stream) {
         dim = DIM;
         nlev = g.nlevels;
         method_ = o.method;
@@ -191,7 +193,7 @@ class Solver : public SolverBase {
         }
         std::vector<host::StencilLevel> lev(nlev);
         if (L_ > 0) {
-            lev[L_] = host::faces_to_stencil(DIM, g.n, faces);
+            lev[L_] = st9 ? host::constant_stencil9(g.n, st9) : host::faces_to_stencil(DIM, g.n, faces);
             for (int l = L_ - 1; l >= 0; --l) {
                 lev[l] = host::galerkin(lev[l + 1]);
                 const int ctr = lev[l].center();
@@ -217,6 +219,15 @@ class Solver : public SolverBase {
         f64_.D = f64_.ex = f64_.ey = f64_.ez = nullptr;
         f64_.inv0 = 1.0 / (2.0 * DIM * h2inv);
         f64_.iD = nullptr;
+        if (DIM == 2 && st9) {
+            fop_.k9 = f64_.k9 = 1;
+            for (int q = 0; q < 9; ++q) {
+                fop_.w9[q] = T(st9[q]);
+                f64_.w9[q] = st9[q];
+            }
+            fop_.inv0 = T(1.0 / st9[4]);
+            f64_.inv0 = 1.0 / st9[4];
+        }
         if (var) {
             upload_faces(faces);
         }
@@ -1755,6 +1766,30 @@ int amgmpcg_setup_grid(const amgmpcg_grid* grid, const amgmpcg_options* opts, vo
             if (grid->dim == 2) h->s.reset(new amg::Solver<float, 2>(*grid, *opts, s));
             else h->s.reset(new amg::Solver<float, 3>(*grid, *opts, s));
         }
+        *out = h.release();
+        return AMGMPCG_OK;
+    });
+}
+
+int amgmpcg_setup_stencil(const amgmpcg_grid* grid, const double* stencil, const amgmpcg_options* opts,
+                          void* stream, amgmpcg_handle** out) {
+    return guarded([&]() -> int {
+        if (!out) throw ApiError(AMGMPCG_INVALID_ARG, "out pointer is NULL");
+        *out = nullptr;
+        validate_grid(grid);
+        validate_options(opts);
+        if (grid->dim != 2) throw ApiError(AMGMPCG_INVALID_ARG, "the 9-point finest stencil needs dim = 2");
+        if (grid->kappa) throw ApiError(AMGMPCG_INVALID_ARG, "kappa must be NULL with a finest stencil");
+        if (!stencil) throw ApiError(AMGMPCG_INVALID_ARG, "stencil is NULL");
+        for (int q = 0; q < 9; ++q) {
+            if (!std::isfinite(stencil[q])) throw ApiError(AMGMPCG_NONFINITE, "non-finite stencil");
+            if (stencil[q] != stencil[8 - q]) throw ApiError(AMGMPCG_INVALID_ARG, "the stencil must be symmetric");
+        }
+        if (!(stencil[4] > 0.0)) throw ApiError(AMGMPCG_NOT_SPD, "non-positive stencil centre");
+        auto h = std::make_unique<amgmpcg_handle>();
+        hipStream_t s = (hipStream_t)stream;
+        if (opts->precision == 0) h->s.reset(new amg::Solver<double, 2>(*grid, *opts, s, stencil));
+        else h->s.reset(new amg::Solver<float, 2>(*grid, *opts, s, stencil));
         *out = h.release();
         return AMGMPCG_OK;
     });

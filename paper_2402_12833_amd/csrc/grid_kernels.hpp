@@ -53,13 +53,34 @@ struct FineOp {
     const T* ex;           // coupling to +x neighbour (positive)
     const T* ey;
     const T* ez;
-    T inv0;                // 1 / (2 dim h^-2) (constant coefficient)
+    T inv0;                // 1 / (2 dim h^-2) (constant coefficient), 1 / w9[4] (9-point)
     const T* iD;           // variable coefficient: 1 / diagonal (rounded once)
+    int k9;                // 2D only: the operator is the constant 9-point stencil w9
+    T w9[9];               // w9[(dy+1)*3 + (dx+1)] = A(idx, idx + dx + n dy)
 };
 
 template <int DIM, typename T>
 __device__ __forceinline__ T fine_diag(const FineOp<T>& op, int idx) {
+    if (DIM == 2 && op.k9) return op.w9[4];
     return op.D ? op.D[idx] : T(2 * DIM) * op.s0;
+}
+
+// sum_{dy,dx} w9 u(idx + dx + n dy) over the neighbours inside the grid
+// (2D constant 9-point stencil), rows dy = -1, 0, 1 in turn.
+template <typename C, typename T, typename F>
+__device__ __forceinline__ C stencil9_apply(const FineOp<T>& op, int i, int j, int idx, F&& u) {
+    const int n = op.n;
+    C acc = C(0);
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+        if (j + dy < 0 || j + dy >= n) continue;
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            if (i + dx < 0 || i + dx >= n) continue;
+            acc += C(op.w9[(dy + 1) * 3 + dx + 1]) * C(u(idx + dx + n * dy));
+        }
+    }
+    return acc;
 }
 
 // 1 / D, precomputed: the smoother multiplies by it instead of dividing.
@@ -74,6 +95,7 @@ __device__ __forceinline__ C fine_apply(const FineOp<T>& op, const U* __restrict
                                         const Idx<DIM>& p) {
     const int n = op.n;
     const int sy = n, sz = n * n;
+    if (DIM == 2 && op.k9) return stencil9_apply<C, T>(op, p.i, p.j, idx, [&](int q) { return u[q]; });
     if (!op.D) {
         C acc = C(2 * DIM) * C(u[idx]);
         if (p.i > 0) acc -= C(u[idx - 1]);
@@ -470,6 +492,23 @@ __device__ __forceinline__ void fine_apply_block(const FineOp<T>& op, const T* _
     const int n = op.n, sy = n, sz = n * n;
     load_node<T, S>(P + (size_t)idx * S, own);
     T nb[S];
+    if (DIM == 2 && op.k9) {
+#pragma unroll
+        for (int c = 0; c < S; ++c) q[c] = T(0);
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy) {
+            if (p.j + dy < 0 || p.j + dy >= n) continue;
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (p.i + dx < 0 || p.i + dx >= n) continue;
+                const T w = op.w9[(dy + 1) * 3 + dx + 1];
+                load_node<T, S>(P + (size_t)(idx + dx + n * dy) * S, nb);
+#pragma unroll
+                for (int c = 0; c < S; ++c) q[c] += w * nb[c];
+            }
+        }
+        return;
+    }
     if (!op.D) {
 #pragma unroll
         for (int c = 0; c < S; ++c) q[c] = T(2 * DIM) * own[c];
@@ -663,7 +702,9 @@ __device__ __forceinline__ T fine_smooth_at(const FineOp<T>& op, const G* __rest
     // A c1 with c1_j = omega g_j / D_j formed on the fly
     auto c1at = [&](int j) -> T { return omega * (T(g[j]) * fine_invdiag<DIM>(op, j)); };
     T Ac;
-    if (!op.D) {
+    if (DIM == 2 && op.k9) {
+        Ac = stencil9_apply<T, T>(op, p.i, p.j, idx, c1at);
+    } else if (!op.D) {
         T acc = T(2 * DIM) * c1;
         if (p.i > 0) acc -= c1at(idx - 1);
         if (p.i < n - 1) acc -= c1at(idx + 1);

@@ -119,6 +119,28 @@ inline StencilLevel faces_to_stencil(int dim, int n, const FineFaces& f) {
 }
 
 // Galerkin product R A P for one level; nc = floor(nf / 2).
+// A constant 2D 9-point stencil w (w[(dy+1)*3 + dx+1] = A(idx, idx + dx + n dy))
+// on the n x n interior nodes; couplings to nodes outside the grid dropped
+// (homogeneous Dirichlet).
+inline StencilLevel constant_stencil9(int n, const double* w) {
+    StencilLevel L;
+    L.dim = 2;
+    L.n = n;
+    L.N = ipow(n, 2);
+    L.coef.assign((size_t)9 * L.N, 0.0);
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+            const int64_t idx = i + (int64_t)n * j;
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    if (i + dx < 0 || i + dx >= n || j + dy < 0 || j + dy >= n) continue;
+                    const int sidx = (dy + 1) * 3 + (dx + 1);
+                    L.coef[(size_t)sidx * L.N + idx] = w[sidx];
+                }
+        }
+    return L;
+}
+
 inline StencilLevel galerkin(const StencilLevel& F) {
     const int dim = F.dim, nf = F.n, nc = nf / 2;
     if (nc < 1) throw std::invalid_argument("grid too small for another level");

@@ -90,6 +90,31 @@ def test_status_strings(lib):
     assert B.status_string(99) == "unknown status"
 
 
+def test_stencil_setup_validation(lib):
+    """Argument checks of the 9-point-stencil setup (before any device call)."""
+    h = ctypes.c_void_p()
+    st = np.array([-1.0, -4.0, -1.0, 2.0, 8.0, 2.0, -1.0, -4.0, -1.0]) / 6.0
+    dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    asym = st.copy()
+    asym[0] += 1.0
+    nan = st.copy()
+    nan[2] = nan[6] = np.nan
+    kap = np.ones(33 * 33)
+    cases = [
+        (B.Grid(3, 15, 2, None), st, B.INVALID_ARG),
+        (B.Grid(2, 31, 3, dp(kap)), st, B.INVALID_ARG),
+        (B.Grid(2, 31, 3, None), asym, B.INVALID_ARG),
+        (B.Grid(2, 31, 3, None), -st, B.NOT_SPD),
+        (B.Grid(2, 31, 3, None), nan, B.NONFINITE),
+    ]
+    for g, w, want in cases:
+        code = lib.amgmpcg_setup_stencil(ctypes.byref(g), dp(np.ascontiguousarray(w)),
+                                         ctypes.byref(amg.default_options()), None, ctypes.byref(h))
+        assert code == want and not h.value, (want, code)
+    assert lib.amgmpcg_setup_stencil(ctypes.byref(B.Grid(2, 31, 3, None)), None,
+                                     ctypes.byref(amg.default_options()), None, ctypes.byref(h)) == B.INVALID_ARG
+
+
 def test_batched_validation(lib):
     """Argument checks of the batched entry point (before any device call)."""
     h = ctypes.c_void_p()

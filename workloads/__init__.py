@@ -170,3 +170,30 @@ def manufactured_solution(dim: int, n: int) -> np.ndarray:
     for _ in range(dim - 1):
         u = np.multiply.outer(s, u)
     return u.reshape(-1).copy()
+
+
+# ---------------------------------------------------------------- Example 1
+# Anisotropic diffusion -div(diag(kxx, kyy) grad u) = f on (0,1)^2 (Sec. 3,
+# Example 1): 160 x 160 bilinear elements, 4 nested levels (coarsest
+# 20 x 20 elements), kxx in 10^-7 .. 1, kyy = 1.  Unstated in the paper and
+# taken here: homogeneous Dirichlet on the whole boundary, f = 1.
+
+EXAMPLE1_ELEMENTS = 160
+EXAMPLE1_LEVELS = 4
+EXAMPLE1_KXX = [10.0 ** e for e in range(-7, 1)]
+
+
+def example1_stencil(kxx: float, kyy: float = 1.0) -> np.ndarray:
+    """Interior 9-point stencil of the assembled bilinear stiffness on square
+    elements (rows dy = -1, 0, 1; columns dx = -1, 0, 1): the x part is kxx
+    times the 1D stiffness in x tensor the 1D mass in y (h cancels in 2D),
+    the y part likewise."""
+    stiff = np.array([-1.0, 2.0, -1.0])           # 1D stiffness, times 1/h
+    mass = np.array([1.0, 4.0, 1.0]) / 6.0          # 1D mass, times h
+    return kxx * np.outer(mass, stiff) + kyy * np.outer(stiff, mass)
+
+
+def example1_rhs(elements: int = EXAMPLE1_ELEMENTS, f: float = 1.0) -> np.ndarray:
+    """Load vector of a constant f on the interior nodes: f h^2 each."""
+    h = 1.0 / elements
+    return np.full((elements - 1) ** 2, f * h * h)
