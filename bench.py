@@ -221,6 +221,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--unet-only", action="store_true",
+                    help="time only the U-Net inference on the 128^3 grid (committed weights) and print its line")
     ap.add_argument("--batched-only", action="store_true",
                     help="time only the 512-problem batched workload (FP32 bulk) and print its line")
     ap.add_argument("--calibrate", action="store_true",
@@ -237,6 +239,20 @@ def main(argv=None):
     import paper_2402_12833_amd as amg
     import workloads as W
     amg.load()
+    if args.unet_only:
+        from paper_2402_12833_amd import train as T
+        dprob = W.DIFFUSION3D_127
+        sol = amg.Solver(dprob.dim, dprob.n, dprob.nlevels, kappa=W.kappa_field(dprob))
+        net = amg.Network(dprob.n)
+        T.load_weights(net)
+        b = torch.as_tensor(W.problem_rhs(dprob), device="cuda")
+        fms = net.time_forward(b, sol.log_kappa(), reps=max(args.steps, 1))
+        gf = unet_gflop((dprob.n + 3) // 4 * 4)
+        print(json.dumps({"workload": "unet_forward_128", "ms": round(fms, 4), "gflop_padded": round(gf, 1),
+                          "TFLOPs": round(gf / fms, 1), "bf16_peak_frac": round(gf / fms / 2500.0, 4)}), flush=True)
+        net.close()
+        sol.close()
+        return 0
     if args.batched_only:
         res = run_batched(amg, torch, 1, args.steps, args.warmup)
         print(json.dumps({"workload": "batched2d_512", "dtype": "f32 bulk / f64 Gram", **res}), flush=True)

@@ -237,10 +237,24 @@ class Solver : public SolverBase {
         c_.resize(nlev);
         c2_.resize(nlev);
         Y_.resize(nlev);
+        cst_.assign(nlev, 0);
         for (int l = 0; l < L_; ++l) {
             const int S = lev[l].S();
-            coef_[l].alloc((size_t)S * N_[l]);
-            upload_conv(coef_[l].p, lev[l].coef);
+            // a level whose stencil is the same at every node (truncated at
+            // the boundary; constant coefficient, odd grid sizes) keeps only
+            // those S values
+            cst_[l] = host::constant_with_truncation(lev[l]) ? 1 : 0;
+            if (cst_[l]) {
+                const int c = n_axis[l] / 2;
+                const int64_t ref = c + (int64_t)n_axis[l] * (c + (DIM == 3 ? (int64_t)n_axis[l] * c : 0));
+                std::vector<double> w(S);
+                for (int q = 0; q < S; ++q) w[q] = lev[l].coef[(size_t)q * N_[l] + ref];
+                coef_[l].alloc((size_t)S);
+                upload_conv(coef_[l].p, w);
+            } else {
+                coef_[l].alloc((size_t)S * N_[l]);
+                upload_conv(coef_[l].p, lev[l].coef);
+            }
             g_[l].alloc(N_[l]);
             c1_[l].alloc(N_[l]);
             if (opt_.nu > 2) {
@@ -547,11 +561,31 @@ class Solver : public SolverBase {
 
     void level_stencil(int level, double* out) override {
         if (level < 0 || level >= L_) throw ApiError(AMGMPCG_INVALID_ARG, "level must be a coarse level");
-        const size_t cnt = (size_t)(DIM == 2 ? 9 : 27) * N_[level];
-        std::vector<T> tmp(cnt);
-        HIPCHK(hipMemcpyAsync(tmp.data(), coef_[level].p, cnt * sizeof(T), hipMemcpyDeviceToHost, stream_));
+        const int S = DIM == 2 ? 9 : 27;
+        const size_t cnt = (size_t)S * N_[level];
+        if (!cst_[level]) {
+            std::vector<T> tmp(cnt);
+            HIPCHK(hipMemcpyAsync(tmp.data(), coef_[level].p, cnt * sizeof(T), hipMemcpyDeviceToHost, stream_));
+            HIPCHK(hipStreamSynchronize(stream_));
+            for (size_t i = 0; i < cnt; ++i) out[i] = double(tmp[i]);
+            return;
+        }
+        // constant stencil: expanded with the couplings outside the grid dropped
+        std::vector<T> w(S);
+        HIPCHK(hipMemcpyAsync(w.data(), coef_[level].p, S * sizeof(T), hipMemcpyDeviceToHost, stream_));
         HIPCHK(hipStreamSynchronize(stream_));
-        for (size_t i = 0; i < cnt; ++i) out[i] = double(tmp[i]);
+        const int n = n_axis[level];
+        for (int64_t idx = 0; idx < N_[level]; ++idx) {
+            const int i = (int)(idx % n), j = (int)((idx / n) % n), k = DIM == 3 ? (int)(idx / ((int64_t)n * n)) : 0;
+            int q = 0;
+            for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx, ++q) {
+                        const bool in = i + dx >= 0 && i + dx < n && j + dy >= 0 && j + dy < n &&
+                                        (DIM == 2 || (k + dz >= 0 && k + dz < n));
+                        out[(size_t)q * N_[level] + idx] = in ? double(w[q]) : 0.0;
+                    }
+        }
     }
 
     void history(int cap, double* alpha, double* res, int* count) override {
@@ -601,7 +635,7 @@ class Solver : public SolverBase {
                 const int l = L_ - 1;
                 timed([&] {
                     k_restrict<DIM, double, T><<<(N_[l] + kBlock - 1) / kBlock, kBlock, 0, stream_>>>(
-                        cf, r_.p, n_axis[L_], g_[l].p, n_axis[l], N_[l], diag(l), c1_[l].p, omega);
+                        cf, r_.p, n_axis[L_], g_[l].p, n_axis[l], N_[l], diag(l), c1_[l].p, omega, cst_[l]);
                 });
                 CoarseLevels<T> cl = coarse_arg(0);
                 const int off = cl.blk_off[L_];
@@ -740,7 +774,9 @@ class Solver : public SolverBase {
     }
 
     // Diagonal (stencil centre) of coarse level l.
-    const T* diag(int l) const { return coef_[l].p + (size_t)(DIM == 2 ? 4 : 13) * N_[l]; }
+    const T* diag(int l) const {
+        return coef_[l].p + (size_t)(DIM == 2 ? 4 : 13) * (cst_[l] ? 1 : N_[l]);
+    }
 
     // The node-major level-(L-1) block from which the fine corrections are formed.
     const T* fine_Y() const { return L_ > 0 ? Y_[L_ - 1].p : nullptr; }
@@ -757,6 +793,7 @@ class Solver : public SolverBase {
             cl.n[l] = n_axis[l];
             cl.N[l] = N_[l];
             cl.coef[l] = coef_[l].p;
+            cl.cst[l] = cst_[l];
             cl.g[l] = g_[l].p;
             cl.c1[l] = c1_[l].p;
             if (final_out || !c_[l].p) {
@@ -853,11 +890,11 @@ class Solver : public SolverBase {
         {
             const int l = L - 1;
             k_restrict<DIM, double, T><<<(N_[l] + kBlock - 1) / kBlock, kBlock, 0, stream_>>>(
-                ctl, r, n_axis[L], g_[l].p, n_axis[l], N_[l], diag(l), c1_[l].p, omega);
+                ctl, r, n_axis[L], g_[l].p, n_axis[l], N_[l], diag(l), c1_[l].p, omega, cst_[l]);
             int m = L - 2;
             for (; m >= 0 && N_[m] > kRestrictTailMax; --m)
                 k_restrict<DIM, T, T><<<(N_[m] + kBlock - 1) / kBlock, kBlock, 0, stream_>>>(
-                    ctl, g_[m + 1].p, n_axis[m + 1], g_[m].p, n_axis[m], N_[m], diag(m), c1_[m].p, omega);
+                    ctl, g_[m + 1].p, n_axis[m + 1], g_[m].p, n_axis[m], N_[m], diag(m), c1_[m].p, omega, cst_[m]);
             if (m >= 0) {
                 RestrictChain<T> ch{};
                 for (; m >= 0; --m) {
@@ -868,6 +905,7 @@ class Solver : public SolverBase {
                     ch.gf[q] = g_[m + 1].p;
                     ch.gc[q] = g_[m].p;
                     ch.D[q] = diag(m);
+                    ch.dconst[q] = cst_[m];
                     ch.c1[q] = c1_[m].p;
                 }
                 k_restrict_tail<DIM, T><<<1, kTailBlock, 0, stream_>>>(ctl, ch, omega);
@@ -1108,7 +1146,7 @@ class Solver : public SolverBase {
     }
     T* vc_coarse_sweeps(const Ctl* ctl, int l, T* cur, int count) {
         const T omega = T(opt_.omega);
-        CoarseOp<T> op{n_axis[l], N_[l], coef_[l].p};
+        CoarseOp<T> op{n_axis[l], N_[l], coef_[l].p, cst_[l]};
         const int blocks = (N_[l] + kBlock - 1) / kBlock;
         for (int s = 0; s < count; ++s) {
             T* nxt = cur == vc_[l].p ? vt_[l].p : vc_[l].p;
@@ -1131,15 +1169,15 @@ class Solver : public SolverBase {
         mark(kSecRestrict);
         k_fine_resid<DIM, T, double><<<FB_, kBlock, 0, stream_>>>(ctl, rows_, fop_, r, cf, vrL_.p);
         k_restrict<DIM, T, T><<<(N_[L - 1] + kBlock - 1) / kBlock, kBlock, 0, stream_>>>(
-            ctl, vrL_.p, n_axis[L], vg_[L - 1].p, n_axis[L - 1], N_[L - 1], diag(L - 1), vc_[L - 1].p, omega);
+            ctl, vrL_.p, n_axis[L], vg_[L - 1].p, n_axis[L - 1], N_[L - 1], diag(L - 1), vc_[L - 1].p, omega, cst_[L - 1]);
         std::vector<T*> c(L, nullptr);
         for (int l = L - 1; l >= 1; --l) {
             c[l] = vc_coarse_sweeps(ctl, l, vc_[l].p, nu - 1);
-            CoarseOp<T> op{n_axis[l], N_[l], coef_[l].p};
+            CoarseOp<T> op{n_axis[l], N_[l], coef_[l].p, cst_[l]};
             k_vc_coarse<DIM, T><<<(N_[l] + kBlock - 1) / kBlock, kBlock, 0, stream_>>>(ctl, op, vg_[l].p, c[l],
                                                                                      vr_[l].p, omega, 2);
             k_restrict<DIM, T, T><<<(N_[l - 1] + kBlock - 1) / kBlock, kBlock, 0, stream_>>>(
-                ctl, vr_[l].p, n_axis[l], vg_[l - 1].p, n_axis[l - 1], N_[l - 1], diag(l - 1), vc_[l - 1].p, omega);
+                ctl, vr_[l].p, n_axis[l], vg_[l - 1].p, n_axis[l - 1], N_[l - 1], diag(l - 1), vc_[l - 1].p, omega, cst_[l - 1]);
         }
         mark(kSecCoarseSmooth);
         c[0] = vc_coarse_sweeps(ctl, 0, vc_[0].p, 2 * nu - 1);
@@ -1293,7 +1331,8 @@ class Solver : public SolverBase {
     T* cL_final_ = nullptr;
     DevBuf<double> x_, r_, b_, part_, small_, ahist_, rhist_, partWin_, partG_;
     DevBuf<T> P_, Q_, cL_, cL2_, dl_;
-    DevBuf<T> zv_, vcL_, vtL_, vrL_;                   // comparison methods: z = B r; fine V-cycle vectors
+    DevBuf<T> zv_, vcL_, vtL_, vrL_;
+    std::vector<int> cst_;                             // per coarse level: constant stencil (coef_ holds 3^d values)                   // comparison methods: z = B r; fine V-cycle vectors
     std::vector<DevBuf<T>> vg_, vc_, vt_, vr_;         // coarse V-cycle vectors (rhs, iterate x2, residual)
     DevBuf<double> xt_;
     DevBuf<unsigned short> lk_;

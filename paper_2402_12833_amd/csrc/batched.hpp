@@ -285,7 +285,7 @@ __global__ void __launch_bounds__(kBlock) k_b_coarse_smooth(const BInst<T>* __re
     if (I.ctl->state != 0) return;
     const int idx = m.start + threadIdx.x;
     if (idx >= m.end) return;
-    CoarseOp<T> op{I.n[l], I.N[l], I.coef[l]};
+    CoarseOp<T> op{I.n[l], I.N[l], I.coef[l], 0};
     I.Y[l][(size_t)idx * even_up(l + 1) + l] =
         coarse_smooth_at<DIM, T>(op, I.g[l], I.c1[l], nullptr, idx, omega, 0, two);
 }

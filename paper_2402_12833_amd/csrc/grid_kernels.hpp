@@ -125,7 +125,8 @@ __device__ __forceinline__ C fine_apply(const FineOp<T>& op, const U* __restrict
 template <typename T>
 struct CoarseOp {
     int n, N;
-    const T* coef;   // 3^DIM * N
+    const T* coef;   // 3^DIM * N, or (cst) the 3^DIM values of a constant stencil
+    int cst;         // 1: every node has the same stencil, truncated at the boundary
 };
 
 template <int DIM>
@@ -150,7 +151,8 @@ __device__ __forceinline__ C coarse_apply_fn(const CoarseOp<T>& op, int idx, con
                 const bool ok = oky && p.i + dx >= 0 && p.i + dx < n;
                 if (ok) {
                     const int nb = idx + dx + n * (dy + n * dz);
-                    acc += C(op.coef[(size_t)s * N + idx]) * value_at(nb);
+                    const T w = op.cst ? op.coef[s] : op.coef[(size_t)s * N + idx];
+                    acc += C(w) * value_at(nb);
                 }
             }
         }
@@ -795,16 +797,17 @@ __device__ __forceinline__ C restrict_at(const TI* __restrict__ gf, int nf, int 
 
 // Restriction to one coarse level (thread per coarse node).  Also writes the
 // first Jacobi sweep c1 = omega (g / D) of that level (read by the smoother).
+// dconst: D is the one diagonal value of a constant stencil.
 template <int DIM, typename TI, typename TO>
 __global__ void __launch_bounds__(kBlock) k_restrict(const Ctl* __restrict__ ctl, const TI* __restrict__ gf, int nf,
                                                      TO* __restrict__ gc, int nc, int Nc, const TO* __restrict__ D,
-                                                     TO* __restrict__ c1, TO omega) {
+                                                     TO* __restrict__ c1, TO omega, int dconst) {
     if (ctl->state != 0) return;
     const int idx = blockIdx.x * kBlock + threadIdx.x;
     if (idx >= Nc) return;
     const TO g = restrict_at<DIM, TI, TO>(gf, nf, nc, idx);
     gc[idx] = g;
-    c1[idx] = omega * (g / D[idx]);
+    c1[idx] = omega * (g / D[dconst ? 0 : idx]);
 }
 
 // The small coarse levels of the restriction chain in one block, one level
@@ -817,6 +820,7 @@ struct RestrictChain {
     T* gc[kMaxLevels];
     const T* D[kMaxLevels];
     T* c1[kMaxLevels];
+    int dconst[kMaxLevels];   // D is one value (constant stencil)
 };
 
 constexpr int kTailBlock = 1024;
@@ -829,7 +833,7 @@ __global__ void __launch_bounds__(kTailBlock) k_restrict_tail(const Ctl* __restr
         for (int idx = threadIdx.x; idx < ch.Nc[m]; idx += kTailBlock) {
             const T g = restrict_at<DIM, T, T>(ch.gf[m], ch.nf[m], ch.nc[m], idx);
             ch.gc[m][idx] = g;
-            ch.c1[m][idx] = omega * (g / ch.D[m][idx]);
+            ch.c1[m][idx] = omega * (g / ch.D[m][ch.dconst[m] ? 0 : idx]);
         }
         __syncthreads();
     }
@@ -848,6 +852,7 @@ struct CoarseLevels {
     int N[kMaxLevels];
     int cstride[kMaxLevels];
     const T* coef[kMaxLevels];
+    int cst[kMaxLevels];       // constant stencil (coef holds 3^d values)
     const T* g[kMaxLevels];
     const T* c1[kMaxLevels];   // first sweep omega (g / D), written by the restriction
     const T* cin[kMaxLevels];
@@ -860,9 +865,9 @@ template <int DIM, typename T>
 __device__ __forceinline__ T coarse_smooth_at(const CoarseOp<T>& op, const T* __restrict__ g,
                                               const T* __restrict__ c1, const T* __restrict__ cin, int idx,
                                               T omega, int mode, int two_sweeps) {
-    const T* __restrict__ D = op.coef + (size_t)stencil_center<DIM>() * op.N;
     const Idx<DIM> p = decomp<DIM>(idx, op.n);
-    const T gi = g[idx], Di = D[idx];
+    const T gi = g[idx];
+    const T Di = op.cst ? op.coef[stencil_center<DIM>()] : op.coef[(size_t)stencil_center<DIM>() * op.N + idx];
     if (mode == 0) {
         if (!two_sweeps) return c1[idx];
         const T Ac = coarse_apply_fn<DIM, T>(op, idx, p, [&](int j) -> T { return c1[j]; });
@@ -881,7 +886,7 @@ __global__ void __launch_bounds__(kBlock) k_coarse_smooth(const Ctl* __restrict_
     const int idx = (blockIdx.x - L.blk_off[l]) * kBlock + threadIdx.x;
     const int N = L.N[l];
     if (idx >= N) return;
-    CoarseOp<T> op{L.n[l], N, L.coef[l]};
+    CoarseOp<T> op{L.n[l], N, L.coef[l], L.cst[l]};
     L.cout[l][(size_t)idx * L.cstride[l]] =
         coarse_smooth_at<DIM, T>(op, L.g[l], L.c1[l], L.cin[l], idx, omega, mode, two_sweeps);
 }

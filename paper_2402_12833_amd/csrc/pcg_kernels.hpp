@@ -107,8 +107,8 @@ __global__ void __launch_bounds__(kBlock) k_vc_coarse(const Ctl* __restrict__ ct
         cout[idx] = res;
         return;
     }
-    const T* __restrict__ D = op.coef + (size_t)stencil_center<DIM>() * op.N;
-    cout[idx] = cin[idx] + omega * (res / D[idx]);
+    const T Di = op.cst ? op.coef[stencil_center<DIM>()] : op.coef[(size_t)stencil_center<DIM>() * op.N + idx];
+    cout[idx] = cin[idx] + omega * (res / Di);
 }
 
 // Coarse-grid correction c_f += P c_c (linear interpolation of one coarse

@@ -119,6 +119,29 @@ inline StencilLevel faces_to_stencil(int dim, int n, const FineFaces& f) {
 }
 
 // Galerkin product R A P for one level; nc = floor(nf / 2).
+// True if every node's stencil equals the stencil of the middle node with
+// the couplings to nodes outside the grid dropped (exact comparison); then
+// the level can be stored as those 3^d values.  Galerkin products of a
+// constant-coefficient operator have this form on grids of odd size.
+inline bool constant_with_truncation(const StencilLevel& L) {
+    const int n = L.n, dim = L.dim;
+    const int c = n / 2;
+    const int64_t ref = c + (int64_t)n * (c + (dim == 3 ? (int64_t)n * c : 0));
+    for (int64_t idx = 0; idx < L.N; ++idx) {
+        const int i = (int)(idx % n), j = (int)((idx / n) % n), k = dim == 3 ? (int)(idx / ((int64_t)n * n)) : 0;
+        int s = 0;
+        for (int dz = (dim == 3 ? -1 : 0); dz <= (dim == 3 ? 1 : 0); ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx, ++s) {
+                    const bool in = i + dx >= 0 && i + dx < n && j + dy >= 0 && j + dy < n &&
+                                    (dim == 2 || (k + dz >= 0 && k + dz < n));
+                    const double want = in ? L.coef[(size_t)s * L.N + ref] : 0.0;
+                    if (L.coef[(size_t)s * L.N + idx] != want) return false;
+                }
+    }
+    return true;
+}
+
 // A constant 2D 9-point stencil w (w[(dy+1)*3 + dx+1] = A(idx, idx + dx + n dy))
 // on the n x n interior nodes; couplings to nodes outside the grid dropped
 // (homogeneous Dirichlet).
