@@ -53,13 +53,21 @@ def traffic_model(dim, n, nlevels, bulk, var):
     Nf = N[L]
     faces = (dim + 1) * bulk * Nf if var else 0
     faces64 = (dim + 1) * 8 * Nf if var else 0
+    # coarse level l keeps one constant stencil (no coefficient arrays) when
+    # the fine operator has constant coefficients and every finer grid size
+    # is odd (the setup checks this exactly)
+    cst = [not var and all(sz % 2 == 1 for sz in sizes[l + 1:]) for l in range(nlevels)]
+    coefb = [0 if cst[l] else S * bulk * N[l] for l in range(nlevels)]
+    diagb = [0 if cst[l] else bulk * N[l] for l in range(nlevels)]
     m = {}
     m["update_r"] = (b * bulk + 16) * Nf
     m["fine_smooth"] = (8 + bulk) * Nf + faces
     if L > 0:
-        m["restrict_fine"] = 8 * Nf + bulk * N[L - 1]
-        m["restrict_coarse"] = sum(bulk * (N[l + 1] + N[l]) for l in range(L - 1))
-        m["coarse_smooth"] = sum((S + 2) * bulk * N[l] for l in range(L))
+        # restriction: read the finer vector, write g and the first sweep c1 (reads D)
+        m["restrict_fine"] = 8 * Nf + 2 * bulk * N[L - 1] + diagb[L - 1]
+        m["restrict_coarse"] = sum(bulk * N[l + 1] + 2 * bulk * N[l] + diagb[l] for l in range(L - 1))
+        # smoothing: read g, c1 and the coefficients, write the result
+        m["coarse_smooth"] = sum(3 * bulk * N[l] + coefb[l] for l in range(L))
         m["prolong_top"] = (L - 1) * bulk * (N[L - 2] + N[L - 1]) if L >= 2 else 0
         m["prolong_all"] = sum((l + 1) * bulk * (N[l] + N[l + 1]) for l in range(L - 1))
         coarse_cols = L * bulk * N[L - 1]
