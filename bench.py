@@ -352,6 +352,23 @@ def main(argv=None):
         for prec, tag in ((1, "fp32bulk"), (0, "fp64")):
             var[f"batched2d_512_{tag}"] = run_batched(amg, torch, prec, args.steps, args.warmup)
         var["example1_160"] = run_example1(amg, torch)
+        # the general (CSR) entry point on an unstructured graph problem
+        A, Ps, bg = W.graph_problem()
+        bt = torch.as_tensor(bg, device="cuda")
+        for prec, tag in ((0, "fp64"), (1, "fp32bulk")):
+            sc = amg.Solver.from_csr(A, Ps, 1.0, precision=prec, maxit=5000)
+            xc = torch.zeros_like(bt)
+            sc.solve(bt, xc, tol=1e-8)
+            tms = []
+            for _ in range(args.steps):
+                xc.zero_()
+                torch.cuda.synchronize()
+                _, ci = sc.solve(bt, xc, tol=1e-8)
+                tms.append(ci["solve_ms"])
+            assert ci["status"] == amg.OK, ci
+            var[f"graph2d_20000_csr_{tag}"] = {"ms": round(float(np.mean(tms)), 4), "iterations": ci["iterations"],
+                                               "unknowns": int(A.shape[0]), "nnz": int(A.nnz), "levels": len(Ps) + 1}
+            sc.close()
         # the learned direction (committed trained weights) on the same problem
         from paper_2402_12833_amd import train as T
         net = amg.Network(dprob.n)

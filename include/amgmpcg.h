@@ -56,6 +56,26 @@ typedef struct {
     const double* kappa;
 } amgmpcg_grid;
 
+/* A sparse matrix in CSR form (HOST arrays, copied during setup): row i
+ * holds colind[rowptr[i] .. rowptr[i+1]-1] with values val[...]; indices
+ * 0-based, int32; duplicates are summed. */
+typedef struct {
+    int32_t nrows, ncols, nnz;
+    const int32_t* rowptr;   /* nrows + 1 entries, rowptr[0] = 0, rowptr[nrows] = nnz */
+    const int32_t* colind;   /* nnz entries in [0, ncols)                            */
+    const double* val;       /* nnz entries                                          */
+} amgmpcg_csr;
+
+/* A nested hierarchy given by its prolongations (Sec. 2.1 with arbitrary
+ * transfers): P[l] maps level l to level l+1 (P[l].nrows = unknowns of
+ * level l+1, P[l].ncols = unknowns of level l; level 0 coarsest, level
+ * nlevels-1 the finest), R_l = restrict_scale * P[l]^T. */
+typedef struct {
+    int32_t nlevels;           /* 1..8                                      */
+    const amgmpcg_csr* P;      /* HOST array of nlevels - 1 matrices (NULL if nlevels = 1) */
+    double restrict_scale;     /* > 0                                       */
+} amgmpcg_hierarchy;
+
 /* Solver options.  Fill with amgmpcg_default_options() first. */
 typedef struct {
     int32_t m;            /* truncation window 1..8 (1): P_{k+1} is made
@@ -122,6 +142,24 @@ void amgmpcg_default_options(amgmpcg_options* opts);
  * handle owns all device memory it allocates; free with amgmpcg_destroy. */
 int amgmpcg_setup_grid(const amgmpcg_grid* grid, const amgmpcg_options* opts,
                        void* stream, amgmpcg_handle** out);
+
+/* setup(A, hierarchy) for a general SPD matrix and hierarchy (Sec. 2.1):
+ * A (nrows = ncols = n) and the prolongations of H, all HOST CSR, copied.
+ * The coarse operators are the Galerkin products R_l A_{l+1} P_l built on
+ * the host (stored symmetrised: upper triangle mirrored), the smoother is
+ * the damped Jacobi of every level; the solve runs Algorithm 1 with CSR
+ * kernels (one thread per row).  Options as for amgmpcg_setup_grid with the
+ * MPCG method only.  Errors (before any device call): AMGMPCG_INVALID_ARG
+ * for malformed CSR data (row pointers, index ranges, nnz) or dimensions
+ * that do not chain, AMGMPCG_NONFINITE for non-finite values,
+ * AMGMPCG_NOT_SPD for a non-symmetric A (relative 1e-12) or a non-positive
+ * diagonal on any level; then AMGMPCG_OOM / AMGMPCG_HIP_ERROR.  Entry points
+ * tied to structured grids or the learned direction (level_stencil,
+ * attach_cnn, log_kappa, make_pairs, time_kernels, profile_solve) return
+ * AMGMPCG_INVALID_ARG for such a handle; amgmpcg_level_size gives a level's
+ * number of unknowns. */
+int amgmpcg_setup_csr(const amgmpcg_csr* A, const amgmpcg_hierarchy* H, const amgmpcg_options* opts,
+                      void* stream, amgmpcg_handle** out);
 
 /* setup(A, hierarchy) for a 2D operator given by a constant 9-point stencil
  * on the finest level (Sec. 3, Example 1: bilinear finite elements for

@@ -86,3 +86,26 @@ def prolong_from(h: Hierarchy, c: np.ndarray, l: int) -> np.ndarray:
     for j in range(l, h.L):
         z = h.levels[j].P @ z
     return z
+
+
+def from_operators(A: sp.spmatrix, prolongations, restrict_scale: float) -> Hierarchy:
+    """A level hierarchy from a fine matrix and given prolongations (Sec. 2.1
+    for a general nested hierarchy): prolongations[l] maps level l to level
+    l+1 (level 0 coarsest), R_l = restrict_scale * P_l^T and the coarse
+    operators are the Galerkin products R A P (stored symmetrised).  The
+    ``n`` of a level is its number of unknowns."""
+    A = sp.csr_matrix(A, dtype=np.float64)
+    Ps = [sp.csr_matrix(P, dtype=np.float64) for P in prolongations]
+    finest_first = [Level(A.shape[0], A, A.diagonal().copy(), None, None)]
+    for P in reversed(Ps):
+        Af = finest_first[-1].A
+        if P.shape[0] != Af.shape[0]:
+            raise ValueError("prolongation rows must match the finer level")
+        R = (restrict_scale * P.T).tocsr()
+        Ac = ops.galerkin(Af, P, R)
+        finest_first.append(Level(P.shape[1], Ac, Ac.diagonal().copy(), P, R))
+    levels = finest_first[::-1]
+    for lev in levels:
+        if np.any(~(lev.D > 0.0)):
+            raise NotSPDError("non-positive diagonal in a level operator")
+    return Hierarchy(0, levels)

@@ -35,6 +35,27 @@ class Options(ctypes.Structure):
                 ("nu_pre", c_int32), ("nu_post", c_int32)]
 
 
+class CsrMatrix(ctypes.Structure):
+    _fields_ = [("nrows", c_int32), ("ncols", c_int32), ("nnz", c_int32), ("rowptr", POINTER(c_int32)),
+                ("colind", POINTER(c_int32)), ("val", POINTER(c_double))]
+
+
+class Hierarchy(ctypes.Structure):
+    _fields_ = [("nlevels", c_int32), ("P", POINTER(CsrMatrix)), ("restrict_scale", c_double)]
+
+
+def _csr_struct(M, keep: list) -> CsrMatrix:
+    """A scipy.sparse matrix as a CsrMatrix over arrays kept alive in `keep`."""
+    import scipy.sparse as sp
+    M = sp.csr_matrix(M)
+    ptr = np.ascontiguousarray(M.indptr, dtype=np.int32)
+    col = np.ascontiguousarray(M.indices, dtype=np.int32)
+    val = np.ascontiguousarray(M.data, dtype=np.float64)
+    keep.extend([ptr, col, val])
+    return CsrMatrix(M.shape[0], M.shape[1], int(val.size), ptr.ctypes.data_as(POINTER(c_int32)),
+                     col.ctypes.data_as(POINTER(c_int32)), val.ctypes.data_as(POINTER(c_double)))
+
+
 class Info(ctypes.Structure):
     _fields_ = [("status", c_int32), ("iterations", c_int32), ("bnorm", c_double), ("relres", c_double),
                 ("refreshes", c_int32), ("nb", c_int32), ("solve_ms", c_double)]
@@ -80,6 +101,9 @@ def load(path: str = LIB_PATH):
     lib.amgmpcg_setup_stencil.argtypes = [POINTER(Grid), POINTER(c_double), POINTER(Options), c_void_p,
                                           POINTER(c_void_p)]
     lib.amgmpcg_setup_stencil.restype = c_int32
+    lib.amgmpcg_setup_csr.argtypes = [POINTER(CsrMatrix), POINTER(Hierarchy), POINTER(Options), c_void_p,
+                                      POINTER(c_void_p)]
+    lib.amgmpcg_setup_csr.restype = c_int32
     lib.amgmpcg_solve.argtypes = [c_void_p, c_void_p, c_void_p, c_double, c_int32, POINTER(Info)]
     lib.amgmpcg_solve_host.argtypes = [c_void_p, POINTER(c_double), POINTER(c_double), c_double, c_int32,
                                        POINTER(Info)]
@@ -215,6 +239,33 @@ class Solver:
         nl, nb = c_int32(), c_int32()
         _check(lib.amgmpcg_level_count(h, byref(nl), byref(nb)))
         self.nb = nb.value
+
+    @classmethod
+    def from_csr(cls, A, prolongations, restrict_scale: float = 1.0, stream=None, **options) -> "Solver":
+        """setup(A, hierarchy) for a general SPD matrix A and prolongations
+        P_l (level l -> l+1, coarsest first; scipy.sparse matrices), with
+        R_l = restrict_scale P_l^T and Galerkin coarse operators."""
+        lib = load()
+        self = cls.__new__(cls)
+        self._lib = lib
+        self.dim, self.nlevels = 0, len(prolongations) + 1
+        self.N = self.n = int(A.shape[0])
+        self._kappa = None
+        keep: list = []
+        a = _csr_struct(A, keep)
+        arr = (CsrMatrix * max(1, len(prolongations)))()
+        for l, P in enumerate(prolongations):
+            arr[l] = _csr_struct(P, keep)
+        H = Hierarchy(self.nlevels, arr if prolongations else None, float(restrict_scale))
+        self.options = default_options(**options)
+        self.stream = _current_stream() if stream is None else stream
+        h = c_void_p()
+        _check(lib.amgmpcg_setup_csr(byref(a), byref(H), byref(self.options), self.stream, byref(h)))
+        self._h = h
+        nl, nb = c_int32(), c_int32()
+        _check(lib.amgmpcg_level_count(h, byref(nl), byref(nb)))
+        self.nb = nb.value
+        return self
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

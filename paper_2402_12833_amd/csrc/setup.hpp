@@ -12,6 +12,7 @@
 #include <stdexcept>
 #include <thread>
 #include <vector>
+#include <utility>
 
 namespace amg {
 namespace host {
@@ -138,6 +139,157 @@ inline bool constant_with_truncation(const StencilLevel& L) {
                     const double want = in ? L.coef[(size_t)s * L.N + ref] : 0.0;
                     if (L.coef[(size_t)s * L.N + idx] != want) return false;
                 }
+    }
+    return true;
+}
+
+// ------------------------------------------------------ sparse hierarchy
+// General hierarchies (Sec. 2.1 with given transfer operators): CSR
+// matrices on the host, Galerkin products R A P by row-wise sparse products.
+
+struct Csr {
+    int n = 0, m = 0;            // rows, columns
+    std::vector<int> ptr, col;   // ptr: n + 1
+    std::vector<double> val;
+    int64_t nnz() const { return (int64_t)col.size(); }
+};
+
+inline Csr csr_transpose(const Csr& A, double scale = 1.0) {
+    Csr T;
+    T.n = A.m;
+    T.m = A.n;
+    T.ptr.assign(T.n + 1, 0);
+    for (int c : A.col) ++T.ptr[c + 1];
+    for (int i = 0; i < T.n; ++i) T.ptr[i + 1] += T.ptr[i];
+    T.col.resize(A.col.size());
+    T.val.resize(A.col.size());
+    std::vector<int> next(T.ptr.begin(), T.ptr.end() - 1);
+    for (int i = 0; i < A.n; ++i)
+        for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+            const int q = next[A.col[k]]++;
+            T.col[q] = i;
+            T.val[q] = scale * A.val[k];
+        }
+    return T;
+}
+
+// C = A B, each row summed in ascending order of A's entries, columns sorted.
+inline Csr csr_multiply(const Csr& A, const Csr& B) {
+    if (A.m != B.n) throw std::invalid_argument("inner dimensions differ");
+    Csr C;
+    C.n = A.n;
+    C.m = B.m;
+    std::vector<std::vector<int>> cols(A.n);
+    std::vector<std::vector<double>> vals(A.n);
+    const int nt = std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t)
+        th.emplace_back([&, t] {
+            std::vector<double> acc(B.m, 0.0);
+            std::vector<char> used(B.m, 0);
+            std::vector<int> list;
+            for (int i = t; i < A.n; i += nt) {
+                list.clear();
+                for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+                    const int j = A.col[k];
+                    const double a = A.val[k];
+                    for (int q = B.ptr[j]; q < B.ptr[j + 1]; ++q) {
+                        const int c = B.col[q];
+                        if (!used[c]) {
+                            used[c] = 1;
+                            acc[c] = 0.0;
+                            list.push_back(c);
+                        }
+                        acc[c] += a * B.val[q];
+                    }
+                }
+                std::sort(list.begin(), list.end());
+                cols[i] = list;
+                vals[i].resize(list.size());
+                for (size_t q = 0; q < list.size(); ++q) {
+                    vals[i][q] = acc[list[q]];
+                    used[list[q]] = 0;
+                }
+            }
+        });
+    for (auto& x : th) x.join();
+    C.ptr.assign(C.n + 1, 0);
+    for (int i = 0; i < C.n; ++i) C.ptr[i + 1] = C.ptr[i] + (int)cols[i].size();
+    C.col.reserve(C.ptr[C.n]);
+    C.val.reserve(C.ptr[C.n]);
+    for (int i = 0; i < C.n; ++i) {
+        C.col.insert(C.col.end(), cols[i].begin(), cols[i].end());
+        C.val.insert(C.val.end(), vals[i].begin(), vals[i].end());
+    }
+    return C;
+}
+
+// Upper triangle (with the diagonal) kept and mirrored: a symmetric matrix.
+inline Csr csr_symmetrise_upper(const Csr& A) {
+    Csr U;
+    U.n = A.n;
+    U.m = A.m;
+    U.ptr.assign(A.n + 1, 0);
+    for (int i = 0; i < A.n; ++i) {
+        for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
+            if (A.col[k] >= i) {
+                U.col.push_back(A.col[k]);
+                U.val.push_back(A.val[k]);
+            }
+        U.ptr[i + 1] = (int)U.col.size();
+    }
+    // mirror: entries (i, j), j > i, also as (j, i)
+    std::vector<std::vector<std::pair<int, double>>> rows(A.n);
+    for (int i = 0; i < U.n; ++i)
+        for (int k = U.ptr[i]; k < U.ptr[i + 1]; ++k) {
+            rows[i].push_back({U.col[k], U.val[k]});
+            if (U.col[k] != i) rows[U.col[k]].push_back({i, U.val[k]});
+        }
+    Csr S;
+    S.n = A.n;
+    S.m = A.m;
+    S.ptr.assign(A.n + 1, 0);
+    for (int i = 0; i < A.n; ++i) {
+        std::sort(rows[i].begin(), rows[i].end());
+        for (auto& e : rows[i]) {
+            S.col.push_back(e.first);
+            S.val.push_back(e.second);
+        }
+        S.ptr[i + 1] = (int)S.col.size();
+    }
+    return S;
+}
+
+// Galerkin coarse operator R A P with R = scale P^T, stored symmetrised.
+inline Csr csr_galerkin(const Csr& A, const Csr& P, double scale) {
+    const Csr AP = csr_multiply(A, P);
+    const Csr R = csr_transpose(P, scale);
+    return csr_symmetrise_upper(csr_multiply(R, AP));
+}
+
+inline std::vector<double> csr_diagonal(const Csr& A) {
+    std::vector<double> d(A.n, 0.0);
+    for (int i = 0; i < A.n; ++i)
+        for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
+            if (A.col[k] == i) d[i] += A.val[k];
+    return d;
+}
+
+// A == A^T up to rtol relative to the largest |a_ij| (same pattern not required).
+inline bool csr_symmetric(const Csr& A, double rtol) {
+    const Csr T = csr_transpose(A);
+    double amax = 0.0;
+    for (double v : A.val) amax = std::max(amax, std::fabs(v));
+    std::vector<double> row(A.m, 0.0);
+    for (int i = 0; i < A.n; ++i) {
+        for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) row[A.col[k]] += A.val[k];
+        for (int k = T.ptr[i]; k < T.ptr[i + 1]; ++k) row[T.col[k]] -= T.val[k];
+        bool ok = true;
+        for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) ok = ok && std::fabs(row[A.col[k]]) <= rtol * amax;
+        for (int k = T.ptr[i]; k < T.ptr[i + 1]; ++k) ok = ok && std::fabs(row[T.col[k]]) <= rtol * amax;
+        for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) row[A.col[k]] = 0.0;
+        for (int k = T.ptr[i]; k < T.ptr[i + 1]; ++k) row[T.col[k]] = 0.0;
+        if (!ok) return false;
     }
     return true;
 }

@@ -115,6 +115,49 @@ def test_stencil_setup_validation(lib):
                                      ctypes.byref(amg.default_options()), None, ctypes.byref(h)) == B.INVALID_ARG
 
 
+def test_csr_setup_validation(lib):
+    """Argument checks of the CSR setup (before any device call)."""
+    import scipy.sparse as sp
+    h = ctypes.c_void_p()
+    A = sp.diags([np.full(8, -1.0), np.full(9, 2.0), np.full(8, -1.0)], [-1, 0, 1]).tocsr()
+    P = sp.csr_matrix((np.ones(9), (np.arange(9), np.arange(9) // 3)), shape=(9, 3))
+
+    def setup(Am, Pm=None, nl=2, scale=1.0, **kw):
+        keep = []
+        a = B._csr_struct(Am, keep)
+        arr = (B.CsrMatrix * 1)()
+        if Pm is not None:
+            arr[0] = B._csr_struct(Pm, keep)
+        H = B.Hierarchy(nl, arr if Pm is not None else None, scale)
+        return lib.amgmpcg_setup_csr(ctypes.byref(a), ctypes.byref(H), ctypes.byref(amg.default_options(**kw)),
+                                     None, ctypes.byref(h))
+
+    nonsym = A.tolil()
+    nonsym[0, 1] = -2.0
+    nan = A.copy()
+    nan.data[3] = np.nan
+    badP = sp.csr_matrix((np.ones(8), (np.arange(8), np.arange(8) // 3)), shape=(8, 3))
+    assert setup(A[:, :8], P) == B.INVALID_ARG                      # not square
+    assert setup(nonsym.tocsr(), P) == B.NOT_SPD                     # not symmetric
+    assert setup(nan, P) == B.NONFINITE
+    assert setup(A, badP) == B.INVALID_ARG                           # P rows != unknowns
+    assert setup(A, P, scale=0.0) == B.INVALID_ARG
+    assert setup(A, None, nl=2) == B.INVALID_ARG                     # prolongations missing
+    assert setup(A, P, method=1) == B.INVALID_ARG
+    keep = []
+    a = B._csr_struct(A, keep)
+    keep[0][3] = 99                                                  # corrupt row pointers
+    H = B.Hierarchy(1, None, 1.0)
+    assert lib.amgmpcg_setup_csr(ctypes.byref(a), ctypes.byref(H), ctypes.byref(amg.default_options()), None,
+                                 ctypes.byref(h)) == B.INVALID_ARG
+    keep = []
+    a = B._csr_struct(A, keep)
+    keep[1][0] = 40                                                  # column out of range
+    assert lib.amgmpcg_setup_csr(ctypes.byref(a), ctypes.byref(H), ctypes.byref(amg.default_options()), None,
+                                 ctypes.byref(h)) == B.INVALID_ARG
+    assert not h.value
+
+
 def test_batched_validation(lib):
     """Argument checks of the batched entry point (before any device call)."""
     h = ctypes.c_void_p()

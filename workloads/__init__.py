@@ -197,3 +197,57 @@ def example1_rhs(elements: int = EXAMPLE1_ELEMENTS, f: float = 1.0) -> np.ndarra
     """Load vector of a constant f on the interior nodes: f h^2 each."""
     h = 1.0 / elements
     return np.full((elements - 1) ** 2, f * h * h)
+
+
+# ------------------------------------------------------ unstructured graph
+# A general sparse SPD problem for the CSR entry point: random points in
+# the unit square, the symmetric k-nearest-neighbour graph with weights
+# 1 / distance^2, A = diag(degree) - W + shift I (shift = 1e-3 x mean degree),
+# and a nested hierarchy of aggregates given by square cells (4 x 4 cells on
+# the coarsest level, twice as many per axis on each finer one; empty cells
+# dropped), prolongations piecewise constant (restrict_scale 1).
+
+
+def graph_problem(npts: int = 20000, seed: int = 7, nlevels: int = 4, k: int = 6):
+    """(A, prolongations coarsest first, b) as scipy.sparse CSR matrices."""
+    import scipy.sparse as sp
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(seed)
+    pts = rng.random((npts, 2))
+    dist, nbr = cKDTree(pts).query(pts, k + 1)
+    rows = np.repeat(np.arange(npts), k)
+    cols = nbr[:, 1:].reshape(-1)
+    w = 1.0 / (dist[:, 1:].reshape(-1) ** 2)
+    W = sp.csr_matrix((w, (rows, cols)), shape=(npts, npts))
+    W = W.maximum(W.T).tocsr()
+    deg = np.asarray(W.sum(axis=1)).reshape(-1)
+    A = (sp.diags(deg + 1e-3 * deg.mean()) - W).tocsr()
+    A.sort_indices()
+    # cell index of every point at each coarse level, coarsest first
+    cells = []
+    for l in range(nlevels - 1):
+        g = 4 * 2 ** l
+        ij = np.minimum((pts * g).astype(np.int64), g - 1)
+        cells.append(ij[:, 0] + g * ij[:, 1])
+    Ps = []
+    # renumber the non-empty cells of each level; a fine unknown (point or
+    # cell) belongs to the cell of the next coarser level containing it
+    ids = []
+    for l in range(nlevels - 1):
+        uniq, inv = np.unique(cells[l], return_inverse=True)
+        ids.append((uniq, inv))
+    for l in range(nlevels - 1):
+        nc = ids[l][0].size
+        if l + 1 < nlevels - 1:
+            # level l+1 cells -> level l cells, through any point of each finer cell
+            uniq_f, inv_f = ids[l + 1]
+            first = np.zeros(uniq_f.size, dtype=np.int64)
+            first[inv_f[::-1]] = np.arange(npts)[::-1]
+            parent = ids[l][1][first]
+            nf = uniq_f.size
+        else:
+            parent = ids[l][1]
+            nf = npts
+        Ps.append(sp.csr_matrix((np.ones(nf), (np.arange(nf), parent)), shape=(nf, nc)))
+    b = rhs(npts, seed + 1)
+    return A, Ps, b
