@@ -134,10 +134,13 @@ __host__ __device__ constexpr int stencil_points() { return DIM == 2 ? 9 : 27; }
 template <int DIM>
 __host__ __device__ constexpr int stencil_center() { return DIM == 2 ? 4 : 13; }
 
-template <int DIM, typename C, typename T, typename F>
-__device__ __forceinline__ C coarse_apply_fn(const CoarseOp<T>& op, int idx, const Idx<DIM>& p,
-                                             F&& value_at) {
-    const int n = op.n, N = op.N;
+// The 3^d taps of a coarse stencil at node idx, weight(s) giving tap s.  A
+// neighbour outside the grid takes weight 0 and the node's own (valid)
+// address, so every load is unconditional and all of them issue at once (a
+// load under a divergent branch waits for the one before it); the zero
+// terms add exactly 0 in the same summation order.
+template <int DIM, typename C, typename W, typename F>
+__device__ __forceinline__ C coarse_taps(int n, int idx, const Idx<DIM>& p, W&& weight, F&& value_at) {
     C acc = C(0);
     int s = 0;
 #pragma unroll
@@ -149,15 +152,25 @@ __device__ __forceinline__ C coarse_apply_fn(const CoarseOp<T>& op, int idx, con
 #pragma unroll
             for (int dx = -1; dx <= 1; ++dx, ++s) {
                 const bool ok = oky && p.i + dx >= 0 && p.i + dx < n;
-                if (ok) {
-                    const int nb = idx + dx + n * (dy + n * dz);
-                    const T w = op.cst ? op.coef[s] : op.coef[(size_t)s * N + idx];
-                    acc += C(w) * value_at(nb);
-                }
+                const int nb = ok ? idx + dx + n * (dy + n * dz) : idx;
+                const C w = C(weight(s));
+                acc += (ok ? w : C(0)) * value_at(nb);
             }
         }
     }
     return acc;
+}
+
+// A_l applied at node idx.  The constant-stencil branch is taken per level
+// (uniform), so its 3^d weights are read once per wave through scalar loads
+// rather than once per lane and tap.
+template <int DIM, typename C, typename T, typename F>
+__device__ __forceinline__ C coarse_apply_fn(const CoarseOp<T>& op, int idx, const Idx<DIM>& p,
+                                             F&& value_at) {
+    const T* __restrict__ coef = op.coef;
+    if (op.cst) return coarse_taps<DIM, C>(op.n, idx, p, [&](int s) -> T { return coef[s]; }, value_at);
+    const int N = op.N;
+    return coarse_taps<DIM, C>(op.n, idx, p, [&](int s) -> T { return coef[(size_t)s * N + idx]; }, value_at);
 }
 
 // --------------------------------------------------------------- transfers
@@ -381,18 +394,25 @@ __device__ __forceinline__ XPar xparents(int f, int nc) {
 template <int DIM, typename T, int S>
 __device__ __forceinline__ void interp_block(const T* __restrict__ Y, int nc, const XPar& px, const Par& py,
                                              const Par& pz, T (&z)[S]) {
+    // Two parents per axis always: a missing second parent takes weight 0
+    // and the first one's address, so all node loads are unconditional and
+    // issue together; the zero terms add exactly 0 in the same order.
 #pragma unroll
     for (int c = 0; c < S; ++c) z[c] = T(0);
-    const int nzc = DIM == 3 ? pz.cnt : 1;
+    constexpr int nzc = DIM == 3 ? 2 : 1;
+#pragma unroll
     for (int cz = 0; cz < nzc; ++cz) {
-        const int K = DIM == 3 ? (cz ? pz.hi : pz.lo) : 0;
-        const T wz = DIM == 3 ? T(cz ? pz.whi : pz.wlo) : T(1);
+        const bool zlo = cz == 0 || pz.cnt < 2;
+        const int K = DIM == 3 ? (zlo ? pz.lo : pz.hi) : 0;
+        const T wz = DIM == 3 ? (cz == 0 ? T(pz.wlo) : (pz.cnt < 2 ? T(0) : T(pz.whi))) : T(1);
         T plane[S];
 #pragma unroll
         for (int c = 0; c < S; ++c) plane[c] = T(0);
-        for (int b = 0; b < py.cnt; ++b) {
-            const int J = b ? py.hi : py.lo;
-            const T wy = T(b ? py.whi : py.wlo);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const bool ylo = b == 0 || py.cnt < 2;
+            const int J = ylo ? py.lo : py.hi;
+            const T wy = b == 0 ? T(py.wlo) : (py.cnt < 2 ? T(0) : T(py.whi));
             const size_t rowbase = (size_t)nc * (J + (size_t)nc * K);
             T lo[S], hi[S];
             load_node<T, S>(Y + (rowbase + px.lo) * S, lo);
