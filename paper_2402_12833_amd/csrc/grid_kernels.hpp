@@ -69,19 +69,58 @@ __device__ __forceinline__ T fine_diag(const FineOp<T>& op, int idx) {
 // (2D constant 9-point stencil), rows dy = -1, 0, 1 in turn.
 template <typename C, typename T, typename F>
 __device__ __forceinline__ C stencil9_apply(const FineOp<T>& op, int i, int j, int idx, F&& u) {
+    // out-of-grid neighbours: weight 0 at the node's own address (loads
+    // unconditional, the zero terms add exactly 0 in the same order)
     const int n = op.n;
     C acc = C(0);
 #pragma unroll
     for (int dy = -1; dy <= 1; ++dy) {
-        if (j + dy < 0 || j + dy >= n) continue;
+        const bool oky = j + dy >= 0 && j + dy < n;
 #pragma unroll
         for (int dx = -1; dx <= 1; ++dx) {
-            if (i + dx < 0 || i + dx >= n) continue;
-            acc += C(op.w9[(dy + 1) * 3 + dx + 1]) * C(u(idx + dx + n * dy));
+            const bool ok = oky && i + dx >= 0 && i + dx < n;
+            const C w = ok ? C(op.w9[(dy + 1) * 3 + dx + 1]) : C(0);
+            acc += w * C(u(ok ? idx + dx + n * dy : idx));
         }
     }
     return acc;
 }
+
+// The 2*DIM face neighbours of a fine node in the order -x, +x, -y, +y, -z,
+// +z: whether each lies inside the grid and its index, the node's own index
+// when it does not (a valid address, so that neighbour loads need no
+// branch: callers weight an outside neighbour by 0, which adds exactly 0).
+template <int DIM>
+struct FaceNbrs {
+    bool ok[2 * DIM];
+    int j[2 * DIM];
+    int self;
+    __device__ __forceinline__ FaceNbrs(const Idx<DIM>& p, int n, int idx) : self(idx) {
+        const int sy = n, sz = n * n;
+        ok[0] = p.i > 0;
+        ok[1] = p.i < n - 1;
+        ok[2] = p.j > 0;
+        ok[3] = p.j < n - 1;
+        j[0] = ok[0] ? idx - 1 : idx;
+        j[1] = ok[1] ? idx + 1 : idx;
+        j[2] = ok[2] ? idx - sy : idx;
+        j[3] = ok[3] ? idx + sy : idx;
+        if constexpr (DIM == 3) {
+            ok[4] = p.k > 0;
+            ok[5] = p.k < n - 1;
+            j[4] = ok[4] ? idx - sz : idx;
+            j[5] = ok[5] ? idx + sz : idx;
+        }
+    }
+    // Face coefficient between the node and neighbour q, stored at the lower
+    // node of the face: the neighbour for -x/-y/-z, the node itself for
+    // +x/+y/+z (for an outside neighbour a valid address, weighted 0).
+    template <typename Op>
+    __device__ __forceinline__ auto face(const Op& op, int q) const {
+        const auto* e = q < 2 ? op.ex : (q < 4 ? op.ey : op.ez);
+        return e[(q & 1) ? self : j[q]];
+    }
+};
 
 // 1 / D, precomputed: the smoother multiplies by it instead of dividing.
 template <int DIM, typename T>
@@ -96,27 +135,16 @@ __device__ __forceinline__ C fine_apply(const FineOp<T>& op, const U* __restrict
     const int n = op.n;
     const int sy = n, sz = n * n;
     if (DIM == 2 && op.k9) return stencil9_apply<C, T>(op, p.i, p.j, idx, [&](int q) { return u[q]; });
+    const FaceNbrs<DIM> f(p, n, idx);
     if (!op.D) {
         C acc = C(2 * DIM) * C(u[idx]);
-        if (p.i > 0) acc -= C(u[idx - 1]);
-        if (p.i < n - 1) acc -= C(u[idx + 1]);
-        if (p.j > 0) acc -= C(u[idx - sy]);
-        if (p.j < n - 1) acc -= C(u[idx + sy]);
-        if (DIM == 3) {
-            if (p.k > 0) acc -= C(u[idx - sz]);
-            if (p.k < n - 1) acc -= C(u[idx + sz]);
-        }
+#pragma unroll
+        for (int q = 0; q < 2 * DIM; ++q) acc -= (f.ok[q] ? C(1) : C(0)) * C(u[f.j[q]]);
         return C(op.s0) * acc;
     }
     C acc = C(op.D[idx]) * C(u[idx]);
-    if (p.i > 0) acc -= C(op.ex[idx - 1]) * C(u[idx - 1]);
-    if (p.i < n - 1) acc -= C(op.ex[idx]) * C(u[idx + 1]);
-    if (p.j > 0) acc -= C(op.ey[idx - sy]) * C(u[idx - sy]);
-    if (p.j < n - 1) acc -= C(op.ey[idx]) * C(u[idx + sy]);
-    if (DIM == 3) {
-        if (p.k > 0) acc -= C(op.ez[idx - sz]) * C(u[idx - sz]);
-        if (p.k < n - 1) acc -= C(op.ez[idx]) * C(u[idx + sz]);
-    }
+#pragma unroll
+    for (int q = 0; q < 2 * DIM; ++q) acc -= (f.ok[q] ? C(f.face(op, q)) : C(0)) * C(u[f.j[q]]);
     return acc;
 }
 
@@ -726,28 +754,19 @@ __device__ __forceinline__ T fine_smooth_at(const FineOp<T>& op, const G* __rest
     T Ac;
     if (DIM == 2 && op.k9) {
         Ac = stencil9_apply<T, T>(op, p.i, p.j, idx, c1at);
-    } else if (!op.D) {
-        T acc = T(2 * DIM) * c1;
-        if (p.i > 0) acc -= c1at(idx - 1);
-        if (p.i < n - 1) acc -= c1at(idx + 1);
-        if (p.j > 0) acc -= c1at(idx - sy);
-        if (p.j < n - 1) acc -= c1at(idx + sy);
-        if (DIM == 3) {
-            if (p.k > 0) acc -= c1at(idx - sz);
-            if (p.k < n - 1) acc -= c1at(idx + sz);
-        }
-        Ac = op.s0 * acc;
     } else {
-        T acc = op.D[idx] * c1;
-        if (p.i > 0) acc -= op.ex[idx - 1] * c1at(idx - 1);
-        if (p.i < n - 1) acc -= op.ex[idx] * c1at(idx + 1);
-        if (p.j > 0) acc -= op.ey[idx - sy] * c1at(idx - sy);
-        if (p.j < n - 1) acc -= op.ey[idx] * c1at(idx + sy);
-        if (DIM == 3) {
-            if (p.k > 0) acc -= op.ez[idx - sz] * c1at(idx - sz);
-            if (p.k < n - 1) acc -= op.ez[idx] * c1at(idx + sz);
+        const FaceNbrs<DIM> f(p, n, idx);
+        if (!op.D) {
+            T acc = T(2 * DIM) * c1;
+#pragma unroll
+            for (int q = 0; q < 2 * DIM; ++q) acc -= (f.ok[q] ? T(1) : T(0)) * c1at(f.j[q]);
+            Ac = op.s0 * acc;
+        } else {
+            T acc = op.D[idx] * c1;
+#pragma unroll
+            for (int q = 0; q < 2 * DIM; ++q) acc -= (f.ok[q] ? f.face(op, q) : T(0)) * c1at(f.j[q]);
+            Ac = acc;
         }
-        Ac = acc;
     }
     return c1 + omega * ((gi - Ac) * iDi);
 }
