@@ -836,6 +836,10 @@ class Solver : public SolverBase {
     // Without a network the fork costs more than it overlaps (measured), and
     // while profiling every kernel is timed alone: serial.
     void enqueue_mg(const Ctl* ctl, const double* r) {
+        if (fused_mg()) {
+            enqueue_mg_fused(ctl, r);
+            return;
+        }
         if (prof_on_ || !side_ || !net_) {
             enqueue_fine(ctl, r);
             enqueue_coarse(ctl, r);
@@ -855,6 +859,72 @@ class Solver : public SolverBase {
         HIPCHK(hipEventRecord(ev_join_, side_));
         enqueue_coarse(ctl, r);
         HIPCHK(hipStreamWaitEvent(stream_, ev_join_, 0));
+    }
+
+    // With nu <= 2 and no network the chain runs in fused launches: the
+    // finest smoother beside the first restriction, the smoother of each
+    // restricted level beside the next restriction, the smallest levels'
+    // restrictions and smoothers in the tail launch (the kernels' arithmetic
+    // is that of the separate launches, so the results are the same).
+    bool fused_mg() const { return L_ > 0 && opt_.nu <= 2 && !net_; }
+
+    SmoothLevel<T> smooth_level(int l) const {
+        SmoothLevel<T> sm;
+        sm.op = CoarseOp<T>{n_axis[l], N_[l], coef_[l].p, cst_[l]};
+        sm.g = g_[l].p;
+        sm.c1 = c1_[l].p;
+        sm.out = Y_[l].p + l;
+        sm.stride = even_up(l + 1);
+        return sm;
+    }
+
+    void enqueue_mg_fused(const Ctl* ctl, const double* r) {
+        const int L = L_;
+        const T omega = T(opt_.omega);
+        const int two = opt_.nu >= 2 ? 1 : 0;
+        mark(kSecRestrict);
+        {
+            const int l = L - 1;
+            const RestrictStep<double, T> rs{r, n_axis[L], g_[l].p, n_axis[l], N_[l], diag(l), c1_[l].p, cst_[l]};
+            const int nbr = ((N_[l] + kBlock - 1) / kBlock + kNumXcd - 1) / kNumXcd * kNumXcd;
+            k_restrict_fine_smooth<DIM, T><<<nbr + FB_, kBlock, 0, stream_>>>(ctl, rs, nbr, rows_, fop_, r, cL_.p,
+                                                                            omega, two);
+            cL_final_ = cL_.p;
+        }
+        int m = L - 2;
+        for (; m >= 0 && N_[m] > kRestrictTailMax; --m) {
+            const RestrictStep<T, T> rs{g_[m + 1].p, n_axis[m + 1], g_[m].p, n_axis[m], N_[m], diag(m), c1_[m].p,
+                                        cst_[m]};
+            const int nbr = (N_[m] + kBlock - 1) / kBlock;
+            const int nbs = (N_[m + 1] + kBlock - 1) / kBlock;
+            k_restrict_coarse_smooth<DIM, T><<<nbr + nbs, kBlock, 0, stream_>>>(ctl, rs, nbr, smooth_level(m + 1),
+                                                                              omega, two);
+        }
+        // level m+1 is restricted but not yet smoothed; levels m..0 are small
+        if (m >= 0) {
+            RestrictChain<T> ch{};
+            SmoothChain<T> sc{};
+            for (int q = m; q >= 0; --q) {
+                const int c = ch.count++;
+                ch.nf[c] = n_axis[q + 1];
+                ch.nc[c] = n_axis[q];
+                ch.Nc[c] = N_[q];
+                ch.gf[c] = g_[q + 1].p;
+                ch.gc[c] = g_[q].p;
+                ch.D[c] = diag(q);
+                ch.dconst[c] = cst_[q];
+                ch.c1[c] = c1_[q].p;
+                sc.lev[sc.count++] = smooth_level(q);
+            }
+            const int nbt = (N_[m + 1] + kTailBlock - 1) / kTailBlock;
+            k_tail_smooth<DIM, T><<<1 + nbt, kTailBlock, 0, stream_>>>(ctl, ch, sc, smooth_level(m + 1), omega, two);
+        } else {
+            const int nbs = (N_[0] + kBlock - 1) / kBlock;
+            k_restrict_coarse_smooth<DIM, T><<<nbs, kBlock, 0, stream_>>>(ctl, RestrictStep<T, T>{}, 0,
+                                                                        smooth_level(0), omega, two);
+        }
+        mark(kSecProlong);
+        enqueue_prolong(ctl);
     }
 
     // the finest level's smoother output cL_final_ (nu sweeps from zero)
@@ -940,8 +1010,13 @@ class Solver : public SolverBase {
                 }
             }
         }
-        // prolongation chain Y_{l+1}[:, 0..l] = P Y_l: small levels in one block
         mark(kSecProlong);
+        enqueue_prolong(ctl);
+    }
+
+    // prolongation chain Y_{l+1}[:, 0..l] = P Y_l: small levels in one block
+    void enqueue_prolong(const Ctl* ctl) {
+        const int L = L_;
         {
             int l = 0;
             ProlongChain<T> ch{};

@@ -367,11 +367,13 @@ struct Band {
     int start, end, stride;
 };
 
-__device__ __forceinline__ Band row_band(int total) {
-    const int g = gridDim.x;
-    const int x = (g % kNumXcd) ? 0 : (int)blockIdx.x % kNumXcd;
+// The band of block bid in a walk by g blocks (a launch's own blocks, or a
+// block range of a launch that starts at a multiple of 8, which keeps every
+// block on the XCD its index names).
+__device__ __forceinline__ Band row_band_of(int total, int bid, int g) {
+    const int x = (g % kNumXcd) ? 0 : bid % kNumXcd;
     const int nb = (g % kNumXcd) ? g : g / kNumXcd;
-    const int j = (g % kNumXcd) ? (int)blockIdx.x : (int)blockIdx.x / kNumXcd;
+    const int j = (g % kNumXcd) ? bid : bid / kNumXcd;
     const int slabs = (g % kNumXcd) ? 1 : kNumXcd;
     const int per = ((total + slabs - 1) / slabs + kBlock - 1) / kBlock * kBlock;
     Band b;
@@ -380,6 +382,8 @@ __device__ __forceinline__ Band row_band(int total) {
     b.stride = nb * kBlock;
     return b;
 }
+
+__device__ __forceinline__ Band row_band(int total) { return row_band_of(total, (int)blockIdx.x, (int)gridDim.x); }
 
 // lb: the block's index for its reduction partials (unused by the walk).
 #define ROW_LOOP(R, lb)                                                                           \
@@ -983,6 +987,121 @@ __global__ void __launch_bounds__(kTailBlock) k_prolong_head(const Ctl* __restri
         }
         __syncthreads();
     }
+}
+
+// --------------------------------------------- fused launches of the chain
+//
+// With nu <= 2 the additive levels leave much of the restriction/smoothing
+// chain independent: the finest smoother and the first restriction read only
+// r, and the smoother of level m+1 reads only what the restriction into
+// m+1 wrote, as does the restriction m+1 -> m.  Each launch below runs one
+// restriction in its first nbr blocks and one such smoother pass in the
+// blocks after them, so their latencies overlap and the separate smoothing
+// launches disappear.  The arithmetic is that of k_restrict, k_fine_smooth
+// and k_coarse_smooth.
+
+template <typename TI, typename T>
+struct RestrictStep {
+    const TI* gf;
+    int nf;
+    T* gc;
+    int nc, Nc;
+    const T* D;
+    T* c1;
+    int dconst;
+};
+
+// The first min(nu, 2) sweeps of one coarse level from zero, into out[i * stride].
+template <typename T>
+struct SmoothLevel {
+    CoarseOp<T> op;
+    const T* g;
+    const T* c1;
+    T* out;
+    int stride;
+};
+
+template <int DIM, typename TI, typename T>
+__device__ __forceinline__ void restrict_step(const RestrictStep<TI, T>& rs, int idx, T omega) {
+    const T g = restrict_at<DIM, TI, T>(rs.gf, rs.nf, rs.nc, idx);
+    rs.gc[idx] = g;
+    rs.c1[idx] = omega * (g / rs.D[rs.dconst ? 0 : idx]);
+}
+
+template <int DIM, typename T>
+__device__ __forceinline__ void smooth_level_at(const SmoothLevel<T>& sm, int idx, T omega, int two) {
+    sm.out[(size_t)idx * sm.stride] = coarse_smooth_at<DIM, T>(sm.op, sm.g, sm.c1, nullptr, idx, omega, 0, two);
+}
+
+// Blocks [0, nbr): restriction r -> level L-1.  Blocks [nbr, grid): the
+// finest smoother over the row walk of grid - nbr blocks (nbr is a multiple
+// of 8, so the rows keep their XCD bands).
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kBlock) k_restrict_fine_smooth(const Ctl* __restrict__ ctl,
+                                                                 RestrictStep<double, T> rs, int nbr, Rows R,
+                                                                 FineOp<T> op, const double* __restrict__ r,
+                                                                 T* __restrict__ c, T omega, int two) {
+    if (ctl->state != 0) return;
+    if ((int)blockIdx.x < nbr) {
+        const int idx = blockIdx.x * kBlock + threadIdx.x;
+        if (idx < rs.Nc) restrict_step<DIM>(rs, idx, omega);
+        return;
+    }
+    const Band b = row_band_of(R.total, (int)blockIdx.x - nbr, (int)gridDim.x - nbr);
+    for (int w = b.start; w < b.end; w += b.stride) {
+        Idx<DIM> p;
+        int idx;
+        if (!row_item<DIM>(R, w, p, idx)) continue;
+        c[idx] = fine_smooth_at<DIM, T, double>(op, r, idx, p, omega, two);
+    }
+}
+
+// Blocks [0, nbr): restriction level m+1 -> m (nbr = 0: none).  Blocks
+// [nbr, grid): the smoother of level m+1, one thread per node.
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kBlock) k_restrict_coarse_smooth(const Ctl* __restrict__ ctl,
+                                                                   RestrictStep<T, T> rs, int nbr,
+                                                                   SmoothLevel<T> sm, T omega, int two) {
+    if (ctl->state != 0) return;
+    if ((int)blockIdx.x < nbr) {
+        const int idx = blockIdx.x * kBlock + threadIdx.x;
+        if (idx < rs.Nc) restrict_step<DIM>(rs, idx, omega);
+        return;
+    }
+    const int idx = ((int)blockIdx.x - nbr) * kBlock + threadIdx.x;
+    if (idx < sm.op.N) smooth_level_at<DIM>(sm, idx, omega, two);
+}
+
+// Block 0: the restriction chain into the small levels, one level after the
+// other, then the smoother of every small level.  Blocks 1..: the smoother of
+// the level the chain starts from.
+template <typename T>
+struct SmoothChain {
+    int count;
+    SmoothLevel<T> lev[kMaxLevels];
+};
+
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kTailBlock) k_tail_smooth(const Ctl* __restrict__ ctl, RestrictChain<T> ch,
+                                                            SmoothChain<T> small, SmoothLevel<T> top, T omega,
+                                                            int two) {
+    if (ctl->state != 0) return;
+    if (blockIdx.x > 0) {
+        const int idx = ((int)blockIdx.x - 1) * kTailBlock + threadIdx.x;
+        if (idx < top.op.N) smooth_level_at<DIM>(top, idx, omega, two);
+        return;
+    }
+    for (int m = 0; m < ch.count; ++m) {
+        for (int idx = threadIdx.x; idx < ch.Nc[m]; idx += kTailBlock) {
+            const T g = restrict_at<DIM, T, T>(ch.gf[m], ch.nf[m], ch.nc[m], idx);
+            ch.gc[m][idx] = g;
+            ch.c1[m][idx] = omega * (g / ch.D[m][ch.dconst[m] ? 0 : idx]);
+        }
+        __syncthreads();
+    }
+    for (int q = 0; q < small.count; ++q)
+        for (int idx = threadIdx.x; idx < small.lev[q].op.N; idx += kTailBlock)
+            smooth_level_at<DIM>(small.lev[q], idx, omega, two);
 }
 
 // W = Q_k^T Z_{k+1} partial sums (NB x NB, entry a*NB+c = Q column a . z^c).
