@@ -172,6 +172,7 @@ class Solver : public SolverBase {
         rows_.total = (int)host::ipow(g.n, DIM - 1) * rows_.nxp;
         FB_ = fine_blocks(rows_.total);
         FBG_ = fine_blocks(rows_.total, kGramBlocks);
+        XPB_ = fine_blocks(rows_.total, xp_blocks_per_cu<1>() * kNumCU);
         if (DIM == 3) {
             // z chunks so that the units fill the resident blocks (2 or 3 per
             // CU) about once
@@ -449,7 +450,7 @@ class Solver : public SolverBase {
         dispatch_plain([&](auto nbc) {
             constexpr int NB = decltype(nbc)::value;
             const int nc = L_ > 0 ? n_axis[L_ - 1] : 1;
-            k_update_xP<DIM, T, NB, 0><<<FB_, kBlock, 0, s>>>(ctl_proj_, rows_, fine_Y(), nc, cL_final_, nullptr,
+            k_update_xP<DIM, T, NB, 0><<<xp_grid<NB>(), kBlock, 0, s>>>(ctl_proj_, rows_, fine_Y(), nc, cL_final_, nullptr,
                                                                nullptr, single(), 1, 0, 0, x_.p, d_alpha(), d_beta(),
                                                                1);
             launch_spmm<NB>(ctl_proj_, P_.p, Q_.p, r_dev, s);
@@ -657,7 +658,7 @@ class Solver : public SolverBase {
                                                                       Q_.p, part_W());
             });
             timed([&] {
-                k_update_xP<DIM, T, NB, NE><<<FB_, kBlock, 0, stream_>>>(cf, rows_, fine_Y(), nc, cL_final_, dl(),
+                k_update_xP<DIM, T, NB, NE><<<xp_grid<NB>(), kBlock, 0, stream_>>>(cf, rows_, fine_Y(), nc, cL_final_, dl(),
                                                                          dflag(), single(), 1, 0, 0, x_.p,
                                                                          d_alpha(), d_beta(), 0);
             });
@@ -1042,6 +1043,13 @@ class Solver : public SolverBase {
     // Q = A P and the Gram partials (spmm_blocks<NB>() partial rows at
     // part_G()): z-marching on 3D grids for blocks of <= 48 bytes per node,
     // row-mapped otherwise.
+    // grid of the x/P update: one round of its resident blocks (5 per CU up
+    // to 6 columns; wider blocks keep the fine grid)
+    template <int NB>
+    int xp_grid() const {
+        return xp_blocks_per_cu<NB>() == xp_blocks_per_cu<1>() ? XPB_ : FB_;
+    }
+
     template <int NB>
     int spmm_blocks() const {
         if constexpr (DIM == 3 && zt_fits<T, NB>()) return SB_[zvar<NB>()];
@@ -1105,7 +1113,7 @@ class Solver : public SolverBase {
             constexpr int NB = decltype(nbc)::value;
             [[maybe_unused]] constexpr int NE = decltype(nbc)::ne;
             const int nc = L_ > 0 ? n_axis[L_ - 1] : 1;
-            k_update_xP<DIM, T, NB, NE><<<FB_, kBlock, 0, stream_>>>(ctl_, rows_, fine_Y(), nc, cL_final_, dl(),
+            k_update_xP<DIM, T, NB, NE><<<xp_grid<NB>(), kBlock, 0, stream_>>>(ctl_, rows_, fine_Y(), nc, cL_final_, dl(),
                                                                        dflag(), window(), m_, 0, 0, x_.p, d_alpha(),
                                                                        d_beta(), 1);
             launch_spmm<NB>(ctl_, Pslot(0), Qslot(0), r_.p, stream_);
@@ -1142,7 +1150,7 @@ class Solver : public SolverBase {
                                                    d_Gplus(0), d_beta(0), hist_cap_ ? rhist_.p : nullptr,
                                                    mixed_ ? 1 : 0);
             mark(kSecUpdateXP);
-            k_update_xP<DIM, T, NB, NE><<<FB_, kBlock, 0, s>>>(ctl_, rows_, fine_Y(), nc, cL_final_, dl(), dflag(),
+            k_update_xP<DIM, T, NB, NE><<<xp_grid<NB>(), kBlock, 0, s>>>(ctl_, rows_, fine_Y(), nc, cL_final_, dl(), dflag(),
                                                             window(), m_, cur, nxt, x_.p, d_alpha(), d_beta(0), 0);
             if (mixed_) {
                 mark(kSecRefresh);
@@ -1389,7 +1397,7 @@ class Solver : public SolverBase {
     hipGraphExec_t exec_ = nullptr;
     bool graph_ready_ = false;
     bool mixed_ = false;
-    int L_ = 0, FB_ = 1, FBG_ = 1, hist_cap_ = 0, last_iters_ = 0;
+    int L_ = 0, FB_ = 1, FBG_ = 1, XPB_ = 1, hist_cap_ = 0, last_iters_ = 0;
     int method_ = AMGMPCG_METHOD_MPCG, vnu_ = 1;   // solution method; V-cycle sweeps per side
     // z-marching SpMM: x tiles; per resident-block count (2, 3): planes per
     // unit, z chunks, units (= blocks)
