@@ -156,7 +156,10 @@ __device__ __forceinline__ void reduce_beta_body(Ctl* ctl, const double* part_rh
                                                  const double* part_Wall, int nblk_W, int nwin, int cur,
                                                  const double* Gplus_all, double* beta_all, double* rhist,
                                                  int mixed) {
-    if (ctl->state != 0) return;
+    // the state is tested after the reduction, so that its load and the
+    // partial loads are in flight together (the partials are valid memory
+    // whatever the state; with a stopped solve the sums are discarded)
+    const int state = ctl->state;
     // slot j of W partials / G^+ / beta: part_Wall + j kMaxNB^2 nblk_W, + j kMaxNB^2
     const double* part_W = part_Wall + (size_t)cur * kMaxNB * kMaxNB * nblk_W;
     const double* Gplus = Gplus_all + (size_t)cur * kMaxNB * kMaxNB;
@@ -178,6 +181,7 @@ __device__ __forceinline__ void reduce_beta_body(Ctl* ctl, const double* part_rh
         reduce_partials<1>(part_rho, nblk_rho, rho_s);
         reduce_partials<NB * NB>(part_W, nblk_W, W);
     }
+    if (state != 0) return;
     __shared__ int stop;
     if (threadIdx.x == 0) {
         const double rho = rho_s[0];
@@ -238,18 +242,20 @@ __global__ void __launch_bounds__(kRedBlock) k_reduce_beta(Ctl* ctl, const doubl
 template <int NB>
 __device__ __forceinline__ void reduce_alpha_body(Ctl* ctl, const double* part, int nblk, double* Gplus,
                                                   double* alpha, double* ahist) {
+    // the state is tested after the reduction, so that its load and the
+    // partial loads are in flight together (see reduce_beta_body)
     const int state = ctl->state;
-    if (state == 2) return;
-    if (state == 1) {
-        if (threadIdx.x == 0) ctl->state = 2;
-        return;
-    }
     constexpr int NG = NB * (NB + 1) / 2;
     __shared__ double red[NG + NB];
     __shared__ double G[NB * NB];
     __shared__ double Gp[NB * NB];
     __shared__ int rank_s;
     reduce_partials<NG + NB>(part, nblk, red);
+    if (state == 2) return;
+    if (state == 1) {
+        if (threadIdx.x == 0) ctl->state = 2;
+        return;
+    }
     if (threadIdx.x == 0) {
         int q = 0;
         for (int a = 0; a < NB; ++a)
