@@ -237,6 +237,17 @@ int amgmpcg_solve_batched(amgmpcg_handle* h, const double* b_dev, double* x_dev,
 /* Number of problems and total unknowns of a batched handle. */
 int amgmpcg_batched_size(const amgmpcg_handle* h, int32_t* count, int64_t* total_dofs);
 
+/* Device memory a handle (of any setup) holds: the bytes of the buffers its
+ * setup allocated (level operators and transfers, vectors, direction
+ * blocks and their rings, partial sums, history) and those that attaching a
+ * network added (the wider direction blocks), not counting a few hundred
+ * bytes of control words and the captured iteration graph.  The handle owns
+ * this memory until amgmpcg_destroy; a solve allocates nothing except on a
+ * handle's first solve, which captures the iteration graph.  The network's
+ * own buffers belong to the network.  Errors: INVALID_ARG for a NULL handle
+ * or output pointer. */
+int amgmpcg_workspace_bytes(const amgmpcg_handle* h, int64_t* bytes);
+
 /* Measurement aid: average duration in ms of each hot kernel of one
  * iteration, each launched reps times back to back between two HIP events
  * on the handle's stream, on the state left by the last solve (call it after

@@ -124,6 +124,8 @@ def load(path: str = LIB_PATH):
     lib.amgmpcg_solve_batched.restype = c_int32
     lib.amgmpcg_batched_size.argtypes = [c_void_p, POINTER(c_int32), POINTER(ctypes.c_int64)]
     lib.amgmpcg_batched_size.restype = c_int32
+    lib.amgmpcg_workspace_bytes.argtypes = [c_void_p, POINTER(ctypes.c_int64)]
+    lib.amgmpcg_workspace_bytes.restype = c_int32
     lib.amgmpcg_gram_pinv.argtypes = [POINTER(c_double), c_int32, c_double, POINTER(c_double), POINTER(c_int32)]
     lib.amgmpcg_gram_pinv.restype = c_int32
     lib.amgmpcg_destroy.argtypes = [c_void_p]
@@ -336,6 +338,12 @@ class Solver:
                                              int(bool(marginal)), c_void_p(g.data_ptr()), byref(loss)))
         return loss.value, g
 
+    def workspace_bytes(self) -> int:
+        """Device bytes the handle's buffers take (allocated at setup)."""
+        v = ctypes.c_int64()
+        _check(self._lib.amgmpcg_workspace_bytes(self._h, byref(v)))
+        return v.value
+
     def attach(self, net: Optional["Network"]):
         """Append the network's output as one more search direction (None removes it)."""
         _check(self._lib.amgmpcg_attach_cnn(self._h, None if net is None else net._h))
@@ -448,6 +456,12 @@ class BatchedSolver:
             self.close()
         except Exception:
             pass
+
+    def workspace_bytes(self) -> int:
+        """Device bytes the handle's buffers take (allocated at setup)."""
+        v = ctypes.c_int64()
+        _check(self._lib.amgmpcg_workspace_bytes(self._h, byref(v)))
+        return v.value
 
     def solve(self, b, x=None, tol: float = 1e-8, maxit: int = 0):
         """b, x: contiguous float64 device tensors of all problems concatenated.

@@ -58,6 +58,10 @@ constexpr int kTailMax = 4096;          // prolongation outputs up to this size:
 constexpr int kRestrictTailMax = 512;   // restriction outputs up to this size: single-block chain
 constexpr int kPartRow = 2 + 1 + kMaxNB * kMaxNB + (kMaxNB * (kMaxNB + 1) / 2 + kMaxNB) + 1;
 
+// Device bytes held by the DevBufs of this thread (a handle's footprint is
+// the difference across its construction).
+thread_local int64_t g_devbuf_bytes = 0;
+
 template <typename T>
 struct DevBuf {
     T* p = nullptr;
@@ -67,9 +71,13 @@ struct DevBuf {
         if (count == 0) return;
         HIPCHK(hipMalloc((void**)&p, count * sizeof(T)));
         n = count;
+        g_devbuf_bytes += (int64_t)(count * sizeof(T));
     }
     void free() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            (void)hipFree(p);
+            g_devbuf_bytes -= (int64_t)(n * sizeof(T));
+        }
         p = nullptr;
         n = 0;
     }
@@ -2199,6 +2207,7 @@ class BatchedSolver : public BatchedBase {
 struct amgmpcg_handle {
     std::unique_ptr<amg::SolverBase> s;
     std::unique_ptr<amg::BatchedBase> bs;
+    int64_t bytes = 0;   // device buffers allocated at setup and by attach
 };
 
 struct amgmpcg_cnn {
@@ -2291,6 +2300,7 @@ int amgmpcg_setup_grid(const amgmpcg_grid* grid, const amgmpcg_options* opts, vo
         validate_grid(grid);
         validate_options(opts);
         auto h = std::make_unique<amgmpcg_handle>();
+        const int64_t bytes0 = amg::g_devbuf_bytes;
         hipStream_t s = (hipStream_t)stream;
         if (opts->precision == 0) {
             if (grid->dim == 2) h->s.reset(new amg::Solver<double, 2>(*grid, *opts, s));
@@ -2299,6 +2309,7 @@ int amgmpcg_setup_grid(const amgmpcg_grid* grid, const amgmpcg_options* opts, vo
             if (grid->dim == 2) h->s.reset(new amg::Solver<float, 2>(*grid, *opts, s));
             else h->s.reset(new amg::Solver<float, 3>(*grid, *opts, s));
         }
+        h->bytes = amg::g_devbuf_bytes - bytes0;
         *out = h.release();
         return AMGMPCG_OK;
     });
@@ -2349,9 +2360,11 @@ int amgmpcg_setup_csr(const amgmpcg_csr* A, const amgmpcg_hierarchy* H, const am
             rows = Ps[l].m;
         }
         auto h = std::make_unique<amgmpcg_handle>();
+        const int64_t bytes0 = amg::g_devbuf_bytes;
         hipStream_t s = (hipStream_t)stream;
         if (opts->precision == 0) h->s.reset(new amg::CsrSolver<double>(Ah, Ps, H->restrict_scale, *opts, s));
         else h->s.reset(new amg::CsrSolver<float>(Ah, Ps, H->restrict_scale, *opts, s));
+        h->bytes = amg::g_devbuf_bytes - bytes0;
         *out = h.release();
         return AMGMPCG_OK;
     });
@@ -2373,9 +2386,11 @@ int amgmpcg_setup_stencil(const amgmpcg_grid* grid, const double* stencil, const
         }
         if (!(stencil[4] > 0.0)) throw ApiError(AMGMPCG_NOT_SPD, "non-positive stencil centre");
         auto h = std::make_unique<amgmpcg_handle>();
+        const int64_t bytes0 = amg::g_devbuf_bytes;
         hipStream_t s = (hipStream_t)stream;
         if (opts->precision == 0) h->s.reset(new amg::Solver<double, 2>(*grid, *opts, s, stencil));
         else h->s.reset(new amg::Solver<float, 2>(*grid, *opts, s, stencil));
+        h->bytes = amg::g_devbuf_bytes - bytes0;
         *out = h.release();
         return AMGMPCG_OK;
     });
@@ -2513,6 +2528,7 @@ int amgmpcg_setup_batched(int32_t count, const amgmpcg_grid* grids, const amgmpc
         if (opts->m != 1 || opts->method != AMGMPCG_METHOD_MPCG)
             throw ApiError(AMGMPCG_INVALID_ARG, "batched solves use the MPCG method with m = 1");
         auto h = std::make_unique<amgmpcg_handle>();
+        const int64_t bytes0 = amg::g_devbuf_bytes;
         hipStream_t s = (hipStream_t)stream;
         if (opts->precision == 0) {
             if (dim == 2) h->bs.reset(new amg::BatchedSolver<double, 2>(count, grids, *opts, s));
@@ -2521,6 +2537,7 @@ int amgmpcg_setup_batched(int32_t count, const amgmpcg_grid* grids, const amgmpc
             if (dim == 2) h->bs.reset(new amg::BatchedSolver<float, 2>(count, grids, *opts, s));
             else h->bs.reset(new amg::BatchedSolver<float, 3>(count, grids, *opts, s));
         }
+        h->bytes = amg::g_devbuf_bytes - bytes0;
         *out = h.release();
         return AMGMPCG_OK;
     });
@@ -2533,6 +2550,15 @@ int amgmpcg_solve_batched(amgmpcg_handle* h, const double* b_dev, double* x_dev,
         if (!b_dev || !x_dev) throw ApiError(AMGMPCG_INVALID_ARG, "b or x is NULL");
         if (!(tol >= 0.0) || !std::isfinite(tol)) throw ApiError(AMGMPCG_INVALID_ARG, "tol must be finite and >= 0");
         return h->bs->solve(b_dev, x_dev, tol, maxit, infos, batch_ms);
+    });
+}
+
+int amgmpcg_workspace_bytes(const amgmpcg_handle* h, int64_t* bytes) {
+    return guarded([&]() -> int {
+        if (!h || (!h->s && !h->bs)) throw ApiError(AMGMPCG_INVALID_ARG, "handle is NULL");
+        if (!bytes) throw ApiError(AMGMPCG_INVALID_ARG, "bytes is NULL");
+        *bytes = h->bytes;
+        return AMGMPCG_OK;
     });
 }
 
@@ -2776,7 +2802,9 @@ void amgmpcg_cnn_destroy(amgmpcg_cnn* net) { delete net; }
 int amgmpcg_attach_cnn(amgmpcg_handle* h, amgmpcg_cnn* net) {
     return guarded([&]() -> int {
         if (!h || !h->s) throw ApiError(AMGMPCG_INVALID_ARG, "handle is NULL");
+        const int64_t bytes0 = amg::g_devbuf_bytes;
         h->s->attach(net ? &net->net : nullptr);
+        h->bytes += amg::g_devbuf_bytes - bytes0;
         return AMGMPCG_OK;
     });
 }

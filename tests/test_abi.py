@@ -81,6 +81,8 @@ def test_null_arguments(lib):
     info = B.Info()
     assert lib.amgmpcg_solve(None, None, None, 1e-8, 0, ctypes.byref(info)) == B.INVALID_ARG
     assert lib.amgmpcg_mg_block(None, None, None) == B.INVALID_ARG
+    v = ctypes.c_int64(-1)
+    assert lib.amgmpcg_workspace_bytes(None, ctypes.byref(v)) == B.INVALID_ARG and v.value == -1
     lib.amgmpcg_destroy(None)
 
 

@@ -140,6 +140,7 @@ def test_csr_matches_structured_path():
 def test_csr_handle_restrictions():
     A, Ps, scale, b = graph_case(500, 13, 2)
     s = amg.Solver.from_csr(A, Ps, scale)
+    assert s.workspace_bytes() > A.nnz * 12
     with pytest.raises(amg.AmgMpcgError):
         s.level_stencil(0)
     s.close()

@@ -208,6 +208,22 @@ def test_deterministic_bitwise():
     s.close()
 
 
+def test_workspace_bytes():
+    """The truncation window's rings are the only buffers that depend on m:
+    two rings (P and Q) of m slots, each N * even_up(b) values rounded up to
+    64 values, so m = 5 holds exactly 8 slots more than m = 1."""
+    n, nl = 31, 4
+    N = n ** 3
+    slot_bytes = (4 * N + 63) // 64 * 64 * 8
+    w = {}
+    for m in (1, 5):
+        s = amg.Solver(3, n, nl, m=m)
+        w[m] = s.workspace_bytes()
+        s.close()
+    assert w[5] - w[1] == 2 * 4 * slot_bytes, w
+    assert w[1] > 2 * slot_bytes + 3 * N * 8
+
+
 @pytest.mark.parametrize("case", [(2, 31, 4, None, 1), (3, 31, 4, None, 17), (3, 31, 4, 3, 18)], ids=case_id)
 def test_mixed_precision_reaches_tolerance(case):
     dim, n, nl, ks, seed = case
