@@ -873,8 +873,9 @@ class Solver : public SolverBase {
     // With nu <= 2 and no network the chain runs in fused launches: the
     // finest smoother beside the first restriction, the smoother of each
     // restricted level beside the next restriction, the smallest levels'
-    // restrictions and smoothers in the tail launch (the kernels' arithmetic
-    // is that of the separate launches, so the results are the same).
+    // restrictions, smoothers and prolongations in the tail launch (the
+    // kernels' arithmetic is that of the separate launches, so the results
+    // are the same).
     bool fused_mg() const { return L_ > 0 && opt_.nu <= 2 && !net_; }
 
     SmoothLevel<T> smooth_level(int l) const {
@@ -925,15 +926,29 @@ class Solver : public SolverBase {
                 ch.c1[c] = c1_[q].p;
                 sc.lev[sc.count++] = smooth_level(q);
             }
+            // block 0 also carries the block up through the small levels
+            ProlongChain<T> up{};
+            up.l0 = 0;
+            for (int l = 0; l < m; ++l) {
+                const int q = up.count++;
+                up.nc[q] = n_axis[l];
+                up.nf[q] = n_axis[l + 1];
+                up.Nf[q] = N_[l + 1];
+                up.Yc[q] = Y_[l].p;
+                up.Yf[q] = Y_[l + 1].p;
+            }
             const int nbt = (N_[m + 1] + kTailBlock - 1) / kTailBlock;
-            k_tail_smooth<DIM, T><<<1 + nbt, kTailBlock, 0, stream_>>>(ctl, ch, sc, smooth_level(m + 1), omega, two);
+            k_tail_smooth<DIM, T><<<1 + nbt, kTailBlock, 0, stream_>>>(ctl, ch, sc, smooth_level(m + 1), up, omega,
+                                                                      two);
+            mark(kSecProlong);
+            for (int l = m; l + 1 < L; ++l) launch_prolong(ctl, l);
         } else {
             const int nbs = (N_[0] + kBlock - 1) / kBlock;
             k_restrict_coarse_smooth<DIM, T><<<nbs, kBlock, 0, stream_>>>(ctl, RestrictStep<T, T>{}, 0,
                                                                         smooth_level(0), omega, two);
+            mark(kSecProlong);
+            enqueue_prolong(ctl);
         }
-        mark(kSecProlong);
-        enqueue_prolong(ctl);
     }
 
     // the finest level's smoother output cL_final_ (nu sweeps from zero)

@@ -969,9 +969,10 @@ struct ProlongChain {
     T* Yf[kMaxLevels];
 };
 
+// The chain of ch.count prolongations, one level after the other, by one
+// block of kTailBlock threads (all of them must call it).
 template <int DIM, typename T>
-__global__ void __launch_bounds__(kTailBlock) k_prolong_head(const Ctl* __restrict__ ctl, ProlongChain<T> ch) {
-    if (ctl->state != 0) return;
+__device__ __forceinline__ void prolong_chain_block(const ProlongChain<T>& ch) {
     for (int m = 0; m < ch.count; ++m) {
         const int NC = ch.l0 + m + 1;
         for (int idx = threadIdx.x; idx < ch.Nf[m]; idx += kTailBlock) {
@@ -987,6 +988,12 @@ __global__ void __launch_bounds__(kTailBlock) k_prolong_head(const Ctl* __restri
         }
         __syncthreads();
     }
+}
+
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kTailBlock) k_prolong_head(const Ctl* __restrict__ ctl, ProlongChain<T> ch) {
+    if (ctl->state != 0) return;
+    prolong_chain_block<DIM, T>(ch);
 }
 
 // --------------------------------------------- fused launches of the chain
@@ -1073,8 +1080,9 @@ __global__ void __launch_bounds__(kBlock) k_restrict_coarse_smooth(const Ctl* __
 }
 
 // Block 0: the restriction chain into the small levels, one level after the
-// other, then the smoother of every small level.  Blocks 1..: the smoother of
-// the level the chain starts from.
+// other, the smoother of every small level, then the prolongation chain
+// among them (up: coarsest first; it needs only what block 0 wrote).
+// Blocks 1..: the smoother of the level the chain starts from.
 template <typename T>
 struct SmoothChain {
     int count;
@@ -1083,8 +1091,8 @@ struct SmoothChain {
 
 template <int DIM, typename T>
 __global__ void __launch_bounds__(kTailBlock) k_tail_smooth(const Ctl* __restrict__ ctl, RestrictChain<T> ch,
-                                                            SmoothChain<T> small, SmoothLevel<T> top, T omega,
-                                                            int two) {
+                                                            SmoothChain<T> small, SmoothLevel<T> top,
+                                                            ProlongChain<T> up, T omega, int two) {
     if (ctl->state != 0) return;
     if (blockIdx.x > 0) {
         const int idx = ((int)blockIdx.x - 1) * kTailBlock + threadIdx.x;
@@ -1102,6 +1110,9 @@ __global__ void __launch_bounds__(kTailBlock) k_tail_smooth(const Ctl* __restric
     for (int q = 0; q < small.count; ++q)
         for (int idx = threadIdx.x; idx < small.lev[q].op.N; idx += kTailBlock)
             smooth_level_at<DIM>(small.lev[q], idx, omega, two);
+    if (up.count == 0) return;
+    __syncthreads();
+    prolong_chain_block<DIM, T>(up);
 }
 
 // W = Q_k^T Z_{k+1} partial sums (NB x NB, entry a*NB+c = Q column a . z^c).
