@@ -2137,13 +2137,19 @@ class BatchedSolver : public BatchedBase {
         const T omega = T(opt_.omega);
         const int two = opt_.nu >= 2 ? 1 : 0;
         const int L = G.nlev - 1;
-        k_b_fine_smooth<DIM, T><<<G.fine.cnt, kBlock, 0, s>>>(inst_.p, map(G.fine), omega, two);
-        if (L == 0) return;
-        k_b_restrict<DIM, T, true><<<G.lev[L - 1].cnt, kBlock, 0, s>>>(inst_.p, map(G.lev[L - 1]), L - 1, omega);
+        if (L == 0) {
+            k_b_fine_smooth<DIM, T><<<G.fine.cnt, kBlock, 0, s>>>(inst_.p, map(G.fine), omega, two);
+            return;
+        }
+        // the finest smoother beside the first restriction, each restricted
+        // level's smoother beside the next restriction, then level 0's alone
+        k_b_restrict_fine_smooth<DIM, T><<<G.lev[L - 1].cnt + G.fine.cnt, kBlock, 0, s>>>(
+            inst_.p, map(G.lev[L - 1]), G.lev[L - 1].cnt, L - 1, map(G.fine), omega, two);
         for (int l = L - 2; l >= 0; --l)
-            k_b_restrict<DIM, T, false><<<G.lev[l].cnt, kBlock, 0, s>>>(inst_.p, map(G.lev[l]), l, omega);
-        for (int l = 0; l < L; ++l)
-            k_b_coarse_smooth<DIM, T><<<G.lev[l].cnt, kBlock, 0, s>>>(inst_.p, map(G.lev[l]), l, omega, two);
+            k_b_restrict_coarse_smooth<DIM, T><<<G.lev[l].cnt + G.lev[l + 1].cnt, kBlock, 0, s>>>(
+                inst_.p, map(G.lev[l]), G.lev[l].cnt, l, map(G.lev[l + 1]), l + 1, omega, two);
+        k_b_restrict_coarse_smooth<DIM, T><<<G.lev[0].cnt, kBlock, 0, s>>>(inst_.p, nullptr, 0, -1, map(G.lev[0]),
+                                                                          0, omega, two);
         for (int l = 0; l + 1 < L; ++l) {
             dispatch(l + 1, [&](auto nc) {
                 constexpr int NC = decltype(nc)::value;

@@ -117,9 +117,8 @@ __global__ void __launch_bounds__(kBlock) k_b_update_r(const BInst<T>* __restric
 
 // Finest smoother output cL = S^nu r (nu = 1 or 2 sweeps from zero).
 template <int DIM, typename T>
-__global__ void __launch_bounds__(kBlock) k_b_fine_smooth(const BInst<T>* __restrict__ insts,
-                                                          const BBlk* __restrict__ map, T omega, int two) {
-    const BBlk m = map[blockIdx.x];
+__device__ __forceinline__ void b_fine_smooth_block(const BInst<T>* __restrict__ insts, const BBlk& m, T omega,
+                                                    int two) {
     const BInst<T>& I = insts[m.inst];
     if (I.ctl->state != 0) return;
     const int n = I.n[I.nlev - 1];
@@ -127,6 +126,12 @@ __global__ void __launch_bounds__(kBlock) k_b_fine_smooth(const BInst<T>* __rest
         const Idx<DIM> p = decomp<DIM>(idx, n);
         I.cL[idx] = fine_smooth_at<DIM, T, double>(I.op, I.r, idx, p, omega, two);
     }
+}
+
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kBlock) k_b_fine_smooth(const BInst<T>* __restrict__ insts,
+                                                          const BBlk* __restrict__ map, T omega, int two) {
+    b_fine_smooth_block<DIM, T>(insts, map[blockIdx.x], omega, two);
 }
 
 // W = Q^T Z partial sums (NB x NB), Z from the level-(L-1) block carry and cL.
@@ -260,9 +265,7 @@ __global__ void __launch_bounds__(kBlock) k_b_spmm_gram(const BInst<T>* __restri
 // Restriction to level l (thread per coarse node) and the first sweep
 // c1 = omega g / D; FINE: from the finest residual r.
 template <int DIM, typename T, bool FINE>
-__global__ void __launch_bounds__(kBlock) k_b_restrict(const BInst<T>* __restrict__ insts,
-                                                       const BBlk* __restrict__ map, int l, T omega) {
-    const BBlk m = map[blockIdx.x];
+__device__ __forceinline__ void b_restrict_block(const BInst<T>* __restrict__ insts, const BBlk& m, int l, T omega) {
     const BInst<T>& I = insts[m.inst];
     if (I.ctl->state != 0) return;
     const int idx = m.start + threadIdx.x;
@@ -275,12 +278,17 @@ __global__ void __launch_bounds__(kBlock) k_b_restrict(const BInst<T>* __restric
     I.c1[l][idx] = omega * (g / D[idx]);
 }
 
+template <int DIM, typename T, bool FINE>
+__global__ void __launch_bounds__(kBlock) k_b_restrict(const BInst<T>* __restrict__ insts,
+                                                       const BBlk* __restrict__ map, int l, T omega) {
+    b_restrict_block<DIM, T, FINE>(insts, map[blockIdx.x], l, omega);
+}
+
 // Damped Jacobi on level l (nu = 1 or 2 sweeps from zero) into the last
 // column of the level's block carry.
 template <int DIM, typename T>
-__global__ void __launch_bounds__(kBlock) k_b_coarse_smooth(const BInst<T>* __restrict__ insts,
-                                                            const BBlk* __restrict__ map, int l, T omega, int two) {
-    const BBlk m = map[blockIdx.x];
+__device__ __forceinline__ void b_coarse_smooth_block(const BInst<T>* __restrict__ insts, const BBlk& m, int l,
+                                                      T omega, int two) {
     const BInst<T>& I = insts[m.inst];
     if (I.ctl->state != 0) return;
     const int idx = m.start + threadIdx.x;
@@ -288,6 +296,34 @@ __global__ void __launch_bounds__(kBlock) k_b_coarse_smooth(const BInst<T>* __re
     CoarseOp<T> op{I.n[l], I.N[l], I.coef[l], 0};
     I.Y[l][(size_t)idx * even_up(l + 1) + l] =
         coarse_smooth_at<DIM, T>(op, I.g[l], I.c1[l], nullptr, idx, omega, 0, two);
+}
+
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kBlock) k_b_coarse_smooth(const BInst<T>* __restrict__ insts,
+                                                            const BBlk* __restrict__ map, int l, T omega, int two) {
+    b_coarse_smooth_block<DIM, T>(insts, map[blockIdx.x], l, omega, two);
+}
+
+// Fused launches of the chain (as for a single problem): blocks [0, nr)
+// restrict into level l with map mr (FINE: from r), the blocks after them
+// smooth with map ms, the finest level (k_b_restrict_fine_smooth) or level
+// ls, which the previous launch restricted into (k_b_restrict_coarse_smooth;
+// nr = 0: smoothing only).  The two halves read and write disjoint data.
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kBlock) k_b_restrict_fine_smooth(const BInst<T>* __restrict__ insts,
+                                                                   const BBlk* __restrict__ mr, int nr, int l,
+                                                                   const BBlk* __restrict__ ms, T omega, int two) {
+    if ((int)blockIdx.x < nr) b_restrict_block<DIM, T, true>(insts, mr[blockIdx.x], l, omega);
+    else b_fine_smooth_block<DIM, T>(insts, ms[blockIdx.x - nr], omega, two);
+}
+
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kBlock) k_b_restrict_coarse_smooth(const BInst<T>* __restrict__ insts,
+                                                                     const BBlk* __restrict__ mr, int nr, int l,
+                                                                     const BBlk* __restrict__ ms, int ls, T omega,
+                                                                     int two) {
+    if ((int)blockIdx.x < nr) b_restrict_block<DIM, T, false>(insts, mr[blockIdx.x], l, omega);
+    else b_coarse_smooth_block<DIM, T>(insts, ms[blockIdx.x - nr], ls, omega, two);
 }
 
 // Block carry up from level l to l+1: Y_{l+1}[:, 0..l] = P Y_l (NC = l + 1).
