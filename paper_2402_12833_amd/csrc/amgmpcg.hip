@@ -2004,8 +2004,7 @@ class BatchedSolver : public BatchedBase {
         inst_.alloc(cnt);
         HIPCHK(hipMemcpy(inst_.p, hinst_.data(), cnt * sizeof(BInst<T>), hipMemcpyHostToDevice));
 
-        // block maps: all problems' fine nodes, then per group its fine nodes
-        // and each coarse level's nodes
+        // block maps: all problems' fine nodes, per group its fine nodes
         std::vector<BBlk> maps;
         auto fine_blocks = [&](int q0, int q1) {
             for (int q = q0; q < q1; ++q) {
@@ -2022,14 +2021,26 @@ class BatchedSolver : public BatchedBase {
             G.fine.off = (int)maps.size();
             fine_blocks(G.first, G.first + G.count);
             G.fine.cnt = (int)maps.size() - G.fine.off;
-            for (int l = 0; l + 1 < G.nlev; ++l) {
-                G.lev[l].off = (int)maps.size();
-                for (int q = G.first; q < G.first + G.count; ++q) {
-                    const int Nl = hinst_[q].N[l];
-                    for (int j = 0, s0 = 0; s0 < Nl; ++j, s0 += kBlock)
-                        maps.push_back(BBlk{q, j, s0, std::min(Nl, s0 + kBlock)});
+        }
+        // per depth below the finest level, over all groups: that coarse
+        // level's nodes (restriction and smoothing), and the same for the
+        // problems where it is not the coarsest level (carry into it)
+        dmax_ = 0;
+        for (const Group& G : groups_) dmax_ = std::max(dmax_, G.nlev - 1);
+        for (int d = 1; d <= dmax_; ++d) {
+            for (int pass = 0; pass < 2; ++pass) {
+                Range& R = pass == 0 ? dep_[d] : pro_[d];
+                R.off = (int)maps.size();
+                for (const Group& G : groups_) {
+                    const int l = G.nlev - 1 - d;
+                    if (l < 0 || (pass == 1 && l == 0)) continue;
+                    for (int q = G.first; q < G.first + G.count; ++q) {
+                        const int Nl = hinst_[q].N[l];
+                        for (int j = 0, s0 = 0; s0 < Nl; ++j, s0 += kBlock)
+                            maps.push_back(BBlk{q, j, s0, std::min(Nl, s0 + kBlock)});
+                    }
                 }
-                G.lev[l].cnt = (int)maps.size() - G.lev[l].off;
+                R.cnt = (int)maps.size() - R.off;
             }
         }
         maps_.alloc(maps.size());
@@ -2109,10 +2120,11 @@ class BatchedSolver : public BatchedBase {
     struct Group {
         int nlev, first, count;   // problems first .. first+count-1 of the instance array
         Range fine;
-        Range lev[kMaxLevels];
     };
 
     const BBlk* map(const Range& r) const { return maps_.p + r.off; }
+    Range dep_[kMaxLevels], pro_[kMaxLevels];   // per depth below the finest level, all groups
+    int dmax_ = 0;
 
     template <int V>
     struct IC {
@@ -2133,37 +2145,35 @@ class BatchedSolver : public BatchedBase {
 
     // Z = MG(r) of every problem of group G: finest smoother, restriction
     // chain, coarse smoothing, prolongation of the block carry.
-    void enqueue_mg(hipStream_t s, const Group& G) {
+    // The multigrid chain of every problem in the same launches, a level
+    // named by its depth below the finest one: the finest smoother beside
+    // the restriction to depth 1, the smoother of each depth beside the
+    // restriction to the next, the deepest alone, then the block carry from
+    // the deepest depth up (2 dmax launches, whatever the groups).
+    void enqueue_mg_all(hipStream_t s) {
         const T omega = T(opt_.omega);
         const int two = opt_.nu >= 2 ? 1 : 0;
-        const int L = G.nlev - 1;
-        if (L == 0) {
-            k_b_fine_smooth<DIM, T><<<G.fine.cnt, kBlock, 0, s>>>(inst_.p, map(G.fine), omega, two);
+        if (dmax_ == 0) {
+            k_b_fine_smooth<DIM, T><<<all_.cnt, kBlock, 0, s>>>(inst_.p, map(all_), omega, two);
             return;
         }
-        // the finest smoother beside the first restriction, each restricted
-        // level's smoother beside the next restriction, then level 0's alone
-        k_b_restrict_fine_smooth<DIM, T><<<G.lev[L - 1].cnt + G.fine.cnt, kBlock, 0, s>>>(
-            inst_.p, map(G.lev[L - 1]), G.lev[L - 1].cnt, L - 1, map(G.fine), omega, two);
-        for (int l = L - 2; l >= 0; --l)
-            k_b_restrict_coarse_smooth<DIM, T><<<G.lev[l].cnt + G.lev[l + 1].cnt, kBlock, 0, s>>>(
-                inst_.p, map(G.lev[l]), G.lev[l].cnt, l, map(G.lev[l + 1]), l + 1, omega, two);
-        k_b_restrict_coarse_smooth<DIM, T><<<G.lev[0].cnt, kBlock, 0, s>>>(inst_.p, nullptr, 0, -1, map(G.lev[0]),
-                                                                          0, omega, two);
-        for (int l = 0; l + 1 < L; ++l) {
-            dispatch(l + 1, [&](auto nc) {
-                constexpr int NC = decltype(nc)::value;
-                k_b_prolong<DIM, T, NC><<<G.lev[l + 1].cnt, kBlock, 0, s>>>(inst_.p, map(G.lev[l + 1]), l);
-            });
-        }
+        k_b_dep_restrict_fine_smooth<DIM, T><<<dep_[1].cnt + all_.cnt, kBlock, 0, s>>>(
+            inst_.p, map(dep_[1]), dep_[1].cnt, map(all_), omega, two);
+        for (int d = 2; d <= dmax_; ++d)
+            k_b_dep_restrict_coarse_smooth<DIM, T><<<dep_[d].cnt + dep_[d - 1].cnt, kBlock, 0, s>>>(
+                inst_.p, map(dep_[d]), dep_[d].cnt, d, map(dep_[d - 1]), d - 1, omega, two);
+        k_b_dep_restrict_coarse_smooth<DIM, T><<<dep_[dmax_].cnt, kBlock, 0, s>>>(
+            inst_.p, nullptr, 0, 0, map(dep_[dmax_]), dmax_, omega, two);
+        for (int d = dmax_ - 1; d >= 1; --d)
+            if (pro_[d].cnt > 0) k_b_dep_prolong<DIM, T><<<pro_[d].cnt, kBlock, 0, s>>>(inst_.p, map(pro_[d]), d);
     }
 
     void enqueue_init(hipStream_t s, double tol) {
         k_b_init_residual<DIM, T><<<all_.cnt, kBlock, 0, s>>>(inst_.p, map(all_));
         k_b_reduce_init<T><<<count, kRedBlock, 0, s>>>(inst_.p, tol);
         k_b_zero_if<T><<<all_.cnt, kBlock, 0, s>>>(inst_.p, map(all_));
+        enqueue_mg_all(s);
         for (const Group& G : groups_) {
-            enqueue_mg(s, G);
             dispatch(G.nlev, [&](auto nbc) {
                 constexpr int NB = decltype(nbc)::value;
                 k_b_update_xP<DIM, T, NB><<<G.fine.cnt, kBlock, 0, s>>>(inst_.p, map(G.fine), 1);
@@ -2178,7 +2188,12 @@ class BatchedSolver : public BatchedBase {
             dispatch(G.nlev, [&](auto nbc) {
                 constexpr int NB = decltype(nbc)::value;
                 k_b_update_r<T, NB><<<G.fine.cnt, kBlock, 0, s>>>(inst_.p, map(G.fine));
-                enqueue_mg(s, G);
+            });
+        }
+        enqueue_mg_all(s);
+        for (const Group& G : groups_) {
+            dispatch(G.nlev, [&](auto nbc) {
+                constexpr int NB = decltype(nbc)::value;
                 k_b_fine_W<DIM, T, NB><<<G.fine.cnt, kBlock, 0, s>>>(inst_.p, map(G.fine));
                 k_b_reduce_beta<T, NB><<<G.count, kRedBlock, 0, s>>>(inst_.p, G.first, mixed_ ? 1 : 0);
                 k_b_update_xP<DIM, T, NB><<<G.fine.cnt, kBlock, 0, s>>>(inst_.p, map(G.fine), 0);

@@ -278,12 +278,6 @@ __device__ __forceinline__ void b_restrict_block(const BInst<T>* __restrict__ in
     I.c1[l][idx] = omega * (g / D[idx]);
 }
 
-template <int DIM, typename T, bool FINE>
-__global__ void __launch_bounds__(kBlock) k_b_restrict(const BInst<T>* __restrict__ insts,
-                                                       const BBlk* __restrict__ map, int l, T omega) {
-    b_restrict_block<DIM, T, FINE>(insts, map[blockIdx.x], l, omega);
-}
-
 // Damped Jacobi on level l (nu = 1 or 2 sweeps from zero) into the last
 // column of the level's block carry.
 template <int DIM, typename T>
@@ -298,44 +292,67 @@ __device__ __forceinline__ void b_coarse_smooth_block(const BInst<T>* __restrict
         coarse_smooth_at<DIM, T>(op, I.g[l], I.c1[l], nullptr, idx, omega, 0, two);
 }
 
-template <int DIM, typename T>
-__global__ void __launch_bounds__(kBlock) k_b_coarse_smooth(const BInst<T>* __restrict__ insts,
-                                                            const BBlk* __restrict__ map, int l, T omega, int two) {
-    b_coarse_smooth_block<DIM, T>(insts, map[blockIdx.x], l, omega, two);
-}
-
-// Fused launches of the chain (as for a single problem): blocks [0, nr)
-// restrict into level l with map mr (FINE: from r), the blocks after them
-// smooth with map ms, the finest level (k_b_restrict_fine_smooth) or level
-// ls, which the previous launch restricted into (k_b_restrict_coarse_smooth;
-// nr = 0: smoothing only).  The two halves read and write disjoint data.
-template <int DIM, typename T>
-__global__ void __launch_bounds__(kBlock) k_b_restrict_fine_smooth(const BInst<T>* __restrict__ insts,
-                                                                   const BBlk* __restrict__ mr, int nr, int l,
-                                                                   const BBlk* __restrict__ ms, T omega, int two) {
-    if ((int)blockIdx.x < nr) b_restrict_block<DIM, T, true>(insts, mr[blockIdx.x], l, omega);
-    else b_fine_smooth_block<DIM, T>(insts, ms[blockIdx.x - nr], omega, two);
+// The chain of every group in the same launches: a coarse level is named by
+// its depth below the finest one (level l = nlev - 1 - depth of each
+// problem), so one launch serves the problems of all level counts.  As for
+// a single problem the smoothers run inside the restriction launches:
+// blocks [0, nr) restrict into depth dr with map mr (depth 1: from r), the
+// blocks after them smooth with map ms, the finest level
+// (k_b_dep_restrict_fine_smooth) or depth ds, which the previous launch
+// restricted into (k_b_dep_restrict_coarse_smooth; nr = 0: smoothing only).
+// The two halves read and write disjoint data.
+template <typename T>
+__device__ __forceinline__ int b_level(const BInst<T>* __restrict__ insts, const BBlk& m, int depth) {
+    return insts[m.inst].nlev - 1 - depth;
 }
 
 template <int DIM, typename T>
-__global__ void __launch_bounds__(kBlock) k_b_restrict_coarse_smooth(const BInst<T>* __restrict__ insts,
-                                                                     const BBlk* __restrict__ mr, int nr, int l,
-                                                                     const BBlk* __restrict__ ms, int ls, T omega,
-                                                                     int two) {
-    if ((int)blockIdx.x < nr) b_restrict_block<DIM, T, false>(insts, mr[blockIdx.x], l, omega);
-    else b_coarse_smooth_block<DIM, T>(insts, ms[blockIdx.x - nr], ls, omega, two);
+__global__ void __launch_bounds__(kBlock) k_b_dep_restrict_fine_smooth(const BInst<T>* __restrict__ insts,
+                                                                       const BBlk* __restrict__ mr, int nr,
+                                                                       const BBlk* __restrict__ ms, T omega,
+                                                                       int two) {
+    if ((int)blockIdx.x < nr) {
+        const BBlk m = mr[blockIdx.x];
+        b_restrict_block<DIM, T, true>(insts, m, b_level(insts, m, 1), omega);
+    } else {
+        b_fine_smooth_block<DIM, T>(insts, ms[blockIdx.x - nr], omega, two);
+    }
 }
 
-// Block carry up from level l to l+1: Y_{l+1}[:, 0..l] = P Y_l (NC = l + 1).
-template <int DIM, typename T, int NC>
-__global__ void __launch_bounds__(kBlock) k_b_prolong(const BInst<T>* __restrict__ insts,
-                                                      const BBlk* __restrict__ map, int l) {
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kBlock) k_b_dep_restrict_coarse_smooth(const BInst<T>* __restrict__ insts,
+                                                                         const BBlk* __restrict__ mr, int nr,
+                                                                         int dr, const BBlk* __restrict__ ms,
+                                                                         int ds, T omega, int two) {
+    if ((int)blockIdx.x < nr) {
+        const BBlk m = mr[blockIdx.x];
+        b_restrict_block<DIM, T, false>(insts, m, b_level(insts, m, dr), omega);
+    } else {
+        const BBlk m = ms[blockIdx.x - nr];
+        b_coarse_smooth_block<DIM, T>(insts, m, b_level(insts, m, ds), omega, two);
+    }
+}
+
+// Block carry into depth d from depth d + 1: Y_{l+1}[:, 0..l] = P Y_l with
+// l + 1 = nlev - 1 - d, the column count chosen per problem.
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kBlock) k_b_dep_prolong(const BInst<T>* __restrict__ insts,
+                                                          const BBlk* __restrict__ map, int d) {
     const BBlk m = map[blockIdx.x];
     const BInst<T>& I = insts[m.inst];
     if (I.ctl->state != 0) return;
     const int idx = m.start + threadIdx.x;
     if (idx >= m.end) return;
-    prolong_at<DIM, T, NC>(I.Y[l], I.n[l], I.Y[l + 1], I.n[l + 1], idx);
+    const int l = I.nlev - 2 - d;
+    switch (l + 1) {
+        case 1: prolong_at<DIM, T, 1>(I.Y[l], I.n[l], I.Y[l + 1], I.n[l + 1], idx); break;
+        case 2: prolong_at<DIM, T, 2>(I.Y[l], I.n[l], I.Y[l + 1], I.n[l + 1], idx); break;
+        case 3: prolong_at<DIM, T, 3>(I.Y[l], I.n[l], I.Y[l + 1], I.n[l + 1], idx); break;
+        case 4: prolong_at<DIM, T, 4>(I.Y[l], I.n[l], I.Y[l + 1], I.n[l + 1], idx); break;
+        case 5: prolong_at<DIM, T, 5>(I.Y[l], I.n[l], I.Y[l + 1], I.n[l + 1], idx); break;
+        case 6: prolong_at<DIM, T, 6>(I.Y[l], I.n[l], I.Y[l + 1], I.n[l + 1], idx); break;
+        default: prolong_at<DIM, T, 7>(I.Y[l], I.n[l], I.Y[l + 1], I.n[l + 1], idx); break;
+    }
 }
 
 // ---------------------------------------------------------- reductions
