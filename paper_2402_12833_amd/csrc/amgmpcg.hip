@@ -1772,6 +1772,10 @@ class CsrSolver : public SolverBase {
     // smoother on every coarse level (into the last column of its block
     // carry) and the prolongation of the block carry up to level L-1.
     void enqueue_mg(const Ctl* ctl, const double* r) {
+        if (opt_.nu <= 2 && L_ > 0) {
+            enqueue_mg_fused(ctl, r);
+            return;
+        }
         smooth<double>(ctl, L_, r, cL_.p, 1, cL2_.p, cL3_.p);
         cL_final_ = cL_.p;
         if (L_ == 0) return;
@@ -1779,6 +1783,35 @@ class CsrSolver : public SolverBase {
         for (int l = L_ - 2; l >= 0; --l)
             k_csr_restrict<T, T><<<blocks(N_[l]), kBlock, 0, stream_>>>(ctl, R_l_[l].op(), g_[l + 1].p, g_[l].p);
         for (int l = 0; l < L_; ++l) smooth<T>(ctl, l, g_[l].p, Y_[l].p + l, even_up(l + 1), c_[l].p, c2_[l].p);
+        enqueue_prolong(ctl);
+    }
+
+    // nu <= 2: each smoother runs beside a restriction (the finest beside
+    // the first, both reading r; each restricted level beside the
+    // restriction from it), level 0's alone: L + 1 launches for the chain's
+    // restriction and smoothing instead of 2L + 1, with the same arithmetic.
+    void enqueue_mg_fused(const Ctl* ctl, const double* r) {
+        const T omega = T(opt_.omega);
+        const int two = opt_.nu >= 2 ? 1 : 0;
+        {
+            const int l = L_ - 1, nr = blocks(N_[l]);
+            k_csr_restrict_smooth<T, double, double><<<nr + blocks(N_[L_]), kBlock, 0, stream_>>>(
+                ctl, R_l_[l].op(), r, g_[l].p, nr, A_[L_].op(), D_[L_].p, r, cL_.p, 1, omega, two);
+            cL_final_ = cL_.p;
+        }
+        for (int l = L_ - 2; l >= 0; --l) {
+            const int nr = blocks(N_[l]);
+            k_csr_restrict_smooth<T, T, T><<<nr + blocks(N_[l + 1]), kBlock, 0, stream_>>>(
+                ctl, R_l_[l].op(), g_[l + 1].p, g_[l].p, nr, A_[l + 1].op(), D_[l + 1].p, g_[l + 1].p,
+                Y_[l + 1].p + (l + 1), even_up(l + 2), omega, two);
+        }
+        k_csr_restrict_smooth<T, T, T><<<blocks(N_[0]), kBlock, 0, stream_>>>(
+            ctl, CsrOp<T>{0, nullptr, nullptr, nullptr}, static_cast<const T*>(nullptr), nullptr, 0, A_[0].op(),
+            D_[0].p, g_[0].p, Y_[0].p, even_up(1), omega, two);
+        enqueue_prolong(ctl);
+    }
+
+    void enqueue_prolong(const Ctl* ctl) {
         for (int l = 0; l + 1 < L_; ++l) {
             dispatch_nc(l + 1, [&](auto ncc) {
                 constexpr int NC = decltype(ncc)::value;
@@ -1787,6 +1820,7 @@ class CsrSolver : public SolverBase {
             });
         }
     }
+
 
     void enqueue_init(double tol) {
         const int N = N_[L_];

@@ -70,20 +70,24 @@ __global__ void __launch_bounds__(kBlock) k_csr_apply(CsrOp<double> A, const dou
 // two sweeps c = c1 + omega (g - A c1) / D, c1 formed on the fly.  Output
 // to out[i * stride] (a vector, or one column of a node-major block).
 template <typename T, typename G>
+__device__ __forceinline__ T csr_smooth_at(const CsrOp<T>& A, const T* __restrict__ D, const G* __restrict__ g, int i,
+                                           T omega, int two) {
+    const T gi = T(g[i]);
+    const T c1 = omega * (gi / D[i]);
+    T c = c1;
+    if (two) {
+        const T Ac = csr_row_dot<T>(A, i, [&](int j) { return omega * (T(g[j]) / D[j]); });
+        c = c1 + omega * ((gi - Ac) / D[i]);
+    }
+    return c;
+}
+
+template <typename T, typename G>
 __global__ void __launch_bounds__(kBlock) k_csr_smooth(const Ctl* __restrict__ ctl, CsrOp<T> A,
                                                        const T* __restrict__ D, const G* __restrict__ g,
                                                        T* __restrict__ out, int stride, T omega, int two) {
     if (ctl->state != 0) return;
-    CSR_LOOP(i, A.n) {
-        const T gi = T(g[i]);
-        const T c1 = omega * (gi / D[i]);
-        T c = c1;
-        if (two) {
-            const T Ac = csr_row_dot<T>(A, i, [&](int j) { return omega * (T(g[j]) / D[j]); });
-            c = c1 + omega * ((gi - Ac) / D[i]);
-        }
-        out[(size_t)i * stride] = c;
-    }
+    CSR_LOOP(i, A.n) out[(size_t)i * stride] = csr_smooth_at<T, G>(A, D, g, i, omega, two);
 }
 
 // One further sweep cout = cin + omega (g - A cin) / D.
@@ -105,6 +109,29 @@ __global__ void __launch_bounds__(kBlock) k_csr_restrict(const Ctl* __restrict__
                                                          const TI* __restrict__ gf, T* __restrict__ g) {
     if (ctl->state != 0) return;
     CSR_LOOP(i, R.n) g[i] = csr_row_dot<T>(R, i, [&](int j) { return T(gf[j]); });
+}
+
+// One restriction in blocks [0, nr) (grid-stride over them) and, in the
+// blocks after them, the first min(nu, 2) sweeps on a level whose input is
+// already in place (the finest level beside the first restriction, both
+// reading r; a restricted level beside the restriction from it; nr = 0:
+// the smoother alone).  The halves read and write disjoint data.
+template <typename T, typename TI, typename G>
+__global__ void __launch_bounds__(kBlock) k_csr_restrict_smooth(const Ctl* __restrict__ ctl, CsrOp<T> R,
+                                                                const TI* __restrict__ gf, T* __restrict__ gc,
+                                                                int nr, CsrOp<T> A, const T* __restrict__ D,
+                                                                const G* __restrict__ g, T* __restrict__ out,
+                                                                int stride, T omega, int two) {
+    if (ctl->state != 0) return;
+    const int b = (int)blockIdx.x;
+    if (b < nr) {
+        for (int i = b * kBlock + (int)threadIdx.x; i < R.n; i += nr * kBlock)
+            gc[i] = csr_row_dot<T>(R, i, [&](int j) { return T(gf[j]); });
+        return;
+    }
+    const int bs = b - nr, gs = (int)gridDim.x - nr;
+    for (int i = bs * kBlock + (int)threadIdx.x; i < A.n; i += gs * kBlock)
+        out[(size_t)i * stride] = csr_smooth_at<T, G>(A, D, g, i, omega, two);
 }
 
 // Block carry up one level: Yf[:, 0..NC-1] = P Yc[:, 0..NC-1] (node-major,
