@@ -16,7 +16,8 @@ Readings where the paper is silent or ambiguous (all listed in DESIGN):
   * convergence: ||r_k||_2 <= tol ||b||_2 on the recursively updated r,
     tested after every update; iterations = number of x updates;
   * the truncation sum over j runs over the last m stored blocks (m = 1 is
-    the "previous block only" form).
+    the "previous block only" form), in classical Gram-Schmidt form (every
+    beta_j from Z_{k+1}); modified Gram-Schmidt is the variant ``orth="mgs"``.
 """
 from __future__ import annotations
 
@@ -112,12 +113,30 @@ class Result:
     bnorm: float = 0.0
 
 
+def a_orthogonalize(Z: np.ndarray, window, orth: str = "cgs") -> np.ndarray:
+    """The next block P_{k+1} from Z_{k+1} and the stored (P_j, Q_j = A P_j,
+    G_j^+) of the window, oldest first (Sec. 2.2, the truncated sum over j):
+    P_{k+1} = Z - sum_j P_j beta_j with beta_j = G_j^+ Q_j^T V, where V is
+    Z for every j (classical Gram-Schmidt, ``"cgs"``) or the block as far as
+    it is orthogonalised, block after block (modified, ``"mgs"``).  The two
+    agree in exact arithmetic when the stored blocks are mutually
+    A-orthogonal, as the window's blocks are."""
+    if orth not in ("cgs", "mgs"):
+        raise ValueError("orth must be 'cgs' or 'mgs'")
+    Pn = Z.copy()
+    for (Pj, Qj, Gpj) in window:
+        beta = Gpj @ (Qj.T @ (Z if orth == "cgs" else Pn))
+        Pn = Pn - Pj @ beta
+    return Pn
+
+
 def mpcg(h: Hierarchy, b: np.ndarray, x0: Optional[np.ndarray] = None,
          tol: float = 1e-8, maxit: int = 1000, m: int = 1, nu: int = 2,
          omega: float = 2.0 / 3.0, tau: Optional[float] = None,
          extra: Optional[Callable[[np.ndarray], np.ndarray]] = None,
          coarse_exact: bool = False, snapshots: Sequence[int] = (),
-         callback: Optional[Callable[[int, np.ndarray, np.ndarray], None]] = None) -> Result:
+         callback: Optional[Callable[[int, np.ndarray, np.ndarray], None]] = None,
+         orth: str = "cgs") -> Result:
     """Algorithm 1 with truncation window m.
 
     ``extra``, if given, maps r to one more search direction appended after
@@ -146,7 +165,7 @@ def mpcg(h: Hierarchy, b: np.ndarray, x0: Optional[np.ndarray] = None,
         res.x = np.zeros(n)
         res.resnorms = [0.0]
         return res
-    r = b - A_ @ x                                    # line 1: r_0 = b - A x_0
+    r = b - A_ @ x                                    # r_0 = b - A x_0
     rn = float(np.linalg.norm(r))
     res.resnorms.append(rn)
     if 0 in snapshots:
@@ -156,7 +175,7 @@ def mpcg(h: Hierarchy, b: np.ndarray, x0: Optional[np.ndarray] = None,
         return res
     if rn <= tol * nb:
         return res
-    Z = directions(r)                                 # lines 2-3: P_0 = Z_0
+    Z = directions(r)                                 # P_0 = Z_0 = MG(r_0)
     bw = Z.shape[1]
     if tau is None:
         tau = default_tau(bw)
@@ -171,13 +190,13 @@ def mpcg(h: Hierarchy, b: np.ndarray, x0: Optional[np.ndarray] = None,
             res.status = BREAKDOWN
             break
         g = P.T @ r
-        alpha = pv.Gplus @ g                          # line 6
+        alpha = pv.Gplus @ g                          # alpha_k = (P^T A P)^+ P^T r
         res.alphas.append(alpha.copy())
         res.ranks.append(pv.rank)
         if callback is not None:
             callback(k, x.copy(), P.copy())
-        x = x + P @ alpha                             # line 7
-        r = r - Q @ alpha                             # line 8
+        x = x + P @ alpha                             # x_{k+1}
+        r = r - Q @ alpha                             # r_{k+1}
         k += 1
         rn = float(np.linalg.norm(r))
         res.resnorms.append(rn)
@@ -194,12 +213,8 @@ def mpcg(h: Hierarchy, b: np.ndarray, x0: Optional[np.ndarray] = None,
         window.append((P, Q, pv.Gplus))
         if len(window) > m:
             window.pop(0)
-        Z = directions(r)                             # lines 9-10
-        Pn = Z.copy()
-        for (Pj, Qj, Gpj) in window:                  # line 11 (beta from Z for every j)
-            beta = Gpj @ (Qj.T @ Z)
-            Pn = Pn - Pj @ beta
-        P = Pn
+        Z = directions(r)                             # Z_{k+1} = MG(r_{k+1})
+        P = a_orthogonalize(Z, window, orth)          # P_{k+1}, A-orthogonal to the window
         Q = np.column_stack([A_ @ P[:, j] for j in range(bw)])
         G = gram(P, Q)
         pv = pinv_gram(G, tau)
