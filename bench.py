@@ -324,6 +324,17 @@ def main(argv=None):
                                         "hbm_GBps_algorithmic": round(pi2 * it2 / (ms2 * 1e-3) / 1e9, 1),
                                         "speedup_vs_fp64": round(ms / ms2, 3)}
         s2.close()
+        # the same problem at 255^3: 16.6 M DoF, 7 levels, a working set far
+        # beyond the 256 MB Infinity Cache
+        bprob = W.POISSON3D_255
+        for prec, tag, bulk in ((0, "fp64", 8), (1, "fp32bulk", 4)):
+            sb, _, _, msb, itb, setb, infb = run_solver(amg, torch, bprob, prec, max(2, args.steps // 2), 1)
+            _, pib = traffic_model(3, bprob.n, bprob.nlevels, bulk, False)
+            var[f"poisson3d_255_{tag}"] = {"ms": round(msb, 4), "iterations": itb, "refreshes": infb["refreshes"],
+                                           "dofs": bprob.ndof, "levels": bprob.nlevels,
+                                           "hbm_GBps_algorithmic": round(pib * itb / (msb * 1e-3) / 1e9, 1),
+                                           "setup_s": round(setb, 3)}
+            sb.close()
         dprob = W.DIFFUSION3D_127
         kap = W.kappa_field(dprob)
         for prec, tag, bulk in ((0, "fp64", 8), (1, "fp32bulk", 4)):

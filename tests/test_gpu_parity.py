@@ -208,6 +208,24 @@ def test_deterministic_bitwise():
     s.close()
 
 
+def test_poisson3d_255_beyond_cache():
+    """16.6 M DoF, 7 levels (seven columns: the row-mapped SpMM in FP64, the
+    z-marching one in FP32 bulk): both converge to a true residual <= 1e-8
+    with the same iteration count."""
+    prob = W.POISSON3D_255
+    b = dev(W.problem_rhs(prob))
+    its = []
+    for prec in (0, 1):
+        s = amg.Solver(3, prob.n, prob.nlevels, precision=prec)
+        x, info = s.solve(b, tol=1e-8)
+        assert info["status"] == amg.OK and info["nb"] == 7
+        rt = s.residual(b, x)
+        assert float(torch.linalg.norm(rt) / torch.linalg.norm(b)) <= 1.01e-8
+        its.append(info["iterations"])
+        s.close()
+    assert abs(its[0] - its[1]) <= 1, its
+
+
 def test_workspace_bytes():
     """The truncation window's rings are the only buffers that depend on m:
     two rings (P and Q) of m slots, each N * even_up(b) values rounded up to

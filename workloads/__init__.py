@@ -43,6 +43,8 @@ class GridProblem:
 POISSON2D_31 = GridProblem("poisson2d_31", 2, 31, 4, rhs_seed=1)
 POISSON3D_127 = GridProblem("poisson3d_127", 3, 127, 6, rhs_seed=2)
 DIFFUSION3D_127 = GridProblem("diffusion3d_127", 3, 127, 6, rhs_seed=2, kappa_seed=3)
+# beyond the 256 MB Infinity Cache: 16,581,375 DoF, 7 levels (255 .. 3)
+POISSON3D_255 = GridProblem("poisson3d_255", 3, 255, 7, rhs_seed=2)
 
 PROBLEMS = {p.name: p for p in (POISSON2D_31, POISSON3D_127, DIFFUSION3D_127)}
 
