@@ -1355,9 +1355,11 @@ struct ZOps {
 };
 
 // The z-marching SpMM serves blocks of at most 48 bytes per node (FP64 up to
-// six columns, FP32 up to eight); wider ones use the row-mapped kernel.
+// six columns, FP32 up to eight) and seven FP64 columns (64 bytes, two
+// blocks per CU); eight FP64 columns would spill and take the row-mapped
+// kernel.
 template <typename T, int NB>
-__host__ __device__ constexpr bool zt_fits() { return even_up(NB) * (int)sizeof(T) <= 48; }
+__host__ __device__ constexpr bool zt_fits() { return even_up(NB) * (int)sizeof(T) <= 48 || NB == 7; }
 
 template <typename T, int NPT, int RPP, bool VAR>
 __device__ __forceinline__ void zt_ops(const FineOp<T>& op, const double* __restrict__ r, int n, int i, int j0, int yl,
@@ -1392,10 +1394,11 @@ __device__ __forceinline__ void zt_ops(const FineOp<T>& op, const double* __rest
 // VAR: variable coefficients (op.D, ex, ey, ez), else the constant h^-2
 // stencil.  Three blocks of 4 waves fit a CU (LDS of the FP64 six-column tile
 // ~51 KB); the variable-coefficient kernels on wide blocks carry the next
-// step's coefficients as well and get two, which keeps them free of spills.
+// step's coefficients as well and get two, which keeps them free of spills,
+// and so do tiles of 64-byte nodes (~67 KB of LDS).
 template <typename T, int NB, bool VAR>
 __host__ __device__ constexpr int zt_min_blocks() {
-    return (VAR && (sizeof(T) == 8 ? NB >= 5 : NB >= 7)) ? 2 : 3;
+    return (even_up(NB) * (int)sizeof(T) > 48 || (VAR && (sizeof(T) == 8 ? NB >= 5 : NB >= 7))) ? 2 : 3;
 }
 template <typename T, int NB, int TY, bool VAR>
 __global__ void __launch_bounds__(kBlock, (zt_min_blocks<T, NB, VAR>())) k_spmm_gram_z(const Ctl* __restrict__ ctl, int n, int ntx, int kz,

@@ -144,6 +144,8 @@ ZGRIDS = [
     (3, 3, 1, None, 23),
     (3, 2, 2, 9, 24),
     (3, 5, 2, None, 25),
+    (3, 127, 7, None, 26),      # seven columns: 64-byte FP64 nodes
+    (3, 127, 7, 7, 27),
 ]
 
 
