@@ -1,0 +1,21 @@
+"""Host-side logic of bench.py (no GPU): the one-GPU contract and the
+algorithmic byte model the roofline divides by."""
+import bench
+
+
+def test_more_than_one_gpu_is_refused(capsys):
+    assert bench.main(["--gpus", "2", "--steps", "1"]) == 2
+    assert "one GPU only" in capsys.readouterr().err
+
+
+def test_traffic_model_matches_the_documented_figures():
+    # the per-launch algorithmic bytes quoted for 127^3 FP64 (6 levels,
+    # constant coefficients) in the design notes' kernel table
+    m, per_iter = bench.traffic_model(3, 127, 6, 8, False)
+    assert round(m["update_xP"] / 1e6, 1) == 255.8
+    assert round(m["spmm_gram"] / 1e6, 1) == 213.0
+    assert round(m["update_r"] / 1e6, 1) == 131.1
+    assert round(m["fine_W"] / 1e6, 1) == 124.7
+    # FP32 bulk halves the block traffic; x and r stay FP64
+    m32, per32 = bench.traffic_model(3, 127, 6, 4, False)
+    assert m32["update_r"] == (6 * 4 + 16) * 127 ** 3 and per32 < per_iter
