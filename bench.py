@@ -123,6 +123,36 @@ def per_dof(dim, nlevels, bulk, var):
             "update_xP": 2 * b * bulk + 16 + bulk, "fine_W": b * bulk + bulk}
 
 
+def poisson_csr(n, nlevels):
+    """The 3D 7-point Poisson operator on n^3 interior nodes (h = 1/(n+1),
+    Dirichlet) and the tensor-product linear interpolations of the grid
+    hierarchy (coarse node J on fine node 2J+1), as CSR inputs for the
+    general entry point; with R = P^T / 8 this is the structured workload."""
+    import scipy.sparse as sp
+
+    def lap1(m):
+        h = 1.0 / (m + 1)
+        return sp.diags([-np.ones(m - 1), 2.0 * np.ones(m), -np.ones(m - 1)], [-1, 0, 1]) / h ** 2
+
+    def interp1(nc):
+        j = np.arange(nc)
+        rows = np.concatenate([2 * j + 1, 2 * j, 2 * j + 2])
+        vals = np.concatenate([np.ones(nc), np.full(nc, 0.5), np.full(nc, 0.5)])
+        return sp.csr_matrix((vals, (rows, np.concatenate([j, j, j]))), shape=(2 * nc + 1, nc))
+
+    L1, I = lap1(n), sp.identity(n)
+    A = (sp.kron(sp.kron(I, I), L1) + sp.kron(sp.kron(I, L1), I) + sp.kron(sp.kron(L1, I), I)).tocsr()
+    sizes = [n]
+    for _ in range(nlevels - 1):
+        sizes.append(sizes[-1] // 2)
+    sizes = sizes[::-1]
+    Ps = []
+    for l in range(nlevels - 1):
+        P1 = interp1(sizes[l])
+        Ps.append(sp.kron(sp.kron(P1, P1), P1).tocsr())
+    return A, Ps
+
+
 def run_solver(amg, torch, prob, precision, steps, warmup, kappa=None, net=None, m=1, method=0):
     import workloads as W
     b = torch.as_tensor(W.problem_rhs(prob), device="cuda")
@@ -382,6 +412,28 @@ def main(argv=None):
             assert ci["status"] == amg.OK, ci
             var[f"graph2d_20000_csr_{tag}"] = {"ms": round(float(np.mean(tms)), 4), "iterations": ci["iterations"],
                                                "unknowns": int(A.shape[0]), "nnz": int(A.nnz), "levels": len(Ps) + 1}
+            sc.close()
+        # the 127^3 Poisson workload through the general entry point: the
+        # fine operator as a 14.2 M-nonzero CSR matrix (the cost of generality)
+        Ac, Psc = poisson_csr(prob.n, prob.nlevels)
+        bc = torch.as_tensor(W.problem_rhs(prob), device="cuda")
+        for prec, tag in ((0, "fp64"), (1, "fp32bulk")):
+            t0 = time.time()
+            sc = amg.Solver.from_csr(Ac, Psc, 0.125, precision=prec)
+            set_c = time.time() - t0
+            xc = torch.zeros_like(bc)
+            sc.solve(bc, xc, tol=1e-8)
+            tms = []
+            for _ in range(max(2, args.steps // 2)):
+                xc.zero_()
+                torch.cuda.synchronize()
+                _, ci = sc.solve(bc, xc, tol=1e-8)
+                tms.append(ci["solve_ms"])
+            assert ci["status"] == amg.OK, ci
+            ref = ms if prec == 0 else var["poisson3d_127_fp32bulk"]["ms"]
+            var[f"poisson3d_127_csr_{tag}"] = {"ms": round(float(np.mean(tms)), 4), "iterations": ci["iterations"],
+                                               "nnz": int(Ac.nnz), "setup_s": round(set_c, 3),
+                                               "time_vs_structured": round(float(np.mean(tms)) / ref, 3)}
             sc.close()
         # the learned direction (committed trained weights) on the same problem
         from paper_2402_12833_amd import train as T

@@ -19,3 +19,16 @@ def test_traffic_model_matches_the_documented_figures():
     # FP32 bulk halves the block traffic; x and r stay FP64
     m32, per32 = bench.traffic_model(3, 127, 6, 4, False)
     assert m32["update_r"] == (6 * 4 + 16) * 127 ** 3 and per32 < per_iter
+
+
+def test_poisson_csr_inputs_match_the_structured_hierarchy():
+    """The CSR inputs bench.py builds for the general entry point are the
+    structured workload's operator and prolongations (compared with the
+    oracle's own construction at 15^3, 3 levels)."""
+    from oracle import hierarchy
+    A, Ps = bench.poisson_csr(15, 3)
+    h = hierarchy.build(3, 15, 3)
+    assert abs(A - h.fine.A).max() <= 1e-12 * abs(h.fine.A).max()
+    for l in range(2):
+        assert Ps[l].shape == h.levels[l].P.shape
+        assert abs(Ps[l] - h.levels[l].P).max() == 0.0
