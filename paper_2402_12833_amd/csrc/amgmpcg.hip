@@ -1664,21 +1664,51 @@ class CsrSolver : public SolverBase {
     template <typename V>
     struct DevCsr {
         int n = 0;
-        DevBuf<int> ptr, col;
+        DevBuf<int> soff, swid, col;
         DevBuf<V> val;
+        // the sliced layout of CsrOp: slices of 64 rows, each padded to its
+        // longest row, column by column; padding has weight 0 at the row's
+        // first column (column 0 for an empty row)
         void upload(const host::Csr& M) {
             n = M.n;
-            ptr.alloc(M.ptr.size());
-            HIPCHK(hipMemcpy(ptr.p, M.ptr.data(), M.ptr.size() * sizeof(int), hipMemcpyHostToDevice));
-            if (M.nnz() > 0) {
-                col.alloc((size_t)M.nnz());
-                HIPCHK(hipMemcpy(col.p, M.col.data(), M.col.size() * sizeof(int), hipMemcpyHostToDevice));
-                val.alloc((size_t)M.nnz());
-                std::vector<V> tmp(M.val.begin(), M.val.end());
-                HIPCHK(hipMemcpy(val.p, tmp.data(), tmp.size() * sizeof(V), hipMemcpyHostToDevice));
+            const int ns = (n + 63) / 64;
+            std::vector<int> off(ns), wid(ns);
+            long long total = 0;
+            for (int s = 0; s < ns; ++s) {
+                int w = 0;
+                for (int r = s * 64; r < std::min(n, s * 64 + 64); ++r) w = std::max(w, M.ptr[r + 1] - M.ptr[r]);
+                off[s] = (int)total;
+                wid[s] = w;
+                total += 64LL * w;
+                if (total > INT32_MAX) throw ApiError(AMGMPCG_INVALID_ARG, "sparse matrix too large");
             }
+            std::vector<int> c((size_t)std::max<long long>(total, 1), 0);
+            std::vector<V> v((size_t)std::max<long long>(total, 1), V(0));
+            for (int s = 0; s < ns; ++s)
+                for (int l = 0; l < 64; ++l) {
+                    const int r = s * 64 + l;
+                    if (r >= n) break;
+                    const int b = M.ptr[r], len = M.ptr[r + 1] - b;
+                    for (int k = 0; k < wid[s]; ++k) {
+                        const size_t e = (size_t)off[s] + 64 * (size_t)k + l;
+                        if (k < len) {
+                            c[e] = M.col[b + k];
+                            v[e] = V(M.val[b + k]);
+                        } else {
+                            c[e] = len > 0 ? M.col[b] : 0;
+                        }
+                    }
+                }
+            soff.alloc(ns);
+            swid.alloc(ns);
+            col.alloc(c.size());
+            val.alloc(v.size());
+            HIPCHK(hipMemcpy(soff.p, off.data(), ns * sizeof(int), hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(swid.p, wid.data(), ns * sizeof(int), hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(col.p, c.data(), c.size() * sizeof(int), hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(val.p, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice));
         }
-        CsrOp<V> op() const { return CsrOp<V>{n, ptr.p, col.p, val.p}; }
+        CsrOp<V> op() const { return CsrOp<V>{n, soff.p, swid.p, col.p, val.p}; }
     };
 
     static void upload_conv(T* dst, const std::vector<double>& src) {
@@ -1722,7 +1752,7 @@ class CsrSolver : public SolverBase {
     }
 
     CsrOp<T> fineP() const {
-        return L_ > 0 ? P_l_[L_ - 1].op() : CsrOp<T>{N_[L_], nullptr, nullptr, nullptr};
+        return L_ > 0 ? P_l_[L_ - 1].op() : CsrOp<T>{N_[L_], nullptr, nullptr, nullptr, nullptr};
     }
     const T* fine_Y() const { return L_ > 0 ? Y_[L_ - 1].p : nullptr; }
     T* Pslot(int j) { return P_.p + (size_t)j * pstride_; }
@@ -1806,7 +1836,7 @@ class CsrSolver : public SolverBase {
                 Y_[l + 1].p + (l + 1), even_up(l + 2), omega, two);
         }
         k_csr_restrict_smooth<T, T, T><<<blocks(N_[0]), kBlock, 0, stream_>>>(
-            ctl, CsrOp<T>{0, nullptr, nullptr, nullptr}, static_cast<const T*>(nullptr), nullptr, 0, A_[0].op(),
+            ctl, CsrOp<T>{0, nullptr, nullptr, nullptr, nullptr}, static_cast<const T*>(nullptr), nullptr, 0, A_[0].op(),
             D_[0].p, g_[0].p, Y_[0].p, even_up(1), omega, two);
         enqueue_prolong(ctl);
     }

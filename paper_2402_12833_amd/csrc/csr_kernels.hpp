@@ -13,19 +13,36 @@
 
 namespace amg {
 
+// A sparse matrix given in CSR, stored on the device sliced: slices of 64
+// consecutive rows (one wavefront), each padded to its longest row and
+// stored column by column (entry k of row 64 s + l at soff[s] + 64 k + l),
+// so that the 64 lanes of a wave read 64 consecutive entries per step and
+// loop the same number of times.  A row's stored entries come in its CSR
+// order, then padding of weight 0 at one of the row's own columns, so every
+// row sum is the CSR one plus exact zeros.
 template <typename T>
 struct CsrOp {
     int n;              // rows
-    const int* ptr;     // n + 1
+    const int* soff;    // per slice: first entry
+    const int* swid;    // per slice: entries per row (padded)
     const int* col;
     const T* val;
 };
 
+// f(column, value) for the stored entries of row i in order.  The rows of a
+// wave must be the 64 rows of one slice (loops start waves at multiples of
+// 64), so soff and swid are wave-uniform.
+template <typename T, typename F>
+__device__ __forceinline__ void for_row(const CsrOp<T>& A, int i, F&& f) {
+    const int s = i >> 6;
+    const int off = A.soff[s] + (i & 63), w = A.swid[s];
+    for (int k = 0; k < w; ++k) f(A.col[off + 64 * k], A.val[off + 64 * k]);
+}
+
 template <typename C, typename T, typename F>
 __device__ __forceinline__ C csr_row_dot(const CsrOp<T>& A, int i, F&& u) {
     C acc = C(0);
-    const int e = A.ptr[i + 1];
-    for (int k = A.ptr[i]; k < e; ++k) acc += C(A.val[k]) * C(u(A.col[k]));
+    for_row(A, i, [&](int j, T v) { acc += C(v) * C(u(j)); });
     return acc;
 }
 
@@ -145,13 +162,11 @@ __global__ void __launch_bounds__(kBlock) k_csr_prolong(const Ctl* __restrict__ 
         T acc[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) acc[c] = T(0);
-        const int e = P.ptr[i + 1];
-        for (int k = P.ptr[i]; k < e; ++k) {
-            const T w = P.val[k];
-            const T* y = Yc + (size_t)P.col[k] * SC;
+        for_row(P, i, [&](int j, T w) {
+            const T* y = Yc + (size_t)j * SC;
 #pragma unroll
             for (int c = 0; c < NC; ++c) acc[c] += w * y[c];
-        }
+        });
 #pragma unroll
         for (int c = 0; c < NC; ++c) Yf[(size_t)i * SF + c] = acc[c];
     }
@@ -166,13 +181,11 @@ __device__ __forceinline__ void csr_fine_z(const CsrOp<T>& P, const T* __restric
         constexpr int SY = even_up(NB - 1);
 #pragma unroll
         for (int c = 0; c < NB - 1; ++c) z[c] = T(0);
-        const int e = P.ptr[i + 1];
-        for (int k = P.ptr[i]; k < e; ++k) {
-            const T w = P.val[k];
-            const T* y = Y + (size_t)P.col[k] * SY;
+        for_row(P, i, [&](int j, T w) {
+            const T* y = Y + (size_t)j * SY;
 #pragma unroll
             for (int c = 0; c < NB - 1; ++c) z[c] += w * y[c];
-        }
+        });
     }
     z[NB - 1] = cL[i];
 }
@@ -283,13 +296,11 @@ __global__ void __launch_bounds__(kBlock) k_csr_spmm_gram(const Ctl* __restrict_
         T q[S], pv[S], nb[S];
 #pragma unroll
         for (int c = 0; c < S; ++c) q[c] = T(0);
-        const int e = A.ptr[i + 1];
-        for (int k = A.ptr[i]; k < e; ++k) {
-            const T w = A.val[k];
-            load_node<T, S>(P + (size_t)A.col[k] * S, nb);
+        for_row(A, i, [&](int j, T w) {
+            load_node<T, S>(P + (size_t)j * S, nb);
 #pragma unroll
             for (int c = 0; c < S; ++c) q[c] += w * nb[c];
-        }
+        });
         store_node<T, S>(Q + (size_t)i * S, q);
         load_node<T, S>(P + (size_t)i * S, pv);
         const double ri = r[i];
