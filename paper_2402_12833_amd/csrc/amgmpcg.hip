@@ -849,6 +849,10 @@ class Solver : public SolverBase {
             enqueue_mg_fused(ctl, r);
             return;
         }
+        if (L_ > 0 && !net_) {
+            enqueue_mg_paired(ctl, r);
+            return;
+        }
         if (prof_on_ || !side_ || !net_) {
             enqueue_fine(ctl, r);
             enqueue_coarse(ctl, r);
@@ -951,6 +955,46 @@ class Solver : public SolverBase {
         }
     }
 
+    // nu > 2 and no network: the restriction chain, then each sweep index
+    // of every level (finest and all coarse) in one launch, then the
+    // prolongation chain; the buffers alternate as in the separate launches.
+    void enqueue_mg_paired(const Ctl* ctl, const double* r) {
+        const int L = L_;
+        const T omega = T(opt_.omega);
+        const int extra = opt_.nu - 2;
+        mark(kSecRestrict);
+        enqueue_restrict_chain(ctl, r);
+        mark(kSecCoarseSmooth);
+        CoarseLevels<T> cl = coarse_arg(0);     // first sweeps into c_
+        const int nbc = (cl.blk_off[L] + kNumXcd - 1) / kNumXcd * kNumXcd;
+        T* first = (extra % 2 == 0) ? cL_.p : cL2_.p;
+        T* other = (extra % 2 == 0) ? cL2_.p : cL_.p;
+        k_sweep_levels<DIM, T><<<nbc + FB_, kBlock, 0, stream_>>>(ctl, cl, nbc, omega, 0, 1, rows_, fop_, r, nullptr,
+                                                                  first);
+        T* cur = first;
+        for (int s2 = 0; s2 < extra; ++s2) {
+            const bool last = s2 == extra - 1;
+            const bool from_c = (s2 % 2) == 0;
+            for (int l = 0; l < L; ++l) {
+                cl.cin[l] = from_c ? c_[l].p : c2_[l].p;
+                if (last) {
+                    cl.cout[l] = Y_[l].p + l;
+                    cl.cstride[l] = even_up(l + 1);
+                } else {
+                    cl.cout[l] = from_c ? c2_[l].p : c_[l].p;
+                    cl.cstride[l] = 1;
+                }
+            }
+            T* nxt = (cur == first) ? other : first;
+            k_sweep_levels<DIM, T><<<nbc + FB_, kBlock, 0, stream_>>>(ctl, cl, nbc, omega, 1, 1, rows_, fop_, r, cur,
+                                                                      nxt);
+            cur = nxt;
+        }
+        cL_final_ = cur;
+        mark(kSecProlong);
+        enqueue_prolong(ctl);
+    }
+
     // the finest level's smoother output cL_final_ (nu sweeps from zero)
     void enqueue_fine(const Ctl* ctl, const double* r) {
         const T omega = T(opt_.omega);
@@ -972,6 +1016,34 @@ class Solver : public SolverBase {
         }
     }
 
+    // restriction chain: big levels one launch each, the small ones in one block
+    void enqueue_restrict_chain(const Ctl* ctl, const double* r) {
+        const int L = L_;
+        const T omega = T(opt_.omega);
+        const int l = L - 1;
+        k_restrict<DIM, double, T><<<(N_[l] + kBlock - 1) / kBlock, kBlock, 0, stream_>>>(
+            ctl, r, n_axis[L], g_[l].p, n_axis[l], N_[l], diag(l), c1_[l].p, omega, cst_[l]);
+        int m = L - 2;
+        for (; m >= 0 && N_[m] > kRestrictTailMax; --m)
+            k_restrict<DIM, T, T><<<(N_[m] + kBlock - 1) / kBlock, kBlock, 0, stream_>>>(
+                ctl, g_[m + 1].p, n_axis[m + 1], g_[m].p, n_axis[m], N_[m], diag(m), c1_[m].p, omega, cst_[m]);
+        if (m >= 0) {
+            RestrictChain<T> ch{};
+            for (; m >= 0; --m) {
+                const int q = ch.count++;
+                ch.nf[q] = n_axis[m + 1];
+                ch.nc[q] = n_axis[m];
+                ch.Nc[q] = N_[m];
+                ch.gf[q] = g_[m + 1].p;
+                ch.gc[q] = g_[m].p;
+                ch.D[q] = diag(m);
+                ch.dconst[q] = cst_[m];
+                ch.c1[q] = c1_[m].p;
+            }
+            k_restrict_tail<DIM, T><<<1, kTailBlock, 0, stream_>>>(ctl, ch, omega);
+        }
+    }
+
     // the coarse levels: restriction chain, smoothing, prolongation chain
     void enqueue_coarse(const Ctl* ctl, const double* r) {
         const int L = L_;
@@ -980,32 +1052,8 @@ class Solver : public SolverBase {
         const int two = nu >= 2 ? 1 : 0;
         const int extra = nu > 2 ? nu - 2 : 0;
         if (L == 0) return;
-        // restriction chain: big levels one launch each, the small ones in one block
         mark(kSecRestrict);
-        {
-            const int l = L - 1;
-            k_restrict<DIM, double, T><<<(N_[l] + kBlock - 1) / kBlock, kBlock, 0, stream_>>>(
-                ctl, r, n_axis[L], g_[l].p, n_axis[l], N_[l], diag(l), c1_[l].p, omega, cst_[l]);
-            int m = L - 2;
-            for (; m >= 0 && N_[m] > kRestrictTailMax; --m)
-                k_restrict<DIM, T, T><<<(N_[m] + kBlock - 1) / kBlock, kBlock, 0, stream_>>>(
-                    ctl, g_[m + 1].p, n_axis[m + 1], g_[m].p, n_axis[m], N_[m], diag(m), c1_[m].p, omega, cst_[m]);
-            if (m >= 0) {
-                RestrictChain<T> ch{};
-                for (; m >= 0; --m) {
-                    const int q = ch.count++;
-                    ch.nf[q] = n_axis[m + 1];
-                    ch.nc[q] = n_axis[m];
-                    ch.Nc[q] = N_[m];
-                    ch.gf[q] = g_[m + 1].p;
-                    ch.gc[q] = g_[m].p;
-                    ch.D[q] = diag(m);
-                    ch.dconst[q] = cst_[m];
-                    ch.c1[q] = c1_[m].p;
-                }
-                k_restrict_tail<DIM, T><<<1, kTailBlock, 0, stream_>>>(ctl, ch, omega);
-            }
-        }
+        enqueue_restrict_chain(ctl, r);
         // all coarse levels smoothed in one launch (per sweep); the final sweep
         // writes c_l into the last column of the level's block carry
         mark(kSecCoarseSmooth);

@@ -920,18 +920,55 @@ __device__ __forceinline__ T coarse_smooth_at(const CoarseOp<T>& op, const T* __
     return cin[idx] + omega * ((gi - Ac) / Di);
 }
 
+// Block b of a level-fused coarse pass (blocks past blk_off[nlev] idle).
 template <int DIM, typename T>
-__global__ void __launch_bounds__(kBlock) k_coarse_smooth(const Ctl* __restrict__ ctl, CoarseLevels<T> L,
-                                                          T omega, int mode, int two_sweeps) {
-    if (ctl->state != 0) return;
+__device__ __forceinline__ void coarse_levels_block(const CoarseLevels<T>& L, int b, T omega, int mode,
+                                                    int two_sweeps) {
     int l = 0;
-    while (l + 1 < L.nlev && (int)blockIdx.x >= L.blk_off[l + 1]) ++l;
-    const int idx = (blockIdx.x - L.blk_off[l]) * kBlock + threadIdx.x;
+    while (l + 1 < L.nlev && b >= L.blk_off[l + 1]) ++l;
+    const int idx = (b - L.blk_off[l]) * kBlock + threadIdx.x;
     const int N = L.N[l];
     if (idx >= N) return;
     CoarseOp<T> op{L.n[l], N, L.coef[l], L.cst[l]};
     L.cout[l][(size_t)idx * L.cstride[l]] =
         coarse_smooth_at<DIM, T>(op, L.g[l], L.c1[l], L.cin[l], idx, omega, mode, two_sweeps);
+}
+
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kBlock) k_coarse_smooth(const Ctl* __restrict__ ctl, CoarseLevels<T> L,
+                                                          T omega, int mode, int two_sweeps) {
+    if (ctl->state != 0) return;
+    coarse_levels_block<DIM, T>(L, (int)blockIdx.x, omega, mode, two_sweeps);
+}
+
+// One sweep index of every level in one launch (nu > 2): blocks [0, nbc)
+// the level-fused coarse pass, the blocks after them the same pass on the
+// finest level (mode 0: the first min(nu, 2) sweeps from r into fout;
+// mode 1: one further sweep fin -> fout), over the row walk of grid - nbc
+// blocks (nbc a multiple of 8 keeps the rows' XCD bands).  The levels are
+// independent, so the sweeps of one index need no order among them.
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kBlock) k_sweep_levels(const Ctl* __restrict__ ctl, CoarseLevels<T> L, int nbc,
+                                                         T omega, int mode, int two, Rows R, FineOp<T> op,
+                                                         const double* __restrict__ r, const T* __restrict__ fin,
+                                                         T* __restrict__ fout) {
+    if (ctl->state != 0) return;
+    if ((int)blockIdx.x < nbc) {
+        coarse_levels_block<DIM, T>(L, (int)blockIdx.x, omega, mode, two);
+        return;
+    }
+    const Band b = row_band_of(R.total, (int)blockIdx.x - nbc, (int)gridDim.x - nbc);
+    for (int w = b.start; w < b.end; w += b.stride) {
+        Idx<DIM> p;
+        int idx;
+        if (!row_item<DIM>(R, w, p, idx)) continue;
+        if (mode == 0) {
+            fout[idx] = fine_smooth_at<DIM, T, double>(op, r, idx, p, omega, two);
+        } else {
+            const T res = T(r[idx]) - fine_apply<DIM, T>(op, fin, idx, p);
+            fout[idx] = fin[idx] + omega * (res * fine_invdiag<DIM>(op, idx));
+        }
+    }
 }
 
 // Block carry up one level: Y_{l+1}[:, 0..NC-1] = P Y_l[:, 0..NC-1], both
