@@ -663,7 +663,7 @@ class Solver : public SolverBase {
             enqueue_mg(cf, r_.p);
             timed([&] {
                 k_fine_W<DIM, T, NB, NE><<<FBG_, kBlock, 0, stream_>>>(cf, rows_, fine_Y(), nc, cL_final_, dl(), dflag(),
-                                                                      Q_.p, part_W());
+                                                                      Q_.p, 0, part_W(), 0, FBG_);
             });
             timed([&] {
                 k_update_xP<DIM, T, NB, NE><<<xp_grid<NB>(), kBlock, 0, stream_>>>(cf, rows_, fine_Y(), nc, cL_final_, dl(),
@@ -1213,9 +1213,10 @@ class Solver : public SolverBase {
             k_update_r<T, NB><<<FB_, kBlock, 0, s>>>(ctl_, N, Qslot(cur), d_alpha(), r_.p, part_rho());
             enqueue_mg(ctl_, r_.p);
             mark(kSecFineW);
-            for (int q = 0; q < m_; ++q)
-                k_fine_W<DIM, T, NB, NE><<<FBG_, kBlock, 0, s>>>(ctl_, rows_, fine_Y(), nc, cL_final_, dl(), dflag(),
-                                                             Qslot(q), part_Wslot(q));
+            // W_j for every stored block of the window in one launch
+            k_fine_W<DIM, T, NB, NE><<<m_ * FBG_, kBlock, 0, s>>>(
+                ctl_, rows_, fine_Y(), nc, cL_final_, dl(), dflag(), Qslot(0), pstride_, part_Wslot(0),
+                (size_t)(part_Wslot(1) - part_Wslot(0)), FBG_);
             mark(kSecReduceBeta);
             k_reduce_beta<NB><<<1, kRedBlock, 0, s>>>(ctl_, part_rho(), FB_, part_Wslot(0), FBG_, m_, cur,
                                                    d_Gplus(0), d_beta(0), hist_cap_ ? rhist_.p : nullptr,

@@ -41,11 +41,12 @@ struct Ctl {
 // Logical block index so that each XCD (blockIdx % 8) owns a contiguous range
 // of logical blocks, hence a contiguous slab of the grid: stencil neighbours in
 // y and z are then mostly produced and consumed inside the same XCD's L2.
-__device__ __forceinline__ int xcd_block(int nblocks) {
-    const int b = blockIdx.x;
+__device__ __forceinline__ int xcd_block_of(int b, int nblocks) {
     if (nblocks % kNumXcd) return b;
     return (b % kNumXcd) * (nblocks / kNumXcd) + b / kNumXcd;
 }
+
+__device__ __forceinline__ int xcd_block(int nblocks) { return xcd_block_of((int)blockIdx.x, nblocks); }
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

@@ -1152,20 +1152,29 @@ __global__ void __launch_bounds__(kTailBlock) k_tail_smooth(const Ctl* __restric
     prolong_chain_block<DIM, T>(up);
 }
 
-// W = Q_k^T Z_{k+1} partial sums (NB x NB, entry a*NB+c = Q column a . z^c).
+// W_j = Q_j^T Z_{k+1} partial sums (NB x NB, entry a*NB+c = Q_j column
+// a . z^c) for the stored blocks j of the window in one launch: blocks
+// [j nbs, (j+1) nbs) work on slot j (Q + j qstride, partials at
+// part + j pstride), each range a full row walk of nbs blocks (nbs a
+// multiple of 8 keeps every block on its XCD band).
 template <int DIM, typename T, int NB, int NE>
 __global__ void __launch_bounds__(kBlock) k_fine_W(const Ctl* __restrict__ ctl, Rows R, const T* __restrict__ Y,
                                                    int nc, const T* __restrict__ cL, const T* __restrict__ dl,
                                                    const int* __restrict__ dflag, const T* __restrict__ Q,
-                                                   double* __restrict__ part) {
+                                                   size_t qstride, double* __restrict__ part, size_t pstride,
+                                                   int nbs) {
     if (ctl->state != 0) return;
     const bool dzero = NE && *dflag != 0;
     constexpr int S = even_up(NB);
-    const int lb = xcd_block(gridDim.x);
+    const int j = (int)blockIdx.x / nbs, bj = (int)blockIdx.x - j * nbs;
+    Q += j * qstride;
+    part += j * pstride;
+    const int lb = xcd_block_of(bj, nbs);
     double w[NB * NB];
 #pragma unroll
     for (int q = 0; q < NB * NB; ++q) w[q] = 0.0;
-    ROW_LOOP(R, lb) {
+    const Band band = row_band_of(R.total, bj, nbs);
+    for (int w_ = band.start; w_ < band.end; w_ += band.stride) {
         Idx<DIM> p;
         int idx;
         const bool act = row_item<DIM>(R, w_, p, idx);
@@ -1181,7 +1190,7 @@ __global__ void __launch_bounds__(kBlock) k_fine_W(const Ctl* __restrict__ ctl, 
             for (int c = 0; c < NB; ++c) w[a * NB + c] += qa * double(z[c]);
         }
     }
-    block_sum_store<NB * NB>(w, part, gridDim.x, lb);
+    block_sum_store<NB * NB>(w, part, nbs, lb);
 }
 
 // The stored direction blocks of the truncation window (a ring of m slots).
