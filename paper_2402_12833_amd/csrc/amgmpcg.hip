@@ -56,6 +56,7 @@ struct ApiError : std::runtime_error {
 constexpr int kMaxFineBlocks = AMG_FINE_BLOCKS;   // blocks of the fine-level kernels (multiple of 8)
 constexpr int kTailMax = 4096;          // prolongation outputs up to this size: single-block chain
 constexpr int kRestrictTailMax = 512;   // restriction outputs up to this size: single-block chain
+constexpr int kProlong2Max = 65536;     // two carry steps in one launch up to this many target nodes
 constexpr int kPartRow = 2 + 1 + kMaxNB * kMaxNB + (kMaxNB * (kMaxNB + 1) / 2 + kMaxNB) + 1;
 
 // Device bytes held by the DevBufs of this thread (a handle's footprint is
@@ -819,6 +820,23 @@ class Solver : public SolverBase {
         return cl;
     }
 
+    // Y_{l+2}[:, 0..l+1] from Y_l and c_{l+1} in one launch (k_prolong2).
+    void launch_prolong2(const Ctl* ctl, int l) {
+        const int grid = (N_[l + 2] + kBlock - 1) / kBlock;
+        const T* Yc = Y_[l].p;
+        const T* Ym = Y_[l + 1].p;
+        T* Yf = Y_[l + 2].p;
+        const int nc = n_axis[l], nm = n_axis[l + 1], nf = n_axis[l + 2], Nf = N_[l + 2];
+        switch (l + 1) {
+            case 1: k_prolong2<DIM, T, 1><<<grid, kBlock, 0, stream_>>>(ctl, Yc, nc, Ym, nm, Yf, nf, Nf); break;
+            case 2: k_prolong2<DIM, T, 2><<<grid, kBlock, 0, stream_>>>(ctl, Yc, nc, Ym, nm, Yf, nf, Nf); break;
+            case 3: k_prolong2<DIM, T, 3><<<grid, kBlock, 0, stream_>>>(ctl, Yc, nc, Ym, nm, Yf, nf, Nf); break;
+            case 4: k_prolong2<DIM, T, 4><<<grid, kBlock, 0, stream_>>>(ctl, Yc, nc, Ym, nm, Yf, nf, Nf); break;
+            case 5: k_prolong2<DIM, T, 5><<<grid, kBlock, 0, stream_>>>(ctl, Yc, nc, Ym, nm, Yf, nf, Nf); break;
+            default: k_prolong2<DIM, T, 6><<<grid, kBlock, 0, stream_>>>(ctl, Yc, nc, Ym, nm, Yf, nf, Nf); break;
+        }
+    }
+
     // Y_{l+1}[:, 0..l] = P Y_l (l+1 columns).
     void launch_prolong(const Ctl* ctl, int l) {
         const int grid = (N_[l + 1] + kBlock - 1) / kBlock;
@@ -945,7 +963,16 @@ class Solver : public SolverBase {
             k_tail_smooth<DIM, T><<<1 + nbt, kTailBlock, 0, stream_>>>(ctl, ch, sc, smooth_level(m + 1), up, omega,
                                                                       two);
             mark(kSecProlong);
-            for (int l = m; l + 1 < L; ++l) launch_prolong(ctl, l);
+            for (int l = m; l + 1 < L;) {
+                // two small carry steps in one launch where the level two up is small
+                if (l + 2 < L && N_[l + 2] <= kProlong2Max) {
+                    launch_prolong2(ctl, l);
+                    l += 2;
+                } else {
+                    launch_prolong(ctl, l);
+                    l += 1;
+                }
+            }
         } else {
             const int nbs = (N_[0] + kBlock - 1) / kBlock;
             k_restrict_coarse_smooth<DIM, T><<<nbs, kBlock, 0, stream_>>>(ctl, RestrictStep<T, T>{}, 0,

@@ -423,9 +423,9 @@ __device__ __forceinline__ XPar xparents(int f, int nc) {
 
 // Interpolate all S columns of a node-major coarse block (stride S) at a fine
 // node; the y/z parents are uniform across the wavefront.
-template <int DIM, typename T, int S>
-__device__ __forceinline__ void interp_block(const T* __restrict__ Y, int nc, const XPar& px, const Par& py,
-                                             const Par& pz, T (&z)[S]) {
+template <int DIM, typename T, int S, typename Node>
+__device__ __forceinline__ void interp_block_fn(Node&& node, const XPar& px, const Par& py, const Par& pz,
+                                                T (&z)[S]) {
     // Two parents per axis always: a missing second parent takes weight 0
     // and the first one's address, so all node loads are unconditional and
     // issue together; the zero terms add exactly 0 in the same order.
@@ -445,16 +445,24 @@ __device__ __forceinline__ void interp_block(const T* __restrict__ Y, int nc, co
             const bool ylo = b == 0 || py.cnt < 2;
             const int J = ylo ? py.lo : py.hi;
             const T wy = b == 0 ? T(py.wlo) : (py.cnt < 2 ? T(0) : T(py.whi));
-            const size_t rowbase = (size_t)nc * (J + (size_t)nc * K);
             T lo[S], hi[S];
-            load_node<T, S>(Y + (rowbase + px.lo) * S, lo);
-            load_node<T, S>(Y + (rowbase + px.hi) * S, hi);
+            node(px.lo, J, K, lo);
+            node(px.hi, J, K, hi);
 #pragma unroll
             for (int c = 0; c < S; ++c) plane[c] += wy * (T(px.wlo) * lo[c] + T(px.whi) * hi[c]);
         }
 #pragma unroll
         for (int c = 0; c < S; ++c) z[c] += wz * plane[c];
     }
+}
+
+// Interpolation of a node-major coarse block Y (S values per node).
+template <int DIM, typename T, int S>
+__device__ __forceinline__ void interp_block(const T* __restrict__ Y, int nc, const XPar& px, const Par& py,
+                                             const Par& pz, T (&z)[S]) {
+    interp_block_fn<DIM, T, S>(
+        [&](int I, int J, int K, T (&o)[S]) { load_node<T, S>(Y + ((size_t)nc * (J + (size_t)nc * K) + I) * S, o); },
+        px, py, pz, z);
 }
 
 // Directions at one fine node: the NB - NE level corrections, z[c] for
@@ -985,6 +993,42 @@ __device__ __forceinline__ void prolong_at(const T* __restrict__ Yc, int nc, T* 
     T* o = Yf + (size_t)idx * SF;
 #pragma unroll
     for (int c = 0; c < NC; ++c) o[c] = z[c];
+}
+
+// Block carry two levels up in one launch (level l -> l+2, NC = l + 1
+// columns in Y_l): Y_{l+2}[:, 0..NC] = P [P Y_l | c_{l+1}] without storing
+// level l+1's carried columns.  Each parent row of level l+1 is formed where
+// it is needed exactly as the one-level carry stores it (the same
+// interpolation from level l, then its own smoothed value c_{l+1}, already
+// in Y_{l+1}, and the zero padding), so the results are those of two
+// one-level launches.
+template <int DIM, typename T, int NC>
+__global__ void __launch_bounds__(kBlock) k_prolong2(const Ctl* __restrict__ ctl, const T* __restrict__ Yc, int nc,
+                                                     const T* __restrict__ Ym, int nm, T* __restrict__ Yf, int nf,
+                                                     int Nf) {
+    if (ctl->state != 0) return;
+    const int idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= Nf) return;
+    constexpr int SC = even_up(NC), SM = even_up(NC + 1), SF = even_up(NC + 2);
+    const Idx<DIM> p = decomp<DIM>(idx, nf);
+    const XPar px = xparents(p.i, nm);
+    const Par py = parents(p.j, nm);
+    const Par pz = DIM == 3 ? parents(p.k, nm) : Par{0, 0, 1.f, 0.f, 1};
+    auto mid = [&](int I, int J, int K, T (&row)[SM]) {
+        const XPar qx = xparents(I, nc);
+        const Par qy = parents(J, nc);
+        const Par qz = DIM == 3 ? parents(K, nc) : Par{0, 0, 1.f, 0.f, 1};
+        T zc[SC];
+        interp_block<DIM, T, SC>(Yc, nc, qx, qy, qz, zc);
+        const T cm = Ym[((size_t)nm * (J + (size_t)nm * K) + I) * SM + NC];
+#pragma unroll
+        for (int c = 0; c < SM; ++c) row[c] = c < NC ? zc[c < SC ? c : 0] : (c == NC ? cm : T(0));
+    };
+    T z[SM];
+    interp_block_fn<DIM, T, SM>(mid, px, py, pz, z);
+    T* o = Yf + (size_t)idx * SF;
+#pragma unroll
+    for (int c = 0; c <= NC; ++c) o[c] = z[c];
 }
 
 template <int DIM, typename T, int NC>
