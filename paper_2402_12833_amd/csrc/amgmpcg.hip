@@ -1742,46 +1742,21 @@ class CsrSolver : public SolverBase {
         int n = 0;
         DevBuf<int> soff, swid, col;
         DevBuf<V> val;
-        // the sliced layout of CsrOp: slices of 64 rows, each padded to its
-        // longest row, column by column; padding has weight 0 at the row's
-        // first column (column 0 for an empty row)
+        // the sliced layout of CsrOp (host::csr_sliced)
         void upload(const host::Csr& M) {
             n = M.n;
-            const int ns = (n + 63) / 64;
-            std::vector<int> off(ns), wid(ns);
-            long long total = 0;
-            for (int s = 0; s < ns; ++s) {
-                int w = 0;
-                for (int r = s * 64; r < std::min(n, s * 64 + 64); ++r) w = std::max(w, M.ptr[r + 1] - M.ptr[r]);
-                off[s] = (int)total;
-                wid[s] = w;
-                total += 64LL * w;
-                if (total > INT32_MAX) throw ApiError(AMGMPCG_INVALID_ARG, "sparse matrix too large");
-            }
-            std::vector<int> c((size_t)std::max<long long>(total, 1), 0);
-            std::vector<V> v((size_t)std::max<long long>(total, 1), V(0));
-            for (int s = 0; s < ns; ++s)
-                for (int l = 0; l < 64; ++l) {
-                    const int r = s * 64 + l;
-                    if (r >= n) break;
-                    const int b = M.ptr[r], len = M.ptr[r + 1] - b;
-                    for (int k = 0; k < wid[s]; ++k) {
-                        const size_t e = (size_t)off[s] + 64 * (size_t)k + l;
-                        if (k < len) {
-                            c[e] = M.col[b + k];
-                            v[e] = V(M.val[b + k]);
-                        } else {
-                            c[e] = len > 0 ? M.col[b] : 0;
-                        }
-                    }
-                }
-            soff.alloc(ns);
-            swid.alloc(ns);
-            col.alloc(c.size());
+            host::Sliced S;
+            if (!host::csr_sliced(M, S)) throw ApiError(AMGMPCG_INVALID_ARG, "sparse matrix too large");
+            std::vector<V> v(S.val.begin(), S.val.end());
+            soff.alloc(S.off.size());
+            swid.alloc(S.wid.size());
+            col.alloc(S.col.size());
             val.alloc(v.size());
-            HIPCHK(hipMemcpy(soff.p, off.data(), ns * sizeof(int), hipMemcpyHostToDevice));
-            HIPCHK(hipMemcpy(swid.p, wid.data(), ns * sizeof(int), hipMemcpyHostToDevice));
-            HIPCHK(hipMemcpy(col.p, c.data(), c.size() * sizeof(int), hipMemcpyHostToDevice));
+            if (!S.off.empty()) {
+                HIPCHK(hipMemcpy(soff.p, S.off.data(), S.off.size() * sizeof(int), hipMemcpyHostToDevice));
+                HIPCHK(hipMemcpy(swid.p, S.wid.data(), S.wid.size() * sizeof(int), hipMemcpyHostToDevice));
+            }
+            HIPCHK(hipMemcpy(col.p, S.col.data(), S.col.size() * sizeof(int), hipMemcpyHostToDevice));
             HIPCHK(hipMemcpy(val.p, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice));
         }
         CsrOp<V> op() const { return CsrOp<V>{n, soff.p, swid.p, col.p, val.p}; }

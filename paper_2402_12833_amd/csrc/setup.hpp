@@ -154,6 +154,51 @@ struct Csr {
     int64_t nnz() const { return (int64_t)col.size(); }
 };
 
+// The sliced layout the device kernels read a CSR matrix in: slices of 64
+// consecutive rows, each padded to its longest row and stored column by
+// column (entry k of row 64 s + l at off[s] + 64 k + l).  A row's entries
+// come in CSR order, then padding of weight 0 at the row's first column
+// (column 0 for an empty row), so a row sum over the layout is the CSR one
+// followed by exact zeros.  False when the layout would not fit int32
+// offsets.
+struct Sliced {
+    std::vector<int> off, wid, col;
+    std::vector<double> val;
+};
+
+inline bool csr_sliced(const Csr& M, Sliced& S) {
+    const int ns = (M.n + 63) / 64;
+    S.off.assign(ns, 0);
+    S.wid.assign(ns, 0);
+    long long total = 0;
+    for (int s = 0; s < ns; ++s) {
+        int w = 0;
+        for (int r = s * 64; r < std::min(M.n, s * 64 + 64); ++r) w = std::max(w, M.ptr[r + 1] - M.ptr[r]);
+        S.off[s] = (int)total;
+        S.wid[s] = w;
+        total += 64LL * w;
+        if (total > INT32_MAX) return false;
+    }
+    S.col.assign((size_t)std::max<long long>(total, 1), 0);
+    S.val.assign((size_t)std::max<long long>(total, 1), 0.0);
+    for (int s = 0; s < ns; ++s)
+        for (int l = 0; l < 64; ++l) {
+            const int r = s * 64 + l;
+            if (r >= M.n) break;
+            const int b = M.ptr[r], len = M.ptr[r + 1] - b;
+            for (int k = 0; k < S.wid[s]; ++k) {
+                const size_t e = (size_t)S.off[s] + 64 * (size_t)k + l;
+                if (k < len) {
+                    S.col[e] = M.col[b + k];
+                    S.val[e] = M.val[b + k];
+                } else {
+                    S.col[e] = len > 0 ? M.col[b] : 0;
+                }
+            }
+        }
+    return true;
+}
+
 inline Csr csr_transpose(const Csr& A, double scale = 1.0) {
     Csr T;
     T.n = A.m;
