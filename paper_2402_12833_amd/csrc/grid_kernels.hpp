@@ -1131,7 +1131,9 @@ __global__ void __launch_bounds__(kBlock) k_restrict_fine_smooth(const Ctl* __re
                                                                  T* __restrict__ c, T omega, int two) {
     if (ctl->state != 0) return;
     if ((int)blockIdx.x < nbr) {
-        const int idx = blockIdx.x * kBlock + threadIdx.x;
+        // nbr is a multiple of 8: XCD x restricts the x-th band of coarse
+        // nodes, which lies over the band of fine rows its smoother blocks read
+        const int idx = xcd_block_of((int)blockIdx.x, nbr) * kBlock + threadIdx.x;
         if (idx < rs.Nc) restrict_step<DIM>(rs, idx, omega);
         return;
     }
