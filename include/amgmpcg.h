@@ -264,9 +264,13 @@ int amgmpcg_time_kernels(amgmpcg_handle* h, int32_t reps, double* ms_out, int32_
  * that ran in full (*samples of them; the last iteration, whose SpMM and
  * alpha step the stop flag skips, is left out), of: update_r, fine_smooth,
  * restrict, coarse_smooth, prolong, learned, fine_W, reduce_beta,
- * update_xP, refresh, spmm_gram, reduce_alpha, whole iteration (13
- * entries, *count = 13; 0 for a group that does not run).  b, x, tol, maxit
- * and the result as for amgmpcg_solve (info->solve_ms = 0). */
+ * update_xP, refresh, spmm_gram, reduce_alpha, whole iteration, and the
+ * x/P update kernel alone (14 entries, *count = 14; 0 for a group that does
+ * not run).  The groups are spans between events recorded on the stream, so
+ * they include the launch latency; the last entry comes from events bound
+ * to the x/P update's dispatch itself (hipExtLaunchKernel start and stop
+ * events), the kernel's own duration.  b, x, tol, maxit and the result as
+ * for amgmpcg_solve (info->solve_ms = 0). */
 int amgmpcg_profile_solve(amgmpcg_handle* h, const double* b_dev, double* x_dev, double tol, int32_t maxit,
                           amgmpcg_info* info, double* ms_out, int32_t cap, int32_t* count, int32_t* samples);
 

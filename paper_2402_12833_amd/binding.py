@@ -394,12 +394,15 @@ class Solver:
         return {k: float(out[i]) for i, k in enumerate(self.KERNELS[: cnt.value])}
 
     SECTIONS = ("update_r", "fine_smooth", "restrict", "coarse_smooth", "prolong", "learned", "fine_W",
-                "reduce_beta", "update_xP", "refresh", "spmm_gram", "reduce_alpha", "iteration")
+                "reduce_beta", "update_xP", "refresh", "spmm_gram", "reduce_alpha", "iteration",
+                "update_xP_kernel")
 
     def profile_solve(self, b, x=None, tol: float = 1e-8, maxit: int = 0):
         """Solve with per-section HIP-event timing inside the iterations.
 
-        Returns (x, info, {section: average ms per full iteration}, samples)."""
+        Returns (x, info, {section: average ms per full iteration}, samples).
+        The sections span consecutive stream events (launch latency included);
+        "update_xP_kernel" is the x/P update's dispatch alone."""
         import torch
         if x is None:
             x = torch.zeros_like(b)

@@ -13,6 +13,8 @@
 #include <memory>
 #include <stdexcept>
 #include <string>
+#include <tuple>
+#include <utility>
 #include <vector>
 
 #include "amgmpcg.h"
@@ -49,6 +51,22 @@ struct ApiError : std::runtime_error {
                                std::to_string(__LINE__));                                              \
         }                                                                                              \
     } while (0)
+
+// Launch kernel k with the dispatch's own start and end times recorded on
+// e0 and e1 (hipExtLaunchKernel), so hipEventElapsedTime(e0, e1) is the
+// kernel's duration without the launch latency around it.  Each argument is
+// converted to the kernel's parameter type first.
+template <typename... P, typename... A>
+void launch_with_events(void (*k)(P...), dim3 grid, dim3 block, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                        A&&... a) {
+    std::tuple<P...> t{std::forward<A>(a)...};
+    void* args[sizeof...(P)];
+    std::apply([&](auto&... v) {
+        int i = 0;
+        ((args[i++] = static_cast<void*>(&v)), ...);
+    }, t);
+    HIPCHK(hipExtLaunchKernel(reinterpret_cast<const void*>(k), grid, block, args, 0, s, e0, e1, 0));
+}
 
 #ifndef AMG_FINE_BLOCKS
 #define AMG_FINE_BLOCKS 2048
@@ -506,6 +524,8 @@ class Solver : public SolverBase {
         if (ev0_) (void)hipEventDestroy(ev0_);
         if (ev1_) (void)hipEventDestroy(ev1_);
         for (hipEvent_t e : prof_ev_) (void)hipEventDestroy(e);
+        for (hipEvent_t e : xp_ev_)
+            if (e) (void)hipEventDestroy(e);
         if (ev_fork_) (void)hipEventDestroy(ev_fork_);
         if (ev_join_) (void)hipEventDestroy(ev_join_);
         if (side_) (void)hipStreamDestroy(side_);
@@ -1249,8 +1269,14 @@ class Solver : public SolverBase {
                                                    d_Gplus(0), d_beta(0), hist_cap_ ? rhist_.p : nullptr,
                                                    mixed_ ? 1 : 0);
             mark(kSecUpdateXP);
-            k_update_xP<DIM, T, NB, NE><<<xp_grid<NB>(), kBlock, 0, s>>>(ctl_, rows_, fine_Y(), nc, cL_final_, dl(), dflag(),
-                                                            window(), m_, cur, nxt, x_.p, d_alpha(), d_beta(0), 0);
+            if (prof_on_)
+                launch_with_events(k_update_xP<DIM, T, NB, NE>, dim3(xp_grid<NB>()), dim3(kBlock), s, xp_events(),
+                                   xp_ev_[1], ctl_, rows_, fine_Y(), nc, cL_final_, dl(), dflag(), window(), m_, cur,
+                                   nxt, x_.p, d_alpha(), d_beta(0), 0);
+            else
+                k_update_xP<DIM, T, NB, NE><<<xp_grid<NB>(), kBlock, 0, s>>>(ctl_, rows_, fine_Y(), nc, cL_final_, dl(),
+                                                                dflag(), window(), m_, cur, nxt, x_.p, d_alpha(),
+                                                                d_beta(0), 0);
             if (mixed_) {
                 mark(kSecRefresh);
                 k_refresh<DIM><<<FB_, kBlock, 0, s>>>(ctl_, rows_, f64_, b_.p, x_.p, r_.p, part_ref());
@@ -1279,7 +1305,11 @@ class Solver : public SolverBase {
         k_reduce_beta<1><<<1, kRedBlock, 0, s>>>(ctl_, part_rho(), FB_, part_Wslot(0), FB_, 1, 0, d_Gplus(0),
                                               d_beta(0), hist_cap_ ? rhist_.p : nullptr, mixed_ ? 1 : 0);
         mark(kSecUpdateXP);
-        k_xP1<T><<<FB_, kBlock, 0, s>>>(ctl_, N, Pslot(0), z, x_.p, d_alpha(), d_beta(0), 0);
+        if (prof_on_)
+            launch_with_events(k_xP1<T>, dim3(FB_), dim3(kBlock), s, xp_events(), xp_ev_[1], ctl_, N, Pslot(0), z,
+                               x_.p, d_alpha(), d_beta(0), 0);
+        else
+            k_xP1<T><<<FB_, kBlock, 0, s>>>(ctl_, N, Pslot(0), z, x_.p, d_alpha(), d_beta(0), 0);
         if (mixed_) {
             mark(kSecRefresh);
             k_refresh<DIM><<<FB_, kBlock, 0, s>>>(ctl_, rows_, f64_, b_.p, x_.p, r_.p, part_ref());
@@ -1379,6 +1409,14 @@ class Solver : public SolverBase {
     // mark(sec) records an event before the launches of section sec; a
     // section lasts until the next mark.  A no-op outside profile_solve, in
     // particular during graph capture.
+    // The event pair bound to the x/P update's dispatch; start event returned.
+    hipEvent_t xp_events() {
+        for (hipEvent_t& e : xp_ev_)
+            if (!e) HIPCHK(hipEventCreate(&e));
+        xp_rec_ = true;
+        return xp_ev_[0];
+    }
+
     void mark(int sec) {
         if (!prof_on_) return;
         if (prof_n_ == (int)prof_ev_.size()) {
@@ -1418,6 +1456,7 @@ class Solver : public SolverBase {
             if (hctl_->state != 0) break;
             prof_on_ = true;
             prof_n_ = 0;
+            xp_rec_ = false;
             enqueue_iteration(stream_, it);
             prof_on_ = false;
             HIPCHK(hipGetLastError());
@@ -1433,6 +1472,10 @@ class Solver : public SolverBase {
             float t = 0.f;
             HIPCHK(hipEventElapsedTime(&t, prof_ev_[0], prof_ev_[prof_n_ - 1]));
             sum[kSecEnd] += t;
+            if (xp_rec_) {
+                HIPCHK(hipEventElapsedTime(&t, xp_ev_[0], xp_ev_[1]));
+                sum[kSecXPKernel] += t;
+            }
         }
         HIPCHK(hipMemcpyAsync(x_dev, x_.p, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, stream_));
         HIPCHK(hipMemcpyAsync(hctl_, ctl_, sizeof(Ctl), hipMemcpyDeviceToHost, stream_));
@@ -1480,6 +1523,7 @@ class Solver : public SolverBase {
         kSecSpmmGram,
         kSecReduceAlpha,
         kSecEnd,          // slot of the whole iteration
+        kSecXPKernel,     // the x/P update launch alone, timed by its dispatch
         kSecCount
     };
     bool prof_on_ = false;
@@ -1488,6 +1532,8 @@ class Solver : public SolverBase {
     int prof_n_ = 0;
     std::vector<hipEvent_t> prof_ev_;
     std::vector<int> prof_sec_;
+    hipEvent_t xp_ev_[2] = {nullptr, nullptr};   // the x/P update's own dispatch (profile_solve)
+    bool xp_rec_ = false;
 
     amgmpcg_options opt_;
     hipStream_t stream_;
