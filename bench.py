@@ -253,6 +253,16 @@ def cpu_baseline(prob, max_iters=None):
     return dt * 1e3, res.iterations
 
 
+def calibration_kernel(torch):
+    """One plain elementwise kernel reading and writing 512 MiB each, the
+    known-size reference for the HBM byte counters."""
+    a = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    c = a * 2.0
+    torch.cuda.synchronize()
+    del a, c
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -264,6 +274,8 @@ def main(argv=None):
                     help="time only the U-Net inference on the 128^3 grid (committed weights) and print its line")
     ap.add_argument("--batched-only", action="store_true",
                     help="time only the 512-problem batched workload (FP32 bulk) and print its line")
+    ap.add_argument("--large-only", action="store_true",
+                    help="time only the 255^3 Poisson solve (FP64, 16.6 M DoF) and print its line")
     ap.add_argument("--calibrate", action="store_true",
                     help="end with one plain 512 MiB read + 512 MiB write elementwise kernel (counter calibration)")
     args = ap.parse_args(argv)
@@ -291,6 +303,16 @@ def main(argv=None):
                           "TFLOPs": round(gf / fms, 1), "bf16_peak_frac": round(gf / fms / 2500.0, 4)}), flush=True)
         net.close()
         sol.close()
+        return 0
+    if args.large_only:
+        bprob = W.POISSON3D_255
+        sb, _, _, msb, itb, _, _ = run_solver(amg, torch, bprob, 0, max(args.steps, 1), args.warmup)
+        _, pib = traffic_model(3, bprob.n, bprob.nlevels, 8, False)
+        print(json.dumps({"workload": "poisson3d_255", "dtype": "f64", "ms": round(msb, 4), "iterations": itb,
+                          "hbm_GBps_algorithmic": round(pib * itb / (msb * 1e-3) / 1e9, 1)}), flush=True)
+        sb.close()
+        if args.calibrate:
+            calibration_kernel(torch)
         return 0
     if args.batched_only:
         res = run_batched(amg, torch, 1, args.steps, args.warmup)
@@ -472,11 +494,7 @@ def main(argv=None):
                                          f"{cpu_it} iterations, setup excluded",
                                "cpu": platform.processor() or platform.machine()}
     if args.calibrate:
-        a = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
-        torch.cuda.synchronize()
-        c = a * 2.0
-        torch.cuda.synchronize()
-        del a, c
+        calibration_kernel(torch)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -158,24 +158,18 @@ __device__ __forceinline__ void block_reduce(double (&v)[K], double* res, int co
 }
 
 // Reduce the value-major partials part[k * nblk + b] of K values into res[k]
-// (shared memory); groups of up to 40 values, each with its loads in flight
-// together.
-template <int K>
+// (shared memory); groups of up to 40 values (values K0 .. K0 + GK - 1 here,
+// the rest in the next group), each with its loads in flight together.  Every
+// group's size is a compile-time constant, so its per-thread sums stay in
+// registers.
+template <int K, int K0 = 0>
 __device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int nblk,
                                                 double* res /* shared, K */) {
-    constexpr int GK = K <= 40 ? K : 32;
-    for (int k0 = 0; k0 < K; k0 += GK) {
-        double v[GK];
-        if (k0 + GK <= K) {
-            partial_rows<GK>(part + (size_t)k0 * nblk, nblk, v);
-        } else {
-#pragma unroll
-            for (int g = 0; g < GK; ++g) v[g] = 0.0;
-            for (int g = 0; g < K - k0; ++g)
-                for (int b = threadIdx.x; b < nblk; b += kRedBlock) v[g] += part[(size_t)(k0 + g) * nblk + b];
-        }
-        block_reduce<GK>(v, res + k0, K - k0 < GK ? K - k0 : GK);
-    }
+    constexpr int GK = K - K0 <= 40 ? K - K0 : 32;
+    double v[GK];
+    partial_rows<GK>(part + (size_t)K0 * nblk, nblk, v);
+    block_reduce<GK>(v, res + K0);
+    if constexpr (K0 + GK < K) reduce_partials<K, K0 + GK>(part, nblk, res);
 }
 
 }  // namespace amg
