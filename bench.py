@@ -276,6 +276,8 @@ def main(argv=None):
                     help="time only the 512-problem batched workload (FP32 bulk) and print its line")
     ap.add_argument("--large-only", action="store_true",
                     help="time only the 255^3 Poisson solve (FP64, 16.6 M DoF) and print its line")
+    ap.add_argument("--csr-only", action="store_true",
+                    help="time only the 127^3 Poisson solve through the CSR entry point (FP64) and print its line")
     ap.add_argument("--calibrate", action="store_true",
                     help="end with one plain 512 MiB read + 512 MiB write elementwise kernel (counter calibration)")
     args = ap.parse_args(argv)
@@ -313,6 +315,26 @@ def main(argv=None):
         sb.close()
         if args.calibrate:
             calibration_kernel(torch)
+        return 0
+    if args.csr_only:
+        cprob = W.POISSON3D_127
+        Ac, Psc = poisson_csr(cprob.n, cprob.nlevels)
+        bc = torch.as_tensor(W.problem_rhs(cprob), device="cuda")
+        sc = amg.Solver.from_csr(Ac, Psc, 0.125)
+        xc = torch.zeros_like(bc)
+        for _ in range(args.warmup):
+            xc.zero_()
+            sc.solve(bc, xc, tol=1e-8)
+        tms = []
+        for _ in range(max(args.steps, 1)):
+            xc.zero_()
+            torch.cuda.synchronize()
+            _, ci = sc.solve(bc, xc, tol=1e-8)
+            assert ci["status"] == amg.OK, ci
+            tms.append(ci["solve_ms"])
+        print(json.dumps({"workload": "poisson3d_127_csr", "dtype": "f64", "ms": round(float(np.mean(tms)), 4),
+                          "iterations": ci["iterations"], "nnz": int(Ac.nnz)}), flush=True)
+        sc.close()
         return 0
     if args.batched_only:
         res = run_batched(amg, torch, 1, args.steps, args.warmup)
