@@ -50,6 +50,7 @@ def test_batched_iterates_match_oracle():
             xi = xh[s.offsets[i]:s.offsets[i + 1]]
             assert infos[i]["iterations"] == o.iterations, (i, n)
             assert np.linalg.norm(xi - o.x) <= 1e-10 * np.linalg.norm(o.x), (i, n, k)
+            assert np.abs(xi - o.x).max() <= 1e-10 * np.abs(o.x).max(), (i, n, k)
     x, infos, ms = s.solve(bcat, tol=1e-8)
     for i, (d, n, nl, seed) in enumerate(probs):
         h = hierarchy.build(d, n, nl)

@@ -31,7 +31,8 @@ def dev(a):
 
 
 def rel(a, b):
-    return np.linalg.norm(a - b) / np.linalg.norm(b)
+    """max(normwise, element-wise max |a - b| / max |b|) relative error."""
+    return max(np.linalg.norm(a - b) / np.linalg.norm(b), np.abs(a - b).max() / np.abs(b).max())
 
 
 def structured_case(dim, n, nl, ks, seed):

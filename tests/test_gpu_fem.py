@@ -40,7 +40,11 @@ def dev(a):
 
 
 def rel(a, b):
-    return np.linalg.norm(a - b) / np.linalg.norm(b)
+    """max(normwise, element-wise max |a - b| / max |b|) relative error."""
+    nb = np.linalg.norm(b)
+    mb = np.abs(b).max() if b.size else 0.0
+    return max(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0),
+               (np.abs(a - b).max() / mb) if mb > 0 else 0.0)
 
 
 def oracle_h(kxx):
