@@ -94,7 +94,7 @@ def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2402_12833_amd", "csrc")
-    for f in ("common.hpp", "grid_kernels.hpp", "small_kernels.hpp", "amgmpcg.hip"):
+    for f in ("common.hpp", "grid_kernels.hpp", "small_kernels.hpp", "host_common.hpp", "solver_grid.hpp"):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -233,7 +233,7 @@ __global__ void __launch_bounds__(kCB) k_conv_wgrad(const Ctl* __restrict__ ctl,
 
 // Network input: channel 0 = r * scale (scale = 1 / rms(r)), channel 1 =
 // normalised log kappa (or 0), channels 2..15 = 0; voxels outside n^3 = 0.
-__global__ void __launch_bounds__(kCB) k_pack_input(const Ctl* __restrict__ ctl, const double* __restrict__ r,
+static __global__ void __launch_bounds__(kCB) k_pack_input(const Ctl* __restrict__ ctl, const double* __restrict__ r,
                                                     const double* __restrict__ scale, const bf16* __restrict__ lk,
                                                     bf16* __restrict__ X, int n, int S) {
     if (ctl && ctl->state != 0) return;
@@ -251,7 +251,7 @@ __global__ void __launch_bounds__(kCB) k_pack_input(const Ctl* __restrict__ ctl,
 }
 
 // Sum of squares of v (N values): per-block partials part[b], fixed order.
-__global__ void __launch_bounds__(kCB) k_sumsq(const Ctl* __restrict__ ctl, const double* __restrict__ v, int N,
+static __global__ void __launch_bounds__(kCB) k_sumsq(const Ctl* __restrict__ ctl, const double* __restrict__ v, int N,
                                                double* __restrict__ part) {
     if (ctl && ctl->state != 0) return;
     double s[1] = {0.0};
@@ -261,7 +261,7 @@ __global__ void __launch_bounds__(kCB) k_sumsq(const Ctl* __restrict__ ctl, cons
 
 // mode 0: out = 1 / rms (1 if the values are all zero), rms^2 = sum / N;
 // mode 1: out = sum of the partials (the loss).
-__global__ void __launch_bounds__(kRedBlock) k_finish_sum(const Ctl* __restrict__ ctl,
+static __global__ void __launch_bounds__(kRedBlock) k_finish_sum(const Ctl* __restrict__ ctl,
                                                          const double* __restrict__ part, int nblk, int N, int mode,
                                                          double* __restrict__ out) {
     if (ctl && ctl->state != 0) return;
@@ -278,7 +278,7 @@ __global__ void __launch_bounds__(kRedBlock) k_finish_sum(const Ctl* __restrict_
 }
 
 // 2x2x2 average pooling, S -> S/2 (C channels).
-__global__ void __launch_bounds__(kCB) k_avgpool(const Ctl* __restrict__ ctl, const bf16* __restrict__ X,
+static __global__ void __launch_bounds__(kCB) k_avgpool(const Ctl* __restrict__ ctl, const bf16* __restrict__ X,
                                                  bf16* __restrict__ Y, int Sc, int C) {
     if (ctl && ctl->state != 0) return;
     const size_t e = (size_t)blockIdx.x * kCB + threadIdx.x;
@@ -296,7 +296,7 @@ __global__ void __launch_bounds__(kCB) k_avgpool(const Ctl* __restrict__ ctl, co
 }
 
 // Y (S^3, C1 + C2 channels) = [upsample2(A) (C1 channels, grid S/2) | B (C2)].
-__global__ void __launch_bounds__(kCB) k_upcat(const Ctl* __restrict__ ctl, const bf16* __restrict__ A,
+static __global__ void __launch_bounds__(kCB) k_upcat(const Ctl* __restrict__ ctl, const bf16* __restrict__ A,
                                                const bf16* __restrict__ B, bf16* __restrict__ Y, int S, int C1,
                                                int C2) {
     if (ctl && ctl->state != 0) return;
@@ -315,7 +315,7 @@ __global__ void __launch_bounds__(kCB) k_upcat(const Ctl* __restrict__ ctl, cons
 }
 
 // dPre = dPost * (post > 0)
-__global__ void __launch_bounds__(kCB) k_relu_mask(const Ctl* __restrict__ ctl, const bf16* __restrict__ dpost,
+static __global__ void __launch_bounds__(kCB) k_relu_mask(const Ctl* __restrict__ ctl, const bf16* __restrict__ dpost,
                                                    const bf16* __restrict__ post, bf16* __restrict__ dpre,
                                                    size_t count) {
     if (ctl && ctl->state != 0) return;
@@ -326,7 +326,7 @@ __global__ void __launch_bounds__(kCB) k_relu_mask(const Ctl* __restrict__ ctl, 
 
 // dA (S/2 grid, C1 channels) = sum over the 8 children of dY[:, c0 + c]
 // (adjoint of nearest upsampling on the first C1 of C channels).
-__global__ void __launch_bounds__(kCB) k_upsample_bwd(const Ctl* __restrict__ ctl, const bf16* __restrict__ dY,
+static __global__ void __launch_bounds__(kCB) k_upsample_bwd(const Ctl* __restrict__ ctl, const bf16* __restrict__ dY,
                                                       bf16* __restrict__ dA, int Sc, int C1, int C) {
     if (ctl && ctl->state != 0) return;
     const size_t e = (size_t)blockIdx.x * kCB + threadIdx.x;
@@ -345,7 +345,7 @@ __global__ void __launch_bounds__(kCB) k_upsample_bwd(const Ctl* __restrict__ ct
 
 // dE (S^3, C2 channels) = dY[:, C1 + c] (skip part of a concat gradient)
 // + upsample2(dP) / 8 (adjoint of average pooling).
-__global__ void __launch_bounds__(kCB) k_skip_pool_bwd(const Ctl* __restrict__ ctl, const bf16* __restrict__ dY,
+static __global__ void __launch_bounds__(kCB) k_skip_pool_bwd(const Ctl* __restrict__ ctl, const bf16* __restrict__ dY,
                                                        const bf16* __restrict__ dP, bf16* __restrict__ dE, int S,
                                                        int C1, int C2) {
     if (ctl && ctl->state != 0) return;
@@ -362,7 +362,7 @@ __global__ void __launch_bounds__(kCB) k_skip_pool_bwd(const Ctl* __restrict__ c
 
 // MSE loss over the n^3 voxels against target e * escale; writes the FP32
 // loss partials and the bfloat16 gradient (16 channels, channel 0).
-__global__ void __launch_bounds__(kCB) k_mse_grad(const float* __restrict__ out, const double* __restrict__ e,
+static __global__ void __launch_bounds__(kCB) k_mse_grad(const float* __restrict__ out, const double* __restrict__ e,
                                                   const double* __restrict__ escale, bf16* __restrict__ G, int n,
                                                   int S, double* __restrict__ part) {
     const int v = blockIdx.x * kCB + threadIdx.x;
@@ -388,7 +388,7 @@ __global__ void __launch_bounds__(kCB) k_mse_grad(const float* __restrict__ out,
 
 // Energy loss of the direction d (the network output on the n^3 nodes) for
 // the pair (r, e) with q = A d: partial sums of d.r, d.q and e.r.
-__global__ void __launch_bounds__(kCB) k_dots3(const double* __restrict__ d, const double* __restrict__ q,
+static __global__ void __launch_bounds__(kCB) k_dots3(const double* __restrict__ d, const double* __restrict__ q,
                                                const double* __restrict__ r, const double* __restrict__ e, int N,
                                                double* __restrict__ part) {
     double v[3] = {0.0, 0.0, 0.0};
@@ -403,7 +403,7 @@ __global__ void __launch_bounds__(kCB) k_dots3(const double* __restrict__ d, con
 
 // s[0..2] = d.r, d.Ad, e.r; s[3] = loss 1 - (d.r)^2 / ((d.Ad)(e.r)) (1 when
 // d.Ad or e.r is not positive).
-__global__ void __launch_bounds__(kRedBlock) k_energy_finish(const double* __restrict__ part, int nblk,
+static __global__ void __launch_bounds__(kRedBlock) k_energy_finish(const double* __restrict__ part, int nblk,
                                                             double* __restrict__ s) {
     __shared__ double res[3];
     reduce_partials<3>(part, nblk, res);
@@ -419,7 +419,7 @@ __global__ void __launch_bounds__(kRedBlock) k_energy_finish(const double* __res
 // Output gradient of the energy loss, dL/dd = 2a/(cE) ((a/c) q - r), as the
 // bfloat16 gradient of channel 0 on the S^3 grid (zero outside the n^3 nodes
 // and in the other channels).
-__global__ void __launch_bounds__(kCB) k_energy_grad(const double* __restrict__ s, const double* __restrict__ q,
+static __global__ void __launch_bounds__(kCB) k_energy_grad(const double* __restrict__ s, const double* __restrict__ q,
                                                      const double* __restrict__ r, bf16* __restrict__ G, int n,
                                                      int S) {
     const int v = blockIdx.x * kCB + threadIdx.x;
@@ -439,7 +439,7 @@ __global__ void __launch_bounds__(kCB) k_energy_grad(const double* __restrict__ 
 }
 
 // dL/dd of the energy loss in FP64 on the n^3 nodes (no network).
-__global__ void __launch_bounds__(kCB) k_energy_grad64(const double* __restrict__ s, const double* __restrict__ q,
+static __global__ void __launch_bounds__(kCB) k_energy_grad64(const double* __restrict__ s, const double* __restrict__ q,
                                                        const double* __restrict__ r, double* __restrict__ g, int N) {
     const int i = blockIdx.x * kCB + threadIdx.x;
     if (i >= N) return;
@@ -461,14 +461,14 @@ __global__ void __launch_bounds__(kCB) k_unpack_output(const Ctl* __restrict__ c
     d[idx] = T(v);
 }
 
-__global__ void k_clear_flag(const Ctl* __restrict__ ctl, int* flag) {
+static __global__ void k_clear_flag(const Ctl* __restrict__ ctl, int* flag) {
     if (ctl && ctl->state != 0) return;
     if (threadIdx.x == 0) *flag = 0;
 }
 
 // Adam on FP32 masters; refreshes the bfloat16 forward copy [t][co][ci] and
 // the tap-flipped, transposed copy [26 - t][ci][co] used by the data gradient.
-__global__ void __launch_bounds__(kCB) k_adam(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
+static __global__ void __launch_bounds__(kCB) k_adam(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
                                               const float* __restrict__ g, bf16* __restrict__ wb,
                                               bf16* __restrict__ wt, int taps, int cout, int cin, float lr,
                                               float b1, float b2, float eps, float c1, float c2) {
@@ -488,7 +488,7 @@ __global__ void __launch_bounds__(kCB) k_adam(float* __restrict__ w, float* __re
 }
 
 // bfloat16 copies of FP32 weights (forward and flipped-transposed layouts).
-__global__ void __launch_bounds__(kCB) k_weights_bf16(const float* __restrict__ w, bf16* __restrict__ wb,
+static __global__ void __launch_bounds__(kCB) k_weights_bf16(const float* __restrict__ w, bf16* __restrict__ wb,
                                                       bf16* __restrict__ wt, int taps, int cout, int cin) {
     const int e = blockIdx.x * kCB + threadIdx.x;
     if (e >= taps * cout * cin) return;

@@ -414,5 +414,9 @@ class Net {
     }
 };
 
+// net.forward(ctl, r, lk, s), compiled once (with the rest of the network's
+// kernels) rather than in every solver translation unit.
+void net_forward(Net& net, const Ctl* ctl, const double* r, const bf16* lk, hipStream_t s);
+
 }  // namespace cnn
 }  // namespace amg

@@ -67,7 +67,7 @@ __device__ __forceinline__ C csr_row_dot(const CsrOp<T>& A, int i, F&& u) {
 #define CSR_LOOP(i, n) for (int i = blockIdx.x * kBlock + threadIdx.x; i < (n); i += gridDim.x * kBlock)
 
 // r = b - A x (FP64), partial ||b||^2 and ||r||^2.
-__global__ void __launch_bounds__(kBlock) k_csr_init_residual(CsrOp<double> A, const double* __restrict__ b,
+static __global__ void __launch_bounds__(kBlock) k_csr_init_residual(CsrOp<double> A, const double* __restrict__ b,
                                                               const double* __restrict__ x, double* __restrict__ r,
                                                               double* __restrict__ part) {
     double v[2] = {0.0, 0.0};
@@ -82,7 +82,7 @@ __global__ void __launch_bounds__(kBlock) k_csr_init_residual(CsrOp<double> A, c
 }
 
 // True-residual refresh r = b - A x in FP64 (mixed form, when requested).
-__global__ void __launch_bounds__(kBlock) k_csr_refresh(const Ctl* __restrict__ ctl, CsrOp<double> A,
+static __global__ void __launch_bounds__(kBlock) k_csr_refresh(const Ctl* __restrict__ ctl, CsrOp<double> A,
                                                         const double* __restrict__ b, const double* __restrict__ x,
                                                         double* __restrict__ r, double* __restrict__ part) {
     if (ctl->state == 2 || !ctl->refresh_req) return;
@@ -96,7 +96,7 @@ __global__ void __launch_bounds__(kBlock) k_csr_refresh(const Ctl* __restrict__ 
 }
 
 // y = A x (FP64).
-__global__ void __launch_bounds__(kBlock) k_csr_apply(CsrOp<double> A, const double* __restrict__ x,
+static __global__ void __launch_bounds__(kBlock) k_csr_apply(CsrOp<double> A, const double* __restrict__ x,
                                                       double* __restrict__ y) {
     CSR_LOOP(i, A.n) y[i] = csr_row_dot<double>(A, i, [&](int j) { return x[j]; });
 }

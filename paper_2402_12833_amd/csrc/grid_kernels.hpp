@@ -1638,7 +1638,7 @@ __global__ void __launch_bounds__(kBlock) k_write_Z(Rows R, int N, const T* __re
 }
 
 // b == 0: x = 0.
-__global__ void __launch_bounds__(kBlock) k_zero_if(const Ctl* __restrict__ ctl, double* __restrict__ x, int N) {
+static __global__ void __launch_bounds__(kBlock) k_zero_if(const Ctl* __restrict__ ctl, double* __restrict__ x, int N) {
     if (!ctl->zero_x) return;
     for (int idx = blockIdx.x * kBlock + threadIdx.x; idx < N; idx += gridDim.x * kBlock) x[idx] = 0.0;
 }

@@ -143,7 +143,7 @@ __device__ __forceinline__ void reduce_init_body(Ctl* ctl, const double* part, i
     }
 }
 
-__global__ void __launch_bounds__(kRedBlock) k_reduce_init(Ctl* ctl, const double* part, int nblk, double tol,
+static __global__ void __launch_bounds__(kRedBlock) k_reduce_init(Ctl* ctl, const double* part, int nblk, double tol,
                                                         double* rhist) {
     reduce_init_body(ctl, part, nblk, tol, rhist);
 }
@@ -312,7 +312,7 @@ __device__ __forceinline__ void refresh_reduce_body(Ctl* ctl, const double* part
     }
 }
 
-__global__ void __launch_bounds__(kRedBlock) k_refresh_reduce(Ctl* ctl, const double* part, int nblk, double* rhist) {
+static __global__ void __launch_bounds__(kRedBlock) k_refresh_reduce(Ctl* ctl, const double* part, int nblk, double* rhist) {
     refresh_reduce_body(ctl, part, nblk, rhist);
 }
 
