@@ -105,6 +105,12 @@ typedef struct {
                              from zero; 0: max(1, nu / 2).  Must be equal
                              (a symmetric preconditioner for CG)            */
     int32_t nu_post;
+    int32_t true_residual; /* 1: every solve also computes the true relative
+                             residual ||b - A x||_2 / ||b||_2 of the returned
+                             x with the FP64 finest operator (one more
+                             operator application and norm, part of the
+                             solve's device time) into info->relres_true;
+                             0: not computed (relres_true = -1)  (1)     */
 } amgmpcg_options;
 
 /* Solution methods (amgmpcg_options.method).  The comparison methods share
@@ -126,12 +132,16 @@ typedef struct {
     int32_t nb;              /* search directions per iteration (L + 1, or L + 2
                                 with the learned direction)                     */
     double  solve_ms;        /* device time of the solve (HIP events)           */
+    double  relres_true;     /* ||b - A x||_2 / ||b||_2 of the returned x in FP64
+                                (options.true_residual = 1), else -1; -1 for
+                                batched solves                                  */
+    double  setup_ms;        /* host wall time of the handle's setup call       */
 } amgmpcg_info;
 
 typedef struct amgmpcg_handle amgmpcg_handle;
 
 /* Default options (m=1, nu=2, omega=2/3, maxit=1000, FP64, k_poll=8,
- * method MPCG, nu_pre = nu_post = 0). */
+ * method MPCG, nu_pre = nu_post = 0, true_residual = 1). */
 void amgmpcg_default_options(amgmpcg_options* opts);
 
 /* setup(A, hierarchy): build the level hierarchy of a structured problem.
@@ -237,16 +247,36 @@ int amgmpcg_solve_batched(amgmpcg_handle* h, const double* b_dev, double* x_dev,
 /* Number of problems and total unknowns of a batched handle. */
 int amgmpcg_batched_size(const amgmpcg_handle* h, int32_t* count, int64_t* total_dofs);
 
-/* Device memory a handle (of any setup) holds: the bytes of the buffers its
- * setup allocated (level operators and transfers, vectors, direction
- * blocks and their rings, partial sums, history) and those that attaching a
- * network added (the wider direction blocks), not counting a few hundred
- * bytes of control words and the captured iteration graph.  The handle owns
- * this memory until amgmpcg_destroy; a solve allocates nothing except on a
- * handle's first solve, which captures the iteration graph.  The network's
- * own buffers belong to the network.  Errors: INVALID_ARG for a NULL handle
- * or output pointer. */
+/* Device memory a handle holds, in bytes.  For a handle of setup_grid,
+ * setup_stencil or setup_csr: the bytes of a caller workspace that holds all
+ * of the handle's device buffers (level operators and transfers, vectors,
+ * direction blocks and their rings, partial sums, history; with an attached
+ * network also its wider blocks), each at a 256-byte aligned offset: the
+ * size amgmpcg_bind_workspace needs.  Not counted: a few hundred bytes of
+ * control words and the captured iteration graph, which the handle always
+ * owns.  For a batched handle: the bytes its setup allocated.  A solve
+ * allocates nothing except on a handle's first solve (after setup or a
+ * bind), which captures the iteration graph.  The network's own buffers
+ * belong to the network.  Errors: INVALID_ARG for a NULL handle or output
+ * pointer. */
 int amgmpcg_workspace_bytes(const amgmpcg_handle* h, int64_t* bytes);
+
+/* Route the device buffers of a handle through caller-owned device memory
+ * (for example a torch tensor), in the spirit of Algorithm 1's problem
+ * statement: the caller provides all storage of the iteration.
+ * device_ptr: DEVICE memory of at least amgmpcg_workspace_bytes(h) bytes,
+ * 256-byte aligned.  Every buffer of the handle is copied into it (on the
+ * handle's stream; the call synchronises), the handle's own copies are
+ * freed, and the next solve captures the iteration graph anew.  From then
+ * on the caller owns the memory: it must stay allocated, and must not be
+ * written, while the handle exists; amgmpcg_destroy does not free it.
+ * Binding again moves the buffers to the new region (the old one may then
+ * be released).  Results are bit for bit those of the unbound handle.
+ * Attach or detach a network (amgmpcg_attach_cnn) before binding.  Errors,
+ * checked on the host before any copy: AMGMPCG_INVALID_ARG for a NULL or
+ * batched handle, a NULL, host or unaligned pointer, or bytes below the
+ * need; then AMGMPCG_HIP_ERROR for a failed copy. */
+int amgmpcg_bind_workspace(amgmpcg_handle* h, void* device_ptr, int64_t bytes);
 
 /* Measurement aid: average duration in ms of each hot kernel of one
  * iteration, each launched reps times back to back between two HIP events
@@ -282,6 +312,7 @@ int amgmpcg_profile_solve(amgmpcg_handle* h, const double* b_dev, double* x_dev,
  * Gplus = S Ghat^+ S.  *rank = eigenvalues kept.  Runs on the default
  * stream and synchronises. */
 int amgmpcg_gram_pinv(const double* G, int32_t nb, double tau, double* Gplus, int32_t* rank);
+
 
 /* r = b - A x with the finest operator in FP64.  b_dev, x_dev, r_dev:
  * DEVICE, n^dim doubles each (r may not alias b or x). */

@@ -32,7 +32,7 @@ class Options(ctypes.Structure):
     _fields_ = [("m", c_int32), ("nu", c_int32), ("omega", c_double), ("maxit", c_int32),
                 ("precision", c_int32), ("pinv_tau", c_double), ("k_poll", c_int32),
                 ("record_history", c_int32), ("refresh_drop", c_double), ("method", c_int32),
-                ("nu_pre", c_int32), ("nu_post", c_int32)]
+                ("nu_pre", c_int32), ("nu_post", c_int32), ("true_residual", c_int32)]
 
 
 class CsrMatrix(ctypes.Structure):
@@ -58,7 +58,8 @@ def _csr_struct(M, keep: list) -> CsrMatrix:
 
 class Info(ctypes.Structure):
     _fields_ = [("status", c_int32), ("iterations", c_int32), ("bnorm", c_double), ("relres", c_double),
-                ("refreshes", c_int32), ("nb", c_int32), ("solve_ms", c_double)]
+                ("refreshes", c_int32), ("nb", c_int32), ("solve_ms", c_double), ("relres_true", c_double),
+                ("setup_ms", c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -126,6 +127,8 @@ def load(path: str = LIB_PATH):
     lib.amgmpcg_batched_size.restype = c_int32
     lib.amgmpcg_workspace_bytes.argtypes = [c_void_p, POINTER(ctypes.c_int64)]
     lib.amgmpcg_workspace_bytes.restype = c_int32
+    lib.amgmpcg_bind_workspace.argtypes = [c_void_p, c_void_p, ctypes.c_int64]
+    lib.amgmpcg_bind_workspace.restype = c_int32
     lib.amgmpcg_gram_pinv.argtypes = [POINTER(c_double), c_int32, c_double, POINTER(c_double), POINTER(c_int32)]
     lib.amgmpcg_gram_pinv.restype = c_int32
     lib.amgmpcg_destroy.argtypes = [c_void_p]
@@ -339,10 +342,24 @@ class Solver:
         return loss.value, g
 
     def workspace_bytes(self) -> int:
-        """Device bytes the handle's buffers take (allocated at setup)."""
+        """Device bytes the handle's buffers take: the size of a workspace
+        that amgmpcg_bind_workspace can route them through."""
         v = ctypes.c_int64()
         _check(self._lib.amgmpcg_workspace_bytes(self._h, byref(v)))
         return v.value
+
+    def bind_workspace(self, ws=None):
+        """Move the handle's device buffers into a caller-owned device
+        tensor (uint8, at least workspace_bytes(), 256-byte aligned); a new
+        one is allocated by torch when ws is None.  The tensor is kept alive
+        with this object.  Returns it."""
+        import torch
+        if ws is None:
+            ws = torch.empty(self.workspace_bytes(), dtype=torch.uint8, device="cuda")
+        _check(self._lib.amgmpcg_bind_workspace(self._h, c_void_p(ws.data_ptr()),
+                                                ws.numel() * ws.element_size()))
+        self._ws = ws
+        return ws
 
     def attach(self, net: Optional["Network"]):
         """Append the network's output as one more search direction (None removes it)."""

@@ -11,6 +11,21 @@ namespace amg {
 thread_local std::string g_last_error;
 thread_local int64_t g_devbuf_bytes = 0;
 
+// One pseudo-inverse of an nb x nb Gram matrix at device G (kernel k_pinv_only).
+static void launch_pinv(int nb, const double* G, double tau, double* Gplus, int* rank) {
+    switch (nb) {
+        case 1: k_pinv_only<1><<<1, 64>>>(G, tau, Gplus, rank); break;
+        case 2: k_pinv_only<2><<<1, 64>>>(G, tau, Gplus, rank); break;
+        case 3: k_pinv_only<3><<<1, 64>>>(G, tau, Gplus, rank); break;
+        case 4: k_pinv_only<4><<<1, 64>>>(G, tau, Gplus, rank); break;
+        case 5: k_pinv_only<5><<<1, 64>>>(G, tau, Gplus, rank); break;
+        case 6: k_pinv_only<6><<<1, 64>>>(G, tau, Gplus, rank); break;
+        case 7: k_pinv_only<7><<<1, 64>>>(G, tau, Gplus, rank); break;
+        default: k_pinv_only<8><<<1, 64>>>(G, tau, Gplus, rank); break;
+    }
+    HIPCHK(hipGetLastError());
+}
+
 SolverBase* new_grid_solver_d2(const amgmpcg_grid&, const amgmpcg_options&, hipStream_t, const double*);
 SolverBase* new_grid_solver_d3(const amgmpcg_grid&, const amgmpcg_options&, hipStream_t, const double*);
 SolverBase* new_grid_solver_f2(const amgmpcg_grid&, const amgmpcg_options&, hipStream_t, const double*);
@@ -34,7 +49,13 @@ struct amgmpcg_handle {
     std::unique_ptr<amg::SolverBase> s;
     std::unique_ptr<amg::BatchedBase> bs;
     int64_t bytes = 0;   // device buffers allocated at setup and by attach
+    double setup_ms = 0.0;   // host wall time of the setup call
 };
+
+// Host wall time since t0 in ms.
+static double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
 
 struct amgmpcg_cnn {
     amg::cnn::Net net;
@@ -77,6 +98,8 @@ static void validate_options(const amgmpcg_options* o) {
         throw ApiError(AMGMPCG_INVALID_ARG, "nu_pre and nu_post must be in 0..8");
     if (o->nu_pre != o->nu_post)
         throw ApiError(AMGMPCG_INVALID_ARG, "nu_pre and nu_post must be equal (symmetric V-cycle)");
+    if (o->true_residual != 0 && o->true_residual != 1)
+        throw ApiError(AMGMPCG_INVALID_ARG, "true_residual must be 0 or 1");
 }
 
 static void validate_grid(const amgmpcg_grid* g) {
@@ -117,6 +140,7 @@ void amgmpcg_default_options(amgmpcg_options* o) {
     o->method = AMGMPCG_METHOD_MPCG;
     o->nu_pre = 0;
     o->nu_post = 0;
+    o->true_residual = 1;
 }
 
 int amgmpcg_setup_grid(const amgmpcg_grid* grid, const amgmpcg_options* opts, void* stream, amgmpcg_handle** out) {
@@ -125,11 +149,13 @@ int amgmpcg_setup_grid(const amgmpcg_grid* grid, const amgmpcg_options* opts, vo
         *out = nullptr;
         validate_grid(grid);
         validate_options(opts);
+        const auto t0 = std::chrono::steady_clock::now();
         auto h = std::make_unique<amgmpcg_handle>();
         const int64_t bytes0 = amg::g_devbuf_bytes;
         hipStream_t s = (hipStream_t)stream;
         h->s.reset(amg::new_grid_solver(opts->precision, grid->dim, *grid, *opts, s, nullptr));
         h->bytes = amg::g_devbuf_bytes - bytes0;
+        h->setup_ms = ms_since(t0);
         *out = h.release();
         return AMGMPCG_OK;
     });
@@ -179,11 +205,13 @@ int amgmpcg_setup_csr(const amgmpcg_csr* A, const amgmpcg_hierarchy* H, const am
             if (Ps[l].n != rows) throw ApiError(AMGMPCG_INVALID_ARG, "P[l] rows must equal the unknowns of level l+1");
             rows = Ps[l].m;
         }
+        const auto t0 = std::chrono::steady_clock::now();
         auto h = std::make_unique<amgmpcg_handle>();
         const int64_t bytes0 = amg::g_devbuf_bytes;
         hipStream_t s = (hipStream_t)stream;
         h->s.reset(amg::new_csr_solver(opts->precision, Ah, Ps, H->restrict_scale, *opts, s));
         h->bytes = amg::g_devbuf_bytes - bytes0;
+        h->setup_ms = ms_since(t0);
         *out = h.release();
         return AMGMPCG_OK;
     });
@@ -204,11 +232,13 @@ int amgmpcg_setup_stencil(const amgmpcg_grid* grid, const double* stencil, const
             if (stencil[q] != stencil[8 - q]) throw ApiError(AMGMPCG_INVALID_ARG, "the stencil must be symmetric");
         }
         if (!(stencil[4] > 0.0)) throw ApiError(AMGMPCG_NOT_SPD, "non-positive stencil centre");
+        const auto t0 = std::chrono::steady_clock::now();
         auto h = std::make_unique<amgmpcg_handle>();
         const int64_t bytes0 = amg::g_devbuf_bytes;
         hipStream_t s = (hipStream_t)stream;
         h->s.reset(amg::new_grid_solver(opts->precision, 2, *grid, *opts, s, stencil));
         h->bytes = amg::g_devbuf_bytes - bytes0;
+        h->setup_ms = ms_since(t0);
         *out = h.release();
         return AMGMPCG_OK;
     });
@@ -220,7 +250,9 @@ int amgmpcg_solve(amgmpcg_handle* h, const double* b_dev, double* x_dev, double 
         if (!h || !h->s) throw ApiError(AMGMPCG_INVALID_ARG, "handle is NULL");
         if (!b_dev || !x_dev) throw ApiError(AMGMPCG_INVALID_ARG, "b or x is NULL");
         if (!(tol >= 0.0) || !std::isfinite(tol)) throw ApiError(AMGMPCG_INVALID_ARG, "tol must be finite and >= 0");
-        return h->s->solve(b_dev, x_dev, tol, maxit, info);
+        const int st = h->s->solve(b_dev, x_dev, tol, maxit, info);
+        if (info) info->setup_ms = h->setup_ms;
+        return st;
     });
 }
 
@@ -243,6 +275,7 @@ int amgmpcg_solve_host(amgmpcg_handle* h, const double* b, double* x, double tol
             HIPCHK(hipMemcpy(db, b, N * sizeof(double), hipMemcpyHostToDevice));
             HIPCHK(hipMemcpy(dx, x, N * sizeof(double), hipMemcpyHostToDevice));
             st = h->s->solve(db, dx, tol, maxit, info);
+            if (info) info->setup_ms = h->setup_ms;
             HIPCHK(hipMemcpy(x, dx, N * sizeof(double), hipMemcpyDeviceToHost));
         } catch (...) {
             (void)hipFree(db);
@@ -321,6 +354,7 @@ int amgmpcg_profile_solve(amgmpcg_handle* h, const double* b_dev, double* x_dev,
         amgmpcg_info local{};
         int smp = 0;
         const int c = h->s->profile_solve(b_dev, x_dev, tol, maxit, &local, ms_out, cap, &smp);
+        local.setup_ms = h->setup_ms;
         if (info) *info = local;
         if (count) *count = c;
         if (samples) *samples = smp;
@@ -345,11 +379,13 @@ int amgmpcg_setup_batched(int32_t count, const amgmpcg_grid* grids, const amgmpc
         }
         if (opts->m != 1 || opts->method != AMGMPCG_METHOD_MPCG)
             throw ApiError(AMGMPCG_INVALID_ARG, "batched solves use the MPCG method with m = 1");
+        const auto t0 = std::chrono::steady_clock::now();
         auto h = std::make_unique<amgmpcg_handle>();
         const int64_t bytes0 = amg::g_devbuf_bytes;
         hipStream_t s = (hipStream_t)stream;
         h->bs.reset(amg::new_batched_solver(opts->precision, dim, count, grids, *opts, s));
         h->bytes = amg::g_devbuf_bytes - bytes0;
+        h->setup_ms = ms_since(t0);
         *out = h.release();
         return AMGMPCG_OK;
     });
@@ -361,7 +397,13 @@ int amgmpcg_solve_batched(amgmpcg_handle* h, const double* b_dev, double* x_dev,
         if (!h || !h->bs) throw ApiError(AMGMPCG_INVALID_ARG, "handle is not a batched handle");
         if (!b_dev || !x_dev) throw ApiError(AMGMPCG_INVALID_ARG, "b or x is NULL");
         if (!(tol >= 0.0) || !std::isfinite(tol)) throw ApiError(AMGMPCG_INVALID_ARG, "tol must be finite and >= 0");
-        return h->bs->solve(b_dev, x_dev, tol, maxit, infos, batch_ms);
+        const int st = h->bs->solve(b_dev, x_dev, tol, maxit, infos, batch_ms);
+        if (infos)
+            for (int i = 0; i < h->bs->count; ++i) {
+                infos[i].relres_true = -1.0;
+                infos[i].setup_ms = h->setup_ms;
+            }
+        return st;
     });
 }
 
@@ -369,7 +411,28 @@ int amgmpcg_workspace_bytes(const amgmpcg_handle* h, int64_t* bytes) {
     return guarded([&]() -> int {
         if (!h || (!h->s && !h->bs)) throw ApiError(AMGMPCG_INVALID_ARG, "handle is NULL");
         if (!bytes) throw ApiError(AMGMPCG_INVALID_ARG, "bytes is NULL");
-        *bytes = h->bytes;
+        *bytes = h->s ? h->s->workspace_need() : h->bytes;
+        return AMGMPCG_OK;
+    });
+}
+
+int amgmpcg_bind_workspace(amgmpcg_handle* h, void* device_ptr, int64_t bytes) {
+    return guarded([&]() -> int {
+        if (!h || (!h->s && !h->bs)) throw ApiError(AMGMPCG_INVALID_ARG, "handle is NULL");
+        if (!h->s) throw ApiError(AMGMPCG_INVALID_ARG, "a batched handle owns its memory");
+        if (!device_ptr) throw ApiError(AMGMPCG_INVALID_ARG, "workspace pointer is NULL");
+        if (reinterpret_cast<uintptr_t>(device_ptr) % amg::kWsAlign != 0)
+            throw ApiError(AMGMPCG_INVALID_ARG, "workspace must be 256-byte aligned");
+        const int64_t need = h->s->workspace_need();
+        if (bytes < need)
+            throw ApiError(AMGMPCG_INVALID_ARG,
+                           "workspace too small: " + std::to_string(bytes) + " < " + std::to_string(need) + " bytes");
+        hipPointerAttribute_t attr;
+        if (hipPointerGetAttributes(&attr, device_ptr) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+            (void)hipGetLastError();
+            throw ApiError(AMGMPCG_INVALID_ARG, "workspace is not device memory");
+        }
+        h->s->bind_workspace(static_cast<char*>(device_ptr), bytes);
         return AMGMPCG_OK;
     });
 }
@@ -393,17 +456,7 @@ int amgmpcg_gram_pinv(const double* G, int32_t nb, double tau, double* Gplus, in
         HIPCHK(hipMemcpy(d.p, G, sizeof(double) * nb * nb, hipMemcpyHostToDevice));
         int* drank = (int*)(d.p + 2 * nb * nb);
         double* dGp = d.p + nb * nb;
-        switch (nb) {
-            case 1: amg::k_pinv_only<1><<<1, 64>>>(d.p, tau, dGp, drank); break;
-            case 2: amg::k_pinv_only<2><<<1, 64>>>(d.p, tau, dGp, drank); break;
-            case 3: amg::k_pinv_only<3><<<1, 64>>>(d.p, tau, dGp, drank); break;
-            case 4: amg::k_pinv_only<4><<<1, 64>>>(d.p, tau, dGp, drank); break;
-            case 5: amg::k_pinv_only<5><<<1, 64>>>(d.p, tau, dGp, drank); break;
-            case 6: amg::k_pinv_only<6><<<1, 64>>>(d.p, tau, dGp, drank); break;
-            case 7: amg::k_pinv_only<7><<<1, 64>>>(d.p, tau, dGp, drank); break;
-            default: amg::k_pinv_only<8><<<1, 64>>>(d.p, tau, dGp, drank); break;
-        }
-        HIPCHK(hipGetLastError());
+        amg::launch_pinv(nb, d.p, tau, dGp, drank);
         HIPCHK(hipMemcpy(Gplus, dGp, sizeof(double) * nb * nb, hipMemcpyDeviceToHost));
         int r = 0;
         HIPCHK(hipMemcpy(&r, drank, sizeof(int), hipMemcpyDeviceToHost));

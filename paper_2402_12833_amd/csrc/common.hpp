@@ -36,6 +36,7 @@ struct Ctl {
     double rho_ref;   // ||r||^2 at the last refresh
     double drop2;     // refresh_drop^2
     double tau;       // eigenvalue cut of the unit-diagonal Gram
+    double relres_true;   // ||b - A x||_2 / ||b||_2 of the returned x (FP64), when computed
 };
 
 // Logical block index so that each XCD (blockIdx % 8) owns a contiguous range

@@ -84,6 +84,7 @@ template <typename T>
 struct DevBuf {
     T* p = nullptr;
     size_t n = 0;
+    bool ext = false;   // p lies in a caller's workspace (amgmpcg_bind_workspace): not freed here
     void alloc(size_t count) {
         free();
         if (count == 0) return;
@@ -92,32 +93,52 @@ struct DevBuf {
         g_devbuf_bytes += (int64_t)(count * sizeof(T));
     }
     void free() {
-        if (p) {
+        if (p && !ext) {
             (void)hipFree(p);
             g_devbuf_bytes -= (int64_t)(n * sizeof(T));
         }
         p = nullptr;
         n = 0;
+        ext = false;
     }
     ~DevBuf() { free(); }
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
-    DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) {
+    DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), ext(o.ext) {
         o.p = nullptr;
         o.n = 0;
+        o.ext = false;
     }
     DevBuf& operator=(DevBuf&& o) noexcept {
         if (this != &o) {
             free();
             p = o.p;
             n = o.n;
+            ext = o.ext;
             o.p = nullptr;
             o.n = 0;
+            o.ext = false;
         }
         return *this;
     }
 };
+
+// A device buffer of a handle, type-erased: where its pointer lives, its size
+// and whether it lies in a caller's workspace.
+struct BufRef {
+    void** p;
+    size_t bytes;
+    bool* ext;
+};
+template <typename T>
+BufRef buf_ref(DevBuf<T>& b) {
+    return BufRef{reinterpret_cast<void**>(&b.p), b.n * sizeof(T), &b.ext};
+}
+
+// Alignment of every buffer placed in a caller's workspace.
+constexpr size_t kWsAlign = 256;
+inline size_t ws_round(size_t bytes) { return (bytes + kWsAlign - 1) / kWsAlign * kWsAlign; }
 
 class SolverBase {
    public:
@@ -137,6 +158,58 @@ class SolverBase {
     virtual void apply_fine(const double* x_dev, double* y_dev, hipStream_t s) = 0;
     virtual void project_prepare(const double* r_dev, double* rhat_dev, hipStream_t s) = 0;
     virtual void project_direction(const double* d_dev, const double* q_dev, double* qhat_dev, hipStream_t s) = 0;
+    // Every device buffer of the handle (not the control words), and what
+    // to redo once they have moved: pointers cached in operator structs,
+    // the captured iteration graph (its kernel arguments hold the old
+    // addresses).
+    virtual void buffers(std::vector<BufRef>& out) = 0;
+    virtual void rebound() = 0;
+    virtual hipStream_t stream() const = 0;
+
+    // Bytes of a caller workspace that holds all buffers, each at a
+    // kWsAlign-aligned offset.
+    int64_t workspace_need() {
+        std::vector<BufRef> v;
+        buffers(v);
+        int64_t s = 0;
+        for (const BufRef& b : v) s += (int64_t)ws_round(b.bytes);
+        return s;
+    }
+
+    // Move every buffer into [ws, ws + bytes) (contents copied on the
+    // handle's stream), free the handle's own copies and redo what holds
+    // the old addresses.  The caller checks size and alignment first.
+    void bind_workspace(char* ws, int64_t bytes) {
+        std::vector<BufRef> v;
+        buffers(v);
+        std::vector<std::pair<void*, size_t>> old;
+        size_t off = 0;
+        for (const BufRef& b : v) {
+            if (b.bytes == 0 || !*b.p) continue;
+            char* dst = ws + off;
+            if ((int64_t)(off + b.bytes) > bytes) throw ApiError(AMGMPCG_INVALID_ARG, "workspace too small");
+            HIPCHK(hipMemcpyAsync(dst, *b.p, b.bytes, hipMemcpyDeviceToDevice, stream()));
+            if (!*b.ext) old.emplace_back(*b.p, b.bytes);
+            *b.p = dst;
+            *b.ext = true;
+            off += ws_round(b.bytes);
+        }
+        HIPCHK(hipStreamSynchronize(stream()));
+        for (auto& o : old) {
+            (void)hipFree(o.first);
+            g_devbuf_bytes -= (int64_t)o.second;
+        }
+        rebound();
+    }
+
+    bool bound() {
+        std::vector<BufRef> v;
+        buffers(v);
+        for (const BufRef& b : v)
+            if (*b.ext) return true;
+        return false;
+    }
+
     cnn::Net* net_ = nullptr;
     int dim = 0, nlev = 0, nb = 0;
     std::vector<int> n_axis;   // per level, 0 = coarsest

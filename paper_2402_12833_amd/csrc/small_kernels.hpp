@@ -148,6 +148,14 @@ static __global__ void __launch_bounds__(kRedBlock) k_reduce_init(Ctl* ctl, cons
     reduce_init_body(ctl, part, nblk, tol, rhist);
 }
 
+// The true relative residual ||b - A x|| / ||b|| of the returned iterate,
+// from the partials (||b||^2, ||r||^2) of the FP64 residual kernel.
+static __global__ void __launch_bounds__(kRedBlock) k_true_relres(Ctl* ctl, const double* part, int nblk) {
+    __shared__ double res[2];
+    reduce_partials<2>(part, nblk, res);
+    if (threadIdx.x == 0) ctl->relres_true = res[0] > 0.0 ? sqrt(res[1] / res[0]) : 0.0;
+}
+
 // Residual check of r_{k+1} and beta = G_k^+ W (W = Q_k^T Z_{k+1}).
 // mixed != 0: convergence on the recursive residual only requests a
 // true-residual refresh; the refresh decides.

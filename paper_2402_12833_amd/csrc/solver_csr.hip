@@ -142,6 +142,11 @@ class CsrSolver : public SolverBase {
             if (hctl_->state == 2) break;
             HIPCHK(hipGraphLaunch(exec_, stream_));
         }
+        if (opt_.true_residual) {
+            // ||b - A x|| / ||b|| of the returned x with the FP64 operator
+            k_csr_init_residual<<<FB_, kBlock, 0, stream_>>>(A64_.op(), b_.p, x_.p, r_.p, part_init());
+            k_true_relres<<<1, kRedBlock, 0, stream_>>>(ctl_, part_init(), FB_);
+        }
         HIPCHK(hipMemcpyAsync(x_dev, x_.p, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, stream_));
         HIPCHK(hipEventRecord(ev1_, stream_));
         HIPCHK(hipMemcpyAsync(hctl_, ctl_, sizeof(Ctl), hipMemcpyDeviceToHost, stream_));
@@ -159,8 +164,38 @@ class CsrSolver : public SolverBase {
             info->refreshes = h.refreshes;
             info->nb = nb;
             info->solve_ms = ms;
+            info->relres_true = opt_.true_residual ? h.relres_true : -1.0;
         }
         return status;
+    }
+
+    hipStream_t stream() const override { return stream_; }
+
+    void buffers(std::vector<BufRef>& v) override {
+        auto csr = [&](DevCsr<T>& M) {
+            v.push_back(buf_ref(M.soff));
+            v.push_back(buf_ref(M.swid));
+            v.push_back(buf_ref(M.col));
+            v.push_back(buf_ref(M.val));
+        };
+        for (std::vector<DevCsr<T>>* vm : {&A_, &P_l_, &R_l_})
+            for (DevCsr<T>& M : *vm) csr(M);
+        v.push_back(buf_ref(A64_.soff));
+        v.push_back(buf_ref(A64_.swid));
+        v.push_back(buf_ref(A64_.col));
+        v.push_back(buf_ref(A64_.val));
+        for (std::vector<DevBuf<T>>* vb : {&D_, &g_, &c_, &c2_, &Y_})
+            for (DevBuf<T>& b : *vb) v.push_back(buf_ref(b));
+        for (DevBuf<double>* b : {&x_, &r_, &b_, &part_, &partG_, &partWin_, &small_, &ahist_, &rhist_})
+            v.push_back(buf_ref(*b));
+        for (DevBuf<T>* b : {&P_, &Q_, &cL_, &cL2_, &cL3_}) v.push_back(buf_ref(*b));
+    }
+
+    void rebound() override {
+        if (exec_) (void)hipGraphExecDestroy(exec_);
+        if (graph_) (void)hipGraphDestroy(graph_);
+        exec_ = nullptr;
+        graph_ = nullptr;
     }
 
     void mg_block(const double* r_dev, double* Z_dev) override {

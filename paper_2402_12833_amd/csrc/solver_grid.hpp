@@ -237,6 +237,8 @@ class Solver : public SolverBase {
             if (net->n != n_axis[L_]) throw ApiError(AMGMPCG_DIM_MISMATCH, "network grid differs from the problem grid");
             if (nlev + 1 > kMaxNB) throw ApiError(AMGMPCG_INVALID_ARG, "too many levels for an extra direction");
         }
+        // the wider blocks would be allocated anew: do it before the buffers move
+        if (bound()) throw ApiError(AMGMPCG_INVALID_ARG, "attach or detach the network before binding the workspace");
         net_ = net;
         nb = nlev + (net ? 1 : 0);
         pstride_ = slot_elems(nb, N);
@@ -250,11 +252,7 @@ class Solver : public SolverBase {
         if (net && !dl_.p) dl_.alloc(N);
         if (hist_cap_ > 0) ahist_.alloc((size_t)hist_cap_ * nb);
         set_tau();
-        if (exec_) (void)hipGraphExecDestroy(exec_);
-        if (graph_) (void)hipGraphDestroy(graph_);
-        exec_ = nullptr;
-        graph_ = nullptr;
-        graph_ready_ = false;
+        drop_graph();
     }
 
     void residual(const double* b_dev, const double* x_dev, double* r_dev) override {
@@ -390,6 +388,11 @@ class Solver : public SolverBase {
             if (hctl_->state == 2) break;
             HIPCHK(hipGraphLaunch(exec_, stream_));
         }
+        if (opt_.true_residual) {
+            // ||b - A x|| / ||b|| of the returned x with the FP64 operator
+            k_init_residual<DIM><<<FB_, kBlock, 0, stream_>>>(rows_, f64_, b_.p, x_.p, r_.p, part_init());
+            k_true_relres<<<1, kRedBlock, 0, stream_>>>(ctl_, part_init(), FB_);
+        }
         HIPCHK(hipMemcpyAsync(x_dev, x_.p, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, stream_));
         HIPCHK(hipEventRecord(ev1_, stream_));
         HIPCHK(hipMemcpyAsync(hctl_, ctl_, sizeof(Ctl), hipMemcpyDeviceToHost, stream_));
@@ -407,8 +410,52 @@ class Solver : public SolverBase {
             info->refreshes = h.refreshes;
             info->nb = nb;
             info->solve_ms = ms;
+            info->relres_true = opt_.true_residual ? h.relres_true : -1.0;
         }
         return status;
+    }
+
+    hipStream_t stream() const override { return stream_; }
+
+    void buffers(std::vector<BufRef>& v) override {
+        for (DevBuf<T>* b : {&fD_, &fex_, &fey_, &fez_, &fiD_, &P_, &Q_, &cL_, &cL2_, &dl_, &zv_, &vcL_, &vtL_, &vrL_})
+            v.push_back(buf_ref(*b));
+        for (DevBuf<double>* b : {&gD_, &gex_, &gey_, &gez_, &giD_, &x_, &r_, &b_, &part_, &small_, &ahist_, &rhist_,
+                                  &partWin_, &partG_, &xt_})
+            v.push_back(buf_ref(*b));
+        for (std::vector<DevBuf<T>>* vb : {&coef_, &g_, &c1_, &c_, &c2_, &Y_, &vg_, &vc_, &vt_, &vr_})
+            for (DevBuf<T>& b : *vb) v.push_back(buf_ref(b));
+        v.push_back(buf_ref(lk_));
+    }
+
+    void rebound() override {
+        fop_.D = fD_.p;
+        fop_.ex = fex_.p;
+        fop_.ey = fey_.p;
+        fop_.ez = DIM == 3 ? fez_.p : nullptr;
+        fop_.iD = fiD_.p;
+        if (std::is_same<T, double>::value) {
+            f64_.D = (const double*)fD_.p;
+            f64_.ex = (const double*)fex_.p;
+            f64_.ey = (const double*)fey_.p;
+            f64_.ez = DIM == 3 ? (const double*)fez_.p : nullptr;
+            f64_.iD = (const double*)fiD_.p;
+        } else {
+            f64_.D = gD_.p;
+            f64_.ex = gex_.p;
+            f64_.ey = gey_.p;
+            f64_.ez = DIM == 3 ? gez_.p : nullptr;
+            f64_.iD = giD_.p;
+        }
+        drop_graph();
+    }
+
+    void drop_graph() {
+        if (exec_) (void)hipGraphExecDestroy(exec_);
+        if (graph_) (void)hipGraphDestroy(graph_);
+        exec_ = nullptr;
+        graph_ = nullptr;
+        graph_ready_ = false;
     }
 
     void mg_block(const double* r_dev, double* Z_dev) override {
@@ -1326,6 +1373,7 @@ class Solver : public SolverBase {
             info->refreshes = h.refreshes;
             info->nb = nb;
             info->solve_ms = 0.0;
+            info->relres_true = -1.0;
         }
         for (int k = 0; k < kSecCount && k < cap; ++k) ms[k] = full ? sum[k] / full : 0.0;
         if (samples) *samples = full;

@@ -32,6 +32,7 @@ def test_exports_every_declared_symbol(lib):
 def test_default_options(lib):
     o = amg.default_options()
     assert (o.m, o.nu, o.maxit, o.precision, o.k_poll) == (1, 2, 1000, 0, 8)
+    assert o.true_residual == 1
     assert o.omega == pytest.approx(2.0 / 3.0)
     assert o.refresh_drop == pytest.approx(1e-2)
 
@@ -59,7 +60,8 @@ def test_grid_validation(lib, grid, expect):
 
 @pytest.mark.parametrize("kw", [dict(m=0), dict(m=9), dict(nu=0), dict(omega=1.5), dict(maxit=0), dict(precision=3),
                                 dict(k_poll=0), dict(refresh_drop=2.0), dict(method=3), dict(method=-1),
-                                dict(method=1, m=2), dict(method=2, nu_pre=1, nu_post=2), dict(nu_pre=9, nu_post=9)])
+                                dict(method=1, m=2), dict(method=2, nu_pre=1, nu_post=2), dict(nu_pre=9, nu_post=9),
+                                dict(true_residual=2), dict(true_residual=-1)])
 def test_option_validation(lib, kw):
     code, _ = _setup(lib, B.Grid(2, 31, 3, None), amg.default_options(**kw))
     assert code == B.INVALID_ARG
@@ -204,3 +206,20 @@ def test_cnn_argument_validation(lib):
     ks = (ctypes.c_int32 * 1)(0)
     assert lib.amgmpcg_make_pairs(None, None, None, ks, 1, None, None) == B.INVALID_ARG
     lib.amgmpcg_cnn_destroy(None)
+
+
+def test_bind_workspace_null_handle(lib):
+    """The workspace entry points reject a missing handle on the host."""
+    buf = ctypes.create_string_buffer(1024)
+    assert lib.amgmpcg_bind_workspace(None, ctypes.cast(buf, ctypes.c_void_p), 1024) == B.INVALID_ARG
+    v = ctypes.c_int64()
+    assert lib.amgmpcg_workspace_bytes(None, ctypes.byref(v)) == B.INVALID_ARG
+
+
+def test_info_layout(lib):
+    """The info struct carries the true residual and the setup time after the
+    fields of the first layout (offsets of a plain C struct)."""
+    names = [f for f, _ in B.Info._fields_]
+    assert names[-2:] == ["relres_true", "setup_ms"]
+    assert B.Info.relres_true.offset == B.Info.solve_ms.offset + 8
+    assert ctypes.sizeof(B.Info) == B.Info.setup_ms.offset + 8
