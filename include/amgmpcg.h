@@ -313,6 +313,17 @@ int amgmpcg_profile_solve(amgmpcg_handle* h, const double* b_dev, double* x_dev,
  * stream and synchronises. */
 int amgmpcg_gram_pinv(const double* G, int32_t nb, double tau, double* Gplus, int32_t* rank);
 
+/* amgmpcg_gram_pinv for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernel and result, with the device staging of G, G^+
+ * and the rank in a static device array of the library (1 KiB on every GPU
+ * it runs on, held until the process ends) instead of a buffer allocated per
+ * call; no hipMalloc, hipFree or other allocating call.  nb is limited to
+ * 1..8 (the array holds an 8 x 8 Gram); larger nb returns
+ * AMGMPCG_INVALID_ARG.  Every call on one GPU uses that GPU's one array:
+ * calls that overlap on one GPU (from several host threads) race.  Runs on
+ * the default stream of the current device and synchronises. */
+int amgmpcg_gram_pinv_noalloc(const double* G, int32_t nb, double tau, double* Gplus, int32_t* rank);
 
 /* r = b - A x with the finest operator in FP64.  b_dev, x_dev, r_dev:
  * DEVICE, n^dim doubles each (r may not alias b or x). */

@@ -131,6 +131,9 @@ def load(path: str = LIB_PATH):
     lib.amgmpcg_bind_workspace.restype = c_int32
     lib.amgmpcg_gram_pinv.argtypes = [POINTER(c_double), c_int32, c_double, POINTER(c_double), POINTER(c_int32)]
     lib.amgmpcg_gram_pinv.restype = c_int32
+    lib.amgmpcg_gram_pinv_noalloc.argtypes = [POINTER(c_double), c_int32, c_double, POINTER(c_double),
+                                              POINTER(c_int32)]
+    lib.amgmpcg_gram_pinv_noalloc.restype = c_int32
     lib.amgmpcg_destroy.argtypes = [c_void_p]
     lib.amgmpcg_destroy.restype = None
     lib.amgmpcg_status_string.argtypes = [c_int32]
@@ -203,6 +206,17 @@ def gram_pinv(G: np.ndarray, tau: float):
     rank = c_int32()
     _check(load().amgmpcg_gram_pinv(G.ctypes.data_as(POINTER(c_double)), nb, float(tau),
                                     out.ctypes.data_as(POINTER(c_double)), byref(rank)))
+    return out, rank.value
+
+
+def gram_pinv_noalloc(G: np.ndarray, tau: float):
+    """gram_pinv through the entry point that allocates no device memory."""
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    nb = G.shape[0]
+    out = np.empty((nb, nb))
+    rank = c_int32()
+    _check(load().amgmpcg_gram_pinv_noalloc(G.ctypes.data_as(POINTER(c_double)), nb, float(tau),
+                                            out.ctypes.data_as(POINTER(c_double)), byref(rank)))
     return out, rank.value
 
 

@@ -3,6 +3,8 @@
 // The extern "C" entry points declared in include/amgmpcg.h: argument
 // validation on the host, the handle, and dispatch to the solver types
 // (each in its own translation unit) and to the learned direction.
+#include <mutex>
+
 #include "host_common.hpp"
 #include "cnn_host.hpp"
 
@@ -10,6 +12,32 @@ namespace amg {
 
 thread_local std::string g_last_error;
 thread_local int64_t g_devbuf_bytes = 0;
+
+// Device staging of amgmpcg_gram_pinv_noalloc: G (kMaxNB^2 doubles), G^+
+// (kMaxNB^2) and the rank, in a file-scope device array that every GPU the
+// library runs on holds until the process ends.  In host code its name is a
+// host-side stand-in: kernels and copies use the address from
+// hipGetSymbolAddress, looked up once per device.
+constexpr int kPinvScratch = 2 * kMaxNB * kMaxNB + 8;
+static __device__ __align__(256) double scratch[kPinvScratch];
+constexpr int kMaxDevices = 64;
+static double* g_scratch_dev[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+// The current device's address of the staging array.
+static double* pinv_scratch() {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) throw ApiError(AMGMPCG_INVALID_ARG, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) throw ApiError(AMGMPCG_HIP_ERROR, "no device address for the staging array");
+        g_scratch_dev[dev] = static_cast<double*>(ptr);
+    }
+    return g_scratch_dev[dev];
+}
 
 // One pseudo-inverse of an nb x nb Gram matrix at device G (kernel k_pinv_only).
 static void launch_pinv(int nb, const double* G, double tau, double* Gplus, int* rank) {
@@ -457,6 +485,26 @@ int amgmpcg_gram_pinv(const double* G, int32_t nb, double tau, double* Gplus, in
         int* drank = (int*)(d.p + 2 * nb * nb);
         double* dGp = d.p + nb * nb;
         amg::launch_pinv(nb, d.p, tau, dGp, drank);
+        HIPCHK(hipMemcpy(Gplus, dGp, sizeof(double) * nb * nb, hipMemcpyDeviceToHost));
+        int r = 0;
+        HIPCHK(hipMemcpy(&r, drank, sizeof(int), hipMemcpyDeviceToHost));
+        *rank = r;
+        return AMGMPCG_OK;
+    });
+}
+
+int amgmpcg_gram_pinv_noalloc(const double* G, int32_t nb, double tau, double* Gplus, int32_t* rank) {
+    return guarded([&]() -> int {
+        if (!G || !Gplus || !rank) throw ApiError(AMGMPCG_INVALID_ARG, "NULL argument");
+        if (nb < 1 || nb > amg::kMaxNB)
+            throw ApiError(AMGMPCG_INVALID_ARG, "nb must be in 1..8 (the static staging holds an 8 x 8 Gram)");
+        if (!(tau > 0.0)) throw ApiError(AMGMPCG_INVALID_ARG, "tau must be > 0");
+        double* sc = amg::pinv_scratch();
+        double* dG = sc;
+        double* dGp = sc + amg::kMaxNB * amg::kMaxNB;
+        int* drank = reinterpret_cast<int*>(sc + 2 * amg::kMaxNB * amg::kMaxNB);
+        HIPCHK(hipMemcpy(dG, G, sizeof(double) * nb * nb, hipMemcpyHostToDevice));
+        amg::launch_pinv(nb, dG, tau, dGp, drank);
         HIPCHK(hipMemcpy(Gplus, dGp, sizeof(double) * nb * nb, hipMemcpyDeviceToHost));
         int r = 0;
         HIPCHK(hipMemcpy(&r, drank, sizeof(int), hipMemcpyDeviceToHost));
