@@ -209,8 +209,10 @@ def run_batched(amg, torch, precision, steps, warmup):
     out = {"ms": round(float(np.mean(tms)), 4), "problems": len(table), "dofs": int(bsolv.N),
            "iterations_min": int(min(its)), "iterations_max": int(max(its)),
            "iterations_mean": round(float(np.mean(its)), 2)}
+    offs = bsolv.offsets
+    xs = (xb.clone(), [xb[offs[i]:offs[i + 1]].clone() for i in range(len(table))])
     bsolv.close()
-    return out
+    return out, xs
 
 
 def run_example1(amg, torch):
@@ -239,18 +241,55 @@ def run_example1(amg, torch):
     return out
 
 
-def cpu_baseline(prob, max_iters=None):
-    """The FP64 oracle (numpy/scipy, one thread) on the same workload."""
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo, as lscpu reports it)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.lower().startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def host_threads():
+    """Host CPUs this process may run on (its affinity set)."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(prob, threads, max_iters=None):
+    """The FP64 oracle (numpy/scipy, as it stands) on the same workload with
+    at most `threads` library threads: (ms, iterations, cores it used =
+    process CPU time / wall time of the solve, oracle x).  Setup excluded."""
     from threadpoolctl import threadpool_limits
     import workloads as W
     from oracle import hierarchy, mpcg
-    with threadpool_limits(limits=1):
+    with threadpool_limits(limits=threads):
         h = hierarchy.build(prob.dim, prob.n, prob.nlevels, kappa=W.kappa_field(prob))
         b = W.problem_rhs(prob)
-        t0 = time.perf_counter()
+        t0, c0 = time.perf_counter(), time.process_time()
         res = mpcg.mpcg(h, b, tol=1e-8, maxit=max_iters or 1000)
-        dt = time.perf_counter() - t0
-    return dt * 1e3, res.iterations
+        dt, dc = time.perf_counter() - t0, time.process_time() - c0
+    return dt * 1e3, res.iterations, dc / dt, res.x
+
+
+def rel_err(x, ref):
+    """Full-vector relative error ||x - ref|| / ||ref|| (device tensors or arrays)."""
+    import torch
+    x = torch.as_tensor(x, dtype=torch.float64)
+    ref = torch.as_tensor(ref, dtype=torch.float64, device=x.device)
+    return float(torch.linalg.norm(x - ref) / torch.linalg.norm(ref))
+
+
+def x1_fields(x32, info32, x64, it64):
+    """The mixed-precision result against the FP64 one: full-vector relative
+    error, FP64 iteration count, true FP64 residual of the FP32-bulk x."""
+    return {"err_vs_fp64": float(f"{rel_err(x32, x64):.3e}"), "iterations_fp64": it64,
+            "relres_true": float(f"{info32['relres_true']:.3e}")}
 
 
 def calibration_kernel(torch):
@@ -337,12 +376,13 @@ def main(argv=None):
         sc.close()
         return 0
     if args.batched_only:
-        res = run_batched(amg, torch, 1, args.steps, args.warmup)
+        res, _ = run_batched(amg, torch, 1, args.steps, args.warmup)
         print(json.dumps({"workload": "batched2d_512", "dtype": "f32 bulk / f64 Gram", **res}), flush=True)
         return 0
 
     prob = W.POISSON3D_127
     s, b, x, ms, iters, setup_s, info = run_solver(amg, torch, prob, 0, args.steps, args.warmup)
+    x64 = x.clone()
     m, per_iter = traffic_model(prob.dim, prob.n, prob.nlevels, 8, False)
     gbs = per_iter * iters / (ms * 1e-3) / 1e9
     # kernel durations inside real iterations (each kernel on the data the
@@ -364,8 +404,12 @@ def main(argv=None):
     dom_ms = own if own > 0 else sec[dom]
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     m[dom + "_kernel"] = dom_bytes
+    # every section of the iteration with its algorithmic bytes, rate and
+    # fraction of the 8 TB/s peak (spans between stream events: launch
+    # latency included, so these understate the kernels' own rates)
     kernels = {k: {"ms": round(v, 5), "bytes": m.get(k),
-                   "GB/s": round(m[k] / (v * 1e-3) / 1e9, 1) if m.get(k) and v > 0 else None}
+                   "GB/s": round(m[k] / (v * 1e-3) / 1e9, 1) if m.get(k) and v > 0 else None,
+                   "frac": round(m[k] / (v * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if m.get(k) and v > 0 else None}
                for k, v in sec.items() if v > 0}
     out = {
         "metric": METRIC,
@@ -384,6 +428,7 @@ def main(argv=None):
                    "coarse": "Galerkin 27-point", "smoother": "damped Jacobi nu=2 omega=2/3", "m": 1,
                    "tol": 1e-8, "rhs": "U[-1,1] seed 2", "x0": 0},
         "iterations": iters,
+        "relres_true": float(f"{info['relres_true']:.3e}"),
         "ms_per_iteration": round(ms / max(iters, 1), 5),
         "hbm_GBps_algorithmic": round(gbs, 1),
         "bytes_per_iteration_model": per_iter,
@@ -402,39 +447,54 @@ def main(argv=None):
     s.close()
     if not args.no_variants:
         var = {}
-        s2, _, _, ms2, it2, _, info2 = run_solver(amg, torch, prob, 1, args.steps, args.warmup)
+        s2, _, x2, ms2, it2, _, info2 = run_solver(amg, torch, prob, 1, args.steps, args.warmup)
         _, pi2 = traffic_model(3, prob.n, prob.nlevels, 4, False)
         var["poisson3d_127_fp32bulk"] = {"ms": round(ms2, 4), "iterations": it2, "refreshes": info2["refreshes"],
                                         "hbm_GBps_algorithmic": round(pi2 * it2 / (ms2 * 1e-3) / 1e9, 1),
-                                        "speedup_vs_fp64": round(ms / ms2, 3)}
+                                        "speedup_vs_fp64": round(ms / ms2, 3), **x1_fields(x2, info2, x64, iters)}
+        x32_headline = x2.clone()
         s2.close()
         # the same problem at 255^3: 16.6 M DoF, 7 levels, a working set far
         # beyond the 256 MB Infinity Cache
         bprob = W.POISSON3D_255
         for prec, tag, bulk in ((0, "fp64", 8), (1, "fp32bulk", 4)):
-            sb, _, _, msb, itb, setb, infb = run_solver(amg, torch, bprob, prec, max(2, args.steps // 2), 1)
+            sb, _, xb_, msb, itb, setb, infb = run_solver(amg, torch, bprob, prec, max(2, args.steps // 2), 1)
             _, pib = traffic_model(3, bprob.n, bprob.nlevels, bulk, False)
             var[f"poisson3d_255_{tag}"] = {"ms": round(msb, 4), "iterations": itb, "refreshes": infb["refreshes"],
                                            "dofs": bprob.ndof, "levels": bprob.nlevels,
                                            "hbm_GBps_algorithmic": round(pib * itb / (msb * 1e-3) / 1e9, 1),
                                            "setup_s": round(setb, 3)}
+            if prec == 0:
+                x255, it255 = xb_.clone(), itb
+            else:
+                var[f"poisson3d_255_{tag}"].update(x1_fields(xb_, infb, x255, it255))
+                del x255
             sb.close()
         dprob = W.DIFFUSION3D_127
         kap = W.kappa_field(dprob)
+        dref = {}
         for prec, tag, bulk in ((0, "fp64", 8), (1, "fp32bulk", 4)):
-            s3, _, _, ms3, it3, _, info3 = run_solver(amg, torch, dprob, prec, args.steps, args.warmup, kappa=kap)
+            s3, _, x3, ms3, it3, _, info3 = run_solver(amg, torch, dprob, prec, args.steps, args.warmup, kappa=kap)
             _, pi3 = traffic_model(3, dprob.n, dprob.nlevels, bulk, True)
             var[f"diffusion3d_127_{tag}"] = {"ms": round(ms3, 4), "iterations": it3, "refreshes": info3["refreshes"],
                                              "hbm_GBps_algorithmic": round(pi3 * it3 / (ms3 * 1e-3) / 1e9, 1)}
+            if prec == 0:
+                dref["m1"] = (x3.clone(), it3)
+            else:
+                var[f"diffusion3d_127_{tag}"].update(x1_fields(x3, info3, *dref["m1"]))
             s3.close()
             # truncation window m = 5: each new direction block A-orthogonalised
             # against the last four blocks as well
-            s5, _, _, ms5, it5, _, info5 = run_solver(amg, torch, dprob, prec, args.steps, args.warmup, kappa=kap,
-                                                      m=5)
+            s5, _, x5, ms5, it5, _, info5 = run_solver(amg, torch, dprob, prec, args.steps, args.warmup, kappa=kap,
+                                                       m=5)
             plain = var[f"diffusion3d_127_{tag}"]
             var[f"diffusion3d_127_m5_{tag}"] = {"ms": round(ms5, 4), "iterations": it5, "refreshes": info5["refreshes"],
                                                 "iterations_m1": plain["iterations"],
                                                 "time_vs_m1": round(ms5 / plain["ms"], 3)}
+            if prec == 0:
+                dref["m5"] = (x5.clone(), it5)
+            else:
+                var[f"diffusion3d_127_m5_{tag}"].update(x1_fields(x5, info5, *dref["m5"]))
             s5.close()
         # the comparison methods of Sec. 3 on the same hierarchy and kernels:
         # CG preconditioned by the summed additive correction and by one
@@ -447,8 +507,13 @@ def main(argv=None):
                 var[f"{pname}_{tag}_fp64"] = {"ms": round(ms6, 4), "iterations": it6,
                                               "mpcg_iterations": ref["iterations"], "mpcg_ms": ref["ms"]}
                 s6.close()
+        bx = {}
         for prec, tag in ((1, "fp32bulk"), (0, "fp64")):
-            var[f"batched2d_512_{tag}"] = run_batched(amg, torch, prec, args.steps, args.warmup)
+            var[f"batched2d_512_{tag}"], bx[prec] = run_batched(amg, torch, prec, args.steps, args.warmup)
+        var["batched2d_512_fp32bulk"]["err_vs_fp64"] = float(f"{rel_err(bx[1][0], bx[0][0]):.3e}")
+        var["batched2d_512_fp32bulk"]["err_vs_fp64_max_problem"] = float(f"{max(rel_err(a, c) for a, c in zip(bx[1][1], bx[0][1])):.3e}")
+        var["batched2d_512_fp32bulk"]["iterations_fp64_mean"] = var["batched2d_512_fp64"]["iterations_mean"]
+        del bx
         var["example1_160"] = run_example1(amg, torch)
         # the general (CSR) entry point on an unstructured graph problem
         A, Ps, bg = W.graph_problem()
@@ -466,6 +531,10 @@ def main(argv=None):
             assert ci["status"] == amg.OK, ci
             var[f"graph2d_20000_csr_{tag}"] = {"ms": round(float(np.mean(tms)), 4), "iterations": ci["iterations"],
                                                "unknowns": int(A.shape[0]), "nnz": int(A.nnz), "levels": len(Ps) + 1}
+            if prec == 0:
+                gref = (xc.clone(), ci["iterations"])
+            else:
+                var[f"graph2d_20000_csr_{tag}"].update(x1_fields(xc, ci, *gref))
             sc.close()
         # the 127^3 Poisson workload through the general entry point: the
         # fine operator as a 14.2 M-nonzero CSR matrix (the cost of generality)
@@ -488,18 +557,24 @@ def main(argv=None):
             var[f"poisson3d_127_csr_{tag}"] = {"ms": round(float(np.mean(tms)), 4), "iterations": ci["iterations"],
                                                "nnz": int(Ac.nnz), "setup_s": round(set_c, 3),
                                                "time_vs_structured": round(float(np.mean(tms)) / ref, 3)}
+            if prec == 1:
+                var[f"poisson3d_127_csr_{tag}"].update(x1_fields(xc, ci, x64, iters))
             sc.close()
         # the learned direction (committed trained weights) on the same problem
         from paper_2402_12833_amd import train as T
         net = amg.Network(dprob.n)
         T.load_weights(net)
         for prec, tag in ((0, "fp64"), (1, "fp32bulk")):
-            s4, b4, _, ms4, it4, _, info4 = run_solver(amg, torch, dprob, prec, args.steps, args.warmup, kappa=kap,
-                                                       net=net)
+            s4, b4, x4, ms4, it4, _, info4 = run_solver(amg, torch, dprob, prec, args.steps, args.warmup, kappa=kap,
+                                                        net=net)
             plain = var[f"diffusion3d_127_{tag}"]
             var[f"diffusion3d_127_learned_{tag}"] = {
                 "ms": round(ms4, 4), "iterations": it4, "refreshes": info4["refreshes"], "nb": info4["nb"],
                 "iterations_plain": plain["iterations"], "time_vs_plain": round(ms4 / plain["ms"], 3)}
+            if prec == 0:
+                lref = (x4.clone(), it4)
+            else:
+                var[f"diffusion3d_127_learned_{tag}"].update(x1_fields(x4, info4, *lref))
             if prec == 0:
                 lk = s4.log_kappa()
                 fms = net.time_forward(b4, lk, reps=20)
@@ -510,11 +585,20 @@ def main(argv=None):
         net.close()
         out["variants"] = var
     if not args.no_cpu:
-        cpu_ms, cpu_it = cpu_baseline(prob)
-        out["cpu_baseline"] = {"value": round(cpu_ms, 1), "unit": "ms", "cores": 1, "kind": "oracle",
-                               "sample": f"FP64 oracle (numpy/scipy, 1 thread) full solve of poisson3d_127 to 1e-8, "
-                                         f"{cpu_it} iterations, setup excluded",
-                               "cpu": platform.processor() or platform.machine()}
+        nthr = host_threads()
+        cpu_ms, cpu_it, used, xo = cpu_baseline(prob, nthr)
+        cpu1_ms, _, used1, _ = cpu_baseline(prob, 1)
+        out["cpu_baseline"] = {"value": round(cpu_ms, 1), "unit": "ms", "cores": max(1, round(used)), "kind": "oracle",
+                               "sample": f"FP64 oracle (numpy/scipy as it stands) full solve of poisson3d_127 to 1e-8, "
+                                         f"{cpu_it} iterations, setup excluded, library threads limited to the "
+                                         f"{nthr} host CPUs; cores = process CPU time / wall time of the solve",
+                               "threads_allowed": nthr, "cores_measured": round(used, 2),
+                               "value_1thread": round(cpu1_ms, 1), "cores_measured_1thread": round(used1, 2),
+                               "cpu": cpu_model()}
+        # the benchmarked solution against the oracle's, full vector
+        out["err_vs_fp64_oracle"] = float(f"{rel_err(x64, xo):.3e}")
+        if "variants" in out:
+            out["variants"]["poisson3d_127_fp32bulk"]["err_vs_fp64_oracle"] = float(f"{rel_err(x32_headline, xo):.3e}")
     if args.calibrate:
         calibration_kernel(torch)
     print(json.dumps(out), flush=True)

@@ -32,3 +32,17 @@ def test_poisson_csr_inputs_match_the_structured_hierarchy():
     for l in range(2):
         assert Ps[l].shape == h.levels[l].P.shape
         assert abs(Ps[l] - h.levels[l].P).max() == 0.0
+
+
+def test_x1_fields_and_host_description():
+    """The mixed-precision error fields and the CPU description of the
+    baseline (host only)."""
+    import numpy as np
+    x64 = np.linspace(1.0, 2.0, 100)
+    x32 = x64 * (1.0 + 1e-7)
+    f = bench.x1_fields(x32, {"relres_true": 5e-9}, x64, 16)
+    assert abs(f["err_vs_fp64"] - 1e-7) <= 1e-9
+    assert f["iterations_fp64"] == 16 and f["relres_true"] == 5e-9
+    assert bench.rel_err(x64, x64) == 0.0
+    assert bench.host_threads() >= 1
+    assert isinstance(bench.cpu_model(), str) and bench.cpu_model()
