@@ -2,6 +2,7 @@
 #include "host_common.hpp"
 #include "grid_kernels.hpp"
 #include "batched.hpp"
+#include "batched_layout.hpp"
 
 namespace amg {
 
@@ -15,100 +16,70 @@ class BatchedSolver : public BatchedBase {
         : opt_(o), stream_(stream) {
         count = cnt;
         mixed_ = std::is_same<T, float>::value;
-        offs_.assign(cnt + 1, 0);
-        nlev_.resize(cnt);
-        std::vector<std::vector<int>> sizes(cnt);
-        size_t nP = 0, ncoef = 0, nvec = 0, nY = 0;
+        std::vector<int> ns(cnt), nls(cnt);
         for (int i = 0; i < cnt; ++i) {
-            const int nl = grids[i].nlevels;
-            nlev_[i] = nl;
-            sizes[i].resize(nl);
-            sizes[i][nl - 1] = grids[i].n;
-            for (int l = nl - 2; l >= 0; --l) sizes[i][l] = sizes[i][l + 1] / 2;
-            const size_t N = (size_t)host::ipow(grids[i].n, DIM);
-            offs_[i + 1] = offs_[i] + N;
-            nP += (size_t)even_up(nl) * N;
-            for (int l = 0; l + 1 < nl; ++l) {
-                const size_t Nl = (size_t)host::ipow(sizes[i][l], DIM);
-                ncoef += (size_t)(DIM == 2 ? 9 : 27) * Nl;
-                nvec += Nl;
-                nY += (size_t)even_up(l + 1) * Nl;
-            }
+            ns[i] = grids[i].n;
+            nls[i] = grids[i].nlevels;
         }
+        const host::BatchLayout lay = host::batch_layout(DIM, ns, nls, kBChunk, kBlock, kBPartRows);
+        offs_ = lay.offs;
+        nlev_ = nls;
+        pos_ = lay.pos;
         total = (int64_t)offs_[cnt];
         x_.alloc(offs_[cnt]);
         r_.alloc(offs_[cnt]);
         b_.alloc(offs_[cnt]);
-        P_.alloc(nP);
-        Q_.alloc(nP);
+        P_.alloc(lay.nP);
+        Q_.alloc(lay.nP);
         cL_.alloc(offs_[cnt]);
-        coef_.alloc(std::max<size_t>(ncoef, 1));
-        g_.alloc(std::max<size_t>(nvec, 1));
-        c1_.alloc(std::max<size_t>(nvec, 1));
-        Y_.alloc(std::max<size_t>(nY, 1));
+        coef_.alloc(std::max<size_t>(lay.ncoef, 1));
+        g_.alloc(std::max<size_t>(lay.nvec, 1));
+        c1_.alloc(std::max<size_t>(lay.nvec, 1));
+        Y_.alloc(std::max<size_t>(lay.nY, 1));
         HIPCHK(hipMemset(P_.p, 0, P_.n * sizeof(T)));
         HIPCHK(hipMemset(Q_.p, 0, Q_.n * sizeof(T)));
         HIPCHK(hipMemset(Y_.p, 0, Y_.n * sizeof(T)));
-
-        // instance array ordered by number of levels: the groups
-        std::vector<int> order(cnt);
-        for (int i = 0; i < cnt; ++i) order[i] = i;
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nlev_[a] < nlev_[b]; });
-        pos_.resize(cnt);
-        for (int q = 0; q < cnt; ++q) pos_[order[q]] = q;
-        for (int q = 0; q < cnt; ++q) {
-            const int nl = nlev_[order[q]];
-            if (groups_.empty() || groups_.back().nlev != nl) groups_.push_back(Group{nl, q, 0});
-            ++groups_.back().count;
+        for (const host::BatchGroup& G : lay.groups) {
+            groups_.push_back(Group{G.nlev, G.first, G.count, Range{G.fine.off, G.fine.cnt}});
         }
-
         ctl_.alloc(cnt);
         small_.alloc((size_t)cnt * kBSmall);
         HIPCHK(hipMemset(small_.p, 0, small_.n * sizeof(double)));
-        size_t npart = 0;
-        std::vector<int> pcnt(cnt);
-        for (int i = 0; i < cnt; ++i) {
-            const size_t N = offs_[i + 1] - offs_[i];
-            pcnt[i] = (int)((N + kBChunk - 1) / kBChunk);
-            npart += (size_t)pcnt[i] * kBPartRows;
-        }
-        part_.alloc(npart);
+        part_.alloc(lay.npart);
 
         // per-problem hierarchy (host Galerkin) and device pointers
         hinst_.resize(cnt);
-        size_t oP = 0, oc = 0, ov = 0, oY = 0, opart = 0;
-        std::vector<T> coef_host(ncoef);
-        for (int i = 0; i < cnt; ++i) {
-            const int nl = nlev_[i], n = grids[i].n;
-            BInst<T>& I = hinst_[pos_[i]];
+        std::vector<T> coef_host(lay.ncoef);
+        for (int q = 0; q < cnt; ++q) {
+            const host::BatchProblem& B = lay.inst[q];
+            const int nl = B.nlev, n = B.n[nl - 1];
+            BInst<T>& I = hinst_[q];
             std::memset(&I, 0, sizeof(I));
             I.nlev = nl;
             for (int l = 0; l < nl; ++l) {
-                I.n[l] = sizes[i][l];
-                I.N[l] = (int)host::ipow(sizes[i][l], DIM);
+                I.n[l] = B.n[l];
+                I.N[l] = (int)B.N[l];
             }
-            const size_t N = offs_[i + 1] - offs_[i];
+            const int N = (int)B.N[nl - 1];
             const double h2inv = double(n + 1) * double(n + 1);
             I.op.n = n;
-            I.op.N = (int)N;
+            I.op.N = N;
             I.op.s0 = T(h2inv);
             I.op.inv0 = T(1.0 / (2.0 * DIM * h2inv));
             I.op64.n = n;
-            I.op64.N = (int)N;
+            I.op64.N = N;
             I.op64.s0 = h2inv;
             I.op64.inv0 = 1.0 / (2.0 * DIM * h2inv);
-            I.x = x_.p + offs_[i];
-            I.r = r_.p + offs_[i];
-            I.b = b_.p + offs_[i];
-            I.cL = cL_.p + offs_[i];
-            I.P = P_.p + oP;
-            I.Q = Q_.p + oP;
-            oP += (size_t)even_up(nl) * N;
-            I.ctl = ctl_.p + pos_[i];
-            I.small = small_.p + (size_t)pos_[i] * kBSmall;
-            I.part = part_.p + opart;
-            I.pcnt = pcnt[i];
-            opart += (size_t)pcnt[i] * kBPartRows;
+            I.x = x_.p + B.fine_off;
+            I.r = r_.p + B.fine_off;
+            I.b = b_.p + B.fine_off;
+            I.cL = cL_.p + B.fine_off;
+            I.P = P_.p + B.P_off;
+            I.Q = Q_.p + B.P_off;
+            I.ctl = ctl_.p + q;
+            I.small = small_.p + (size_t)q * kBSmall;
+            I.part = part_.p + B.part_off;
+            I.pcnt = B.pcnt;
             if (nl > 1) {
                 host::FineFaces faces = host::fine_faces(DIM, n, nullptr);
                 std::vector<host::StencilLevel> lev(nl);
@@ -116,67 +87,35 @@ class BatchedSolver : public BatchedBase {
                 for (int l = nl - 2; l >= 0; --l) {
                     lev[l] = host::galerkin(lev[l + 1]);
                     const int ctr = lev[l].center();
-                    for (int64_t q = 0; q < lev[l].N; ++q)
-                        if (!(lev[l].coef[(size_t)ctr * lev[l].N + q] > 0.0))
+                    for (int64_t k = 0; k < lev[l].N; ++k)
+                        if (!(lev[l].coef[(size_t)ctr * lev[l].N + k] > 0.0))
                             throw ApiError(AMGMPCG_NOT_SPD, "non-positive diagonal on a coarse level");
                 }
                 for (int l = 0; l + 1 < nl; ++l) {
-                    const size_t Nl = (size_t)I.N[l];
-                    const size_t cnt_c = (size_t)(DIM == 2 ? 9 : 27) * Nl;
-                    for (size_t q = 0; q < cnt_c; ++q) coef_host[oc + q] = T(lev[l].coef[q]);
-                    I.coef[l] = coef_.p + oc;
-                    oc += cnt_c;
-                    I.g[l] = g_.p + ov;
-                    I.c1[l] = c1_.p + ov;
-                    ov += Nl;
-                    I.Y[l] = Y_.p + oY;
-                    oY += (size_t)even_up(l + 1) * Nl;
+                    const size_t cnt_c = (size_t)(DIM == 2 ? 9 : 27) * (size_t)B.N[l];
+                    for (size_t k = 0; k < cnt_c; ++k) coef_host[B.coef_off[l] + k] = T(lev[l].coef[k]);
+                    I.coef[l] = coef_.p + B.coef_off[l];
+                    I.g[l] = g_.p + B.vec_off[l];
+                    I.c1[l] = c1_.p + B.vec_off[l];
+                    I.Y[l] = Y_.p + B.Y_off[l];
                 }
             }
         }
-        if (ncoef) HIPCHK(hipMemcpy(coef_.p, coef_host.data(), ncoef * sizeof(T), hipMemcpyHostToDevice));
+        if (lay.ncoef) HIPCHK(hipMemcpy(coef_.p, coef_host.data(), lay.ncoef * sizeof(T), hipMemcpyHostToDevice));
         inst_.alloc(cnt);
         HIPCHK(hipMemcpy(inst_.p, hinst_.data(), cnt * sizeof(BInst<T>), hipMemcpyHostToDevice));
 
-        // block maps: all problems' fine nodes, per group its fine nodes
-        std::vector<BBlk> maps;
-        auto fine_blocks = [&](int q0, int q1) {
-            for (int q = q0; q < q1; ++q) {
-                const BInst<T>& I = hinst_[q];
-                const int N = I.N[I.nlev - 1];
-                for (int j = 0; j < I.pcnt; ++j)
-                    maps.push_back(BBlk{q, j, j * kBChunk, std::min(N, (j + 1) * kBChunk)});
-            }
-        };
-        all_.off = (int)maps.size();
-        fine_blocks(0, cnt);
-        all_.cnt = (int)maps.size() - all_.off;
-        for (Group& G : groups_) {
-            G.fine.off = (int)maps.size();
-            fine_blocks(G.first, G.first + G.count);
-            G.fine.cnt = (int)maps.size() - G.fine.off;
+        // block maps (the same four ints per block as the kernels' BBlk)
+        static_assert(sizeof(BBlk) == sizeof(host::BatchBlock), "block map entry layout");
+        all_ = Range{lay.all.off, lay.all.cnt};
+        dmax_ = lay.dmax;
+        for (int d = 0; d < kMaxLevels; ++d) {
+            dep_[d] = Range{lay.dep[d].off, lay.dep[d].cnt};
+            pro_[d] = Range{lay.pro[d].off, lay.pro[d].cnt};
         }
-        // per depth below the finest level, over all groups: that coarse
-        // level's nodes (restriction and smoothing), and the same for the
-        // problems where it is not the coarsest level (carry into it)
-        dmax_ = 0;
-        for (const Group& G : groups_) dmax_ = std::max(dmax_, G.nlev - 1);
-        for (int d = 1; d <= dmax_; ++d) {
-            for (int pass = 0; pass < 2; ++pass) {
-                Range& R = pass == 0 ? dep_[d] : pro_[d];
-                R.off = (int)maps.size();
-                for (const Group& G : groups_) {
-                    const int l = G.nlev - 1 - d;
-                    if (l < 0 || (pass == 1 && l == 0)) continue;
-                    for (int q = G.first; q < G.first + G.count; ++q) {
-                        const int Nl = hinst_[q].N[l];
-                        for (int j = 0, s0 = 0; s0 < Nl; ++j, s0 += kBlock)
-                            maps.push_back(BBlk{q, j, s0, std::min(Nl, s0 + kBlock)});
-                    }
-                }
-                R.cnt = (int)maps.size() - R.off;
-            }
-        }
+        std::vector<BBlk> maps(lay.maps.size());
+        for (size_t k = 0; k < maps.size(); ++k)
+            maps[k] = BBlk{lay.maps[k].inst, lay.maps[k].blk, lay.maps[k].start, lay.maps[k].end};
         maps_.alloc(maps.size());
         HIPCHK(hipMemcpy(maps_.p, maps.data(), maps.size() * sizeof(BBlk), hipMemcpyHostToDevice));
         HIPCHK(hipHostMalloc((void**)&hctl_, (size_t)cnt * sizeof(Ctl), hipHostMallocDefault));
