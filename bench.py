@@ -186,13 +186,14 @@ def run_solver(amg, torch, prob, precision, steps, warmup, kappa=None, net=None,
     return s, b, x, ms, it, setup_s, infos[-1]
 
 
-def run_batched(amg, torch, precision, steps, warmup):
+def run_batched(amg, torch, precision, steps, warmup, persistent=0):
     """The batched workload: 512 2D Poisson problems (sides U{31..255}), all
-    solved by one graph of batched launches per k_poll iterations."""
+    solved by one graph of batched launches per k_poll iterations (or, with
+    persistent=1, by one persistent launch: a workgroup per problem)."""
     import workloads as W
     table = W.batched_instances()
     bcat = torch.as_tensor(np.concatenate([W.batched_rhs(t) for t in table]), device="cuda")
-    bsolv = amg.BatchedSolver([(2, t.n, t.nlevels) for t in table], precision=precision)
+    bsolv = amg.BatchedSolver([(2, t.n, t.nlevels) for t in table], precision=precision, persistent=persistent)
     xb = torch.zeros_like(bcat)
     for _ in range(warmup):
         xb.zero_()
@@ -513,7 +514,12 @@ def main(argv=None):
         var["batched2d_512_fp32bulk"]["err_vs_fp64"] = float(f"{rel_err(bx[1][0], bx[0][0]):.3e}")
         var["batched2d_512_fp32bulk"]["err_vs_fp64_max_problem"] = float(f"{max(rel_err(a, c) for a, c in zip(bx[1][1], bx[0][1])):.3e}")
         var["batched2d_512_fp32bulk"]["iterations_fp64_mean"] = var["batched2d_512_fp64"]["iterations_mean"]
-        del bx
+        # the same batch in one persistent launch (the other launch form)
+        var["batched2d_512_fp32bulk_persistent"], bpx = run_batched(amg, torch, 1, args.steps, args.warmup,
+                                                                    persistent=1)
+        var["batched2d_512_fp32bulk_persistent"]["err_vs_fp64"] = float(f"{rel_err(bpx[0], bx[0][0]):.3e}")
+        var["batched2d_512_fp32bulk_persistent"]["iterations_fp64_mean"] = var["batched2d_512_fp64"]["iterations_mean"]
+        del bx, bpx
         var["example1_160"] = run_example1(amg, torch)
         # the general (CSR) entry point on an unstructured graph problem
         A, Ps, bg = W.graph_problem()

@@ -111,6 +111,13 @@ typedef struct {
                              operator application and norm, part of the
                              solve's device time) into info->relres_true;
                              0: not computed (relres_true = -1)  (1)     */
+    int32_t persistent;   /* batched handles: 1 = the whole solve of every
+                             problem in one persistent launch (each workgroup
+                             runs Algorithm 1 for one problem at a time,
+                             problems taken largest first from a queue);
+                             0 = one batched launch per step of Algorithm 1
+                             over all problems, k_poll iterations per graph
+                             (0: the faster form on MI355X)                 */
 } amgmpcg_options;
 
 /* Solution methods (amgmpcg_options.method).  The comparison methods share
@@ -141,7 +148,7 @@ typedef struct {
 typedef struct amgmpcg_handle amgmpcg_handle;
 
 /* Default options (m=1, nu=2, omega=2/3, maxit=1000, FP64, k_poll=8,
- * method MPCG, nu_pre = nu_post = 0, true_residual = 1). */
+ * method MPCG, nu_pre = nu_post = 0, true_residual = 1, persistent = 0). */
 void amgmpcg_default_options(amgmpcg_options* opts);
 
 /* setup(A, hierarchy): build the level hierarchy of a structured problem.
@@ -226,13 +233,19 @@ int amgmpcg_history(const amgmpcg_handle* h, int32_t cap, double* alpha_out,
  * all of one dim, each with its own n and nlevels <= 6) whose hierarchies
  * are built here (Sec. 2.1 per problem); grids: HOST array of count entries.
  * opts as for amgmpcg_setup_grid (nu must be 1 or 2, m = 1, the MPCG
- * method).  The problems are solved together (Algorithm 1 for each): every
+ * method).  The problems are solved together (Algorithm 1 for each), each
+ * with its own convergence flag.  With opts->persistent = 0 (default) every
  * step is one launch over all problems with the same number of levels, each
- * block working on one problem's nodes; k_poll iterations of all problems
- * are captured in one HIP graph, launched until every problem has stopped;
- * each problem has its own convergence flag.  Errors: AMGMPCG_INVALID_ARG
- * for bad arguments (checked before any device call), AMGMPCG_NOT_SPD,
- * AMGMPCG_OOM / AMGMPCG_HIP_ERROR from the device. */
+ * block working on one problem's nodes, and k_poll iterations of all
+ * problems are captured in one HIP graph, launched until every problem has
+ * stopped.  With opts->persistent = 1 one persistent launch, captured in a
+ * HIP graph with the reset of its work queue, runs every problem's whole
+ * solve: each workgroup of 512 threads takes the next problem (largest
+ * first), runs all iterations of Algorithm 1 for it with workgroup-wide
+ * reductions and barriers between the steps, and takes the next, until none
+ * is left.  Both forms give the same iterates up to rounding order.  Errors: AMGMPCG_INVALID_ARG for bad arguments (checked before
+ * any device call), AMGMPCG_NOT_SPD, AMGMPCG_OOM / AMGMPCG_HIP_ERROR from
+ * the device. */
 int amgmpcg_setup_batched(int32_t count, const amgmpcg_grid* grids, const amgmpcg_options* opts,
                           void* stream, amgmpcg_handle** out);
 

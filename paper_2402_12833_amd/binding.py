@@ -32,7 +32,8 @@ class Options(ctypes.Structure):
     _fields_ = [("m", c_int32), ("nu", c_int32), ("omega", c_double), ("maxit", c_int32),
                 ("precision", c_int32), ("pinv_tau", c_double), ("k_poll", c_int32),
                 ("record_history", c_int32), ("refresh_drop", c_double), ("method", c_int32),
-                ("nu_pre", c_int32), ("nu_post", c_int32), ("true_residual", c_int32)]
+                ("nu_pre", c_int32), ("nu_post", c_int32), ("true_residual", c_int32),
+                ("persistent", c_int32)]
 
 
 class CsrMatrix(ctypes.Structure):

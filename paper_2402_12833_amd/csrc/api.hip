@@ -128,6 +128,7 @@ static void validate_options(const amgmpcg_options* o) {
         throw ApiError(AMGMPCG_INVALID_ARG, "nu_pre and nu_post must be equal (symmetric V-cycle)");
     if (o->true_residual != 0 && o->true_residual != 1)
         throw ApiError(AMGMPCG_INVALID_ARG, "true_residual must be 0 or 1");
+    if (o->persistent != 0 && o->persistent != 1) throw ApiError(AMGMPCG_INVALID_ARG, "persistent must be 0 or 1");
 }
 
 static void validate_grid(const amgmpcg_grid* g) {
@@ -169,6 +170,7 @@ void amgmpcg_default_options(amgmpcg_options* o) {
     o->nu_pre = 0;
     o->nu_post = 0;
     o->true_residual = 1;
+    o->persistent = 0;
 }
 
 int amgmpcg_setup_grid(const amgmpcg_grid* grid, const amgmpcg_options* opts, void* stream, amgmpcg_handle** out) {

@@ -37,6 +37,7 @@ struct Ctl {
     double drop2;     // refresh_drop^2
     double tau;       // eigenvalue cut of the unit-diagonal Gram
     double relres_true;   // ||b - A x||_2 / ||b||_2 of the returned x (FP64), when computed
+    double tol;           // relative tolerance (read by the persistent batched launch)
 };
 
 // Logical block index so that each XCD (blockIdx % 8) owns a contiguous range
@@ -119,6 +120,27 @@ __device__ __forceinline__ void block_sum_store(const double (&v)[K], double* pa
 
 constexpr int kRedBlock = 1024;    // threads of the single-block reduction kernels
 constexpr int kRedWaves = kRedBlock / 64;
+
+// Sum K per-thread values over a block of BS threads into res[0 .. K)
+// (shared): the waves reduce by recursive halving, then the wave sums are
+// added in wave order.  Fixed order: deterministic.
+template <int K, int BS>
+__device__ __forceinline__ void block_reduce_bs(double (&v)[K], double* res) {
+    constexpr int KP = pow2_up(K);
+    constexpr int NW = BS / 64;
+    __shared__ double sh[NW][KP];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int vi = wave_reduce_multi<K>(v);
+    if ((lane & (64 / KP - 1)) == 0) sh[w][vi] = v[0];
+    __syncthreads();
+    for (int k = t; k < K; k += BS) {
+        double s = sh[0][k];
+#pragma unroll
+        for (int q = 1; q < NW; ++q) s += sh[q][k];
+        res[k] = s;
+    }
+    __syncthreads();
+}
 
 // Thread t's sum of rows t, t + kRedBlock, ... of each of K value-major
 // partial arrays part[k * nblk + b] (b < nblk), fixed order.  For

@@ -115,12 +115,8 @@ __device__ int wave_pinv(const double* G, double tau, double* Gplus) {
 }
 
 // After the init residual: ||b||, ||r_0||, stop if r_0 already small.
-__device__ __forceinline__ void reduce_init_body(Ctl* ctl, const double* part, int nblk, double tol,
-                                                 double* rhist) {
-    __shared__ double res[2];
-    reduce_partials<2>(part, nblk, res);
-    if (threadIdx.x != 0) return;
-    const double bn2 = res[0], rho = res[1];
+// One thread, given the sums ||b||^2 and ||r_0||^2.
+__device__ __forceinline__ void init_decide(Ctl* ctl, double bn2, double rho, double tol, double* rhist) {
     ctl->bnorm2 = bn2;
     ctl->tol2 = tol * tol * bn2;
     ctl->rho = rho;
@@ -143,6 +139,14 @@ __device__ __forceinline__ void reduce_init_body(Ctl* ctl, const double* part, i
     }
 }
 
+__device__ __forceinline__ void reduce_init_body(Ctl* ctl, const double* part, int nblk, double tol,
+                                                 double* rhist) {
+    __shared__ double res[2];
+    reduce_partials<2>(part, nblk, res);
+    if (threadIdx.x != 0) return;
+    init_decide(ctl, res[0], res[1], tol, rhist);
+}
+
 static __global__ void __launch_bounds__(kRedBlock) k_reduce_init(Ctl* ctl, const double* part, int nblk, double tol,
                                                         double* rhist) {
     reduce_init_body(ctl, part, nblk, tol, rhist);
@@ -154,6 +158,44 @@ static __global__ void __launch_bounds__(kRedBlock) k_true_relres(Ctl* ctl, cons
     __shared__ double res[2];
     reduce_partials<2>(part, nblk, res);
     if (threadIdx.x == 0) ctl->relres_true = res[0] > 0.0 ? sqrt(res[1] / res[0]) : 0.0;
+}
+
+// Residual check of r_{k+1} (one thread, given rho = ||r_{k+1}||^2): counts
+// the x update, stops on convergence, a non-finite residual or maxit, and
+// in the mixed form (mixed != 0) only requests a true-residual refresh on
+// convergence of the recursive residual (the refresh decides).  Returns the
+// new state (0 running, 1 stop after the pending x update).
+__device__ __forceinline__ int beta_decide(Ctl* ctl, double rho, double* rhist, int mixed) {
+    const int it = ctl->it + 1;
+    ctl->it = it;
+    ctl->rho = rho;
+    if (rhist && it < ctl->hist_cap + 1) rhist[it] = sqrt(rho);
+    int st = 0;
+    if (!isfinite(rho)) {
+        ctl->status = kNONFINITE;
+        st = 1;
+    } else if (rho <= ctl->tol2 && !mixed) {
+        ctl->status = kOK;
+        st = 1;
+    } else if (it >= ctl->maxit) {
+        ctl->status = kMAXIT;
+        st = 1;
+    } else if (mixed && (rho <= ctl->tol2 || rho <= ctl->drop2 * ctl->rho_ref)) {
+        ctl->refresh_req = 1;
+    }
+    ctl->state = st;
+    return st;
+}
+
+// beta = G^+ W (NB x NB), entries q = tid, tid + nt, ... of this thread.
+template <int NB>
+__device__ __forceinline__ void beta_apply(const double* Gplus, const double* W, double* beta, int tid, int nt) {
+    for (int q = tid; q < NB * NB; q += nt) {
+        const int a = q / NB, c = q % NB;
+        double s = 0.0;
+        for (int m = 0; m < NB; ++m) s += Gplus[a * NB + m] * W[m * NB + c];
+        beta[q] = s;
+    }
 }
 
 // Residual check of r_{k+1} and beta = G_k^+ W (W = Q_k^T Z_{k+1}).
@@ -191,49 +233,17 @@ __device__ __forceinline__ void reduce_beta_body(Ctl* ctl, const double* part_rh
     }
     if (state != 0) return;
     __shared__ int stop;
-    if (threadIdx.x == 0) {
-        const double rho = rho_s[0];
-        const int it = ctl->it + 1;
-        ctl->it = it;
-        ctl->rho = rho;
-        if (rhist && it < ctl->hist_cap + 1) rhist[it] = sqrt(rho);
-        int st = 0;
-        if (!isfinite(rho)) {
-            ctl->status = kNONFINITE;
-            st = 1;
-        } else if (rho <= ctl->tol2 && !mixed) {
-            ctl->status = kOK;
-            st = 1;
-        } else if (it >= ctl->maxit) {
-            ctl->status = kMAXIT;
-            st = 1;
-        } else if (mixed && (rho <= ctl->tol2 || rho <= ctl->drop2 * ctl->rho_ref)) {
-            ctl->refresh_req = 1;
-        }
-        ctl->state = st;
-        stop = st;
-    }
+    if (threadIdx.x == 0) stop = beta_decide(ctl, rho_s[0], rhist, mixed);
     __syncthreads();
     if (stop) return;
-    for (int q = threadIdx.x; q < NB * NB; q += kRedBlock) {
-        const int a = q / NB, c = q % NB;
-        double s = 0.0;
-        for (int m = 0; m < NB; ++m) s += Gplus[a * NB + m] * W[m * NB + c];
-        beta[q] = s;
-    }
+    beta_apply<NB>(Gplus, W, beta, threadIdx.x, kRedBlock);
     // the other blocks of the window: beta_j = G_j^+ (Q_j^T Z)
     for (int j = 0; j < nwin; ++j) {
         if (j == cur) continue;
         __syncthreads();
         reduce_partials<NB * NB>(part_Wall + (size_t)j * kMaxNB * kMaxNB * nblk_W, nblk_W, W);
-        const double* Gj = Gplus_all + (size_t)j * kMaxNB * kMaxNB;
-        double* bj = beta_all + (size_t)j * kMaxNB * kMaxNB;
-        for (int q = threadIdx.x; q < NB * NB; q += kRedBlock) {
-            const int a = q / NB, c = q % NB;
-            double s = 0.0;
-            for (int m = 0; m < NB; ++m) s += Gj[a * NB + m] * W[m * NB + c];
-            bj[q] = s;
-        }
+        beta_apply<NB>(Gplus_all + (size_t)j * kMaxNB * kMaxNB, W, beta_all + (size_t)j * kMaxNB * kMaxNB,
+                       threadIdx.x, kRedBlock);
     }
 }
 
@@ -243,6 +253,42 @@ __global__ void __launch_bounds__(kRedBlock) k_reduce_beta(Ctl* ctl, const doubl
                                                         const double* Gplus_all, double* beta_all, double* rhist,
                                                         int mixed) {
     reduce_beta_body<NB>(ctl, part_rho, nblk_rho, part_Wall, nblk_W, nwin, cur, Gplus_all, beta_all, rhist, mixed);
+}
+
+// Gram G = P^T A P (upper triangle mirrored) and g = P^T r from the sums
+// red[0 .. NG + NB) (shared), pseudo-inverse, alpha = G^+ g, rank; a rank of 0
+// is a breakdown.  All threads of the block (at least 64) call it; G, Gp:
+// shared NB x NB scratch, rank_s: a shared int.
+template <int NB>
+__device__ __forceinline__ void alpha_apply(Ctl* ctl, const double* red, double* G, double* Gp, int* rank_s,
+                                            double* Gplus, double* alpha, double* ahist) {
+    constexpr int NG = NB * (NB + 1) / 2;
+    if (threadIdx.x == 0) {
+        int q = 0;
+        for (int a = 0; a < NB; ++a)
+            for (int c = a; c < NB; ++c, ++q) G[a * NB + c] = G[c * NB + a] = red[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int rk = wave_pinv<NB>(G, ctl->tau, Gp);
+        if (threadIdx.x == 0) *rank_s = rk;
+    }
+    __syncthreads();
+    if (threadIdx.x < NB * NB) Gplus[threadIdx.x] = Gp[threadIdx.x];
+    if (threadIdx.x < NB) {
+        double s = 0.0;
+        for (int m = 0; m < NB; ++m) s += Gp[threadIdx.x * NB + m] * red[NG + m];
+        alpha[threadIdx.x] = s;
+        const int it = ctl->it;
+        if (ahist && it < ctl->hist_cap) ahist[(size_t)it * NB + threadIdx.x] = s;
+    }
+    if (threadIdx.x == 0) {
+        ctl->rank = *rank_s;
+        if (*rank_s == 0) {
+            ctl->status = kBREAKDOWN;
+            ctl->state = 2;
+        }
+    }
 }
 
 // Gram G = P^T A P (upper triangle mirrored), g = P^T r, pseudo-inverse,
@@ -264,32 +310,7 @@ __device__ __forceinline__ void reduce_alpha_body(Ctl* ctl, const double* part, 
         if (threadIdx.x == 0) ctl->state = 2;
         return;
     }
-    if (threadIdx.x == 0) {
-        int q = 0;
-        for (int a = 0; a < NB; ++a)
-            for (int c = a; c < NB; ++c, ++q) G[a * NB + c] = G[c * NB + a] = red[q];
-    }
-    __syncthreads();
-    if (threadIdx.x < 64) {
-        const int rk = wave_pinv<NB>(G, ctl->tau, Gp);
-        if (threadIdx.x == 0) rank_s = rk;
-    }
-    __syncthreads();
-    if (threadIdx.x < NB * NB) Gplus[threadIdx.x] = Gp[threadIdx.x];
-    if (threadIdx.x < NB) {
-        double s = 0.0;
-        for (int m = 0; m < NB; ++m) s += Gp[threadIdx.x * NB + m] * red[NG + m];
-        alpha[threadIdx.x] = s;
-        const int it = ctl->it;
-        if (ahist && it < ctl->hist_cap) ahist[(size_t)it * NB + threadIdx.x] = s;
-    }
-    if (threadIdx.x == 0) {
-        ctl->rank = rank_s;
-        if (rank_s == 0) {
-            ctl->status = kBREAKDOWN;
-            ctl->state = 2;
-        }
-    }
+    alpha_apply<NB>(ctl, red, G, Gp, &rank_s, Gplus, alpha, ahist);
 }
 
 template <int NB>
@@ -299,12 +320,8 @@ __global__ void __launch_bounds__(kRedBlock) k_reduce_alpha(Ctl* ctl, const doub
 }
 
 // After a true-residual refresh r = b - A x: accept convergence or go on.
-__device__ __forceinline__ void refresh_reduce_body(Ctl* ctl, const double* part, int nblk, double* rhist) {
-    if (ctl->state == 2 || !ctl->refresh_req) return;
-    __shared__ double res[1];
-    reduce_partials<1>(part, nblk, res);
-    if (threadIdx.x != 0) return;
-    const double rho = res[0];
+// One thread, given rho = ||b - A x||^2.
+__device__ __forceinline__ void refresh_decide(Ctl* ctl, double rho, double* rhist) {
     ctl->refresh_req = 0;
     ctl->refreshes += 1;
     ctl->rho = rho;
@@ -318,6 +335,14 @@ __device__ __forceinline__ void refresh_reduce_body(Ctl* ctl, const double* part
         ctl->status = kOK;
         ctl->state = 2;
     }
+}
+
+__device__ __forceinline__ void refresh_reduce_body(Ctl* ctl, const double* part, int nblk, double* rhist) {
+    if (ctl->state == 2 || !ctl->refresh_req) return;
+    __shared__ double res[1];
+    reduce_partials<1>(part, nblk, res);
+    if (threadIdx.x != 0) return;
+    refresh_decide(ctl, res[0], rhist);
 }
 
 static __global__ void __launch_bounds__(kRedBlock) k_refresh_reduce(Ctl* ctl, const double* part, int nblk, double* rhist) {

@@ -3,6 +3,7 @@
 #include "grid_kernels.hpp"
 #include "batched.hpp"
 #include "batched_layout.hpp"
+#include "batched_persistent.hpp"
 
 namespace amg {
 
@@ -118,6 +119,22 @@ class BatchedSolver : public BatchedBase {
             maps[k] = BBlk{lay.maps[k].inst, lay.maps[k].blk, lay.maps[k].start, lay.maps[k].end};
         maps_.alloc(maps.size());
         HIPCHK(hipMemcpy(maps_.p, maps.data(), maps.size() * sizeof(BBlk), hipMemcpyHostToDevice));
+
+        // persistent launch: the problems largest first (then in table order)
+        std::vector<int> ord(cnt);
+        for (int q = 0; q < cnt; ++q) ord[q] = q;
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+            return lay.inst[a].N[lay.inst[a].nlev - 1] > lay.inst[b].N[lay.inst[b].nlev - 1];
+        });
+        porder_.alloc(cnt);
+        HIPCHK(hipMemcpy(porder_.p, ord.data(), cnt * sizeof(int), hipMemcpyHostToDevice));
+        queue_.alloc(1);
+        HIPCHK(hipMemset(queue_.p, 0, sizeof(int)));
+        int dev = 0, cus = 0, per_cu = 0;
+        HIPCHK(hipGetDevice(&dev));
+        HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_b_persistent<DIM, T>, kPB, 0));
+        pgrid_ = std::max(1, std::min(cnt, cus * std::max(1, per_cu)));
         HIPCHK(hipHostMalloc((void**)&hctl_, (size_t)cnt * sizeof(Ctl), hipHostMallocDefault));
         HIPCHK(hipEventCreate(&ev0_));
         HIPCHK(hipEventCreate(&ev1_));
@@ -127,6 +144,8 @@ class BatchedSolver : public BatchedBase {
     ~BatchedSolver() override {
         if (exec_) (void)hipGraphExecDestroy(exec_);
         if (graph_) (void)hipGraphDestroy(graph_);
+        if (pexec_) (void)hipGraphExecDestroy(pexec_);
+        if (pgraph_) (void)hipGraphDestroy(pgraph_);
         if (cap_stream_) (void)hipStreamDestroy(cap_stream_);
         if (hctl_) (void)hipHostFree(hctl_);
         if (ev0_) (void)hipEventDestroy(ev0_);
@@ -143,8 +162,10 @@ class BatchedSolver : public BatchedBase {
             c.maxit = maxit;
             c.drop2 = opt_.refresh_drop * opt_.refresh_drop;
             c.tau = opt_.pinv_tau > 0 ? opt_.pinv_tau : 64.0 * nlev_[i] * unit;
+            c.tol = tol;
         }
         const size_t nbytes = (size_t)offs_[count] * sizeof(double);
+        if (opt_.persistent) return solve_persistent(b_dev, x_dev, nbytes, infos, batch_ms);
         HIPCHK(hipEventRecord(ev0_, stream_));
         HIPCHK(hipMemcpyAsync(ctl_.p, hctl_, (size_t)count * sizeof(Ctl), hipMemcpyHostToDevice, stream_));
         HIPCHK(hipMemcpyAsync(b_.p, b_dev, nbytes, hipMemcpyDeviceToDevice, stream_));
@@ -167,6 +188,41 @@ class BatchedSolver : public BatchedBase {
         HIPCHK(hipStreamSynchronize(stream_));
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, ev0_, ev1_));
+        return finish(infos, batch_ms, ms);
+    }
+
+   private:
+    // One persistent launch (with the reset of its queue) for the whole
+    // solve: captured once into a graph and launched once per solve.
+    int solve_persistent(const double* b_dev, double* x_dev, size_t nbytes, amgmpcg_info* infos, double* batch_ms) {
+        if (!pexec_) {
+            if (!cap_stream_) HIPCHK(hipStreamCreateWithFlags(&cap_stream_, hipStreamNonBlocking));
+            HIPCHK(hipStreamBeginCapture(cap_stream_, hipStreamCaptureModeThreadLocal));
+            k_b_reset_queue<<<1, 64, 0, cap_stream_>>>(queue_.p);
+            k_b_persistent<DIM, T><<<pgrid_, kPB, 0, cap_stream_>>>(inst_.p, porder_.p, count, queue_.p,
+                                                                     T(opt_.omega), opt_.nu >= 2 ? 1 : 0,
+                                                                     mixed_ ? 1 : 0);
+            hipError_t launch_err = hipGetLastError();
+            HIPCHK(hipStreamEndCapture(cap_stream_, &pgraph_));
+            HIPCHK(launch_err);
+            HIPCHK(hipGraphInstantiate(&pexec_, pgraph_, nullptr, nullptr, 0));
+        }
+        HIPCHK(hipEventRecord(ev0_, stream_));
+        HIPCHK(hipMemcpyAsync(ctl_.p, hctl_, (size_t)count * sizeof(Ctl), hipMemcpyHostToDevice, stream_));
+        HIPCHK(hipMemcpyAsync(b_.p, b_dev, nbytes, hipMemcpyDeviceToDevice, stream_));
+        HIPCHK(hipMemcpyAsync(x_.p, x_dev, nbytes, hipMemcpyDeviceToDevice, stream_));
+        HIPCHK(hipGraphLaunch(pexec_, stream_));
+        HIPCHK(hipMemcpyAsync(x_dev, x_.p, nbytes, hipMemcpyDeviceToDevice, stream_));
+        HIPCHK(hipEventRecord(ev1_, stream_));
+        HIPCHK(hipMemcpyAsync(hctl_, ctl_.p, (size_t)count * sizeof(Ctl), hipMemcpyDeviceToHost, stream_));
+        HIPCHK(hipStreamSynchronize(stream_));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, ev0_, ev1_));
+        return finish(infos, batch_ms, ms);
+    }
+
+    // Per-problem results from the control words (hctl_, instance order).
+    int finish(amgmpcg_info* infos, double* batch_ms, float ms) {
         if (batch_ms) *batch_ms = ms;
         int worst = AMGMPCG_OK;
         for (int i = 0; i < count; ++i) {
@@ -186,7 +242,6 @@ class BatchedSolver : public BatchedBase {
         return worst;
     }
 
-   private:
     struct Range {
         int off = 0, cnt = 0;   // entries of maps_
     };
@@ -281,7 +336,7 @@ class BatchedSolver : public BatchedBase {
     }
 
     void capture() {
-        HIPCHK(hipStreamCreateWithFlags(&cap_stream_, hipStreamNonBlocking));
+        if (!cap_stream_) HIPCHK(hipStreamCreateWithFlags(&cap_stream_, hipStreamNonBlocking));
         HIPCHK(hipStreamBeginCapture(cap_stream_, hipStreamCaptureModeThreadLocal));
         for (int k = 0; k < kpoll_; ++k) enqueue_iteration(cap_stream_);
         hipError_t launch_err = hipGetLastError();
@@ -307,6 +362,10 @@ class BatchedSolver : public BatchedBase {
     DevBuf<Ctl> ctl_;
     DevBuf<BInst<T>> inst_;
     DevBuf<BBlk> maps_;
+    DevBuf<int> porder_, queue_;      // persistent launch: problem order and queue counter
+    int pgrid_ = 1;                   // its workgroups
+    hipGraph_t pgraph_ = nullptr;
+    hipGraphExec_t pexec_ = nullptr;
     Ctl* hctl_ = nullptr;
     hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
 };

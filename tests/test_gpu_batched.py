@@ -1,10 +1,12 @@
-"""GPU parity of the batched solve (many problems, one graph of batched
-launches) against the FP64 oracle.
+"""GPU parity of the batched solve (many problems) against the FP64 oracle,
+for both forms of the launch: one persistent launch that runs each
+problem's whole solve in one workgroup (persistent = 1), and
+one batched launch per step over all problems (persistent = 0, the default).
 
 Each problem of the batch must match the oracle run on that problem alone:
-iterates at equal k to 1e-10 relative (FP64), converged iteration counts
-within one; in the mixed form every problem reaches a true FP64 relative
-residual <= 1e-8.
+iterates at equal k to 1e-10 relative (FP64, normwise and element-wise),
+converged iteration counts within one; in the mixed form every problem
+reaches a true FP64 relative residual <= 1e-8.
 """
 import numpy as np
 import pytest
@@ -36,10 +38,14 @@ def small_batch():
     return probs
 
 
-def test_batched_iterates_match_oracle():
+PATHS = pytest.mark.parametrize("persistent", [1, 0], ids=["persistent", "steps"])
+
+
+@PATHS
+def test_batched_iterates_match_oracle(persistent):
     probs = small_batch()
     bs = [W.rhs(n * n, seed) for (_, n, _, seed) in probs]
-    s = amg.BatchedSolver([(d, n, nl) for (d, n, nl, _) in probs])
+    s = amg.BatchedSolver([(d, n, nl) for (d, n, nl, _) in probs], persistent=persistent)
     bcat = torch.as_tensor(np.concatenate(bs), device="cuda")
     for k in (1, 4):
         x, infos, _ = s.solve(bcat, tol=0.0, maxit=k)
@@ -60,10 +66,11 @@ def test_batched_iterates_match_oracle():
     s.close()
 
 
-def test_batched_mixed_precision():
+@PATHS
+def test_batched_mixed_precision(persistent):
     probs = small_batch()
     bs = [W.rhs(n * n, seed) for (_, n, _, seed) in probs]
-    s = amg.BatchedSolver([(d, n, nl) for (d, n, nl, _) in probs], precision=1)
+    s = amg.BatchedSolver([(d, n, nl) for (d, n, nl, _) in probs], precision=1, persistent=persistent)
     x, infos, ms = s.solve(torch.as_tensor(np.concatenate(bs), device="cuda"), tol=1e-8)
     xh = x.cpu().numpy()
     for i, (d, n, nl, seed) in enumerate(probs):
@@ -74,9 +81,10 @@ def test_batched_mixed_precision():
     s.close()
 
 
-def test_batched_edge_cases():
+@PATHS
+def test_batched_edge_cases(persistent):
     probs = [(2, 31, 3), (2, 15, 2)]
-    s = amg.BatchedSolver(probs)
+    s = amg.BatchedSolver(probs, persistent=persistent)
     b = np.concatenate([np.zeros(31 * 31), W.rhs(225, 3)])
     x0 = torch.ones(31 * 31 + 225, dtype=torch.float64, device="cuda")
     x, infos, _ = s.solve(torch.as_tensor(b, device="cuda"), x0, tol=1e-8)
@@ -91,10 +99,11 @@ def test_batched_edge_cases():
     s.close()
 
 
-def test_batched_512_full():
-    """The 512-problem workload (sides 31..255) in one launch, FP32 bulk."""
+@PATHS
+def test_batched_512_full(persistent):
+    """The 512-problem workload (sides 31..255), FP32 bulk."""
     table = W.batched_instances()
-    s = amg.BatchedSolver([(2, t.n, t.nlevels) for t in table], precision=1)
+    s = amg.BatchedSolver([(2, t.n, t.nlevels) for t in table], precision=1, persistent=persistent)
     bs = [W.batched_rhs(t) for t in table]
     x, infos, ms = s.solve(torch.as_tensor(np.concatenate(bs), device="cuda"), tol=1e-8)
     xh = x.cpu().numpy()
@@ -114,4 +123,55 @@ def test_batched_512_full():
         assert abs(infos[i]["iterations"] - o.iterations) <= 2, (i, t, infos[i]["iterations"], o.iterations)
     print(f"batched 512: {ms:.2f} ms, worst true relres {worst:.2e}, "
           f"iterations {min(i['iterations'] for i in infos)}..{max(i['iterations'] for i in infos)}")
+    s.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_persistent_matches_step_path(precision):
+    """The persistent launch and the per-step launches compute the same
+    iterates (their sums run over different partitions: equal to rounding)
+    and the same iteration counts; repeated persistent solves agree bit for
+    bit (each problem's sums have a fixed order whichever workgroup takes
+    it)."""
+    probs = small_batch()
+    bs = torch.as_tensor(np.concatenate([W.rhs(n * n, seed) for (_, n, _, seed) in probs]), device="cuda")
+    grid = [(d, n, nl) for (d, n, nl, _) in probs]
+    pers = amg.BatchedSolver(grid, precision=precision, persistent=1)
+    step = amg.BatchedSolver(grid, precision=precision, persistent=0)
+    for k in (1, 3):
+        xp, ip, _ = pers.solve(bs, tol=0.0, maxit=k)
+        xs, is_, _ = step.solve(bs, tol=0.0, maxit=k)
+        for i in range(len(probs)):
+            a = xp[pers.offsets[i]:pers.offsets[i + 1]].cpu().numpy()
+            b = xs[step.offsets[i]:step.offsets[i + 1]].cpu().numpy()
+            bar = 1e-10 if precision == 0 else 1e-4
+            assert np.linalg.norm(a - b) <= bar * np.linalg.norm(b), (i, k)
+            assert np.abs(a - b).max() <= bar * np.abs(b).max(), (i, k)
+            assert ip[i]["iterations"] == is_[i]["iterations"], (i, k)
+    xp, ip, _ = pers.solve(bs, tol=1e-8)
+    xs, is_, _ = step.solve(bs, tol=1e-8)
+    for i in range(len(probs)):
+        assert ip[i]["status"] == is_[i]["status"] == amg.OK
+        assert abs(ip[i]["iterations"] - is_[i]["iterations"]) <= 1
+    xq, iq, _ = pers.solve(bs, tol=1e-8)
+    assert torch.equal(xp, xq) and [i["iterations"] for i in iq] == [i["iterations"] for i in ip]
+    pers.close()
+    step.close()
+
+
+def test_persistent_3d_batch():
+    """Three-dimensional problems through the persistent launch: iterates at
+    equal k against the oracle to 1e-10."""
+    probs = [(3, 15, 3, 71), (3, 8, 2, 72), (3, 20, 3, 73), (3, 3, 1, 74)]
+    bs = [W.rhs(n ** 3, seed) for (_, n, _, seed) in probs]
+    s = amg.BatchedSolver([(d, n, nl) for (d, n, nl, _) in probs])
+    bcat = torch.as_tensor(np.concatenate(bs), device="cuda")
+    for k in (1, 3):
+        x, infos, _ = s.solve(bcat, tol=0.0, maxit=k)
+        xh = x.cpu().numpy()
+        for i, (d, n, nl, seed) in enumerate(probs):
+            o = mpcg.mpcg(hierarchy.build(d, n, nl), bs[i], tol=0.0, maxit=k)
+            xi = xh[s.offsets[i]:s.offsets[i + 1]]
+            assert infos[i]["iterations"] == o.iterations, (i, n)
+            assert np.linalg.norm(xi - o.x) <= 1e-10 * np.linalg.norm(o.x), (i, n, k)
     s.close()
