@@ -489,6 +489,106 @@ __device__ __forceinline__ void fine_z(const T* __restrict__ Y, int nc, const T*
     if (NE) z[NB - 1] = dzero ? T(0) : dl[idx];
 }
 
+template <int DIM, typename T, int NB, int NE>
+struct ZWave {
+    static constexpr int NL = NB - NE;
+    static constexpr int SY = even_up(NL > 1 ? NL - 1 : 1);
+    static constexpr int NZC = DIM == 3 ? 2 : 1;
+    T v[NL > 1 ? NZC : 1][2][NL > 1 ? SY : 1];   // coarse parents: [z][y][column]
+    T cl, dlv;                                  // cL and the learned direction at the node
+};
+
+// Load phase: every load of fine_z_wave, issued without waiting on any of
+// them (the branches around them are uniform or lane masks), so that a
+// caller can issue its own loads beside them and wait once.  Lanes 0..32
+// load the coarse parents (outside the grid at a clamped node); a missing
+// second y or z parent is not loaded but set to zero (weight 0 in the
+// combine phase).
+template <int DIM, typename T, int NB, int NE>
+__device__ __forceinline__ void fine_z_wave_load(const T* __restrict__ Y, int nc, const T* __restrict__ cL,
+                                                 const T* __restrict__ dl, int idx, const Idx<DIM>& p, int i_row,
+                                                 ZWave<DIM, T, NB, NE>& zw) {
+    using ZW = ZWave<DIM, T, NB, NE>;
+    zw.cl = cL[idx];
+    zw.dlv = NE ? dl[idx] : T(0);
+    if constexpr (ZW::NL > 1) {
+        const int lane = threadIdx.x & 63;
+        const int i0 = __builtin_amdgcn_readfirstlane(i_row);
+        const int Jc = min(max((i0 >> 1) - 1 + lane, 0), nc - 1);
+        const Par py = parents(p.j, nc);
+        const Par pz = DIM == 3 ? parents(p.k, nc) : Par{0, 0, 1.f, 0.f, 1};
+#pragma unroll
+        for (int cz = 0; cz < ZW::NZC; ++cz)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int c = 0; c < ZW::SY; ++c) zw.v[cz][b][c] = T(0);
+        if (lane <= 32) {
+#pragma unroll
+            for (int cz = 0; cz < ZW::NZC; ++cz) {
+                if (cz == 1 && pz.cnt < 2) continue;
+                const int K = DIM == 3 ? (cz == 0 ? pz.lo : pz.hi) : 0;
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    if (b == 1 && py.cnt < 2) continue;
+                    const int Jy = b == 0 ? py.lo : py.hi;
+                    load_node<T, ZW::SY>(Y + ((size_t)nc * (Jy + (size_t)nc * K) + Jc) * ZW::SY, zw.v[cz][b]);
+                }
+            }
+        }
+    }
+}
+
+// Combine phase (all 64 lanes): the y/z weights per coarse x parent, then
+// each fine lane's two x parents by shuffles; the zero-weight terms add
+// exactly 0.
+template <int DIM, typename T, int NB, int NE>
+__device__ __forceinline__ void fine_z_wave_finish(const ZWave<DIM, T, NB, NE>& zw, int nc, bool dzero,
+                                                   const Idx<DIM>& p, int i_row, T (&z)[NB]) {
+    using ZW = ZWave<DIM, T, NB, NE>;
+    constexpr int NL = ZW::NL;
+    if constexpr (NL > 1) {
+        constexpr int SY = ZW::SY;
+        const int lane = threadIdx.x & 63;
+        const int i0 = __builtin_amdgcn_readfirstlane(i_row);
+        const int jb = (i0 >> 1) - 1;
+        const int J = jb + lane;
+        const bool jin = lane <= 32 && J >= 0 && J < nc;
+        const Par py = parents(p.j, nc);
+        const Par pz = DIM == 3 ? parents(p.k, nc) : Par{0, 0, 1.f, 0.f, 1};
+        T row[SY];
+#pragma unroll
+        for (int c = 0; c < SY; ++c) row[c] = T(0);
+#pragma unroll
+        for (int cz = 0; cz < ZW::NZC; ++cz) {
+            const T wz = DIM == 3 ? (cz == 0 ? T(pz.wlo) : (pz.cnt < 2 ? T(0) : T(pz.whi))) : T(1);
+            T plane[SY];
+#pragma unroll
+            for (int c = 0; c < SY; ++c) plane[c] = T(0);
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const T wy = b == 0 ? T(py.wlo) : (py.cnt < 2 ? T(0) : T(py.whi));
+#pragma unroll
+                for (int c = 0; c < SY; ++c) plane[c] += wy * zw.v[cz][b][c];
+            }
+#pragma unroll
+            for (int c = 0; c < SY; ++c) row[c] += wz * plane[c];
+        }
+#pragma unroll
+        for (int c = 0; c < SY; ++c) row[c] = jin ? row[c] : T(0);
+        const XPar px = xparents(p.i, nc);
+        const int llo = min(max(px.lo - jb, 0), 32), lhi = min(max(px.hi - jb, 0), 32);
+#pragma unroll
+        for (int c = 0; c < NL - 1; ++c) {
+            const T a = __shfl(row[c], llo);
+            const T b2 = __shfl(row[c], lhi);
+            z[c] = T(px.wlo) * a + T(px.whi) * b2;
+        }
+    }
+    z[NL - 1] = zw.cl;
+    if (NE) z[NB - 1] = dzero ? T(0) : zw.dlv;
+}
+
 // fine_z for a whole wavefront (all 64 lanes must call it; lanes past the
 // row end use a clamped node and their result is discarded).  The wave's 64
 // fine nodes lie in one x-row, so their y/z parents are common and their x
@@ -500,51 +600,9 @@ template <int DIM, typename T, int NB, int NE>
 __device__ __forceinline__ void fine_z_wave(const T* __restrict__ Y, int nc, const T* __restrict__ cL,
                                             const T* __restrict__ dl, bool dzero, int idx, const Idx<DIM>& p,
                                             int i_row, T (&z)[NB]) {
-    constexpr int NL = NB - NE;
-    if constexpr (NL > 1) {
-        constexpr int SY = even_up(NL > 1 ? NL - 1 : 1);
-        const int lane = threadIdx.x & 63;
-        const int i0 = __builtin_amdgcn_readfirstlane(i_row);
-        const int jb = (i0 >> 1) - 1;
-        const Par py = parents(p.j, nc);
-        const Par pz = DIM == 3 ? parents(p.k, nc) : Par{0, 0, 1.f, 0.f, 1};
-        const int J = jb + lane;
-        const bool jin = lane <= 32 && J >= 0 && J < nc;
-        const int Jc = jin ? J : 0;
-        T row[SY];
-#pragma unroll
-        for (int c = 0; c < SY; ++c) row[c] = T(0);
-        if (jin) {
-            const int nzc = DIM == 3 ? pz.cnt : 1;
-            for (int cz = 0; cz < nzc; ++cz) {
-                const int K = DIM == 3 ? (cz ? pz.hi : pz.lo) : 0;
-                const T wz = DIM == 3 ? T(cz ? pz.whi : pz.wlo) : T(1);
-                T plane[SY];
-#pragma unroll
-                for (int c = 0; c < SY; ++c) plane[c] = T(0);
-                for (int b = 0; b < py.cnt; ++b) {
-                    const int Jy = b ? py.hi : py.lo;
-                    const T wy = T(b ? py.whi : py.wlo);
-                    T v[SY];
-                    load_node<T, SY>(Y + ((size_t)nc * (Jy + (size_t)nc * K) + Jc) * SY, v);
-#pragma unroll
-                    for (int c = 0; c < SY; ++c) plane[c] += wy * v[c];
-                }
-#pragma unroll
-                for (int c = 0; c < SY; ++c) row[c] += wz * plane[c];
-            }
-        }
-        const XPar px = xparents(p.i, nc);
-        const int llo = min(max(px.lo - jb, 0), 32), lhi = min(max(px.hi - jb, 0), 32);
-#pragma unroll
-        for (int c = 0; c < NL - 1; ++c) {
-            const T a = __shfl(row[c], llo);
-            const T b2 = __shfl(row[c], lhi);
-            z[c] = T(px.wlo) * a + T(px.whi) * b2;
-        }
-    }
-    z[NL - 1] = cL[idx];
-    if (NE) z[NB - 1] = dzero ? T(0) : dl[idx];
+    ZWave<DIM, T, NB, NE> zw;
+    fine_z_wave_load<DIM, T, NB, NE>(Y, nc, cL, dl, idx, p, i_row, zw);
+    fine_z_wave_finish<DIM, T, NB, NE>(zw, nc, dzero, p, i_row, z);
 }
 
 // (A P)_idx for all columns of a node-major block on the finest level.
@@ -1198,6 +1256,12 @@ __global__ void __launch_bounds__(kTailBlock) k_tail_smooth(const Ctl* __restric
     prolong_chain_block<DIM, T>(up);
 }
 
+// Walk items per pass of the W kernel.
+#ifndef AMG_W_ITEMS
+#define AMG_W_ITEMS 1
+#endif
+constexpr int kWItems = AMG_W_ITEMS;
+
 // W_j = Q_j^T Z_{k+1} partial sums (NB x NB, entry a*NB+c = Q_j column
 // a . z^c) for the stored blocks j of the window in one launch: blocks
 // [j nbs, (j+1) nbs) work on slot j (Q + j qstride, partials at
@@ -1220,20 +1284,35 @@ __global__ void __launch_bounds__(kBlock) k_fine_W(const Ctl* __restrict__ ctl, 
 #pragma unroll
     for (int q = 0; q < NB * NB; ++q) w[q] = 0.0;
     const Band band = row_band_of(R.total, bj, nbs);
-    for (int w_ = band.start; w_ < band.end; w_ += band.stride) {
-        Idx<DIM> p;
-        int idx;
-        const bool act = row_item<DIM>(R, w_, p, idx);
-        T z[NB];
-        fine_z_wave<DIM, T, NB, NE>(Y, nc, cL, dl, dzero, idx, p, row_x(R, w_), z);
-        if (!act) continue;
-        T q[S];
-        load_node<T, S>(Q + (size_t)idx * S, q);
+    // kWItems items of the walk per pass (items past the band end repeat the
+    // first one and are not accumulated), every load of a pass issued before
+    // any is used; the sums keep the walk's order
+    constexpr int U = kWItems;
+    for (int w_ = band.start; w_ < band.end; w_ += U * band.stride) {
+        Idx<DIM> p[U];
+        int idx[U], ix[U];
+        bool act[U];
+        ZWave<DIM, T, NB, NE> zw[U];
+        T q[U][S];
 #pragma unroll
-        for (int a = 0; a < NB; ++a) {
-            const double qa = double(q[a]);
+        for (int u = 0; u < U; ++u) {
+            const int wu = w_ + u * band.stride < band.end ? w_ + u * band.stride : w_;   // uniform per wavefront
+            act[u] = row_item<DIM>(R, wu, p[u], idx[u]) && (u == 0 || wu != w_);
+            ix[u] = row_x(R, wu);
+            fine_z_wave_load<DIM, T, NB, NE>(Y, nc, cL, dl, idx[u], p[u], ix[u], zw[u]);
+            load_node<T, S>(Q + (size_t)idx[u] * S, q[u]);
+        }
 #pragma unroll
-            for (int c = 0; c < NB; ++c) w[a * NB + c] += qa * double(z[c]);
+        for (int u = 0; u < U; ++u) {
+            T z[NB];
+            fine_z_wave_finish<DIM, T, NB, NE>(zw[u], nc, dzero, p[u], ix[u], z);
+            if (!act[u]) continue;
+#pragma unroll
+            for (int a = 0; a < NB; ++a) {
+                const double qa = double(q[u][a]);
+#pragma unroll
+                for (int c = 0; c < NB; ++c) w[a * NB + c] += qa * double(z[c]);
+            }
         }
     }
     block_sum_store<NB * NB>(w, part, nbs, lb);
@@ -1284,28 +1363,46 @@ __global__ void __launch_bounds__(kBlock, (xp_blocks_per_cu<NB>())) k_update_xP(
     __syncthreads();
     T* __restrict__ Pc = win.p[cur];
     T* __restrict__ Pn = win.p[nxt];
+    if (!init && state != 0) {
+        // the stopping launch: the deferred x update alone
+        ROW_LOOP(R, lb) {
+            Idx<DIM> p;
+            int idx;
+            if (!row_item<DIM>(R, w_, p, idx)) continue;
+            T pk[S];
+            load_node<T, S>(Pc + (size_t)idx * S, pk);
+            double xi = x[idx];
+#pragma unroll
+            for (int c = 0; c < NB; ++c) xi += double(pk[c]) * sab[c];
+            x[idx] = xi;
+        }
+        return;
+    }
     ROW_LOOP(R, lb) {
         Idx<DIM> p;
         int idx;
         const bool act = row_item<DIM>(R, w_, p, idx);
+        const int ix = row_x(R, w_);
+        // every load of the item first (P_k and x unless init, the coarse
+        // parents, cL), then the arithmetic
         T pk[S];
+        double xi = 0.0;
         if (!init) {
             load_node<T, S>(Pc + (size_t)idx * S, pk);
-            if (act) {
-                double xi = x[idx];
-#pragma unroll
-                for (int c = 0; c < NB; ++c) xi += double(pk[c]) * sab[c];
-                x[idx] = xi;
-            }
-            if (state != 0) continue;
+            xi = x[idx];
         }
+        ZWave<DIM, T, NB, NE> zw;
+        fine_z_wave_load<DIM, T, NB, NE>(Y, nc, cL, dl, idx, p, ix, zw);
         T z[NB];
-        fine_z_wave<DIM, T, NB, NE>(Y, nc, cL, dl, dzero, idx, p, row_x(R, w_), z);
+        fine_z_wave_finish<DIM, T, NB, NE>(zw, nc, dzero, p, ix, z);
         if (!act) continue;
         double v[NB];
 #pragma unroll
         for (int c = 0; c < NB; ++c) v[c] = double(z[c]);
         if (!init) {
+#pragma unroll
+            for (int c = 0; c < NB; ++c) xi += double(pk[c]) * sab[c];
+            x[idx] = xi;
             const double* bc = sab + NB + cur * NB * NB;
 #pragma unroll
             for (int c = 0; c < NB; ++c)

@@ -565,8 +565,8 @@ class Solver : public SolverBase {
             }
             enqueue_mg(cf, r_.p);
             timed([&] {
-                k_fine_W<DIM, T, NB, NE><<<FBG_, kBlock, 0, stream_>>>(cf, rows_, fine_Y(), nc, cL_final_, dl(), dflag(),
-                                                                      Q_.p, 0, part_W(), 0, FBG_);
+                k_fine_W<DIM, T, NB, NE><<<fw_grid<NB, NE>(), kBlock, 0, stream_>>>(
+                    cf, rows_, fine_Y(), nc, cL_final_, dl(), dflag(), Q_.p, 0, part_W(), 0, fw_grid<NB, NE>());
             });
             timed([&] {
                 k_update_xP<DIM, T, NB, NE><<<xp_grid<NB>(), kBlock, 0, stream_>>>(cf, rows_, fine_Y(), nc, cL_final_, dl(),
@@ -1050,6 +1050,18 @@ class Solver : public SolverBase {
         return xp_blocks_per_cu<NB>() == xp_blocks_per_cu<1>() ? XPB_ : FB_;
     }
 
+    // blocks of the W launch per stored slot: one round of the resident
+    // blocks of that kernel instance (its occupancy), at most kGramBlocks
+    template <int NB, int NE>
+    int fw_grid() const {
+        static const int per_cu = [] {
+            int b = 0;
+            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_fine_W<DIM, T, NB, NE>, kBlock, 0));
+            return std::max(b, 1);
+        }();
+        return fine_blocks(rows_.total, std::min(kGramBlocks, per_cu * kNumCU));
+    }
+
     template <int NB>
     int spmm_blocks() const {
         if constexpr (DIM == 3 && zt_fits<T, NB>()) return SB_[zvar<NB>()];
@@ -1082,7 +1094,9 @@ class Solver : public SolverBase {
     double* d_Gplus(int j = 0) { return small_.p + kMaxNB + (size_t)(kMaxWin + j) * kMaxNB * kMaxNB; }
     T* Pslot(int j) { return P_.p + (size_t)j * pstride_; }
     T* Qslot(int j) { return Q_.p + (size_t)j * pstride_; }
-    double* part_Wslot(int j) { return partWin_.p + (size_t)j * kMaxNB * kMaxNB * FBG_; }
+    // W partials of every stored slot: slot j of a launch with nbs blocks per
+    // slot starts at j kMaxNB^2 nbs (nbs <= FBG_, for which it is sized)
+    double* part_Wall() { return partWin_.p; }
     PWin<T> window() {
         PWin<T> w{};
         for (int j = 0; j < m_; ++j) w.p[j] = Pslot(j);
@@ -1143,11 +1157,12 @@ class Solver : public SolverBase {
             enqueue_mg(ctl_, r_.p);
             mark(kSecFineW);
             // W_j for every stored block of the window in one launch
-            k_fine_W<DIM, T, NB, NE><<<m_ * FBG_, kBlock, 0, s>>>(
-                ctl_, rows_, fine_Y(), nc, cL_final_, dl(), dflag(), Qslot(0), pstride_, part_Wslot(0),
-                (size_t)(part_Wslot(1) - part_Wslot(0)), FBG_);
+            const int fw = fw_grid<NB, NE>();
+            k_fine_W<DIM, T, NB, NE><<<m_ * fw, kBlock, 0, s>>>(
+                ctl_, rows_, fine_Y(), nc, cL_final_, dl(), dflag(), Qslot(0), pstride_, part_Wall(),
+                (size_t)kMaxNB * kMaxNB * fw, fw);
             mark(kSecReduceBeta);
-            k_reduce_beta<NB><<<1, kRedBlock, 0, s>>>(ctl_, part_rho(), FB_, part_Wslot(0), FBG_, m_, cur,
+            k_reduce_beta<NB><<<1, kRedBlock, 0, s>>>(ctl_, part_rho(), FB_, part_Wall(), fw, m_, cur,
                                                    d_Gplus(0), d_beta(0), hist_cap_ ? rhist_.p : nullptr,
                                                    mixed_ ? 1 : 0);
             mark(kSecUpdateXP);
@@ -1182,9 +1197,9 @@ class Solver : public SolverBase {
         k_update_r<T, 1><<<FB_, kBlock, 0, s>>>(ctl_, N, Qslot(0), d_alpha(), r_.p, part_rho());
         T* z = precondition(ctl_, r_.p);
         mark(kSecFineW);
-        k_W1<T><<<FB_, kBlock, 0, s>>>(ctl_, N, Qslot(0), z, part_Wslot(0));
+        k_W1<T><<<FB_, kBlock, 0, s>>>(ctl_, N, Qslot(0), z, part_Wall());
         mark(kSecReduceBeta);
-        k_reduce_beta<1><<<1, kRedBlock, 0, s>>>(ctl_, part_rho(), FB_, part_Wslot(0), FB_, 1, 0, d_Gplus(0),
+        k_reduce_beta<1><<<1, kRedBlock, 0, s>>>(ctl_, part_rho(), FB_, part_Wall(), FB_, 1, 0, d_Gplus(0),
                                               d_beta(0), hist_cap_ ? rhist_.p : nullptr, mixed_ ? 1 : 0);
         mark(kSecUpdateXP);
         if (prof_on_)
