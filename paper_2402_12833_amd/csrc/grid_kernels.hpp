@@ -18,6 +18,8 @@
 
 #include "common.hpp"
 
+#include <type_traits>
+
 namespace amg {
 
 // ------------------------------------------------------------------ indexing
@@ -315,6 +317,37 @@ __device__ __forceinline__ void store_node(T* __restrict__ p, const T (&o)[S]) {
         v.y = o[2 * c + 1];
         q[c] = v;
     }
+}
+
+// Store the node-major values o of the wavefront's 64 consecutive nodes
+// (lane l: node l of the range starting at dst; lanes >= nact store nothing)
+// as whole-wavefront runs: the values pass through the wavefront's LDS slice
+// buf (64 S values), then store q writes bytes [q * 64 PB, (q + 1) * 64 PB) of
+// the range, PB bytes per lane, instead of each lane writing its own node's
+// bytes at a 64-node stride (three times the L2 write requests for 48-byte
+// nodes).  All 64 lanes must call it; dst must be PB-aligned.
+template <typename T, int S>
+__device__ __forceinline__ void store_nodes_wave(T* __restrict__ dst, int nact, T* buf, const T (&o)[S]) {
+    constexpr int NBYTES = S * (int)sizeof(T);
+    constexpr int PB = NBYTES % 16 == 0 ? 16 : 8;   // bytes per lane and store
+    constexpr int NP = NBYTES / PB;                 // stores per wavefront
+    using Piece = typename std::conditional<PB == 16, int4, int2>::type;
+    const int lane = threadIdx.x & 63;
+    store_node<T, S>(buf + lane * S, o);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const Piece* src = reinterpret_cast<const Piece*>(buf);
+    Piece* d = reinterpret_cast<Piece*>(dst);
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        const int pc = q * 64 + lane;
+        if (pc < nact * NP) d[pc] = src[pc];
+    }
+    // the slice is free again once every lane has read its pieces
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // ------------------------------------------------------- row-mapped fine loop
@@ -1350,6 +1383,10 @@ __global__ void __launch_bounds__(kBlock, (xp_blocks_per_cu<NB>())) k_update_xP(
     constexpr int S = even_up(NB);
     const int lb = xcd_block(gridDim.x);
     __shared__ double sab[NB + kMaxWin * NB * NB];
+    // per-wavefront staging of the FP64 block stores (FP32 nodes store
+    // directly: measured faster at 24 bytes per node)
+    constexpr bool kStage = sizeof(T) == 8;
+    __shared__ __align__(16) T pbuf[kWaves][kStage ? 64 * S : 2];
     if (!init) {
         for (int q = threadIdx.x; q < NB + m * NB * NB; q += kBlock) {
             if (q < NB) {
@@ -1395,14 +1432,15 @@ __global__ void __launch_bounds__(kBlock, (xp_blocks_per_cu<NB>())) k_update_xP(
         fine_z_wave_load<DIM, T, NB, NE>(Y, nc, cL, dl, idx, p, ix, zw);
         T z[NB];
         fine_z_wave_finish<DIM, T, NB, NE>(zw, nc, dzero, p, ix, z);
-        if (!act) continue;
+        // every lane computes (lanes past the row end on a clamped node) and,
+        // in FP64, takes part in the wavefront's store of the new block
         double v[NB];
 #pragma unroll
         for (int c = 0; c < NB; ++c) v[c] = double(z[c]);
         if (!init) {
 #pragma unroll
             for (int c = 0; c < NB; ++c) xi += double(pk[c]) * sab[c];
-            x[idx] = xi;
+            if (act) x[idx] = xi;
             const double* bc = sab + NB + cur * NB * NB;
 #pragma unroll
             for (int c = 0; c < NB; ++c)
@@ -1424,7 +1462,15 @@ __global__ void __launch_bounds__(kBlock, (xp_blocks_per_cu<NB>())) k_update_xP(
         for (int c = 0; c < NB; ++c) pn[c] = T(v[c]);
 #pragma unroll
         for (int c = NB; c < S; ++c) pn[c] = T(0);
-        store_node<T, S>(Pn + (size_t)idx * S, pn);
+        if constexpr (kStage) {
+            // lane 0 is always inside the row (row starts are multiples of
+            // 64 below n), so its node starts the wavefront's range
+            const int i0 = __builtin_amdgcn_readfirstlane(ix);
+            const int first = __builtin_amdgcn_readfirstlane(idx);
+            store_nodes_wave<T, S>(Pn + (size_t)first * S, min(64, R.n - i0), pbuf[threadIdx.x >> 6], pn);
+        } else if (act) {
+            store_node<T, S>(Pn + (size_t)idx * S, pn);
+        }
     }
 }
 
