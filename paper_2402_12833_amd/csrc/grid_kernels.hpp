@@ -848,28 +848,50 @@ template <int DIM, typename T, typename G>
 __device__ __forceinline__ T fine_smooth_at(const FineOp<T>& op, const G* __restrict__ g, int idx, const Idx<DIM>& p,
                                             T omega, int two_sweeps) {
     const int n = op.n, sy = n, sz = n * n;
+    if (!two_sweeps || (DIM == 2 && op.k9)) {
+        const T gi = T(g[idx]);
+        const T iDi = fine_invdiag<DIM>(op, idx);
+        const T c1 = omega * (gi * iDi);
+        if (!two_sweeps) return c1;
+        // A c1 with c1_j = omega g_j / D_j formed on the fly
+        auto c1at = [&](int j) -> T { return omega * (T(g[j]) * fine_invdiag<DIM>(op, j)); };
+        const T Ac = stencil9_apply<T, T>(op, p.i, p.j, idx, c1at);
+        return c1 + omega * ((gi - Ac) * iDi);
+    }
+    // face stencil, two sweeps: every load first (g at the node and its face
+    // neighbours at clamped indices, then 1/D and the coefficients when they
+    // vary; the branches on them are uniform), then the arithmetic
+    const FaceNbrs<DIM> f(p, n, idx);
     const T gi = T(g[idx]);
-    const T iDi = fine_invdiag<DIM>(op, idx);
+    T gq[2 * DIM], iq[2 * DIM], fq[2 * DIM];
+#pragma unroll
+    for (int q = 0; q < 2 * DIM; ++q) gq[q] = T(g[f.j[q]]);
+    T iDi = op.inv0, Dd = T(0);
+#pragma unroll
+    for (int q = 0; q < 2 * DIM; ++q) iq[q] = op.inv0;
+    if (op.iD) {
+        iDi = op.iD[idx];
+#pragma unroll
+        for (int q = 0; q < 2 * DIM; ++q) iq[q] = op.iD[f.j[q]];
+    }
+    if (op.D) {
+        Dd = op.D[idx];
+#pragma unroll
+        for (int q = 0; q < 2 * DIM; ++q) fq[q] = f.face(op, q);
+    }
+    // A c1 with c1_j = omega g_j / D_j
     const T c1 = omega * (gi * iDi);
-    if (!two_sweeps) return c1;
-    // A c1 with c1_j = omega g_j / D_j formed on the fly
-    auto c1at = [&](int j) -> T { return omega * (T(g[j]) * fine_invdiag<DIM>(op, j)); };
     T Ac;
-    if (DIM == 2 && op.k9) {
-        Ac = stencil9_apply<T, T>(op, p.i, p.j, idx, c1at);
+    if (!op.D) {
+        T acc = T(2 * DIM) * c1;
+#pragma unroll
+        for (int q = 0; q < 2 * DIM; ++q) acc -= (f.ok[q] ? T(1) : T(0)) * (omega * (gq[q] * iq[q]));
+        Ac = op.s0 * acc;
     } else {
-        const FaceNbrs<DIM> f(p, n, idx);
-        if (!op.D) {
-            T acc = T(2 * DIM) * c1;
+        T acc = Dd * c1;
 #pragma unroll
-            for (int q = 0; q < 2 * DIM; ++q) acc -= (f.ok[q] ? T(1) : T(0)) * c1at(f.j[q]);
-            Ac = op.s0 * acc;
-        } else {
-            T acc = op.D[idx] * c1;
-#pragma unroll
-            for (int q = 0; q < 2 * DIM; ++q) acc -= (f.ok[q] ? f.face(op, q) : T(0)) * c1at(f.j[q]);
-            Ac = acc;
-        }
+        for (int q = 0; q < 2 * DIM; ++q) acc -= (f.ok[q] ? fq[q] : T(0)) * (omega * (gq[q] * iq[q]));
+        Ac = acc;
     }
     return c1 + omega * ((gi - Ac) * iDi);
 }
