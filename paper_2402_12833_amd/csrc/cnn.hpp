@@ -45,21 +45,42 @@ constexpr int kCB = 256;   // threads per block of the CNN kernels (4 wavefronts
 
 typedef short bf16x8 __attribute__((ext_vector_type(8)));
 
-// LDS-tiled convolution.  A block computes a 16 (x) x 4 (y) x 4 (z) tile of
-// output voxels, one z plane per wavefront and four 16-voxel rows (M tiles)
-// per wavefront, for COUT / CSPLIT output channels (blockIdx.z also selects
-// the channel slice).  The input tile with its one-voxel halo is staged in
-// LDS once per chunk of CC input channels.  K (taps x channels) is walked
-// with v_mfma_f32_16x16x32_bf16: a step fixes, per lane group kq, one
-// (dz, dx) offset and 8 channels (CC = 32: one offset, channels 8 kq..;
-// CC = 16: two offsets, lane groups 0-1 and 2-3), reads the A fragments of
-// the six input rows once and uses row y0 + i + dy for output row i and tap
-// dy, so each fragment serves three taps.  A (input) and B (weights) use the
-// same K assignment, so the sum does not depend on the hardware's K order.
-// Input channels c < C1 come from Xc, a grid of S/2 read at (z/2, y/2, x/2)
-// (nearest upsampling), the rest from X (CIN - C1 channels): the skip
-// concatenation is read in place.  OUT_F32: FP32 output of channel 0 only,
-// one value per voxel (the network output layer).
+// LDS-tiled convolution.  A block computes a 16 (x) x TY (y) x 4 (z) tile of
+// output voxels, one z plane per wavefront and TY 16-voxel rows per
+// wavefront, for COUT / CSPLIT output channels (blockIdx.z also selects the
+// channel slice).  The input tile with its one-voxel halo is staged in LDS
+// once per chunk of CC input channels, row by row: each thread keeps one
+// (x, 8-channel piece) column of the tile rows and walks the rows, so the
+// index arithmetic per 16-byte piece is a few adds.  K (taps x channels) is
+// walked with v_mfma_f32_16x16x32_bf16 with the weights as the M operand
+// (16 output channels) and the input as the N operand (16 voxels along x): a
+// step fixes, per lane group kq, one (dz, dx) offset and 8 channels (CC = 32:
+// one offset, channels 8 kq..; CC = 16: two offsets, lane groups 0-1 and
+// 2-3), reads the fragments of the TY + 2 input rows once and uses row
+// y0 + i + dy for output row i and tap dy, so each fragment serves three
+// taps.  Both operands use the same K assignment, so the sum does not depend
+// on the hardware's K order.  Each lane then holds 4 consecutive output
+// channels of one voxel: the epilogue converts them pairwise to bfloat16
+// (round to nearest even) and writes 8 bytes per lane.  Input channels
+// c < C1 come from Xc, a grid of S/2 read at (z/2, y/2, x/2) (nearest
+// upsampling), the rest from X (CIN - C1 channels): the skip concatenation
+// is read in place.  OUT_F32: FP32 output of channel 0 only, one value per
+// voxel (the network output layer).
+// Output rows (y) per wavefront.  4: with 8 (fewer fragment reads per MFMA)
+// the LDS tile of a 16-channel chunk grows to 52 KB, three blocks per CU
+// instead of five, and the layers ran slower (52 -> 57 us at 128^3).
+template <int CIN>
+__host__ __device__ constexpr int conv_ty() { return 4; }
+
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef short i16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ unsigned pack_bf16x2(float lo, float hi) {
+    const bf16x2_t v = __builtin_convertvector(f32x2_t{lo, hi}, bf16x2_t);
+    return __builtin_bit_cast(unsigned, v);
+}
+
 template <int CIN, int C1, int COUT, int KS, int RELU, int OUT_F32, int CSPLIT>
 __global__ void __launch_bounds__(kCB) k_conv_lds(const Ctl* __restrict__ ctl, const bf16* __restrict__ Xc,
                                                   const bf16* __restrict__ X, const bf16* __restrict__ W,
@@ -70,7 +91,8 @@ __global__ void __launch_bounds__(kCB) k_conv_lds(const Ctl* __restrict__ ctl, c
     constexpr int CC = (CIN % 32 == 0) ? 32 : 16;      // channels per LDS stage
     constexpr int NCH = CIN / CC;
     constexpr int H = KS == 3 ? 1 : 0;
-    constexpr int LX = 16 + 2 * H, LY = 4 + 2 * H, LZ = 4 + 2 * H;
+    constexpr int TY = conv_ty<CIN>();
+    constexpr int LX = 16 + 2 * H, LY = TY + 2 * H, LZ = 4 + 2 * H;
     constexpr int NV = LX * LY * LZ;
     constexpr int VS = CC + 8;                         // padded voxel stride (elements)
     constexpr int NT = COUT / 16 / CSPLIT;
@@ -78,94 +100,144 @@ __global__ void __launch_bounds__(kCB) k_conv_lds(const Ctl* __restrict__ ctl, c
     constexpr int NSTEP = CC == 32 ? NCOMBO : (NCOMBO + 1) / 2;
     constexpr int NDY = KS == 3 ? 3 : 1;
     constexpr int PIECES = CC / 8;                     // 16-byte pieces per voxel and stage
+    constexpr int PR = LX * PIECES;                    // pieces per tile row
+    constexpr int NR = LY * LZ;                        // tile rows
+    constexpr int RPP = kCB / PR;                      // tile rows per staging pass
     __shared__ __attribute__((aligned(16))) bf16 tile[NV * VS];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int m = lane & 15, kq = lane >> 4;
     const int ztiles = (S + 3) >> 2;
     const int zt = blockIdx.z % ztiles, cs = blockIdx.z / ztiles;
-    const int x0 = blockIdx.x * 16, y0 = blockIdx.y * 4, z0 = zt * 4;
+    const int x0 = blockIdx.x * 16, y0 = blockIdx.y * TY, z0 = zt * 4;
     const int co0 = cs * NT * 16;
     const int Sc = S >> 1;
-    f32x4 acc[4][NT];
+    // this thread's staging column: x = slx of the tile, 8 channels from sq * 8
+    const int srow = threadIdx.x / PR, scol = threadIdx.x - srow * PR;
+    const int slx = scol / PIECES, sq = scol % PIECES;
+    const int gx = x0 - H + slx;
+    const bool xin = srow < RPP && gx >= 0 && gx < S;
+    // per-lane parts of the fragment addresses: lane group kq reads channels
+    // cl.. (lane half hb: the second offset of a CC = 16 step); tl: this
+    // lane's input for output row 0 at offset 0
+    const int cl = CC == 32 ? 8 * kq : 8 * (kq & 1);
+    const bool hb = CC == 16 && (kq >> 1) != 0;
+    const bf16* const tl = tile + (((w + H) * LY) * LX + (m + H)) * VS + cl;
+    const unsigned wbase = (unsigned)((co0 + m) * CIN + cl);
+    const char* const Wb = reinterpret_cast<const char*>(W);
+    f32x4 acc[TY][NT];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < TY; ++i)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) acc[i][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int ch = 0; ch < NCH; ++ch) {
-        for (int p = threadIdx.x; p < NV * PIECES; p += kCB) {
-            const int v = p / PIECES, q = p - v * PIECES;
-            const int lx = v % LX, ly = (v / LX) % LY, lz = v / (LX * LY);
-            const int gx = x0 - H + lx, gy = y0 - H + ly, gz = z0 - H + lz;
-            int4 val = int4{0, 0, 0, 0};
-            if (gx >= 0 && gx < S && gy >= 0 && gy < S && gz >= 0 && gz < S) {
-                const int c = ch * CC + q * 8;
-                if (c < C1)
-                    val = *reinterpret_cast<const int4*>(
-                        Xc + ((size_t)((gz >> 1) * Sc + (gy >> 1)) * Sc + (gx >> 1)) * C1 + c);
-                else
-                    val = *reinterpret_cast<const int4*>(X + ((size_t)(gz * S + gy) * S + gx) * C2 + (c - C1));
+        const int c = ch * CC + sq * 8;
+        if (srow < RPP) {
+            for (int r = srow; r < NR; r += RPP) {
+                const int ly = r % LY, lz = r / LY;
+                const int gy = y0 - H + ly, gz = z0 - H + lz;
+                int4 val = int4{0, 0, 0, 0};
+                if (xin && gy >= 0 && gy < S && gz >= 0 && gz < S) {
+                    // 32-bit byte offsets from the (uniform) array bases
+                    if (c < C1)
+                        val = *reinterpret_cast<const int4*>(
+                            reinterpret_cast<const char*>(Xc) +
+                            2u * (unsigned)((((gz >> 1) * Sc + (gy >> 1)) * Sc + (gx >> 1)) * C1 + c));
+                    else
+                        val = *reinterpret_cast<const int4*>(reinterpret_cast<const char*>(X) +
+                                                             2u * (unsigned)(((gz * S + gy) * S + gx) * C2 + (c - C1)));
+                }
+                *reinterpret_cast<int4*>(tile + (r * LX + slx) * VS + sq * 8) = val;
             }
-            *reinterpret_cast<int4*>(tile + v * VS + q * 8) = val;
         }
         __syncthreads();
-#pragma unroll
-        for (int st = 0; st < NSTEP; ++st) {
-            const int combo = CC == 32 ? st : 2 * st + (kq >> 1);
-            const int c = CC == 32 ? 8 * kq : 8 * (kq & 1);
-            const bool valid = combo < NCOMBO;
-            const int cb = valid ? combo : 0;
-            const int dz = KS == 3 ? cb / 3 - 1 : 0, dx = KS == 3 ? cb % 3 - 1 : 0;
-            bf16x8 a[4 + 2 * H];
-#pragma unroll
-            for (int r = 0; r < 4 + 2 * H; ++r) {
-                a[r] = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
-                if (valid)
-                    a[r] = *reinterpret_cast<const bf16x8*>(
-                        tile + (((w + dz + H) * LY + r) * LX + (m + dx + H)) * VS + c);
-            }
+        // step st's (dz, dx) offset: one for all lanes (CC = 32), or one per
+        // lane half (CC = 16; combo 9 of the last step is past the taps: its
+        // weights are zero, its input any valid row); the weights of step
+        // st + 1 are loaded during step st
+        auto combo_of = [&](int st, int& dz, int& dx, bool& none) {
+            const int cA = CC == 32 ? st : 2 * st, cB = CC == 32 ? st : 2 * st + 1;
+            const int c = hb ? cB : cA;
+            none = c >= NCOMBO;
+            const int cv = none ? 0 : c;
+            dz = KS == 3 ? cv / 3 - 1 : 0;
+            dx = KS == 3 ? cv % 3 - 1 : 0;
+        };
+        auto load_w = [&](int st, bf16x8 (&b)[NDY][NT]) {
+            int dz, dx;
+            bool none;
+            combo_of(st, dz, dx, none);
 #pragma unroll
             for (int dyi = 0; dyi < NDY; ++dyi) {
                 const int dy = KS == 3 ? dyi - 1 : 0;
                 const int tap = KS == 3 ? (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1) : 0;
-                bf16x8 b[NT];
+                const unsigned woff = wbase + (unsigned)(tap * COUT * CIN + ch * CC);
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) {
-                    b[nt] = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
-                    if (valid)
-                        b[nt] = *reinterpret_cast<const bf16x8*>(
-                            W + ((size_t)(tap * COUT + co0 + nt * 16 + m) * CIN + ch * CC + c));
+                    b[dyi][nt] = *reinterpret_cast<const bf16x8*>(Wb + 2u * (woff + (unsigned)(nt * 16 * CIN)));
+                    if (none) b[dyi][nt] = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
                 }
+            }
+        };
+        bf16x8 bw[2][NDY][NT];
+        load_w(0, bw[0]);
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
+        for (int st = 0; st < NSTEP; ++st) {
+            int dz, dx;
+            bool none;
+            combo_of(st, dz, dx, none);
+            const int voff = dz * LY * LX + dx;
+            bf16x8 a[TY + 2 * H];
+#pragma unroll
+            for (int r = 0; r < TY + 2 * H; ++r)
+                a[r] = *reinterpret_cast<const bf16x8*>(tl + (voff + r * LX) * VS);
+            if (st + 1 < NSTEP) load_w(st + 1, bw[(st + 1) & 1]);
+            // keep those loads here: the scheduler would otherwise sink them
+            // next to their first use and wait for them there
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int dyi = 0; dyi < NDY; ++dyi) {
+                const int dy = KS == 3 ? dyi - 1 : 0;
+#pragma unroll
+                for (int i = 0; i < TY; ++i)
 #pragma unroll
                     for (int nt = 0; nt < NT; ++nt)
-                        acc[i][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i + dy + H], b[nt], acc[i][nt], 0,
-                                                                             0, 0);
+                        acc[i][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[st & 1][dyi][nt], a[i + dy + H],
+                                                                             acc[i][nt], 0, 0, 0);
             }
         }
         __syncthreads();
     }
-    const int z = z0 + w;
-    if (z >= S) return;
+    // lane (m, kq): voxel x0 + m, channels co0 + nt * 16 + 4 kq .. + 3
+    const int z = z0 + w, x = x0 + m;
+    if (z >= S || x >= S) return;
+    char* const Yb = static_cast<char*>(Yv);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < TY; ++i) {
         const int y = y0 + i;
-        if (y >= S) continue;
+        if (y >= S) break;
+        const unsigned vox = (unsigned)((z * S + y) * S + x);
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int x = x0 + kq * 4 + j;
-                if (x >= S) continue;
-                float v = acc[i][nt][j];
+        for (int nt = 0; nt < NT; ++nt) {
+            const int co = co0 + nt * 16 + 4 * kq;
+            if (OUT_F32) {
+                float v = acc[i][nt][0];
                 if (RELU) v = v > 0.f ? v : 0.f;
-                const size_t vox = (size_t)(z * S + y) * S + x;
-                if (OUT_F32) {
-                    if (co0 + nt * 16 + m == 0) static_cast<float*>(Yv)[vox] = v;
-                } else {
-                    static_cast<bf16*>(Yv)[vox * COUT + co0 + nt * 16 + m] = f2bf(v);
+                if (co == 0) *reinterpret_cast<float*>(Yb + 4u * vox) = v;
+            } else {
+                // ReLU on the bfloat16 pairs as signed 16-bit integers: a
+                // negative value (sign bit set) is below 0 and becomes +0
+                i16x2 p0 = __builtin_bit_cast(i16x2, pack_bf16x2(acc[i][nt][0], acc[i][nt][1]));
+                i16x2 p1 = __builtin_bit_cast(i16x2, pack_bf16x2(acc[i][nt][2], acc[i][nt][3]));
+                if (RELU) {
+                    p0 = __builtin_elementwise_max(p0, i16x2{0, 0});
+                    p1 = __builtin_elementwise_max(p1, i16x2{0, 0});
                 }
+                uint2 pk;
+                pk.x = __builtin_bit_cast(unsigned, p0);
+                pk.y = __builtin_bit_cast(unsigned, p1);
+                *reinterpret_cast<uint2*>(Yb + 2u * (vox * COUT + (unsigned)co)) = pk;
             }
+        }
     }
 }
 

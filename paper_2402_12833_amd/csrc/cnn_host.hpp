@@ -348,8 +348,8 @@ class Net {
         }
     }
 
-    static dim3 conv_grid(int Sg, int split) {
-        return dim3((Sg + 15) / 16, (Sg + 3) / 4, ((Sg + 3) / 4) * split);
+    static dim3 conv_grid(int Sg, int split, int ty) {
+        return dim3((Sg + 15) / 16, (Sg + ty - 1) / ty, ((Sg + 3) / 4) * split);
     }
 
     // Small grids (fewer than kConvFill tiles) split the output channels
@@ -358,20 +358,20 @@ class Net {
     template <int CIN, int C1, int COUT, int KS, int RELU, int F32>
     static void conv_launch(const Ctl* ctl, const bf16* Xc, const bf16* X, const bf16* Wl, void* Y, int Sg,
                             hipStream_t s) {
-        const int tiles = ((Sg + 15) / 16) * ((Sg + 3) / 4) * ((Sg + 3) / 4);
+        const int tiles = ((Sg + 15) / 16) * ((Sg + conv_ty<CIN>() - 1) / conv_ty<CIN>()) * ((Sg + 3) / 4);
         if constexpr (!F32 && COUT % 64 == 0) {
             if (tiles < kConvFill) {
-                k_conv_lds<CIN, C1, COUT, KS, RELU, F32, 4><<<conv_grid(Sg, 4), kCB, 0, s>>>(ctl, Xc, X, Wl, Y, Sg);
+                k_conv_lds<CIN, C1, COUT, KS, RELU, F32, 4><<<conv_grid(Sg, 4, conv_ty<CIN>()), kCB, 0, s>>>(ctl, Xc, X, Wl, Y, Sg);
                 return;
             }
         }
         if constexpr (!F32 && COUT % 32 == 0) {
             if (tiles < kConvFill) {
-                k_conv_lds<CIN, C1, COUT, KS, RELU, F32, 2><<<conv_grid(Sg, 2), kCB, 0, s>>>(ctl, Xc, X, Wl, Y, Sg);
+                k_conv_lds<CIN, C1, COUT, KS, RELU, F32, 2><<<conv_grid(Sg, 2, conv_ty<CIN>()), kCB, 0, s>>>(ctl, Xc, X, Wl, Y, Sg);
                 return;
             }
         }
-        k_conv_lds<CIN, C1, COUT, KS, RELU, F32, 1><<<conv_grid(Sg, 1), kCB, 0, s>>>(ctl, Xc, X, Wl, Y, Sg);
+        k_conv_lds<CIN, C1, COUT, KS, RELU, F32, 1><<<conv_grid(Sg, 1, conv_ty<CIN>()), kCB, 0, s>>>(ctl, Xc, X, Wl, Y, Sg);
     }
 
     template <int CIN, int COUT, int KS, int RELU, int F32>
