@@ -241,6 +241,77 @@ __global__ void __launch_bounds__(kCB) k_conv_lds(const Ctl* __restrict__ ctl, c
     }
 }
 
+// The network's first layer (3x3x3, 16 outputs, ReLU) on its input, whose
+// channels 2..15 are zero: K = 27 taps x 2 channels (54, padded to 64 = two
+// v_mfma_f32_16x16x32_bf16 steps instead of 14 over the zero channels).  X2:
+// channels 0 and 1 of each voxel as one 32-bit word; W: the layer's weights
+// [tap][16][16] of which channels 0 and 1 are read.  K slot k of a step:
+// tap 16 st + k / 2, channel k % 2; lane group kq holds slots 8 kq .. 8 kq + 7
+// (taps 16 st + 4 kq + j, j = 0..3) for both operands, so the sum does not
+// depend on the hardware's K order.  Tile, wavefront rows and epilogue as in
+// k_conv_lds.
+static __global__ void __launch_bounds__(kCB) k_conv_in2(const Ctl* __restrict__ ctl, const unsigned* __restrict__ X2,
+                                                  const bf16* __restrict__ W, bf16* __restrict__ Y, int S) {
+    if (ctl && ctl->state != 0) return;
+    constexpr int LX = 18, LY = 6, LZ = 6, NV = LX * LY * LZ;
+    __shared__ unsigned tile[NV];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int m = lane & 15, kq = lane >> 4;
+    const int x0 = blockIdx.x * 16, y0 = blockIdx.y * 4, z0 = blockIdx.z * 4;
+    for (int v = threadIdx.x; v < NV; v += kCB) {
+        const int lx = v % LX, ly = (v / LX) % LY, lz = v / (LX * LY);
+        const int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z0 - 1 + lz;
+        unsigned val = 0u;
+        if (gx >= 0 && gx < S && gy >= 0 && gy < S && gz >= 0 && gz < S) val = X2[(gz * S + gy) * S + gx];
+        tile[v] = val;
+    }
+    // this lane's 4 taps per step: weights (channels 0, 1) and tile offsets
+    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+    u32x4 bw[2];
+    int toff[2][4];
+#pragma unroll
+    for (int st = 0; st < 2; ++st)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int t = 16 * st + 4 * kq + j;
+            const int tv = t < 27 ? t : 0;
+            toff[st][j] = (tap_dz(tv) + 1) * LY * LX + (tap_dy(tv) + 1) * LX + (tap_dx(tv) + 1);
+            bw[st][j] = t < 27 ? *reinterpret_cast<const unsigned*>(W + (size_t)(t * 16 + m) * 16) : 0u;
+        }
+    __syncthreads();
+    f32x4 acc[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const unsigned* tl = tile + (w * LY) * LX + m;   // output row 0 of this wavefront at tap (-1, -1, -1)
+#pragma unroll
+    for (int st = 0; st < 2; ++st)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            u32x4 a;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) a[j] = tl[toff[st][j] + i * LX];
+            acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, bw[st]),
+                                                            __builtin_bit_cast(bf16x8, a), acc[i], 0, 0, 0);
+        }
+    const int z = z0 + w, x = x0 + m;
+    if (z >= S || x >= S) return;
+    char* const Yb = reinterpret_cast<char*>(Y);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int y = y0 + i;
+        if (y >= S) break;
+        const unsigned vox = (unsigned)((z * S + y) * S + x);
+        i16x2 p0 = __builtin_bit_cast(i16x2, pack_bf16x2(acc[i][0], acc[i][1]));
+        i16x2 p1 = __builtin_bit_cast(i16x2, pack_bf16x2(acc[i][2], acc[i][3]));
+        p0 = __builtin_elementwise_max(p0, i16x2{0, 0});
+        p1 = __builtin_elementwise_max(p1, i16x2{0, 0});
+        uint2 pk;
+        pk.x = __builtin_bit_cast(unsigned, p0);
+        pk.y = __builtin_bit_cast(unsigned, p1);
+        *reinterpret_cast<uint2*>(Yb + 2u * (vox * 16u + 4u * kq)) = pk;
+    }
+}
+
 // dW[t, co, ci] += sum over voxels of dY[v, co] X[v + o_t, ci]; block = one
 // tap and a range of 16-voxel x-tiles; lane l supplies A[m = co][k = voxel
 // 4(l/16)+j] and B[k][n = ci]; each wavefront adds its sums with FP32 atomics.
@@ -307,7 +378,7 @@ __global__ void __launch_bounds__(kCB) k_conv_wgrad(const Ctl* __restrict__ ctl,
 // normalised log kappa (or 0), channels 2..15 = 0; voxels outside n^3 = 0.
 static __global__ void __launch_bounds__(kCB) k_pack_input(const Ctl* __restrict__ ctl, const double* __restrict__ r,
                                                     const double* __restrict__ scale, const bf16* __restrict__ lk,
-                                                    bf16* __restrict__ X, int n, int S) {
+                                                    bf16* __restrict__ X, unsigned* __restrict__ X2, int n, int S) {
     if (ctl && ctl->state != 0) return;
     const int v = blockIdx.x * kCB + threadIdx.x;
     if (v >= S * S * S) return;
@@ -315,11 +386,17 @@ static __global__ void __launch_bounds__(kCB) k_pack_input(const Ctl* __restrict
     const bool in = x < n && y < n && z < n;
     const int idx = x + n * (y + n * z);
     const float s = (float)(*scale);
-    bf16* o = X + (size_t)v * 16;
-    o[0] = in ? f2bf((float)r[idx] * s) : (bf16)0;
-    o[1] = (in && lk) ? lk[idx] : (bf16)0;
-#pragma unroll
-    for (int c = 2; c < 16; ++c) o[c] = 0;
+    const bf16 c0 = in ? f2bf((float)r[idx] * s) : (bf16)0;
+    const bf16 c1 = (in && lk) ? lk[idx] : (bf16)0;
+    const unsigned c01 = (unsigned)c0 | ((unsigned)c1 << 16);
+    // X2: the two channels that can be non-zero, one 32-bit word per voxel;
+    // X (if given): all 16 channels (32 bytes) in two 16-byte stores
+    X2[v] = c01;
+    if (X) {
+        uint4* o = reinterpret_cast<uint4*>(X + (size_t)v * 16);
+        o[0] = make_uint4(c01, 0u, 0u, 0u);
+        o[1] = make_uint4(0u, 0u, 0u, 0u);
+    }
 }
 
 // Sum of squares of v (N values): per-block partials part[b], fixed order.
@@ -350,21 +427,37 @@ static __global__ void __launch_bounds__(kRedBlock) k_finish_sum(const Ctl* __re
 }
 
 // 2x2x2 average pooling, S -> S/2 (C channels).
+// One thread per coarse voxel and 8 channels (16-byte loads and store); the
+// 8 children are summed in (z, y, x) order.  C must be a multiple of 8.
 static __global__ void __launch_bounds__(kCB) k_avgpool(const Ctl* __restrict__ ctl, const bf16* __restrict__ X,
                                                  bf16* __restrict__ Y, int Sc, int C) {
     if (ctl && ctl->state != 0) return;
+    const int G = C / 8;
     const size_t e = (size_t)blockIdx.x * kCB + threadIdx.x;
-    if (e >= (size_t)Sc * Sc * Sc * C) return;
-    const int c = e % C;
-    const size_t v = e / C;
+    if (e >= (size_t)Sc * Sc * Sc * G) return;
+    const int g = e % G;
+    const size_t v = e / G;
     const int x = v % Sc, y = (v / Sc) % Sc, z = v / ((size_t)Sc * Sc);
     const int Sf = 2 * Sc;
-    float s = 0.f;
+    float s[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s[k] = 0.f;
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b)
-            for (int d = 0; d < 2; ++d)
-                s += bf2f(X[(((size_t)(2 * z + a) * Sf + 2 * y + b) * Sf + 2 * x + d) * C + c]);
-    Y[e] = f2bf(s * 0.125f);
+            for (int d = 0; d < 2; ++d) {
+                const uint4 q = *reinterpret_cast<const uint4*>(
+                    X + (((size_t)(2 * z + a) * Sf + 2 * y + b) * Sf + 2 * x + d) * C + 8 * g);
+                const unsigned u[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    s[2 * k] += bf2f((bf16)(u[k] & 0xffffu));
+                    s[2 * k + 1] += bf2f((bf16)(u[k] >> 16));
+                }
+            }
+    unsigned o[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) o[k] = (unsigned)f2bf(s[2 * k] * 0.125f) | ((unsigned)f2bf(s[2 * k + 1] * 0.125f) << 16);
+    *reinterpret_cast<uint4*>(Y + v * C + 8 * g) = make_uint4(o[0], o[1], o[2], o[3]);
 }
 
 // Y (S^3, C1 + C2 channels) = [upsample2(A) (C1 channels, grid S/2) | B (C2)].

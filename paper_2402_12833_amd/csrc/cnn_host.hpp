@@ -57,6 +57,7 @@ class Net {
         hipError_t err = hipSuccess;
         const size_t V0 = (size_t)S * S * S, V1 = V0 / 8, V2 = V1 / 8;
         x0.alloc(V0 * 16, err);
+        x0c.alloc(V0, err);
         e1.alloc(V0 * 16, err);
         e2.alloc(V0 * 16, err);
         p1.alloc(V1 * 16, err);
@@ -167,13 +168,17 @@ class Net {
         const int S0 = S, S1 = S / 2, S2 = S / 4;
         k_sumsq<<<kSumBlocks, kCB, 0, s>>>(ctl, r, n * n * n, part.p);
         k_finish_sum<<<1, kRedBlock, 0, s>>>(ctl, part.p, kSumBlocks, n * n * n, 0, small.p);
-        k_pack_input<<<blocks((size_t)S0 * S0 * S0), kCB, 0, s>>>(ctl, r, small.p, lk, x0.p, n, S0);
-        conv<16, 16, 3, 1, 0>(ctl, x0.p, 0, e1.p, S0, s);
+        // the 16-channel input only for training (the weight gradient of
+        // the first layer reads it); the first layer reads channels 0 and 1
+        k_pack_input<<<blocks((size_t)S0 * S0 * S0), kCB, 0, s>>>(ctl, r, small.p, lk, train ? x0.p : nullptr,
+                                                                   x0c.p, n, S0);
+        k_conv_in2<<<dim3(S0 / 16 + (S0 % 16 != 0), S0 / 4, S0 / 4), kCB, 0, s>>>(ctl, x0c.p, wb.p + woff(0), e1.p,
+                                                                                 S0);
         conv<16, 16, 3, 1, 0>(ctl, e1.p, 1, e2.p, S0, s);
-        k_avgpool<<<blocks((size_t)S1 * S1 * S1 * 16), kCB, 0, s>>>(ctl, e2.p, p1.p, S1, 16);
+        k_avgpool<<<blocks((size_t)S1 * S1 * S1 * 2), kCB, 0, s>>>(ctl, e2.p, p1.p, S1, 16);
         conv<16, 32, 3, 1, 0>(ctl, p1.p, 2, e3.p, S1, s);
         conv<32, 32, 3, 1, 0>(ctl, e3.p, 3, e4.p, S1, s);
-        k_avgpool<<<blocks((size_t)S2 * S2 * S2 * 32), kCB, 0, s>>>(ctl, e4.p, p2.p, S2, 32);
+        k_avgpool<<<blocks((size_t)S2 * S2 * S2 * 4), kCB, 0, s>>>(ctl, e4.p, p2.p, S2, 32);
         conv<32, 64, 3, 1, 0>(ctl, p2.p, 4, b1.p, S2, s);
         conv<64, 64, 3, 1, 0>(ctl, b1.p, 5, b2.p, S2, s);
         if (train) k_upcat<<<blocks((size_t)S1 * S1 * S1 * 96), kCB, 0, s>>>(ctl, b2.p, e4.p, c1.p, S1, 64, 32);
@@ -301,6 +306,7 @@ class Net {
     }
 
     Buf<bf16> x0, e1, e2, p1, e3, e4, p2, b1, b2, c1, d1, d2, c2, d3, d4;
+    Buf<unsigned> x0c;   // input channels 0 and 1, one word per voxel
     Buf<float> out;
     Buf<bf16> g0a, g0b, g0c, g1a, g1b, g1c, g2a, g2b, g2c;
     Buf<double> small, part, dvec, qvec, rvec, q2vec;
