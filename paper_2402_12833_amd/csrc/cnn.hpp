@@ -64,8 +64,12 @@ typedef short bf16x8 __attribute__((ext_vector_type(8)));
 // (round to nearest even) and writes 8 bytes per lane.  Input channels
 // c < C1 come from Xc, a grid of S/2 read at (z/2, y/2, x/2) (nearest
 // upsampling), the rest from X (CIN - C1 channels): the skip concatenation
-// is read in place.  OUT_F32: FP32 output of channel 0 only, one value per
-// voxel (the network output layer).
+// is read in place.  OUT_F32 = 1: FP32 output of channel 0 only, one value per
+// voxel (the network output layer).  OUT_F32 = 2 (16 output channels in one
+// block): the network's last two layers at once, the ReLU output rounded to
+// bfloat16 as if stored, then the 1x1 output layer W2 (channel 0 of its
+// [16][16] weights) summed over the 16 channels in FP32 (per lane its 4
+// channels, then the 4 lane groups), one FP32 value per voxel.
 // Output rows (y) per wavefront.  4: with 8 (fewer fragment reads per MFMA)
 // the LDS tile of a 16-channel chunk grows to 52 KB, three blocks per CU
 // instead of five, and the layers ran slower (52 -> 57 us at 128^3).
@@ -84,9 +88,10 @@ __device__ __forceinline__ unsigned pack_bf16x2(float lo, float hi) {
 template <int CIN, int C1, int COUT, int KS, int RELU, int OUT_F32, int CSPLIT>
 __global__ void __launch_bounds__(kCB) k_conv_lds(const Ctl* __restrict__ ctl, const bf16* __restrict__ Xc,
                                                   const bf16* __restrict__ X, const bf16* __restrict__ W,
-                                                  void* __restrict__ Yv, int S) {
+                                                  void* __restrict__ Yv, int S, const bf16* __restrict__ W2) {
     if (ctl && ctl->state != 0) return;
     static_assert(CIN % 16 == 0 && COUT % (16 * CSPLIT) == 0 && C1 % 16 == 0 && C1 < CIN, "channel layout");
+    static_assert(OUT_F32 != 2 || COUT / CSPLIT == 16, "the fused output layer needs all 16 channels in one block");
     constexpr int C2 = CIN - C1;
     constexpr int CC = (CIN % 32 == 0) ? 32 : 16;      // channels per LDS stage
     constexpr int NCH = CIN / CC;
@@ -219,7 +224,18 @@ __global__ void __launch_bounds__(kCB) k_conv_lds(const Ctl* __restrict__ ctl, c
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
             const int co = co0 + nt * 16 + 4 * kq;
-            if (OUT_F32) {
+            if (OUT_F32 == 2) {
+                float part = 0.f;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    float v = bf2f(f2bf(acc[i][nt][j]));
+                    if (RELU) v = v > 0.f ? v : 0.f;
+                    part += v * bf2f(W2[co + j]);
+                }
+                part += __shfl_xor(part, 16);
+                part += __shfl_xor(part, 32);
+                if (kq == 0) *reinterpret_cast<float*>(Yb + 4u * vox) = part;
+            } else if (OUT_F32) {
                 float v = acc[i][nt][0];
                 if (RELU) v = v > 0.f ? v : 0.f;
                 if (co == 0) *reinterpret_cast<float*>(Yb + 4u * vox) = v;

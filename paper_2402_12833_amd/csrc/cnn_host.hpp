@@ -186,8 +186,14 @@ class Net {
         conv<32, 32, 3, 1, 0>(ctl, d1.p, 7, d2.p, S1, s);
         if (train) k_upcat<<<blocks((size_t)S0 * S0 * S0 * 48), kCB, 0, s>>>(ctl, d2.p, e2.p, c2.p, S0, 32, 16);
         conv_cat<48, 32, 16>(ctl, d2.p, e2.p, 8, d3.p, S0, s);
-        conv<16, 16, 3, 1, 0>(ctl, d3.p, 9, d4.p, S0, s);
-        conv<16, 16, 1, 0, 1>(ctl, d4.p, 10, out.p, S0, s);
+        if (train) {
+            conv<16, 16, 3, 1, 0>(ctl, d3.p, 9, d4.p, S0, s);
+            conv<16, 16, 1, 0, 1>(ctl, d4.p, 10, out.p, S0, s);
+        } else {
+            // inference: the last 3x3x3 layer and the 1x1 output layer in one
+            // pass (the 16-channel activation is not stored)
+            conv_launch<16, 0, 16, 3, 1, 2>(ctl, nullptr, d3.p, wb.p + woff(9), out.p, S0, s, wb.p + woff(10));
+        }
     }
 
     // Loss against e / rms(e) and all weight gradients into g (FP32).
@@ -363,21 +369,21 @@ class Net {
     static constexpr int kConvFill = 2048;
     template <int CIN, int C1, int COUT, int KS, int RELU, int F32>
     static void conv_launch(const Ctl* ctl, const bf16* Xc, const bf16* X, const bf16* Wl, void* Y, int Sg,
-                            hipStream_t s) {
+                            hipStream_t s, const bf16* W2 = nullptr) {
         const int tiles = ((Sg + 15) / 16) * ((Sg + conv_ty<CIN>() - 1) / conv_ty<CIN>()) * ((Sg + 3) / 4);
         if constexpr (!F32 && COUT % 64 == 0) {
             if (tiles < kConvFill) {
-                k_conv_lds<CIN, C1, COUT, KS, RELU, F32, 4><<<conv_grid(Sg, 4, conv_ty<CIN>()), kCB, 0, s>>>(ctl, Xc, X, Wl, Y, Sg);
+                k_conv_lds<CIN, C1, COUT, KS, RELU, F32, 4><<<conv_grid(Sg, 4, conv_ty<CIN>()), kCB, 0, s>>>(ctl, Xc, X, Wl, Y, Sg, W2);
                 return;
             }
         }
         if constexpr (!F32 && COUT % 32 == 0) {
             if (tiles < kConvFill) {
-                k_conv_lds<CIN, C1, COUT, KS, RELU, F32, 2><<<conv_grid(Sg, 2, conv_ty<CIN>()), kCB, 0, s>>>(ctl, Xc, X, Wl, Y, Sg);
+                k_conv_lds<CIN, C1, COUT, KS, RELU, F32, 2><<<conv_grid(Sg, 2, conv_ty<CIN>()), kCB, 0, s>>>(ctl, Xc, X, Wl, Y, Sg, W2);
                 return;
             }
         }
-        k_conv_lds<CIN, C1, COUT, KS, RELU, F32, 1><<<conv_grid(Sg, 1, conv_ty<CIN>()), kCB, 0, s>>>(ctl, Xc, X, Wl, Y, Sg);
+        k_conv_lds<CIN, C1, COUT, KS, RELU, F32, 1><<<conv_grid(Sg, 1, conv_ty<CIN>()), kCB, 0, s>>>(ctl, Xc, X, Wl, Y, Sg, W2);
     }
 
     template <int CIN, int COUT, int KS, int RELU, int F32>
