@@ -82,11 +82,27 @@ def traffic_model(dim, n, nlevels, bulk, var):
     return m, per_iter
 
 
-def unet_gflop(S):
-    """MFMA work of one U-Net forward on an S^3 grid (padded channel counts)."""
+def unet_gflop(S, padded=True):
+    """Work of one U-Net forward on an S^3 grid: with the padded channel
+    counts (w1 stored with 16 input channels of which 2 are real, w11 with 16
+    outputs of which 1 is used), or the network's own work (padded=False)."""
     from paper_2402_12833_amd import CNN_LAYERS
     level = {"w1": 0, "w2": 0, "w3": 1, "w4": 1, "w5": 2, "w6": 2, "w7": 1, "w8": 1, "w9": 0, "w10": 0, "w11": 0}
-    return sum(2.0 * (S >> level[name]) ** 3 * taps * cin * cout for name, taps, cin, cout in CNN_LAYERS) / 1e9
+    real = {} if padded else {"w1": (2, None), "w11": (None, 1)}
+    tot = 0.0
+    for name, taps, cin, cout in CNN_LAYERS:
+        ci, co = real.get(name, (None, None))
+        tot += 2.0 * (S >> level[name]) ** 3 * taps * (ci or cin) * (co or cout)
+    return tot / 1e9
+
+
+def unet_line(fms, S):
+    """The U-Net timing fields: work and rate against the BF16 dense peak,
+    on the padded and on the real channel counts."""
+    gp, gu = unet_gflop(S), unet_gflop(S, padded=False)
+    return {"ms": round(fms, 4), "gflop": round(gu, 1), "TFLOPs": round(gu / fms, 1),
+            "bf16_peak_frac": round(gu / fms / 2500.0, 4), "gflop_padded": round(gp, 1),
+            "bf16_peak_frac_padded": round(gp / fms / 2500.0, 4)}
 
 
 def kernel_source_hash():
@@ -340,9 +356,7 @@ def main(argv=None):
         T.load_weights(net)
         b = torch.as_tensor(W.problem_rhs(dprob), device="cuda")
         fms = net.time_forward(b, sol.log_kappa(), reps=max(args.steps, 1))
-        gf = unet_gflop((dprob.n + 3) // 4 * 4)
-        print(json.dumps({"workload": "unet_forward_128", "ms": round(fms, 4), "gflop_padded": round(gf, 1),
-                          "TFLOPs": round(gf / fms, 1), "bf16_peak_frac": round(gf / fms / 2500.0, 4)}), flush=True)
+        print(json.dumps({"workload": "unet_forward_128", **unet_line(fms, (dprob.n + 3) // 4 * 4)}), flush=True)
         net.close()
         sol.close()
         return 0
@@ -584,9 +598,7 @@ def main(argv=None):
             if prec == 0:
                 lk = s4.log_kappa()
                 fms = net.time_forward(b4, lk, reps=20)
-                gf = unet_gflop((dprob.n + 3) // 4 * 4)
-                var["unet_forward_128"] = {"ms": round(fms, 4), "gflop_padded": round(gf, 1),
-                                           "TFLOPs": round(gf / fms, 1), "bf16_peak_frac": round(gf / fms / 2500.0, 4)}
+                var["unet_forward_128"] = unet_line(fms, (dprob.n + 3) // 4 * 4)
             s4.close()
         net.close()
         out["variants"] = var

@@ -46,3 +46,13 @@ def test_x1_fields_and_host_description():
     assert bench.rel_err(x64, x64) == 0.0
     assert bench.host_threads() >= 1
     assert isinstance(bench.cpu_model(), str) and bench.cpu_model()
+
+
+def test_unet_work_counts():
+    """The U-Net's work at 128^3 on the padded channel counts and on the real
+    ones (w1: 2 of 16 input channels, w11: 1 of 16 outputs)."""
+    import bench
+    gp, gu = bench.unet_gflop(128), bench.unet_gflop(128, padded=False)
+    assert abs(gp - 265.6) < 0.05 and abs(gu - 239.2) < 0.05
+    line = bench.unet_line(0.5, 128)
+    assert line["gflop"] == round(gu, 1) and abs(line["bf16_peak_frac"] - gu / 0.5 / 2500.0) < 1e-4
