@@ -223,9 +223,20 @@ def run_batched(amg, torch, precision, steps, warmup, persistent=0):
         tms.append(bms)
     its = [i["iterations"] for i in binfos]
     assert all(i["status"] == amg.OK for i in binfos)
-    out = {"ms": round(float(np.mean(tms)), 4), "problems": len(table), "dofs": int(bsolv.N),
+    # algorithmic bytes of the whole batch: per problem its iterations of the
+    # per-iteration model (2D, its own side and levels) plus the initial and
+    # refresh residuals
+    bulk = 4 if precision == 1 else 8
+    nbytes = 0
+    for t, inf in zip(table, binfos):
+        m, per_iter = traffic_model(2, t.n, t.nlevels, bulk, False)
+        nbytes += inf["iterations"] * per_iter + (1 + inf.get("refreshes", 0)) * m["residual"]
+    ms = float(np.mean(tms))
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    out = {"ms": round(ms, 4), "problems": len(table), "dofs": int(bsolv.N),
            "iterations_min": int(min(its)), "iterations_max": int(max(its)),
-           "iterations_mean": round(float(np.mean(its)), 2)}
+           "iterations_mean": round(float(np.mean(its)), 2), "bytes_model": int(nbytes),
+           "hbm_GBps_algorithmic": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
     offs = bsolv.offsets
     xs = (xb.clone(), [xb[offs[i]:offs[i + 1]].clone() for i in range(len(table))])
     bsolv.close()
