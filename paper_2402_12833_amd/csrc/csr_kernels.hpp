@@ -169,6 +169,70 @@ __global__ void __launch_bounds__(kBlock) k_csr_restrict_smooth(const Ctl* __res
         out[(size_t)i * stride] = csr_smooth_at<T, G>(A, D, g, i, omega, two);
 }
 
+// Sum over the 64 lanes of a wavefront (every lane gets the sum; fixed
+// order, so deterministic).
+template <typename T>
+__device__ __forceinline__ T csr_wave_sum(T v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Row i's dot product with one wavefront per row: lane l takes entries l,
+// l + 64, .. of the row (all loads of a lane issued together), then the
+// lanes' sums are added by the butterfly.  For rows of the small coarse
+// levels, where one thread per row walks its ~27 entries in dependent
+// groups while few rows keep the chip busy.
+template <typename T, typename F>
+__device__ __forceinline__ T csr_row_dot_wave(const CsrOp<T>& A, int i, F&& u) {
+    const int s = i >> 6;
+    const int off = A.soff[s] + (i & 63), w = A.swid[s];
+    T acc = T(0);
+    for (int k = (int)threadIdx.x & 63; k < w; k += 64) acc += A.val[off + 64 * k] * u(A.col[off + 64 * k]);
+    return csr_wave_sum(acc);
+}
+
+// k_csr_restrict_smooth with the rows of either half taken one per
+// wavefront (WR: the restriction's, WS: the smoother's), the same
+// arithmetic up to the order of each row's sum.
+template <typename T, typename TI, typename G, int WR, int WS>
+__global__ void __launch_bounds__(kBlock) k_csr_restrict_smooth_w(const Ctl* __restrict__ ctl, CsrOp<T> R,
+                                                                  const TI* __restrict__ gf, T* __restrict__ gc,
+                                                                  int nr, CsrOp<T> A, const T* __restrict__ D,
+                                                                  const G* __restrict__ g, T* __restrict__ out,
+                                                                  int stride, T omega, int two) {
+    if (ctl->state != 0) return;
+    const int b = (int)blockIdx.x, wv = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+    if (b < nr) {
+        if (WR) {
+            for (int i = b * kWaves + wv; i < R.n; i += nr * kWaves) {
+                const T v = csr_row_dot_wave<T>(R, i, [&](int j) { return T(gf[j]); });
+                if (lane == 0) gc[i] = v;
+            }
+        } else {
+            for (int i = b * kBlock + (int)threadIdx.x; i < R.n; i += nr * kBlock)
+                gc[i] = csr_row_dot<T>(R, i, [&](int j) { return T(gf[j]); });
+        }
+        return;
+    }
+    const int bs = b - nr, gs = (int)gridDim.x - nr;
+    if (WS) {
+        for (int i = bs * kWaves + wv; i < A.n; i += gs * kWaves) {
+            const T gi = T(g[i]), Di = D[i];
+            const T c1 = omega * (gi / Di);
+            T c = c1;
+            if (two) {
+                const T Ac = csr_row_dot_wave<T>(A, i, [&](int j) { return omega * (T(g[j]) / D[j]); });
+                c = c1 + omega * ((gi - Ac) / Di);
+            }
+            if (lane == 0) out[(size_t)i * stride] = c;
+        }
+    } else {
+        for (int i = bs * kBlock + (int)threadIdx.x; i < A.n; i += gs * kBlock)
+            out[(size_t)i * stride] = csr_smooth_at<T, G>(A, D, g, i, omega, two);
+    }
+}
+
 // Block carry up one level: Yf[:, 0..NC-1] = P Yc[:, 0..NC-1] (node-major,
 // strides even_up(NC) and even_up(NC+1)).
 template <typename T, int NC>

@@ -251,6 +251,7 @@ class CsrSolver : public SolverBase {
     template <typename V>
     struct DevCsr {
         int n = 0;
+        int maxw = 0;   // widest slice (entries per row, padded)
         DevBuf<int> soff, swid, col;
         DevBuf<V> val;
         // the sliced layout of CsrOp (host::csr_sliced)
@@ -258,6 +259,8 @@ class CsrSolver : public SolverBase {
             n = M.n;
             host::Sliced S;
             if (!host::csr_sliced(M, S)) throw ApiError(AMGMPCG_INVALID_ARG, "sparse matrix too large");
+            maxw = 0;
+            for (int w : S.wid) maxw = std::max(maxw, w);
             std::vector<V> v(S.val.begin(), S.val.end());
             soff.alloc(S.off.size());
             swid.alloc(S.wid.size());
@@ -386,21 +389,39 @@ class CsrSolver : public SolverBase {
         const T omega = T(opt_.omega);
         const int two = opt_.nu >= 2 ? 1 : 0;
         {
-            const int l = L_ - 1, nr = blocks(N_[l]);
-            k_csr_restrict_smooth<T, double, double><<<nr + blocks(N_[L_]), kBlock, 0, stream_>>>(
-                ctl, R_l_[l].op(), r, g_[l].p, nr, A_[L_].op(), D_[L_].p, r, cL_.p, 1, omega, two);
+            const int l = L_ - 1;
+            launch_rs<double, double>(ctl, &R_l_[l], r, g_[l].p, A_[L_], D_[L_].p, r, cL_.p, 1, omega, two);
             cL_final_ = cL_.p;
         }
-        for (int l = L_ - 2; l >= 0; --l) {
-            const int nr = blocks(N_[l]);
-            k_csr_restrict_smooth<T, T, T><<<nr + blocks(N_[l + 1]), kBlock, 0, stream_>>>(
-                ctl, R_l_[l].op(), g_[l + 1].p, g_[l].p, nr, A_[l + 1].op(), D_[l + 1].p, g_[l + 1].p,
-                Y_[l + 1].p + (l + 1), even_up(l + 2), omega, two);
-        }
-        k_csr_restrict_smooth<T, T, T><<<blocks(N_[0]), kBlock, 0, stream_>>>(
-            ctl, CsrOp<T>{0, nullptr, nullptr, nullptr, nullptr}, static_cast<const T*>(nullptr), nullptr, 0, A_[0].op(),
-            D_[0].p, g_[0].p, Y_[0].p, even_up(1), omega, two);
+        for (int l = L_ - 2; l >= 0; --l)
+            launch_rs<T, T>(ctl, &R_l_[l], g_[l + 1].p, g_[l].p, A_[l + 1], D_[l + 1].p, g_[l + 1].p,
+                            Y_[l + 1].p + (l + 1), even_up(l + 2), omega, two);
+        launch_rs<T, T>(ctl, nullptr, static_cast<const T*>(nullptr), nullptr, A_[0], D_[0].p, g_[0].p, Y_[0].p,
+                        even_up(1), omega, two);
         enqueue_prolong(ctl);
+    }
+
+    // One restriction + smoother launch; the rows of a half with at most
+    // kCsrWaveRows rows of at least kCsrWaveWidth entries (padded slice
+    // width) are taken one per wavefront (small coarse levels: their
+    // ~27-entry rows would otherwise be walked by few threads in dependent
+    // groups), the others one per thread.
+    static constexpr int kCsrWaveRows = 1 << 12;
+    static constexpr int kCsrWaveWidth = 16;
+    static bool wave_rows(const DevCsr<T>& M) { return M.n <= kCsrWaveRows && M.maxw >= kCsrWaveWidth; }
+    template <typename TI, typename G>
+    void launch_rs(const Ctl* ctl, const DevCsr<T>* Rm, const TI* gf, T* gc, const DevCsr<T>& Am, const T* D,
+                   const G* g, T* out, int stride, T omega, int two) {
+        const CsrOp<T> R = Rm ? Rm->op() : CsrOp<T>{0, nullptr, nullptr, nullptr, nullptr};
+        const CsrOp<T> A = Am.op();
+        const bool wr = Rm && R.n > 0 && wave_rows(*Rm), ws = wave_rows(Am);
+        const int nr = R.n > 0 ? (wr ? (R.n + kWaves - 1) / kWaves : blocks(R.n)) : 0;
+        const int ns = ws ? (A.n + kWaves - 1) / kWaves : blocks(A.n);
+        auto go = [&](auto k) { k<<<nr + ns, kBlock, 0, stream_>>>(ctl, R, gf, gc, nr, A, D, g, out, stride, omega, two); };
+        if (wr && ws) go(k_csr_restrict_smooth_w<T, TI, G, 1, 1>);
+        else if (wr) go(k_csr_restrict_smooth_w<T, TI, G, 1, 0>);
+        else if (ws) go(k_csr_restrict_smooth_w<T, TI, G, 0, 1>);
+        else go(k_csr_restrict_smooth<T, TI, G>);
     }
 
     void enqueue_prolong(const Ctl* ctl) {
