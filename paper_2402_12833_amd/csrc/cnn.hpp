@@ -134,27 +134,47 @@ __global__ void __launch_bounds__(kCB) k_conv_lds(const Ctl* __restrict__ ctl, c
     for (int i = 0; i < TY; ++i)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) acc[i][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int ch = 0; ch < NCH; ++ch) {
+    // the 16-byte pieces of this thread's column of chunk ch: rows srow,
+    // srow + RPP, .. (at most NPASS).  With 32-channel chunks (their LDS
+    // tile already limits a CU to three blocks, so the registers are there)
+    // the next chunk's pieces are loaded during the current chunk's MFMAs.
+    constexpr int NPASS = (NR + RPP - 1) / RPP;
+    int4 stg[NPASS];
+    auto stage_load = [&](int ch) {
         const int c = ch * CC + sq * 8;
+#pragma unroll
+        for (int t = 0; t < NPASS; ++t) {
+            const int r = srow + t * RPP;
+            const int ly = r % LY, lz = r / LY;
+            const int gy = y0 - H + ly, gz = z0 - H + lz;
+            int4 val = int4{0, 0, 0, 0};
+            if (r < NR && xin && gy >= 0 && gy < S && gz >= 0 && gz < S) {
+                // 32-bit byte offsets from the (uniform) array bases
+                if (c < C1)
+                    val = *reinterpret_cast<const int4*>(
+                        reinterpret_cast<const char*>(Xc) +
+                        2u * (unsigned)((((gz >> 1) * Sc + (gy >> 1)) * Sc + (gx >> 1)) * C1 + c));
+                else
+                    val = *reinterpret_cast<const int4*>(reinterpret_cast<const char*>(X) +
+                                                         2u * (unsigned)(((gz * S + gy) * S + gx) * C2 + (c - C1)));
+            }
+            stg[t] = val;
+        }
+    };
+    constexpr bool kPre = CC == 32;
+    stage_load(0);
+    for (int ch = 0; ch < NCH; ++ch) {
+        if (ch > 0) __syncthreads();   // the previous chunk's MFMAs are done with the tile
+        if (!kPre && ch > 0) stage_load(ch);
         if (srow < RPP) {
-            for (int r = srow; r < NR; r += RPP) {
-                const int ly = r % LY, lz = r / LY;
-                const int gy = y0 - H + ly, gz = z0 - H + lz;
-                int4 val = int4{0, 0, 0, 0};
-                if (xin && gy >= 0 && gy < S && gz >= 0 && gz < S) {
-                    // 32-bit byte offsets from the (uniform) array bases
-                    if (c < C1)
-                        val = *reinterpret_cast<const int4*>(
-                            reinterpret_cast<const char*>(Xc) +
-                            2u * (unsigned)((((gz >> 1) * Sc + (gy >> 1)) * Sc + (gx >> 1)) * C1 + c));
-                    else
-                        val = *reinterpret_cast<const int4*>(reinterpret_cast<const char*>(X) +
-                                                             2u * (unsigned)(((gz * S + gy) * S + gx) * C2 + (c - C1)));
-                }
-                *reinterpret_cast<int4*>(tile + (r * LX + slx) * VS + sq * 8) = val;
+#pragma unroll
+            for (int t = 0; t < NPASS; ++t) {
+                const int r = srow + t * RPP;
+                if (r < NR) *reinterpret_cast<int4*>(tile + (r * LX + slx) * VS + sq * 8) = stg[t];
             }
         }
         __syncthreads();
+        if (kPre && ch + 1 < NCH) stage_load(ch + 1);
         // step st's (dz, dx) offset: one for all lanes (CC = 32), or one per
         // lane half (CC = 16; combo 9 of the last step is past the taps: its
         // weights are zero, its input any valid row); the weights of step
@@ -210,7 +230,6 @@ __global__ void __launch_bounds__(kCB) k_conv_lds(const Ctl* __restrict__ ctl, c
                                                                              acc[i][nt], 0, 0, 0);
             }
         }
-        __syncthreads();
     }
     // lane (m, kq): voxel x0 + m, channels co0 + nt * 16 + 4 kq .. + 3
     const int z = z0 + w, x = x0 + m;
