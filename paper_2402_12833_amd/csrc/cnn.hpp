@@ -278,27 +278,42 @@ __global__ void __launch_bounds__(kCB) k_conv_lds(const Ctl* __restrict__ ctl, c
 
 // The network's first layer (3x3x3, 16 outputs, ReLU) on its input, whose
 // channels 2..15 are zero: K = 27 taps x 2 channels (54, padded to 64 = two
-// v_mfma_f32_16x16x32_bf16 steps instead of 14 over the zero channels).  X2:
-// channels 0 and 1 of each voxel as one 32-bit word; W: the layer's weights
-// [tap][16][16] of which channels 0 and 1 are read.  K slot k of a step:
+// v_mfma_f32_16x16x32_bf16 steps instead of 14 over the zero channels).  The
+// input is formed while the tile is staged, as k_pack_input forms it:
+// channel 0 = bfloat16(r * scale) from the n^3 FP64 vector r, channel 1 =
+// lk (or 0), both 0 outside n^3; one 32-bit word per voxel in LDS.  W: the
+// layer's weights [tap][16][16] of which channels 0 and 1 are read.  K slot k of a step:
 // tap 16 st + k / 2, channel k % 2; lane group kq holds slots 8 kq .. 8 kq + 7
 // (taps 16 st + 4 kq + j, j = 0..3) for both operands, so the sum does not
 // depend on the hardware's K order.  Tile, wavefront rows and epilogue as in
 // k_conv_lds.
-static __global__ void __launch_bounds__(kCB) k_conv_in2(const Ctl* __restrict__ ctl, const unsigned* __restrict__ X2,
-                                                  const bf16* __restrict__ W, bf16* __restrict__ Y, int S) {
+static __global__ void __launch_bounds__(kCB) k_conv_in2(const Ctl* __restrict__ ctl, const double* __restrict__ r,
+                                                  const double* __restrict__ scale, const bf16* __restrict__ lk,
+                                                  int n, const bf16* __restrict__ W, bf16* __restrict__ Y, int S) {
     if (ctl && ctl->state != 0) return;
-    constexpr int LX = 18, LY = 6, LZ = 6, NV = LX * LY * LZ;
+    constexpr int LX = 18, LY = 6, LZ = 6, NV = LX * LY * LZ, NIT = (NV + kCB - 1) / kCB;
     __shared__ unsigned tile[NV];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int m = lane & 15, kq = lane >> 4;
     const int x0 = blockIdx.x * 16, y0 = blockIdx.y * 4, z0 = blockIdx.z * 4;
-    for (int v = threadIdx.x; v < NV; v += kCB) {
+    const float sc = (float)(*scale);
+    // all loads of the tile first, then the conversions and LDS stores
+    double rv[NIT];
+    bf16 kv[NIT];
+#pragma unroll
+    for (int q = 0; q < NIT; ++q) {
+        const int v = threadIdx.x + q * kCB;
         const int lx = v % LX, ly = (v / LX) % LY, lz = v / (LX * LY);
         const int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z0 - 1 + lz;
-        unsigned val = 0u;
-        if (gx >= 0 && gx < S && gy >= 0 && gy < S && gz >= 0 && gz < S) val = X2[(gz * S + gy) * S + gx];
-        tile[v] = val;
+        const bool in = v < NV && gx >= 0 && gx < n && gy >= 0 && gy < n && gz >= 0 && gz < n;
+        const int idx = in ? gx + n * (gy + n * gz) : 0;
+        rv[q] = in ? r[idx] : 0.0;
+        kv[q] = (in && lk) ? lk[idx] : (bf16)0;
+    }
+#pragma unroll
+    for (int q = 0; q < NIT; ++q) {
+        const int v = threadIdx.x + q * kCB;
+        if (v < NV) tile[v] = (unsigned)f2bf((float)rv[q] * sc) | ((unsigned)kv[q] << 16);
     }
     // this lane's 4 taps per step: weights (channels 0, 1) and tile offsets
     typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
@@ -411,9 +426,11 @@ __global__ void __launch_bounds__(kCB) k_conv_wgrad(const Ctl* __restrict__ ctl,
 
 // Network input: channel 0 = r * scale (scale = 1 / rms(r)), channel 1 =
 // normalised log kappa (or 0), channels 2..15 = 0; voxels outside n^3 = 0.
+// Written as a 16-channel tensor for training (the weight gradient of the
+// first layer reads it); inference forms it inside k_conv_in2.
 static __global__ void __launch_bounds__(kCB) k_pack_input(const Ctl* __restrict__ ctl, const double* __restrict__ r,
                                                     const double* __restrict__ scale, const bf16* __restrict__ lk,
-                                                    bf16* __restrict__ X, unsigned* __restrict__ X2, int n, int S) {
+                                                    bf16* __restrict__ X, int n, int S) {
     if (ctl && ctl->state != 0) return;
     const int v = blockIdx.x * kCB + threadIdx.x;
     if (v >= S * S * S) return;
@@ -424,22 +441,31 @@ static __global__ void __launch_bounds__(kCB) k_pack_input(const Ctl* __restrict
     const bf16 c0 = in ? f2bf((float)r[idx] * s) : (bf16)0;
     const bf16 c1 = (in && lk) ? lk[idx] : (bf16)0;
     const unsigned c01 = (unsigned)c0 | ((unsigned)c1 << 16);
-    // X2: the two channels that can be non-zero, one 32-bit word per voxel;
-    // X (if given): all 16 channels (32 bytes) in two 16-byte stores
-    X2[v] = c01;
-    if (X) {
-        uint4* o = reinterpret_cast<uint4*>(X + (size_t)v * 16);
-        o[0] = make_uint4(c01, 0u, 0u, 0u);
-        o[1] = make_uint4(0u, 0u, 0u, 0u);
-    }
+    // all 16 channels (32 bytes) in two 16-byte stores
+    uint4* o = reinterpret_cast<uint4*>(X + (size_t)v * 16);
+    o[0] = make_uint4(c01, 0u, 0u, 0u);
+    o[1] = make_uint4(0u, 0u, 0u, 0u);
 }
 
-// Sum of squares of v (N values): per-block partials part[b], fixed order.
+// Sum of squares of v (N values): per-block partials part[b], fixed order
+// (each thread adds its values i, i + stride, ... in increasing i; the loads
+// of 8 of them are issued before the additions).
 static __global__ void __launch_bounds__(kCB) k_sumsq(const Ctl* __restrict__ ctl, const double* __restrict__ v, int N,
                                                double* __restrict__ part) {
     if (ctl && ctl->state != 0) return;
+    constexpr int U = 8;
+    const int stride = gridDim.x * kCB;
     double s[1] = {0.0};
-    for (int i = blockIdx.x * kCB + threadIdx.x; i < N; i += gridDim.x * kCB) s[0] += v[i] * v[i];
+    for (int i0 = blockIdx.x * kCB + threadIdx.x; i0 < N; i0 += U * stride) {
+        double t[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int i = i0 + j * stride;
+            t[j] = i < N ? v[i] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) s[0] += t[j] * t[j];
+    }
     block_sum_store<1>(s, part, gridDim.x, blockIdx.x);
 }
 

@@ -20,7 +20,8 @@ struct LayerSpec {
 constexpr LayerSpec kLayers[11] = {{27, 16, 16}, {27, 16, 16}, {27, 16, 32}, {27, 32, 32}, {27, 32, 64}, {27, 64, 64},
                                    {27, 96, 32}, {27, 32, 32}, {27, 48, 16}, {27, 16, 16}, {1, 16, 16}};
 constexpr int kInChannels = 2;
-constexpr int kSumBlocks = 512;   // blocks of the sum-of-squares partials
+constexpr int kSumBlocks = 512;   // blocks of the dot-product partials
+constexpr int kSqBlocks = 1024;   // blocks of the sum-of-squares partials (8 values per thread at 128^3)
 
 inline int64_t layer_size(int l) { return (int64_t)kLayers[l].taps * kLayers[l].cout * kLayers[l].cin; }
 inline int64_t total_weights() {
@@ -57,7 +58,6 @@ class Net {
         hipError_t err = hipSuccess;
         const size_t V0 = (size_t)S * S * S, V1 = V0 / 8, V2 = V1 / 8;
         x0.alloc(V0 * 16, err);
-        x0c.alloc(V0, err);
         e1.alloc(V0 * 16, err);
         e2.alloc(V0 * 16, err);
         p1.alloc(V1 * 16, err);
@@ -90,6 +90,7 @@ class Net {
         flag.alloc(1, err);
         // block partials: one per block of the loss kernel, or up to three
         // values (k_dots3) per block of the kSumBlocks-block reductions
+        static_assert(kSqBlocks <= 3 * kSumBlocks, "partials buffer");
         part.alloc((V0 + kCB - 1) / kCB > 3 * kSumBlocks ? (V0 + kCB - 1) / kCB : 3 * kSumBlocks, err);
         const int64_t NW = total_weights();
         w.alloc(NW, err);
@@ -166,14 +167,14 @@ class Net {
     // of w7 and w9 read them); inference reads them in place.
     void forward(const Ctl* ctl, const double* r, const bf16* lk, hipStream_t s, bool train = false) {
         const int S0 = S, S1 = S / 2, S2 = S / 4;
-        k_sumsq<<<kSumBlocks, kCB, 0, s>>>(ctl, r, n * n * n, part.p);
-        k_finish_sum<<<1, kRedBlock, 0, s>>>(ctl, part.p, kSumBlocks, n * n * n, 0, small.p);
+        k_sumsq<<<kSqBlocks, kCB, 0, s>>>(ctl, r, n * n * n, part.p);
+        k_finish_sum<<<1, kRedBlock, 0, s>>>(ctl, part.p, kSqBlocks, n * n * n, 0, small.p);
         // the 16-channel input only for training (the weight gradient of
-        // the first layer reads it); the first layer reads channels 0 and 1
-        k_pack_input<<<blocks((size_t)S0 * S0 * S0), kCB, 0, s>>>(ctl, r, small.p, lk, train ? x0.p : nullptr,
-                                                                   x0c.p, n, S0);
-        k_conv_in2<<<dim3(S0 / 16 + (S0 % 16 != 0), S0 / 4, S0 / 4), kCB, 0, s>>>(ctl, x0c.p, wb.p + woff(0), e1.p,
-                                                                                 S0);
+        // the first layer reads it); the first layer forms channels 0 and 1
+        // from r itself
+        if (train) k_pack_input<<<blocks((size_t)S0 * S0 * S0), kCB, 0, s>>>(ctl, r, small.p, lk, x0.p, n, S0);
+        k_conv_in2<<<dim3(S0 / 16 + (S0 % 16 != 0), S0 / 4, S0 / 4), kCB, 0, s>>>(ctl, r, small.p, lk, n,
+                                                                                 wb.p + woff(0), e1.p, S0);
         conv<16, 16, 3, 1, 0>(ctl, e1.p, 1, e2.p, S0, s);
         k_avgpool<<<blocks((size_t)S1 * S1 * S1 * 2), kCB, 0, s>>>(ctl, e2.p, p1.p, S1, 16);
         conv<16, 32, 3, 1, 0>(ctl, p1.p, 2, e3.p, S1, s);
@@ -200,8 +201,8 @@ class Net {
     // MSE loss against e / rms(e): loss -> small[2], output gradient -> g0a.
     void loss_mse(const double* e, hipStream_t s) {
         const size_t V0 = (size_t)S * S * S;
-        k_sumsq<<<kSumBlocks, kCB, 0, s>>>(nullptr, e, n * n * n, part.p);
-        k_finish_sum<<<1, kRedBlock, 0, s>>>(nullptr, part.p, kSumBlocks, n * n * n, 0, small.p + 1);
+        k_sumsq<<<kSqBlocks, kCB, 0, s>>>(nullptr, e, n * n * n, part.p);
+        k_finish_sum<<<1, kRedBlock, 0, s>>>(nullptr, part.p, kSqBlocks, n * n * n, 0, small.p + 1);
         k_mse_grad<<<blocks(V0), kCB, 0, s>>>(out.p, e, small.p + 1, g0a.p, n, S, part.p);
         k_finish_sum<<<1, kRedBlock, 0, s>>>(nullptr, part.p, (int)blocks(V0), 0, 1, small.p + 2);
     }
@@ -312,7 +313,6 @@ class Net {
     }
 
     Buf<bf16> x0, e1, e2, p1, e3, e4, p2, b1, b2, c1, d1, d2, c2, d3, d4;
-    Buf<unsigned> x0c;   // input channels 0 and 1, one word per voxel
     Buf<float> out;
     Buf<bf16> g0a, g0b, g0c, g1a, g1b, g1c, g2a, g2b, g2c;
     Buf<double> small, part, dvec, qvec, rvec, q2vec;
@@ -366,7 +366,7 @@ class Net {
 
     // Small grids (fewer than kConvFill tiles) split the output channels
     // over blocks so that the whole chip works.
-    static constexpr int kConvFill = 2048;
+    static constexpr int kConvFill = 1024;
     template <int CIN, int C1, int COUT, int KS, int RELU, int F32>
     static void conv_launch(const Ctl* ctl, const bf16* Xc, const bf16* X, const bf16* Wl, void* Y, int Sg,
                             hipStream_t s, const bf16* W2 = nullptr) {
