@@ -276,6 +276,8 @@ __global__ void __launch_bounds__(kCB) k_conv_lds(const Ctl* __restrict__ ctl, c
     }
 }
 
+constexpr int kIn2Slabs = 4;   // 4-plane z slabs per block of k_conv_in2
+
 // The network's first layer (3x3x3, 16 outputs, ReLU) on its input, whose
 // channels 2..15 are zero: K = 27 taps x 2 channels (54, padded to 64 = two
 // v_mfma_f32_16x16x32_bf16 steps instead of 14 over the zero channels).  The
@@ -295,26 +297,34 @@ static __global__ void __launch_bounds__(kCB) k_conv_in2(const Ctl* __restrict__
     __shared__ unsigned tile[NV];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int m = lane & 15, kq = lane >> 4;
-    const int x0 = blockIdx.x * 16, y0 = blockIdx.y * 4, z0 = blockIdx.z * 4;
+    const int x0 = blockIdx.x * 16, y0 = blockIdx.y * 4;
     const float sc = (float)(*scale);
-    // all loads of the tile first, then the conversions and LDS stores
-    double rv[NIT];
-    bf16 kv[NIT];
+    // this thread's tile voxels (v = threadIdx.x + q kCB): fixed (x, y),
+    // z offset from the slab's first plane
+    int toffs[NIT], tz[NIT];
+    bool txy[NIT];
 #pragma unroll
     for (int q = 0; q < NIT; ++q) {
         const int v = threadIdx.x + q * kCB;
         const int lx = v % LX, ly = (v / LX) % LY, lz = v / (LX * LY);
-        const int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z0 - 1 + lz;
-        const bool in = v < NV && gx >= 0 && gx < n && gy >= 0 && gy < n && gz >= 0 && gz < n;
-        const int idx = in ? gx + n * (gy + n * gz) : 0;
-        rv[q] = in ? r[idx] : 0.0;
-        kv[q] = (in && lk) ? lk[idx] : (bf16)0;
+        const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+        txy[q] = v < NV && gx >= 0 && gx < n && gy >= 0 && gy < n;
+        toffs[q] = gx + n * gy;
+        tz[q] = lz - 1;
     }
+    // the slab's loads: all issued before any use
+    double rv[NIT];
+    bf16 kv[NIT];
+    auto load_slab = [&](int z0) {
 #pragma unroll
-    for (int q = 0; q < NIT; ++q) {
-        const int v = threadIdx.x + q * kCB;
-        if (v < NV) tile[v] = (unsigned)f2bf((float)rv[q] * sc) | ((unsigned)kv[q] << 16);
-    }
+        for (int q = 0; q < NIT; ++q) {
+            const int gz = z0 + tz[q];
+            const bool in = txy[q] && gz >= 0 && gz < n;
+            const int idx = in ? toffs[q] + n * n * gz : 0;
+            rv[q] = in ? r[idx] : 0.0;
+            kv[q] = (in && lk) ? lk[idx] : (bf16)0;
+        }
+    };
     // this lane's 4 taps per step: weights (channels 0, 1) and tile offsets
     typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
     u32x4 bw[2];
@@ -328,37 +338,54 @@ static __global__ void __launch_bounds__(kCB) k_conv_in2(const Ctl* __restrict__
             toff[st][j] = (tap_dz(tv) + 1) * LY * LX + (tap_dy(tv) + 1) * LX + (tap_dx(tv) + 1);
             bw[st][j] = t < 27 ? *reinterpret_cast<const unsigned*>(W + (size_t)(t * 16 + m) * 16) : 0u;
         }
-    __syncthreads();
-    f32x4 acc[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
     const unsigned* tl = tile + (w * LY) * LX + m;   // output row 0 of this wavefront at tap (-1, -1, -1)
-#pragma unroll
-    for (int st = 0; st < 2; ++st)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            u32x4 a;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) a[j] = tl[toff[st][j] + i * LX];
-            acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, bw[st]),
-                                                            __builtin_bit_cast(bf16x8, a), acc[i], 0, 0, 0);
-        }
-    const int z = z0 + w, x = x0 + m;
-    if (z >= S || x >= S) return;
     char* const Yb = reinterpret_cast<char*>(Y);
+    const int x = x0 + m;
+    // blockIdx.z: a group of kIn2Slabs consecutive 4-plane slabs; the next
+    // slab's input is loaded during this slab's MFMAs and stores
+    const int zs0 = blockIdx.z * kIn2Slabs;
+    load_slab(zs0 * 4);
+    for (int k = 0; k < kIn2Slabs; ++k) {
+        const int z0 = (zs0 + k) * 4;
+        if (z0 >= S) break;
+        if (k > 0) __syncthreads();   // the previous slab's MFMAs are done with the tile
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int y = y0 + i;
-        if (y >= S) break;
-        const unsigned vox = (unsigned)((z * S + y) * S + x);
-        i16x2 p0 = __builtin_bit_cast(i16x2, pack_bf16x2(acc[i][0], acc[i][1]));
-        i16x2 p1 = __builtin_bit_cast(i16x2, pack_bf16x2(acc[i][2], acc[i][3]));
-        p0 = __builtin_elementwise_max(p0, i16x2{0, 0});
-        p1 = __builtin_elementwise_max(p1, i16x2{0, 0});
-        uint2 pk;
-        pk.x = __builtin_bit_cast(unsigned, p0);
-        pk.y = __builtin_bit_cast(unsigned, p1);
-        *reinterpret_cast<uint2*>(Yb + 2u * (vox * 16u + 4u * kq)) = pk;
+        for (int q = 0; q < NIT; ++q) {
+            const int v = threadIdx.x + q * kCB;
+            if (v < NV) tile[v] = (unsigned)f2bf((float)rv[q] * sc) | ((unsigned)kv[q] << 16);
+        }
+        __syncthreads();
+        if (k + 1 < kIn2Slabs && z0 + 4 < S) load_slab(z0 + 4);
+        f32x4 acc[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int st = 0; st < 2; ++st)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                u32x4 a;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) a[j] = tl[toff[st][j] + i * LX];
+                acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, bw[st]),
+                                                                __builtin_bit_cast(bf16x8, a), acc[i], 0, 0, 0);
+            }
+        const int z = z0 + w;
+        if (z < S && x < S) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int y = y0 + i;
+                if (y >= S) break;
+                const unsigned vox = (unsigned)((z * S + y) * S + x);
+                i16x2 p0 = __builtin_bit_cast(i16x2, pack_bf16x2(acc[i][0], acc[i][1]));
+                i16x2 p1 = __builtin_bit_cast(i16x2, pack_bf16x2(acc[i][2], acc[i][3]));
+                p0 = __builtin_elementwise_max(p0, i16x2{0, 0});
+                p1 = __builtin_elementwise_max(p1, i16x2{0, 0});
+                uint2 pk;
+                pk.x = __builtin_bit_cast(unsigned, p0);
+                pk.y = __builtin_bit_cast(unsigned, p1);
+                *reinterpret_cast<uint2*>(Yb + 2u * (vox * 16u + 4u * kq)) = pk;
+            }
+        }
     }
 }
 

@@ -173,7 +173,8 @@ class Net {
         // the first layer reads it); the first layer forms channels 0 and 1
         // from r itself
         if (train) k_pack_input<<<blocks((size_t)S0 * S0 * S0), kCB, 0, s>>>(ctl, r, small.p, lk, x0.p, n, S0);
-        k_conv_in2<<<dim3(S0 / 16 + (S0 % 16 != 0), S0 / 4, S0 / 4), kCB, 0, s>>>(ctl, r, small.p, lk, n,
+        k_conv_in2<<<dim3(S0 / 16 + (S0 % 16 != 0), S0 / 4, (S0 / 4 + kIn2Slabs - 1) / kIn2Slabs), kCB, 0, s>>>(
+            ctl, r, small.p, lk, n,
                                                                                  wb.p + woff(0), e1.p, S0);
         conv<16, 16, 3, 1, 0>(ctl, e1.p, 1, e2.p, S0, s);
         k_avgpool<<<blocks((size_t)S1 * S1 * S1 * 2), kCB, 0, s>>>(ctl, e2.p, p1.p, S1, 16);
