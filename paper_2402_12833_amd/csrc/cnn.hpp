@@ -85,11 +85,13 @@ __device__ __forceinline__ unsigned pack_bf16x2(float lo, float hi) {
     return __builtin_bit_cast(unsigned, v);
 }
 
-template <int CIN, int C1, int COUT, int KS, int RELU, int OUT_F32, int CSPLIT>
+template <int CIN, int C1, int COUT, int KS, int RELU, int OUT_F32, int CSPLIT, int POOL = 0>
 __global__ void __launch_bounds__(kCB) k_conv_lds(const Ctl* __restrict__ ctl, const bf16* __restrict__ Xc,
                                                   const bf16* __restrict__ X, const bf16* __restrict__ W,
-                                                  void* __restrict__ Yv, int S, const bf16* __restrict__ W2) {
+                                                  void* __restrict__ Yv, int S, const bf16* __restrict__ W2,
+                                                  bf16* __restrict__ Yp) {
     if (ctl && ctl->state != 0) return;
+    static_assert(!POOL || (OUT_F32 == 0 && KS == 3 && conv_ty<CIN>() == 4), "pooling: bfloat16 3x3x3 layers");
     static_assert(CIN % 16 == 0 && COUT % (16 * CSPLIT) == 0 && C1 % 16 == 0 && C1 < CIN, "channel layout");
     static_assert(OUT_F32 != 2 || COUT / CSPLIT == 16, "the fused output layer needs all 16 channels in one block");
     constexpr int C2 = CIN - C1;
@@ -233,44 +235,100 @@ __global__ void __launch_bounds__(kCB) k_conv_lds(const Ctl* __restrict__ ctl, c
     }
     // lane (m, kq): voxel x0 + m, channels co0 + nt * 16 + 4 kq .. + 3
     const int z = z0 + w, x = x0 + m;
-    if (z >= S || x >= S) return;
+    const bool vin = z < S && x < S;
     char* const Yb = static_cast<char*>(Yv);
+    if constexpr (OUT_F32 != 0) {
+        if (!vin) return;
 #pragma unroll
-    for (int i = 0; i < TY; ++i) {
-        const int y = y0 + i;
-        if (y >= S) break;
-        const unsigned vox = (unsigned)((z * S + y) * S + x);
+        for (int i = 0; i < TY; ++i) {
+            const int y = y0 + i;
+            if (y >= S) break;
+            const unsigned vox = (unsigned)((z * S + y) * S + x);
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            const int co = co0 + nt * 16 + 4 * kq;
-            if (OUT_F32 == 2) {
-                float part = 0.f;
+            for (int nt = 0; nt < NT; ++nt) {
+                const int co = co0 + nt * 16 + 4 * kq;
+                if (OUT_F32 == 2) {
+                    float part = 0.f;
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    float v = bf2f(f2bf(acc[i][nt][j]));
+                    for (int j = 0; j < 4; ++j) {
+                        float v = bf2f(f2bf(acc[i][nt][j]));
+                        if (RELU) v = v > 0.f ? v : 0.f;
+                        part += v * bf2f(W2[co + j]);
+                    }
+                    part += __shfl_xor(part, 16);
+                    part += __shfl_xor(part, 32);
+                    if (kq == 0) *reinterpret_cast<float*>(Yb + 4u * vox) = part;
+                } else {
+                    float v = acc[i][nt][0];
                     if (RELU) v = v > 0.f ? v : 0.f;
-                    part += v * bf2f(W2[co + j]);
+                    if (co == 0) *reinterpret_cast<float*>(Yb + 4u * vox) = v;
                 }
-                part += __shfl_xor(part, 16);
-                part += __shfl_xor(part, 32);
-                if (kq == 0) *reinterpret_cast<float*>(Yb + 4u * vox) = part;
-            } else if (OUT_F32) {
-                float v = acc[i][nt][0];
-                if (RELU) v = v > 0.f ? v : 0.f;
-                if (co == 0) *reinterpret_cast<float*>(Yb + 4u * vox) = v;
-            } else {
-                // ReLU on the bfloat16 pairs as signed 16-bit integers: a
-                // negative value (sign bit set) is below 0 and becomes +0
+            }
+        }
+    } else {
+        // ReLU on the bfloat16 pairs as signed 16-bit integers: a negative
+        // value (sign bit set) is below 0 and becomes +0
+        uint2 pk[TY][NT];
+#pragma unroll
+        for (int i = 0; i < TY; ++i)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
                 i16x2 p0 = __builtin_bit_cast(i16x2, pack_bf16x2(acc[i][nt][0], acc[i][nt][1]));
                 i16x2 p1 = __builtin_bit_cast(i16x2, pack_bf16x2(acc[i][nt][2], acc[i][nt][3]));
                 if (RELU) {
                     p0 = __builtin_elementwise_max(p0, i16x2{0, 0});
                     p1 = __builtin_elementwise_max(p1, i16x2{0, 0});
                 }
-                uint2 pk;
-                pk.x = __builtin_bit_cast(unsigned, p0);
-                pk.y = __builtin_bit_cast(unsigned, p1);
-                *reinterpret_cast<uint2*>(Yb + 2u * (vox * COUT + (unsigned)co)) = pk;
+                pk[i][nt].x = __builtin_bit_cast(unsigned, p0);
+                pk[i][nt].y = __builtin_bit_cast(unsigned, p1);
+            }
+        if (vin) {
+#pragma unroll
+            for (int i = 0; i < TY; ++i) {
+                const int y = y0 + i;
+                if (y >= S) break;
+                const unsigned vox = (unsigned)((z * S + y) * S + x);
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    *reinterpret_cast<uint2*>(Yb + 2u * (vox * COUT + (unsigned)(co0 + nt * 16 + 4 * kq))) = pk[i][nt];
+            }
+        }
+        if constexpr (POOL) {
+            // 2x2x2 average pooling of the stored (bfloat16) outputs into Yp
+            // (grid S/2): the block's 16 x 4 x 4 voxels are 8 x 2 x 2 coarse
+            // voxels; the outputs go through LDS (the tile is free once every
+            // wavefront is past its MFMAs), then each thread sums the 8
+            // children of one coarse voxel and 2 channels in FP32 in (z, y,
+            // x) order, scales by 1/8 and rounds to bfloat16.
+            constexpr int CB = NT * 16;
+            static_assert(4 * TY * 16 * CB <= NV * VS, "pool staging fits in the tile");
+            __syncthreads();
+            unsigned* const pw = reinterpret_cast<unsigned*>(tile);
+#pragma unroll
+            for (int i = 0; i < TY; ++i)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    *reinterpret_cast<uint2*>(pw + ((w * TY + i) * 16 + m) * (CB / 2) + nt * 8 + 2 * kq) = pk[i][nt];
+            __syncthreads();
+            const int Sc = S >> 1;
+            for (int q = threadIdx.x; q < 32 * (CB / 2); q += kCB) {
+                const int c2 = q % (CB / 2), cv = q / (CB / 2);
+                const int xc = cv & 7, yc = (cv >> 3) & 1, zc = cv >> 4;
+                const int gxc = (x0 >> 1) + xc, gyc = (y0 >> 1) + yc, gzc = (z0 >> 1) + zc;
+                if (gxc >= Sc || gyc >= Sc || gzc >= Sc) continue;
+                float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+#pragma unroll
+                        for (int d = 0; d < 2; ++d) {
+                            const unsigned u = pw[(((2 * zc + a) * TY + 2 * yc + b) * 16 + 2 * xc + d) * (CB / 2) + c2];
+                            s0 += bf2f((bf16)(u & 0xffffu));
+                            s1 += bf2f((bf16)(u >> 16));
+                        }
+                const unsigned o = (unsigned)f2bf(s0 * 0.125f) | ((unsigned)f2bf(s1 * 0.125f) << 16);
+                *reinterpret_cast<unsigned*>(Yp + ((size_t)(gzc * Sc + gyc) * Sc + gxc) * COUT + co0 + 2 * c2) = o;
             }
         }
     }
@@ -512,40 +570,6 @@ static __global__ void __launch_bounds__(kRedBlock) k_finish_sum(const Ctl* __re
             *out = res[0];
         }
     }
-}
-
-// 2x2x2 average pooling, S -> S/2 (C channels).
-// One thread per coarse voxel and 8 channels (16-byte loads and store); the
-// 8 children are summed in (z, y, x) order.  C must be a multiple of 8.
-static __global__ void __launch_bounds__(kCB) k_avgpool(const Ctl* __restrict__ ctl, const bf16* __restrict__ X,
-                                                 bf16* __restrict__ Y, int Sc, int C) {
-    if (ctl && ctl->state != 0) return;
-    const int G = C / 8;
-    const size_t e = (size_t)blockIdx.x * kCB + threadIdx.x;
-    if (e >= (size_t)Sc * Sc * Sc * G) return;
-    const int g = e % G;
-    const size_t v = e / G;
-    const int x = v % Sc, y = (v / Sc) % Sc, z = v / ((size_t)Sc * Sc);
-    const int Sf = 2 * Sc;
-    float s[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) s[k] = 0.f;
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b)
-            for (int d = 0; d < 2; ++d) {
-                const uint4 q = *reinterpret_cast<const uint4*>(
-                    X + (((size_t)(2 * z + a) * Sf + 2 * y + b) * Sf + 2 * x + d) * C + 8 * g);
-                const unsigned u[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    s[2 * k] += bf2f((bf16)(u[k] & 0xffffu));
-                    s[2 * k + 1] += bf2f((bf16)(u[k] >> 16));
-                }
-            }
-    unsigned o[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) o[k] = (unsigned)f2bf(s[2 * k] * 0.125f) | ((unsigned)f2bf(s[2 * k + 1] * 0.125f) << 16);
-    *reinterpret_cast<uint4*>(Y + v * C + 8 * g) = make_uint4(o[0], o[1], o[2], o[3]);
 }
 
 // Y (S^3, C1 + C2 channels) = [upsample2(A) (C1 channels, grid S/2) | B (C2)].

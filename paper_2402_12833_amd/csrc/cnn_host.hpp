@@ -176,11 +176,10 @@ class Net {
         k_conv_in2<<<dim3(S0 / 16 + (S0 % 16 != 0), S0 / 4, (S0 / 4 + kIn2Slabs - 1) / kIn2Slabs), kCB, 0, s>>>(
             ctl, r, small.p, lk, n,
                                                                                  wb.p + woff(0), e1.p, S0);
-        conv<16, 16, 3, 1, 0>(ctl, e1.p, 1, e2.p, S0, s);
-        k_avgpool<<<blocks((size_t)S1 * S1 * S1 * 2), kCB, 0, s>>>(ctl, e2.p, p1.p, S1, 16);
+        // the second layer also writes its 2x2x2 average pooling (p1)
+        conv_launch<16, 0, 16, 3, 1, 0, 1>(ctl, nullptr, e1.p, wb.p + woff(1), e2.p, S0, s, nullptr, p1.p);
         conv<16, 32, 3, 1, 0>(ctl, p1.p, 2, e3.p, S1, s);
-        conv<32, 32, 3, 1, 0>(ctl, e3.p, 3, e4.p, S1, s);
-        k_avgpool<<<blocks((size_t)S2 * S2 * S2 * 4), kCB, 0, s>>>(ctl, e4.p, p2.p, S2, 32);
+        conv_launch<32, 0, 32, 3, 1, 0, 1>(ctl, nullptr, e3.p, wb.p + woff(3), e4.p, S1, s, nullptr, p2.p);
         conv<32, 64, 3, 1, 0>(ctl, p2.p, 4, b1.p, S2, s);
         conv<64, 64, 3, 1, 0>(ctl, b1.p, 5, b2.p, S2, s);
         if (train) k_upcat<<<blocks((size_t)S1 * S1 * S1 * 96), kCB, 0, s>>>(ctl, b2.p, e4.p, c1.p, S1, 64, 32);
@@ -368,23 +367,27 @@ class Net {
     // Small grids (fewer than kConvFill tiles) split the output channels
     // over blocks so that the whole chip works.
     static constexpr int kConvFill = 1024;
-    template <int CIN, int C1, int COUT, int KS, int RELU, int F32>
+    // POOL: also the 2x2x2 average pooling of the output into Yp (grid Sg/2)
+    template <int CIN, int C1, int COUT, int KS, int RELU, int F32, int POOL = 0>
     static void conv_launch(const Ctl* ctl, const bf16* Xc, const bf16* X, const bf16* Wl, void* Y, int Sg,
-                            hipStream_t s, const bf16* W2 = nullptr) {
+                            hipStream_t s, const bf16* W2 = nullptr, bf16* Yp = nullptr) {
         const int tiles = ((Sg + 15) / 16) * ((Sg + conv_ty<CIN>() - 1) / conv_ty<CIN>()) * ((Sg + 3) / 4);
         if constexpr (!F32 && COUT % 64 == 0) {
             if (tiles < kConvFill) {
-                k_conv_lds<CIN, C1, COUT, KS, RELU, F32, 4><<<conv_grid(Sg, 4, conv_ty<CIN>()), kCB, 0, s>>>(ctl, Xc, X, Wl, Y, Sg, W2);
+                k_conv_lds<CIN, C1, COUT, KS, RELU, F32, 4, POOL><<<conv_grid(Sg, 4, conv_ty<CIN>()), kCB, 0, s>>>(
+                    ctl, Xc, X, Wl, Y, Sg, W2, Yp);
                 return;
             }
         }
         if constexpr (!F32 && COUT % 32 == 0) {
             if (tiles < kConvFill) {
-                k_conv_lds<CIN, C1, COUT, KS, RELU, F32, 2><<<conv_grid(Sg, 2, conv_ty<CIN>()), kCB, 0, s>>>(ctl, Xc, X, Wl, Y, Sg, W2);
+                k_conv_lds<CIN, C1, COUT, KS, RELU, F32, 2, POOL><<<conv_grid(Sg, 2, conv_ty<CIN>()), kCB, 0, s>>>(
+                    ctl, Xc, X, Wl, Y, Sg, W2, Yp);
                 return;
             }
         }
-        k_conv_lds<CIN, C1, COUT, KS, RELU, F32, 1><<<conv_grid(Sg, 1, conv_ty<CIN>()), kCB, 0, s>>>(ctl, Xc, X, Wl, Y, Sg, W2);
+        k_conv_lds<CIN, C1, COUT, KS, RELU, F32, 1, POOL><<<conv_grid(Sg, 1, conv_ty<CIN>()), kCB, 0, s>>>(
+            ctl, Xc, X, Wl, Y, Sg, W2, Yp);
     }
 
     template <int CIN, int COUT, int KS, int RELU, int F32>
