@@ -1259,6 +1259,101 @@ __global__ void __launch_bounds__(kBlock) k_restrict_fine_smooth(const Ctl* __re
     }
 }
 
+// 3D, constant coefficients, two sweeps: the restriction r -> level L-1 and
+// the finest smoother from one LDS tile of r per block.  A block owns a
+// kRTX x kRTY x kRTZ box of fine nodes (even corner), stages r over the box
+// and a one-node halo (as T, zero outside the grid), smooths the box's nodes
+// (4 per thread) and restricts the coarse nodes whose centre 2J+1 lies in the
+// box (their 3^3 support lies in the staged halo).  The arithmetic, in its
+// order, is that of fine_smooth_face without coefficient arrays and of
+// restrict_at (a face neighbour outside the grid is weighted 0 and reads the
+// halo's 0 instead of a clamped node), so the results are the same.  Tiles go
+// to XCDs in contiguous runs (xcd_block_of): neighbouring boxes share a L2.
+constexpr int kRTX = 32, kRTY = 8, kRTZ = 4;
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_restrict_fine_smooth_tile(const Ctl* __restrict__ ctl,
+                                                                      RestrictStep<double, T> rs, FineOp<T> op,
+                                                                      const double* __restrict__ r,
+                                                                      T* __restrict__ c, T omega, int ntx, int nty,
+                                                                      int ntz) {
+    if (ctl->state != 0) return;
+    static_assert(kRTX * kRTY == kBlock, "one thread per (x, y) of the box");
+    constexpr int LX = kRTX + 2, LY = kRTY + 2, LZ = kRTZ + 2, NV = LX * LY * LZ;
+    constexpr int NIT = (NV + kBlock - 1) / kBlock;
+    __shared__ T tile[NV];
+    const int t = xcd_block_of((int)blockIdx.x, ntx * nty * ntz);
+    const int bx = t % ntx, by = (t / ntx) % nty, bz = t / (ntx * nty);
+    const int X0 = bx * kRTX, Y0 = by * kRTY, Z0 = bz * kRTZ;
+    const int n = op.n;
+    // stage r over the box and its halo: all loads first
+    T v[NIT];
+#pragma unroll
+    for (int q = 0; q < NIT; ++q) {
+        const int vi = (int)threadIdx.x + q * kBlock;
+        const int lx = vi % LX, ly = (vi / LX) % LY, lz = vi / (LX * LY);
+        const int gx = X0 - 1 + lx, gy = Y0 - 1 + ly, gz = Z0 - 1 + lz;
+        const bool in = vi < NV && gx >= 0 && gx < n && gy >= 0 && gy < n && gz >= 0 && gz < n;
+        v[q] = in ? T(r[gx + n * (gy + n * gz)]) : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < NIT; ++q) {
+        const int vi = (int)threadIdx.x + q * kBlock;
+        if (vi < NV) tile[vi] = v[q];
+    }
+    __syncthreads();
+    // the finest smoother: c2 = c1 + omega ((g - A c1) / D), c1 = omega g / D
+    const int sx = (int)threadIdx.x % kRTX, sy = (int)threadIdx.x / kRTX;
+    const int x = X0 + sx, y = Y0 + sy;
+#pragma unroll
+    for (int k = 0; k < kRTZ; ++k) {
+        const int z = Z0 + k;
+        if (x >= n || y >= n || z >= n) continue;
+        const T* tp = tile + ((k + 1) * LY + sy + 1) * LX + sx + 1;
+        const T gi = tp[0];
+        const T gq[6] = {tp[-1], tp[1], tp[-LX], tp[LX], tp[-LX * LY], tp[LX * LY]};
+        const bool ok[6] = {x > 0, x < n - 1, y > 0, y < n - 1, z > 0, z < n - 1};
+        const T c1 = omega * (gi * op.inv0);
+        T acc = T(6) * c1;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) acc -= (ok[q] ? T(1) : T(0)) * (omega * (gq[q] * op.inv0));
+        const T Ac = op.s0 * acc;
+        c[x + n * (y + n * z)] = c1 + omega * ((gi - Ac) * op.inv0);
+    }
+    // full weighting into level L-1 at the box's coarse nodes
+    const int nf = rs.nf, nc = rs.nc;
+    constexpr int CX = kRTX / 2, CY = kRTY / 2, CZ = kRTZ / 2;
+    for (int j = threadIdx.x; j < CX * CY * CZ; j += kBlock) {
+        const int Jx = X0 / 2 + j % CX, Jy = Y0 / 2 + (j / CX) % CY, Jz = Z0 / 2 + j / (CX * CY);
+        if (Jx >= nc || Jy >= nc || Jz >= nc) continue;
+        const int fx = 2 * Jx, fy = 2 * Jy, fz = 2 * Jz;
+        const T w2x = fx + 2 < nf ? T(0.5) : T(0), w2y = fy + 2 < nf ? T(0.5) : T(0);
+        const T w2z = fz + 2 < nf ? T(0.5) : T(0);
+        // tile coordinates of the fine nodes 2J, 2J+1 and min(2J+2, nf-1)
+        const int lx0 = fx - X0 + 1, lx2 = min(fx + 2, nf - 1) - X0 + 1;
+        const int ly[3] = {fy - Y0 + 1, fy - Y0 + 2, min(fy + 2, nf - 1) - Y0 + 1};
+        const int lz[3] = {fz - Z0 + 1, fz - Z0 + 2, min(fz + 2, nf - 1) - Z0 + 1};
+        const T wy[3] = {T(0.5), T(1), w2y};
+        const T wz[3] = {T(0.5), T(1), w2z};
+        T acc = T(0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            T plane = T(0);
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const T* rowp = tile + (lz[a] * LY + ly[b]) * LX;
+                const T row = T(0.5) * rowp[lx0] + rowp[lx0 + 1] + w2x * rowp[lx2];
+                plane += wy[b] * row;
+            }
+            acc += wz[a] * plane;
+        }
+        const T g = T(0.125) * acc;
+        const int idx = Jx + nc * (Jy + nc * Jz);
+        rs.gc[idx] = g;
+        rs.c1[idx] = omega * (g / rs.D[rs.dconst ? 0 : idx]);
+    }
+}
+
 // Blocks [0, nbr): restriction level m+1 -> m (nbr = 0: none).  Blocks
 // [nbr, grid): the smoother of level m+1, one thread per node.
 template <int DIM, typename T>

@@ -820,9 +820,22 @@ class Solver : public SolverBase {
         {
             const int l = L - 1;
             const RestrictStep<double, T> rs{r, n_axis[L], g_[l].p, n_axis[l], N_[l], diag(l), c1_[l].p, cst_[l]};
-            const int nbr = ((N_[l] + kBlock - 1) / kBlock + kNumXcd - 1) / kNumXcd * kNumXcd;
-            k_restrict_fine_smooth<DIM, T><<<nbr + FB_, kBlock, 0, stream_>>>(ctl, rs, nbr, rows_, fop_, r, cL_.p,
-                                                                            omega, two);
+            bool tiled = false;
+            if constexpr (DIM == 3) {
+                // constant coefficients, two sweeps, level L-1 of size (n - 1) / 2
+                if (two && !fop_.D && !fop_.iD && n_axis[l] == (n_axis[L] - 1) / 2) {
+                    const int n = n_axis[L];
+                    const int ntx = (n + kRTX - 1) / kRTX, nty = (n + kRTY - 1) / kRTY, ntz = (n + kRTZ - 1) / kRTZ;
+                    k_restrict_fine_smooth_tile<T><<<ntx * nty * ntz, kBlock, 0, stream_>>>(ctl, rs, fop_, r, cL_.p,
+                                                                                           omega, ntx, nty, ntz);
+                    tiled = true;
+                }
+            }
+            if (!tiled) {
+                const int nbr = ((N_[l] + kBlock - 1) / kBlock + kNumXcd - 1) / kNumXcd * kNumXcd;
+                k_restrict_fine_smooth<DIM, T><<<nbr + FB_, kBlock, 0, stream_>>>(ctl, rs, nbr, rows_, fop_, r,
+                                                                                cL_.p, omega, two);
+            }
             cL_final_ = cL_.p;
         }
         int m = L - 2;

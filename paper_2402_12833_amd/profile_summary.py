@@ -27,7 +27,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 # fine-level kernels of one iteration and their entries in the byte model
 FINE = {"update_xP": "update_xP", "spmm_gram_z": "spmm_gram", "spmm_gram": "spmm_gram", "fine_W": "fine_W",
-        "update_r": "update_r", "restrict_fine_smooth": "restrict_fine_smooth"}
+        "update_r": "update_r", "restrict_fine_smooth": "restrict_fine_smooth",
+        "restrict_fine_smooth_tile": "restrict_fine_smooth"}
 GRID = {"poisson3d_127": (3, 127, 6), "poisson3d_255": (3, 255, 7)}
 CAL_BYTES = 512 * 1024 * 1024   # the calibration kernel reads and writes this many bytes
 
