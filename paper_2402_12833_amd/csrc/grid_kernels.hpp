@@ -1370,6 +1370,108 @@ __global__ void __launch_bounds__(kBlock) k_restrict_coarse_smooth(const Ctl* __
     if (idx < sm.op.N) smooth_level_at<DIM>(sm, idx, omega, two);
 }
 
+// 3D, constant coarse stencil, two sweeps: the restriction level m+1 -> m
+// and the smoother of level m+1 from one LDS box of level m+1's g and c1
+// per block (kCBX x kCBY x kCBZ nodes, even corner, one-node halo, zero
+// outside the grid).  The smoother's arithmetic and order are those of
+// coarse_smooth_at (mode 0) and the restriction's those of restrict_at; a
+// stencil tap outside the grid is weighted 0 and reads the halo's 0 instead
+// of the node's own value, so the results are the same.
+constexpr int kCBX = 16, kCBY = 4, kCBZ = 4;
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_restrict_coarse_smooth_tile(const Ctl* __restrict__ ctl,
+                                                                        RestrictStep<T, T> rs, SmoothLevel<T> sm,
+                                                                        T omega, int ntx, int nty, int ntz) {
+    if (ctl->state != 0) return;
+    static_assert(kCBX * kCBY * kCBZ == kBlock, "one thread per node of the box");
+    constexpr int LX = kCBX + 2, LY = kCBY + 2, LZ = kCBZ + 2, NV = LX * LY * LZ;
+    constexpr int NIT = (NV + kBlock - 1) / kBlock;
+    __shared__ T tg[NV], tc[NV];
+    const int t = xcd_block_of((int)blockIdx.x, ntx * nty * ntz);
+    const int X0 = (t % ntx) * kCBX, Y0 = ((t / ntx) % nty) * kCBY, Z0 = (t / (ntx * nty)) * kCBZ;
+    const int n = sm.op.n;
+    T vg[NIT], vc[NIT];
+#pragma unroll
+    for (int q = 0; q < NIT; ++q) {
+        const int vi = (int)threadIdx.x + q * kBlock;
+        const int lx = vi % LX, ly = (vi / LX) % LY, lz = vi / (LX * LY);
+        const int gx = X0 - 1 + lx, gy = Y0 - 1 + ly, gz = Z0 - 1 + lz;
+        const bool in = vi < NV && gx >= 0 && gx < n && gy >= 0 && gy < n && gz >= 0 && gz < n;
+        const int gi = in ? gx + n * (gy + n * gz) : 0;
+        vg[q] = in ? sm.g[gi] : T(0);
+        vc[q] = in ? sm.c1[gi] : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < NIT; ++q) {
+        const int vi = (int)threadIdx.x + q * kBlock;
+        if (vi < NV) {
+            tg[vi] = vg[q];
+            tc[vi] = vc[q];
+        }
+    }
+    __syncthreads();
+    // the smoother of level m+1 at this thread's node
+    {
+        const int sx = (int)threadIdx.x % kCBX, sy = ((int)threadIdx.x / kCBX) % kCBY, sz = (int)threadIdx.x / (kCBX * kCBY);
+        const int x = X0 + sx, y = Y0 + sy, z = Z0 + sz;
+        if (x < n && y < n && z < n) {
+            const int c0 = ((sz + 1) * LY + sy + 1) * LX + sx + 1;
+            const T* __restrict__ coef = sm.op.coef;
+            const T gi = tg[c0];
+            const T Di = coef[stencil_center<3>()];
+            T Ac = T(0);
+            int s = 0;
+#pragma unroll
+            for (int dz = -1; dz <= 1; ++dz) {
+                const bool okz = z + dz >= 0 && z + dz < n;
+#pragma unroll
+                for (int dy = -1; dy <= 1; ++dy) {
+                    const bool oky = okz && y + dy >= 0 && y + dy < n;
+#pragma unroll
+                    for (int dx = -1; dx <= 1; ++dx, ++s) {
+                        const bool ok = oky && x + dx >= 0 && x + dx < n;
+                        const T w = coef[s];
+                        Ac += (ok ? w : T(0)) * tc[c0 + dx + LX * (dy + LY * dz)];
+                    }
+                }
+            }
+            sm.out[(size_t)(x + n * (y + n * z)) * sm.stride] = tc[c0] + omega * ((gi - Ac) / Di);
+        }
+    }
+    // the restriction into level m at the coarse nodes centred in the box
+    const int nf = rs.nf, nc = rs.nc;
+    constexpr int CX = kCBX / 2, CY = kCBY / 2, CZ = kCBZ / 2;
+    for (int j = threadIdx.x; j < CX * CY * CZ; j += kBlock) {
+        const int Jx = X0 / 2 + j % CX, Jy = Y0 / 2 + (j / CX) % CY, Jz = Z0 / 2 + j / (CX * CY);
+        if (Jx >= nc || Jy >= nc || Jz >= nc) continue;
+        const int fx = 2 * Jx, fy = 2 * Jy, fz = 2 * Jz;
+        const T w2x = fx + 2 < nf ? T(0.5) : T(0), w2y = fy + 2 < nf ? T(0.5) : T(0);
+        const T w2z = fz + 2 < nf ? T(0.5) : T(0);
+        const int lx0 = fx - X0 + 1, lx2 = min(fx + 2, nf - 1) - X0 + 1;
+        const int ly[3] = {fy - Y0 + 1, fy - Y0 + 2, min(fy + 2, nf - 1) - Y0 + 1};
+        const int lz[3] = {fz - Z0 + 1, fz - Z0 + 2, min(fz + 2, nf - 1) - Z0 + 1};
+        const T wy[3] = {T(0.5), T(1), w2y};
+        const T wz[3] = {T(0.5), T(1), w2z};
+        T acc = T(0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            T plane = T(0);
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const T* rowp = tg + (lz[a] * LY + ly[b]) * LX;
+                const T row = T(0.5) * rowp[lx0] + rowp[lx0 + 1] + w2x * rowp[lx2];
+                plane += wy[b] * row;
+            }
+            acc += wz[a] * plane;
+        }
+        const T g = T(0.125) * acc;
+        const int idx = Jx + nc * (Jy + nc * Jz);
+        rs.gc[idx] = g;
+        rs.c1[idx] = omega * (g / rs.D[rs.dconst ? 0 : idx]);
+    }
+}
+
 // Block 0: the restriction chain into the small levels, one level after the
 // other, the smoother of every small level, then the prolongation chain
 // among them (up: coarsest first; it needs only what block 0 wrote).

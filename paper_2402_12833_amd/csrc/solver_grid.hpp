@@ -842,10 +842,25 @@ class Solver : public SolverBase {
         for (; m >= 0 && N_[m] > kRestrictTailMax; --m) {
             const RestrictStep<T, T> rs{g_[m + 1].p, n_axis[m + 1], g_[m].p, n_axis[m], N_[m], diag(m), c1_[m].p,
                                         cst_[m]};
-            const int nbr = (N_[m] + kBlock - 1) / kBlock;
-            const int nbs = (N_[m + 1] + kBlock - 1) / kBlock;
-            k_restrict_coarse_smooth<DIM, T><<<nbr + nbs, kBlock, 0, stream_>>>(ctl, rs, nbr, smooth_level(m + 1),
-                                                                              omega, two);
+            bool tiled = false;
+            if constexpr (DIM == 3) {
+                // constant stencil on level m+1, two sweeps, level m of size
+                // (n - 1) / 2, and boxes enough to fill the chip (63^3: 1024;
+                // at 31^3 the 128 boxes ran slower than the per-node form)
+                const int n = n_axis[m + 1];
+                const int ntx = (n + kCBX - 1) / kCBX, nty = (n + kCBY - 1) / kCBY, ntz = (n + kCBZ - 1) / kCBZ;
+                if (two && cst_[m + 1] && n_axis[m] == (n - 1) / 2 && ntx * nty * ntz >= 512) {
+                    k_restrict_coarse_smooth_tile<T><<<ntx * nty * ntz, kBlock, 0, stream_>>>(
+                        ctl, rs, smooth_level(m + 1), omega, ntx, nty, ntz);
+                    tiled = true;
+                }
+            }
+            if (!tiled) {
+                const int nbr = (N_[m] + kBlock - 1) / kBlock;
+                const int nbs = (N_[m + 1] + kBlock - 1) / kBlock;
+                k_restrict_coarse_smooth<DIM, T><<<nbr + nbs, kBlock, 0, stream_>>>(ctl, rs, nbr, smooth_level(m + 1),
+                                                                                  omega, two);
+            }
         }
         // level m+1 is restricted but not yet smoothed; levels m..0 are small
         if (m >= 0) {
