@@ -248,13 +248,21 @@ __global__ void __launch_bounds__(kCB) k_conv_lds(const Ctl* __restrict__ ctl, c
             for (int nt = 0; nt < NT; ++nt) {
                 const int co = co0 + nt * 16 + 4 * kq;
                 if (OUT_F32 == 2) {
+                    // the activation as stored: bfloat16 pairs (round to
+                    // nearest even), ReLU as a 16-bit integer max, then back
+                    // to FP32 for the dot product with the output weights
+                    i16x2 p0 = __builtin_bit_cast(i16x2, pack_bf16x2(acc[i][nt][0], acc[i][nt][1]));
+                    i16x2 p1 = __builtin_bit_cast(i16x2, pack_bf16x2(acc[i][nt][2], acc[i][nt][3]));
+                    if (RELU) {
+                        p0 = __builtin_elementwise_max(p0, i16x2{0, 0});
+                        p1 = __builtin_elementwise_max(p1, i16x2{0, 0});
+                    }
+                    const unsigned u0 = __builtin_bit_cast(unsigned, p0), u1 = __builtin_bit_cast(unsigned, p1);
+                    const float v[4] = {__uint_as_float(u0 << 16), __uint_as_float(u0 & 0xffff0000u),
+                                        __uint_as_float(u1 << 16), __uint_as_float(u1 & 0xffff0000u)};
                     float part = 0.f;
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        float v = bf2f(f2bf(acc[i][nt][j]));
-                        if (RELU) v = v > 0.f ? v : 0.f;
-                        part += v * bf2f(W2[co + j]);
-                    }
+                    for (int j = 0; j < 4; ++j) part += v[j] * bf2f(W2[co + j]);
                     part += __shfl_xor(part, 16);
                     part += __shfl_xor(part, 32);
                     if (kq == 0) *reinterpret_cast<float*>(Yb + 4u * vox) = part;
