@@ -1500,9 +1500,22 @@ __global__ void __launch_bounds__(kTailBlock) k_tail_smooth(const Ctl* __restric
         }
         __syncthreads();
     }
-    for (int q = 0; q < small.count; ++q)
-        for (int idx = threadIdx.x; idx < small.lev[q].op.N; idx += kTailBlock)
-            smooth_level_at<DIM>(small.lev[q], idx, omega, two);
+    // the small levels' smoothers side by side (each level its own range of
+    // threads) when they fit in the block, else one level after the other
+    int tot = 0;
+    for (int q = 0; q < small.count; ++q) tot += small.lev[q].op.N;
+    if (tot <= kTailBlock) {
+        int off = 0;
+        for (int q = 0; q < small.count; ++q) {
+            const int idx = (int)threadIdx.x - off;
+            if (idx >= 0 && idx < small.lev[q].op.N) smooth_level_at<DIM>(small.lev[q], idx, omega, two);
+            off += small.lev[q].op.N;
+        }
+    } else {
+        for (int q = 0; q < small.count; ++q)
+            for (int idx = threadIdx.x; idx < small.lev[q].op.N; idx += kTailBlock)
+                smooth_level_at<DIM>(small.lev[q], idx, omega, two);
+    }
     if (up.count == 0) return;
     __syncthreads();
     prolong_chain_block<DIM, T>(up);
