@@ -136,7 +136,11 @@ class CsrSolver : public SolverBase {
         enqueue_init(tol);
         HIPCHK(hipGetLastError());
         const int launches_max = maxit / kpoll_ + 3;
-        for (int launch = 0; launch < launches_max; ++launch) {
+        // the first graph follows the set-up without a host check (its
+        // kernels are predicated on the device state: a solve that the
+        // set-up already ended runs them as no-ops); later ones after one
+        HIPCHK(hipGraphLaunch(exec_, stream_));
+        for (int launch = 1; launch < launches_max; ++launch) {
             HIPCHK(hipMemcpyAsync(hctl_, ctl_, sizeof(Ctl), hipMemcpyDeviceToHost, stream_));
             HIPCHK(hipStreamSynchronize(stream_));
             if (hctl_->state == 2) break;
